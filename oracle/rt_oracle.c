@@ -1,0 +1,553 @@
+/*
+ * rt_oracle.c -- plain, slow, FP64 CPU oracle for the matrix-free operator
+ * A = Id - J Lambda T of the 1D two-level-atom scattering-polarization
+ * problem (Benedusi, Janett, Belluzzi & Krause, "Krylov methods and
+ * matrix-free implementation", Sect. 3) and for the solvers that call it.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may call, link or
+ * load this file: only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or constant
+ * with the GPU library.
+ *
+ * Every function follows the paper's own order of operations:
+ *   Algorithm 1 (Sect. 3.3): S = T sigma for every (k, m); then for every
+ *   (m, p) a formal solution along the ray with zero incoming radiation;
+ *   then the angle-frequency quadrature of eqs. (J00)/(J02); then
+ *   sigma_out = sigma_in - xi * [J00, W2 J20].
+ * No fusion, blocking or reordering beyond that.  Built with
+ * -ffp-contract=off so every product and sum rounds as written.
+ *
+ * Readings of the paper taken here (each also recorded in the design notes):
+ *  - tau increases downward, tau[0] at the top; mu<0 rays travel downward
+ *    (entering at the top), mu>0 rays travel upward (entering at the
+ *    bottom) -- boundary conditions of Sect. 3.1.
+ *  - the optical-depth step of ray (m,p) over the interval (u,k) is
+ *    r_p |tau_k - tau_u| / |mu_m|, r_p an input opacity ratio.
+ *  - polarizability W2 scales the emission of sigma^2_0 only:
+ *    sigma^2_0 = xi W2 J^2_0 (W2 = 1 is the paper's atom, Sect. 3.1).
+ *  - the frequency weights are w_p phi_p, renormalized to sum to one when
+ *    `normalize` is set, so that scattering conserves photons on the
+ *    truncated frequency grid.
+ *  - Planck function B_k (the paper's W = 1) enters as c = [eps B_k, 0].
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int ns;               /* depth points                                  */
+    const double *tau;    /* [ns] optical depth, top first, increasing      */
+    int nmu;              /* direction nodes on [-1, 1]                     */
+    const double *mu;     /* [nmu]                                          */
+    const double *wmu;    /* [nmu] weights, sum 2                           */
+    int nnu;              /* frequency nodes                                */
+    const double *wnu;    /* [nnu] frequency quadrature weights             */
+    const double *phi;    /* [nnu] absorption profile                       */
+    const double *opac;   /* [nnu] opacity ratio r_p                        */
+    double eps;           /* thermalization parameter, xi = 1 - eps         */
+    double W2;            /* polarizability                                 */
+    double Ibot;          /* incoming intensity at the bottom for mu > 0    */
+    const double *B;      /* [ns] Planck function                           */
+    int fs;               /* 0: DELO-linear, 1: trapezoidal                 */
+    int normalize;        /* renormalize the frequency weights              */
+} orc_slab;
+
+/* ------------------------------------------------------------------------
+ * Polarization tensor components for gamma = 0 (eqs. sourceI/sourceQ).
+ * ---------------------------------------------------------------------- */
+void orc_t20(double mu, double *t1, double *t2)
+{
+    *t1 = sqrt(2.0) * (3.0 * mu * mu - 1.0) / 4.0;
+    *t2 = sqrt(2.0) * (3.0 * mu * mu - 3.0) / 4.0;
+}
+
+/* ------------------------------------------------------------------------
+ * DELO-linear step coefficients (Sect. 4.1; no dichroism, so DELO reduces
+ * to an exact integration of a linearly interpolated source function along
+ * the ray).  With t the optical path from the upwind point (t = 0) to the
+ * current point (t = d):
+ *     I_k = E I_u + pu S_u + pk S_k,   E = exp(-d),
+ *     pu  = int_0^d (1 - t/d) exp(-(d - t)) dt,
+ *     pk  = int_0^d (t/d)     exp(-(d - t)) dt.
+ * Closed forms: pu = (1 - (1 + d) E)/d, pk = (1 - E) - pu.  For small d the
+ * closed forms cancel, so the Taylor series of the same integrals is used:
+ *     pu = sum_{n>=2} (-1)^n (n-1) d^(n-1) / n!
+ *     pk = sum_{n>=2} (-1)^n       d^(n-1) / n!
+ * ---------------------------------------------------------------------- */
+void orc_delo_linear(double d, double *E, double *pu, double *pk)
+{
+    if (d < 0.1) {
+        double term = 1.0;   /* d^(n-1)/n! built incrementally; n = 1 */
+        double su = 0.0, sk = 0.0;
+        int n;
+        for (n = 2; n <= 20; n++) {
+            double sgn = (n % 2 == 0) ? 1.0 : -1.0;
+            term = term * d / (double)n;        /* now d^(n-1)/n! */
+            su += sgn * (double)(n - 1) * term;
+            sk += sgn * term;
+        }
+        *E = exp(-d);
+        *pu = su;
+        *pk = sk;
+    } else {
+        double e = exp(-d);
+        double w0 = -expm1(-d);
+        double w1 = w0 - d * e;
+        *E = e;
+        *pu = w1 / d;
+        *pk = w0 - *pu;
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Trapezoidal (Crank-Nicolson) step on dI/dt = S - I over one interval:
+ *     I_k - I_u = (d/2) [(S_u - I_u) + (S_k - I_k)]
+ *  => I_k = a I_u + b (S_u + S_k),  a = (1 - d/2)/(1 + d/2), b = (d/2)/(1 + d/2).
+ * Not among the paper's formal solvers; used by the benchmark's second
+ * configuration.
+ * ---------------------------------------------------------------------- */
+void orc_trapezoid(double d, double *a, double *b)
+{
+    double h = 0.5 * d;
+    *a = (1.0 - h) / (1.0 + h);
+    *b = h / (1.0 + h);
+}
+
+/* ------------------------------------------------------------------------
+ * Formal solution along one ray (eqs. RTE_delo1/2 written in optical path
+ * along the ray).  kappa = r_p / |mu|.  upward = 0: the ray enters at the
+ * top (index 0) and moves to larger tau; upward = 1: it enters at the
+ * bottom (index ns-1) and moves to smaller tau.  I[entry] = I_entry.
+ * ---------------------------------------------------------------------- */
+void orc_ray(int ns, const double *tau, double kappa, int upward, int fs,
+             const double *S, double I_entry, double *I)
+{
+    int k;
+    if (!upward) {
+        I[0] = I_entry;
+        for (k = 1; k < ns; k++) {
+            int u = k - 1;
+            double d = kappa * fabs(tau[k] - tau[u]);
+            if (fs == 0) {
+                double E, pu, pk;
+                orc_delo_linear(d, &E, &pu, &pk);
+                I[k] = E * I[u] + pu * S[u] + pk * S[k];
+            } else {
+                double a, b;
+                orc_trapezoid(d, &a, &b);
+                I[k] = a * I[u] + b * (S[u] + S[k]);
+            }
+        }
+    } else {
+        I[ns - 1] = I_entry;
+        for (k = ns - 2; k >= 0; k--) {
+            int u = k + 1;
+            double d = kappa * fabs(tau[k] - tau[u]);
+            if (fs == 0) {
+                double E, pu, pk;
+                orc_delo_linear(d, &E, &pu, &pk);
+                I[k] = E * I[u] + pu * S[u] + pk * S[k];
+            } else {
+                double a, b;
+                orc_trapezoid(d, &a, &b);
+                I[k] = a * I[u] + b * (S[u] + S[k]);
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Quadrature weights of eqs. (J00)/(J02): the angular integral
+ * (1/2) int dmu over [-1, 1] with the given nodes, times the spectral
+ * integral int dnu phi with weights w_p phi_p (renormalized if asked).
+ * q[m * nnu + p].
+ * ---------------------------------------------------------------------- */
+void orc_weights(const orc_slab *s, double *q)
+{
+    int m, p;
+    double norm = 1.0;
+    if (s->normalize) {
+        double sum = 0.0;
+        for (p = 0; p < s->nnu; p++) sum += s->wnu[p] * s->phi[p];
+        norm = sum;
+    }
+    for (m = 0; m < s->nmu; m++)
+        for (p = 0; p < s->nnu; p++)
+            q[m * s->nnu + p] = 0.5 * s->wmu[m] * (s->wnu[p] * s->phi[p] / norm);
+}
+
+/* ------------------------------------------------------------------------
+ * Algorithm 1: sigma_out = A sigma_in, sigma interleaved
+ * [s00(z1), s20(z1), s00(z2), ...] (Sect. 3.2).
+ * ---------------------------------------------------------------------- */
+int orc_apply(const orc_slab *s, const double *sin, double *sout)
+{
+    int ns = s->ns, nmu = s->nmu, nnu = s->nnu;
+    int k, m, p;
+    double xi = 1.0 - s->eps;
+    double *SI = (double *)malloc(sizeof(double) * ns * nmu);
+    double *SQ = (double *)malloc(sizeof(double) * ns * nmu);
+    double *I = (double *)malloc(sizeof(double) * ns);
+    double *Q = (double *)malloc(sizeof(double) * ns);
+    double *J0 = (double *)calloc(ns, sizeof(double));
+    double *J2 = (double *)calloc(ns, sizeof(double));
+    double *q = (double *)malloc(sizeof(double) * nmu * nnu);
+    if (!SI || !SQ || !I || !Q || !J0 || !J2 || !q) {
+        free(SI); free(SQ); free(I); free(Q); free(J0); free(J2); free(q);
+        return -1;
+    }
+    orc_weights(s, q);
+
+    /* S = T sigma_in (eqs. sourceI/sourceQ) */
+    for (k = 0; k < ns; k++) {
+        for (m = 0; m < nmu; m++) {
+            double t1, t2;
+            orc_t20(s->mu[m], &t1, &t2);
+            SI[m * ns + k] = sin[2 * k] + t1 * sin[2 * k + 1];
+            SQ[m * ns + k] = t2 * sin[2 * k + 1];
+        }
+    }
+
+    /* I = Lambda S with zero incoming radiation; quadrature into J */
+    for (m = 0; m < nmu; m++) {
+        double t1, t2;
+        int upward = s->mu[m] > 0.0;
+        orc_t20(s->mu[m], &t1, &t2);
+        for (p = 0; p < nnu; p++) {
+            double kappa = s->opac[p] / fabs(s->mu[m]);
+            double w = q[m * nnu + p];
+            orc_ray(ns, s->tau, kappa, upward, s->fs, SI + m * ns, 0.0, I);
+            orc_ray(ns, s->tau, kappa, upward, s->fs, SQ + m * ns, 0.0, Q);
+            for (k = 0; k < ns; k++) {
+                J0[k] += w * I[k];
+                J2[k] += w * (t1 * I[k] + t2 * Q[k]);
+            }
+        }
+    }
+
+    for (k = 0; k < ns; k++) {
+        sout[2 * k] = sin[2 * k] - xi * J0[k];
+        sout[2 * k + 1] = sin[2 * k + 1] - xi * s->W2 * J2[k];
+    }
+    free(SI); free(SQ); free(I); free(Q); free(J0); free(J2); free(q);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Right-hand side b = J t + c (eq. crd_linear_system): t is the radiation
+ * transmitted from the boundaries (S = 0, I = Ibot entering at the bottom
+ * for mu > 0, I = 0 entering at the top, Q = 0 everywhere), c = [eps B, 0].
+ * ---------------------------------------------------------------------- */
+int orc_rhs(const orc_slab *s, double *b)
+{
+    int ns = s->ns, nmu = s->nmu, nnu = s->nnu;
+    int k, m, p;
+    double xi = 1.0 - s->eps;
+    double *zero = (double *)calloc(ns, sizeof(double));
+    double *I = (double *)malloc(sizeof(double) * ns);
+    double *J0 = (double *)calloc(ns, sizeof(double));
+    double *J2 = (double *)calloc(ns, sizeof(double));
+    double *q = (double *)malloc(sizeof(double) * nmu * nnu);
+    if (!zero || !I || !J0 || !J2 || !q) {
+        free(zero); free(I); free(J0); free(J2); free(q);
+        return -1;
+    }
+    orc_weights(s, q);
+    for (m = 0; m < nmu; m++) {
+        double t1, t2;
+        int upward = s->mu[m] > 0.0;
+        orc_t20(s->mu[m], &t1, &t2);
+        for (p = 0; p < nnu; p++) {
+            double kappa = s->opac[p] / fabs(s->mu[m]);
+            double w = q[m * nnu + p];
+            orc_ray(ns, s->tau, kappa, upward, s->fs, zero, upward ? s->Ibot : 0.0, I);
+            for (k = 0; k < ns; k++) {
+                J0[k] += w * I[k];
+                J2[k] += w * (t1 * I[k]); /* transmitted Q is zero */
+            }
+        }
+    }
+    for (k = 0; k < ns; k++) {
+        b[2 * k] = xi * J0[k] + s->eps * s->B[k];
+        b[2 * k + 1] = xi * s->W2 * J2[k];
+    }
+    free(zero); free(I); free(J0); free(J2); free(q);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Diagonal entries of A by their definition: d_i = (A e_i)_i, one matvec
+ * per requested index (column-by-column assembly, Sect. 3.3).
+ * ---------------------------------------------------------------------- */
+int orc_diag(const orc_slab *s, int nidx, const int *idx, double *d)
+{
+    int n = 2 * s->ns, j;
+    double *e = (double *)calloc(n, sizeof(double));
+    double *col = (double *)malloc(sizeof(double) * n);
+    if (!e || !col) { free(e); free(col); return -1; }
+    for (j = 0; j < nidx; j++) {
+        int i = idx[j];
+        e[i] = 1.0;
+        orc_apply(s, e, col);
+        d[j] = col[i];
+        e[i] = 0.0;
+    }
+    free(e); free(col);
+    return 0;
+}
+
+/* Column-by-column assembly of the full A (n x n, row-major). */
+int orc_assemble(const orc_slab *s, double *A)
+{
+    int n = 2 * s->ns, i, j;
+    double *e = (double *)calloc(n, sizeof(double));
+    double *col = (double *)malloc(sizeof(double) * n);
+    if (!e || !col) { free(e); free(col); return -1; }
+    for (j = 0; j < n; j++) {
+        e[j] = 1.0;
+        orc_apply(s, e, col);
+        for (i = 0; i < n; i++) A[i * n + j] = col[i];
+        e[j] = 0.0;
+    }
+    free(e); free(col);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Solvers.  All are right-preconditioned by P^-1 = diag(dinv) (identity if
+ * dinv is NULL), so the residual they stop on is the unpreconditioned
+ * ||b - A x||_2 / ||b||_2 of Sect. 4.2.
+ *
+ * Status: 0 converged, 1 iteration limit reached, 2 breakdown, -1 memory.
+ * ---------------------------------------------------------------------- */
+static double dot(int n, const double *a, const double *b)
+{
+    double s = 0.0;
+    int i;
+    for (i = 0; i < n; i++) s += a[i] * b[i];
+    return s;
+}
+
+static double nrm2(int n, const double *a) { return sqrt(dot(n, a, a)); }
+
+static void precond(int n, const double *dinv, const double *v, double *z)
+{
+    int i;
+    for (i = 0; i < n; i++) z[i] = dinv ? dinv[i] * v[i] : v[i];
+}
+
+static void residual(const orc_slab *s, const double *b, const double *x, double *r)
+{
+    int n = 2 * s->ns, i;
+    orc_apply(s, x, r);
+    for (i = 0; i < n; i++) r[i] = b[i] - r[i];
+}
+
+/*
+ * GMRES(m) (Saad & Schultz 1986; Sect. 2.1): Arnoldi with modified
+ * Gram-Schmidt builds an orthonormal basis of the Krylov space of A P^-1,
+ * Givens rotations reduce the Hessenberg least-squares problem, and
+ * x = x0 + P^-1 V y minimizes ||b - A x||_2.  After each cycle the residual
+ * is recomputed explicitly and the method restarts from x.
+ * restart <= 0 means no restart (cycle length = maxit).
+ * iters counts Arnoldi steps; matvecs counts every application of A.
+ */
+int orc_gmres(const orc_slab *s, const double *b, double *x, const double *dinv,
+              int restart, double tol, int maxit, int *iters, int *matvecs,
+              double *relres, double *hist, int hist_len)
+{
+    int n = 2 * s->ns;
+    int m = (restart <= 0 || restart > maxit) ? maxit : restart;
+    int total = 0, nmv = 0, status = 1, i, j, jj;
+    double bnorm = nrm2(n, b), beta;
+    double *V = (double *)malloc(sizeof(double) * (size_t)n * (m + 1));
+    double *H = (double *)calloc((size_t)(m + 1) * m, sizeof(double));
+    double *cs = (double *)malloc(sizeof(double) * m);
+    double *sn = (double *)malloc(sizeof(double) * m);
+    double *g = (double *)malloc(sizeof(double) * (m + 1));
+    double *y = (double *)malloc(sizeof(double) * m);
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *z = (double *)malloc(sizeof(double) * n);
+    double *w = (double *)malloc(sizeof(double) * n);
+    if (!V || !H || !cs || !sn || !g || !y || !r || !z || !w) { status = -1; goto done; }
+
+    if (bnorm == 0.0) {
+        for (i = 0; i < n; i++) x[i] = 0.0;
+        if (relres) *relres = 0.0;
+        status = 0;
+        goto done;
+    }
+    residual(s, b, x, r); nmv++;
+    beta = nrm2(n, r);
+    if (hist && hist_len > 0) hist[0] = beta / bnorm;
+    if (beta / bnorm < tol) { status = 0; goto done_res; }
+
+    while (total < maxit) {
+        for (i = 0; i < n; i++) V[i] = r[i] / beta;
+        for (i = 0; i <= m; i++) g[i] = 0.0;
+        g[0] = beta;
+        memset(H, 0, sizeof(double) * (size_t)(m + 1) * m);
+        jj = 0;
+        for (j = 0; j < m && total < maxit; j++) {
+            double hnext, resid, tmp, den;
+            precond(n, dinv, V + (size_t)j * n, z);
+            orc_apply(s, z, w); nmv++;
+            total++;
+            for (i = 0; i <= j; i++) {     /* modified Gram-Schmidt */
+                int l;
+                double h = dot(n, w, V + (size_t)i * n);
+                H[i * m + j] = h;
+                for (l = 0; l < n; l++) w[l] -= h * V[(size_t)i * n + l];
+            }
+            hnext = nrm2(n, w);
+            H[(j + 1) * m + j] = hnext;
+            for (i = 0; i < j; i++) {      /* previous rotations */
+                tmp = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = tmp;
+            }
+            den = sqrt(H[j * m + j] * H[j * m + j] + hnext * hnext);
+            cs[j] = H[j * m + j] / den;
+            sn[j] = hnext / den;
+            H[j * m + j] = den;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            resid = fabs(g[j + 1]);
+            if (hist && total < hist_len) hist[total] = resid / bnorm;
+            jj = j + 1;
+            if (hnext != 0.0) {
+                for (i = 0; i < n; i++) V[(size_t)(j + 1) * n + i] = w[i] / hnext;
+            }
+            if (resid / bnorm < tol || hnext == 0.0) break;
+        }
+        /* back substitution H y = g, then x += P^-1 V y */
+        for (i = jj - 1; i >= 0; i--) {
+            double sum = g[i];
+            int l;
+            for (l = i + 1; l < jj; l++) sum -= H[i * m + l] * y[l];
+            y[i] = sum / H[i * m + i];
+        }
+        for (i = 0; i < n; i++) w[i] = 0.0;
+        for (j = 0; j < jj; j++)
+            for (i = 0; i < n; i++) w[i] += y[j] * V[(size_t)j * n + i];
+        precond(n, dinv, w, z);
+        for (i = 0; i < n; i++) x[i] += z[i];
+        residual(s, b, x, r); nmv++;
+        beta = nrm2(n, r);
+        if (beta / bnorm < tol) { status = 0; break; }
+        if (beta == 0.0) { status = 0; break; }
+    }
+done_res:
+    if (relres) *relres = nrm2(n, r) / bnorm;
+done:
+    if (iters) *iters = total;
+    if (matvecs) *matvecs = nmv;
+    free(V); free(H); free(cs); free(sn); free(g); free(y); free(r); free(z); free(w);
+    return status;
+}
+
+/*
+ * BiCGSTAB (van der Vorst 1992; Sect. 2.2), right-preconditioned.
+ * iters counts full steps (two applications of A each); a step that
+ * converges on its half-way residual s counts as a full step.
+ */
+int orc_bicgstab(const orc_slab *s, const double *b, double *x, const double *dinv,
+                 double tol, int maxit, int *iters, int *matvecs, double *relres)
+{
+    int n = 2 * s->ns, it, i, status = 1, nmv = 0;
+    double bnorm = nrm2(n, b);
+    double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *rh = (double *)malloc(sizeof(double) * n);
+    double *p = (double *)calloc(n, sizeof(double));
+    double *v = (double *)calloc(n, sizeof(double));
+    double *ph = (double *)malloc(sizeof(double) * n);
+    double *sv = (double *)malloc(sizeof(double) * n);
+    double *sh = (double *)malloc(sizeof(double) * n);
+    double *t = (double *)malloc(sizeof(double) * n);
+    it = 0;
+    if (!r || !rh || !p || !v || !ph || !sv || !sh || !t) { status = -1; goto done; }
+    if (bnorm == 0.0) {
+        for (i = 0; i < n; i++) x[i] = 0.0;
+        if (relres) *relres = 0.0;
+        status = 0;
+        goto done;
+    }
+    residual(s, b, x, r); nmv++;
+    if (nrm2(n, r) / bnorm < tol) { status = 0; goto done_res; }
+    for (i = 0; i < n; i++) rh[i] = r[i];
+    for (it = 1; it <= maxit; it++) {
+        double rho = dot(n, rh, r), beta, rv, tt;
+        if (rho == 0.0 || !isfinite(rho)) { status = 2; it--; break; }
+        beta = (rho / rho_old) * (alpha / omega);
+        for (i = 0; i < n; i++) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        precond(n, dinv, p, ph);
+        orc_apply(s, ph, v); nmv++;
+        rv = dot(n, rh, v);
+        if (rv == 0.0 || !isfinite(rv)) { status = 2; it--; break; }
+        alpha = rho / rv;
+        for (i = 0; i < n; i++) sv[i] = r[i] - alpha * v[i];
+        if (nrm2(n, sv) / bnorm < tol) {
+            for (i = 0; i < n; i++) x[i] += alpha * ph[i];
+            status = 0;
+            break;
+        }
+        precond(n, dinv, sv, sh);
+        orc_apply(s, sh, t); nmv++;
+        tt = dot(n, t, t);
+        if (tt == 0.0) { status = 2; break; }
+        omega = dot(n, t, sv) / tt;
+        for (i = 0; i < n; i++) x[i] += alpha * ph[i] + omega * sh[i];
+        for (i = 0; i < n; i++) r[i] = sv[i] - omega * t[i];
+        if (nrm2(n, r) / bnorm < tol) { status = 0; break; }
+        if (omega == 0.0 || !isfinite(omega)) { status = 2; break; }
+        rho_old = rho;
+    }
+    if (it > maxit) it = maxit;
+    residual(s, b, x, r); nmv++;
+done_res:
+    if (relres) *relres = nrm2(n, r) / bnorm;
+done:
+    if (iters) *iters = it;
+    if (matvecs) *matvecs = nmv;
+    free(r); free(rh); free(p); free(v); free(ph); free(sv); free(sh); free(t);
+    return status;
+}
+
+/*
+ * Preconditioned Richardson iteration x <- x + P^-1 (b - A x)
+ * (eq. rich_iteration).  iters = number of updates applied when the
+ * relative residual first drops below tol.
+ */
+int orc_richardson(const orc_slab *s, const double *b, double *x, const double *dinv,
+                   double tol, int maxit, int *iters, int *matvecs, double *relres)
+{
+    int n = 2 * s->ns, it, i, status = 1, nmv = 0;
+    double bnorm = nrm2(n, b), rel = 0.0;
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *z = (double *)malloc(sizeof(double) * n);
+    if (!r || !z) { free(r); free(z); return -1; }
+    if (bnorm == 0.0) {
+        for (i = 0; i < n; i++) x[i] = 0.0;
+        if (iters) *iters = 0;
+        if (matvecs) *matvecs = 0;
+        if (relres) *relres = 0.0;
+        free(r); free(z);
+        return 0;
+    }
+    for (it = 0;; it++) {
+        residual(s, b, x, r); nmv++;
+        rel = nrm2(n, r) / bnorm;
+        if (rel < tol) { status = 0; break; }
+        if (!isfinite(rel)) { status = 2; break; }   /* diverged */
+        if (it == maxit) { status = 1; break; }
+        precond(n, dinv, r, z);
+        for (i = 0; i < n; i++) x[i] += z[i];
+    }
+    if (iters) *iters = it;
+    if (matvecs) *matvecs = nmv;
+    if (relres) *relres = rel;
+    free(r); free(z);
+    return status;
+}
