@@ -1,0 +1,255 @@
+"""ctypes binding of librt.so (include/rt.h, include/rt_ext.h).
+
+Argument marshalling only: every step of the operator and of the solvers runs
+in the gfx950 kernels of the library.  Vectors are torch CUDA (HIP) float64
+tensors; streams are torch streams (default: torch's current stream).  There is
+no CPU fallback: if the library is missing or no gfx950 device is present the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librt.so")
+
+RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ENOCONV, RT_EBREAKDOWN = 0, -1, -2, -3, 1, 2
+RT_FS_DELO_LINEAR, RT_FS_TRAPEZOIDAL = 0, 1
+RT_PREC_FP64, RT_PREC_MIXED = 0, 1
+RT_MAX_NS = 2048
+RT_MAX_RESTART = 128
+STATUS_NAMES = {RT_OK: "converged", RT_ENOCONV: "maxit", RT_EBREAKDOWN: "breakdown"}
+
+# every function the headers declare
+EXPORTS = ["rt_default_options", "rt_setup", "rt_destroy", "rt_num_unknowns", "rt_apply_op",
+           "rt_precond_jacobi", "rt_get_rhs", "rt_get_jacobi_diag", "rt_solve_gmres",
+           "rt_solve_bicgstab", "rt_solve_richardson", "rt_last_error", "rt_apply_op_fp32",
+           "rt_plan_info", "rt_validate"]
+
+
+class RTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rt error {code}: {msg}")
+        self.code = code
+
+
+class rt_problem(C.Structure):
+    _fields_ = [
+        ("n_atm", C.c_int), ("ns", C.POINTER(C.c_int)), ("tau", C.POINTER(C.c_double)),
+        ("n_mu", C.c_int), ("mu", C.POINTER(C.c_double)), ("w_mu", C.POINTER(C.c_double)),
+        ("n_nu", C.c_int), ("w_nu", C.POINTER(C.c_double)), ("phi", C.POINTER(C.c_double)),
+        ("opac", C.POINTER(C.c_double)), ("eps", C.POINTER(C.c_double)),
+        ("W2", C.POINTER(C.c_double)), ("B", C.POINTER(C.c_double)),
+        ("I_bot", C.POINTER(C.c_double)), ("formal_solver", C.c_int),
+        ("normalize_profile", C.c_int),
+    ]
+
+
+class rt_options(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int), ("restart", C.c_int), ("maxit", C.c_int), ("rtol", C.c_double),
+        ("inner_rtol", C.c_double), ("inner_maxit", C.c_int), ("max_outer", C.c_int),
+        ("chunk", C.c_int), ("wave_batches", C.c_int), ("check_every", C.c_int),
+    ]
+
+
+class rt_solve_info(C.Structure):
+    _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("matvecs", C.c_int),
+                ("outer_steps", C.c_int), ("relres", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librt.so; raise if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
+                              "python paper_2110_11873_amd/csrc/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        L.rt_default_options.argtypes = [C.POINTER(rt_options)]
+        L.rt_default_options.restype = None
+        L.rt_setup.argtypes = [C.POINTER(vp), C.POINTER(rt_problem), C.POINTER(rt_options)]
+        L.rt_destroy.argtypes = [vp]
+        L.rt_destroy.restype = None
+        L.rt_num_unknowns.argtypes = [vp]
+        for f in ("rt_apply_op", "rt_apply_op_fp32", "rt_precond_jacobi"):
+            getattr(L, f).argtypes = [vp, vp, vp, vp]
+        for f in ("rt_get_rhs", "rt_get_jacobi_diag"):
+            getattr(L, f).argtypes = [vp, vp, vp]
+        for f in ("rt_solve_gmres", "rt_solve_bicgstab", "rt_solve_richardson"):
+            getattr(L, f).argtypes = [vp, vp, vp, C.POINTER(rt_solve_info), vp]
+        L.rt_last_error.argtypes = []
+        L.rt_last_error.restype = C.c_char_p
+        L.rt_plan_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                   C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
+        L.rt_validate.argtypes = [C.POINTER(rt_problem), C.POINTER(rt_options)]
+        _ = dp
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().rt_last_error().decode()
+
+
+def _check(rc):
+    if rc < 0:
+        raise RTError(rc, last_error())
+    return rc
+
+
+def default_options(**kw) -> rt_options:
+    o = rt_options()
+    lib().rt_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+class _ProblemBuffers:
+    """Holds contiguous host copies while rt_setup reads them."""
+
+    def __init__(self, prob):
+        f = lambda a: np.ascontiguousarray(a, dtype=np.float64)  # noqa: E731
+        self.ns = np.ascontiguousarray(prob.ns, dtype=np.int32)
+        self.tau, self.mu, self.w_mu = f(prob.tau), f(prob.mu), f(prob.w_mu)
+        self.w_nu, self.phi, self.opac = f(prob.w_nu), f(prob.phi), f(prob.opac)
+        self.eps, self.W2, self.B, self.I_bot = f(prob.eps), f(prob.W2), f(prob.B), f(prob.I_bot)
+        d = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+        self.c = rt_problem(
+            int(self.ns.shape[0]), self.ns.ctypes.data_as(C.POINTER(C.c_int)), d(self.tau),
+            int(self.mu.shape[0]), d(self.mu), d(self.w_mu), int(self.w_nu.shape[0]), d(self.w_nu),
+            d(self.phi), d(self.opac), d(self.eps), d(self.W2), d(self.B), d(self.I_bot),
+            int(prob.formal_solver), int(bool(prob.normalize_profile)))
+
+
+def validate(prob, options: Optional[rt_options] = None) -> int:
+    """rt_validate: host-side checks only (no device needed)."""
+    pb = _ProblemBuffers(prob)
+    return lib().rt_validate(C.byref(pb.c), C.byref(options) if options is not None else None)
+
+
+@dataclass
+class SolveInfo:
+    status: str
+    iterations: int
+    matvecs: int
+    outer_steps: int
+    relres: float
+
+
+def _ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 \
+            or not t.is_contiguous():
+        raise TypeError("vectors must be contiguous float64 tensors on the GPU")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Handle:
+    """An rt_handle: a problem set up on the current GPU."""
+
+    def __init__(self, prob, options: Optional[rt_options] = None, **kw):
+        self.options = options if options is not None else default_options(**kw)
+        pb = _ProblemBuffers(prob)
+        h = C.c_void_p()
+        _check(lib().rt_setup(C.byref(h), C.byref(pb.c), C.byref(self.options)))
+        self._h = h
+        self.n = lib().rt_num_unknowns(h)
+        self.n_atm = int(pb.ns.shape[0])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _new(self):
+        import torch
+        return torch.empty(self.n, dtype=torch.float64, device="cuda")
+
+    # -- operator and preconditioner ------------------------------------------
+    def apply_op(self, sigma_in, sigma_out=None, stream=None):
+        out = self._new() if sigma_out is None else sigma_out
+        _check(lib().rt_apply_op(self._h, C.c_void_p(_ptr(sigma_in)), C.c_void_p(_ptr(out)),
+                                 _stream(stream)))
+        return out
+
+    def apply_op_fp32(self, sigma_in, sigma_out=None, stream=None):
+        out = self._new() if sigma_out is None else sigma_out
+        _check(lib().rt_apply_op_fp32(self._h, C.c_void_p(_ptr(sigma_in)), C.c_void_p(_ptr(out)),
+                                      _stream(stream)))
+        return out
+
+    def precond_jacobi(self, v, z=None, stream=None):
+        out = self._new() if z is None else z
+        _check(lib().rt_precond_jacobi(self._h, C.c_void_p(_ptr(v)), C.c_void_p(_ptr(out)),
+                                       _stream(stream)))
+        return out
+
+    def get_rhs(self, stream=None):
+        b = self._new()
+        _check(lib().rt_get_rhs(self._h, C.c_void_p(_ptr(b)), _stream(stream)))
+        return b
+
+    def get_jacobi_diag(self, stream=None):
+        d = self._new()
+        _check(lib().rt_get_jacobi_diag(self._h, C.c_void_p(_ptr(d)), _stream(stream)))
+        return d
+
+    def plan_info(self):
+        L, nb = C.c_int(), C.c_int()
+        npairs, nint = C.c_longlong(), C.c_longlong()
+        _check(lib().rt_plan_info(self._h, C.byref(L), C.byref(nb), C.byref(npairs),
+                                  C.byref(nint)))
+        return dict(chunk=L.value, blocks=nb.value, pairs=npairs.value, intervals=nint.value)
+
+    # -- solvers ---------------------------------------------------------------
+    def _solve(self, fn, b, x, stream):
+        info = (rt_solve_info * self.n_atm)()
+        bp = C.c_void_p(_ptr(b)) if b is not None else None
+        rc = getattr(lib(), fn)(self._h, bp, C.c_void_p(_ptr(x)), info, _stream(stream))
+        _check(rc)
+        return rc, [SolveInfo(STATUS_NAMES.get(i.status, str(i.status)), i.iterations, i.matvecs,
+                              i.outer_steps, i.relres) for i in info]
+
+    def solve_gmres(self, x, b=None, stream=None):
+        return self._solve("rt_solve_gmres", b, x, stream)
+
+    def solve_bicgstab(self, x, b=None, stream=None):
+        return self._solve("rt_solve_bicgstab", b, x, stream)
+
+    def solve_richardson(self, x, b=None, stream=None):
+        return self._solve("rt_solve_richardson", b, x, stream)
+
+
+def setup(prob, options: Optional[rt_options] = None, **kw) -> Handle:
+    return Handle(prob, options, **kw)

@@ -1,0 +1,536 @@
+// rt_api.hip -- host runtime behind include/rt.h: validation, launch
+// planning, device memory, setup kernels, and the C entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdint>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "rt_internal.h"
+
+namespace rt {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+hipError_t launch_scale(const double *v, const double *d, double *z, long long n, hipStream_t s);
+int run_solver(rt_handle *h, int kind, const double *b, double *x, rt_solve_info *info,
+               hipStream_t s);
+
+namespace {
+
+bool finite(double v) { return std::isfinite(v); }
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+std::string idx(const char *name, long long i) {
+    return std::string(name) + "[" + std::to_string(i) + "]";
+}
+
+// Validation of the problem and options.  Pure host code: no HIP call.
+// On success fills the positive half of the symmetric direction set.
+int validate(const rt_problem *p, const rt_options *o, std::vector<double> &mu_pos,
+             std::vector<double> &w_pos) {
+    if (!p) return fail(RT_EINVAL, "problem is NULL");
+    if (p->n_atm < 1) return fail(RT_EINVAL, "n_atm must be >= 1");
+    if (!p->ns || !p->tau || !p->mu || !p->w_mu || !p->w_nu || !p->phi || !p->opac || !p->eps ||
+        !p->W2)
+        return fail(RT_EINVAL, "a required problem array is NULL");
+    long long total = 0;
+    for (int a = 0; a < p->n_atm; ++a) {
+        if (p->ns[a] < 2 || p->ns[a] > RT_MAX_NS)
+            return fail(RT_EINVAL, idx("ns", a) + " must be in [2, " +
+                                       std::to_string(RT_MAX_NS) + "]");
+        total += p->ns[a];
+    }
+    if (total > (1LL << 30)) return fail(RT_EINVAL, "too many depth points");
+    long long off = 0;
+    for (int a = 0; a < p->n_atm; ++a) {
+        for (int k = 0; k < p->ns[a]; ++k) {
+            const double t = p->tau[off + k];
+            if (!finite(t)) return fail(RT_EINVAL, idx("tau", off + k) + " is not finite");
+            if (k > 0 && !(t > p->tau[off + k - 1]))
+                return fail(RT_EINVAL, idx("tau", off + k) + " is not strictly increasing");
+        }
+        off += p->ns[a];
+    }
+    if (p->n_mu < 2 || p->n_mu % 2 != 0 || p->n_mu > 4096)
+        return fail(RT_EINVAL, "n_mu must be even, >= 2");
+    double wsum = 0.0;
+    for (int m = 0; m < p->n_mu; ++m) {
+        if (!finite(p->mu[m]) || p->mu[m] == 0.0 || std::fabs(p->mu[m]) > 1.0)
+            return fail(RT_EINVAL, idx("mu", m) + " must be finite, nonzero, |mu| <= 1");
+        if (!finite(p->w_mu[m]) || !(p->w_mu[m] > 0.0))
+            return fail(RT_EINVAL, idx("w_mu", m) + " must be finite and > 0");
+        wsum += p->w_mu[m];
+    }
+    if (std::fabs(wsum - 2.0) > 1e-10)
+        return fail(RT_EINVAL, "w_mu must sum to 2 (quadrature of (1/2) int dmu on [-1,1])");
+    std::vector<int> order(p->n_mu);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int i, int j) { return p->mu[i] < p->mu[j]; });
+    const int M = p->n_mu / 2;
+    mu_pos.assign(M, 0.0);
+    w_pos.assign(M, 0.0);
+    for (int i = 0; i < M; ++i) {
+        const int lo = order[M - 1 - i], hi = order[M + i];
+        const double mn = p->mu[lo], mp = p->mu[hi];
+        if (!(mp > 0.0) || !(mn < 0.0) || std::fabs(mp + mn) > 1e-12 * std::fabs(mp))
+            return fail(RT_EINVAL, "mu must be symmetric: every mu > 0 needs a -mu partner");
+        if (std::fabs(p->w_mu[lo] - p->w_mu[hi]) > 1e-12 * p->w_mu[hi])
+            return fail(RT_EINVAL, "w_mu must be equal for mu and -mu");
+        mu_pos[i] = mp;
+        w_pos[i] = p->w_mu[hi];
+    }
+    if (p->n_nu < 1 || p->n_nu > (1 << 20)) return fail(RT_EINVAL, "n_nu must be >= 1");
+    for (int q = 0; q < p->n_nu; ++q)
+        if (!finite(p->w_nu[q]) || p->w_nu[q] < 0.0)
+            return fail(RT_EINVAL, idx("w_nu", q) + " must be finite and >= 0");
+    for (int a = 0; a < p->n_atm; ++a) {
+        double sw = 0.0;
+        for (int q = 0; q < p->n_nu; ++q) {
+            const long long e = (long long)a * p->n_nu + q;
+            if (!finite(p->phi[e]) || p->phi[e] < 0.0)
+                return fail(RT_EINVAL, idx("phi", e) + " must be finite and >= 0");
+            if (!finite(p->opac[e]) || !(p->opac[e] > 0.0))
+                return fail(RT_EINVAL, idx("opac", e) + " must be finite and > 0");
+            sw += p->w_nu[q] * p->phi[e];
+        }
+        if (!(sw > 0.0)) return fail(RT_EINVAL, "sum of w_nu * phi must be > 0 for every slab");
+        if (!finite(p->eps[a]) || p->eps[a] < 0.0 || p->eps[a] > 1.0)
+            return fail(RT_EINVAL, idx("eps", a) + " must be in [0, 1]");
+        if (!finite(p->W2[a])) return fail(RT_EINVAL, idx("W2", a) + " is not finite");
+        if (p->I_bot && !finite(p->I_bot[a]))
+            return fail(RT_EINVAL, idx("I_bot", a) + " is not finite");
+    }
+    if (p->B)
+        for (long long k = 0; k < total; ++k)
+            if (!finite(p->B[k])) return fail(RT_EINVAL, idx("B", k) + " is not finite");
+    if (p->formal_solver != RT_FS_DELO_LINEAR && p->formal_solver != RT_FS_TRAPEZOIDAL)
+        return fail(RT_EINVAL, "formal_solver must be RT_FS_DELO_LINEAR or RT_FS_TRAPEZOIDAL");
+    if (o) {
+        if (o->precision != RT_PREC_FP64 && o->precision != RT_PREC_MIXED)
+            return fail(RT_EINVAL, "options.precision must be RT_PREC_FP64 or RT_PREC_MIXED");
+        if (o->restart < 1 || o->restart > RT_MAX_RESTART)
+            return fail(RT_EINVAL, "options.restart must be in [1, RT_MAX_RESTART]");
+        if (o->maxit < 0) return fail(RT_EINVAL, "options.maxit must be >= 0");
+        if (!(o->rtol > 0.0) || !finite(o->rtol)) return fail(RT_EINVAL, "options.rtol must be > 0");
+        if (!(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0))
+            return fail(RT_EINVAL, "options.inner_rtol must be in (0, 1)");
+        if (o->max_outer < 1) return fail(RT_EINVAL, "options.max_outer must be >= 1");
+        if (o->inner_maxit < 1) return fail(RT_EINVAL, "options.inner_maxit must be >= 1");
+        if (o->chunk != 0 && !sweep_chunk_supported(o->chunk, false))
+            return fail(RT_EINVAL, "options.chunk must be 0, 4, 8, 16 or 32");
+        if (o->check_every < 1) return fail(RT_EINVAL, "options.check_every must be >= 1");
+        if (o->wave_batches < 0 || o->wave_batches > 64)
+            return fail(RT_EINVAL, "options.wave_batches must be in [0, 64]");
+    }
+    return RT_OK;
+}
+
+int chunks_for(int ns, int L) {
+    const int x = ns - 1;
+    int C = 1;
+    while (C < kWave && C * L < x) C <<= 1;
+    return C;
+}
+
+// Chunk length: the largest L whose lane count fills the chip (about two
+// waves per SIMD) -- longer chunks mean fewer scan steps and partial sums --
+// else the shortest, for the most parallelism on small problems.
+int auto_chunk(const std::vector<int> &ns, int rays) {
+    const long long target = 256LL * 4 * kWave * 2;
+    int best = 4;
+    for (int L : {4, 8, 16}) {
+        bool fits = true;
+        long long lanes = 0;
+        for (int n : ns) {
+            const int C = chunks_for(n, L);
+            if ((long long)C * L < n - 1) fits = false;
+            lanes += (long long)rays * C;
+        }
+        if (fits && lanes >= target) best = L;
+    }
+    // a slab deeper than 64 * best intervals needs longer chunks
+    for (int n : ns)
+        while (best < 32 && (long long)kWave * best < n - 1) best *= 2;
+    return best;
+}
+
+template <typename T>
+int dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return RT_OK;
+    if (hipMalloc((void **)p, count * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(RT_ENOMEM, "device allocation of " + std::to_string(count * sizeof(T)) +
+                                   " bytes failed");
+    }
+    return RT_OK;
+}
+
+template <typename T>
+int h2d(T *dst, const T *src, size_t count) {
+    if (count == 0) return RT_OK;
+    if (hipMemcpy(dst, src, count * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(RT_EDEVICE, "host to device copy failed");
+    return RT_OK;
+}
+
+int hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return RT_OK;
+    return fail(RT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, double *out,
+                          const int *mask, bool fp32, int mode, hipStream_t s) {
+    SweepArgs a{};
+    a.atm = h->d_atm;
+    a.blk = h->d_blk;
+    a.coef = fp32 ? (const void *)h->d_coef32 : (const void *)h->d_coef64;
+    a.rayc = h->d_rayc;
+    a.sig_in = in;
+    a.scale = scale;
+    a.sig_out = out;
+    a.partial = h->d_partial;
+    a.mask = mask;
+    a.B = h->d_B;
+    a.mode = mode;
+    hipError_t e = launch_sweep(h->L, fp32, a, h->n_blocks, h->ns_max, s);
+    if (e != hipSuccess) return e;
+    return launch_finalize(a, h->d_pt_atm, h->ns_total, s);
+}
+
+int ensure_workspace(rt_handle *h) {
+    const int m = h->opt.restart;
+    if (h->d_V && h->ws_restart == m) return RT_OK;
+    (void)hipFree(h->d_V);
+    h->d_V = nullptr;
+    const long long N = h->n_unk;
+    int rc;
+    if ((rc = dalloc(&h->d_V, (size_t)(m + 1) * N)) != RT_OK) return rc;
+    if (!h->d_H) {
+        // restart-independent buffers, sized for the largest restart
+        const int mm = RT_MAX_RESTART;
+        if ((rc = dalloc(&h->d_H, (size_t)h->n_atm * (mm + 1) * mm)) != RT_OK) return rc;
+        if ((rc = dalloc(&h->d_cs, (size_t)h->n_atm * mm)) != RT_OK) return rc;
+        if ((rc = dalloc(&h->d_sn, (size_t)h->n_atm * mm)) != RT_OK) return rc;
+        if ((rc = dalloc(&h->d_g, (size_t)h->n_atm * (mm + 1))) != RT_OK) return rc;
+        double **vecs[] = {&h->d_w, &h->d_r, &h->d_rh, &h->d_p, &h->d_v, &h->d_s, &h->d_t};
+        for (double **v : vecs)
+            if ((rc = dalloc(v, (size_t)N)) != RT_OK) return rc;
+        if ((rc = dalloc(&h->d_state, (size_t)2 * h->n_atm)) != RT_OK) return rc;
+        if ((rc = dalloc(&h->d_active, (size_t)2 * h->n_atm)) != RT_OK) return rc;
+        if ((rc = dalloc(&h->d_cycle, (size_t)h->n_atm)) != RT_OK) return rc;
+        if ((rc = dalloc(&h->d_count, 1)) != RT_OK) return rc;
+        if (hipHostMalloc((void **)&h->h_count, sizeof(int)) != hipSuccess) {
+            h->h_count = nullptr;
+            return fail(RT_ENOMEM, "pinned host allocation failed");
+        }
+    }
+    h->ws_restart = m;
+    return RT_OK;
+}
+
+}  // namespace rt
+
+using namespace rt;
+
+extern "C" {
+
+void rt_default_options(rt_options *o) {
+    if (!o) return;
+    o->precision = RT_PREC_FP64;
+    o->restart = 30;
+    o->maxit = 10000;
+    o->rtol = 1e-10;
+    o->inner_rtol = 1e-4;
+    o->inner_maxit = 100;
+    o->max_outer = 30;
+    o->chunk = 0;
+    o->wave_batches = 0;
+    o->check_every = 16;
+}
+
+const char *rt_last_error(void) { return g_err.c_str(); }
+
+int rt_num_unknowns(const rt_handle *h) { return h ? h->n_unk : 0; }
+
+void rt_destroy(rt_handle *h) {
+    if (!h) return;
+    void *ptrs[] = {h->d_tau,   h->d_B,     h->d_opac,    h->d_phi,     h->d_mu_pos, h->d_w_pos,
+                    h->d_w_nu,  h->d_pt_atm, h->d_atm,    h->d_blk,     h->d_rayc,   h->d_coef64,
+                    h->d_coef32, h->d_partial, h->d_diag,  h->d_dinv,   h->d_b,
+                    h->d_V,     h->d_H,     h->d_cs,      h->d_sn,      h->d_g,      h->d_w,
+                    h->d_r,     h->d_rh,    h->d_p,       h->d_v,       h->d_s,      h->d_t,
+                    h->d_xd,    h->d_state, h->d_active,  h->d_cycle,   h->d_count};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (h->h_count) (void)hipHostFree(h->h_count);
+    delete h;
+}
+
+int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
+    if (!out) return fail(RT_EINVAL, "handle pointer is NULL");
+    *out = nullptr;
+    rt_options opt;
+    rt_default_options(&opt);
+    if (o) opt = *o;
+    std::vector<double> mu_pos, w_pos;
+    int rc = validate(p, &opt, mu_pos, w_pos);
+    if (rc != RT_OK) return rc;
+
+    // ---- device
+    int dev = 0, ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(RT_EDEVICE, "no HIP device available");
+    }
+    if (hipGetDevice(&dev) != hipSuccess) return fail(RT_EDEVICE, "hipGetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(RT_EDEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(RT_EDEVICE, std::string("this library is built for gfx950, device is ") +
+                                    prop.gcnArchName);
+
+    rt_handle *h = new rt_handle();
+    h->device = dev;
+    h->opt = opt;
+    h->n_atm = p->n_atm;
+    h->n_mu = p->n_mu;
+    h->M = p->n_mu / 2;
+    h->n_nu = p->n_nu;
+    h->fs = p->formal_solver;
+    h->normalize = p->normalize_profile != 0;
+    h->ns.assign(p->ns, p->ns + p->n_atm);
+    h->doff.resize(h->n_atm);
+    int acc = 0;
+    for (int a = 0; a < h->n_atm; ++a) {
+        h->doff[a] = acc;
+        acc += h->ns[a];
+        h->ns_max = std::max(h->ns_max, h->ns[a]);
+    }
+    h->ns_total = acc;
+    h->n_unk = 2 * acc;
+
+    // ---- plan: chunks, wave-batches, blocks, tiles, partial sums
+    const int rays = h->M * h->n_nu;
+    h->L = opt.chunk ? opt.chunk : auto_chunk(h->ns, rays);
+    for (int n : h->ns)
+        if ((long long)kWave * h->L < n - 1) {
+            delete h;
+            return fail(RT_EINVAL, "options.chunk too short for ns (need 64 * chunk >= ns - 1)");
+        }
+    long long coef = 0, part = 0;
+    int blk = 0;
+    // waves per block and wave-batches per wave: aim for at most ~16 blocks
+    // per slab so the cross-block combination stays one short round of loads
+    h->W = sweep_waves(h->L, false);
+    {
+        long long nwb_max = 0;
+        for (int n : h->ns) {
+            const int C = chunks_for(n, h->L);
+            nwb_max = std::max<long long>(nwb_max, (rays + kWave / C - 1) / (kWave / C));
+        }
+        h->NB = (int)std::min<long long>(8, std::max<long long>(1, (nwb_max + 16LL * h->W - 1) /
+                                                                      (16LL * h->W)));
+        if (opt.chunk == 0 && h->n_atm > 1) h->NB = std::min(h->NB, 2);
+        if (opt.wave_batches > 0) h->NB = opt.wave_batches;
+    }
+    const int wb_per_block = h->W * h->NB;
+    h->atm_h.resize(h->n_atm);
+    for (int a = 0; a < h->n_atm; ++a) {
+        AtmDesc d{};
+        d.ns = h->ns[a];
+        d.doff = h->doff[a];
+        d.C = chunks_for(d.ns, h->L);
+        d.Leff = (d.ns - 1 + d.C - 1) / d.C;
+        d.G = kWave / d.C;
+        d.nrays = rays;
+        d.ray_off = a * rays;
+        d.nwb = (rays + d.G - 1) / d.G;
+        d.nblk = (d.nwb + wb_per_block - 1) / wb_per_block;
+        d.blk_first = blk;
+        d.coef_off = coef;
+        d.part_off = part;
+        d.eps = p->eps[a];
+        d.xi = 1.0 - p->eps[a];
+        d.W2 = p->W2[a];
+        d.Ibot = p->I_bot ? p->I_bot[a] : (p->B ? p->B[d.doff + d.ns - 1] : 1.0);
+        for (int b = 0; b < d.nblk; ++b) {
+            BlockDesc bd{};
+            bd.atm = a;
+            bd.wb_first = b * wb_per_block;
+            bd.wb_count = std::min(wb_per_block, d.nwb - bd.wb_first);
+            h->blk_h.push_back(bd);
+        }
+        blk += d.nblk;
+        coef += (long long)d.nwb * d.Leff * kWave;
+        part += (long long)d.nblk * 2 * d.ns;
+        h->atm_h[a] = d;
+    }
+    h->n_blocks = blk;
+    h->n_pairs = coef;
+    h->n_partial = part;
+
+    // ---- device memory
+    std::vector<int> pt_atm(acc);
+    for (int a = 0; a < h->n_atm; ++a)
+        std::fill(pt_atm.begin() + h->doff[a], pt_atm.begin() + h->doff[a] + h->ns[a], a);
+    std::vector<double> B(acc, 1.0);
+    if (p->B) std::copy(p->B, p->B + acc, B.begin());
+    const size_t nphi = (size_t)h->n_atm * h->n_nu;
+#define RT_TRY(x)            \
+    do {                     \
+        int _rc = (x);       \
+        if (_rc != RT_OK) {  \
+            rt_destroy(h);   \
+            return _rc;      \
+        }                    \
+    } while (0)
+    RT_TRY(dalloc(&h->d_tau, acc));
+    RT_TRY(dalloc(&h->d_B, acc));
+    RT_TRY(dalloc(&h->d_opac, nphi));
+    RT_TRY(dalloc(&h->d_phi, nphi));
+    RT_TRY(dalloc(&h->d_mu_pos, h->M));
+    RT_TRY(dalloc(&h->d_w_pos, h->M));
+    RT_TRY(dalloc(&h->d_w_nu, h->n_nu));
+    RT_TRY(dalloc(&h->d_pt_atm, acc));
+    RT_TRY(dalloc(&h->d_atm, h->n_atm));
+    RT_TRY(dalloc(&h->d_blk, h->n_blocks));
+    RT_TRY(dalloc(&h->d_rayc, (size_t)h->n_atm * rays));
+    RT_TRY(dalloc(&h->d_coef64, h->n_pairs));
+    RT_TRY(dalloc(&h->d_coef32, h->n_pairs));
+    RT_TRY(dalloc(&h->d_partial, std::max<long long>(h->n_partial, 1)));
+    RT_TRY(dalloc(&h->d_diag, h->n_unk));
+    RT_TRY(dalloc(&h->d_dinv, h->n_unk));
+    RT_TRY(dalloc(&h->d_b, h->n_unk));
+    RT_TRY(h2d(h->d_tau, p->tau, acc));
+    RT_TRY(h2d(h->d_B, B.data(), acc));
+    RT_TRY(h2d(h->d_opac, p->opac, nphi));
+    RT_TRY(h2d(h->d_phi, p->phi, nphi));
+    RT_TRY(h2d(h->d_mu_pos, mu_pos.data(), h->M));
+    RT_TRY(h2d(h->d_w_pos, w_pos.data(), h->M));
+    RT_TRY(h2d(h->d_w_nu, p->w_nu, h->n_nu));
+    RT_TRY(h2d(h->d_pt_atm, pt_atm.data(), acc));
+    RT_TRY(h2d(h->d_atm, h->atm_h.data(), h->n_atm));
+    RT_TRY(h2d(h->d_blk, h->blk_h.data(), h->n_blocks));
+
+    // ---- precompute: ray constants, tile coefficients, D and D^-1, b
+    hipStream_t s = nullptr;
+    RT_TRY(hip_check(launch_ray_setup(h->n_atm, h->d_atm, h->d_mu_pos, h->d_w_pos, h->M,
+                                      h->d_w_nu, h->d_phi, h->n_nu, h->normalize, h->d_rayc, s),
+                     "ray setup launch"));
+    RT_TRY(hip_check(launch_coef_build(h->n_blocks, h->W, h->d_atm, h->d_blk, h->d_tau, h->d_opac,
+                                       h->d_mu_pos, h->n_nu, h->fs, h->d_coef64, h->d_coef32, s),
+                     "coefficient launch"));
+    RT_TRY(hip_check(launch_diag(acc, h->d_pt_atm, h->d_atm, h->d_tau, h->d_opac, h->d_mu_pos,
+                                 h->d_rayc, h->M, h->n_nu, h->fs, h->d_diag, h->d_dinv, s),
+                     "diagonal launch"));
+    RT_TRY(hip_check(apply_operator(h, nullptr, nullptr, h->d_b, nullptr, false, 1, s),
+                     "right-hand side launch"));
+    RT_TRY(hip_check(hipDeviceSynchronize(), "setup"));
+#undef RT_TRY
+    *out = h;
+    return RT_OK;
+}
+
+int rt_apply_op(rt_handle *h, const double *sigma_in, double *sigma_out, void *stream) {
+    if (!h || !sigma_in || !sigma_out) return fail(RT_EINVAL, "NULL handle or vector");
+    if (!aligned16(sigma_in) || !aligned16(sigma_out))
+        return fail(RT_EINVAL, "vectors must be 16-byte aligned");
+    return hip_check(apply_operator(h, sigma_in, nullptr, sigma_out, nullptr, false, 0,
+                                    (hipStream_t)stream),
+                     "rt_apply_op");
+}
+
+int rt_apply_op_fp32(rt_handle *h, const double *sigma_in, double *sigma_out, void *stream) {
+    if (!h || !sigma_in || !sigma_out) return fail(RT_EINVAL, "NULL handle or vector");
+    if (!aligned16(sigma_in) || !aligned16(sigma_out))
+        return fail(RT_EINVAL, "vectors must be 16-byte aligned");
+    return hip_check(apply_operator(h, sigma_in, nullptr, sigma_out, nullptr, true, 0,
+                                    (hipStream_t)stream),
+                     "rt_apply_op_fp32");
+}
+
+int rt_precond_jacobi(rt_handle *h, const double *v, double *z, void *stream) {
+    if (!h || !v || !z) return fail(RT_EINVAL, "NULL handle or vector");
+    if (!aligned16(v) || !aligned16(z)) return fail(RT_EINVAL, "vectors must be 16-byte aligned");
+    return hip_check(launch_scale(v, h->d_dinv, z, h->n_unk, (hipStream_t)stream),
+                     "rt_precond_jacobi");
+}
+
+int rt_get_rhs(rt_handle *h, double *b, void *stream) {
+    if (!h || !b) return fail(RT_EINVAL, "NULL handle or vector");
+    return hip_check(hipMemcpyAsync(b, h->d_b, sizeof(double) * h->n_unk,
+                                    hipMemcpyDeviceToDevice, (hipStream_t)stream),
+                     "rt_get_rhs");
+}
+
+int rt_get_jacobi_diag(rt_handle *h, double *d, void *stream) {
+    if (!h || !d) return fail(RT_EINVAL, "NULL handle or vector");
+    return hip_check(hipMemcpyAsync(d, h->d_diag, sizeof(double) * h->n_unk,
+                                    hipMemcpyDeviceToDevice, (hipStream_t)stream),
+                     "rt_get_jacobi_diag");
+}
+
+int rt_solve_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *info, void *stream) {
+    if (!h || !x) return fail(RT_EINVAL, "NULL handle or x");
+    if (!aligned16(x) || (b && !aligned16(b))) return fail(RT_EINVAL, "vectors must be 16-byte aligned");
+    return run_solver(h, 0, b, x, info, (hipStream_t)stream);
+}
+
+int rt_solve_bicgstab(rt_handle *h, const double *b, double *x, rt_solve_info *info,
+                      void *stream) {
+    if (!h || !x) return fail(RT_EINVAL, "NULL handle or x");
+    if (!aligned16(x) || (b && !aligned16(b))) return fail(RT_EINVAL, "vectors must be 16-byte aligned");
+    return run_solver(h, 1, b, x, info, (hipStream_t)stream);
+}
+
+int rt_solve_richardson(rt_handle *h, const double *b, double *x, rt_solve_info *info,
+                        void *stream) {
+    if (!h || !x) return fail(RT_EINVAL, "NULL handle or x");
+    if (!aligned16(x) || (b && !aligned16(b))) return fail(RT_EINVAL, "vectors must be 16-byte aligned");
+    return run_solver(h, 2, b, x, info, (hipStream_t)stream);
+}
+
+// Sweep-plan introspection for tests and benchmarks (not in the public header).
+int rt_plan_info(const rt_handle *h, int *chunk_L, int *n_blocks, long long *n_pairs,
+                 long long *n_intervals) {
+    if (!h) return fail(RT_EINVAL, "NULL handle");
+    if (chunk_L) *chunk_L = h->L;
+    if (n_blocks) *n_blocks = h->n_blocks;
+    if (n_pairs) *n_pairs = h->n_pairs;
+    if (n_intervals) {
+        long long s = 0;
+        for (int n : h->ns) s += (long long)(n - 1) * h->M * h->n_nu;
+        *n_intervals = s;
+    }
+    return RT_OK;
+}
+
+// Validation only, without touching the device (tests of the error paths).
+int rt_validate(const rt_problem *p, const rt_options *o) {
+    std::vector<double> mp, wp;
+    rt_options opt;
+    rt_default_options(&opt);
+    if (o) opt = *o;
+    return validate(p, &opt, mp, wp);
+}
+
+}  // extern "C"

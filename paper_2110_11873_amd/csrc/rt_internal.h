@@ -1,0 +1,165 @@
+// rt_internal.h -- internal types shared by the host runtime and the kernels
+// of the gfx950 library behind include/rt.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "rt.h"
+#include "rt_ext.h"
+
+namespace rt {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kSweepLdsBudget = 64 * 1024;  // bytes of LDS a sweep block may use
+constexpr int kKrylovThreads = 256;
+constexpr int kKrylovEPT = (2 * RT_MAX_NS + kKrylovThreads - 1) / kKrylovThreads;
+
+// Per-slab launch plan of the formal-solver sweep.  A ray is one (|mu|, nu)
+// pair; its depth recurrence is split into C chunks of Leff intervals, one
+// chunk per lane, G = 64 / C rays per wavefront ("wave-batch").
+struct AtmDesc {
+    int ns;         // depth points
+    int doff;       // first depth point of the slab in concatenated arrays
+    int C;          // chunks per ray (power of two, <= 64)
+    int Leff;       // intervals per chunk (<= the kernel's L)
+    int G;          // rays per wave-batch
+    int nrays;      // rays: (n_mu / 2) * n_nu
+    int ray_off;    // first entry of the slab in the ray-constant table
+    int nwb;        // wave-batches
+    int blk_first;  // first sweep block of the slab
+    int nblk;       // sweep blocks of the slab
+    long long coef_off;  // first coefficient pair of the slab's tiles
+    long long part_off;  // first partial sum of the slab's blocks
+    double xi;      // 1 - eps
+    double W2;      // polarizability
+    double eps;     // thermalization
+    double Ibot;    // bottom inflow for mu > 0
+};
+
+// One sweep block: wave w of a block of W waves handles wave-batches
+// wb_first + w + t * W, t = 0, 1, ..., while < wb_first + wb_count.
+struct BlockDesc {
+    int atm;
+    int wb_first;
+    int wb_count;
+    int pad;
+};
+
+// Quadrature weight of a ray (applied to both directions of the +-mu pair)
+// and its products with the T^2_0 factors: q, q T1, q (T1^2 + T2^2).
+struct RayConst {
+    double q, qt1, qt12, pad;
+};
+
+struct SweepArgs {
+    const AtmDesc *atm;
+    const BlockDesc *blk;
+    const void *coef;        // tile-ordered step coefficients (T pairs)
+    const RayConst *rayc;
+    const double *sig_in;    // FP64 input, NULL = zero source
+    const double *scale;     // optional elementwise scaling of sig_in
+    double *sig_out;         // FP64 output
+    double *partial;         // per-block partial quadrature sums
+    const int *mask;         // optional per-slab activity mask
+    const double *B;         // Planck function (right-hand-side mode)
+    int mode;                // 0: sigma_out = z - xi [J00, W2 J20]
+                             // 1: sigma_out = xi [J00, W2 J20] + [eps B, 0],
+                             //    with the bottom inflow and no source
+    int rows;                // 1: one LDS row per wave (W * 2 ns_max values),
+                             // 0: one shared row filled wave after wave
+};
+
+// Waves per sweep block for a chunk length and precision: as many as the
+// register footprint allows at two waves per SIMD.
+int sweep_waves(int L, bool fp32);
+
+// Launch helpers (rt_sweep.hip).  launch_sweep writes the per-block partial
+// quadrature sums; launch_finalize turns them into sigma_out.
+hipError_t launch_sweep(int L, bool fp32, const SweepArgs &a, int nblocks, int ns_max,
+                        hipStream_t s);
+hipError_t launch_finalize(const SweepArgs &a, const int *pt_atm, int npts, hipStream_t s);
+hipError_t launch_coef_build(int nblocks, int W, const AtmDesc *atm, const BlockDesc *blk,
+                             const double *tau, const double *opac, const double *mu_pos,
+                             int n_nu, int fs, double2 *coef64, float2 *coef32, hipStream_t s);
+hipError_t launch_ray_setup(int n_atm, const AtmDesc *atm, const double *mu_pos,
+                            const double *w_pos, int M, const double *w_nu, const double *phi,
+                            int n_nu, int normalize, RayConst *rayc, hipStream_t s);
+hipError_t launch_diag(int npts, const int *pt_atm, const AtmDesc *atm, const double *tau,
+                       const double *opac, const double *mu_pos, const RayConst *rayc, int M,
+                       int n_nu, int fs, double *diag, double *dinv, hipStream_t s);
+bool sweep_chunk_supported(int L, bool fp32);
+
+// Krylov state kept on the device, one entry per slab.
+struct KState {
+    double bnorm;     // ||b||
+    double beta;      // last explicit residual norm
+    double resid;     // GMRES residual estimate |g_{j+1}|
+    double rho, alpha, omega, rho_old;  // BiCGSTAB scalars
+    double relres;    // final explicit relative residual
+    int status;       // RT_OK / RT_ENOCONV / RT_EBREAKDOWN
+    int iters;        // iterations counted for maxit
+    int matvecs;      // applications of A
+    int inner;        // GMRES: Arnoldi steps in the current cycle
+    int outer;        // mixed precision: refinement steps
+    int half_done;    // BiCGSTAB: converged at the half step
+    int pad0, pad1;
+};
+
+}  // namespace rt
+
+// The handle (opaque to C callers).
+struct rt_handle {
+    int device = 0;
+    int n_atm = 0, n_mu = 0, M = 0, n_nu = 0, fs = 0, normalize = 0;
+    int n_unk = 0, ns_total = 0, ns_max = 0;
+    rt_options opt{};
+    std::vector<int> ns, doff;
+    std::vector<rt::AtmDesc> atm_h;
+    std::vector<rt::BlockDesc> blk_h;
+    int L = 8;                 // chunk length the tiles were built for
+    int W = 8;                 // waves per sweep block the plan was made for
+    int NB = 1;                // wave-batches per wave (per block: W * NB)
+    int n_blocks = 0;
+    long long n_pairs = 0, n_partial = 0;
+
+    // device copies of the problem
+    double *d_tau = nullptr, *d_B = nullptr, *d_opac = nullptr, *d_phi = nullptr;
+    double *d_mu_pos = nullptr, *d_w_pos = nullptr, *d_w_nu = nullptr;
+    int *d_pt_atm = nullptr;
+    rt::AtmDesc *d_atm = nullptr;
+    rt::BlockDesc *d_blk = nullptr;
+    rt::RayConst *d_rayc = nullptr;
+    double2 *d_coef64 = nullptr;
+    float2 *d_coef32 = nullptr;
+    double *d_partial = nullptr;
+    double *d_diag = nullptr, *d_dinv = nullptr, *d_b = nullptr;
+
+    // solver workspace (allocated on first use)
+    int ws_restart = 0;
+    double *d_V = nullptr;      // (restart + 1) x N Krylov basis
+    double *d_H = nullptr;      // per slab (restart + 1) x restart Hessenberg
+    double *d_cs = nullptr, *d_sn = nullptr, *d_g = nullptr;
+    double *d_w = nullptr;      // operator output
+    double *d_r = nullptr, *d_rh = nullptr, *d_p = nullptr, *d_v = nullptr, *d_s = nullptr,
+           *d_t = nullptr;      // BiCGSTAB / refinement vectors
+    double *d_xd = nullptr;     // refinement correction
+    rt::KState *d_state = nullptr;
+    int *d_active = nullptr;    // per slab: still iterating
+    int *d_cycle = nullptr;     // per slab: GMRES cycle still running
+    int *d_count = nullptr;     // reduction target for host checks
+    int *h_count = nullptr;     // pinned host mirror
+};
+
+namespace rt {
+// sigma_out = A (scale .* sigma_in) for the slabs whose mask is set (all if
+// mask is NULL): the sweep, then the finalize pass.  mode as in SweepArgs.
+hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, double *out,
+                          const int *mask, bool fp32, int mode, hipStream_t s);
+
+// Thread-local error message for rt_last_error.
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+}  // namespace rt

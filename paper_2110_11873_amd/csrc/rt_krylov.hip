@@ -1,0 +1,939 @@
+// rt_krylov.hip -- Jacobi-preconditioned GMRES(m), BiCGSTAB and Richardson
+// on gfx950, batched over independent slabs.
+//
+// Every vector kernel uses one workgroup per slab (a slab has at most
+// 2 * RT_MAX_NS unknowns), so a batch of slabs of uneven depth needs no
+// grid-wide reduction and every slab keeps its own scalars, counters and
+// convergence flag.  The operator is applied by the fused sweep; its launches
+// skip converged slabs through a per-slab mask.  The host reads one integer
+// (how many slabs are still active) once per GMRES cycle or every
+// `check_every` iterations.
+//
+// Preconditioning is from the right: x = P^-1 u, so the residual the methods
+// minimize and test is the unpreconditioned ||b - A x|| / ||b|| of Sect. 4.2.
+// The diagonal scaling P^-1 v is folded into the sweep's input load.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "rt_internal.h"
+
+namespace rt {
+
+namespace {
+
+constexpr int NT = kKrylovThreads;
+constexpr int NW = NT / kWave;
+
+__device__ inline double wave_sum(double v) {
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Block-wide sums of two values; every thread receives the same results.
+__device__ inline void block_sum2(double &a, double &b, double *red) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red[2 * (threadIdx.x / kWave)] = a;
+        red[2 * (threadIdx.x / kWave) + 1] = b;
+    }
+    __syncthreads();
+    a = b = 0.0;
+    for (int w = 0; w < NW; ++w) {
+        a += red[2 * w];
+        b += red[2 * w + 1];
+    }
+    __syncthreads();
+}
+
+__device__ inline double block_sum(double a, double *red) {
+    double b = 0.0;
+    block_sum2(a, b, red);
+    return a;
+}
+
+// Reduce 32 per-lane values over the 64 lanes of a wave with 32 shuffles
+// (recursive halving: at each step a lane keeps one half of its values and
+// receives its partner's copy of that half).  Afterwards lane l holds the
+// sum of value index ((l>>5)&1)*16 + ((l>>4)&1)*8 + ((l>>3)&1)*4 +
+// ((l>>2)&1)*2 + ((l>>1)&1); lanes l and l^1 hold the same value.
+__device__ inline double wave_reduce_scatter32(double (&v)[32]) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const bool up = lane & 32;
+        const double send = up ? v[t] : v[t + 16];
+        const double keep = up ? v[t + 16] : v[t];
+        v[t] = keep + __shfl_xor(send, 32);
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const bool up = lane & 16;
+        const double send = up ? v[t] : v[t + 8];
+        const double keep = up ? v[t + 8] : v[t];
+        v[t] = keep + __shfl_xor(send, 16);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const bool up = lane & 8;
+        const double send = up ? v[t] : v[t + 4];
+        const double keep = up ? v[t + 4] : v[t];
+        v[t] = keep + __shfl_xor(send, 8);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const bool up = lane & 4;
+        const double send = up ? v[t] : v[t + 2];
+        const double keep = up ? v[t + 2] : v[t];
+        v[t] = keep + __shfl_xor(send, 4);
+    }
+    {
+        const bool up = lane & 2;
+        const double send = up ? v[0] : v[1];
+        const double keep = up ? v[1] : v[0];
+        v[0] = keep + __shfl_xor(send, 2);
+    }
+    return v[0] + __shfl_xor(v[0], 1);
+}
+
+__device__ inline int scatter_index(int lane) {
+    return ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 +
+           ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
+}
+
+struct VecArgs {
+    const AtmDesc *atm;
+    long long N;         // total unknowns (row stride of the basis)
+    int m;               // GMRES restart length
+    double *V, *H, *cs, *sn, *g;
+    const double *w;     // operator output
+    const double *b;
+    double *x;
+    const double *dinv;
+    double *r, *rh, *p, *v, *s, *t;  // BiCGSTAB / refinement vectors
+    KState *st;
+    int *active;
+    int *cycle;
+    double tol;
+    int maxit;
+    int max_outer;
+};
+
+// ---------------------------------------------------------------- counting
+__global__ void count_kernel(const int *flags, int n, int *out) {
+    __shared__ int red[NW];
+    int c = 0;
+    for (int i = threadIdx.x; i < n; i += NT) c += flags[i] != 0;
+    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int w = 0; w < NW; ++w) s += red[w];
+        *out = s;
+    }
+}
+
+__global__ void init_state_kernel(KState *st, int *active, int *cycle, int n_atm,
+                                  const int *from_mask) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_atm) return;
+    KState k = {};
+    k.status = RT_ENOCONV;
+    st[i] = k;
+    active[i] = from_mask ? (from_mask[i] != 0) : 1;
+    cycle[i] = 0;
+}
+
+// -------------------------------------------------------------------- GMRES
+// (Re)start a cycle: r = b - A x (A x in w; r = b when x is known to be zero),
+// test it, and set v_0 = r / ||r||, g = [||r||, 0, ...].  accept_est: also
+// accept the previous cycle's Arnoldi residual estimate (inner solves of the
+// mixed-precision refinement, whose explicitly recomputed FP32 residual has a
+// rounding floor well above the estimate; the outer FP64 residual decides).
+__global__ void gm_restart_kernel(VecArgs a, int first, int x_zero, int accept_est) {
+    __shared__ double red[2 * NW];
+    __shared__ int s_go;
+    __shared__ double s_beta;
+    const int atm = blockIdx.x;
+    if (!a.active[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    double rr = 0.0, bb = 0.0;
+    for (int l = threadIdx.x; l < n; l += NT) {
+        const double bl = a.b[base + l];
+        const double rl = x_zero ? bl : bl - a.w[base + l];
+        a.V[base + l] = rl;
+        rr += rl * rl;
+        bb += bl * bl;
+    }
+    block_sum2(rr, bb, red);
+    KState &S = a.st[atm];
+    if (threadIdx.x == 0) {
+        if (first) S.bnorm = sqrt(bb);
+        if (!x_zero) S.matvecs += 1;
+        const double beta = sqrt(rr);
+        S.beta = beta;
+        s_beta = beta;
+        int go = 0;
+        if (S.bnorm == 0.0) {
+            S.status = RT_OK;
+            S.relres = 0.0;
+            go = -1;  // zero right-hand side: x = 0
+        } else if (!(beta == beta) || isinf(beta)) {
+            S.status = RT_EBREAKDOWN;
+            S.relres = beta / S.bnorm;
+        } else if (beta / S.bnorm < a.tol ||
+                   (accept_est && !first && S.resid / S.bnorm < a.tol)) {
+            S.status = RT_OK;
+            S.relres = beta / S.bnorm;
+        } else if (S.iters >= a.maxit) {
+            S.status = RT_ENOCONV;
+            S.relres = beta / S.bnorm;
+        } else {
+            go = 1;
+        }
+        s_go = go;
+        if (go != 1) {
+            a.active[atm] = 0;
+            a.cycle[atm] = 0;
+        } else {
+            S.inner = 0;
+            a.cycle[atm] = 1;
+            double *g = a.g + (long long)atm * (a.m + 1);
+            g[0] = beta;
+            for (int i = 1; i <= a.m; ++i) g[i] = 0.0;
+        }
+    }
+    __syncthreads();
+    if (s_go == -1) {
+        for (int l = threadIdx.x; l < n; l += NT) a.x[base + l] = 0.0;
+    } else if (s_go == 1) {
+        const double inv = 1.0 / s_beta;
+        for (int l = threadIdx.x; l < n; l += NT) a.V[base + l] *= inv;
+    }
+}
+
+// One Arnoldi step j: w = A P^-1 v_j is in a.w.  Classical Gram-Schmidt twice
+// (h = V^T w; w -= V h; repeated), h_{j+1,j} = ||w||, v_{j+1} = w / ||w||,
+// then the Givens rotations of the Hessenberg column and the residual
+// estimate |g_{j+1}| (Saad & Schultz).  E: vector elements per thread; the
+// basis is read 32 rows at a time so that 32 loads per element are in flight.
+template <int E>
+__global__ __launch_bounds__(NT) void gm_arnoldi_kernel(VecArgs a, int j) {
+    __shared__ double red[32 * NW];
+    __shared__ double hsum[RT_MAX_RESTART + 1];
+    __shared__ double hp[RT_MAX_RESTART + 1];
+    __shared__ double red2[2 * NW];
+    const int atm = blockIdx.x;
+    if (!a.cycle[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+
+    double wl[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int l = tid + e * NT;
+        wl[e] = (l < n) ? a.w[base + l] : 0.0;
+    }
+    for (int i = tid; i <= j; i += NT) hsum[i] = 0.0;
+
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i0 = 0; i0 <= j; i0 += 32) {
+            const int cnt = min(32, j + 1 - i0);
+            double part[32];
+#pragma unroll
+            for (int t = 0; t < 32; ++t) part[t] = 0.0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int l = tid + e * NT;
+                if (l < n) {
+                    const double *vp = a.V + (long long)i0 * a.N + base + l;
+#pragma unroll
+                    for (int t = 0; t < 32; ++t)
+                        if (t < cnt) part[t] += vp[(long long)t * a.N] * wl[e];
+                }
+            }
+            const double sum = wave_reduce_scatter32(part);
+            if ((lane & 1) == 0) red[scatter_index(lane) * NW + wave] = sum;
+            __syncthreads();
+            if (tid < cnt) {
+                double s = 0.0;
+                for (int w = 0; w < NW; ++w) s += red[tid * NW + w];
+                hp[i0 + tid] = s;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int l = tid + e * NT;
+            if (l < n) {
+                double s = 0.0;
+                for (int i0 = 0; i0 <= j; i0 += 32) {
+                    const int cnt = min(32, j + 1 - i0);
+                    const double *vp = a.V + (long long)i0 * a.N + base + l;
+                    double v[32];
+#pragma unroll
+                    for (int t = 0; t < 32; ++t) v[t] = (t < cnt) ? vp[(long long)t * a.N] : 0.0;
+#pragma unroll
+                    for (int t = 0; t < 32; ++t)
+                        if (t < cnt) s += hp[i0 + t] * v[t];
+                }
+                wl[e] -= s;
+            }
+        }
+        for (int i = tid; i <= j; i += NT) hsum[i] += hp[i];
+        __syncthreads();
+    }
+
+    double nn = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) nn += wl[e] * wl[e];
+    const double hn = sqrt(block_sum(nn, red2));
+    if (hn > 0.0) {
+        const double inv = 1.0 / hn;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int l = tid + e * NT;
+            if (l < n) a.V[(long long)(j + 1) * a.N + base + l] = wl[e] * inv;
+        }
+    }
+    if (tid == 0) {
+        const int m = a.m;
+        double *H = a.H + (long long)atm * (m + 1) * m;
+        double *cs = a.cs + (long long)atm * m;
+        double *sn = a.sn + (long long)atm * m;
+        double *g = a.g + (long long)atm * (m + 1);
+        for (int i = 0; i <= j; ++i) H[i * m + j] = hsum[i];
+        for (int i = 0; i < j; ++i) {  // earlier rotations
+            const double h0 = H[i * m + j], h1 = H[(i + 1) * m + j];
+            H[i * m + j] = cs[i] * h0 + sn[i] * h1;
+            H[(i + 1) * m + j] = -sn[i] * h0 + cs[i] * h1;
+        }
+        const double hjj = H[j * m + j];
+        const double den = sqrt(hjj * hjj + hn * hn);
+        const double c = (den > 0.0) ? hjj / den : 1.0;
+        const double s = (den > 0.0) ? hn / den : 0.0;
+        cs[j] = c;
+        sn[j] = s;
+        H[j * m + j] = den;
+        H[(j + 1) * m + j] = 0.0;
+        g[j + 1] = -s * g[j];
+        g[j] = c * g[j];
+        KState &S = a.st[atm];
+        S.resid = fabs(g[j + 1]);
+        S.iters += 1;
+        S.matvecs += 1;
+        S.inner = j + 1;
+        const bool done = (S.resid / S.bnorm < a.tol) || !(hn > 0.0) || (S.iters >= a.maxit) ||
+                          (j + 1 == m) || !(S.resid == S.resid);
+        if (done) a.cycle[atm] = 0;
+    }
+}
+
+// End of a cycle: solve the triangular system H y = g and set x += P^-1 V y.
+template <int E>
+__global__ __launch_bounds__(NT) void gm_update_kernel(VecArgs a) {
+    __shared__ double y[RT_MAX_RESTART];
+    const int atm = blockIdx.x;
+    if (!a.active[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    const int jj = a.st[atm].inner;
+    if (threadIdx.x == 0) {
+        const int m = a.m;
+        const double *H = a.H + (long long)atm * (m + 1) * m;
+        const double *g = a.g + (long long)atm * (m + 1);
+        for (int i = jj - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int l = i + 1; l < jj; ++l) s -= H[i * m + l] * y[l];
+            y[i] = s / H[i * m + i];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int l = threadIdx.x + e * NT;
+        if (l < n) {
+            double s = 0.0;
+            for (int i0 = 0; i0 < jj; i0 += 32) {
+                const int cnt = min(32, jj - i0);
+                const double *vp = a.V + (long long)i0 * a.N + base + l;
+                double v[32];
+#pragma unroll
+                for (int t = 0; t < 32; ++t) v[t] = (t < cnt) ? vp[(long long)t * a.N] : 0.0;
+#pragma unroll
+                for (int t = 0; t < 32; ++t)
+                    if (t < cnt) s += y[i0 + t] * v[t];
+            }
+            a.x[base + l] += a.dinv[base + l] * s;
+        }
+    }
+    if (threadIdx.x == 0) a.cycle[atm] = 0;
+}
+
+// ----------------------------------------------------------------- BiCGSTAB
+// r = b - A x, r^ = r, p = v = 0, rho_old = alpha = omega = 1.
+__global__ void bi_start_kernel(VecArgs a) {
+    __shared__ double red[2 * NW];
+    const int atm = blockIdx.x;
+    if (!a.active[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    double rr = 0.0, bb = 0.0;
+    for (int l = threadIdx.x; l < n; l += NT) {
+        const double bl = a.b[base + l];
+        const double rl = bl - a.w[base + l];
+        a.r[base + l] = rl;
+        a.rh[base + l] = rl;
+        a.p[base + l] = 0.0;
+        a.v[base + l] = 0.0;
+        rr += rl * rl;
+        bb += bl * bl;
+    }
+    block_sum2(rr, bb, red);
+    if (threadIdx.x == 0) {
+        KState &S = a.st[atm];
+        S.bnorm = sqrt(bb);
+        S.matvecs += 1;
+        S.rho_old = S.alpha = S.omega = 1.0;
+        S.iters = 0;
+        const double rn = sqrt(rr);
+        if (S.bnorm == 0.0) {
+            S.status = RT_OK;
+            S.relres = 0.0;
+            a.active[atm] = 0;
+        } else if (rn / S.bnorm < a.tol) {
+            S.status = RT_OK;
+            S.relres = rn / S.bnorm;
+            a.active[atm] = 0;
+        }
+    }
+    if (bb == 0.0)  // every thread holds the same block sum
+        for (int l = threadIdx.x; l < n; l += NT) a.x[base + l] = 0.0;
+}
+
+// rho = (r^, r); beta = (rho / rho_old)(alpha / omega); p = r + beta (p - omega v).
+__global__ void bi_dir_kernel(VecArgs a) {
+    __shared__ double red[2 * NW];
+    __shared__ int s_ok;
+    const int atm = blockIdx.x;
+    if (!a.active[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    KState &S = a.st[atm];
+    double rho = 0.0;
+    for (int l = threadIdx.x; l < n; l += NT) rho += a.rh[base + l] * a.r[base + l];
+    rho = block_sum(rho, red);
+    if (threadIdx.x == 0) {
+        s_ok = (rho != 0.0) && isfinite(rho) && (S.iters < a.maxit);
+        if (!s_ok) {
+            S.status = (S.iters >= a.maxit) ? RT_ENOCONV : RT_EBREAKDOWN;
+            a.active[atm] = 0;
+        } else {
+            S.rho = rho;
+        }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    const double beta = (rho / S.rho_old) * (S.alpha / S.omega);
+    const double om = S.omega;
+    for (int l = threadIdx.x; l < n; l += NT)
+        a.p[base + l] = a.r[base + l] + beta * (a.p[base + l] - om * a.v[base + l]);
+}
+
+// v = A P^-1 p is in a.v.  alpha = rho / (r^, v); s = r - alpha v.
+__global__ void bi_half_kernel(VecArgs a) {
+    __shared__ double red[2 * NW];
+    __shared__ int s_state;
+    __shared__ double s_alpha;
+    const int atm = blockIdx.x;
+    if (!a.active[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    KState &S = a.st[atm];
+    double rv = 0.0;
+    for (int l = threadIdx.x; l < n; l += NT) rv += a.rh[base + l] * a.v[base + l];
+    rv = block_sum(rv, red);
+    if (threadIdx.x == 0) {
+        S.matvecs += 1;
+        if (rv == 0.0 || !isfinite(rv)) {
+            S.status = RT_EBREAKDOWN;
+            a.active[atm] = 0;
+            s_state = 0;
+        } else {
+            S.alpha = S.rho / rv;
+            s_alpha = S.alpha;
+            s_state = 1;
+        }
+    }
+    __syncthreads();
+    if (!s_state) return;
+    const double alpha = s_alpha;
+    double ss = 0.0;
+    for (int l = threadIdx.x; l < n; l += NT) {
+        const double sl = a.r[base + l] - alpha * a.v[base + l];
+        a.s[base + l] = sl;
+        ss += sl * sl;
+    }
+    ss = block_sum(ss, red);
+    const double bnorm = S.bnorm;  // written by an earlier kernel
+    if (sqrt(ss) / bnorm < a.tol) {  // converged at the half step
+        for (int l = threadIdx.x; l < n; l += NT)
+            a.x[base + l] += alpha * a.dinv[base + l] * a.p[base + l];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            S.iters += 1;
+            S.status = RT_OK;
+            S.half_done = 1;
+            a.active[atm] = 0;
+        }
+    }
+}
+
+// t = A P^-1 s is in a.t.  omega = (t, s) / (t, t); x += alpha P^-1 p + omega
+// P^-1 s; r = s - omega t.
+__global__ void bi_full_kernel(VecArgs a) {
+    __shared__ double red[2 * NW];
+    __shared__ int s_ok;
+    __shared__ double s_omega;
+    const int atm = blockIdx.x;
+    if (!a.active[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    KState &S = a.st[atm];
+    double ts = 0.0, tt = 0.0;
+    for (int l = threadIdx.x; l < n; l += NT) {
+        const double tl = a.t[base + l];
+        ts += tl * a.s[base + l];
+        tt += tl * tl;
+    }
+    block_sum2(ts, tt, red);
+    if (threadIdx.x == 0) {
+        S.matvecs += 1;
+        s_ok = (tt != 0.0) && isfinite(tt);
+        if (!s_ok) {
+            S.status = RT_EBREAKDOWN;
+            a.active[atm] = 0;
+        } else {
+            S.omega = ts / tt;
+            s_omega = S.omega;
+        }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    const double alpha = S.alpha, om = s_omega;  // alpha: written by an earlier kernel
+    double rr = 0.0;
+    for (int l = threadIdx.x; l < n; l += NT) {
+        const double d = a.dinv[base + l];
+        a.x[base + l] += alpha * d * a.p[base + l] + om * d * a.s[base + l];
+        const double rl = a.s[base + l] - om * a.t[base + l];
+        a.r[base + l] = rl;
+        rr += rl * rl;
+    }
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) {
+        S.iters += 1;
+        const double rel = sqrt(rr) / S.bnorm;
+        if (rel < a.tol) {
+            S.status = RT_OK;
+            a.active[atm] = 0;
+        } else if (om == 0.0 || !isfinite(rel)) {
+            S.status = RT_EBREAKDOWN;
+            a.active[atm] = 0;
+        } else if (S.iters >= a.maxit) {
+            S.status = RT_ENOCONV;
+            a.active[atm] = 0;
+        }
+        S.rho_old = S.rho;
+    }
+}
+
+// --------------------------------------------------------------- Richardson
+// One step of x <- x + P^-1 (b - A x) (eq. rich_iteration), A x in a.w.
+__global__ void ri_step_kernel(VecArgs a, int first) {
+    __shared__ double red[2 * NW];
+    __shared__ int s_go;
+    const int atm = blockIdx.x;
+    if (!a.active[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    KState &S = a.st[atm];
+    double rr = 0.0, bb = 0.0;
+    for (int l = threadIdx.x; l < n; l += NT) {
+        const double bl = a.b[base + l];
+        const double rl = bl - a.w[base + l];
+        a.r[base + l] = rl;
+        rr += rl * rl;
+        bb += bl * bl;
+    }
+    block_sum2(rr, bb, red);
+    if (threadIdx.x == 0) {
+        if (first) S.bnorm = sqrt(bb);
+        S.matvecs += 1;
+        const double rel = (S.bnorm > 0.0) ? sqrt(rr) / S.bnorm : 0.0;
+        S.relres = rel;
+        int go = 0;
+        if (S.bnorm == 0.0) {
+            S.status = RT_OK;
+            go = -1;
+        } else if (rel < a.tol) {
+            S.status = RT_OK;
+        } else if (!isfinite(rel)) {
+            S.status = RT_EBREAKDOWN;
+        } else if (S.iters >= a.maxit) {
+            S.status = RT_ENOCONV;
+        } else {
+            go = 1;
+            S.iters += 1;
+        }
+        if (go != 1) a.active[atm] = 0;
+        s_go = go;
+    }
+    __syncthreads();
+    if (s_go == 1) {
+        for (int l = threadIdx.x; l < n; l += NT) a.x[base + l] += a.dinv[base + l] * a.r[base + l];
+    } else if (s_go == -1) {
+        for (int l = threadIdx.x; l < n; l += NT) a.x[base + l] = 0.0;
+    }
+}
+
+// ------------------------------------------------- residual and refinement
+// relres = ||b - A x|| / ||b|| (A x in a.w); used after BiCGSTAB.
+__global__ void relres_kernel(VecArgs a) {
+    __shared__ double red[2 * NW];
+    const int atm = blockIdx.x;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    double rr = 0.0, bb = 0.0;
+    for (int l = threadIdx.x; l < n; l += NT) {
+        const double bl = a.b[base + l];
+        const double rl = bl - a.w[base + l];
+        rr += rl * rl;
+        bb += bl * bl;
+    }
+    block_sum2(rr, bb, red);
+    if (threadIdx.x == 0) {
+        KState &S = a.st[atm];
+        S.relres = (bb > 0.0) ? sqrt(rr / bb) : 0.0;
+        S.matvecs += 1;
+    }
+}
+
+// Outer step of the mixed-precision refinement: r = b - A x in FP64 (A x in
+// a.w), test it; if the slab goes on, clear the correction d (a.s).
+__global__ void ir_residual_kernel(VecArgs a, int first) {
+    __shared__ double red[2 * NW];
+    __shared__ int s_go;
+    const int atm = blockIdx.x;
+    if (!a.active[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    KState &S = a.st[atm];
+    double rr = 0.0, bb = 0.0;
+    for (int l = threadIdx.x; l < n; l += NT) {
+        const double bl = a.b[base + l];
+        const double rl = bl - a.w[base + l];
+        a.r[base + l] = rl;
+        rr += rl * rl;
+        bb += bl * bl;
+    }
+    block_sum2(rr, bb, red);
+    if (threadIdx.x == 0) {
+        if (first) S.bnorm = sqrt(bb);
+        S.matvecs += 1;
+        const double rel = (S.bnorm > 0.0) ? sqrt(rr) / S.bnorm : 0.0;
+        S.relres = rel;
+        int go = 0;
+        if (S.bnorm == 0.0) {
+            S.status = RT_OK;
+            go = -1;
+        } else if (rel < a.tol) {
+            S.status = RT_OK;
+        } else if (!isfinite(rel)) {
+            S.status = RT_EBREAKDOWN;
+        } else if (S.outer >= a.max_outer || S.iters >= a.maxit) {
+            S.status = RT_ENOCONV;
+        } else {
+            go = 1;
+            S.outer += 1;
+        }
+        if (go != 1) a.active[atm] = 0;
+        s_go = go;
+    }
+    __syncthreads();
+    if (s_go == 1) {
+        for (int l = threadIdx.x; l < n; l += NT) a.s[base + l] = 0.0;
+    } else if (s_go == -1) {
+        for (int l = threadIdx.x; l < n; l += NT) a.x[base + l] = 0.0;
+    }
+}
+
+// x += d for slabs still refining; fold the inner solve's counters in.
+__global__ void ir_update_kernel(VecArgs a, const KState *inner) {
+    const int atm = blockIdx.x;
+    if (!a.active[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    for (int l = threadIdx.x; l < n; l += NT) a.x[base + l] += a.s[base + l];
+    if (threadIdx.x == 0) {
+        a.st[atm].iters += inner[atm].iters;
+        a.st[atm].matvecs += inner[atm].matvecs;
+    }
+}
+
+__global__ void scale_kernel(const double *v, const double *d, double *z, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = d[i] * v[i];
+}
+
+}  // namespace
+
+// ===================================================================== host
+
+hipError_t launch_scale(const double *v, const double *d, double *z, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, d, z,
+                       n);
+    return hipGetLastError();
+}
+
+namespace {
+
+struct Driver {
+    rt_handle *h;
+    hipStream_t s;
+    hipError_t err = hipSuccess;
+
+    bool ok(hipError_t e) {
+        if (e != hipSuccess && err == hipSuccess) err = e;
+        return err == hipSuccess;
+    }
+
+    // w = A (scale .* in), FP64 or FP32 sweep, for slabs whose mask is set
+    void sweep(const double *in, const double *scale, double *out, const int *mask, bool fp32) {
+        ok(apply_operator(h, in, scale, out, mask, fp32, 0, s));
+    }
+
+    // elements per thread for the largest slab: 2, 4, 8 or 16
+    int ept() const {
+        const int need = (2 * h->ns_max + NT - 1) / NT;
+        return need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
+    }
+
+    void arnoldi(const VecArgs &a, int j) {
+        const dim3 g(h->n_atm), b(NT);
+        switch (ept()) {
+            case 2: hipLaunchKernelGGL(gm_arnoldi_kernel<2>, g, b, 0, s, a, j); break;
+            case 4: hipLaunchKernelGGL(gm_arnoldi_kernel<4>, g, b, 0, s, a, j); break;
+            case 8: hipLaunchKernelGGL(gm_arnoldi_kernel<8>, g, b, 0, s, a, j); break;
+            default: hipLaunchKernelGGL(gm_arnoldi_kernel<16>, g, b, 0, s, a, j); break;
+        }
+        ok(hipGetLastError());
+    }
+
+    void update(const VecArgs &a) {
+        const dim3 g(h->n_atm), b(NT);
+        switch (ept()) {
+            case 2: hipLaunchKernelGGL(gm_update_kernel<2>, g, b, 0, s, a); break;
+            case 4: hipLaunchKernelGGL(gm_update_kernel<4>, g, b, 0, s, a); break;
+            case 8: hipLaunchKernelGGL(gm_update_kernel<8>, g, b, 0, s, a); break;
+            default: hipLaunchKernelGGL(gm_update_kernel<16>, g, b, 0, s, a); break;
+        }
+        ok(hipGetLastError());
+    }
+
+    int count(const int *flags) {
+        hipLaunchKernelGGL(count_kernel, dim3(1), dim3(NT), 0, s, flags, h->n_atm, h->d_count);
+        ok(hipGetLastError());
+        ok(hipMemcpyAsync(h->h_count, h->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+        ok(hipStreamSynchronize(s));
+        return err == hipSuccess ? *h->h_count : 0;
+    }
+
+    void init_state(KState *st, const int *from_mask) {
+        hipLaunchKernelGGL(init_state_kernel, dim3((h->n_atm + 255) / 256), dim3(256), 0, s, st,
+                           h->d_active, h->d_cycle, h->n_atm, from_mask);
+        ok(hipGetLastError());
+    }
+
+    VecArgs args(const double *b, double *x, KState *st, int *active, double tol, int maxit) {
+        VecArgs a{};
+        a.atm = h->d_atm;
+        a.N = h->n_unk;
+        a.m = h->ws_restart;
+        a.V = h->d_V;
+        a.H = h->d_H;
+        a.cs = h->d_cs;
+        a.sn = h->d_sn;
+        a.g = h->d_g;
+        a.w = h->d_w;
+        a.b = b;
+        a.x = x;
+        a.dinv = h->d_dinv;
+        a.r = h->d_r;
+        a.rh = h->d_rh;
+        a.p = h->d_p;
+        a.v = h->d_v;
+        a.s = h->d_s;
+        a.t = h->d_t;
+        a.st = st;
+        a.active = active;
+        a.cycle = h->d_cycle;
+        a.tol = tol;
+        a.maxit = maxit;
+        a.max_outer = h->opt.max_outer;
+        return a;
+    }
+
+    // Restarted GMRES on the slabs flagged in d_active.  st must be
+    // initialized; x_zero: x is zero on entry (skip the first A x).
+    void gmres(const double *b, double *x, KState *st, double tol, int maxit, bool fp32,
+               bool x_zero, bool accept_est = false) {
+        const int nb = h->n_atm;
+        VecArgs a = args(b, x, st, h->d_active, tol, maxit);
+        const int m = h->ws_restart;
+        const int check = std::max(1, h->opt.check_every);
+        if (!x_zero) sweep(x, nullptr, h->d_w, h->d_active, fp32);
+        hipLaunchKernelGGL(gm_restart_kernel, dim3(nb), dim3(NT), 0, s, a, 1, x_zero ? 1 : 0,
+                           accept_est ? 1 : 0);
+        ok(hipGetLastError());
+        while (err == hipSuccess) {
+            if (count(h->d_active) == 0) break;
+            for (int j = 0; j < m; ++j) {
+                sweep(h->d_V + (long long)j * h->n_unk, h->d_dinv, h->d_w, h->d_cycle, fp32);
+                arnoldi(a, j);
+                if ((j + 1) % check == 0 && j + 1 < m && count(h->d_cycle) == 0) break;
+            }
+            update(a);
+            sweep(x, nullptr, h->d_w, h->d_active, fp32);
+            hipLaunchKernelGGL(gm_restart_kernel, dim3(nb), dim3(NT), 0, s, a, 0, 0,
+                               accept_est ? 1 : 0);
+            ok(hipGetLastError());
+        }
+    }
+
+    void bicgstab(const double *b, double *x, KState *st, double tol, int maxit) {
+        const int nb = h->n_atm;
+        VecArgs a = args(b, x, st, h->d_active, tol, maxit);
+        const int check = std::max(1, h->opt.check_every);
+        sweep(x, nullptr, h->d_w, h->d_active, false);
+        hipLaunchKernelGGL(bi_start_kernel, dim3(nb), dim3(NT), 0, s, a);
+        ok(hipGetLastError());
+        for (int it = 0; err == hipSuccess; ++it) {
+            if (it % check == 0 && count(h->d_active) == 0) break;
+            hipLaunchKernelGGL(bi_dir_kernel, dim3(nb), dim3(NT), 0, s, a);
+            sweep(h->d_p, h->d_dinv, h->d_v, h->d_active, false);
+            hipLaunchKernelGGL(bi_half_kernel, dim3(nb), dim3(NT), 0, s, a);
+            sweep(h->d_s, h->d_dinv, h->d_t, h->d_active, false);
+            hipLaunchKernelGGL(bi_full_kernel, dim3(nb), dim3(NT), 0, s, a);
+            ok(hipGetLastError());
+        }
+        // explicit final residual of every slab
+        sweep(x, nullptr, h->d_w, nullptr, false);
+        hipLaunchKernelGGL(relres_kernel, dim3(nb), dim3(NT), 0, s, a);
+        ok(hipGetLastError());
+    }
+
+    void richardson(const double *b, double *x, KState *st, double tol, int maxit) {
+        const int nb = h->n_atm;
+        VecArgs a = args(b, x, st, h->d_active, tol, maxit);
+        const int check = std::max(1, h->opt.check_every);
+        for (int it = 0; err == hipSuccess; ++it) {
+            if (it > 0 && it % check == 0 && count(h->d_active) == 0) break;
+            sweep(x, nullptr, h->d_w, h->d_active, false);
+            hipLaunchKernelGGL(ri_step_kernel, dim3(nb), dim3(NT), 0, s, a, it == 0 ? 1 : 0);
+            ok(hipGetLastError());
+        }
+    }
+
+    // FP64 iterative refinement around FP32-sweep GMRES solves of A d = r.
+    void mixed_gmres(const double *b, double *x, KState *st, KState *st_in) {
+        const int nb = h->n_atm;
+        // outer flags live in d_cycle's companion: keep them in d_active of the
+        // outer loop, and give the inner solve its own copy in the count buffer
+        int *outer_active = h->d_active + h->n_atm;  // second half of the flag buffer
+        VecArgs a = args(b, x, st, outer_active, h->opt.rtol, h->opt.maxit);
+        hipLaunchKernelGGL(init_state_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, st,
+                           outer_active, h->d_cycle, nb, (const int *)nullptr);
+        ok(hipGetLastError());
+        for (int k = 0; err == hipSuccess; ++k) {
+            sweep(x, nullptr, h->d_w, outer_active, false);
+            hipLaunchKernelGGL(ir_residual_kernel, dim3(nb), dim3(NT), 0, s, a, k == 0 ? 1 : 0);
+            ok(hipGetLastError());
+            if (count(outer_active) == 0) break;
+            // inner: A32 d = r, d = 0 initially, on the slabs still refining
+            init_state(st_in, outer_active);
+            gmres(h->d_r, h->d_s, st_in, h->opt.inner_rtol, h->opt.inner_maxit, true, true, true);
+            hipLaunchKernelGGL(ir_update_kernel, dim3(nb), dim3(NT), 0, s, a, (const KState *)st_in);
+            ok(hipGetLastError());
+        }
+    }
+};
+
+}  // namespace
+
+// Allocate the Krylov workspace for the handle's restart length.
+int ensure_workspace(rt_handle *h);
+
+int run_solver(rt_handle *h, int kind, const double *b, double *x, rt_solve_info *info,
+               hipStream_t s) {
+    int rc = ensure_workspace(h);
+    if (rc != RT_OK) return rc;
+    if (!b) b = h->d_b;
+    Driver d{h, s};
+    KState *st = h->d_state;
+    KState *st_in = h->d_state + h->n_atm;
+    if (kind == 0 && h->opt.precision == RT_PREC_MIXED) {
+        d.mixed_gmres(b, x, st, st_in);
+    } else {
+        d.init_state(st, nullptr);
+        if (kind == 0)
+            d.gmres(b, x, st, h->opt.rtol, h->opt.maxit, false, false);
+        else if (kind == 1)
+            d.bicgstab(b, x, st, h->opt.rtol, h->opt.maxit);
+        else
+            d.richardson(b, x, st, h->opt.rtol, h->opt.maxit);
+    }
+    std::vector<KState> hs(h->n_atm);
+    d.ok(hipMemcpyAsync(hs.data(), st, sizeof(KState) * h->n_atm, hipMemcpyDeviceToHost, s));
+    d.ok(hipStreamSynchronize(s));
+    if (d.err != hipSuccess)
+        return fail(RT_EDEVICE, std::string("solver: ") + hipGetErrorString(d.err));
+    int worst = RT_OK;
+    for (int i = 0; i < h->n_atm; ++i) {
+        const KState &k = hs[i];
+        if (k.status > worst) worst = k.status;
+        if (info) {
+            info[i].status = k.status;
+            info[i].iterations = k.iters;
+            info[i].matvecs = k.matvecs;
+            info[i].outer_steps = k.outer;
+            info[i].relres = (kind == 0 && h->opt.precision != RT_PREC_MIXED && k.bnorm > 0.0)
+                                 ? k.beta / k.bnorm
+                                 : k.relres;
+        }
+    }
+    if (worst != RT_OK)
+        set_error(worst == RT_ENOCONV ? "solver did not reach rtol within the iteration limit"
+                                      : "solver breakdown");
+    return worst;
+}
+
+}  // namespace rt

@@ -1,0 +1,608 @@
+// rt_sweep.hip -- the operator A = Id - J Lambda T on gfx950.
+//
+// Algorithm 1 of the paper computes S = T sigma, then a formal solution along
+// every ray (mu_m, nu_p) with zero incoming radiation, then the quadrature of
+// eqs. J00/J02.  This file fuses the three steps into one launch:
+//
+//  * T step (eqs. sourceI/sourceQ).  S_I = s00 + T1(mu) s20, S_Q = T2(mu) s20
+//    with T1, T2 functions of mu^2 only, so the rays mu and -mu see the same
+//    source.  The formal solver is linear, so Lambda S_I = Lambda s00 +
+//    T1 Lambda s20 and Lambda S_Q = T2 Lambda s20: each lane runs two
+//    recurrences per direction (sources s00 and s20) and the T factors are
+//    applied when the intensities are weighted into the quadrature.
+//  * Lambda step (eqs. RTE_delo1/2).  One lane owns one chunk of one ray
+//    pair (|mu|, nu); it sweeps its chunk downward (the mu < 0 ray) and upward
+//    (the mu > 0 ray) with the step I_k = E I_u + c_u S_u + c_k S_k,
+//    E = 1 - c_u - c_k (true of both DELO-linear and the trapezoidal rule,
+//    which reproduce a constant source exactly).  The C chunks of a ray sit in
+//    C adjacent lanes; a chunk is swept once with zero inflow, the affine
+//    maps I_out = P I_in + e of the chunks are composed by a lane scan
+//    (Hillis-Steele, log2 C shuffles), and the inflow's share T_k I_in (T_k
+//    the transmission from the chunk's entry to point k, kept from the sweep)
+//    is added at every point.  The step coefficients are read once per
+//    launch, in a tile order where a wavefront's 64 lanes read 64 consecutive
+//    pairs, one ray batch ahead of use.
+//  * J step (eqs. J00/J02, S00/S02).  Each lane accumulates
+//    q (I_down + I_up) and the T-weighted combination for J20 over all the
+//    rays it handles, in registers; the rays of a wave are summed by an xor
+//    butterfly, the waves of a block in LDS in a fixed order, and each block
+//    stores its sums in a slot of its own.  A second, light pass adds a
+//    slab's slots in block order and applies the scattering step.  No
+//    atomics and no device-wide fences (which on gfx950 write back and
+//    invalidate a whole L2): results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "rt_internal.h"
+
+namespace rt {
+
+// --------------------------------------------------------------------------
+// Step coefficients of one interval with optical step d (FP64).
+//
+// DELO-linear (exact integral of a linearly interpolated source along the
+// ray, Sect. 4.1): c_u = int_0^d (s/d) e^{-s} ds = (1 - (1 + d) e^{-d}) / d,
+// c_k = (1 - e^{-d}) - c_u.  Below d = 0.1 the closed forms cancel; their
+// Taylor series sum_{n>=2} (-1)^n (n-1) d^(n-1)/n! and
+// sum_{n>=2} (-1)^n d^(n-1)/n! are evaluated by Horner's rule instead.
+// Trapezoidal (Crank-Nicolson): c_u = c_k = (d/2) / (1 + d/2).
+// --------------------------------------------------------------------------
+namespace {
+
+constexpr int kSeriesTerms = 14;  // n = 2 .. 15: below 1e-20 relative at d = 0.1
+
+struct SeriesCoef {
+    double u[kSeriesTerms];
+    double k[kSeriesTerms];
+};
+
+constexpr SeriesCoef make_series() {
+    SeriesCoef s{};
+    double fact = 1.0;  // n!
+    for (int n = 1; n <= kSeriesTerms + 1; ++n) {
+        fact *= n;
+        if (n >= 2) {
+            const double sgn = (n % 2 == 0) ? 1.0 : -1.0;
+            s.u[n - 2] = sgn * (n - 1) / fact;
+            s.k[n - 2] = sgn / fact;
+        }
+    }
+    return s;
+}
+
+__constant__ SeriesCoef c_series = make_series();
+
+}  // namespace
+
+__device__ inline void step_coef(int fs, double d, double &cu, double &ck) {
+    if (fs == RT_FS_TRAPEZOIDAL) {
+        const double h = 0.5 * d;
+        cu = ck = h / (1.0 + h);
+        return;
+    }
+    if (d < 0.1) {
+        double pu = c_series.u[kSeriesTerms - 1];
+        double pk = c_series.k[kSeriesTerms - 1];
+#pragma unroll
+        for (int t = kSeriesTerms - 2; t >= 0; --t) {
+            pu = fma(pu, d, c_series.u[t]);
+            pk = fma(pk, d, c_series.k[t]);
+        }
+        cu = pu * d;
+        ck = pk * d;
+    } else {
+        const double e = exp(-d);
+        const double w0 = -expm1(-d);
+        const double w1 = w0 - d * e;
+        cu = w1 / d;
+        ck = w0 - cu;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Ray constants: q = (w_m / 2) w~_p, w~_p = w_p phi_p (/ sum if normalized),
+// with T1 = sqrt2 (3 mu^2 - 1) / 4, T2 = sqrt2 (3 mu^2 - 3) / 4.
+// One block per slab.
+// --------------------------------------------------------------------------
+__global__ void ray_setup_kernel(const AtmDesc *atm, const double *mu_pos, const double *w_pos,
+                                 int M, const double *w_nu, const double *phi, int n_nu,
+                                 int normalize, RayConst *rayc) {
+    __shared__ double red[256 / kWave];
+    const int a = blockIdx.x;
+    const double *ph = phi + (long long)a * n_nu;
+    double norm = 1.0;
+    if (normalize) {
+        double s = 0.0;
+        for (int p = threadIdx.x; p < n_nu; p += blockDim.x) s += w_nu[p] * ph[p];
+        for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+        __syncthreads();
+        norm = 0.0;
+        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) norm += red[i];
+    }
+    const AtmDesc at = atm[a];
+    for (int r = threadIdx.x; r < M * n_nu; r += blockDim.x) {
+        const int m = r / n_nu, p = r % n_nu;
+        const double mu2 = mu_pos[m] * mu_pos[m];
+        const double t1 = sqrt(2.0) * (3.0 * mu2 - 1.0) / 4.0;
+        const double t2 = sqrt(2.0) * (3.0 * mu2 - 3.0) / 4.0;
+        const double q = 0.5 * w_pos[m] * (w_nu[p] * ph[p] / norm);
+        RayConst rc;
+        rc.q = q;
+        rc.qt1 = q * t1;
+        rc.qt12 = q * (t1 * t1 + t2 * t2);
+        rc.pad = 0.0;
+        rayc[at.ray_off + r] = rc;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Tile-ordered coefficients: pair (c_u, c_k) of step i of the chunk held by
+// lane `lane` in wave-batch b lives at coef_off + (b * Leff + i) * 64 + lane.
+// Lane = g * C + c holds chunk c (intervals c*Leff .. c*Leff+Leff-1) of ray
+// b*G + g.  Padding (rays beyond the last, intervals beyond ns - 2) is zero,
+// which makes the step the identity.
+// --------------------------------------------------------------------------
+__global__ void coef_build_kernel(int W, const AtmDesc *atm, const BlockDesc *blk,
+                                  const double *tau, const double *opac, const double *mu_pos,
+                                  int n_nu, int fs, double2 *coef64, float2 *coef32) {
+    const BlockDesc bd = blk[blockIdx.x];
+    const AtmDesc at = atm[bd.atm];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int c = lane % at.C, g = lane / at.C;
+    for (int b = bd.wb_first + wave; b < bd.wb_first + bd.wb_count; b += W) {
+        const int r = b * at.G + g;
+        for (int i = 0; i < at.Leff; ++i) {
+            const int j = c * at.Leff + i;
+            double cu = 0.0, ck = 0.0;
+            if (r < at.nrays && j < at.ns - 1) {
+                const int m = r / n_nu, p = r % n_nu;
+                const double kap = opac[(long long)bd.atm * n_nu + p] / mu_pos[m];
+                const double d = kap * (tau[at.doff + j + 1] - tau[at.doff + j]);
+                step_coef(fs, d, cu, ck);
+            }
+            const long long e = at.coef_off + ((long long)b * at.Leff + i) * kWave + lane;
+            coef64[e] = make_double2(cu, ck);
+            coef32[e] = make_float2((float)cu, (float)ck);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Jacobi diagonal D = diag(A).  A point source at depth k reaches the
+// intensity at k only through the c_k coefficient of the interval entering
+// k on each ray (the upwind part of the sweep is zero), so
+//   D(k,0) = 1 - xi     sum_rays q        (c_k^down(k) + c_k^up(k)),
+//   D(k,2) = 1 - xi W2  sum_rays q (T1^2 + T2^2) (c_k^down(k) + c_k^up(k)),
+// the second because s20 enters S_I through T1 and S_Q through T2 and J20
+// weights I by T1 and Q by T2.  One thread per depth point.
+// --------------------------------------------------------------------------
+__global__ void diag_kernel(int npts, const int *pt_atm, const AtmDesc *atm, const double *tau,
+                            const double *opac, const double *mu_pos, const RayConst *rayc, int M,
+                            int n_nu, int fs, double *diag, double *dinv) {
+    const int kk = blockIdx.x * blockDim.x + threadIdx.x;
+    if (kk >= npts) return;
+    const int a = pt_atm[kk];
+    const AtmDesc at = atm[a];
+    const int k = kk - at.doff;
+    const double dprev = (k >= 1) ? tau[kk] - tau[kk - 1] : 0.0;
+    const double dnext = (k <= at.ns - 2) ? tau[kk + 1] - tau[kk] : 0.0;
+    double s0 = 0.0, s2 = 0.0;
+    for (int m = 0; m < M; ++m) {
+        for (int p = 0; p < n_nu; ++p) {
+            const double kap = opac[(long long)a * n_nu + p] / mu_pos[m];
+            double cu, ck, s = 0.0;
+            if (k >= 1) {
+                step_coef(fs, kap * dprev, cu, ck);
+                s += ck;
+            }
+            if (k <= at.ns - 2) {
+                step_coef(fs, kap * dnext, cu, ck);
+                s += ck;
+            }
+            const RayConst rc = rayc[at.ray_off + m * n_nu + p];
+            s0 += rc.q * s;
+            s2 += rc.qt12 * s;
+        }
+    }
+    const double d0 = 1.0 - at.xi * s0;
+    const double d2 = 1.0 - at.xi * at.W2 * s2;
+    diag[2 * (long long)kk] = d0;
+    diag[2 * (long long)kk + 1] = d2;
+    dinv[2 * (long long)kk] = 1.0 / d0;
+    dinv[2 * (long long)kk + 1] = 1.0 / d2;
+}
+
+// --------------------------------------------------------------------------
+// The fused sweep.  T: arithmetic type of the recurrences and accumulators
+// (double, or float inside the mixed-precision inner solve).  L: register
+// capacity of a chunk (Leff <= L).  W: waves per block.  Each block writes
+// the 2 ns quadrature sums of its rays to its own slot of `partial`; the
+// finalize pass (or a Krylov kernel) adds the slots of a slab in block order
+// and applies sigma_out = z - xi [J00, W2 J20].
+// --------------------------------------------------------------------------
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+    using type = double2;
+};
+template <>
+struct Pair<float> {
+    using type = float2;
+};
+
+template <typename T, int L, int W>
+__global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
+    using P2 = typename Pair<T>::type;
+    extern __shared__ unsigned char smem_raw[];
+    T *sacc = reinterpret_cast<T *>(smem_raw);  // LDS rows of quadrature sums
+
+    const BlockDesc bd = a.blk[blockIdx.x];
+    if (a.mask && a.mask[bd.atm] == 0) return;  // uniform over the block
+    const AtmDesc at = a.atm[bd.atm];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int C = at.C, Leff = at.Leff, ns = at.ns;
+    const int c = lane % C, g = lane / C;
+    const int s0 = c * Leff;  // first depth point of this lane's chunk
+    const long long vbase = 2LL * at.doff;
+
+    // sources s00, s20 at the chunk's points: every load issued before any
+    // use (addresses clamped into the slab, values past it zeroed)
+    T sg0[L + 1], sg2[L + 1];
+    if (a.sig_in) {
+        double2 v[L + 1];
+#pragma unroll
+        for (int i = 0; i <= L; ++i) {
+            const int k = min(s0 + i, ns - 1);
+            v[i] = *reinterpret_cast<const double2 *>(a.sig_in + vbase + 2LL * k);
+        }
+        if (a.scale) {
+            double2 sc[L + 1];
+#pragma unroll
+            for (int i = 0; i <= L; ++i) {
+                const int k = min(s0 + i, ns - 1);
+                sc[i] = *reinterpret_cast<const double2 *>(a.scale + vbase + 2LL * k);
+            }
+#pragma unroll
+            for (int i = 0; i <= L; ++i) {
+                v[i].x *= sc[i].x;
+                v[i].y *= sc[i].y;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i <= L; ++i) {
+            const bool in = (i <= Leff) && (s0 + i < ns);
+            sg0[i] = in ? (T)v[i].x : (T)0;
+            sg2[i] = in ? (T)v[i].y : (T)0;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i <= L; ++i) sg0[i] = sg2[i] = (T)0;
+    }
+
+    T acc0[L + 1], acc2[L + 1];
+#pragma unroll
+    for (int i = 0; i <= L; ++i) acc0[i] = acc2[i] = (T)0;
+
+    const T inflow = (a.mode == 1) ? (T)at.Ibot : (T)0;
+    const P2 *coef = reinterpret_cast<const P2 *>(a.coef) + at.coef_off;
+    const int bend = bd.wb_first + bd.wb_count;
+
+    // software pipeline: batch b + W's coefficients load while b computes
+    P2 cn[L];
+    double4 rn = make_double4(0.0, 0.0, 0.0, 0.0);
+    auto load_batch = [&](int b) {
+        const P2 *tile = coef + (long long)b * Leff * kWave + lane;
+#pragma unroll
+        for (int i = 0; i < L; ++i) cn[i] = tile[(long long)min(i, Leff - 1) * kWave];
+        const int r = b * at.G + g;
+        rn = *reinterpret_cast<const double4 *>(a.rayc + at.ray_off + min(r, at.nrays - 1));
+        if (r >= at.nrays) rn = make_double4(0.0, 0.0, 0.0, 0.0);
+    };
+    int b = bd.wb_first + wave;
+    if (b < bend) load_batch(b);
+    for (; b < bend; b += W) {
+        T cu[L], ck[L];
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            cu[i] = cn[i].x;
+            ck[i] = cn[i].y;
+        }
+        const T q = (T)rn.x, qt1 = (T)rn.y, qt12 = (T)rn.z;
+        if (b + W < bend) load_batch(b + W);
+
+        // one pass over the chunk with zero inflow in both directions: the
+        // local intensities go into the quadrature at once, and the running
+        // transmissions Td[i] = E_0..E_i, Tu[i] = E_i..E_{Leff-1} are kept
+        // for the inflow term added after the scan
+        T Td[L], Tu[L];
+        T dU = (T)0, dV = (T)0, t = (T)1;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            if (i < Leff) {
+                const T E = (T)1 - cu[i] - ck[i];
+                dU = E * dU + (cu[i] * sg0[i] + ck[i] * sg0[i + 1]);
+                dV = E * dV + (cu[i] * sg2[i] + ck[i] * sg2[i + 1]);
+                t *= E;
+                Td[i] = t;
+                acc0[i + 1] += q * dU + qt1 * dV;
+                acc2[i + 1] += qt1 * dU + qt12 * dV;
+            }
+        }
+        T uU = (T)0, uV = (T)0;
+        t = (T)1;
+#pragma unroll
+        for (int i = L - 1; i >= 0; --i) {
+            if (i < Leff) {
+                const T E = (T)1 - cu[i] - ck[i];
+                uU = E * uU + (cu[i] * sg0[i + 1] + ck[i] * sg0[i]);
+                uV = E * uV + (cu[i] * sg2[i + 1] + ck[i] * sg2[i]);
+                t *= E;
+                Tu[i] = t;
+                acc0[i] += q * uU + qt1 * uV;
+                acc2[i] += qt1 * uU + qt12 * uV;
+            }
+        }
+
+        // lane scans of the chunk maps I_out = P I_in + e: downward chunks
+        // compose left to right, upward ones right to left
+        T Pd = t, Pu = t;
+        for (int d = 1; d < C; d <<= 1) {
+            const T pP = __shfl_up(Pd, d, C), pU = __shfl_up(dU, d, C), pV = __shfl_up(dV, d, C);
+            const T nP = __shfl_down(Pu, d, C), nU = __shfl_down(uU, d, C),
+                    nV = __shfl_down(uV, d, C);
+            if (c >= d) {
+                dU = Pd * pU + dU;
+                dV = Pd * pV + dV;
+                Pd *= pP;
+            }
+            if (c + d < C) {
+                uU = Pu * nU + uU;
+                uV = Pu * nV + uV;
+                Pu *= nP;
+            }
+        }
+        // inflows at the chunk's entry points: from the chunk above (down),
+        // from the chunk below or the bottom boundary (up)
+        T cdU = __shfl_up(dU, 1, C), cdV = __shfl_up(dV, 1, C);
+        const T nPu = __shfl_down(Pu, 1, C);
+        T cuU = __shfl_down(uU, 1, C) + nPu * inflow, cuV = __shfl_down(uV, 1, C);
+        if (c == 0) cdU = cdV = (T)0;
+        if (c == C - 1) {
+            cuU = inflow;
+            cuV = (T)0;
+        }
+
+        // inflow terms: I_true = I_local + T * I_in at every point of the chunk
+        const T cD0 = q * cdU + qt1 * cdV, cD2 = qt1 * cdU + qt12 * cdV;
+        const T cU0 = q * cuU + qt1 * cuV, cU2 = qt1 * cuU + qt12 * cuV;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            if (i < Leff) {
+                acc0[i + 1] += Td[i] * cD0;
+                acc2[i + 1] += Td[i] * cD2;
+                acc0[i] += Tu[i] * cU0;
+                acc2[i] += Tu[i] * cU2;
+            }
+        }
+        if (a.mode == 1 && c == C - 1 && s0 + Leff == ns - 1) {
+            // the bottom point is this chunk's entry point: its intensity is the inflow
+#pragma unroll
+            for (int i = 0; i <= L; ++i) {
+                if (i == Leff) {
+                    acc0[i] += cU0;
+                    acc2[i] += cU2;
+                }
+            }
+        }
+    }
+
+    // sum over the G rays of the wave that share chunk c (lanes c, c+C, ...)
+    for (int off = C; off < kWave; off <<= 1) {
+#pragma unroll
+        for (int i = 0; i <= L; ++i) {
+            acc0[i] += __shfl_xor(acc0[i], off);
+            acc2[i] += __shfl_xor(acc2[i], off);
+        }
+    }
+    // the downward value at a chunk's end point belongs to the next chunk's first point
+    T b0 = (T)0, b2 = (T)0;
+#pragma unroll
+    for (int i = 0; i <= L; ++i) {
+        if (i == Leff) {
+            b0 = acc0[i];
+            b2 = acc2[i];
+        }
+    }
+    {
+        const T p0 = __shfl_up(b0, 1, C), p2 = __shfl_up(b2, 1, C);
+        if (c > 0) {
+            acc0[0] += p0;
+            acc2[0] += p2;
+        }
+    }
+
+    // block totals of the 2 ns quadrature sums
+    const int nthr = kWave * W;
+    double *mine = a.partial + at.part_off + (long long)(blockIdx.x - at.blk_first) * 2 * ns;
+    if (a.rows) {
+        // one LDS row per wave, then a fixed-order sum over the rows
+        T *row = sacc + (long long)wave * 2 * ns;
+        if (g == 0) {
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                const int k = s0 + i;
+                if (i < Leff && k < ns) {
+                    row[2 * k] = acc0[i];
+                    row[2 * k + 1] = acc2[i];
+                }
+            }
+            if (c == C - 1 && s0 + Leff == ns - 1) {
+                row[2 * (ns - 1)] = b0;
+                row[2 * (ns - 1) + 1] = b2;
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 2 * ns; e += nthr) {
+            T t = sacc[e];
+            for (int w = 1; w < W; ++w) t += sacc[(long long)w * 2 * ns + e];
+            mine[e] = (double)t;
+        }
+    } else {
+        // one shared row, filled wave after wave (fixed order)
+        for (int e = threadIdx.x; e < 2 * ns; e += nthr) sacc[e] = (T)0;
+        __syncthreads();
+        for (int w = 0; w < W; ++w) {
+            if (wave == w && g == 0) {
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    const int k = s0 + i;
+                    if (i < Leff && k < ns) {
+                        sacc[2 * k] += acc0[i];
+                        sacc[2 * k + 1] += acc2[i];
+                    }
+                }
+                if (c == C - 1 && s0 + Leff == ns - 1) {
+                    sacc[2 * (ns - 1)] += b0;
+                    sacc[2 * (ns - 1) + 1] += b2;
+                }
+            }
+            __syncthreads();
+        }
+        for (int e = threadIdx.x; e < 2 * ns; e += nthr) mine[e] = (double)sacc[e];
+    }
+}
+
+// --------------------------------------------------------------------------
+// Finalize: J = sum over the slab's blocks (in block order) of the partial
+// quadrature sums, then
+//   mode 0: sigma_out = z - xi [J00, W2 J20], z = scale .* sigma_in;
+//   mode 1: sigma_out = xi [J00, W2 J20] + [eps B, 0].
+// One thread per depth point.
+// --------------------------------------------------------------------------
+__global__ void finalize_kernel(SweepArgs a, const int *pt_atm, int npts) {
+    const int kk = blockIdx.x * blockDim.x + threadIdx.x;
+    if (kk >= npts) return;
+    const int atm = pt_atm[kk];
+    if (a.mask && a.mask[atm] == 0) return;
+    const AtmDesc at = a.atm[atm];
+    const int k = kk - at.doff;
+    const long long stride = 2LL * at.ns;
+    const double *pJ = a.partial + at.part_off + 2 * k;
+    double J0 = 0.0, J2 = 0.0;
+    for (int j0 = 0; j0 < at.nblk; j0 += 8) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = min(j0 + u, at.nblk - 1);
+            v[u] = *reinterpret_cast<const double2 *>(pJ + j * stride);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (j0 + u < at.nblk) {
+                J0 += v[u].x;
+                J2 += v[u].y;
+            }
+        }
+    }
+    const long long e = 2LL * kk;
+    double o0, o2;
+    if (a.mode == 0) {
+        double z0 = a.sig_in[e], z2 = a.sig_in[e + 1];
+        if (a.scale) {
+            z0 *= a.scale[e];
+            z2 *= a.scale[e + 1];
+        }
+        o0 = z0 - at.xi * J0;
+        o2 = z2 - at.xi * at.W2 * J2;
+    } else {
+        o0 = at.xi * J0 + at.eps * a.B[kk];
+        o2 = at.xi * at.W2 * J2;
+    }
+    a.sig_out[e] = o0;
+    a.sig_out[e + 1] = o2;
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+int sweep_waves(int L, bool fp32) {
+    // register footprints measured for gfx950: FP64 L=16 and FP32 L=32 need
+    // more than 256 VGPRs + AGPRs, i.e. one wave per SIMD
+    if (fp32) return L >= 32 ? 4 : 8;
+    return L >= 16 ? 4 : 8;
+}
+
+template <typename T, int L, int W>
+static hipError_t launch_sweep_tw(SweepArgs a, int nblocks, int ns_max, hipStream_t s) {
+    const size_t row = 2 * (size_t)ns_max * sizeof(T);
+    a.rows = (W * row <= (size_t)kSweepLdsBudget) ? 1 : 0;
+    const size_t lds = a.rows ? W * row : row;
+    hipLaunchKernelGGL((sweep_kernel<T, L, W>), dim3(nblocks), dim3(kWave * W), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const SweepArgs &a, const int *pt_atm, int npts, hipStream_t s) {
+    if (npts <= 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3((npts + 255) / 256), dim3(256), 0, s, a, pt_atm, npts);
+    return hipGetLastError();
+}
+
+template <typename T, int L>
+static hipError_t launch_sweep_t(const SweepArgs &a, int nblocks, int ns_max, hipStream_t s) {
+    if (sweep_waves(L, sizeof(T) == 4) == 8) return launch_sweep_tw<T, L, 8>(a, nblocks, ns_max, s);
+    return launch_sweep_tw<T, L, 4>(a, nblocks, ns_max, s);
+}
+
+bool sweep_chunk_supported(int L, bool fp32) {
+    (void)fp32;
+    return L == 4 || L == 8 || L == 16 || L == 32;
+}
+
+hipError_t launch_sweep(int L, bool fp32, const SweepArgs &a, int nblocks, int ns_max,
+                        hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    if (fp32) {
+        switch (L) {
+            case 4: return launch_sweep_t<float, 4>(a, nblocks, ns_max, s);
+            case 8: return launch_sweep_t<float, 8>(a, nblocks, ns_max, s);
+            case 16: return launch_sweep_t<float, 16>(a, nblocks, ns_max, s);
+            case 32: return launch_sweep_t<float, 32>(a, nblocks, ns_max, s);
+        }
+    } else {
+        switch (L) {
+            case 4: return launch_sweep_t<double, 4>(a, nblocks, ns_max, s);
+            case 8: return launch_sweep_t<double, 8>(a, nblocks, ns_max, s);
+            case 16: return launch_sweep_t<double, 16>(a, nblocks, ns_max, s);
+            case 32: return launch_sweep_t<double, 32>(a, nblocks, ns_max, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_coef_build(int nblocks, int W, const AtmDesc *atm, const BlockDesc *blk,
+                             const double *tau, const double *opac, const double *mu_pos,
+                             int n_nu, int fs, double2 *coef64, float2 *coef32, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(coef_build_kernel, dim3(nblocks), dim3(kWave * W), 0, s, W, atm, blk, tau,
+                       opac, mu_pos, n_nu, fs, coef64, coef32);
+    return hipGetLastError();
+}
+
+hipError_t launch_ray_setup(int n_atm, const AtmDesc *atm, const double *mu_pos,
+                            const double *w_pos, int M, const double *w_nu, const double *phi,
+                            int n_nu, int normalize, RayConst *rayc, hipStream_t s) {
+    hipLaunchKernelGGL(ray_setup_kernel, dim3(n_atm), dim3(256), 0, s, atm, mu_pos, w_pos, M,
+                       w_nu, phi, n_nu, normalize, rayc);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(int npts, const int *pt_atm, const AtmDesc *atm, const double *tau,
+                       const double *opac, const double *mu_pos, const RayConst *rayc, int M,
+                       int n_nu, int fs, double *diag, double *dinv, hipStream_t s) {
+    hipLaunchKernelGGL(diag_kernel, dim3((npts + 255) / 256), dim3(256), 0, s, npts, pt_atm, atm,
+                       tau, opac, mu_pos, rayc, M, n_nu, fs, diag, dinv);
+    return hipGetLastError();
+}
+
+}  // namespace rt

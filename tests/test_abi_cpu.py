@@ -1,0 +1,95 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+headers declare, validates inputs without a device, and fails cleanly when no
+GPU is present."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2110_11873_amd import binding as B
+from paper_2110_11873_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for h in ("rt.h", "rt_ext.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"\b(rt_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    declared = _declared()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(B.EXPORTS) == declared
+
+
+def test_default_options():
+    o = B.default_options()
+    assert (o.precision, o.restart, o.maxit, o.rtol, o.inner_rtol, o.inner_maxit, o.max_outer,
+            o.chunk, o.wave_batches, o.check_every) == (0, 30, 10000, 1e-10, 1e-4, 100, 30, 0, 0, 16)
+
+
+def test_valid_configs_pass_validation():
+    for p in (W.config1(), W.config1_subgrid(), W.config2(), W.config2("trapezoidal"),
+              W.paper_replica(20)):
+        assert B.validate(p) == 0, B.last_error()
+
+
+@pytest.mark.parametrize("mutate,fragment", [
+    (lambda p: p.with_(tau=p.tau[::-1].copy()), "tau"),
+    (lambda p: p.with_(tau=np.where(np.arange(p.tau.size) == 3, np.nan, p.tau)), "tau"),
+    (lambda p: p.with_(ns=np.array([1], dtype=np.int32), tau=p.tau[:1].copy(), B=p.B[:1].copy()),
+     "ns"),
+    (lambda p: p.with_(mu=np.abs(p.mu)), "symmetric"),
+    (lambda p: p.with_(mu=np.where(np.arange(p.mu.size) == 0, 0.0, p.mu)), "mu"),
+    (lambda p: p.with_(w_mu=p.w_mu * 1.1), "sum to 2"),
+    (lambda p: p.with_(opac=-p.opac), "opac"),
+    (lambda p: p.with_(phi=np.zeros_like(p.phi)), "phi"),
+    (lambda p: p.with_(eps=np.array([1.5])), "eps"),
+    (lambda p: p.with_(W2=np.array([np.inf])), "W2"),
+    (lambda p: p.with_(formal_solver=7), "formal_solver"),
+])
+def test_invalid_problems_rejected(mutate, fragment):
+    p = mutate(W.config1())
+    assert B.validate(p) == B.RT_EINVAL
+    assert fragment in B.last_error()
+
+
+def test_invalid_options_rejected():
+    p = W.config1()
+    for kw, frag in [(dict(restart=0), "restart"), (dict(restart=500), "restart"),
+                     (dict(rtol=0.0), "rtol"), (dict(chunk=5), "chunk"),
+                     (dict(precision=9), "precision"), (dict(inner_rtol=2.0), "inner_rtol"),
+                     (dict(inner_maxit=0), "inner_maxit"), (dict(wave_batches=-1), "wave_batches")]:
+        assert B.validate(p, B.default_options(**kw)) == B.RT_EINVAL, kw
+        assert frag in B.last_error()
+
+
+def test_setup_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(B.RTError) as e:
+        B.setup(W.config1())
+    assert e.value.code == B.RT_EDEVICE
+
+
+def test_null_handle_calls_fail_with_einval():
+    L = B.lib()
+    assert L.rt_apply_op(None, None, None, None) == B.RT_EINVAL
+    assert L.rt_precond_jacobi(None, None, None, None) == B.RT_EINVAL
+    info = (B.rt_solve_info * 1)()
+    assert L.rt_solve_gmres(None, None, None, info, None) == B.RT_EINVAL
+    assert L.rt_num_unknowns(None) == 0
+    L.rt_destroy(None)
+    h = C.c_void_p()
+    assert L.rt_setup(C.byref(h), None, None) == B.RT_EINVAL
