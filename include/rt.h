@@ -132,6 +132,8 @@ typedef struct rt_problem {
  *              else one of 4, 8, 16, 32
  *  wave_batches  ray batches each wavefront of the sweep handles in turn:
  *              0 = choose automatically, else 1..64
+ *  prefetch    step coefficients of later ray batches loaded ahead of use:
+ *              0 = automatic, 1 = none, 2 = one batch ahead, 3 = two
  *  check_every iterations between convergence checks read back by the host
  *              for BiCGSTAB and Richardson (16); GMRES checks once per cycle
  */
@@ -145,6 +147,7 @@ typedef struct rt_options {
     int max_outer;
     int chunk;
     int wave_batches;
+    int prefetch;
     int check_every;
 } rt_options;
 

@@ -133,6 +133,8 @@ int validate(const rt_problem *p, const rt_options *o, std::vector<double> &mu_p
         if (o->chunk != 0 && !sweep_chunk_supported(o->chunk, false))
             return fail(RT_EINVAL, "options.chunk must be 0, 4, 8, 16 or 32");
         if (o->check_every < 1) return fail(RT_EINVAL, "options.check_every must be >= 1");
+        if (o->prefetch < 0 || o->prefetch > 3)
+            return fail(RT_EINVAL, "options.prefetch must be in [0, 3]");
         if (o->wave_batches < 0 || o->wave_batches > 64)
             return fail(RT_EINVAL, "options.wave_batches must be in [0, 64]");
     }
@@ -152,7 +154,7 @@ int chunks_for(int ns, int L) {
 int auto_chunk(const std::vector<int> &ns, int rays) {
     const long long target = 256LL * 4 * kWave * 2;
     int best = 4;
-    for (int L : {4, 8, 16}) {
+    for (int L : {4, 8}) {
         bool fits = true;
         long long lanes = 0;
         for (int n : ns) {
@@ -202,7 +204,8 @@ hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, d
     a.atm = h->d_atm;
     a.blk = h->d_blk;
     a.coef = fp32 ? (const void *)h->d_coef32 : (const void *)h->d_coef64;
-    a.rayc = h->d_rayc;
+    a.q = h->d_qt;
+    a.dirc = h->d_dirc;
     a.sig_in = in;
     a.scale = scale;
     a.sig_out = out;
@@ -210,6 +213,7 @@ hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, d
     a.mask = mask;
     a.B = h->d_B;
     a.mode = mode;
+    a.prefetch = h->opt.prefetch;
     hipError_t e = launch_sweep(h->L, fp32, a, h->n_blocks, h->ns_max, s);
     if (e != hipSuccess) return e;
     return launch_finalize(a, h->d_pt_atm, h->ns_total, s);
@@ -263,6 +267,7 @@ void rt_default_options(rt_options *o) {
     o->max_outer = 30;
     o->chunk = 0;
     o->wave_batches = 0;
+    o->prefetch = 0;
     o->check_every = 16;
 }
 
@@ -274,6 +279,7 @@ void rt_destroy(rt_handle *h) {
     if (!h) return;
     void *ptrs[] = {h->d_tau,   h->d_B,     h->d_opac,    h->d_phi,     h->d_mu_pos, h->d_w_pos,
                     h->d_w_nu,  h->d_pt_atm, h->d_atm,    h->d_blk,     h->d_rayc,   h->d_coef64,
+                    h->d_q,     h->d_qt,      h->d_dirc,
                     h->d_coef32, h->d_partial, h->d_diag,  h->d_dinv,   h->d_b,
                     h->d_V,     h->d_H,     h->d_cs,      h->d_sn,      h->d_g,      h->d_w,
                     h->d_r,     h->d_rh,    h->d_p,       h->d_v,       h->d_s,      h->d_t,
@@ -336,23 +342,14 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
             delete h;
             return fail(RT_EINVAL, "options.chunk too short for ns (need 64 * chunk >= ns - 1)");
         }
-    long long coef = 0, part = 0;
+    long long coef = 0, part = 0, qt = 0;
     int blk = 0;
-    // waves per block and wave-batches per wave: aim for at most ~16 blocks
-    // per slab so the cross-block combination stays one short round of loads
+    // Waves per block and wave-batches per wave.  A block never mixes
+    // directions.  Big batches: one block per (slab, direction), the fewest
+    // partial sums; small problems: about 48 blocks in all, for parallelism.
     h->W = sweep_waves(h->L, false);
-    {
-        long long nwb_max = 0;
-        for (int n : h->ns) {
-            const int C = chunks_for(n, h->L);
-            nwb_max = std::max<long long>(nwb_max, (rays + kWave / C - 1) / (kWave / C));
-        }
-        h->NB = (int)std::min<long long>(8, std::max<long long>(1, (nwb_max + 16LL * h->W - 1) /
-                                                                      (16LL * h->W)));
-        if (opt.chunk == 0 && h->n_atm > 1) h->NB = std::min(h->NB, 2);
-        if (opt.wave_batches > 0) h->NB = opt.wave_batches;
-    }
-    const int wb_per_block = h->W * h->NB;
+    const long long dirs_total = (long long)h->n_atm * h->M;
+    const int blocks_per_dir = (int)std::max<long long>(1, (48 + dirs_total - 1) / dirs_total);
     h->atm_h.resize(h->n_atm);
     for (int a = 0; a < h->n_atm; ++a) {
         AtmDesc d{};
@@ -361,30 +358,42 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
         d.C = chunks_for(d.ns, h->L);
         d.Leff = (d.ns - 1 + d.C - 1) / d.C;
         d.G = kWave / d.C;
-        d.nrays = rays;
+        d.n_nu = h->n_nu;
+        d.nwb = (h->n_nu + d.G - 1) / d.G;
         d.ray_off = a * rays;
-        d.nwb = (rays + d.G - 1) / d.G;
-        d.nblk = (d.nwb + wb_per_block - 1) / wb_per_block;
+        int nb = (d.nwb + h->W * blocks_per_dir - 1) / (h->W * blocks_per_dir);
+        nb = std::min(std::max(nb, 1), 32);
+        if (opt.wave_batches > 0) nb = opt.wave_batches;
+        const int wb_per_block = h->W * nb;
+        const int blk_per_dir = (d.nwb + wb_per_block - 1) / wb_per_block;
+        d.nblk = h->M * blk_per_dir;
         d.blk_first = blk;
         d.coef_off = coef;
         d.part_off = part;
+        d.q_off = qt;
         d.eps = p->eps[a];
         d.xi = 1.0 - p->eps[a];
         d.W2 = p->W2[a];
         d.Ibot = p->I_bot ? p->I_bot[a] : (p->B ? p->B[d.doff + d.ns - 1] : 1.0);
-        for (int b = 0; b < d.nblk; ++b) {
-            BlockDesc bd{};
-            bd.atm = a;
-            bd.wb_first = b * wb_per_block;
-            bd.wb_count = std::min(wb_per_block, d.nwb - bd.wb_first);
-            h->blk_h.push_back(bd);
+        for (int m = 0; m < h->M; ++m) {
+            for (int bb = 0; bb < blk_per_dir; ++bb) {
+                BlockDesc bd{};
+                bd.atm = a;
+                bd.m = m;
+                bd.wb_first = bb * wb_per_block;
+                bd.wb_count = std::min(wb_per_block, d.nwb - bd.wb_first);
+                h->blk_h.push_back(bd);
+            }
         }
+        h->NB = nb;
         blk += d.nblk;
-        coef += (long long)d.nwb * d.Leff * kWave;
+        coef += (long long)h->M * d.nwb * d.Leff * kWave;
+        qt += (long long)h->M * d.nwb * d.G;
         part += (long long)d.nblk * 2 * d.ns;
         h->atm_h[a] = d;
     }
     h->n_blocks = blk;
+    h->n_qt = qt;
     h->n_pairs = coef;
     h->n_partial = part;
 
@@ -414,6 +423,9 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     RT_TRY(dalloc(&h->d_atm, h->n_atm));
     RT_TRY(dalloc(&h->d_blk, h->n_blocks));
     RT_TRY(dalloc(&h->d_rayc, (size_t)h->n_atm * rays));
+    RT_TRY(dalloc(&h->d_q, (size_t)h->n_atm * rays));
+    RT_TRY(dalloc(&h->d_qt, (size_t)h->n_qt));
+    RT_TRY(dalloc(&h->d_dirc, (size_t)h->M));
     RT_TRY(dalloc(&h->d_coef64, h->n_pairs));
     RT_TRY(dalloc(&h->d_coef32, h->n_pairs));
     RT_TRY(dalloc(&h->d_partial, std::max<long long>(h->n_partial, 1)));
@@ -434,10 +446,12 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     // ---- precompute: ray constants, tile coefficients, D and D^-1, b
     hipStream_t s = nullptr;
     RT_TRY(hip_check(launch_ray_setup(h->n_atm, h->d_atm, h->d_mu_pos, h->d_w_pos, h->M,
-                                      h->d_w_nu, h->d_phi, h->n_nu, h->normalize, h->d_rayc, s),
+                                      h->d_w_nu, h->d_phi, h->n_nu, h->normalize, h->d_rayc,
+                                      h->d_q, h->d_dirc, s),
                      "ray setup launch"));
     RT_TRY(hip_check(launch_coef_build(h->n_blocks, h->W, h->d_atm, h->d_blk, h->d_tau, h->d_opac,
-                                       h->d_mu_pos, h->n_nu, h->fs, h->d_coef64, h->d_coef32, s),
+                                       h->d_mu_pos, h->fs, h->d_q, h->d_coef64, h->d_coef32,
+                                       h->d_qt, s),
                      "coefficient launch"));
     RT_TRY(hip_check(launch_diag(acc, h->d_pt_atm, h->d_atm, h->d_tau, h->d_opac, h->d_mu_pos,
                                  h->d_rayc, h->M, h->n_nu, h->fs, h->d_diag, h->d_dinv, s),

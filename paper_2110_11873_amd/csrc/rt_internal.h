@@ -17,20 +17,23 @@ constexpr int kSweepLdsBudget = 64 * 1024;  // bytes of LDS a sweep block may us
 constexpr int kKrylovThreads = 256;
 constexpr int kKrylovEPT = (2 * RT_MAX_NS + kKrylovThreads - 1) / kKrylovThreads;
 
-// Per-slab launch plan of the formal-solver sweep.  A ray is one (|mu|, nu)
+// Per-slab launch plan of the formal-solver sweep.  A ray is one (|mu_m|, nu_p)
 // pair; its depth recurrence is split into C chunks of Leff intervals, one
-// chunk per lane, G = 64 / C rays per wavefront ("wave-batch").
+// chunk per lane, G = 64 / C rays per wavefront ("wave-batch").  Wave-batches
+// never mix directions: batch b of direction m holds the rays p = b*G + g.
 struct AtmDesc {
     int ns;         // depth points
     int doff;       // first depth point of the slab in concatenated arrays
     int C;          // chunks per ray (power of two, <= 64)
     int Leff;       // intervals per chunk (<= the kernel's L)
     int G;          // rays per wave-batch
-    int nrays;      // rays: (n_mu / 2) * n_nu
-    int ray_off;    // first entry of the slab in the ray-constant table
-    int nwb;        // wave-batches
+    int n_nu;       // frequencies: rays per direction
+    int nwb;        // wave-batches per direction
+    int ray_off;    // first ray of the slab in the ray tables (rays m*n_nu + p)
     int blk_first;  // first sweep block of the slab
     int nblk;       // sweep blocks of the slab
+    int pad0;
+    long long q_off;     // first entry of the slab's tile-ordered weights
     long long coef_off;  // first coefficient pair of the slab's tiles
     long long part_off;  // first partial sum of the slab's blocks
     double xi;      // 1 - eps
@@ -39,13 +42,14 @@ struct AtmDesc {
     double Ibot;    // bottom inflow for mu > 0
 };
 
-// One sweep block: wave w of a block of W waves handles wave-batches
-// wb_first + w + t * W, t = 0, 1, ..., while < wb_first + wb_count.
+// One sweep block: direction m of slab atm; wave w of a block of W waves
+// handles wave-batches wb_first + w + t * W, t = 0, 1, ..., while below
+// wb_first + wb_count.
 struct BlockDesc {
     int atm;
+    int m;
     int wb_first;
     int wb_count;
-    int pad;
 };
 
 // Quadrature weight of a ray (applied to both directions of the +-mu pair)
@@ -58,7 +62,8 @@ struct SweepArgs {
     const AtmDesc *atm;
     const BlockDesc *blk;
     const void *coef;        // tile-ordered step coefficients (T pairs)
-    const RayConst *rayc;
+    const double *q;         // tile-ordered quadrature weights (see q_off)
+    const double2 *dirc;     // per direction: (T1, T1^2 + T2^2)
     const double *sig_in;    // FP64 input, NULL = zero source
     const double *scale;     // optional elementwise scaling of sig_in
     double *sig_out;         // FP64 output
@@ -70,6 +75,7 @@ struct SweepArgs {
                              //    with the bottom inflow and no source
     int rows;                // 1: one LDS row per wave (W * 2 ns_max values),
                              // 0: one shared row filled wave after wave
+    int prefetch;            // 0: automatic; 1 + number of ray batches loaded ahead
 };
 
 // Waves per sweep block for a chunk length and precision: as many as the
@@ -82,11 +88,13 @@ hipError_t launch_sweep(int L, bool fp32, const SweepArgs &a, int nblocks, int n
                         hipStream_t s);
 hipError_t launch_finalize(const SweepArgs &a, const int *pt_atm, int npts, hipStream_t s);
 hipError_t launch_coef_build(int nblocks, int W, const AtmDesc *atm, const BlockDesc *blk,
-                             const double *tau, const double *opac, const double *mu_pos,
-                             int n_nu, int fs, double2 *coef64, float2 *coef32, hipStream_t s);
+                             const double *tau, const double *opac, const double *mu_pos, int fs,
+                             const double *qray, double2 *coef64, float2 *coef32, double *qtile,
+                             hipStream_t s);
 hipError_t launch_ray_setup(int n_atm, const AtmDesc *atm, const double *mu_pos,
                             const double *w_pos, int M, const double *w_nu, const double *phi,
-                            int n_nu, int normalize, RayConst *rayc, hipStream_t s);
+                            int n_nu, int normalize, RayConst *rayc, double *q, double2 *dirc,
+                            hipStream_t s);
 hipError_t launch_diag(int npts, const int *pt_atm, const AtmDesc *atm, const double *tau,
                        const double *opac, const double *mu_pos, const RayConst *rayc, int M,
                        int n_nu, int fs, double *diag, double *dinv, hipStream_t s);
@@ -121,6 +129,7 @@ struct rt_handle {
     std::vector<rt::BlockDesc> blk_h;
     int L = 8;                 // chunk length the tiles were built for
     int W = 8;                 // waves per sweep block the plan was made for
+    int prefetch = 0;          // sweep prefetch setting (SweepArgs::prefetch)
     int NB = 1;                // wave-batches per wave (per block: W * NB)
     int n_blocks = 0;
     long long n_pairs = 0, n_partial = 0;
@@ -132,6 +141,10 @@ struct rt_handle {
     rt::AtmDesc *d_atm = nullptr;
     rt::BlockDesc *d_blk = nullptr;
     rt::RayConst *d_rayc = nullptr;
+    double *d_q = nullptr;        // per ray quadrature weight
+    double *d_qt = nullptr;       // tile-ordered, zero-padded quadrature weights
+    long long n_qt = 0;
+    double2 *d_dirc = nullptr;    // per direction (T1, T1^2 + T2^2)
     double2 *d_coef64 = nullptr;
     float2 *d_coef32 = nullptr;
     double *d_partial = nullptr;

@@ -17,7 +17,7 @@
 //    which reproduce a constant source exactly).  The C chunks of a ray sit in
 //    C adjacent lanes; a chunk is swept once with zero inflow, the affine
 //    maps I_out = P I_in + e of the chunks are composed by a lane scan
-//    (Hillis-Steele, log2 C shuffles), and the inflow's share T_k I_in (T_k
+//    (row-local DPP shifts, then row broadcasts), and the inflow's share T_k I_in (T_k
 //    the transmission from the chunk's entry to point k, kept from the sweep)
 //    is added at every point.  The step coefficients are read once per
 //    launch, in a tile order where a wavefront's 64 lanes read 64 consecutive
@@ -105,7 +105,7 @@ __device__ inline void step_coef(int fs, double d, double &cu, double &ck) {
 // --------------------------------------------------------------------------
 __global__ void ray_setup_kernel(const AtmDesc *atm, const double *mu_pos, const double *w_pos,
                                  int M, const double *w_nu, const double *phi, int n_nu,
-                                 int normalize, RayConst *rayc) {
+                                 int normalize, RayConst *rayc, double *qray, double2 *dirc) {
     __shared__ double red[256 / kWave];
     const int a = blockIdx.x;
     const double *ph = phi + (long long)a * n_nu;
@@ -132,35 +132,44 @@ __global__ void ray_setup_kernel(const AtmDesc *atm, const double *mu_pos, const
         rc.qt12 = q * (t1 * t1 + t2 * t2);
         rc.pad = 0.0;
         rayc[at.ray_off + r] = rc;
+        qray[at.ray_off + r] = q;
+        if (a == 0 && p == 0) dirc[m] = make_double2(t1, t1 * t1 + t2 * t2);
     }
 }
 
 // --------------------------------------------------------------------------
 // Tile-ordered coefficients: pair (c_u, c_k) of step i of the chunk held by
-// lane `lane` in wave-batch b lives at coef_off + (b * Leff + i) * 64 + lane.
-// Lane = g * C + c holds chunk c (intervals c*Leff .. c*Leff+Leff-1) of ray
-// b*G + g.  Padding (rays beyond the last, intervals beyond ns - 2) is zero,
-// which makes the step the identity.
+// lane `lane` in wave-batch b of direction m lives at
+//   coef_off + ((m * nwb + b) * Leff + i) * 64 + lane.
+// Lane = g * C + c holds chunk c (intervals c*Leff .. c*Leff+Leff-1) of the
+// ray (m, p = b*G + g).  Padding (frequencies beyond the last, intervals
+// beyond ns - 2) is zero, which makes the step the identity.  The rays'
+// quadrature weights are laid out the same way (q_off + (m*nwb + b)*G + g),
+// zero for padding rays, so the sweep never masks a loaded value.
 // --------------------------------------------------------------------------
 __global__ void coef_build_kernel(int W, const AtmDesc *atm, const BlockDesc *blk,
                                   const double *tau, const double *opac, const double *mu_pos,
-                                  int n_nu, int fs, double2 *coef64, float2 *coef32) {
+                                  int fs, const double *qray, double2 *coef64, float2 *coef32,
+                                  double *qtile) {
     const BlockDesc bd = blk[blockIdx.x];
     const AtmDesc at = atm[bd.atm];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int c = lane % at.C, g = lane / at.C;
     for (int b = bd.wb_first + wave; b < bd.wb_first + bd.wb_count; b += W) {
-        const int r = b * at.G + g;
+        const int p = b * at.G + g;
+        if (c == 0)  // quadrature weight of the ray, zero for padding rays
+            qtile[at.q_off + ((long long)bd.m * at.nwb + b) * at.G + g] =
+                (p < at.n_nu) ? qray[at.ray_off + (long long)bd.m * at.n_nu + p] : 0.0;
         for (int i = 0; i < at.Leff; ++i) {
             const int j = c * at.Leff + i;
             double cu = 0.0, ck = 0.0;
-            if (r < at.nrays && j < at.ns - 1) {
-                const int m = r / n_nu, p = r % n_nu;
-                const double kap = opac[(long long)bd.atm * n_nu + p] / mu_pos[m];
+            if (p < at.n_nu && j < at.ns - 1) {
+                const double kap = opac[(long long)bd.atm * at.n_nu + p] / mu_pos[bd.m];
                 const double d = kap * (tau[at.doff + j + 1] - tau[at.doff + j]);
                 step_coef(fs, d, cu, ck);
             }
-            const long long e = at.coef_off + ((long long)b * at.Leff + i) * kWave + lane;
+            const long long e =
+                at.coef_off + (((long long)bd.m * at.nwb + b) * at.Leff + i) * kWave + lane;
             coef64[e] = make_double2(cu, ck);
             coef32[e] = make_float2((float)cu, (float)ck);
         }
@@ -231,7 +240,103 @@ struct Pair<float> {
     using type = float2;
 };
 
-template <typename T, int L, int W>
+// --------------------------------------------------------------------------
+// Cross-lane moves for the chunk scans.  DPP (data-parallel primitives) move
+// a register between lanes inside the VALU without going through LDS:
+// row_shr:d / row_shl:d shift within rows of 16 lanes, row_bcast:15 / :31
+// broadcast the last lane of a row (of two rows) to the next row(s),
+// wave_shr:1 / wave_shl:1 shift the whole wave by one lane.  Lanes with no
+// source receive 0.
+// --------------------------------------------------------------------------
+namespace {
+
+constexpr int kRowShr = 0x110, kRowShl = 0x100, kWaveShr1 = 0x138, kWaveShl1 = 0x130,
+              kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+template <int CTRL, int ROWS>
+__device__ inline float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+template <int CTRL, int ROWS>
+__device__ inline double dpp(double v) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(x & 0xffffffffLL), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, ROWS, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Compose the chunk maps x -> P x + e of a ray's C chunks (C adjacent lanes,
+// C a power of two).  Forward: lane c ends with the map of chunks 0..c;
+// backward: lane c ends with the map of chunks c..C-1.  (U, V) are the two
+// sources sharing the transmission P.
+template <typename T>
+__device__ inline void affine_level(T &P, T &U, T &V, T pP, T pU, T pV, bool take) {
+    if (take) {
+        U = P * pU + U;
+        V = P * pV + V;
+        P = P * pP;
+    }
+}
+
+template <int D, typename T>
+__device__ inline void fwd_row_level(T &P, T &U, T &V, int lr, int R) {
+    if (D < R) {
+        const T pP = dpp<kRowShr + D, 0xF>(P), pU = dpp<kRowShr + D, 0xF>(U),
+                pV = dpp<kRowShr + D, 0xF>(V);
+        affine_level(P, U, V, pP, pU, pV, lr >= D);
+    }
+}
+template <int D, typename T>
+__device__ inline void bwd_row_level(T &P, T &U, T &V, int lr, int R) {
+    if (D < R) {
+        const T nP = dpp<kRowShl + D, 0xF>(P), nU = dpp<kRowShl + D, 0xF>(U),
+                nV = dpp<kRowShl + D, 0xF>(V);
+        affine_level(P, U, V, nP, nU, nV, lr + D < R);
+    }
+}
+
+template <typename T>
+__device__ inline void scan_forward(T &P, T &U, T &V, int lane, int C) {
+    const int R = C < 16 ? C : 16;  // segment length inside a row
+    const int lr = lane & (R - 1);
+    fwd_row_level<1>(P, U, V, lr, R);
+    fwd_row_level<2>(P, U, V, lr, R);
+    fwd_row_level<4>(P, U, V, lr, R);
+    fwd_row_level<8>(P, U, V, lr, R);
+    if (C >= 32) {  // rows 1 and 3 take the last lane of rows 0 and 2
+        const T pP = dpp<kRowBcast15, 0xA>(P), pU = dpp<kRowBcast15, 0xA>(U),
+                pV = dpp<kRowBcast15, 0xA>(V);
+        affine_level(P, U, V, pP, pU, pV, (lane & 16) != 0);
+    }
+    if (C == 64) {  // rows 2 and 3 take lane 31
+        const T pP = dpp<kRowBcast31, 0xC>(P), pU = dpp<kRowBcast31, 0xC>(U),
+                pV = dpp<kRowBcast31, 0xC>(V);
+        affine_level(P, U, V, pP, pU, pV, (lane & 32) != 0);
+    }
+}
+
+template <typename T>
+__device__ inline void scan_backward(T &P, T &U, T &V, int lane, int C) {
+    const int R = C < 16 ? C : 16;
+    const int lr = lane & (R - 1);
+    bwd_row_level<1>(P, U, V, lr, R);
+    bwd_row_level<2>(P, U, V, lr, R);
+    bwd_row_level<4>(P, U, V, lr, R);
+    bwd_row_level<8>(P, U, V, lr, R);
+    if (C >= 32) {  // rows 0 and 2 take the first lane of rows 1 and 3
+        const int src = (lane | 15) + 1;
+        const T nP = __shfl(P, src & 63), nU = __shfl(U, src & 63), nV = __shfl(V, src & 63);
+        affine_level(P, U, V, nP, nU, nV, (lane & 16) == 0);
+    }
+    if (C == 64) {  // rows 0 and 1 take lane 32
+        const T nP = __shfl(P, 32), nU = __shfl(U, 32), nV = __shfl(V, 32);
+        affine_level(P, U, V, nP, nU, nV, (lane & 32) == 0);
+    }
+}
+
+}  // namespace
+
+template <typename T, int L, int W, int PF>
 __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
     using P2 = typename Pair<T>::type;
     extern __shared__ unsigned char smem_raw[];
@@ -280,36 +385,52 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
         for (int i = 0; i <= L; ++i) sg0[i] = sg2[i] = (T)0;
     }
 
-    T acc0[L + 1], acc2[L + 1];
+    // AU = sum_rays q (I from s00), AV = sum_rays q (I from s20), by point;
+    // every ray of the block has the same direction, so the T factors are
+    // applied once at the end
+    T AU[L + 1], AV[L + 1];
 #pragma unroll
-    for (int i = 0; i <= L; ++i) acc0[i] = acc2[i] = (T)0;
+    for (int i = 0; i <= L; ++i) AU[i] = AV[i] = (T)0;
 
     const T inflow = (a.mode == 1) ? (T)at.Ibot : (T)0;
-    const P2 *coef = reinterpret_cast<const P2 *>(a.coef) + at.coef_off;
+    const P2 *coef = reinterpret_cast<const P2 *>(a.coef) + at.coef_off +
+                     (long long)bd.m * at.nwb * Leff * kWave + lane;
+    const double *qdir = a.q + at.q_off + (long long)bd.m * at.nwb * at.G + g;
     const int bend = bd.wb_first + bd.wb_count;
 
-    // software pipeline: batch b + W's coefficients load while b computes
-    P2 cn[L];
-    double4 rn = make_double4(0.0, 0.0, 0.0, 0.0);
-    auto load_batch = [&](int b) {
-        const P2 *tile = coef + (long long)b * Leff * kWave + lane;
+    // ray batches are loaded PF batches ahead of use (PF = 0: on use)
+    constexpr int NBUF = PF > 0 ? PF : 1;
+    P2 cbuf[NBUF][L];
+    double qbuf[NBUF];
+    auto load_batch = [&](int b, P2 (&cn)[L], double &qn) {
+        const P2 *tile = coef + (long long)b * Leff * kWave;
 #pragma unroll
         for (int i = 0; i < L; ++i) cn[i] = tile[(long long)min(i, Leff - 1) * kWave];
-        const int r = b * at.G + g;
-        rn = *reinterpret_cast<const double4 *>(a.rayc + at.ray_off + min(r, at.nrays - 1));
-        if (r >= at.nrays) rn = make_double4(0.0, 0.0, 0.0, 0.0);
+        qn = qdir[(long long)b * at.G];
     };
-    int b = bd.wb_first + wave;
-    if (b < bend) load_batch(b);
-    for (; b < bend; b += W) {
+    const int b0 = bd.wb_first + wave;
+#pragma unroll
+    for (int s = 0; s < PF; ++s)
+        if (b0 + s * W < bend) load_batch(b0 + s * W, cbuf[s], qbuf[s]);
+    for (int b = b0; b < bend; b += W) {
+        if (PF == 0) load_batch(b, cbuf[0], qbuf[0]);
         T cu[L], ck[L];
 #pragma unroll
         for (int i = 0; i < L; ++i) {
-            cu[i] = cn[i].x;
-            ck[i] = cn[i].y;
+            cu[i] = cbuf[0][i].x;
+            ck[i] = cbuf[0][i].y;
         }
-        const T q = (T)rn.x, qt1 = (T)rn.y, qt12 = (T)rn.z;
-        if (b + W < bend) load_batch(b + W);
+        const T q = (T)qbuf[0];
+        if (PF > 0) {
+            // rotate the ring and load the batch PF steps ahead into its tail
+#pragma unroll
+            for (int s = 0; s + 1 < NBUF; ++s) {
+#pragma unroll
+                for (int i = 0; i < L; ++i) cbuf[s][i] = cbuf[s + 1][i];
+                qbuf[s] = qbuf[s + 1];
+            }
+            if (b + PF * W < bend) load_batch(b + PF * W, cbuf[NBUF - 1], qbuf[NBUF - 1]);
+        }
 
         // one pass over the chunk with zero inflow in both directions: the
         // local intensities go into the quadrature at once, and the running
@@ -325,8 +446,8 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
                 dV = E * dV + (cu[i] * sg2[i] + ck[i] * sg2[i + 1]);
                 t *= E;
                 Td[i] = t;
-                acc0[i + 1] += q * dU + qt1 * dV;
-                acc2[i + 1] += qt1 * dU + qt12 * dV;
+                AU[i + 1] = fma(q, dU, AU[i + 1]);
+                AV[i + 1] = fma(q, dV, AV[i + 1]);
             }
         }
         T uU = (T)0, uV = (T)0;
@@ -339,34 +460,21 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
                 uV = E * uV + (cu[i] * sg2[i + 1] + ck[i] * sg2[i]);
                 t *= E;
                 Tu[i] = t;
-                acc0[i] += q * uU + qt1 * uV;
-                acc2[i] += qt1 * uU + qt12 * uV;
+                AU[i] = fma(q, uU, AU[i]);
+                AV[i] = fma(q, uV, AV[i]);
             }
         }
 
         // lane scans of the chunk maps I_out = P I_in + e: downward chunks
         // compose left to right, upward ones right to left
         T Pd = t, Pu = t;
-        for (int d = 1; d < C; d <<= 1) {
-            const T pP = __shfl_up(Pd, d, C), pU = __shfl_up(dU, d, C), pV = __shfl_up(dV, d, C);
-            const T nP = __shfl_down(Pu, d, C), nU = __shfl_down(uU, d, C),
-                    nV = __shfl_down(uV, d, C);
-            if (c >= d) {
-                dU = Pd * pU + dU;
-                dV = Pd * pV + dV;
-                Pd *= pP;
-            }
-            if (c + d < C) {
-                uU = Pu * nU + uU;
-                uV = Pu * nV + uV;
-                Pu *= nP;
-            }
-        }
+        scan_forward(Pd, dU, dV, lane, C);
+        scan_backward(Pu, uU, uV, lane, C);
         // inflows at the chunk's entry points: from the chunk above (down),
         // from the chunk below or the bottom boundary (up)
-        T cdU = __shfl_up(dU, 1, C), cdV = __shfl_up(dV, 1, C);
-        const T nPu = __shfl_down(Pu, 1, C);
-        T cuU = __shfl_down(uU, 1, C) + nPu * inflow, cuV = __shfl_down(uV, 1, C);
+        T cdU = dpp<kWaveShr1, 0xF>(dU), cdV = dpp<kWaveShr1, 0xF>(dV);
+        const T nPu = dpp<kWaveShl1, 0xF>(Pu);
+        T cuU = dpp<kWaveShl1, 0xF>(uU) + nPu * inflow, cuV = dpp<kWaveShl1, 0xF>(uV);
         if (c == 0) cdU = cdV = (T)0;
         if (c == C - 1) {
             cuU = inflow;
@@ -374,15 +482,14 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
         }
 
         // inflow terms: I_true = I_local + T * I_in at every point of the chunk
-        const T cD0 = q * cdU + qt1 * cdV, cD2 = qt1 * cdU + qt12 * cdV;
-        const T cU0 = q * cuU + qt1 * cuV, cU2 = qt1 * cuU + qt12 * cuV;
+        const T qdU = q * cdU, qdV = q * cdV, quU = q * cuU, quV = q * cuV;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             if (i < Leff) {
-                acc0[i + 1] += Td[i] * cD0;
-                acc2[i + 1] += Td[i] * cD2;
-                acc0[i] += Tu[i] * cU0;
-                acc2[i] += Tu[i] * cU2;
+                AU[i + 1] = fma(Td[i], qdU, AU[i + 1]);
+                AV[i + 1] = fma(Td[i], qdV, AV[i + 1]);
+                AU[i] = fma(Tu[i], quU, AU[i]);
+                AV[i] = fma(Tu[i], quV, AV[i]);
             }
         }
         if (a.mode == 1 && c == C - 1 && s0 + Leff == ns - 1) {
@@ -390,8 +497,8 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
 #pragma unroll
             for (int i = 0; i <= L; ++i) {
                 if (i == Leff) {
-                    acc0[i] += cU0;
-                    acc2[i] += cU2;
+                    AU[i] += quU;
+                    AV[i] += quV;
                 }
             }
         }
@@ -401,26 +508,29 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
     for (int off = C; off < kWave; off <<= 1) {
 #pragma unroll
         for (int i = 0; i <= L; ++i) {
-            acc0[i] += __shfl_xor(acc0[i], off);
-            acc2[i] += __shfl_xor(acc2[i], off);
+            AU[i] += __shfl_xor(AU[i], off);
+            AV[i] += __shfl_xor(AV[i], off);
         }
     }
     // the downward value at a chunk's end point belongs to the next chunk's first point
-    T b0 = (T)0, b2 = (T)0;
+    T bU = (T)0, bV = (T)0;
 #pragma unroll
     for (int i = 0; i <= L; ++i) {
         if (i == Leff) {
-            b0 = acc0[i];
-            b2 = acc2[i];
+            bU = AU[i];
+            bV = AV[i];
         }
     }
     {
-        const T p0 = __shfl_up(b0, 1, C), p2 = __shfl_up(b2, 1, C);
+        const T pU = dpp<kWaveShr1, 0xF>(bU), pV = dpp<kWaveShr1, 0xF>(bV);
         if (c > 0) {
-            acc0[0] += p0;
-            acc2[0] += p2;
+            AU[0] += pU;
+            AV[0] += pV;
         }
     }
+    // J00 = AU + T1 AV, J20 = T1 AU + (T1^2 + T2^2) AV for this direction
+    const double2 tf = a.dirc[bd.m];
+    const T t1 = (T)tf.x, t12 = (T)tf.y;
 
     // block totals of the 2 ns quadrature sums
     const int nthr = kWave * W;
@@ -433,20 +543,20 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
             for (int i = 0; i < L; ++i) {
                 const int k = s0 + i;
                 if (i < Leff && k < ns) {
-                    row[2 * k] = acc0[i];
-                    row[2 * k + 1] = acc2[i];
+                    row[2 * k] = AU[i] + t1 * AV[i];
+                    row[2 * k + 1] = t1 * AU[i] + t12 * AV[i];
                 }
             }
             if (c == C - 1 && s0 + Leff == ns - 1) {
-                row[2 * (ns - 1)] = b0;
-                row[2 * (ns - 1) + 1] = b2;
+                row[2 * (ns - 1)] = bU + t1 * bV;
+                row[2 * (ns - 1) + 1] = t1 * bU + t12 * bV;
             }
         }
         __syncthreads();
         for (int e = threadIdx.x; e < 2 * ns; e += nthr) {
-            T t = sacc[e];
-            for (int w = 1; w < W; ++w) t += sacc[(long long)w * 2 * ns + e];
-            mine[e] = (double)t;
+            T s = sacc[e];
+            for (int w = 1; w < W; ++w) s += sacc[(long long)w * 2 * ns + e];
+            mine[e] = (double)s;
         }
     } else {
         // one shared row, filled wave after wave (fixed order)
@@ -458,13 +568,13 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
                 for (int i = 0; i < L; ++i) {
                     const int k = s0 + i;
                     if (i < Leff && k < ns) {
-                        sacc[2 * k] += acc0[i];
-                        sacc[2 * k + 1] += acc2[i];
+                        sacc[2 * k] += AU[i] + t1 * AV[i];
+                        sacc[2 * k + 1] += t1 * AU[i] + t12 * AV[i];
                     }
                 }
                 if (c == C - 1 && s0 + Leff == ns - 1) {
-                    sacc[2 * (ns - 1)] += b0;
-                    sacc[2 * (ns - 1) + 1] += b2;
+                    sacc[2 * (ns - 1)] += bU + t1 * bV;
+                    sacc[2 * (ns - 1) + 1] += t1 * bU + t12 * bV;
                 }
             }
             __syncthreads();
@@ -538,7 +648,16 @@ static hipError_t launch_sweep_tw(SweepArgs a, int nblocks, int ns_max, hipStrea
     const size_t row = 2 * (size_t)ns_max * sizeof(T);
     a.rows = (W * row <= (size_t)kSweepLdsBudget) ? 1 : 0;
     const size_t lds = a.rows ? W * row : row;
-    hipLaunchKernelGGL((sweep_kernel<T, L, W>), dim3(nblocks), dim3(kWave * W), lds, s, a);
+    // ray batches in flight ahead of use: a.prefetch (0 = by register budget)
+    int pf = a.prefetch;
+    if (pf == 0) pf = (sizeof(T) * L <= 32) ? 2 : 1;
+    pf -= 1;
+    if (pf >= 2 && sizeof(T) * L <= 64)
+        hipLaunchKernelGGL((sweep_kernel<T, L, W, 2>), dim3(nblocks), dim3(kWave * W), lds, s, a);
+    else if (pf >= 1)
+        hipLaunchKernelGGL((sweep_kernel<T, L, W, 1>), dim3(nblocks), dim3(kWave * W), lds, s, a);
+    else
+        hipLaunchKernelGGL((sweep_kernel<T, L, W, 0>), dim3(nblocks), dim3(kWave * W), lds, s, a);
     return hipGetLastError();
 }
 
@@ -581,19 +700,21 @@ hipError_t launch_sweep(int L, bool fp32, const SweepArgs &a, int nblocks, int n
 }
 
 hipError_t launch_coef_build(int nblocks, int W, const AtmDesc *atm, const BlockDesc *blk,
-                             const double *tau, const double *opac, const double *mu_pos,
-                             int n_nu, int fs, double2 *coef64, float2 *coef32, hipStream_t s) {
+                             const double *tau, const double *opac, const double *mu_pos, int fs,
+                             const double *qray, double2 *coef64, float2 *coef32, double *qtile,
+                             hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(coef_build_kernel, dim3(nblocks), dim3(kWave * W), 0, s, W, atm, blk, tau,
-                       opac, mu_pos, n_nu, fs, coef64, coef32);
+                       opac, mu_pos, fs, qray, coef64, coef32, qtile);
     return hipGetLastError();
 }
 
 hipError_t launch_ray_setup(int n_atm, const AtmDesc *atm, const double *mu_pos,
                             const double *w_pos, int M, const double *w_nu, const double *phi,
-                            int n_nu, int normalize, RayConst *rayc, hipStream_t s) {
+                            int n_nu, int normalize, RayConst *rayc, double *q, double2 *dirc,
+                            hipStream_t s) {
     hipLaunchKernelGGL(ray_setup_kernel, dim3(n_atm), dim3(256), 0, s, atm, mu_pos, w_pos, M,
-                       w_nu, phi, n_nu, normalize, rayc);
+                       w_nu, phi, n_nu, normalize, rayc, q, dirc);
     return hipGetLastError();
 }
 
