@@ -206,6 +206,7 @@ hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, d
     a.coef = fp32 ? (const void *)h->d_coef32 : (const void *)h->d_coef64;
     a.q = h->d_qt;
     a.dirc = h->d_dirc;
+    a.Qs = h->d_Qs;
     a.sig_in = in;
     a.scale = scale;
     a.sig_out = out;
@@ -279,7 +280,7 @@ void rt_destroy(rt_handle *h) {
     if (!h) return;
     void *ptrs[] = {h->d_tau,   h->d_B,     h->d_opac,    h->d_phi,     h->d_mu_pos, h->d_w_pos,
                     h->d_w_nu,  h->d_pt_atm, h->d_atm,    h->d_blk,     h->d_rayc,   h->d_coef64,
-                    h->d_q,     h->d_qt,      h->d_dirc,
+                    h->d_q,     h->d_qt,      h->d_dirc,    h->d_Qs,
                     h->d_coef32, h->d_partial, h->d_diag,  h->d_dinv,   h->d_b,
                     h->d_V,     h->d_H,     h->d_cs,      h->d_sn,      h->d_g,      h->d_w,
                     h->d_r,     h->d_rh,    h->d_p,       h->d_v,       h->d_s,      h->d_t,
@@ -426,6 +427,7 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     RT_TRY(dalloc(&h->d_q, (size_t)h->n_atm * rays));
     RT_TRY(dalloc(&h->d_qt, (size_t)h->n_qt));
     RT_TRY(dalloc(&h->d_dirc, (size_t)h->M));
+    RT_TRY(dalloc(&h->d_Qs, (size_t)h->n_atm));
     RT_TRY(dalloc(&h->d_coef64, h->n_pairs));
     RT_TRY(dalloc(&h->d_coef32, h->n_pairs));
     RT_TRY(dalloc(&h->d_partial, std::max<long long>(h->n_partial, 1)));
@@ -447,7 +449,7 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     hipStream_t s = nullptr;
     RT_TRY(hip_check(launch_ray_setup(h->n_atm, h->d_atm, h->d_mu_pos, h->d_w_pos, h->M,
                                       h->d_w_nu, h->d_phi, h->n_nu, h->normalize, h->d_rayc,
-                                      h->d_q, h->d_dirc, s),
+                                      h->d_q, h->d_dirc, h->d_Qs, s),
                      "ray setup launch"));
     RT_TRY(hip_check(launch_coef_build(h->n_blocks, h->W, h->d_atm, h->d_blk, h->d_tau, h->d_opac,
                                        h->d_mu_pos, h->fs, h->d_q, h->d_coef64, h->d_coef32,

@@ -64,6 +64,7 @@ struct SweepArgs {
     const void *coef;        // tile-ordered step coefficients (T pairs)
     const double *q;         // tile-ordered quadrature weights (see q_off)
     const double2 *dirc;     // per direction: (T1, T1^2 + T2^2)
+    const double4 *Qs;       // per slab: sums over all rays of q, q T1, q (T1^2 + T2^2)
     const double *sig_in;    // FP64 input, NULL = zero source
     const double *scale;     // optional elementwise scaling of sig_in
     double *sig_out;         // FP64 output
@@ -94,7 +95,7 @@ hipError_t launch_coef_build(int nblocks, int W, const AtmDesc *atm, const Block
 hipError_t launch_ray_setup(int n_atm, const AtmDesc *atm, const double *mu_pos,
                             const double *w_pos, int M, const double *w_nu, const double *phi,
                             int n_nu, int normalize, RayConst *rayc, double *q, double2 *dirc,
-                            hipStream_t s);
+                            double4 *Qs, hipStream_t s);
 hipError_t launch_diag(int npts, const int *pt_atm, const AtmDesc *atm, const double *tau,
                        const double *opac, const double *mu_pos, const RayConst *rayc, int M,
                        int n_nu, int fs, double *diag, double *dinv, hipStream_t s);
@@ -145,6 +146,7 @@ struct rt_handle {
     double *d_qt = nullptr;       // tile-ordered, zero-padded quadrature weights
     long long n_qt = 0;
     double2 *d_dirc = nullptr;    // per direction (T1, T1^2 + T2^2)
+    double4 *d_Qs = nullptr;      // per slab quadrature moments (Q0, Q1, Q2)
     double2 *d_coef64 = nullptr;
     float2 *d_coef32 = nullptr;
     double *d_partial = nullptr;

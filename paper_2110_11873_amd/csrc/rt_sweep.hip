@@ -105,8 +105,10 @@ __device__ inline void step_coef(int fs, double d, double &cu, double &ck) {
 // --------------------------------------------------------------------------
 __global__ void ray_setup_kernel(const AtmDesc *atm, const double *mu_pos, const double *w_pos,
                                  int M, const double *w_nu, const double *phi, int n_nu,
-                                 int normalize, RayConst *rayc, double *qray, double2 *dirc) {
+                                 int normalize, RayConst *rayc, double *qray, double2 *dirc,
+                                 double4 *Qs) {
     __shared__ double red[256 / kWave];
+    __shared__ double red3[3 * (256 / kWave)];
     const int a = blockIdx.x;
     const double *ph = phi + (long long)a * n_nu;
     double norm = 1.0;
@@ -120,6 +122,7 @@ __global__ void ray_setup_kernel(const AtmDesc *atm, const double *mu_pos, const
         for (int i = 0; i < (int)(blockDim.x / kWave); ++i) norm += red[i];
     }
     const AtmDesc at = atm[a];
+    double sq = 0.0, sq1 = 0.0, sq12 = 0.0;
     for (int r = threadIdx.x; r < M * n_nu; r += blockDim.x) {
         const int m = r / n_nu, p = r % n_nu;
         const double mu2 = mu_pos[m] * mu_pos[m];
@@ -134,6 +137,31 @@ __global__ void ray_setup_kernel(const AtmDesc *atm, const double *mu_pos, const
         rayc[at.ray_off + r] = rc;
         qray[at.ray_off + r] = q;
         if (a == 0 && p == 0) dirc[m] = make_double2(t1, t1 * t1 + t2 * t2);
+        sq += rc.q;
+        sq1 += rc.qt1;
+        sq12 += rc.qt12;
+    }
+    // both directions of every (|mu|, nu) pair carry the weight q
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        sq += __shfl_xor(sq, off);
+        sq1 += __shfl_xor(sq1, off);
+        sq12 += __shfl_xor(sq12, off);
+    }
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red3[3 * (threadIdx.x / kWave)] = sq;
+        red3[3 * (threadIdx.x / kWave) + 1] = sq1;
+        red3[3 * (threadIdx.x / kWave) + 2] = sq12;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+            t0 += red3[3 * w];
+            t1 += red3[3 * w + 1];
+            t2 += red3[3 * w + 2];
+        }
+        Qs[a] = make_double4(2.0 * t0, 2.0 * t1, 2.0 * t2, 0.0);
     }
 }
 
@@ -351,48 +379,84 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
     const int s0 = c * Leff;  // first depth point of this lane's chunk
     const long long vbase = 2LL * at.doff;
 
-    // sources s00, s20 at the chunk's points: every load issued before any
-    // use (addresses clamped into the slab, values past it zeroed)
-    T sg0[L + 1], sg2[L + 1];
+    // The sweep carries the deviation D = I - S of the intensity from the
+    // local source: with E + c_u = 1 - c_k the step becomes
+    //   D_k = E D_u + (1 - c_k) (S_u - S_k),
+    // which only accumulates differences of the source, so its rounding stays
+    // small against J even where I ~ S (thermalized layers, the FP32 sweep of
+    // the mixed-precision solve).  The source part sum q S is added exactly,
+    // in FP64, by the finalize pass.
+    //
+    // Sources s00, s20 at the chunk's points, every load issued before any
+    // use (addresses clamped into the slab, values past it zeroed); dl[i] =
+    // S(point i) - S(point i + 1); top/bottom: sources at the slab's first and
+    // last point, for the boundary deviations.
+    T dl0[L], dl2[L];
+    T top0 = (T)0, top2 = (T)0, bot0 = (T)0, bot2 = (T)0;
     if (a.sig_in) {
-        double2 v[L + 1];
+        double2 v[L + 1], vt, vb;
 #pragma unroll
         for (int i = 0; i <= L; ++i) {
             const int k = min(s0 + i, ns - 1);
             v[i] = *reinterpret_cast<const double2 *>(a.sig_in + vbase + 2LL * k);
         }
+        vt = *reinterpret_cast<const double2 *>(a.sig_in + vbase);
+        vb = *reinterpret_cast<const double2 *>(a.sig_in + vbase + 2LL * (ns - 1));
         if (a.scale) {
-            double2 sc[L + 1];
+            double2 sc[L + 1], st, sb;
 #pragma unroll
             for (int i = 0; i <= L; ++i) {
                 const int k = min(s0 + i, ns - 1);
                 sc[i] = *reinterpret_cast<const double2 *>(a.scale + vbase + 2LL * k);
             }
+            st = *reinterpret_cast<const double2 *>(a.scale + vbase);
+            sb = *reinterpret_cast<const double2 *>(a.scale + vbase + 2LL * (ns - 1));
 #pragma unroll
             for (int i = 0; i <= L; ++i) {
                 v[i].x *= sc[i].x;
                 v[i].y *= sc[i].y;
             }
+            vt.x *= st.x;
+            vt.y *= st.y;
+            vb.x *= sb.x;
+            vb.y *= sb.y;
         }
+        T s0v[L + 1], s2v[L + 1];
 #pragma unroll
         for (int i = 0; i <= L; ++i) {
             const bool in = (i <= Leff) && (s0 + i < ns);
-            sg0[i] = in ? (T)v[i].x : (T)0;
-            sg2[i] = in ? (T)v[i].y : (T)0;
+            s0v[i] = in ? (T)v[i].x : (T)0;
+            s2v[i] = in ? (T)v[i].y : (T)0;
         }
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            dl0[i] = s0v[i] - s0v[i + 1];
+            dl2[i] = s2v[i] - s2v[i + 1];
+        }
+        top0 = (T)vt.x;
+        top2 = (T)vt.y;
+        bot0 = (T)vb.x;
+        bot2 = (T)vb.y;
     } else {
 #pragma unroll
-        for (int i = 0; i <= L; ++i) sg0[i] = sg2[i] = (T)0;
+        for (int i = 0; i < L; ++i) dl0[i] = dl2[i] = (T)0;
     }
 
-    // AU = sum_rays q (I from s00), AV = sum_rays q (I from s20), by point;
+    // AU = sum_rays q (D from s00), AV = sum_rays q (D from s20), by point;
     // every ray of the block has the same direction, so the T factors are
     // applied once at the end
     T AU[L + 1], AV[L + 1];
 #pragma unroll
     for (int i = 0; i <= L; ++i) AU[i] = AV[i] = (T)0;
 
+    // deviations entering the slab: I = 0 at the top; I = Ibot (right-hand
+    // side) or 0 (operator) at the bottom, whose entry point is the last
+    // chunk's end point -- a point of the slab or past it (source zero)
     const T inflow = (a.mode == 1) ? (T)at.Ibot : (T)0;
+    const T topD0 = -top0, topD2 = -top2;
+    const bool bottom_on_grid = C * Leff == ns - 1;
+    const T botD0 = inflow - (bottom_on_grid ? bot0 : (T)0);
+    const T botD2 = -(bottom_on_grid ? bot2 : (T)0);
     const P2 *coef = reinterpret_cast<const P2 *>(a.coef) + at.coef_off +
                      (long long)bd.m * at.nwb * Leff * kWave + lane;
     const double *qdir = a.q + at.q_off + (long long)bd.m * at.nwb * at.G + g;
@@ -433,7 +497,7 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
         }
 
         // one pass over the chunk with zero inflow in both directions: the
-        // local intensities go into the quadrature at once, and the running
+        // local deviations go into the quadrature at once, and the running
         // transmissions Td[i] = E_0..E_i, Tu[i] = E_i..E_{Leff-1} are kept
         // for the inflow term added after the scan
         T Td[L], Tu[L];
@@ -441,9 +505,10 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             if (i < Leff) {
-                const T E = (T)1 - cu[i] - ck[i];
-                dU = E * dU + (cu[i] * sg0[i] + ck[i] * sg0[i + 1]);
-                dV = E * dV + (cu[i] * sg2[i] + ck[i] * sg2[i + 1]);
+                const T w = (T)1 - ck[i];
+                const T E = w - cu[i];
+                dU = fma(E, dU, w * dl0[i]);
+                dV = fma(E, dV, w * dl2[i]);
                 t *= E;
                 Td[i] = t;
                 AU[i + 1] = fma(q, dU, AU[i + 1]);
@@ -455,9 +520,10 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
 #pragma unroll
         for (int i = L - 1; i >= 0; --i) {
             if (i < Leff) {
-                const T E = (T)1 - cu[i] - ck[i];
-                uU = E * uU + (cu[i] * sg0[i + 1] + ck[i] * sg0[i]);
-                uV = E * uV + (cu[i] * sg2[i + 1] + ck[i] * sg2[i]);
+                const T w = (T)1 - ck[i];
+                const T E = w - cu[i];
+                uU = fma(E, uU, -w * dl0[i]);
+                uV = fma(E, uV, -w * dl2[i]);
                 t *= E;
                 Tu[i] = t;
                 AU[i] = fma(q, uU, AU[i]);
@@ -472,16 +538,19 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
         scan_backward(Pu, uU, uV, lane, C);
         // inflows at the chunk's entry points: from the chunk above (down),
         // from the chunk below or the bottom boundary (up)
-        T cdU = dpp<kWaveShr1, 0xF>(dU), cdV = dpp<kWaveShr1, 0xF>(dV);
-        const T nPu = dpp<kWaveShl1, 0xF>(Pu);
-        T cuU = dpp<kWaveShl1, 0xF>(uU) + nPu * inflow, cuV = dpp<kWaveShl1, 0xF>(uV);
-        if (c == 0) cdU = cdV = (T)0;
+        const T pPd = dpp<kWaveShr1, 0xF>(Pd), nPu = dpp<kWaveShl1, 0xF>(Pu);
+        T cdU = dpp<kWaveShr1, 0xF>(dU) + pPd * topD0, cdV = dpp<kWaveShr1, 0xF>(dV) + pPd * topD2;
+        T cuU = dpp<kWaveShl1, 0xF>(uU) + nPu * botD0, cuV = dpp<kWaveShl1, 0xF>(uV) + nPu * botD2;
+        if (c == 0) {
+            cdU = topD0;
+            cdV = topD2;
+        }
         if (c == C - 1) {
-            cuU = inflow;
-            cuV = (T)0;
+            cuU = botD0;
+            cuV = botD2;
         }
 
-        // inflow terms: I_true = I_local + T * I_in at every point of the chunk
+        // inflow terms: D_true = D_local + T * D_in at every point of the chunk
         const T qdU = q * cdU, qdV = q * cdV, quU = q * cuU, quV = q * cuV;
 #pragma unroll
         for (int i = 0; i < L; ++i) {
@@ -492,8 +561,13 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
                 AV[i] = fma(Tu[i], quV, AV[i]);
             }
         }
-        if (a.mode == 1 && c == C - 1 && s0 + Leff == ns - 1) {
-            // the bottom point is this chunk's entry point: its intensity is the inflow
+        if (c == 0) {  // the top point's downward deviation is the top inflow's
+            AU[0] += qdU;
+            AV[0] += qdV;
+        }
+        if (c == C - 1 && bottom_on_grid) {
+            // the bottom point is this chunk's entry point: its upward
+            // deviation is the bottom inflow's
 #pragma unroll
             for (int i = 0; i <= L; ++i) {
                 if (i == Leff) {
@@ -585,7 +659,9 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
 
 // --------------------------------------------------------------------------
 // Finalize: J = sum over the slab's blocks (in block order) of the partial
-// quadrature sums, then
+// quadrature sums of the deviations, plus the source part
+//   sum_rays q S = [Q0 s00 + Q1 s20,  Q1 s00 + Q2 s20],
+// Q0, Q1, Q2 the sums over all rays of q, q T1, q (T1^2 + T2^2); then
 //   mode 0: sigma_out = z - xi [J00, W2 J20], z = scale .* sigma_in;
 //   mode 1: sigma_out = xi [J00, W2 J20] + [eps B, 0].
 // One thread per depth point.
@@ -623,6 +699,10 @@ __global__ void finalize_kernel(SweepArgs a, const int *pt_atm, int npts) {
             z0 *= a.scale[e];
             z2 *= a.scale[e + 1];
         }
+        // source part of the quadrature: sum over all rays of q S
+        const double4 Q = a.Qs[atm];
+        J0 += z0 * Q.x + z2 * Q.y;
+        J2 += z0 * Q.y + z2 * Q.z;
         o0 = z0 - at.xi * J0;
         o2 = z2 - at.xi * at.W2 * J2;
     } else {
@@ -650,7 +730,10 @@ static hipError_t launch_sweep_tw(SweepArgs a, int nblocks, int ns_max, hipStrea
     const size_t lds = a.rows ? W * row : row;
     // ray batches in flight ahead of use: a.prefetch (0 = by register budget)
     int pf = a.prefetch;
-    if (pf == 0) pf = (sizeof(T) * L <= 32) ? 2 : 1;
+    // measured on gfx950 (512-slab batch): one batch ahead helps the FP64
+    // sweep (its occupancy is register-bound at two waves per SIMD either
+    // way); the FP32 sweep does better keeping four waves per SIMD
+    if (pf == 0) pf = (sizeof(T) == 8 && L <= 8) ? 2 : 1;
     pf -= 1;
     if (pf >= 2 && sizeof(T) * L <= 64)
         hipLaunchKernelGGL((sweep_kernel<T, L, W, 2>), dim3(nblocks), dim3(kWave * W), lds, s, a);
@@ -712,9 +795,9 @@ hipError_t launch_coef_build(int nblocks, int W, const AtmDesc *atm, const Block
 hipError_t launch_ray_setup(int n_atm, const AtmDesc *atm, const double *mu_pos,
                             const double *w_pos, int M, const double *w_nu, const double *phi,
                             int n_nu, int normalize, RayConst *rayc, double *q, double2 *dirc,
-                            hipStream_t s) {
+                            double4 *Qs, hipStream_t s) {
     hipLaunchKernelGGL(ray_setup_kernel, dim3(n_atm), dim3(256), 0, s, atm, mu_pos, w_pos, M,
-                       w_nu, phi, n_nu, normalize, rayc, q, dirc);
+                       w_nu, phi, n_nu, normalize, rayc, q, dirc, Qs);
     return hipGetLastError();
 }
 
