@@ -2,17 +2,20 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
-A step is one Jacobi-preconditioned GMRES(30) solve, in FP64, of the
-paper-shaped slab (Ns = 200 log-spaced in tau in [1e-4, 1e8], 20 Gauss-Legendre
-directions, 101 frequencies on x in [-10, 10], Voigt a = 1e-3, eps = 1e-4,
-W2 = 0.5, DELO-linear) to ||b - A x|| / ||b|| < 1e-10 from x0 = [1, 0, ...],
-with the inputs already resident on the GPU.  `value` is solves per second.
+Workload: a batch of 512 independent isothermal slabs of uneven depth
+(Ns ~ U{64..512}, tau in [1e-4, tau_max], tau_max ~ logU[1e4, 1e8], 16
+Gauss-Legendre directions, 101 frequencies on x in [-10, 10], Voigt profiles
+with a ~ logU[1e-4, 1e-2], eps ~ logU[1e-6, 1e-2], W2 ~ U[0, 0.7], DELO-linear),
+seeded.  A step is one Jacobi-preconditioned GMRES(30) solve of every slab to
+||b - A x|| / ||b|| < 1e-9, in mixed precision (FP32 sweeps inside inner
+GMRES solves, FP64 residuals and refinement), starting from x0 = [1, 0, ...]
+with the inputs resident on the GPU.  `value` counts solved slabs per second.
 
-Also reported on the same line: the operator alone (matvecs/s, with the
-achieved bandwidth of the sweep kernel against the HBM peak, timed with HIP
-events on the stream the kernel runs on), the same solve in mixed precision,
-BiCGSTAB and Jacobi-Richardson, a batched 512-slab workload, and the FP64 CPU
-oracle timed on this host.  Prints one JSON line.
+Also on the same JSON line: the same solve in plain FP64; the operator alone
+(FP64 and FP32 applications per second and their achieved bandwidth against
+the HBM peak, timed with HIP events on the stream the kernels run on); the
+single paper-shaped slab (Ns = 200, 20 mu, 101 nu) solved by Jacobi-GMRES,
+BiCGSTAB and Richardson in FP64; and the FP64 CPU oracle timed on this host.
 """
 import argparse
 import json
@@ -27,24 +30,26 @@ sys.path.insert(0, ROOT)
 
 METRIC = "(Id−TΛ) matvecs/s, HBM GB/s frac; GMRES solves/s to 1e-9, FP64 vs mixed"
 HBM_PEAK_GBS = 8000.0
+RTOL = 1e-9
 
 
-def algorithmic_bytes_fp64(plan, n_unknowns):
-    # one (c_u, c_k) FP64 pair per ray-interval, sigma in and sigma out
-    return 16.0 * plan["intervals"] + 16.0 * n_unknowns
+def op_bytes(plan, n_unknowns, coef_bytes):
+    """Algorithmic bytes of one operator application: one (c_u, c_k) pair per
+    ray-interval, sigma read, sigma_out written (FP64)."""
+    return 2 * coef_bytes * plan["intervals"] + 16.0 * n_unknowns
 
 
-def time_matvecs(torch, h, v, out, n):
+def time_ops(torch, fn, v, out, n):
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for _ in range(10):
-        h.apply_op(v, out)
+    for _ in range(5):
+        fn(v, out)
     e0.record(s)
     for _ in range(n):
-        h.apply_op(v, out)
+        fn(v, out)
     e1.record(s)
     e1.synchronize()
-    return e0.elapsed_time(e1) / n  # ms per launch
+    return e0.elapsed_time(e1) / n  # ms per application
 
 
 def time_solves(torch, h, x0, kind, steps, warmup):
@@ -60,40 +65,45 @@ def time_solves(torch, h, x0, kind, steps, warmup):
         x.copy_(x0)
         _, info = fn(x)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return dt, info, x
+    return time.perf_counter() - t0, info
 
 
-def cpu_baseline(p):
-    """The FP64 oracle on this host: one Jacobi-GMRES(30) solve of the same
-    slab (its Jacobi diagonal computed beforehand, untimed, as the GPU's is
-    at setup)."""
+def cpu_baseline(p, dinv, n_sample=8):
+    """The FP64 oracle's Jacobi-GMRES(30) on a sample of the batch's slabs."""
     from oracle import oracle as O
-    dinv = 1.0 / O.diag(p)
-    b = O.rhs(p)
-    t0 = time.perf_counter()
-    x, info = O.gmres(p, b=b, dinv=dinv, tol=1e-10, restart=30)
-    dt = time.perf_counter() - t0
-    return dict(value=1.0 / dt, unit="solves/s", cores=1, kind="oracle",
-                sample=f"one full Jacobi-GMRES(30) FP64 solve of the same slab to 1e-10 "
-                       f"({info[0]['iterations']} iterations, {info[0]['matvecs']} matvecs, "
-                       f"{dt:.2f} s single-threaded); Jacobi diagonal precomputed untimed")
+    idx = np.linspace(0, p.n_atm - 1, n_sample).round().astype(int)
+    off = 2 * p.offsets
+    t = 0.0
+    its = []
+    for i in idx:
+        sl = p.slab(int(i))
+        d = dinv[off[i]:off[i + 1]]
+        b = O.rhs(sl)
+        t0 = time.perf_counter()
+        _, info = O.gmres(sl, b=b, dinv=d, tol=RTOL, restart=30)
+        t += time.perf_counter() - t0
+        its.append(info[0]["iterations"])
+    return dict(value=len(idx) / t, unit="solves/s", cores=1, kind="oracle",
+                sample=f"{len(idx)} of the 512 slabs (indices {idx.tolist()}, Ns "
+                       f"{[int(p.ns[i]) for i in idx]}), each one FP64 Jacobi-GMRES(30) solve "
+                       f"to 1e-9 by the oracle ({sum(its)} iterations, {t:.1f} s single-threaded); "
+                       f"Jacobi diagonal and right-hand side computed before the timed region")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--matvecs", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--matvecs", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: the slabs are independent and a single slab's "
-              "solve is latency-bound, so this build measures one GPU's throughput "
-              "(see the sharding notes in the design document).", file=sys.stderr)
+        print("bench.py measures one GPU: the slabs of the batch are independent (a multi-GPU "
+              "run would split them with no communication), so only N=1 is run here.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -101,46 +111,59 @@ def main():
     from paper_2110_11873_amd import workloads as W
 
     torch.cuda.set_device(0)
-    p = W.config2("delo_linear")
-    x0 = torch.from_numpy(W.initial_guess(p)).cuda()
     out = {}
-    with B.setup(p, rtol=1e-10, restart=30) as h:
+    p = W.config4(512)
+    x0 = torch.from_numpy(W.initial_guess(p)).cuda()
+    with B.setup(p, rtol=RTOL, restart=30, maxit=20000, precision=B.RT_PREC_MIXED) as h:
         plan = h.plan_info()
-        dt, info, _ = time_solves(torch, h, x0, "gmres", args.steps, args.warmup)
+        dt, info = time_solves(torch, h, x0, "gmres", args.steps, args.warmup)
+        value = p.n_atm * args.steps / dt
         ms_step = 1e3 * dt / args.steps
-        value = args.steps / dt
+        st = [i.status for i in info]
+        out["mixed_converged"] = sum(s == "converged" for s in st)
+        out["mixed_relres_max"] = max(i.relres for i in info)
+        out["mixed_outer_steps_max"] = max(i.outer_steps for i in info)
+        out["mixed_iterations_max"] = max(i.iterations for i in info)
         v = torch.from_numpy(W.random_vector(p.n_unknowns, 0)).cuda()
         y = torch.empty_like(v)
-        mv_ms = time_matvecs(torch, h, v, y, args.matvecs)
-        bytes_mv = algorithmic_bytes_fp64(plan, p.n_unknowns)
-        achieved = bytes_mv / (mv_ms * 1e-3) / 1e9
-        out["gmres_iterations"] = info[0].iterations
-        out["gmres_matvecs"] = info[0].matvecs
-        out["gmres_relres"] = info[0].relres
-        out["matvecs_per_s"] = 1e3 / mv_ms
-        out["matvec_us"] = mv_ms * 1e3
-        out["sweep_plan"] = plan
-        if not args.no_extras:
-            dtb, infob, _ = time_solves(torch, h, x0, "bicgstab", max(3, args.steps // 4), 1)
-            out["bicgstab_solves_per_s"] = max(3, args.steps // 4) / dtb
-            out["bicgstab_iterations"] = infob[0].iterations
+        t32 = time_ops(torch, h.apply_op_fp32, v, y, args.matvecs)
+        t64 = time_ops(torch, h.apply_op, v, y, args.matvecs)
+        dinv = h.precond_jacobi(torch.ones_like(v)).cpu().numpy()
+    b32, b64 = op_bytes(plan, p.n_unknowns, 4), op_bytes(plan, p.n_unknowns, 8)
+    a32 = b32 / (t32 * 1e-3) / 1e9
+    a64 = b64 / (t64 * 1e-3) / 1e9
+    out["matvecs_per_s_fp32"] = 1e3 / t32
+    out["matvecs_per_s_fp64"] = 1e3 / t64
+    out["matvec_us_fp32"] = t32 * 1e3
+    out["matvec_us_fp64"] = t64 * 1e3
+    out["roofline_fp64"] = {"bound": "hbm", "achieved": a64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": a64 / HBM_PEAK_GBS, "bytes_per_launch": b64,
+                            "launch_us": t64 * 1e3}
+    out["sweep_plan"] = plan
+    with B.setup(p, rtol=RTOL, restart=30, maxit=20000) as h:
+        dt64, info64 = time_solves(torch, h, x0, "gmres", max(2, args.steps // 2), 1)
+        out["fp64_solves_per_s"] = p.n_atm * max(2, args.steps // 2) / dt64
+        out["fp64_converged"] = sum(i.status == "converged" for i in info64)
+        out["fp64_iterations_max"] = max(i.iterations for i in info64)
+    out["mixed_over_fp64"] = value / out["fp64_solves_per_s"]
+
     if not args.no_extras:
-        with B.setup(p, rtol=1e-10, restart=30, precision=B.RT_PREC_MIXED) as hm:
-            dtm, infom, _ = time_solves(torch, hm, x0, "gmres", max(3, args.steps // 2), 1)
-            out["mixed_solves_per_s"] = max(3, args.steps // 2) / dtm
-            out["mixed_outer_steps"] = infom[0].outer_steps
-            out["mixed_relres"] = infom[0].relres
-            v32 = torch.empty_like(v)
-            s = torch.cuda.current_stream()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            for _ in range(10):
-                hm.apply_op_fp32(v, v32)
-            e0.record(s)
-            for _ in range(args.matvecs):
-                hm.apply_op_fp32(v, v32)
-            e1.record(s)
-            e1.synchronize()
-            out["matvec_fp32_us"] = e0.elapsed_time(e1) / args.matvecs * 1e3
+        # the single paper-shaped slab (Ns = 200, 20 mu, 101 nu), FP64
+        q = W.config2("delo_linear")
+        xq = torch.from_numpy(W.initial_guess(q)).cuda()
+        with B.setup(q, rtol=1e-10, restart=30) as h:
+            d, inf = time_solves(torch, h, xq, "gmres", 20, 3)
+            out["c2_gmres_solves_per_s"] = 20 / d
+            out["c2_gmres_iterations"] = inf[0].iterations
+            d, inf = time_solves(torch, h, xq, "bicgstab", 10, 2)
+            out["c2_bicgstab_solves_per_s"] = 10 / d
+            out["c2_bicgstab_iterations"] = inf[0].iterations
+            vq = torch.from_numpy(W.random_vector(q.n_unknowns, 0)).cuda()
+            out["c2_matvec_us"] = 1e3 * time_ops(torch, h.apply_op, vq, torch.empty_like(vq), 500)
+        with B.setup(q, rtol=1e-10, maxit=200000) as h:
+            d, inf = time_solves(torch, h, xq, "richardson", 3, 1)
+            out["c2_richardson_solves_per_s"] = 3 / d
+            out["c2_richardson_iterations"] = inf[0].iterations
 
     line = {
         "metric": METRIC,
@@ -153,20 +176,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32/f64 mixed",
         "data": "synthetic",
-        "config": {"workload": "single slab Ns=200, 20 mu, 101 nu, DELO-linear, "
-                               "Jacobi-GMRES(30) FP64 to 1e-10",
-                   "ns": 200, "n_mu": 20, "n_nu": 101, "tau": [1e-4, 1e8], "eps": 1e-4,
-                   "W2": 0.5, "a": 1e-3, "restart": 30, "rtol": 1e-10},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sweep_kernel<double,L,4>",
-                     "bytes_per_launch": bytes_mv, "launch_us": mv_ms * 1e3},
+        "config": {"workload": "512 uneven isothermal slabs (Ns 64..512), 16 mu x 101 nu, "
+                               "Jacobi-GMRES(30), FP32 sweeps + FP64 refinement to 1e-9",
+                   "n_slabs": 512, "ns_range": [64, 512], "n_mu": 16, "n_nu": 101,
+                   "formal_solver": "DELO-linear", "restart": 30, "rtol": RTOL,
+                   "seed": W.SEED_BASE + 4},
+        "roofline": {"bound": "hbm", "achieved": a32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": a32 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "FP32 operator: sweep_kernel<float,8,8,0> + finalize_kernel",
+                     "bytes_per_launch": b32, "launch_us": t32 * 1e3},
     }
     line.update(out)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(p)
+        line["cpu_baseline"] = cpu_baseline(p, dinv)
     print(json.dumps(line), flush=True)
 
 
