@@ -1,6 +1,9 @@
 """Benchmark of the matrix-free (Id - J Lambda T) operator and its Jacobi-Krylov solves.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --op-only fp32|fp64 [--matvecs N]   # operator leg alone
+    python bench.py --copy-calib                        # 512 MiB device copy x3
+    python bench.py --summarize-pmc DIR                 # counters -> profiles/
 
 Workload: a batch of 512 independent isothermal slabs of uneven depth
 (Ns ~ U{64..512}, tau in [1e-4, tau_max], tau_max ~ logU[1e4, 1e8], 16
@@ -18,6 +21,9 @@ single paper-shaped slab (Ns = 200, 20 mu, 101 nu) solved by Jacobi-GMRES,
 BiCGSTAB and Richardson in FP64; and the FP64 CPU oracle timed on this host.
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -31,6 +37,118 @@ sys.path.insert(0, ROOT)
 METRIC = "(Id−TΛ) matvecs/s, HBM GB/s frac; GMRES solves/s to 1e-9, FP64 vs mixed"
 HBM_PEAK_GBS = 8000.0
 RTOL = 1e-9
+COPY_BYTES = 512 * 1024 * 1024
+# the sources that define the operator's kernels and launch plan: counter
+# readings are only used while these are unchanged
+SWEEP_SOURCES = ["rt_sweep_kernel.h", "rt_sweep.hip", "rt_sweep_f32.hip", "rt_sweep_f64.hip",
+                 "rt_internal.h", "rt_api.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c4.json")
+
+
+def sweep_source_hash():
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2110_11873_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind):
+    """HBM bytes per operator application (sweep + finalize) from the committed
+    counter summary, or None if there is none or the kernels changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != sweep_source_hash() or kind not in t:
+        return None
+    return t[kind]["hbm_bytes_per_launch"]
+
+
+def op_only(kind, n):
+    """The operator leg alone (for counter passes): n applications."""
+    import torch
+    from paper_2110_11873_amd import binding as B
+    from paper_2110_11873_amd import workloads as W
+    torch.cuda.set_device(0)
+    p = W.config4(512)
+    with B.setup(p) as h:
+        v = torch.from_numpy(W.random_vector(p.n_unknowns, 0)).cuda()
+        y = torch.empty_like(v)
+        f = h.apply_op_fp32 if kind == "fp32" else h.apply_op
+        for _ in range(n):
+            f(v, y)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(op=kind, applications=n, plan=h.plan_info())), flush=True)
+
+
+def copy_calib():
+    """A plain device-to-device copy of known size, three times."""
+    import torch
+    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes=COPY_BYTES, copies=3)), flush=True)
+
+
+def _counters(path):
+    """{kernel name: {counter: [value per dispatch]}} from a rocprofv3 CSV."""
+    out = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            k = r["Kernel_Name"]
+            out.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def _find(d, key):
+    hits = [k for k in d if key in k]
+    if len(hits) != 1:
+        raise SystemExit(f"expected one kernel matching {key!r}, found {hits}")
+    return d[hits[0]]
+
+
+def summarize_pmc(root):
+    """Turn the FETCH_SIZE / WRITE_SIZE passes under `root` (subfolders
+    copy_fetch, copy_write, {fp32,fp64}_fetch, {fp32,fp64}_write, each holding
+    rocprofv3's *counter_collection.csv) into profiles/traffic_c4.json."""
+    def load(sub):
+        fs = glob.glob(os.path.join(root, sub, "**", "*counter_collection.csv"), recursive=True)
+        if len(fs) != 1:
+            raise SystemExit(f"{sub}: expected one counter CSV, found {fs}")
+        return _counters(fs[0])
+    kib = COPY_BYTES / 1024
+    cf = _find(load("copy_fetch"), "copyBuffer")["FETCH_SIZE"]
+    cw = _find(load("copy_write"), "copyBuffer")["WRITE_SIZE"]
+    f_fetch = kib / (sum(cf) / len(cf))
+    f_write = kib / (sum(cw) / len(cw))
+    out = {"source_hash": sweep_source_hash(), "copy_bytes": COPY_BYTES,
+           "fetch_factor": f_fetch, "write_factor": f_write,
+           "copy_fetch_kib": sum(cf) / len(cf), "copy_write_kib": sum(cw) / len(cw)}
+    for kind, tname in (("fp32", "sweep_kernel<float"), ("fp64", "sweep_kernel<double")):
+        fe, wr = load(kind + "_fetch"), load(kind + "_write")
+        # the operator applications are the last `applications` dispatches
+        # (set-up runs the FP64 sweep and the finalize pass once before them)
+        with open(os.path.join(root, kind + "_fetch.log")) as fh:
+            n = [json.loads(ln) for ln in fh if ln.startswith('{"op"')][0]["applications"]
+        rec = {"applications": n}
+        total = 0.0
+        for short, key in (("sweep", tname), ("finalize", "finalize_kernel")):
+            fk = _find(fe, key)["FETCH_SIZE"][-n:]
+            wk = _find(wr, key)["WRITE_SIZE"][-n:]
+            fkib, wkib = sum(fk) / len(fk), sum(wk) / len(wk)
+            b = 1024 * (fkib * f_fetch + wkib * f_write)
+            rec[short] = {"dispatches": len(fk), "fetch_kib": fkib, "write_kib": wkib,
+                          "hbm_bytes": b}
+            total += b
+        rec["hbm_bytes_per_launch"] = total
+        out[kind] = rec
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
 
 
 def op_bytes(plan, n_unknowns, coef_bytes):
@@ -98,13 +216,22 @@ def main():
     ap.add_argument("--matvecs", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--op-only", choices=["fp32", "fp64"])
+    ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--summarize-pmc", metavar="DIR")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        return summarize_pmc(args.summarize_pmc)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the slabs of the batch are independent (a multi-GPU "
               "run would split them with no communication), so only N=1 is run here.",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calib:
+        return copy_calib()
+    if args.op_only:
+        return op_only(args.op_only, args.matvecs)
 
     import torch
     from paper_2110_11873_amd import binding as B
@@ -116,6 +243,7 @@ def main():
     x0 = torch.from_numpy(W.initial_guess(p)).cuda()
     with B.setup(p, rtol=RTOL, restart=30, maxit=20000, precision=B.RT_PREC_MIXED) as h:
         plan = h.plan_info()
+        kname32, kname64 = h.sweep_kernel_name(True), h.sweep_kernel_name(False)
         dt, info = time_solves(torch, h, x0, "gmres", args.steps, args.warmup)
         value = p.n_atm * args.steps / dt
         ms_step = 1e3 * dt / args.steps
@@ -137,8 +265,9 @@ def main():
     out["matvec_us_fp32"] = t32 * 1e3
     out["matvec_us_fp64"] = t64 * 1e3
     out["roofline_fp64"] = {"bound": "hbm", "achieved": a64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": a64 / HBM_PEAK_GBS, "bytes_per_launch": b64,
-                            "launch_us": t64 * 1e3}
+                            "frac": a64 / HBM_PEAK_GBS, "traffic": measured_traffic("fp64"),
+                            "kernel": kname64 + " + rt::finalize_kernel",
+                            "bytes_per_launch": b64, "launch_us": t64 * 1e3}
     out["sweep_plan"] = plan
     with B.setup(p, rtol=RTOL, restart=30, maxit=20000) as h:
         dt64, info64 = time_solves(torch, h, x0, "gmres", max(2, args.steps // 2), 1)
@@ -184,8 +313,8 @@ def main():
                    "formal_solver": "DELO-linear", "restart": 30, "rtol": RTOL,
                    "seed": W.SEED_BASE + 4},
         "roofline": {"bound": "hbm", "achieved": a32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": a32 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "FP32 operator: sweep_kernel<float,8,8,0> + finalize_kernel",
+                     "frac": a32 / HBM_PEAK_GBS, "traffic": measured_traffic("fp32"),
+                     "kernel": kname32 + " + rt::finalize_kernel",
                      "bytes_per_launch": b32, "launch_us": t32 * 1e3},
     }
     line.update(out)

@@ -132,10 +132,13 @@ typedef struct rt_problem {
  *              else one of 4, 8, 16, 32
  *  wave_batches  ray batches each wavefront of the sweep handles in turn:
  *              0 = choose automatically, else 1..64
- *  prefetch    step coefficients of later ray batches loaded ahead of use:
- *              0 = automatic, 1 = none, 2 = one batch ahead, 3 = two
+ *  prefetch    step coefficients of the next ray batch loaded while the
+ *              current one is swept: 0 = automatic, 1 = no, 2 or 3 = yes
+ *              (yes is available for chunk lengths up to 8)
  *  check_every iterations between convergence checks read back by the host
  *              for BiCGSTAB and Richardson (16); GMRES checks once per cycle
+ *  sweep_waves wavefronts per sweep workgroup: 0 = automatic, 4 or 8 (8 is
+ *              available for chunk lengths up to 8)
  */
 typedef struct rt_options {
     int precision;
@@ -149,6 +152,7 @@ typedef struct rt_options {
     int wave_batches;
     int prefetch;
     int check_every;
+    int sweep_waves;
 } rt_options;
 
 /* Per-slab outcome of a solve. */

@@ -32,6 +32,15 @@ int rt_plan_info(const rt_handle *h, int *chunk_L, int *n_blocks, long long *n_p
                  long long *n_intervals);
 
 /*
+ * The sweep launch configuration of rt_apply_op (fp32 = 0) or
+ * rt_apply_op_fp32 (fp32 != 0) on this handle: wavefronts per workgroup, and
+ * 1 if the step coefficients of a wavefront's next ray batch are loaded while
+ * the current one is swept, 0 if they are loaded on use.  Any output pointer
+ * may be NULL.  Host only.
+ */
+int rt_sweep_config(const rt_handle *h, int fp32, int *waves, int *prefetch);
+
+/*
  * Run the validation of rt_setup on (p, o) without touching any device:
  * RT_OK or RT_EINVAL with the message in rt_last_error().  o may be NULL.
  */

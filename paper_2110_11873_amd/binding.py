@@ -29,7 +29,7 @@ STATUS_NAMES = {RT_OK: "converged", RT_ENOCONV: "maxit", RT_EBREAKDOWN: "breakdo
 EXPORTS = ["rt_default_options", "rt_setup", "rt_destroy", "rt_num_unknowns", "rt_apply_op",
            "rt_precond_jacobi", "rt_get_rhs", "rt_get_jacobi_diag", "rt_solve_gmres",
            "rt_solve_bicgstab", "rt_solve_richardson", "rt_last_error", "rt_apply_op_fp32",
-           "rt_plan_info", "rt_validate"]
+           "rt_plan_info", "rt_sweep_config", "rt_validate"]
 
 
 class RTError(RuntimeError):
@@ -55,7 +55,7 @@ class rt_options(C.Structure):
         ("precision", C.c_int), ("restart", C.c_int), ("maxit", C.c_int), ("rtol", C.c_double),
         ("inner_rtol", C.c_double), ("inner_maxit", C.c_int), ("max_outer", C.c_int),
         ("chunk", C.c_int), ("wave_batches", C.c_int), ("prefetch", C.c_int),
-        ("check_every", C.c_int),
+        ("check_every", C.c_int), ("sweep_waves", C.c_int),
     ]
 
 
@@ -92,6 +92,7 @@ def lib():
         L.rt_last_error.restype = C.c_char_p
         L.rt_plan_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                    C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
+        L.rt_sweep_config.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.rt_validate.argtypes = [C.POINTER(rt_problem), C.POINTER(rt_options)]
         _ = dp
         _lib = L
@@ -232,6 +233,17 @@ class Handle:
         _check(lib().rt_plan_info(self._h, C.byref(L), C.byref(nb), C.byref(npairs),
                                   C.byref(nint)))
         return dict(chunk=L.value, blocks=nb.value, pairs=npairs.value, intervals=nint.value)
+
+    def sweep_config(self, fp32=False):
+        w, pf = C.c_int(), C.c_int()
+        _check(lib().rt_sweep_config(self._h, 1 if fp32 else 0, C.byref(w), C.byref(pf)))
+        return dict(waves=w.value, prefetch=pf.value)
+
+    def sweep_kernel_name(self, fp32=False):
+        """The sweep kernel rt_apply_op(_fp32) launches, as profilers name it."""
+        c = self.sweep_config(fp32)
+        return "rt::sweep::sweep_kernel<%s, %d, %d, %d>" % (
+            "float" if fp32 else "double", self.plan_info()["chunk"], c["waves"], c["prefetch"])
 
     # -- solvers ---------------------------------------------------------------
     def _solve(self, fn, b, x, stream):

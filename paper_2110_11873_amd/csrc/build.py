@@ -2,42 +2,65 @@
 
     python -m paper_2110_11873_amd.csrc.build      # or: python build.py
 
-Compiles every .hip file of this directory for gfx950 only and links them into
-paper_2110_11873_amd/librt.so.  Packed FP32 instructions are disabled for the
+Compiles every .hip file of this directory for gfx950 only, one process per
+file in parallel (objects under paper_2110_11873_amd/_build/), and links them
+into paper_2110_11873_amd/librt.so.  Packed FP32 instructions are disabled for the
 device code (-packed-fp32-ops); hipcc's host pass warns that it does not know
 the feature, which is harmless.
 """
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "librt.so")
-SOURCES = ["rt_api.hip", "rt_sweep.hip", "rt_krylov.hip"]
+SOURCES = ["rt_api.hip", "rt_sweep.hip", "rt_sweep_f32.hip", "rt_sweep_f64.hip", "rt_krylov.hip"]
+OBJDIR = os.path.join(PKG, "_build")
 
-FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 
 
-def build(verbose: bool = False) -> str:
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = OUT + f".tmp{os.getpid()}"
-    cmd = [hipcc, *FLAGS, "-I", INCLUDE, "-I", HERE,
-           *[os.path.join(HERE, s) for s in SOURCES], "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building librt.so")
     noise = [ln for ln in (r.stdout + r.stderr).splitlines()
              if ln.strip() and "packed-fp32-ops" not in ln and "warning generated" not in ln]
-    if verbose and noise:
-        print("\n".join(noise))
+    return r.returncode, "\n".join(noise)
+
+
+def build(verbose: bool = False) -> str:
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJDIR, exist_ok=True)
+    tag = f".{os.getpid()}"
+    objs = [os.path.join(OBJDIR, os.path.splitext(src)[0] + tag + ".o") for src in SOURCES]
+    cmds = [[hipcc, *FLAGS, "-I", INCLUDE, "-I", HERE, "-c", os.path.join(HERE, src), "-o", obj]
+            for src, obj in zip(SOURCES, objs)]
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(lambda c: _run(c, verbose), cmds))
+    failed = [(c, msg) for c, (rc, msg) in zip(cmds, results) if rc != 0]
+    for c, msg in failed:
+        sys.stderr.write(msg + "\n")
+    if verbose:
+        for _, msg in results:
+            if msg:
+                print(msg)
+    if failed:
+        raise RuntimeError("hipcc failed building librt.so")
+    tmp = OUT + f".tmp{os.getpid()}"
+    rc, msg = _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+    for o in objs:
+        os.remove(o)
+    if rc != 0:
+        sys.stderr.write(msg + "\n")
+        raise RuntimeError("linking librt.so failed")
     os.replace(tmp, OUT)
     return OUT
 

@@ -137,13 +137,17 @@ int validate(const rt_problem *p, const rt_options *o, std::vector<double> &mu_p
             return fail(RT_EINVAL, "options.prefetch must be in [0, 3]");
         if (o->wave_batches < 0 || o->wave_batches > 64)
             return fail(RT_EINVAL, "options.wave_batches must be in [0, 64]");
+        if (o->sweep_waves != 0 && o->sweep_waves != 4 && o->sweep_waves != 8)
+            return fail(RT_EINVAL, "options.sweep_waves must be 0, 4 or 8");
+        if (o->sweep_waves == 8 && o->chunk > 8)
+            return fail(RT_EINVAL, "options.sweep_waves = 8 needs chunk <= 8");
     }
     return RT_OK;
 }
 
 int chunks_for(int ns, int L) {
     const int x = ns - 1;
-    int C = 1;
+    int C = kMinChunks;
     while (C < kWave && C * L < x) C <<= 1;
     return C;
 }
@@ -214,8 +218,10 @@ hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, d
     a.mask = mask;
     a.B = h->d_B;
     a.mode = mode;
-    a.prefetch = h->opt.prefetch;
-    hipError_t e = launch_sweep(h->L, fp32, a, h->n_blocks, h->ns_max, s);
+    int W;
+    bool pf;
+    sweep_config(h, fp32, &W, &pf);
+    hipError_t e = launch_sweep(h->L, W, pf, fp32, a, h->n_blocks, h->ns_max, s);
     if (e != hipSuccess) return e;
     return launch_finalize(a, h->d_pt_atm, h->ns_total, s);
 }
@@ -269,6 +275,7 @@ void rt_default_options(rt_options *o) {
     o->chunk = 0;
     o->wave_batches = 0;
     o->prefetch = 0;
+    o->sweep_waves = 0;
     o->check_every = 16;
 }
 
@@ -348,7 +355,7 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     // Waves per block and wave-batches per wave.  A block never mixes
     // directions.  Big batches: one block per (slab, direction), the fewest
     // partial sums; small problems: about 48 blocks in all, for parallelism.
-    h->W = sweep_waves(h->L, false);
+    h->W = opt.sweep_waves ? opt.sweep_waves : sweep_waves(h->L, false);
     const long long dirs_total = (long long)h->n_atm * h->M;
     const int blocks_per_dir = (int)std::max<long long>(1, (48 + dirs_total - 1) / dirs_total);
     h->atm_h.resize(h->n_atm);
@@ -357,7 +364,7 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
         d.ns = h->ns[a];
         d.doff = h->doff[a];
         d.C = chunks_for(d.ns, h->L);
-        d.Leff = (d.ns - 1 + d.C - 1) / d.C;
+        d.Leff = chunk_len(d.ns, d.C, h->L);
         d.G = kWave / d.C;
         d.n_nu = h->n_nu;
         d.nwb = (h->n_nu + d.G - 1) / d.G;
@@ -537,6 +544,16 @@ int rt_plan_info(const rt_handle *h, int *chunk_L, int *n_blocks, long long *n_p
         for (int n : h->ns) s += (long long)(n - 1) * h->M * h->n_nu;
         *n_intervals = s;
     }
+    return RT_OK;
+}
+
+int rt_sweep_config(const rt_handle *h, int fp32, int *waves, int *prefetch) {
+    if (!h) return fail(RT_EINVAL, "NULL handle");
+    int W;
+    bool pf;
+    sweep_config(h, fp32 != 0, &W, &pf);
+    if (waves) *waves = W;
+    if (prefetch) *prefetch = pf ? 1 : 0;
     return RT_OK;
 }
 

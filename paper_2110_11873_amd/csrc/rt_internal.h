@@ -25,7 +25,7 @@ struct AtmDesc {
     int ns;         // depth points
     int doff;       // first depth point of the slab in concatenated arrays
     int C;          // chunks per ray (power of two, <= 64)
-    int Leff;       // intervals per chunk (<= the kernel's L)
+    int Leff;       // intervals per chunk (chunk_len; <= the kernel's L)
     int G;          // rays per wave-batch
     int n_nu;       // frequencies: rays per direction
     int nwb;        // wave-batches per direction
@@ -76,17 +76,54 @@ struct SweepArgs {
                              //    with the bottom inflow and no source
     int rows;                // 1: one LDS row per wave (W * 2 ns_max values),
                              // 0: one shared row filled wave after wave
-    int prefetch;            // 0: automatic; 1 + number of ray batches loaded ahead
+    int src_lds;             // byte offset of the sources in the sweep's LDS (set at launch)
 };
 
-// Waves per sweep block for a chunk length and precision: as many as the
-// register footprint allows at two waves per SIMD.
+// --------------------------------------------------------------------------
+// Lane layout of a wave-batch.  A ray's C chunks sit C lanes apart in chunk
+// order; for C < 16 the chunks of one ray are spread over a row of 16 lanes
+// with stride s = 16 / C (s rays interleaved per row), for C >= 16 a ray
+// fills C consecutive lanes.  Either way a DPP shift by s lanes inside a row
+// (or a row broadcast across rows) moves data from chunk c to chunk c + 1 of
+// the same ray, and lanes whose source would be another ray's chunk have no
+// source at all, so the lane scans need no masks.
+// --------------------------------------------------------------------------
+__host__ __device__ inline int lane_chunk(int lane, int C) {
+    return C >= 16 ? (lane & (C - 1)) : ((lane & 15) / (16 / C));
+}
+__host__ __device__ inline int lane_slot(int lane, int C) {
+    if (C >= 16) return lane / C;
+    const int s = 16 / C;
+    return (lane >> 4) * s + (lane & (s - 1));
+}
+
+
+// Chunk counts of a plan: powers of two from kMinChunks to 64 (short slabs
+// get identity-padded chunks rather than fewer of them, so the sweep has one
+// lane layout per chunk count it is compiled for).
+constexpr int kMinChunks = 8;
+
+// Chunk lengths compiled for a plan of longest chunk L: L/2+1 .. L for L <= 8,
+// L/2 + L/8, L/2 + 2L/8, .. L for L >= 16.  A slab's chunk length is
+// ceil((ns - 1) / C) rounded up to one of them (the extra steps are identity
+// padding).
+constexpr int chunk_len_step(int L) { return L >= 16 ? L / 8 : 1; }
+constexpr int chunk_len_min(int L) { return L / 2 + chunk_len_step(L); }
+
+// Waves per sweep block for a chunk length and precision (automatic choice).
 int sweep_waves(int L, bool fp32);
 
 // Launch helpers (rt_sweep.hip).  launch_sweep writes the per-block partial
 // quadrature sums; launch_finalize turns them into sigma_out.
-hipError_t launch_sweep(int L, bool fp32, const SweepArgs &a, int nblocks, int ns_max,
-                        hipStream_t s);
+hipError_t launch_sweep(int L, int W, bool pf, bool fp32, const SweepArgs &a, int nblocks,
+                        int ns_max, hipStream_t s);
+hipError_t launch_sweep_f32(int L, int W, bool pf, const SweepArgs &a, int nblocks, int ns_max,
+                            hipStream_t s);
+hipError_t launch_sweep_f64(int L, int W, bool pf, const SweepArgs &a, int nblocks, int ns_max,
+                            hipStream_t s);
+// Launch configuration of the sweep for a handle: waves per block and whether
+// the next ray batch is loaded during the current one.
+void sweep_config(const rt_handle *h, bool fp32, int *W, bool *pf);
 hipError_t launch_finalize(const SweepArgs &a, const int *pt_atm, int npts, hipStream_t s);
 hipError_t launch_coef_build(int nblocks, int W, const AtmDesc *atm, const BlockDesc *blk,
                              const double *tau, const double *opac, const double *mu_pos, int fs,
@@ -100,6 +137,10 @@ hipError_t launch_diag(int npts, const int *pt_atm, const AtmDesc *atm, const do
                        const double *opac, const double *mu_pos, const RayConst *rayc, int M,
                        int n_nu, int fs, double *diag, double *dinv, hipStream_t s);
 bool sweep_chunk_supported(int L, bool fp32);
+// Chunk length of a slab of ns points split into C chunks, for a plan of
+// longest chunk L: ceil((ns - 1) / C) rounded up to a length the sweep is
+// compiled for.
+int chunk_len(int ns, int C, int L);
 
 // Krylov state kept on the device, one entry per slab.
 struct KState {
@@ -129,8 +170,7 @@ struct rt_handle {
     std::vector<rt::AtmDesc> atm_h;
     std::vector<rt::BlockDesc> blk_h;
     int L = 8;                 // chunk length the tiles were built for
-    int W = 8;                 // waves per sweep block the plan was made for
-    int prefetch = 0;          // sweep prefetch setting (SweepArgs::prefetch)
+    int W = 4;                 // waves per sweep block the plan was made for
     int NB = 1;                // wave-batches per wave (per block: W * NB)
     int n_blocks = 0;
     long long n_pairs = 0, n_partial = 0;

@@ -99,6 +99,26 @@ def test_apply_forced_chunks_and_ragged_tails(chunk, ns):
         check_apply(p, h, seeds=(3,))
 
 
+@pytest.mark.parametrize("chunk", [4, 8])
+@pytest.mark.parametrize("waves", [4, 8])
+@pytest.mark.parametrize("prefetch", [1, 2])
+def test_apply_kernel_variants(chunk, waves, prefetch):
+    """Every compiled sweep variant (loads on use or one batch ahead, 4 or 8
+    waves per block) on slabs whose depths give every chunk count (8..64) and
+    several chunk lengths, with wave-batch counts that leave some waves idle;
+    FP64 to the matvec tolerance, FP32 to its rounding level."""
+    ns = [2, 20, 33, 64, 65, 130, 200, 257]
+    ns = [n for n in ns if n - 1 <= 64 * chunk]
+    p = W.make_slabs(ns, [(1e-3, 1e5)] * len(ns), 6, 21, 6.0, [1e-3] * len(ns),
+                     [1e-3] * len(ns), [0.6] * len(ns))
+    with B.setup(p, chunk=chunk, sweep_waves=waves, prefetch=prefetch, wave_batches=3) as h:
+        check_apply(p, h, seeds=(11,))
+        v = W.random_vector(p.n_unknowns, 12)
+        y32 = host(h.apply_op_fp32(dev(v)))
+    err = normwise(p, v, y32)
+    assert err < 1e-5, err
+
+
 def test_apply_batched_uneven_slabs():
     p = W.config4(n_slabs=512)
     sel = [0, 1, 2, 3, 17, 100, 255, 511]
