@@ -125,8 +125,8 @@ typedef struct rt_problem {
  *              relative residual of Sect. 4.2, computed in FP64 (1e-10)
  *  inner_rtol  MIXED: each inner FP32 GMRES solve stops once its Arnoldi
  *              residual estimate falls below inner_rtol times its right-hand
- *              side (1e-4) ...
- *  inner_maxit MIXED: ... or after this many Arnoldi steps (100)
+ *              side (3e-4) ...
+ *  inner_maxit MIXED: ... or after this many Arnoldi steps (200)
  *  max_outer   MIXED: refinement steps limit (30)
  *  chunk       formal-solver sweep chunk length: 0 = choose automatically,
  *              else one of 4, 8, 16, 32
@@ -139,6 +139,11 @@ typedef struct rt_problem {
  *              for BiCGSTAB and Richardson (16); GMRES checks once per cycle
  *  sweep_waves wavefronts per sweep workgroup: 0 = automatic, 4 or 8 (8 is
  *              available for chunk lengths up to 8)
+ *  graphs      1 = the kernels of one GMRES cycle (of check_every BiCGSTAB or
+ *              Richardson iterations) are captured once in a HIP graph and
+ *              replayed, the host testing convergence between replays;
+ *              0 = kernels launched one by one, GMRES also testing every
+ *              check_every steps within a cycle (default: measured faster)
  */
 typedef struct rt_options {
     int precision;
@@ -153,6 +158,7 @@ typedef struct rt_options {
     int prefetch;
     int check_every;
     int sweep_waves;
+    int graphs;
 } rt_options;
 
 /* Per-slab outcome of a solve. */

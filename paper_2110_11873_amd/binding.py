@@ -55,7 +55,7 @@ class rt_options(C.Structure):
         ("precision", C.c_int), ("restart", C.c_int), ("maxit", C.c_int), ("rtol", C.c_double),
         ("inner_rtol", C.c_double), ("inner_maxit", C.c_int), ("max_outer", C.c_int),
         ("chunk", C.c_int), ("wave_batches", C.c_int), ("prefetch", C.c_int),
-        ("check_every", C.c_int), ("sweep_waves", C.c_int),
+        ("check_every", C.c_int), ("sweep_waves", C.c_int), ("graphs", C.c_int),
     ]
 
 

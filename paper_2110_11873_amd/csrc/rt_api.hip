@@ -141,6 +141,7 @@ int validate(const rt_problem *p, const rt_options *o, std::vector<double> &mu_p
             return fail(RT_EINVAL, "options.sweep_waves must be 0, 4 or 8");
         if (o->sweep_waves == 8 && o->chunk > 8)
             return fail(RT_EINVAL, "options.sweep_waves = 8 needs chunk <= 8");
+        if (o->graphs != 0 && o->graphs != 1) return fail(RT_EINVAL, "options.graphs must be 0 or 1");
     }
     return RT_OK;
 }
@@ -202,8 +203,8 @@ int hip_check(hipError_t e, const char *what) {
 
 }  // namespace
 
-hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, double *out,
-                          const int *mask, bool fp32, int mode, hipStream_t s) {
+static SweepArgs sweep_args(rt_handle *h, const double *in, const double *scale, double *out,
+                            const int *mask, bool fp32, int mode) {
     SweepArgs a{};
     a.atm = h->d_atm;
     a.blk = h->d_blk;
@@ -218,6 +219,21 @@ hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, d
     a.mask = mask;
     a.B = h->d_B;
     a.mode = mode;
+    return a;
+}
+
+hipError_t apply_sweep(rt_handle *h, const double *in, const double *scale, const int *mask,
+                       bool fp32, hipStream_t s) {
+    const SweepArgs a = sweep_args(h, in, scale, nullptr, mask, fp32, 0);
+    int W;
+    bool pf;
+    sweep_config(h, fp32, &W, &pf);
+    return launch_sweep(h->L, W, pf, fp32, a, h->n_blocks, h->ns_max, s);
+}
+
+hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, double *out,
+                          const int *mask, bool fp32, int mode, hipStream_t s) {
+    const SweepArgs a = sweep_args(h, in, scale, out, mask, fp32, mode);
     int W;
     bool pf;
     sweep_config(h, fp32, &W, &pf);
@@ -226,9 +242,16 @@ hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, d
     return launch_finalize(a, h->d_pt_atm, h->ns_total, s);
 }
 
+void clear_graphs(rt_handle *h) {
+    for (auto &g : h->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
+}
+
 int ensure_workspace(rt_handle *h) {
     const int m = h->opt.restart;
     if (h->d_V && h->ws_restart == m) return RT_OK;
+    clear_graphs(h);  // captured with the old basis address
     (void)hipFree(h->d_V);
     h->d_V = nullptr;
     const long long N = h->n_unk;
@@ -269,13 +292,14 @@ void rt_default_options(rt_options *o) {
     o->restart = 30;
     o->maxit = 10000;
     o->rtol = 1e-10;
-    o->inner_rtol = 1e-4;
-    o->inner_maxit = 100;
+    o->inner_rtol = 3e-4;
+    o->inner_maxit = 200;
     o->max_outer = 30;
     o->chunk = 0;
     o->wave_batches = 0;
     o->prefetch = 0;
     o->sweep_waves = 0;
+    o->graphs = 0;
     o->check_every = 16;
 }
 
@@ -292,6 +316,10 @@ void rt_destroy(rt_handle *h) {
                     h->d_V,     h->d_H,     h->d_cs,      h->d_sn,      h->d_g,      h->d_w,
                     h->d_r,     h->d_rh,    h->d_p,       h->d_v,       h->d_s,      h->d_t,
                     h->d_xd,    h->d_state, h->d_active,  h->d_cycle,   h->d_count};
+    clear_graphs(h);
+    if (h->gstream) (void)hipStreamDestroy(h->gstream);
+    for (hipEvent_t e : h->gev)
+        if (e) (void)hipEventDestroy(e);
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->h_count) (void)hipHostFree(h->h_count);

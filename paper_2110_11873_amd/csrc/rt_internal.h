@@ -206,6 +206,16 @@ struct rt_handle {
     int *d_cycle = nullptr;     // per slab: GMRES cycle still running
     int *d_count = nullptr;     // reduction target for host checks
     int *h_count = nullptr;     // pinned host mirror
+
+    // captured solver segments (one per distinct argument set), the stream
+    // they are replayed on and the events that order it after the caller's
+    struct Graph {
+        std::vector<unsigned long long> key;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<Graph> graphs;
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
 };
 
 namespace rt {
@@ -213,6 +223,13 @@ namespace rt {
 // mask is NULL): the sweep, then the finalize pass.  mode as in SweepArgs.
 hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, double *out,
                           const int *mask, bool fp32, int mode, hipStream_t s);
+// The sweep of apply_operator (mode 0) alone: leaves the per-block quadrature
+// sums in h->d_partial for a consumer that applies the scattering step itself.
+hipError_t apply_sweep(rt_handle *h, const double *in, const double *scale, const int *mask,
+                       bool fp32, hipStream_t s);
+
+// Destroy the handle's captured solver graphs.
+void clear_graphs(rt_handle *h);
 
 // Thread-local error message for rt_last_error.
 void set_error(const std::string &msg);

@@ -16,6 +16,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
+#include <cstring>
 #include <vector>
 
 #include "rt_internal.h"
@@ -121,6 +123,8 @@ struct VecArgs {
     double tol;
     int maxit;
     int max_outer;
+    const double *partial;  // the sweep's per-block quadrature sums
+    const double4 *Qs;      // per slab: sums over all rays of q, q T1, q (T1^2 + T2^2)
 };
 
 // ---------------------------------------------------------------- counting
@@ -304,6 +308,152 @@ __global__ __launch_bounds__(NT) void gm_arnoldi_kernel(VecArgs a, int j) {
             const int l = tid + e * NT;
             if (l < n) a.V[(long long)(j + 1) * a.N + base + l] = wl[e] * inv;
         }
+    }
+    if (tid == 0) {
+        const int m = a.m;
+        double *H = a.H + (long long)atm * (m + 1) * m;
+        double *cs = a.cs + (long long)atm * m;
+        double *sn = a.sn + (long long)atm * m;
+        double *g = a.g + (long long)atm * (m + 1);
+        for (int i = 0; i <= j; ++i) H[i * m + j] = hsum[i];
+        for (int i = 0; i < j; ++i) {  // earlier rotations
+            const double h0 = H[i * m + j], h1 = H[(i + 1) * m + j];
+            H[i * m + j] = cs[i] * h0 + sn[i] * h1;
+            H[(i + 1) * m + j] = -sn[i] * h0 + cs[i] * h1;
+        }
+        const double hjj = H[j * m + j];
+        const double den = sqrt(hjj * hjj + hn * hn);
+        const double c = (den > 0.0) ? hjj / den : 1.0;
+        const double s = (den > 0.0) ? hn / den : 0.0;
+        cs[j] = c;
+        sn[j] = s;
+        H[j * m + j] = den;
+        H[(j + 1) * m + j] = 0.0;
+        g[j + 1] = -s * g[j];
+        g[j] = c * g[j];
+        KState &S = a.st[atm];
+        S.resid = fabs(g[j + 1]);
+        S.iters += 1;
+        S.matvecs += 1;
+        S.inner = j + 1;
+        const bool done = (S.resid / S.bnorm < a.tol) || !(hn > 0.0) || (S.iters >= a.maxit) ||
+                          (j + 1 == m) || !(S.resid == S.resid);
+        if (done) a.cycle[atm] = 0;
+    }
+}
+
+// The same step for slabs of at most NTF points and restarts m < MR, with the
+// operator's last pass fused in and the basis held in registers:
+//  * w = A P^-1 v_j is formed here from the sweep's per-block quadrature sums
+//    (the finalize pass: J = sum of the slab's block slots in block order plus
+//    the source part Q S, w = z - xi [J00, W2 J20], z = P^-1 v_j), so w is
+//    never written to memory;
+//  * each thread owns one depth point and keeps (s00, s20) of basis rows
+//    0..j in registers, so both Gram-Schmidt passes read the basis once.
+constexpr int NTF = 512;
+constexpr int NWF = NTF / kWave;
+constexpr int MR = 32;
+
+__device__ inline double block_sum_f(double a, double *red) {
+    a = wave_sum(a);
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = a;
+    __syncthreads();
+    a = 0.0;
+    for (int w = 0; w < NWF; ++w) a += red[w];
+    return a;
+}
+
+__global__ __launch_bounds__(NTF) void gm_arnoldi_fused_kernel(VecArgs a, int j) {
+    __shared__ double red[32 * NWF];
+    __shared__ double hp[MR];
+    __shared__ double hsum[MR];
+    __shared__ double red2[NWF];
+    const int atm = blockIdx.x;
+    if (!a.cycle[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int k = tid;  // depth point
+    const bool on = k < at.ns;
+    const long long e0 = 2LL * (at.doff + k);
+
+    // basis rows 0..j at this point (zero beyond)
+    double v0[MR], v2[MR];
+#pragma unroll
+    for (int t = 0; t < MR; ++t) {
+        v0[t] = v2[t] = 0.0;
+        if (on && t <= j) {
+            const double2 x = *reinterpret_cast<const double2 *>(a.V + (long long)t * a.N + e0);
+            v0[t] = x.x;
+            v2[t] = x.y;
+        }
+    }
+    if (tid < MR) hsum[tid] = 0.0;
+
+    // w = A P^-1 v_j; the block slots are read 8 at a time, all loads of a
+    // group in flight together (addresses clamped, extra values unused)
+    double w0 = 0.0, w2 = 0.0;
+    if (on) {
+        double J0 = 0.0, J2 = 0.0;
+        const double *pJ = a.partial + at.part_off + 2 * k;
+        const long long stride = 2LL * at.ns;
+        for (int b0 = 0; b0 < at.nblk; b0 += 8) {
+            double2 p[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                p[u] = *reinterpret_cast<const double2 *>(pJ + min(b0 + u, at.nblk - 1) * stride);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (b0 + u < at.nblk) {
+                    J0 += p[u].x;
+                    J2 += p[u].y;
+                }
+            }
+        }
+        double vj0 = 0.0, vj2 = 0.0;
+#pragma unroll
+        for (int t = 0; t < MR; ++t)
+            if (t == j) {
+                vj0 = v0[t];
+                vj2 = v2[t];
+            }
+        const double2 d = *reinterpret_cast<const double2 *>(a.dinv + e0);
+        const double z0 = vj0 * d.x, z2 = vj2 * d.y;
+        const double4 Q = a.Qs[atm];
+        J0 += z0 * Q.x + z2 * Q.y;
+        J2 += z0 * Q.y + z2 * Q.z;
+        w0 = z0 - at.xi * J0;
+        w2 = z2 - at.xi * at.W2 * J2;
+    }
+
+    // classical Gram-Schmidt, twice
+    for (int pass = 0; pass < 2; ++pass) {
+        double part[32];
+#pragma unroll
+        for (int t = 0; t < MR; ++t) part[t] = v0[t] * w0 + v2[t] * w2;
+        const double sum = wave_reduce_scatter32(part);
+        if ((lane & 1) == 0) red[scatter_index(lane) * NWF + wave] = sum;
+        __syncthreads();
+        if (tid < MR) {
+            double s = 0.0;
+            for (int w = 0; w < NWF; ++w) s += red[tid * NWF + w];
+            hp[tid] = s;
+            hsum[tid] += s;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < MR; ++t) {
+            const double h = hp[t];  // zero for t > j
+            w0 -= h * v0[t];
+            w2 -= h * v2[t];
+        }
+    }
+
+    const double hn = sqrt(block_sum_f(w0 * w0 + w2 * w2, red2));
+    if (hn > 0.0 && on) {
+        const double inv = 1.0 / hn;
+        *reinterpret_cast<double2 *>(a.V + (long long)(j + 1) * a.N + e0) =
+            make_double2(w0 * inv, w2 * inv);
     }
     if (tid == 0) {
         const int m = a.m;
@@ -726,6 +876,59 @@ struct Driver {
         return err == hipSuccess;
     }
 
+    // Run `body` (kernel launches on this->s) as a HIP graph: captured on the
+    // handle's own stream the first time this key is seen, then replayed.
+    // The replay is ordered after the caller's stream and the caller's
+    // stream after it, by events.  Captured launches record their arguments,
+    // so the key holds every argument that can differ between calls.
+    template <typename F>
+    void graph(const std::vector<unsigned long long> &key, F body) {
+        if (err != hipSuccess) return;
+        if (!h->gstream) {
+            if (!ok(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking))) return;
+            for (hipEvent_t &e : h->gev)
+                if (!ok(hipEventCreateWithFlags(&e, hipEventDisableTiming))) return;
+        }
+        hipGraphExec_t exec = nullptr;
+        for (const auto &g : h->graphs)
+            if (g.key == key) exec = g.exec;
+        if (!exec) {
+            const hipStream_t caller = s;
+            s = h->gstream;
+            if (!ok(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal))) {
+                s = caller;
+                return;
+            }
+            body();
+            hipGraph_t gr = nullptr;
+            const hipError_t e = hipStreamEndCapture(s, &gr);
+            s = caller;
+            if (!ok(e)) return;
+            const hipError_t ei = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (!ok(ei)) return;
+            // keep the most recent few (a key holds the caller's x and b)
+            if (h->graphs.size() >= 16) {
+                ok(hipStreamSynchronize(h->gstream));
+                (void)hipGraphExecDestroy(h->graphs.front().exec);
+                h->graphs.erase(h->graphs.begin());
+            }
+            h->graphs.push_back(rt_handle::Graph{key, exec});
+        }
+        ok(hipEventRecord(h->gev[0], s));
+        ok(hipStreamWaitEvent(h->gstream, h->gev[0], 0));
+        ok(hipGraphLaunch(exec, h->gstream));
+        ok(hipEventRecord(h->gev[1], h->gstream));
+        ok(hipStreamWaitEvent(s, h->gev[1], 0));
+    }
+
+    static unsigned long long bits(double v) {
+        unsigned long long u;
+        std::memcpy(&u, &v, sizeof u);
+        return u;
+    }
+    static unsigned long long bits(const void *p) { return (unsigned long long)(uintptr_t)p; }
+
     // w = A (scale .* in), FP64 or FP32 sweep, for slabs whose mask is set
     void sweep(const double *in, const double *scale, double *out, const int *mask, bool fp32) {
         ok(apply_operator(h, in, scale, out, mask, fp32, 0, s));
@@ -735,6 +938,22 @@ struct Driver {
     int ept() const {
         const int need = (2 * h->ns_max + NT - 1) / NT;
         return need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : 16;
+    }
+
+    // the fused Arnoldi step covers every slab and the restart length
+    bool fused() const { return h->ns_max <= NTF && h->ws_restart < MR; }
+
+    // sweep of A P^-1 v_j, then the Arnoldi step (fused or not)
+    void arnoldi_step(const VecArgs &a, int j, bool fp32) {
+        const double *vj = h->d_V + (long long)j * h->n_unk;
+        if (fused()) {
+            ok(apply_sweep(h, vj, h->d_dinv, h->d_cycle, fp32, s));
+            hipLaunchKernelGGL(gm_arnoldi_fused_kernel, dim3(h->n_atm), dim3(NTF), 0, s, a, j);
+            ok(hipGetLastError());
+        } else {
+            sweep(vj, h->d_dinv, h->d_w, h->d_cycle, fp32);
+            arnoldi(a, j);
+        }
     }
 
     void arnoldi(const VecArgs &a, int j) {
@@ -799,6 +1018,8 @@ struct Driver {
         a.tol = tol;
         a.maxit = maxit;
         a.max_outer = h->opt.max_outer;
+        a.partial = h->d_partial;
+        a.Qs = h->d_Qs;
         return a;
     }
 
@@ -814,18 +1035,32 @@ struct Driver {
         hipLaunchKernelGGL(gm_restart_kernel, dim3(nb), dim3(NT), 0, s, a, 1, x_zero ? 1 : 0,
                            accept_est ? 1 : 0);
         ok(hipGetLastError());
-        while (err == hipSuccess) {
-            if (count(h->d_active) == 0) break;
-            for (int j = 0; j < m; ++j) {
-                sweep(h->d_V + (long long)j * h->n_unk, h->d_dinv, h->d_w, h->d_cycle, fp32);
-                arnoldi(a, j);
-                if ((j + 1) % check == 0 && j + 1 < m && count(h->d_cycle) == 0) break;
-            }
+        // one cycle: m Arnoldi steps (masked off per slab once its cycle
+        // ends), the update of x, and the restart with the explicit residual
+        auto tail = [&]() {
             update(a);
             sweep(x, nullptr, h->d_w, h->d_active, fp32);
             hipLaunchKernelGGL(gm_restart_kernel, dim3(nb), dim3(NT), 0, s, a, 0, 0,
                                accept_est ? 1 : 0);
             ok(hipGetLastError());
+        };
+        const std::vector<unsigned long long> key = {
+            0, bits(b), bits(x), bits(st), bits(tol), (unsigned long long)maxit, fp32 ? 1ull : 0ull,
+            accept_est ? 1ull : 0ull};
+        while (err == hipSuccess) {
+            if (count(h->d_active) == 0) break;
+            if (h->opt.graphs) {
+                graph(key, [&]() {
+                    for (int j = 0; j < m; ++j) arnoldi_step(a, j, fp32);
+                    tail();
+                });
+            } else {
+                for (int j = 0; j < m; ++j) {
+                    arnoldi_step(a, j, fp32);
+                    if ((j + 1) % check == 0 && j + 1 < m && count(h->d_cycle) == 0) break;
+                }
+                tail();
+            }
         }
     }
 
@@ -836,14 +1071,26 @@ struct Driver {
         sweep(x, nullptr, h->d_w, h->d_active, false);
         hipLaunchKernelGGL(bi_start_kernel, dim3(nb), dim3(NT), 0, s, a);
         ok(hipGetLastError());
-        for (int it = 0; err == hipSuccess; ++it) {
-            if (it % check == 0 && count(h->d_active) == 0) break;
+        auto step = [&]() {
             hipLaunchKernelGGL(bi_dir_kernel, dim3(nb), dim3(NT), 0, s, a);
             sweep(h->d_p, h->d_dinv, h->d_v, h->d_active, false);
             hipLaunchKernelGGL(bi_half_kernel, dim3(nb), dim3(NT), 0, s, a);
             sweep(h->d_s, h->d_dinv, h->d_t, h->d_active, false);
             hipLaunchKernelGGL(bi_full_kernel, dim3(nb), dim3(NT), 0, s, a);
             ok(hipGetLastError());
+        };
+        const std::vector<unsigned long long> key = {1,         bits(b),   bits(x),
+                                                     bits(st),  bits(tol), (unsigned long long)maxit,
+                                                     (unsigned long long)check};
+        while (err == hipSuccess) {
+            if (count(h->d_active) == 0) break;
+            if (h->opt.graphs) {
+                graph(key, [&]() {
+                    for (int i = 0; i < check; ++i) step();
+                });
+            } else {
+                for (int i = 0; i < check; ++i) step();
+            }
         }
         // explicit final residual of every slab
         sweep(x, nullptr, h->d_w, nullptr, false);
@@ -855,11 +1102,25 @@ struct Driver {
         const int nb = h->n_atm;
         VecArgs a = args(b, x, st, h->d_active, tol, maxit);
         const int check = std::max(1, h->opt.check_every);
-        for (int it = 0; err == hipSuccess; ++it) {
-            if (it > 0 && it % check == 0 && count(h->d_active) == 0) break;
+        auto step = [&](int first) {
             sweep(x, nullptr, h->d_w, h->d_active, false);
-            hipLaunchKernelGGL(ri_step_kernel, dim3(nb), dim3(NT), 0, s, a, it == 0 ? 1 : 0);
+            hipLaunchKernelGGL(ri_step_kernel, dim3(nb), dim3(NT), 0, s, a, first);
             ok(hipGetLastError());
+        };
+        const std::vector<unsigned long long> key = {2,         bits(b),   bits(x),
+                                                     bits(st),  bits(tol), (unsigned long long)maxit,
+                                                     (unsigned long long)check};
+        // the first check_every updates (the first one sets up the state) eagerly
+        for (int i = 0; i < check && err == hipSuccess; ++i) step(i == 0 ? 1 : 0);
+        while (err == hipSuccess) {
+            if (count(h->d_active) == 0) break;
+            if (h->opt.graphs) {
+                graph(key, [&]() {
+                    for (int i = 0; i < check; ++i) step(0);
+                });
+            } else {
+                for (int i = 0; i < check; ++i) step(0);
+            }
         }
     }
 

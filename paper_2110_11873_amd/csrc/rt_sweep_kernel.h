@@ -47,6 +47,10 @@ __device__ inline void load_pair(__amdgpu_buffer_rsrc_t r, int voff, int soff, d
     o.x = __hiloint2double((int)v.y, (int)v.x);
     o.y = __hiloint2double((int)v.w, (int)v.z);
 }
+__device__ inline double load_f64(__amdgpu_buffer_rsrc_t r, int voff) {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0);
+    return __hiloint2double((int)v.y, (int)v.x);
+}
 
 // --------------------------------------------------------------------------
 // Cross-lane moves.  DPP (data-parallel primitives) move a register between
@@ -269,21 +273,27 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
     const T ftop = (c == 0) ? (T)1 : (T)0;
     const T fbot = (c == C - 1 && bottom_on_grid) ? (T)1 : (T)0;
 
-    // this direction's tiles, read through a buffer descriptor: per-lane
-    // byte offset in a register, per-step offset in a scalar register
+    // this direction's tiles and ray weights, read through buffer
+    // descriptors that end at the block's last batch: a load of a batch past
+    // it (the prefetch beyond a wave's last batch) returns zeros and fetches
+    // nothing, so every load is unconditional and the compiler can keep the
+    // next batch's loads in flight across the current batch's work.  Batch
+    // and lane offsets in a register, the step offset in a scalar register.
+    const int bend = bd.wb_first + bd.wb_count;
     const P2 *tiles =
         reinterpret_cast<const P2 *>(a.coef) + at.coef_off + (long long)bd.m * at.nwb * LE * kWave;
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)tiles, 0, at.nwb * LE * kWave * (int)sizeof(P2), kRawBufferWord3);
+        (void *)tiles, 0, bend * LE * kWave * (int)sizeof(P2), kRawBufferWord3);
+    const double *qdir = a.q + at.q_off + (long long)bd.m * at.nwb * at.G;
+    const __amdgpu_buffer_rsrc_t qrsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)qdir, 0, bend * at.G * 8, kRawBufferWord3);
     const int voff = lane * (int)sizeof(P2);
-    const double *qdir = a.q + at.q_off + (long long)bd.m * at.nwb * at.G + g;
-    const int bend = bd.wb_first + bd.wb_count;
 
     auto load_batch = [&](int b, P2 (&cn)[LE], double &qn) {
+        const int vo = voff + b * LE * kWave * (int)sizeof(P2);
 #pragma unroll
-        for (int i = 0; i < LE; ++i)
-            load_pair(rsrc, voff, (b * LE + i) * kWave * (int)sizeof(P2), cn[i]);
-        qn = qdir[(long long)b * at.G];
+        for (int i = 0; i < LE; ++i) load_pair(rsrc, vo, i * kWave * (int)sizeof(P2), cn[i]);
+        qn = load_f64(qrsrc, (b * at.G + g) * 8);
     };
 
     auto process = [&](const P2 (&cn)[LE], double qd) {
@@ -361,13 +371,13 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
     } else {
         // two register sets, each loaded one batch ahead of its use
         P2 cA[LE], cB[LE];
-        double qA = 0.0, qB = 0.0;
-        if (b0 < bend) load_batch(b0, cA, qA);
+        double qA, qB;
+        load_batch(b0, cA, qA);
         for (int b = b0; b < bend; b += 2 * W) {
-            if (b + W < bend) load_batch(b + W, cB, qB);
+            load_batch(b + W, cB, qB);
             process(cA, qA);
             if (b + W >= bend) break;
-            if (b + 2 * W < bend) load_batch(b + 2 * W, cA, qA);
+            load_batch(b + 2 * W, cA, qA);
             process(cB, qB);
         }
     }

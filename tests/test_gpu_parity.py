@@ -259,6 +259,61 @@ def test_solvers_config2(fs, kind):
         assert abs(info[0].iterations - oi[0]["iterations"]) <= max(3, oi[0]["iterations"] // 4)
 
 
+@pytest.mark.parametrize("restart", [30, 31, 32, 40])
+def test_gmres_arnoldi_paths(restart):
+    """Restarts below 32 use the Arnoldi step fused with the operator's last
+    pass (basis in registers); longer ones the general step.  Both must reach
+    the oracle's residual on a batch of uneven slabs, with iteration counts
+    close to the oracle running GMRES(restart) on each slab."""
+    ns = [40, 97, 200, 511]
+    p = W.make_slabs(ns, [(1e-3, 1e5)] * len(ns), 8, 21, 6.0, [1e-3] * len(ns),
+                     [1e-3, 1e-2, 1e-4, 1e-3], [0.6, 0.0, 0.3, 0.5])
+    with B.setup(p, rtol=1e-10, restart=restart) as h:
+        rc, info, x = _solve(h, "gmres", p)
+    assert all(i.status == "converged" for i in info), info
+    rr = oracle_relres(p, x)
+    assert rr.max() < 1e-10, rr
+    for i in range(len(ns)):
+        _, oi = O.gmres(p.slab(i), tol=1e-10, restart=restart)
+        it = oi[0]["iterations"]
+        assert abs(info[i].iterations - it) <= max(2, it // 20), (i, info[i].iterations, it)
+
+
+@pytest.mark.parametrize("kind,mixed", [("gmres", False), ("gmres", True), ("bicgstab", False),
+                                        ("richardson", False)])
+def test_graph_replays_match_eager_launches(kind, mixed):
+    """Solver segments captured in HIP graphs and replayed give the same
+    result, bit for bit, as the same kernels launched one by one; checked on
+    several replays in a row with eager work (operator applications, a
+    synchronization) between them, and two right-hand sides."""
+    ns = [40, 97, 200]
+    p = W.make_slabs(ns, [(1e-3, 1e5)] * len(ns), 8, 21, 6.0, [1e-3] * len(ns),
+                     [1e-3, 1e-2, 1e-4], [0.6, 0.0, 0.3])
+    kw = dict(rtol=1e-10, maxit=100000, check_every=8)
+    if mixed:
+        kw["precision"] = B.RT_PREC_MIXED
+    rng = np.random.default_rng(5)
+    bs = [None, dev(rng.uniform(0.5, 1.5, p.n_unknowns))]
+    ref = []
+    with B.setup(p, graphs=0, **kw) as h:
+        for b in bs:
+            rc, info, x = _solve(h, kind, p, b=b)
+            ref.append((x, [i.iterations for i in info]))
+    with B.setup(p, graphs=1, **kw) as h:
+        v = dev(W.random_vector(p.n_unknowns, 3))
+        x0 = dev(W.initial_guess(p))
+        x = torch.empty_like(x0)  # one buffer: the same captured graphs serve every solve
+        for rep in range(3):
+            for b, (xr, itr) in zip(bs, ref):
+                y = h.apply_op(v)
+                torch.cuda.synchronize()
+                x.copy_(x0)
+                rc, info = getattr(h, "solve_" + kind)(x, b=b)
+                assert [i.iterations for i in info] == itr, (rep, kind)
+                assert np.array_equal(host(x), xr), (rep, kind, np.abs(host(x) - xr).max())
+                assert np.array_equal(host(y), host(h.apply_op(v)))
+
+
 def test_richardson_config2_delo():
     p = W.config2()
     with B.setup(p, rtol=1e-10, maxit=200000) as h:
