@@ -264,5 +264,13 @@ class Handle:
         return self._solve("rt_solve_richardson", b, x, stream)
 
 
-def setup(prob, options: Optional[rt_options] = None, **kw) -> Handle:
+def setup(prob, options: Optional[rt_options] = None, autotune: bool = False, **kw) -> Handle:
+    """Set up `prob` on the current GPU.  autotune=True applies the launch
+    plan the autotuner stored for this problem shape and precision (see
+    paper_2110_11873_amd.autotune), where the caller did not set it."""
+    if autotune and options is None:
+        from . import autotune as AT
+        tuned = AT.lookup(prob, kw.get("precision", RT_PREC_FP64) == RT_PREC_MIXED)
+        if tuned:
+            kw = {**tuned, **kw}
     return Handle(prob, options, **kw)

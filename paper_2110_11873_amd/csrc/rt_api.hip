@@ -418,6 +418,7 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
                 bd.m = m;
                 bd.wb_first = bb * wb_per_block;
                 bd.wb_count = std::min(wb_per_block, d.nwb - bd.wb_first);
+                bd.slot = m * blk_per_dir + bb;
                 h->blk_h.push_back(bd);
             }
         }
@@ -429,6 +430,12 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
         h->atm_h[a] = d;
     }
     h->n_blocks = blk;
+    // longest blocks first (work ~ wave-batches x chunk length, the same
+    // lane count per batch); ties keep slab order
+    std::stable_sort(h->blk_h.begin(), h->blk_h.end(), [&](const BlockDesc &x, const BlockDesc &y) {
+        return (long long)x.wb_count * h->atm_h[x.atm].Leff >
+               (long long)y.wb_count * h->atm_h[y.atm].Leff;
+    });
     h->n_qt = qt;
     h->n_pairs = coef;
     h->n_partial = part;

@@ -44,12 +44,16 @@ struct AtmDesc {
 
 // One sweep block: direction m of slab atm; wave w of a block of W waves
 // handles wave-batches wb_first + w + t * W, t = 0, 1, ..., while below
-// wb_first + wb_count.
+// wb_first + wb_count, and writes its quadrature sums to partial-sum slot
+// `slot` of the slab.  The block list is ordered by decreasing work, so the
+// in-order dispatch of workgroups starts the longest ones first.
 struct BlockDesc {
     int atm;
     int m;
     int wb_first;
     int wb_count;
+    int slot;
+    int pad[3];
 };
 
 // Quadrature weight of a ray (applied to both directions of the +-mu pair)

@@ -407,7 +407,7 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
 
     // block totals of the 2 ns quadrature sums
     const int nthr = kWave * W;
-    double *mine = a.partial + at.part_off + (long long)(blockIdx.x - at.blk_first) * 2 * ns;
+    double *mine = a.partial + at.part_off + (long long)bd.slot * 2 * ns;
     if (a.rows) {
         // one LDS row per wave, then a fixed-order sum over the rows
         T *row = sacc + (long long)wave * 2 * ns;
