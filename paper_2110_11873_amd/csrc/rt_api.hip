@@ -393,9 +393,19 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
         d.doff = h->doff[a];
         d.C = chunks_for(d.ns, h->L);
         d.Leff = chunk_len(d.ns, d.C, h->L);
+        // chunk lengths Leff and Leff - 1 tile the ns - 1 intervals exactly
+        // when Leff is ceil((ns - 1) / C); otherwise (lengths rounded up to
+        // a compiled one) all chunks are long and the last ones end past the
+        // slab's bottom in identity steps
+        d.nlong = d.C;
+        if (chunk_len_step(h->L) == 1) {
+            const int r = (d.ns - 1) - d.C * (d.Leff - 1);
+            if (r >= 1 && r <= d.C) d.nlong = r;
+        }
         d.G = kWave / d.C;
         d.n_nu = h->n_nu;
         d.nwb = (h->n_nu + d.G - 1) / d.G;
+        d.bstride = (d.Leff - 1) * kWave + (d.G * d.nlong + 15) / 16 * 16;
         d.ray_off = a * rays;
         int nb = (d.nwb + h->W * blocks_per_dir - 1) / (h->W * blocks_per_dir);
         nb = std::min(std::max(nb, 1), 32);
@@ -424,7 +434,7 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
         }
         h->NB = nb;
         blk += d.nblk;
-        coef += (long long)h->M * d.nwb * d.Leff * kWave;
+        coef += (long long)h->M * d.nwb * d.bstride;
         qt += (long long)h->M * d.nwb * d.G;
         part += (long long)d.nblk * 2 * d.ns;
         h->atm_h[a] = d;

@@ -18,21 +18,26 @@ constexpr int kKrylovThreads = 256;
 constexpr int kKrylovEPT = (2 * RT_MAX_NS + kKrylovThreads - 1) / kKrylovThreads;
 
 // Per-slab launch plan of the formal-solver sweep.  A ray is one (|mu_m|, nu_p)
-// pair; its depth recurrence is split into C chunks of Leff intervals, one
-// chunk per lane, G = 64 / C rays per wavefront ("wave-batch").  Wave-batches
-// never mix directions: batch b of direction m holds the rays p = b*G + g.
+// pair; its depth recurrence is split into C chunks, one chunk per lane,
+// G = 64 / C rays per wavefront ("wave-batch").  The first nlong chunks have
+// Leff intervals, the others Leff - 1: a short chunk's last step is a
+// zero-length interval (the identity), which is neither stored nor loaded.
+// Wave-batches never mix directions: batch b of direction m holds the rays
+// p = b*G + g.
 struct AtmDesc {
     int ns;         // depth points
     int doff;       // first depth point of the slab in concatenated arrays
     int C;          // chunks per ray (power of two, <= 64)
-    int Leff;       // intervals per chunk (chunk_len; <= the kernel's L)
+    int Leff;       // intervals of a long chunk (chunk_len; <= the kernel's L)
     int G;          // rays per wave-batch
     int n_nu;       // frequencies: rays per direction
     int nwb;        // wave-batches per direction
     int ray_off;    // first ray of the slab in the ray tables (rays m*n_nu + p)
     int blk_first;  // first sweep block of the slab
     int nblk;       // sweep blocks of the slab
-    int pad0;
+    int nlong;      // chunks of Leff intervals (the rest have Leff - 1)
+    int bstride;    // coefficient pairs per wave-batch: Leff - 1 rows of 64 lanes,
+                    // then the long chunks' last steps, packed (padded to 16)
     long long q_off;     // first entry of the slab's tile-ordered weights
     long long coef_off;  // first coefficient pair of the slab's tiles
     long long part_off;  // first partial sum of the slab's blocks

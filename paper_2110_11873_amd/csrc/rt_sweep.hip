@@ -181,15 +181,20 @@ __device__ inline void step_ew(int fs, double d, double &E, double &w) {
     w = E + cu;
 }
 
-// Tile-ordered coefficients: the pair (E, w) of step i of the chunk held by
-// lane `lane` in wave-batch b of direction m lives at
-//   coef_off + ((m * nwb + b) * Leff + i) * 64 + lane,
-// the lane holding chunk lane_chunk(lane, C) (intervals c*Leff ..
-// c*Leff+Leff-1) of ray p = b*G + lane_slot(lane, C).  Padding (frequencies
-// beyond the last, intervals beyond ns - 2) is (1, 1): the step leaves I
-// unchanged, and the source beyond the slab is zero.  The rays' quadrature
-// weights are laid out by slot (q_off + (m*nwb + b)*G + slot), zero for
-// padding rays, so the sweep never masks a loaded value.
+// Tile-ordered coefficients.  The lane `lane` of wave-batch b of direction m
+// holds chunk c = lane_chunk(lane, C) of ray p = b*G + g, g = lane_slot(lane,
+// C); the chunk starts at interval s0 = c (Leff - 1) + min(c, nlong) and has
+// Leff intervals if c < nlong, else Leff - 1.  The pair (E, w) of its step i
+// lives at
+//   coef_off + (m * nwb + b) * bstride + i * 64 + lane          (i < Leff - 1)
+//   coef_off + (m * nwb + b) * bstride + (Leff - 1) * 64 + g * nlong + c
+//                                                       (i = Leff - 1, c < nlong)
+// so a wavefront reads each step as 64 consecutive pairs, and the last step
+// only for the chunks that have one.  Padding (frequencies beyond the last,
+// intervals beyond ns - 2) is (1, 1): the step leaves I unchanged, and the
+// source beyond the slab is zero.  The rays' quadrature weights are laid out
+// by slot (q_off + (m*nwb + b)*G + slot), zero for padding rays, so the sweep
+// never masks a loaded value.
 // --------------------------------------------------------------------------
 __global__ void coef_build_kernel(int W, const AtmDesc *atm, const BlockDesc *blk,
                                   const double *tau, const double *opac, const double *mu_pos,
@@ -199,21 +204,26 @@ __global__ void coef_build_kernel(int W, const AtmDesc *atm, const BlockDesc *bl
     const AtmDesc at = atm[bd.atm];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int c = lane_chunk(lane, at.C), g = lane_slot(lane, at.C);
+    const int s0 = c * (at.Leff - 1) + min(c, at.nlong);
+    const bool longc = c < at.nlong;
     for (int b = bd.wb_first + wave; b < bd.wb_first + bd.wb_count; b += W) {
         const int p = b * at.G + g;
         if (c == 0)  // quadrature weight of the ray, zero for padding rays
             qtile[at.q_off + ((long long)bd.m * at.nwb + b) * at.G + g] =
                 (p < at.n_nu) ? qray[at.ray_off + (long long)bd.m * at.n_nu + p] : 0.0;
         for (int i = 0; i < at.Leff; ++i) {
-            const int j = c * at.Leff + i;
+            const bool last = i == at.Leff - 1;
+            if (last && !longc) continue;
+            const int j = s0 + i;
             double E = 1.0, w = 1.0;
             if (p < at.n_nu && j < at.ns - 1) {
                 const double kap = opac[(long long)bd.atm * at.n_nu + p] / mu_pos[bd.m];
                 const double d = kap * (tau[at.doff + j + 1] - tau[at.doff + j]);
                 step_ew(fs, d, E, w);
             }
-            const long long e =
-                at.coef_off + (((long long)bd.m * at.nwb + b) * at.Leff + i) * kWave + lane;
+            const long long e = at.coef_off + ((long long)bd.m * at.nwb + b) * at.bstride +
+                                (last ? (long long)(at.Leff - 1) * kWave + g * at.nlong + c
+                                      : (long long)i * kWave + lane);
             coef64[e] = make_double2(E, w);
             coef32[e] = make_float2((float)E, (float)w);
         }

@@ -222,7 +222,12 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
     using P2 = typename Pair<T>::type;
     const int ns = at.ns;
     const int c = lane_chunk(lane, C), g = lane_slot(lane, C);
-    const int s0 = c * LE;  // first depth point of this lane's chunk
+    // the chunk: first depth point s0, len = LE or LE - 1 intervals (a short
+    // chunk's step LE - 1 is the zero-length identity: its end point repeats)
+    const int nlong = at.nlong;
+    const bool longc = c < nlong;
+    const int s0 = c * (LE - 1) + min(c, nlong);
+    const int len = longc ? LE : LE - 1;
 
     // The sweep carries the deviation D = I - S of the intensity from the
     // local source: with E + c_u = 1 - c_k = w the step becomes
@@ -241,7 +246,7 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
         P2 sv[LE + 1];
 #pragma unroll
         for (int i = 0; i <= LE; ++i) {
-            const int k = s0 + i;
+            const int k = s0 + min(i, len);
             sv[i] = src2[min(k, ns - 1)];
             if (k >= ns) sv[i].x = sv[i].y = (T)0;
         }
@@ -265,7 +270,7 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
     // chunk's end point -- a point of the slab or past it (source zero)
     const T inflow = (a.mode == 1) ? (T)at.Ibot : (T)0;
     const T topD0 = -top0, topD2 = -top2;
-    const bool bottom_on_grid = C * LE == ns - 1;
+    const bool bottom_on_grid = C * (LE - 1) + nlong == ns - 1;
     const T botD0 = inflow - (bottom_on_grid ? bot0 : (T)0);
     const T botD2 = -(bottom_on_grid ? bot2 : (T)0);
     // the top point's downward deviation is the top inflow's; a bottom point
@@ -280,24 +285,32 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
     // next batch's loads in flight across the current batch's work.  Batch
     // and lane offsets in a register, the step offset in a scalar register.
     const int bend = bd.wb_first + bd.wb_count;
+    const int bbytes = at.bstride * (int)sizeof(P2);  // one wave-batch of pairs
     const P2 *tiles =
-        reinterpret_cast<const P2 *>(a.coef) + at.coef_off + (long long)bd.m * at.nwb * LE * kWave;
-    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)tiles, 0, bend * LE * kWave * (int)sizeof(P2), kRawBufferWord3);
+        reinterpret_cast<const P2 *>(a.coef) + at.coef_off + (long long)bd.m * at.nwb * at.bstride;
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)tiles, 0, bend * bbytes, kRawBufferWord3);
     const double *qdir = a.q + at.q_off + (long long)bd.m * at.nwb * at.G;
     const __amdgpu_buffer_rsrc_t qrsrc =
         __builtin_amdgcn_make_buffer_rsrc((void *)qdir, 0, bend * at.G * 8, kRawBufferWord3);
     const int voff = lane * (int)sizeof(P2);
+    // the packed last step: short chunks read from past the descriptor's
+    // range (zeros, no memory access) and take the identity below
+    constexpr int kNoLoad = 1 << 30;
+    const int voff_last =
+        longc ? ((LE - 1) * kWave + g * nlong + c) * (int)sizeof(P2) : kNoLoad;
 
     auto load_batch = [&](int b, P2 (&cn)[LE], double &qn) {
-        const int vo = voff + b * LE * kWave * (int)sizeof(P2);
+        const int vo = voff + b * bbytes;
 #pragma unroll
-        for (int i = 0; i < LE; ++i) load_pair(rsrc, vo, i * kWave * (int)sizeof(P2), cn[i]);
+        for (int i = 0; i + 1 < LE; ++i) load_pair(rsrc, vo, i * kWave * (int)sizeof(P2), cn[i]);
+        load_pair(rsrc, voff_last + b * bbytes, 0, cn[LE - 1]);
         qn = load_f64(qrsrc, (b * at.G + g) * 8);
     };
 
-    auto process = [&](const P2 (&cn)[LE], double qd) {
+    auto process = [&](P2 (&cn)[LE], double qd) {
         const T q = (T)qd;
+        if (!longc) cn[LE - 1].x = cn[LE - 1].y = (T)1;  // zero-length step
         // one pass over the chunk with zero inflow in both directions: the
         // local deviations go into the quadrature at once, and the running
         // transmissions Td[i] = E_0..E_i, Tu[i] = E_i..E_{LE-1} are kept for
@@ -415,7 +428,7 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
 #pragma unroll
             for (int i = 0; i < LE; ++i) {
                 const int k = s0 + i;
-                if (k < ns) {
+                if (k < ns && i < len) {
                     row[2 * k] = AU[i] + t1 * AV[i];
                     row[2 * k + 1] = t1 * AU[i] + t12 * AV[i];
                 }
@@ -440,7 +453,7 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
 #pragma unroll
                 for (int i = 0; i < LE; ++i) {
                     const int k = s0 + i;
-                    if (k < ns) {
+                    if (k < ns && i < len) {
                         sacc[2 * k] += AU[i] + t1 * AV[i];
                         sacc[2 * k + 1] += t1 * AU[i] + t12 * AV[i];
                     }
