@@ -187,6 +187,22 @@ def time_solves(torch, h, x0, kind, steps, warmup):
     return time.perf_counter() - t0, info
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
+    """Device-to-device copy rate (bytes read + written per second)."""
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record(s)
+    e1.synchronize()
+    return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
 def cpu_baseline(p, dinv, n_sample=8):
     """The FP64 oracle's Jacobi-GMRES(30) on a sample of the batch's slabs."""
     from oracle import oracle as O
@@ -281,6 +297,7 @@ def main():
         out["fp64_converged"] = sum(i.status == "converged" for i in info64)
         out["fp64_iterations_max"] = max(i.iterations for i in info64)
     out["mixed_over_fp64"] = value / out["fp64_solves_per_s"]
+    out["hbm_copy_GBs"] = copy_bandwidth(torch)  # measured, beside the 8 TB/s datasheet peak
 
     if not args.no_extras:
         # the single paper-shaped slab (Ns = 200, 20 mu, 101 nu), FP64
