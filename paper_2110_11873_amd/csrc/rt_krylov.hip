@@ -28,6 +28,7 @@ namespace {
 
 constexpr int NT = kKrylovThreads;
 constexpr int NW = NT / kWave;
+constexpr int kTriLds = 32;  // restarts up to this size solve their triangle from LDS
 
 __device__ inline double wave_sum(double v) {
     for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -223,6 +224,73 @@ __global__ void gm_restart_kernel(VecArgs a, int first, int x_zero, int accept_e
     }
 }
 
+// Column j of the Hessenberg matrix of one slab (thread 0 only): h[0..j]
+// are the Gram-Schmidt coefficients, hn = ||w||; the earlier rotations
+// (cs, sn)[0..j-1] are applied, the new one is formed, and g and the
+// slab's convergence state are updated (Saad & Schultz).  The column is
+// stored already rotated (the triangular factor the update solves with).
+__device__ inline void hessenberg_finish(const VecArgs &a, int atm, int j, double hjj, double hn) {
+    const int m = a.m;
+    double *H = a.H + (long long)atm * (m + 1) * m;
+    double *g = a.g + (long long)atm * (m + 1);
+    const double den = sqrt(hjj * hjj + hn * hn);
+    const double c = (den > 0.0) ? hjj / den : 1.0;
+    const double s = (den > 0.0) ? hn / den : 0.0;
+    a.cs[(long long)atm * m + j] = c;
+    a.sn[(long long)atm * m + j] = s;
+    H[j * m + j] = den;
+    H[(j + 1) * m + j] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -s * gj;
+    g[j] = c * gj;
+    KState &S = a.st[atm];
+    S.resid = fabs(s * gj);
+    S.iters += 1;
+    S.matvecs += 1;
+    S.inner = j + 1;
+    const bool done = (S.resid / S.bnorm < a.tol) || !(hn > 0.0) || (S.iters >= a.maxit) ||
+                      (j + 1 == m) || !(S.resid == S.resid);
+    if (done) a.cycle[atm] = 0;
+}
+
+__device__ inline void hessenberg_column_lds(const VecArgs &a, int atm, int j, double *h,
+                                             const double *cs, const double *sn, double hn) {
+    const int m = a.m;
+    double *H = a.H + (long long)atm * (m + 1) * m;
+    for (int i = 0; i < j; ++i) {
+        const double h0 = h[i], h1 = h[i + 1];
+        h[i] = cs[i] * h0 + sn[i] * h1;
+        h[i + 1] = -sn[i] * h0 + cs[i] * h1;
+    }
+    for (int i = 0; i < j; ++i) H[i * m + j] = h[i];
+    hessenberg_finish(a, atm, j, h[j], hn);
+}
+
+template <int MR_>
+__device__ inline void hessenberg_column_regs(const VecArgs &a, int atm, int j, const double *hs,
+                                              const double *cs, const double *sn, double hn) {
+    const int m = a.m;
+    double *H = a.H + (long long)atm * (m + 1) * m;
+    double h[MR_];
+#pragma unroll
+    for (int i = 0; i < MR_; ++i) h[i] = (i <= j) ? hs[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i + 1 < MR_; ++i) {
+        if (i < j) {
+            const double c = cs[i], s = sn[i], h0 = h[i], h1 = h[i + 1];
+            h[i] = c * h0 + s * h1;
+            h[i + 1] = -s * h0 + c * h1;
+        }
+    }
+    double hjj = 0.0;
+#pragma unroll
+    for (int i = 0; i < MR_; ++i) {
+        if (i < j) H[i * m + j] = h[i];
+        if (i == j) hjj = h[i];
+    }
+    hessenberg_finish(a, atm, j, hjj, hn);
+}
+
 // One Arnoldi step j: w = A P^-1 v_j is in a.w.  Classical Gram-Schmidt twice
 // (h = V^T w; w -= V h; repeated), h_{j+1,j} = ||w||, v_{j+1} = w / ||w||,
 // then the Givens rotations of the Hessenberg column and the residual
@@ -234,12 +302,17 @@ __global__ __launch_bounds__(NT) void gm_arnoldi_kernel(VecArgs a, int j) {
     __shared__ double hsum[RT_MAX_RESTART + 1];
     __shared__ double hp[RT_MAX_RESTART + 1];
     __shared__ double red2[2 * NW];
+    __shared__ double scs[RT_MAX_RESTART], ssn[RT_MAX_RESTART];
     const int atm = blockIdx.x;
     if (!a.cycle[atm]) return;
     const AtmDesc at = a.atm[atm];
     const int n = 2 * at.ns;
     const long long base = 2LL * at.doff;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    if (tid < j) {
+        scs[tid] = a.cs[(long long)atm * a.m + tid];
+        ssn[tid] = a.sn[(long long)atm * a.m + tid];
+    }
 
     double wl[E];
 #pragma unroll
@@ -309,37 +382,11 @@ __global__ __launch_bounds__(NT) void gm_arnoldi_kernel(VecArgs a, int j) {
             if (l < n) a.V[(long long)(j + 1) * a.N + base + l] = wl[e] * inv;
         }
     }
-    if (tid == 0) {
-        const int m = a.m;
-        double *H = a.H + (long long)atm * (m + 1) * m;
-        double *cs = a.cs + (long long)atm * m;
-        double *sn = a.sn + (long long)atm * m;
-        double *g = a.g + (long long)atm * (m + 1);
-        for (int i = 0; i <= j; ++i) H[i * m + j] = hsum[i];
-        for (int i = 0; i < j; ++i) {  // earlier rotations
-            const double h0 = H[i * m + j], h1 = H[(i + 1) * m + j];
-            H[i * m + j] = cs[i] * h0 + sn[i] * h1;
-            H[(i + 1) * m + j] = -sn[i] * h0 + cs[i] * h1;
-        }
-        const double hjj = H[j * m + j];
-        const double den = sqrt(hjj * hjj + hn * hn);
-        const double c = (den > 0.0) ? hjj / den : 1.0;
-        const double s = (den > 0.0) ? hn / den : 0.0;
-        cs[j] = c;
-        sn[j] = s;
-        H[j * m + j] = den;
-        H[(j + 1) * m + j] = 0.0;
-        g[j + 1] = -s * g[j];
-        g[j] = c * g[j];
-        KState &S = a.st[atm];
-        S.resid = fabs(g[j + 1]);
-        S.iters += 1;
-        S.matvecs += 1;
-        S.inner = j + 1;
-        const bool done = (S.resid / S.bnorm < a.tol) || !(hn > 0.0) || (S.iters >= a.maxit) ||
-                          (j + 1 == m) || !(S.resid == S.resid);
-        if (done) a.cycle[atm] = 0;
-    }
+    // the earlier rotations (read into LDS at the start, ordered by the
+    // block sums' barriers) are applied by one thread from LDS: global loads
+    // and stores in that sequential loop would each wait a memory round trip
+    if (tid == 0) hessenberg_column_lds(a, atm, j, hsum, scs, ssn, hn);
+
 }
 
 // The same step for slabs of at most NTF points and restarts m < MR, with the
@@ -369,12 +416,17 @@ __global__ __launch_bounds__(NTF) void gm_arnoldi_fused_kernel(VecArgs a, int j)
     __shared__ double hp[MR];
     __shared__ double hsum[MR];
     __shared__ double red2[NWF];
+    __shared__ double scs[MR], ssn[MR];
     const int atm = blockIdx.x;
     if (!a.cycle[atm]) return;
     const AtmDesc at = a.atm[atm];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int k = tid;  // depth point
     const bool on = k < at.ns;
+    if (tid < j) {
+        scs[tid] = a.cs[(long long)atm * a.m + tid];
+        ssn[tid] = a.sn[(long long)atm * a.m + tid];
+    }
     const long long e0 = 2LL * (at.doff + k);
 
     // basis rows 0..j at this point (zero beyond)
@@ -455,37 +507,10 @@ __global__ __launch_bounds__(NTF) void gm_arnoldi_fused_kernel(VecArgs a, int j)
         *reinterpret_cast<double2 *>(a.V + (long long)(j + 1) * a.N + e0) =
             make_double2(w0 * inv, w2 * inv);
     }
-    if (tid == 0) {
-        const int m = a.m;
-        double *H = a.H + (long long)atm * (m + 1) * m;
-        double *cs = a.cs + (long long)atm * m;
-        double *sn = a.sn + (long long)atm * m;
-        double *g = a.g + (long long)atm * (m + 1);
-        for (int i = 0; i <= j; ++i) H[i * m + j] = hsum[i];
-        for (int i = 0; i < j; ++i) {  // earlier rotations
-            const double h0 = H[i * m + j], h1 = H[(i + 1) * m + j];
-            H[i * m + j] = cs[i] * h0 + sn[i] * h1;
-            H[(i + 1) * m + j] = -sn[i] * h0 + cs[i] * h1;
-        }
-        const double hjj = H[j * m + j];
-        const double den = sqrt(hjj * hjj + hn * hn);
-        const double c = (den > 0.0) ? hjj / den : 1.0;
-        const double s = (den > 0.0) ? hn / den : 0.0;
-        cs[j] = c;
-        sn[j] = s;
-        H[j * m + j] = den;
-        H[(j + 1) * m + j] = 0.0;
-        g[j + 1] = -s * g[j];
-        g[j] = c * g[j];
-        KState &S = a.st[atm];
-        S.resid = fabs(g[j + 1]);
-        S.iters += 1;
-        S.matvecs += 1;
-        S.inner = j + 1;
-        const bool done = (S.resid / S.bnorm < a.tol) || !(hn > 0.0) || (S.iters >= a.maxit) ||
-                          (j + 1 == m) || !(S.resid == S.resid);
-        if (done) a.cycle[atm] = 0;
-    }
+    // the earlier rotations (read into LDS at the start, ordered by the
+    // block sums' barriers) are applied by one thread in registers
+    if (tid == 0) hessenberg_column_regs<MR>(a, atm, j, hsum, scs, ssn, hn);
+
 }
 
 // End of a cycle: solve the triangular system H y = g and set x += P^-1 V y.
@@ -498,10 +523,28 @@ __global__ __launch_bounds__(NT) void gm_update_kernel(VecArgs a) {
     const int n = 2 * at.ns;
     const long long base = 2LL * at.doff;
     const int jj = a.st[atm].inner;
-    if (threadIdx.x == 0) {
-        const int m = a.m;
-        const double *H = a.H + (long long)atm * (m + 1) * m;
-        const double *g = a.g + (long long)atm * (m + 1);
+    const int m = a.m;
+    const double *H = a.H + (long long)atm * (m + 1) * m;
+    const double *g = a.g + (long long)atm * (m + 1);
+    if (jj <= kTriLds) {
+        // the triangle and g read into LDS by all threads at once, then the
+        // back substitution by one thread from LDS (from global memory each
+        // of its ~jj^2/2 reads would wait a full round trip)
+        __shared__ double Ht[kTriLds * kTriLds], gt[kTriLds];
+        for (int e = threadIdx.x; e < jj * jj; e += NT) {
+            const int i = e / jj, l = e % jj;
+            if (l >= i) Ht[i * kTriLds + l] = H[i * m + l];
+        }
+        for (int i = threadIdx.x; i < jj; i += NT) gt[i] = g[i];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int i = jj - 1; i >= 0; --i) {
+                double s = gt[i];
+                for (int l = i + 1; l < jj; ++l) s -= Ht[i * kTriLds + l] * y[l];
+                y[i] = s / Ht[i * kTriLds + i];
+            }
+        }
+    } else if (threadIdx.x == 0) {
         for (int i = jj - 1; i >= 0; --i) {
             double s = g[i];
             for (int l = i + 1; l < jj; ++l) s -= H[i * m + l] * y[l];
