@@ -49,9 +49,12 @@ extern "C" {
 /* Formal solvers (Sect. 4.1).  DELO-linear: exact integration of a linearly
  * interpolated source function along the ray.  Trapezoidal: Crank-Nicolson
  * step of the transfer equation in optical path (not one of the paper's
- * four solvers; provided for comparison). */
+ * four solvers; provided for comparison).  Implicit Euler: the backward
+ * difference I_k = (I_u + d S_k) / (1 + d), d the optical step (one of the
+ * paper's four solvers, Sect. 4.1). */
 #define RT_FS_DELO_LINEAR 0
 #define RT_FS_TRAPEZOIDAL 1
+#define RT_FS_IMPLICIT_EULER 2
 
 /* Arithmetic of the solves.  FP64: every step in FP64.  MIXED: an FP32
  * formal-solver sweep and quadrature inside an inner GMRES, with the outer
@@ -90,7 +93,7 @@ typedef struct rt_handle rt_handle;
  *                   NULL means B = 1.  The constant term is c = [eps B, 0].
  *  I_bot[n_atm]     intensity entering at the bottom for mu > 0 (Sect. 3.1:
  *                   1); NULL means B at the deepest point
- *  formal_solver    RT_FS_DELO_LINEAR or RT_FS_TRAPEZOIDAL
+ *  formal_solver    RT_FS_DELO_LINEAR, RT_FS_TRAPEZOIDAL or RT_FS_IMPLICIT_EULER
  *  normalize_profile  nonzero: divide the spectral weights w_p phi_p by their
  *                   sum so scattering conserves photons on the truncated grid;
  *                   zero: use w_p phi_p as given (the paper's setting)

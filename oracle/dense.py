@@ -38,6 +38,9 @@ def _ray_matrices(tau, kappa, upward, fs):
         if fs == 0:
             E, pu, pk = O.delo_linear(d)
             a, cu, ck = E, pu, pk
+        elif fs == 2:
+            a, ck = O.implicit_euler(d)
+            cu = 0.0
         else:
             a, b = O.trapezoid(d)
             cu = ck = b

@@ -72,6 +72,7 @@ def lib():
             L.orc_t20.argtypes = [C.c_double, D, D]
             L.orc_delo_linear.argtypes = [C.c_double, D, D, D]
             L.orc_trapezoid.argtypes = [C.c_double, D, D]
+            L.orc_implicit_euler.argtypes = [C.c_double, D, D]
             L.orc_ray.argtypes = [C.c_int, D, C.c_double, C.c_int, C.c_int, D, C.c_double, D]
             L.orc_weights.argtypes = [P, D]
             L.orc_apply.argtypes = [P, D, D]
@@ -81,8 +82,9 @@ def lib():
             L.orc_gmres.argtypes = [P, D, D, D, C.c_int, C.c_double, C.c_int, I, I, D, D, C.c_int]
             L.orc_bicgstab.argtypes = [P, D, D, D, C.c_double, C.c_int, I, I, D]
             L.orc_richardson.argtypes = [P, D, D, D, C.c_double, C.c_int, I, I, D]
+            L.orc_cgs.argtypes = [P, D, D, D, C.c_double, C.c_int, I, I, D]
             for f in ("orc_apply", "orc_rhs", "orc_diag", "orc_assemble", "orc_gmres",
-                      "orc_bicgstab", "orc_richardson"):
+                      "orc_bicgstab", "orc_richardson", "orc_cgs"):
                 getattr(L, f).restype = C.c_int
             _lib = L
         return _lib
@@ -136,6 +138,12 @@ def delo_linear(d):
 def trapezoid(d):
     a, b = C.c_double(), C.c_double()
     lib().orc_trapezoid(float(d), C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def implicit_euler(d):
+    a, b = C.c_double(), C.c_double()
+    lib().orc_implicit_euler(float(d), C.byref(a), C.byref(b))
     return a.value, b.value
 
 
@@ -249,6 +257,9 @@ def _solve(kind, prob, b, x0, dinv, tol, maxit, restart=30, hist_len=0):
         elif kind == "richardson":
             st = lib().orc_richardson(v.ref, _dp(bs), _dp(xs), dptr, float(tol), int(maxit),
                                       C.byref(it), C.byref(mv), C.byref(rr))
+        elif kind == "cgs":
+            st = lib().orc_cgs(v.ref, _dp(bs), _dp(xs), dptr, float(tol), int(maxit),
+                               C.byref(it), C.byref(mv), C.byref(rr))
         else:
             raise ValueError(kind)
         x[s] = xs
@@ -279,6 +290,14 @@ def bicgstab(prob, b=None, x0=None, precond=True, tol=1e-10, maxit=10000, dinv=N
     if precond and dinv is None:
         dinv = jacobi_inverse(prob)
     return _solve("bicgstab", prob, b, x0, dinv if precond else None, tol, maxit)
+
+
+def cgs(prob, b=None, x0=None, precond=True, tol=1e-10, maxit=10000, dinv=None):
+    if x0 is None:
+        x0 = _x0(prob)
+    if precond and dinv is None:
+        dinv = jacobi_inverse(prob)
+    return _solve("cgs", prob, b, x0, dinv if precond else None, tol, maxit)
 
 
 def richardson(prob, b=None, x0=None, precond=True, tol=1e-10, maxit=100000, dinv=None):

@@ -48,7 +48,7 @@ typedef struct {
     double W2;            /* polarizability                                 */
     double Ibot;          /* incoming intensity at the bottom for mu > 0    */
     const double *B;      /* [ns] Planck function                           */
-    int fs;               /* 0: DELO-linear, 1: trapezoidal                 */
+    int fs;               /* 0: DELO-linear, 1: trapezoidal, 2: impl. Euler */
     int normalize;        /* renormalize the frequency weights              */
 } orc_slab;
 
@@ -114,6 +114,18 @@ void orc_trapezoid(double d, double *a, double *b)
 }
 
 /* ------------------------------------------------------------------------
+ * Implicit Euler step (one of the paper's formal solvers, Sect. 4.1): the
+ * backward difference of dI/dt = S - I over one interval,
+ *     (I_k - I_u) / d = S_k - I_k  =>  I_k = a I_u + b S_k,
+ *     a = 1/(1 + d), b = d/(1 + d).
+ * ---------------------------------------------------------------------- */
+void orc_implicit_euler(double d, double *a, double *b)
+{
+    *a = 1.0 / (1.0 + d);
+    *b = d / (1.0 + d);
+}
+
+/* ------------------------------------------------------------------------
  * Formal solution along one ray (eqs. RTE_delo1/2 written in optical path
  * along the ray).  kappa = r_p / |mu|.  upward = 0: the ray enters at the
  * top (index 0) and moves to larger tau; upward = 1: it enters at the
@@ -132,6 +144,10 @@ void orc_ray(int ns, const double *tau, double kappa, int upward, int fs,
                 double E, pu, pk;
                 orc_delo_linear(d, &E, &pu, &pk);
                 I[k] = E * I[u] + pu * S[u] + pk * S[k];
+            } else if (fs == 2) {
+                double a, b;
+                orc_implicit_euler(d, &a, &b);
+                I[k] = a * I[u] + b * S[k];
             } else {
                 double a, b;
                 orc_trapezoid(d, &a, &b);
@@ -147,6 +163,10 @@ void orc_ray(int ns, const double *tau, double kappa, int upward, int fs,
                 double E, pu, pk;
                 orc_delo_linear(d, &E, &pu, &pk);
                 I[k] = E * I[u] + pu * S[u] + pk * S[k];
+            } else if (fs == 2) {
+                double a, b;
+                orc_implicit_euler(d, &a, &b);
+                I[k] = a * I[u] + b * S[k];
             } else {
                 double a, b;
                 orc_trapezoid(d, &a, &b);
@@ -512,6 +532,82 @@ done:
     if (iters) *iters = it;
     if (matvecs) *matvecs = nmv;
     free(r); free(rh); free(p); free(v); free(ph); free(sv); free(sh); free(t);
+    return status;
+}
+
+/*
+ * Conjugate gradient squared (Sonneveld 1989; Sect. 2.2), right-
+ * preconditioned.  Each step squares the BCG residual polynomial with two
+ * products by A and none by A^T:
+ *   rho = (rh, r);  beta = rho / rho_old (first step: u = p = r)
+ *   u = r + beta q;  p = u + beta (q + beta p)
+ *   v = A P^-1 p;  alpha = rho / (rh, v);  q = u - alpha v
+ *   x += alpha P^-1 (u + q);  r -= alpha A P^-1 (u + q).
+ * iters counts full steps (two products each); convergence is tested on the
+ * recursively updated residual after each step, and the returned relres is
+ * recomputed from x.
+ */
+int orc_cgs(const orc_slab *s, const double *b, double *x, const double *dinv,
+            double tol, int maxit, int *iters, int *matvecs, double *relres)
+{
+    int n = 2 * s->ns, it, i, status = 1, nmv = 0;
+    double bnorm = nrm2(n, b), rho_old = 1.0;
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *rh = (double *)malloc(sizeof(double) * n);
+    double *u = (double *)malloc(sizeof(double) * n);
+    double *p = (double *)calloc(n, sizeof(double));
+    double *q = (double *)calloc(n, sizeof(double));
+    double *v = (double *)malloc(sizeof(double) * n);
+    double *ph = (double *)malloc(sizeof(double) * n);
+    double *uq = (double *)malloc(sizeof(double) * n);
+    double *uh = (double *)malloc(sizeof(double) * n);
+    it = 0;
+    if (!r || !rh || !u || !p || !q || !v || !ph || !uq || !uh) { status = -1; goto done; }
+    if (bnorm == 0.0) {
+        for (i = 0; i < n; i++) x[i] = 0.0;
+        if (relres) *relres = 0.0;
+        status = 0;
+        goto done;
+    }
+    residual(s, b, x, r); nmv++;
+    if (nrm2(n, r) / bnorm < tol) { status = 0; goto done_res; }
+    for (i = 0; i < n; i++) rh[i] = r[i];
+    for (it = 1; it <= maxit; it++) {
+        double rho = dot(n, rh, r), alpha, sig;
+        if (rho == 0.0 || !isfinite(rho)) { status = 2; it--; break; }
+        if (it == 1) {
+            for (i = 0; i < n; i++) { u[i] = r[i]; p[i] = u[i]; }
+        } else {
+            double beta = rho / rho_old;
+            for (i = 0; i < n; i++) {
+                u[i] = r[i] + beta * q[i];
+                p[i] = u[i] + beta * (q[i] + beta * p[i]);
+            }
+        }
+        precond(n, dinv, p, ph);
+        orc_apply(s, ph, v); nmv++;
+        sig = dot(n, rh, v);
+        if (sig == 0.0 || !isfinite(sig)) { status = 2; it--; break; }
+        alpha = rho / sig;
+        for (i = 0; i < n; i++) {
+            q[i] = u[i] - alpha * v[i];
+            uq[i] = u[i] + q[i];
+        }
+        precond(n, dinv, uq, uh);
+        for (i = 0; i < n; i++) x[i] += alpha * uh[i];
+        orc_apply(s, uh, v); nmv++;              /* v now holds A P^-1 (u + q) */
+        for (i = 0; i < n; i++) r[i] -= alpha * v[i];
+        if (nrm2(n, r) / bnorm < tol) { status = 0; break; }
+        rho_old = rho;
+    }
+    if (it > maxit) it = maxit;
+    residual(s, b, x, r); nmv++;
+done_res:
+    if (relres) *relres = nrm2(n, r) / bnorm;
+done:
+    if (iters) *iters = it;
+    if (matvecs) *matvecs = nmv;
+    free(r); free(rh); free(u); free(p); free(q); free(v); free(ph); free(uq); free(uh);
     return status;
 }
 

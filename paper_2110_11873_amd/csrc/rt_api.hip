@@ -117,8 +117,11 @@ int validate(const rt_problem *p, const rt_options *o, std::vector<double> &mu_p
     if (p->B)
         for (long long k = 0; k < total; ++k)
             if (!finite(p->B[k])) return fail(RT_EINVAL, idx("B", k) + " is not finite");
-    if (p->formal_solver != RT_FS_DELO_LINEAR && p->formal_solver != RT_FS_TRAPEZOIDAL)
-        return fail(RT_EINVAL, "formal_solver must be RT_FS_DELO_LINEAR or RT_FS_TRAPEZOIDAL");
+    if (p->formal_solver != RT_FS_DELO_LINEAR && p->formal_solver != RT_FS_TRAPEZOIDAL &&
+        p->formal_solver != RT_FS_IMPLICIT_EULER)
+        return fail(RT_EINVAL,
+                    "formal_solver must be RT_FS_DELO_LINEAR, RT_FS_TRAPEZOIDAL or "
+                    "RT_FS_IMPLICIT_EULER");
     if (o) {
         if (o->precision != RT_PREC_FP64 && o->precision != RT_PREC_MIXED)
             return fail(RT_EINVAL, "options.precision must be RT_PREC_FP64 or RT_PREC_MIXED");

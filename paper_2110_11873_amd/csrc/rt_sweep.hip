@@ -44,7 +44,8 @@ namespace rt {
 // c_k = (1 - e^{-d}) - c_u.  Below d = 0.1 the closed forms cancel; their
 // Taylor series sum_{n>=2} (-1)^n (n-1) d^(n-1)/n! and
 // sum_{n>=2} (-1)^n d^(n-1)/n! are evaluated by Horner's rule instead.
-// Trapezoidal (Crank-Nicolson): c_u = c_k = (d/2) / (1 + d/2).
+// Trapezoidal (Crank-Nicolson): c_u = c_k = (d/2) / (1 + d/2).  Implicit Euler
+// (backward difference): c_u = 0, c_k = d / (1 + d).
 // --------------------------------------------------------------------------
 namespace {
 
@@ -77,6 +78,11 @@ __device__ inline void step_coef(int fs, double d, double &cu, double &ck) {
     if (fs == RT_FS_TRAPEZOIDAL) {
         const double h = 0.5 * d;
         cu = ck = h / (1.0 + h);
+        return;
+    }
+    if (fs == RT_FS_IMPLICIT_EULER) {
+        cu = 0.0;
+        ck = d / (1.0 + d);
         return;
     }
     if (d < 0.1) {
@@ -173,6 +179,10 @@ __device__ inline void step_ew(int fs, double d, double &E, double &w) {
         const double h = 0.5 * d;
         E = (1.0 - h) / (1.0 + h);
         w = 1.0 / (1.0 + h);
+        return;
+    }
+    if (fs == RT_FS_IMPLICIT_EULER) {  // c_u = 0: E = w = 1 - c_k
+        E = w = 1.0 / (1.0 + d);
         return;
     }
     double cu, ck;

@@ -34,7 +34,9 @@ SEED_BASE = 211011873
 
 FS_DELO_LINEAR = 0
 FS_TRAPEZOIDAL = 1
-_FS_NAMES = {"delo_linear": FS_DELO_LINEAR, "trapezoidal": FS_TRAPEZOIDAL}
+FS_IMPLICIT_EULER = 2
+_FS_NAMES = {"delo_linear": FS_DELO_LINEAR, "trapezoidal": FS_TRAPEZOIDAL,
+             "implicit_euler": FS_IMPLICIT_EULER}
 
 
 @dataclasses.dataclass

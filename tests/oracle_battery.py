@@ -53,6 +53,19 @@ def chk_trapezoid():
         3.8 < errs[1] / errs[2] < 4.2
 
 
+def chk_implicit_euler():
+    errs = []
+    for n in [41, 81, 161]:
+        tau = np.linspace(0.0, 4.0, n)
+        I = O.ray(tau, 1.0, False, 2.0 + 3.0 * tau, I_entry=5.0, fs=2)
+        ex = (2.0 + 3.0 * tau - 3.0) + 6.0 * np.exp(-tau)
+        errs.append(np.abs(I - ex).max())
+    a, b = O.implicit_euler(0.7)
+    up = O.ray(np.linspace(0.0, 4.0, 41), 1.0, True, np.full(41, 0.8), I_entry=0.8, fs=2)
+    return (abs(a + b - 1) < 1e-15 and 1.85 < errs[0] / errs[1] < 2.15
+            and 1.85 < errs[1] / errs[2] < 2.15 and np.abs(up - 0.8).max() < 1e-14)
+
+
 def chk_linear_source():
     tau = np.logspace(-3, 2, 60)
     a, b, kap = 0.3, 0.7, 0.37
@@ -67,7 +80,7 @@ def chk_linear_source():
 
 
 def chk_dense():
-    for fs in ("delo_linear", "trapezoidal"):
+    for fs in ("delo_linear", "trapezoidal", "implicit_euler"):
         p = W.config1_subgrid(fs)
         d = D.Dense(p)
         v = W.random_vector(p.n_unknowns, 0)
@@ -84,7 +97,7 @@ def chk_dense():
 def chk_solvers_vs_lu():
     p = W.config1_subgrid()
     ref = D.Dense(p).solve()
-    for s in (O.gmres, O.bicgstab, O.richardson):
+    for s in (O.gmres, O.bicgstab, O.richardson, O.cgs):
         x, info = s(p, tol=1e-13, maxit=5000)
         if info[0]["status"] != "converged" or np.abs(x - ref).max() > 1e-10 * np.abs(ref).max():
             return False
@@ -100,8 +113,10 @@ def chk_paper_counts():
     _, g40 = O.gmres(p40, precond=False, restart=0, tol=1e-6, maxit=1000)
     p80 = W.paper_replica(80, scale="integrated", normalize=False)
     _, bi = O.bicgstab(p80, precond=True, tol=1e-6, maxit=1000)
+    _, cg = O.cgs(p80, precond=True, tol=1e-6, maxit=1000)
     return (g[0]["iterations"] == 28 and r[0]["iterations"] + 1 == 67
-            and g40[0]["iterations"] == 48 and 18 <= bi[0]["iterations"] <= 19)
+            and g40[0]["iterations"] == 48 and 18 <= bi[0]["iterations"] <= 19
+            and cg[0]["iterations"] == 26)
 
 
 def chk_special_cases():
@@ -113,8 +128,8 @@ def chk_special_cases():
     return np.abs(x[1::2]).max() == 0.0
 
 
-CHECKS = [chk_moments, chk_delo, chk_trapezoid, chk_linear_source, chk_dense, chk_solvers_vs_lu,
-          chk_paper_counts, chk_special_cases]
+CHECKS = [chk_moments, chk_delo, chk_trapezoid, chk_implicit_euler, chk_linear_source, chk_dense,
+          chk_solvers_vs_lu, chk_paper_counts, chk_special_cases]
 
 
 def run():

@@ -59,7 +59,7 @@ def check_apply(p, h, seeds=(0, 1), tol=MATVEC_TOL):
 
 # ------------------------------------------------------------------ operator
 
-@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal"])
+@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal", "implicit_euler"])
 def test_apply_unit_columns_subgrid(fs):
     p = W.config1_subgrid(fs)
     A = D.Dense(p).A
@@ -71,14 +71,14 @@ def test_apply_unit_columns_subgrid(fs):
             assert np.abs(col - A[:, j]).max() <= 1e-13, (fs, j)
 
 
-@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal"])
+@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal", "implicit_euler"])
 def test_apply_config1(fs):
     p = W.config1(fs)
     with B.setup(p) as h:
         check_apply(p, h, seeds=(0, 1, 2))
 
 
-@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal"])
+@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal", "implicit_euler"])
 def test_apply_config2(fs):
     p = W.config2(fs)
     with B.setup(p) as h:
@@ -200,7 +200,7 @@ def test_rhs_and_diag_batched():
     assert np.abs(d[idx] - ref_d).max() <= 1e-13
 
 
-@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal"])
+@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal", "implicit_euler"])
 def test_diag_and_precond(fs):
     p = W.config1(fs)
     with B.setup(p) as h:
@@ -239,7 +239,7 @@ def test_solvers_config1_match_LU(kind):
     assert np.abs(x - ref).max() <= 1e-8 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal"])
+@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal", "implicit_euler"])
 @pytest.mark.parametrize("kind", ["gmres", "bicgstab"])
 def test_solvers_config2(fs, kind):
     p = W.config2(fs)

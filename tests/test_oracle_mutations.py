@@ -47,6 +47,8 @@ MUTATIONS = [
     ("kappa_drops_opacity", "double kappa = s->opac[p] / fabs(s->mu[m]);",
      "double kappa = 1.0 / fabs(s->mu[m]);"),
     ("trap_half_step", "double h = 0.5 * d;", "double h = d;"),
+    ("euler_a", "*a = 1.0 / (1.0 + d);", "*a = 1.0 / (1.0 + 0.5 * d);"),
+    ("euler_uses_upwind_source", "I[k] = a * I[u] + b * S[k];", "I[k] = a * I[u] + b * S[u];"),
     ("trap_beta", "*b = h / (1.0 + h);", "*b = h / (1.0 - h);"),
     ("rhs_drops_thermal", "b[2 * k] = xi * J0[k] + s->eps * s->B[k];", "b[2 * k] = xi * J0[k];"),
     ("rhs_inflow_wrong_side", "upward ? s->Ibot : 0.0", "upward ? 0.0 : s->Ibot"),
@@ -62,6 +64,9 @@ MUTATIONS = [
     ("bicgstab_beta", "beta = (rho / rho_old) * (alpha / omega);", "beta = (rho / rho_old) * (omega / alpha);"),
     ("bicgstab_omega", "omega = dot(n, t, sv) / tt;", "omega = dot(n, sv, sv) / tt;"),
     ("bicgstab_x_update", "x[i] += alpha * ph[i] + omega * sh[i];", "x[i] += alpha * p[i] + omega * sh[i];"),
+    ("cgs_p_update", "p[i] = u[i] + beta * (q[i] + beta * p[i]);", "p[i] = u[i] + beta * (q[i] + p[i]);"),
+    ("cgs_q_sign", "q[i] = u[i] - alpha * v[i];", "q[i] = u[i] + alpha * v[i];"),
+    ("cgs_x_unpreconditioned", "for (i = 0; i < n; i++) x[i] += alpha * uh[i];", "for (i = 0; i < n; i++) x[i] += alpha * uq[i];"),
     ("richardson_sign", "for (i = 0; i < n; i++) x[i] += z[i];\n    }", "for (i = 0; i < n; i++) x[i] -= z[i];\n    }"),
 ]
 

@@ -117,6 +117,27 @@ def test_trapezoid_is_second_order_and_preserves_constants():
     assert all(3.8 < r < 4.2 for r in rates), rates
 
 
+def test_implicit_euler_is_first_order_and_L_stable():
+    """Implicit Euler (Sect. 4.1) on dI/dt = S - I: constants preserved
+    (a + b = 1), the step damps every mode (0 < a < 1, a -> 0 as d grows: L-
+    stable, unlike the trapezoid), and the global error against the exact
+    solution for S = 2 + 3 t is O(h): it halves when the step halves."""
+    for d in [1e-8, 0.3, 2.0, 1e3, 1e8]:
+        a, b = O.implicit_euler(d)
+        assert abs(a + b - 1.0) < 1e-15
+        assert 0.0 < a < 1.0 and b > 0.0
+    assert O.implicit_euler(1e8)[0] < 1e-7
+    errs = []
+    for n in [41, 81, 161, 321]:
+        tau = np.linspace(0.0, 4.0, n)
+        S = 2.0 + 3.0 * tau
+        I = O.ray(tau, 1.0, False, S, I_entry=5.0, fs=2)
+        exact = (2.0 + 3.0 * tau - 3.0) + (5.0 - (2.0 - 3.0)) * np.exp(-tau)
+        errs.append(np.abs(I - exact).max())
+    rates = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(1.85 < r < 2.15 for r in rates), rates
+
+
 # --------------------------------------------------------------------------
 # Formal solution along a ray (eqs. RTE_delo1/2, boundary conditions Sect. 3.1)
 # --------------------------------------------------------------------------
@@ -140,7 +161,7 @@ def test_delo_linear_exact_for_linear_source(kappa):
     assert np.abs(dn - ex_dn).max() <= 1e-12 * np.abs(ex_dn).max()
 
 
-@pytest.mark.parametrize("fs", [0, 1])
+@pytest.mark.parametrize("fs", [0, 1, 2])
 def test_constant_source_with_matching_inflow_is_stationary(fs):
     tau = np.logspace(-4, 8, 50)
     S = np.full(50, 0.8)
@@ -148,7 +169,7 @@ def test_constant_source_with_matching_inflow_is_stationary(fs):
     assert np.abs(I - 0.8).max() < 1e-14
 
 
-@pytest.mark.parametrize("fs", [0, 1])
+@pytest.mark.parametrize("fs", [0, 1, 2])
 def test_point_source_has_exact_upwind_zeros(fs):
     """A point-like source at z_j leaves the intensity zero on the upwind side
     of the ray and decaying on the downwind side (Sect. 4.4 run-time remarks;
@@ -162,7 +183,7 @@ def test_point_source_has_exact_upwind_zeros(fs):
     up = O.ray(tau, 1.0, True, S, fs=fs)
     assert np.all(dn[:j] == 0.0) and dn[j] > 0
     assert np.all(up[j + 1:] == 0.0) and up[j] > 0
-    if fs == 0:   # DELO: nonnegative, decaying beyond the interval next to the source
+    if fs in (0, 2):   # DELO, implicit Euler: nonnegative, decaying past the source's interval
         assert np.all(np.diff(dn[j + 1:]) <= 0) and np.all(dn[j:] >= 0)
         assert np.all(np.diff(up[:j]) >= 0) and np.all(up[:j + 1] >= 0)
 
@@ -171,9 +192,9 @@ def test_point_source_has_exact_upwind_zeros(fs):
 # The operator against an independently assembled dense route (Sect. 3.2-3.3)
 # --------------------------------------------------------------------------
 
-@pytest.fixture(scope="module", params=[0, 1], ids=["delo", "trap"])
+@pytest.fixture(scope="module", params=[0, 1, 2], ids=["delo", "trap", "euler"])
 def sub(request):
-    p = W.config1_subgrid(["delo_linear", "trapezoidal"][request.param])
+    p = W.config1_subgrid(["delo_linear", "trapezoidal", "implicit_euler"][request.param])
     return p, D.Dense(p)
 
 
@@ -202,13 +223,14 @@ def test_I_formulation_gives_same_sigma(sub):
 def test_solvers_agree_with_LU(sub):
     p, d = sub
     ref = d.solve()
-    for solve in (O.gmres, O.bicgstab):
+    for solve in (O.gmres, O.bicgstab, O.cgs):
         x, info = solve(p, tol=1e-13)
         assert info[0]["status"] == "converged", (solve, info)
         assert np.abs(x - ref).max() <= 1e-11 * np.abs(ref).max(), solve
     # Jacobi-Richardson converges iff the spectral radius of Id - D^-1 A is < 1:
-    # true for DELO-linear (M-matrix), false for the trapezoidal solver, whose
-    # step amplification tends to -1 on optically thick intervals.
+    # true for DELO-linear and implicit Euler (nonnegative steps), false for
+    # the trapezoidal solver, whose step amplification tends to -1 on
+    # optically thick intervals.
     rho = np.abs(np.linalg.eigvals(np.eye(d.A.shape[0]) - d.A / np.diag(d.A)[:, None])).max()
     x, info = O.richardson(p, tol=1e-13, maxit=20000)
     if rho < 1.0:
@@ -216,7 +238,7 @@ def test_solvers_agree_with_LU(sub):
         assert np.abs(x - ref).max() <= 1e-11 * np.abs(ref).max()
     else:
         assert info[0]["status"] in ("breakdown", "maxit")
-    assert (rho < 1.0) == (p.formal_solver == 0)
+    assert (rho < 1.0) == (p.formal_solver != 1)
 
 
 def test_unrestarted_gmres_terminates_within_N_steps(sub):
@@ -235,7 +257,7 @@ def test_A_is_positive_definite_nonsymmetric(sub):
     p, d = sub
     A = d.A
     assert np.abs(A - A.T).max() > 1e-3
-    if p.formal_solver == 0:
+    if p.formal_solver in (0, 2):
         assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
     assert np.linalg.eigvals(A).real.min() > 0
 
@@ -367,3 +389,21 @@ def test_paper_jacobi_bicgstab_counts(ns, expected):
     p = _replica(ns)
     _, info = O.bicgstab(p, precond=True, tol=1e-6, maxit=1000)
     assert expected <= info[0]["iterations"] <= expected + 1
+
+
+@pytest.mark.parametrize("ns,expected", list(zip(_G["jacobi_cgs"]["ns"],
+                                                _G["jacobi_cgs"]["iterations"])))
+def test_paper_jacobi_cgs_counts(ns, expected):
+    """Jacobi-CGS (Sect. 2.2, Table tab:jacobi): the printed counts exactly."""
+    p = _replica(ns)
+    _, info = O.cgs(p, precond=True, tol=1e-6, maxit=1000)
+    assert info[0]["status"] == "converged"
+    assert info[0]["iterations"] == expected
+
+
+def test_paper_unpreconditioned_cgs_count_small_grid():
+    """Table tab:no_prec, CGS at N_s = 20 (the larger grids' entries depend on
+    rounding and are not pinned)."""
+    g = _G["no_preconditioner_cgs_ns20"]
+    _, info = O.cgs(_replica(g["ns"]), precond=False, tol=1e-6, maxit=1000)
+    assert info[0]["iterations"] == g["iterations"]
