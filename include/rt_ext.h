@@ -23,6 +23,19 @@ extern "C" {
 int rt_apply_op_fp32(rt_handle *h, const double *sigma_in, double *sigma_out, void *stream);
 
 /*
+ * Solve A x = b with the conjugate gradient squared method (Sect. 2.2;
+ * Sonneveld), right-preconditioned by Jacobi: two products by A per step, none
+ * by A^T.  Same contract as rt_solve_gmres (b NULL means the handle's own
+ * right-hand side; x in: initial guess, out: solution; info host array of
+ * n_atm entries or NULL).  iterations counts full steps; convergence is tested
+ * on the recursively updated residual and relres is recomputed from x at the
+ * end.  rho = 0, (r0, A P^-1 p) = 0 or a non-finite residual returns
+ * RT_EBREAKDOWN for that slab with x at the last iterate.  Synchronizes the
+ * stream before returning.
+ */
+int rt_solve_cgs(rt_handle *h, const double *b, double *x, rt_solve_info *info, void *stream);
+
+/*
  * Describe the sweep plan: chunk length L, number of sweep workgroups, number
  * of stored coefficient pairs (tiles, including padding) and of ray-interval
  * pairs sum_slabs (ns - 1) (n_mu / 2) n_nu.  Any output pointer may be NULL.

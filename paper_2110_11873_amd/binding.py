@@ -28,7 +28,8 @@ STATUS_NAMES = {RT_OK: "converged", RT_ENOCONV: "maxit", RT_EBREAKDOWN: "breakdo
 # every function the headers declare
 EXPORTS = ["rt_default_options", "rt_setup", "rt_destroy", "rt_num_unknowns", "rt_apply_op",
            "rt_precond_jacobi", "rt_get_rhs", "rt_get_jacobi_diag", "rt_solve_gmres",
-           "rt_solve_bicgstab", "rt_solve_richardson", "rt_last_error", "rt_apply_op_fp32",
+           "rt_solve_bicgstab", "rt_solve_richardson", "rt_solve_cgs", "rt_last_error",
+           "rt_apply_op_fp32",
            "rt_plan_info", "rt_sweep_config", "rt_validate"]
 
 
@@ -86,7 +87,7 @@ def lib():
             getattr(L, f).argtypes = [vp, vp, vp, vp]
         for f in ("rt_get_rhs", "rt_get_jacobi_diag"):
             getattr(L, f).argtypes = [vp, vp, vp]
-        for f in ("rt_solve_gmres", "rt_solve_bicgstab", "rt_solve_richardson"):
+        for f in ("rt_solve_gmres", "rt_solve_bicgstab", "rt_solve_richardson", "rt_solve_cgs"):
             getattr(L, f).argtypes = [vp, vp, vp, C.POINTER(rt_solve_info), vp]
         L.rt_last_error.argtypes = []
         L.rt_last_error.restype = C.c_char_p
@@ -262,6 +263,9 @@ class Handle:
 
     def solve_richardson(self, x, b=None, stream=None):
         return self._solve("rt_solve_richardson", b, x, stream)
+
+    def solve_cgs(self, x, b=None, stream=None):
+        return self._solve("rt_solve_cgs", b, x, stream)
 
 
 def setup(prob, options: Optional[rt_options] = None, autotune: bool = False, **kw) -> Handle:

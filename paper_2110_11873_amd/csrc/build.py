@@ -52,12 +52,14 @@ def build(verbose: bool = False) -> str:
         for _, msg in results:
             if msg:
                 print(msg)
+    tmp = OUT + f".tmp{os.getpid()}"
+    rc, msg = (1, "") if failed else _run(
+        [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+    for o in objs:
+        if os.path.exists(o):
+            os.remove(o)
     if failed:
         raise RuntimeError("hipcc failed building librt.so")
-    tmp = OUT + f".tmp{os.getpid()}"
-    rc, msg = _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
-    for o in objs:
-        os.remove(o)
     if rc != 0:
         sys.stderr.write(msg + "\n")
         raise RuntimeError("linking librt.so failed")

@@ -267,7 +267,7 @@ int ensure_workspace(rt_handle *h) {
         if ((rc = dalloc(&h->d_cs, (size_t)h->n_atm * mm)) != RT_OK) return rc;
         if ((rc = dalloc(&h->d_sn, (size_t)h->n_atm * mm)) != RT_OK) return rc;
         if ((rc = dalloc(&h->d_g, (size_t)h->n_atm * (mm + 1))) != RT_OK) return rc;
-        double **vecs[] = {&h->d_w, &h->d_r, &h->d_rh, &h->d_p, &h->d_v, &h->d_s, &h->d_t};
+        double **vecs[] = {&h->d_w, &h->d_r, &h->d_rh, &h->d_p, &h->d_v, &h->d_s, &h->d_t, &h->d_cq};
         for (double **v : vecs)
             if ((rc = dalloc(v, (size_t)N)) != RT_OK) return rc;
         if ((rc = dalloc(&h->d_state, (size_t)2 * h->n_atm)) != RT_OK) return rc;
@@ -318,7 +318,7 @@ void rt_destroy(rt_handle *h) {
                     h->d_coef32, h->d_partial, h->d_diag,  h->d_dinv,   h->d_b,
                     h->d_V,     h->d_H,     h->d_cs,      h->d_sn,      h->d_g,      h->d_w,
                     h->d_r,     h->d_rh,    h->d_p,       h->d_v,       h->d_s,      h->d_t,
-                    h->d_xd,    h->d_state, h->d_active,  h->d_cycle,   h->d_count};
+                    h->d_cq,    h->d_state, h->d_active,  h->d_cycle,   h->d_count};
     clear_graphs(h);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
     for (hipEvent_t e : h->gev)
@@ -578,6 +578,12 @@ int rt_solve_richardson(rt_handle *h, const double *b, double *x, rt_solve_info 
     if (!h || !x) return fail(RT_EINVAL, "NULL handle or x");
     if (!aligned16(x) || (b && !aligned16(b))) return fail(RT_EINVAL, "vectors must be 16-byte aligned");
     return run_solver(h, 2, b, x, info, (hipStream_t)stream);
+}
+
+int rt_solve_cgs(rt_handle *h, const double *b, double *x, rt_solve_info *info, void *stream) {
+    if (!h || !x) return fail(RT_EINVAL, "NULL handle or x");
+    if (!aligned16(x) || (b && !aligned16(b))) return fail(RT_EINVAL, "vectors must be 16-byte aligned");
+    return run_solver(h, 3, b, x, info, (hipStream_t)stream);
 }
 
 // Sweep-plan introspection for tests and benchmarks (not in the public header).

@@ -209,7 +209,7 @@ struct rt_handle {
     double *d_w = nullptr;      // operator output
     double *d_r = nullptr, *d_rh = nullptr, *d_p = nullptr, *d_v = nullptr, *d_s = nullptr,
            *d_t = nullptr;      // BiCGSTAB / refinement vectors
-    double *d_xd = nullptr;     // refinement correction
+    double *d_cq = nullptr;     // CGS
     rt::KState *d_state = nullptr;
     int *d_active = nullptr;    // per slab: still iterating
     int *d_cycle = nullptr;     // per slab: GMRES cycle still running

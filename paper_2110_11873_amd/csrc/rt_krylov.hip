@@ -118,6 +118,7 @@ struct VecArgs {
     double *x;
     const double *dinv;
     double *r, *rh, *p, *v, *s, *t;  // BiCGSTAB / refinement vectors
+    double *q, *u;                   // CGS (u shares the operator output's storage)
     KState *st;
     int *active;
     int *cycle;
@@ -754,6 +755,163 @@ __global__ void bi_full_kernel(VecArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------- CGS
+// Conjugate gradient squared (Sonneveld; Sect. 2.2), right-preconditioned.
+// Vectors: r, r^ (rh), u (the operator output's storage, free after the
+// start), p, q, v = A P^-1 p, s = u + q, t = A P^-1 s.
+// r = b - A x (A x in a.w), r^ = r.
+__global__ void cg_start_kernel(VecArgs a) {
+    __shared__ double red[2 * NW];
+    const int atm = blockIdx.x;
+    if (!a.active[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    double rr = 0.0, bb = 0.0;
+    for (int l = threadIdx.x; l < n; l += NT) {
+        const double bl = a.b[base + l];
+        const double rl = bl - a.w[base + l];
+        a.r[base + l] = rl;
+        a.rh[base + l] = rl;
+        rr += rl * rl;
+        bb += bl * bl;
+    }
+    block_sum2(rr, bb, red);
+    if (threadIdx.x == 0) {
+        KState &S = a.st[atm];
+        S.bnorm = sqrt(bb);
+        S.matvecs += 1;
+        S.rho_old = 1.0;
+        S.iters = 0;
+        const double rn = sqrt(rr);
+        if (S.bnorm == 0.0) {
+            S.status = RT_OK;
+            S.relres = 0.0;
+            a.active[atm] = 0;
+        } else if (rn / S.bnorm < a.tol) {
+            S.status = RT_OK;
+            S.relres = rn / S.bnorm;
+            a.active[atm] = 0;
+        }
+    }
+    if (bb == 0.0)  // every thread holds the same block sum
+        for (int l = threadIdx.x; l < n; l += NT) a.x[base + l] = 0.0;
+}
+
+// rho = (r^, r); first step u = p = r, else beta = rho / rho_old,
+// u = r + beta q, p = u + beta (q + beta p).
+__global__ void cg_dir_kernel(VecArgs a) {
+    __shared__ double red[2 * NW];
+    __shared__ int s_ok;
+    const int atm = blockIdx.x;
+    if (!a.active[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    KState &S = a.st[atm];
+    double rho = 0.0;
+    for (int l = threadIdx.x; l < n; l += NT) rho += a.rh[base + l] * a.r[base + l];
+    rho = block_sum(rho, red);
+    if (threadIdx.x == 0) {
+        s_ok = (rho != 0.0) && isfinite(rho) && (S.iters < a.maxit);
+        if (!s_ok) {
+            S.status = (S.iters >= a.maxit) ? RT_ENOCONV : RT_EBREAKDOWN;
+            a.active[atm] = 0;
+        } else {
+            S.rho = rho;
+        }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    double *u = a.u;
+    if (S.iters == 0) {
+        for (int l = threadIdx.x; l < n; l += NT) u[base + l] = a.p[base + l] = a.r[base + l];
+    } else {
+        const double beta = rho / S.rho_old;
+        for (int l = threadIdx.x; l < n; l += NT) {
+            const double ql = a.q[base + l];
+            const double ul = a.r[base + l] + beta * ql;
+            u[base + l] = ul;
+            a.p[base + l] = ul + beta * (ql + beta * a.p[base + l]);
+        }
+    }
+}
+
+// v = A P^-1 p is in a.v.  alpha = rho / (r^, v); q = u - alpha v;
+// s = u + q; x += alpha P^-1 s.
+__global__ void cg_half_kernel(VecArgs a) {
+    __shared__ double red[2 * NW];
+    __shared__ int s_ok;
+    __shared__ double s_alpha;
+    const int atm = blockIdx.x;
+    if (!a.active[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    KState &S = a.st[atm];
+    double sig = 0.0;
+    for (int l = threadIdx.x; l < n; l += NT) sig += a.rh[base + l] * a.v[base + l];
+    sig = block_sum(sig, red);
+    if (threadIdx.x == 0) {
+        S.matvecs += 1;
+        s_ok = (sig != 0.0) && isfinite(sig);
+        if (!s_ok) {
+            S.status = RT_EBREAKDOWN;
+            a.active[atm] = 0;
+        } else {
+            S.alpha = S.rho / sig;
+            s_alpha = S.alpha;
+        }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    const double alpha = s_alpha;
+    const double *u = a.u;
+    for (int l = threadIdx.x; l < n; l += NT) {
+        const double ul = u[base + l];
+        const double ql = ul - alpha * a.v[base + l];
+        a.q[base + l] = ql;
+        const double sl = ul + ql;
+        a.s[base + l] = sl;
+        a.x[base + l] += alpha * a.dinv[base + l] * sl;
+    }
+}
+
+// t = A P^-1 (u + q) is in a.t.  r -= alpha t; test.
+__global__ void cg_full_kernel(VecArgs a) {
+    __shared__ double red[2 * NW];
+    const int atm = blockIdx.x;
+    if (!a.active[atm]) return;
+    const AtmDesc at = a.atm[atm];
+    const int n = 2 * at.ns;
+    const long long base = 2LL * at.doff;
+    KState &S = a.st[atm];
+    const double alpha = S.alpha;  // written by an earlier kernel
+    double rr = 0.0;
+    for (int l = threadIdx.x; l < n; l += NT) {
+        const double rl = a.r[base + l] - alpha * a.t[base + l];
+        a.r[base + l] = rl;
+        rr += rl * rl;
+    }
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) {
+        S.matvecs += 1;
+        S.iters += 1;
+        const double rel = sqrt(rr) / S.bnorm;
+        if (rel < a.tol) {
+            S.status = RT_OK;
+            a.active[atm] = 0;
+        } else if (!isfinite(rel)) {
+            S.status = RT_EBREAKDOWN;
+            a.active[atm] = 0;
+        } else if (S.iters >= a.maxit) {
+            S.status = RT_ENOCONV;
+            a.active[atm] = 0;
+        }
+        S.rho_old = S.rho;
+    }
+}
+
 // --------------------------------------------------------------- Richardson
 // One step of x <- x + P^-1 (b - A x) (eq. rich_iteration), A x in a.w.
 __global__ void ri_step_kernel(VecArgs a, int first) {
@@ -1055,6 +1213,8 @@ struct Driver {
         a.v = h->d_v;
         a.s = h->d_s;
         a.t = h->d_t;
+        a.q = h->d_cq;
+        a.u = h->d_w;
         a.st = st;
         a.active = active;
         a.cycle = h->d_cycle;
@@ -1123,6 +1283,40 @@ struct Driver {
             ok(hipGetLastError());
         };
         const std::vector<unsigned long long> key = {1,         bits(b),   bits(x),
+                                                     bits(st),  bits(tol), (unsigned long long)maxit,
+                                                     (unsigned long long)check};
+        while (err == hipSuccess) {
+            if (count(h->d_active) == 0) break;
+            if (h->opt.graphs) {
+                graph(key, [&]() {
+                    for (int i = 0; i < check; ++i) step();
+                });
+            } else {
+                for (int i = 0; i < check; ++i) step();
+            }
+        }
+        // explicit final residual of every slab
+        sweep(x, nullptr, h->d_w, nullptr, false);
+        hipLaunchKernelGGL(relres_kernel, dim3(nb), dim3(NT), 0, s, a);
+        ok(hipGetLastError());
+    }
+
+    void cgs(const double *b, double *x, KState *st, double tol, int maxit) {
+        const int nb = h->n_atm;
+        VecArgs a = args(b, x, st, h->d_active, tol, maxit);
+        const int check = std::max(1, h->opt.check_every);
+        sweep(x, nullptr, h->d_w, h->d_active, false);
+        hipLaunchKernelGGL(cg_start_kernel, dim3(nb), dim3(NT), 0, s, a);
+        ok(hipGetLastError());
+        auto step = [&]() {
+            hipLaunchKernelGGL(cg_dir_kernel, dim3(nb), dim3(NT), 0, s, a);
+            sweep(h->d_p, h->d_dinv, h->d_v, h->d_active, false);
+            hipLaunchKernelGGL(cg_half_kernel, dim3(nb), dim3(NT), 0, s, a);
+            sweep(h->d_s, h->d_dinv, h->d_t, h->d_active, false);
+            hipLaunchKernelGGL(cg_full_kernel, dim3(nb), dim3(NT), 0, s, a);
+            ok(hipGetLastError());
+        };
+        const std::vector<unsigned long long> key = {3,         bits(b),   bits(x),
                                                      bits(st),  bits(tol), (unsigned long long)maxit,
                                                      (unsigned long long)check};
         while (err == hipSuccess) {
@@ -1212,6 +1406,8 @@ int run_solver(rt_handle *h, int kind, const double *b, double *x, rt_solve_info
             d.gmres(b, x, st, h->opt.rtol, h->opt.maxit, false, false);
         else if (kind == 1)
             d.bicgstab(b, x, st, h->opt.rtol, h->opt.maxit);
+        else if (kind == 3)
+            d.cgs(b, x, st, h->opt.rtol, h->opt.maxit);
         else
             d.richardson(b, x, st, h->opt.rtol, h->opt.maxit);
     }

@@ -228,7 +228,7 @@ def _solve(h, kind, p, x0=None, b=None):
     return rc, info, host(x)
 
 
-@pytest.mark.parametrize("kind", ["gmres", "bicgstab", "richardson"])
+@pytest.mark.parametrize("kind", ["gmres", "bicgstab", "richardson", "cgs"])
 def test_solvers_config1_match_LU(kind):
     p = W.config1()
     ref = np.linalg.solve(O.assemble(p), O.rhs(p))
@@ -280,6 +280,7 @@ def test_gmres_arnoldi_paths(restart):
 
 
 @pytest.mark.parametrize("kind,mixed", [("gmres", False), ("gmres", True), ("bicgstab", False),
+                                        ("cgs", False),
                                         ("richardson", False)])
 def test_graph_replays_match_eager_launches(kind, mixed):
     """Solver segments captured in HIP graphs and replayed give the same
@@ -369,6 +370,36 @@ def test_paper_richardson_counts_on_gpu():
         with B.setup(p, rtol=1e-6, maxit=100000, check_every=1) as h:
             rc, info, x = _solve(h, "richardson", p)
         assert info[0].iterations + 1 == printed, (ns, info)
+
+
+def test_paper_cgs_counts_on_gpu():
+    """The GPU's Jacobi-CGS against the paper's printed counts (tab:jacobi,
+    CGS row), which the oracle reproduces exactly; the GPU's rounding may
+    move the last step by one."""
+    for ns, printed in [(20, 10), (40, 16), (60, 22), (80, 26)]:
+        p = W.paper_replica(ns, scale="integrated", normalize=False)
+        with B.setup(p, rtol=1e-6, maxit=1000, check_every=1) as h:
+            rc, info, x = _solve(h, "cgs", p)
+        assert info[0].status == "converged"
+        assert abs(info[0].iterations - printed) <= 1, (ns, info)
+        assert oracle_relres(p, x).max() < 1e-6
+
+
+@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal", "implicit_euler"])
+def test_cgs_config1_against_oracle(fs):
+    """Jacobi-CGS on the 40-point slab: the oracle's residual below rtol and an
+    iteration count near the oracle's (CGS amplifies rounding, Sect. 2.2; on
+    the optically much thicker 200-point slab neither the oracle's CGS nor
+    this one converges, the method's known instability)."""
+    p = W.config1(fs)
+    with B.setup(p, rtol=1e-10, maxit=2000) as h:
+        rc, info, x = _solve(h, "cgs", p)
+    _, oi = O.cgs(p, tol=1e-10, maxit=2000)
+    assert oi[0]["status"] == "converged"
+    assert info[0].status == "converged", info
+    assert oracle_relres(p, x).max() < 1e-10
+    it = oi[0]["iterations"]
+    assert abs(info[0].iterations - it) <= max(3, it // 4), (info[0].iterations, it)
 
 
 def test_edge_cases_zero_rhs_maxit_and_exact_start():
