@@ -79,7 +79,8 @@ def lib():
             L.orc_rhs.argtypes = [P, D]
             L.orc_diag.argtypes = [P, C.c_int, I, D]
             L.orc_assemble.argtypes = [P, D]
-            L.orc_gmres.argtypes = [P, D, D, D, C.c_int, C.c_double, C.c_int, I, I, D, D, C.c_int]
+            L.orc_gmres.argtypes = [P, D, D, D, C.c_int, C.c_double, C.c_int, I, I, D, D, C.c_int,
+                                    C.c_int]
             L.orc_bicgstab.argtypes = [P, D, D, D, C.c_double, C.c_int, I, I, D]
             L.orc_richardson.argtypes = [P, D, D, D, C.c_double, C.c_int, I, I, D]
             L.orc_cgs.argtypes = [P, D, D, D, C.c_double, C.c_int, I, I, D]
@@ -232,7 +233,7 @@ def assemble(prob, i=0):
 # solvers (per slab)
 # ----------------------------------------------------------------------------
 
-def _solve(kind, prob, b, x0, dinv, tol, maxit, restart=30, hist_len=0):
+def _solve(kind, prob, b, x0, dinv, tol, maxit, restart=30, hist_len=0, left=False):
     n = prob.n_unknowns
     b = np.ascontiguousarray(b if b is not None else rhs(prob), dtype=np.float64)
     x = np.array(x0, dtype=np.float64, copy=True)
@@ -249,7 +250,7 @@ def _solve(kind, prob, b, x0, dinv, tol, maxit, restart=30, hist_len=0):
             h = np.zeros(max(hist_len, 1))
             st = lib().orc_gmres(v.ref, _dp(bs), _dp(xs), dptr, int(restart), float(tol),
                                  int(maxit), C.byref(it), C.byref(mv), C.byref(rr), _dp(h),
-                                 int(hist_len))
+                                 int(hist_len), int(bool(left)))
             hists.append(h[:min(hist_len, it.value + 1)] if hist_len else None)
         elif kind == "bicgstab":
             st = lib().orc_bicgstab(v.ref, _dp(bs), _dp(xs), dptr, float(tol), int(maxit),
@@ -276,12 +277,16 @@ def jacobi_inverse(prob):
 
 
 def gmres(prob, b=None, x0=None, precond=True, tol=1e-10, maxit=10000, restart=30,
-          dinv=None, hist_len=0):
+          dinv=None, hist_len=0, left=False):
+    """GMRES(restart) of Sect. 2.1, right-preconditioned by default (minimizes
+    and tests the true residual).  left=True preconditions from the left and
+    minimizes and tests the preconditioned residual ||P^-1 (b - A x)||."""
     if x0 is None:
         x0 = _x0(prob)
     if precond and dinv is None:
         dinv = jacobi_inverse(prob)
-    return _solve("gmres", prob, b, x0, dinv if precond else None, tol, maxit, restart, hist_len)
+    return _solve("gmres", prob, b, x0, dinv if precond else None, tol, maxit, restart, hist_len,
+                  left)
 
 
 def bicgstab(prob, b=None, x0=None, precond=True, tol=1e-10, maxit=10000, dinv=None):

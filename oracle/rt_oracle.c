@@ -371,15 +371,19 @@ static void residual(const orc_slab *s, const double *b, const double *x, double
  * is recomputed explicitly and the method restarts from x.
  * restart <= 0 means no restart (cycle length = maxit).
  * iters counts Arnoldi steps; matvecs counts every application of A.
+ * left != 0 selects left preconditioning instead: the basis spans the Krylov
+ * space of P^-1 A, x = x0 + V y, and both the minimized quantity and the
+ * stopping test use the preconditioned residual ||P^-1 (b - A x)|| relative
+ * to ||P^-1 b||.  Without a preconditioner the two variants coincide.
  */
 int orc_gmres(const orc_slab *s, const double *b, double *x, const double *dinv,
               int restart, double tol, int maxit, int *iters, int *matvecs,
-              double *relres, double *hist, int hist_len)
+              double *relres, double *hist, int hist_len, int left)
 {
     int n = 2 * s->ns;
     int m = (restart <= 0 || restart > maxit) ? maxit : restart;
     int total = 0, nmv = 0, status = 1, i, j, jj;
-    double bnorm = nrm2(n, b), beta;
+    double bnorm, beta;
     double *V = (double *)malloc(sizeof(double) * (size_t)n * (m + 1));
     double *H = (double *)calloc((size_t)(m + 1) * m, sizeof(double));
     double *cs = (double *)malloc(sizeof(double) * m);
@@ -391,6 +395,13 @@ int orc_gmres(const orc_slab *s, const double *b, double *x, const double *dinv,
     double *w = (double *)malloc(sizeof(double) * n);
     if (!V || !H || !cs || !sn || !g || !y || !r || !z || !w) { status = -1; goto done; }
 
+    left = left && dinv;
+    if (left) {
+        precond(n, dinv, b, z);
+        bnorm = nrm2(n, z);
+    } else {
+        bnorm = nrm2(n, b);
+    }
     if (bnorm == 0.0) {
         for (i = 0; i < n; i++) x[i] = 0.0;
         if (relres) *relres = 0.0;
@@ -398,6 +409,7 @@ int orc_gmres(const orc_slab *s, const double *b, double *x, const double *dinv,
         goto done;
     }
     residual(s, b, x, r); nmv++;
+    if (left) { precond(n, dinv, r, z); memcpy(r, z, sizeof(double) * n); }
     beta = nrm2(n, r);
     if (hist && hist_len > 0) hist[0] = beta / bnorm;
     if (beta / bnorm < tol) { status = 0; goto done_res; }
@@ -410,8 +422,13 @@ int orc_gmres(const orc_slab *s, const double *b, double *x, const double *dinv,
         jj = 0;
         for (j = 0; j < m && total < maxit; j++) {
             double hnext, resid, tmp, den;
-            precond(n, dinv, V + (size_t)j * n, z);
-            orc_apply(s, z, w); nmv++;
+            if (left) {
+                orc_apply(s, V + (size_t)j * n, z); nmv++;
+                precond(n, dinv, z, w);
+            } else {
+                precond(n, dinv, V + (size_t)j * n, z);
+                orc_apply(s, z, w); nmv++;
+            }
             total++;
             for (i = 0; i <= j; i++) {     /* modified Gram-Schmidt */
                 int l;
@@ -441,7 +458,7 @@ int orc_gmres(const orc_slab *s, const double *b, double *x, const double *dinv,
             }
             if (resid / bnorm < tol || hnext == 0.0) break;
         }
-        /* back substitution H y = g, then x += P^-1 V y */
+        /* back substitution H y = g, then x += P^-1 V y (left: x += V y) */
         for (i = jj - 1; i >= 0; i--) {
             double sum = g[i];
             int l;
@@ -451,9 +468,11 @@ int orc_gmres(const orc_slab *s, const double *b, double *x, const double *dinv,
         for (i = 0; i < n; i++) w[i] = 0.0;
         for (j = 0; j < jj; j++)
             for (i = 0; i < n; i++) w[i] += y[j] * V[(size_t)j * n + i];
-        precond(n, dinv, w, z);
+        if (left) memcpy(z, w, sizeof(double) * n);
+        else precond(n, dinv, w, z);
         for (i = 0; i < n; i++) x[i] += z[i];
         residual(s, b, x, r); nmv++;
+        if (left) { precond(n, dinv, r, z); memcpy(r, z, sizeof(double) * n); }
         beta = nrm2(n, r);
         if (beta / bnorm < tol) { status = 0; break; }
         if (beta == 0.0) { status = 0; break; }

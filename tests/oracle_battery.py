@@ -101,8 +101,11 @@ def chk_solvers_vs_lu():
         x, info = s(p, tol=1e-13, maxit=5000)
         if info[0]["status"] != "converged" or np.abs(x - ref).max() > 1e-10 * np.abs(ref).max():
             return False
-    x, info = O.gmres(p, tol=1e-13, restart=4, maxit=5000)
-    return info[0]["status"] == "converged" and np.abs(x - ref).max() < 1e-10 * np.abs(ref).max()
+    for kw in (dict(restart=4), dict(restart=4, left=True)):
+        x, info = O.gmres(p, tol=1e-13, maxit=5000, **kw)
+        if info[0]["status"] != "converged" or np.abs(x - ref).max() > 1e-10 * np.abs(ref).max():
+            return False
+    return True
 
 
 def chk_paper_counts():
@@ -114,9 +117,12 @@ def chk_paper_counts():
     p80 = W.paper_replica(80, scale="integrated", normalize=False)
     _, bi = O.bicgstab(p80, precond=True, tol=1e-6, maxit=1000)
     _, cg = O.cgs(p80, precond=True, tol=1e-6, maxit=1000)
+    _, gl = O.gmres(p80, precond=True, restart=0, tol=1e-6, maxit=1000, left=True)
+    _, gl40 = O.gmres(p40, precond=True, restart=0, tol=1e-6, maxit=1000, left=True)
     return (g[0]["iterations"] == 28 and r[0]["iterations"] + 1 == 67
             and g40[0]["iterations"] == 48 and 18 <= bi[0]["iterations"] <= 19
-            and cg[0]["iterations"] == 26)
+            and cg[0]["iterations"] == 26 and gl[0]["iterations"] == 29
+            and gl40[0]["iterations"] == 18)
 
 
 def chk_special_cases():

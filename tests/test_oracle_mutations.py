@@ -61,6 +61,12 @@ MUTATIONS = [
     ("gmres_backsolve_transposed", "sum -= H[i * m + l] * y[l];", "sum -= H[l * m + i] * y[l];"),
     ("gmres_update_unpreconditioned", "precond(n, dinv, w, z);\n        for (i = 0; i < n; i++) x[i] += z[i];",
      "precond(n, dinv, w, z);\n        for (i = 0; i < n; i++) x[i] += w[i];"),
+    ("gmres_left_bnorm_unpreconditioned", "bnorm = nrm2(n, z);", "bnorm = nrm2(n, b);"),
+    ("gmres_left_true_residual_restart",
+     "if (left) { precond(n, dinv, r, z); memcpy(r, z, sizeof(double) * n); }\n        beta",
+     "if (0) { precond(n, dinv, r, z); memcpy(r, z, sizeof(double) * n); }\n        beta"),
+    ("gmres_left_update_preconditioned", "if (left) memcpy(z, w, sizeof(double) * n);",
+     "if (left) precond(n, dinv, w, z);"),
     ("bicgstab_beta", "beta = (rho / rho_old) * (alpha / omega);", "beta = (rho / rho_old) * (omega / alpha);"),
     ("bicgstab_omega", "omega = dot(n, t, sv) / tt;", "omega = dot(n, sv, sv) / tt;"),
     ("bicgstab_x_update", "x[i] += alpha * ph[i] + omega * sh[i];", "x[i] += alpha * p[i] + omega * sh[i];"),

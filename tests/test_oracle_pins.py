@@ -366,6 +366,27 @@ def test_paper_unpreconditioned_gmres_counts(ns, expected):
     assert info[0]["iterations"] == expected
 
 
+@pytest.mark.parametrize("ns,expected", list(zip(_G["jacobi_gmres"]["ns"],
+                                                _G["jacobi_gmres"]["iterations"])))
+def test_paper_jacobi_gmres_counts(ns, expected):
+    """Jacobi-GMRES without restarts (Table tab:jacobi): the printed counts
+    exactly, with left preconditioning and the preconditioned-residual test."""
+    p = _replica(ns)
+    _, info = O.gmres(p, precond=True, restart=0, tol=1e-6, maxit=1000, left=True)
+    assert info[0]["status"] == "converged"
+    assert info[0]["iterations"] == expected
+
+
+def test_left_and_right_gmres_solve_the_same_system():
+    """Both preconditioning sides converge to the LU solution (Sect. 2.1)."""
+    p = _replica(20)
+    ref = D.Dense(p).solve()
+    for left in (False, True):
+        x, info = O.gmres(p, tol=1e-13, restart=0, maxit=200, left=left)
+        assert info[0]["status"] == "converged"
+        assert np.max(np.abs(x - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("ns,expected", list(zip(_G["jacobi_richardson"]["ns"],
                                                 _G["jacobi_richardson"]["iterations"])))
 def test_paper_jacobi_richardson_counts(ns, expected):
