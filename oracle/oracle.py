@@ -52,6 +52,14 @@ class _Slab(C.Structure):
     ]
 
 
+class _Prec(C.Structure):
+    _fields_ = [("kind", C.c_int), ("dinv", C.POINTER(C.c_double)),
+                ("A", C.POINTER(C.c_double)), ("omega", C.c_double)]
+
+
+PRECONDITIONERS = {"none": 0, "jacobi": 1, "sor": 2, "ssor": 3}
+
+
 def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
@@ -79,11 +87,12 @@ def lib():
             L.orc_rhs.argtypes = [P, D]
             L.orc_diag.argtypes = [P, C.c_int, I, D]
             L.orc_assemble.argtypes = [P, D]
-            L.orc_gmres.argtypes = [P, D, D, D, C.c_int, C.c_double, C.c_int, I, I, D, D, C.c_int,
+            Q = C.POINTER(_Prec)
+            L.orc_gmres.argtypes = [P, D, D, Q, C.c_int, C.c_double, C.c_int, I, I, D, D, C.c_int,
                                     C.c_int]
-            L.orc_bicgstab.argtypes = [P, D, D, D, C.c_double, C.c_int, I, I, D]
-            L.orc_richardson.argtypes = [P, D, D, D, C.c_double, C.c_int, I, I, D]
-            L.orc_cgs.argtypes = [P, D, D, D, C.c_double, C.c_int, I, I, D]
+            L.orc_bicgstab.argtypes = [P, D, D, Q, C.c_double, C.c_int, I, I, D]
+            L.orc_richardson.argtypes = [P, D, D, Q, C.c_double, C.c_int, I, I, D]
+            L.orc_cgs.argtypes = [P, D, D, Q, C.c_double, C.c_int, I, I, D]
             for f in ("orc_apply", "orc_rhs", "orc_diag", "orc_assemble", "orc_gmres",
                       "orc_bicgstab", "orc_richardson", "orc_cgs"):
                 getattr(L, f).restype = C.c_int
@@ -233,7 +242,8 @@ def assemble(prob, i=0):
 # solvers (per slab)
 # ----------------------------------------------------------------------------
 
-def _solve(kind, prob, b, x0, dinv, tol, maxit, restart=30, hist_len=0, left=False):
+def _solve(kind, prob, b, x0, prec, tol, maxit, restart=30, hist_len=0, left=False):
+    """prec: None, or ("jacobi", dinv over all slabs), or ("sor" | "ssor", omega)."""
     n = prob.n_unknowns
     b = np.ascontiguousarray(b if b is not None else rhs(prob), dtype=np.float64)
     x = np.array(x0, dtype=np.float64, copy=True)
@@ -243,9 +253,17 @@ def _solve(kind, prob, b, x0, dinv, tol, maxit, restart=30, hist_len=0, left=Fal
         v = _SlabView(prob, i)
         bs = np.ascontiguousarray(b[s])
         xs = np.ascontiguousarray(x[s])
-        ds = None if dinv is None else np.ascontiguousarray(dinv[s], dtype=np.float64)
         it, mv, rr = C.c_int(), C.c_int(), C.c_double()
-        dptr = _dp(ds) if ds is not None else None
+        keep = None
+        if prec is None:
+            dptr = None
+        elif prec[0] == "jacobi":
+            keep = np.ascontiguousarray(prec[1][s], dtype=np.float64)
+            dptr = C.byref(_Prec(1, _dp(keep), None, 1.0))
+        else:
+            keep = np.empty((bs.size, bs.size))
+            lib().orc_assemble(v.ref, _dp(keep))
+            dptr = C.byref(_Prec(PRECONDITIONERS[prec[0]], None, _dp(keep), float(prec[1])))
         if kind == "gmres":
             h = np.zeros(max(hist_len, 1))
             st = lib().orc_gmres(v.ref, _dp(bs), _dp(xs), dptr, int(restart), float(tol),
@@ -276,41 +294,51 @@ def jacobi_inverse(prob):
     return 1.0 / diag(prob)
 
 
+def _prec(prob, precond, dinv, omega):
+    """Preconditioner spec (Sect. 2.3): True or "jacobi" (P = D), False or
+    "none", "sor" or "ssor" (relaxation omega, from the assembled A)."""
+    if precond is True:
+        precond = "jacobi"
+    if precond is False or precond is None or precond == "none":
+        return None
+    if precond == "jacobi":
+        return ("jacobi", jacobi_inverse(prob) if dinv is None else dinv)
+    if precond in ("sor", "ssor"):
+        if not 0.0 < omega < 2.0:
+            raise ValueError("omega must lie in (0, 2)")
+        return (precond, float(omega))
+    raise ValueError(f"unknown preconditioner {precond!r}")
+
+
 def gmres(prob, b=None, x0=None, precond=True, tol=1e-10, maxit=10000, restart=30,
-          dinv=None, hist_len=0, left=False):
+          dinv=None, hist_len=0, left=False, omega=1.0):
     """GMRES(restart) of Sect. 2.1, right-preconditioned by default (minimizes
     and tests the true residual).  left=True preconditions from the left and
     minimizes and tests the preconditioned residual ||P^-1 (b - A x)||."""
     if x0 is None:
         x0 = _x0(prob)
-    if precond and dinv is None:
-        dinv = jacobi_inverse(prob)
-    return _solve("gmres", prob, b, x0, dinv if precond else None, tol, maxit, restart, hist_len,
-                  left)
+    return _solve("gmres", prob, b, x0, _prec(prob, precond, dinv, omega), tol, maxit, restart,
+                  hist_len, left)
 
 
-def bicgstab(prob, b=None, x0=None, precond=True, tol=1e-10, maxit=10000, dinv=None):
+def bicgstab(prob, b=None, x0=None, precond=True, tol=1e-10, maxit=10000, dinv=None,
+             omega=1.0):
     if x0 is None:
         x0 = _x0(prob)
-    if precond and dinv is None:
-        dinv = jacobi_inverse(prob)
-    return _solve("bicgstab", prob, b, x0, dinv if precond else None, tol, maxit)
+    return _solve("bicgstab", prob, b, x0, _prec(prob, precond, dinv, omega), tol, maxit)
 
 
-def cgs(prob, b=None, x0=None, precond=True, tol=1e-10, maxit=10000, dinv=None):
+def cgs(prob, b=None, x0=None, precond=True, tol=1e-10, maxit=10000, dinv=None, omega=1.0):
     if x0 is None:
         x0 = _x0(prob)
-    if precond and dinv is None:
-        dinv = jacobi_inverse(prob)
-    return _solve("cgs", prob, b, x0, dinv if precond else None, tol, maxit)
+    return _solve("cgs", prob, b, x0, _prec(prob, precond, dinv, omega), tol, maxit)
 
 
-def richardson(prob, b=None, x0=None, precond=True, tol=1e-10, maxit=100000, dinv=None):
+def richardson(prob, b=None, x0=None, precond=True, tol=1e-10, maxit=100000, dinv=None,
+               omega=1.0):
     if x0 is None:
         x0 = _x0(prob)
-    if precond and dinv is None:
-        dinv = jacobi_inverse(prob)
-    return _solve("richardson", prob, b, x0, dinv if precond else None, tol, maxit)
+    return _solve("richardson", prob, b, x0, _prec(prob, precond, dinv, omega), tol, maxit)
 
 
 def _x0(prob):

@@ -334,12 +334,32 @@ int orc_assemble(const orc_slab *s, double *A)
 }
 
 /* ------------------------------------------------------------------------
- * Solvers.  All are right-preconditioned by P^-1 = diag(dinv) (identity if
- * dinv is NULL), so the residual they stop on is the unpreconditioned
- * ||b - A x||_2 / ||b||_2 of Sect. 4.2.
+ * Solvers.  All are right-preconditioned by P^-1 (identity if pc is NULL),
+ * so the residual they stop on is the unpreconditioned ||b - A x||_2 /
+ * ||b||_2 of Sect. 4.2 (GMRES can also precondition from the left).
+ *
+ * Preconditioners of Sect. 2.3, with A = D + L + U split into its diagonal
+ * and strictly lower and upper triangles (unknowns ordered as sigma, top
+ * depth point first) and 0 < omega < 2:
+ *   Jacobi  P = D;
+ *   SOR     P = omega^-1 D + U;
+ *   SSOR    P = omega (2 - omega)^-1 (omega^-1 D + U) D^-1 (omega^-1 D + L).
+ * Sect. 2.3 prints SOR as omega^-1 D + L (or + U) and SSOR with the lower
+ * factor first, and Sect. 4.2 names the upper-triangle variant; numbering
+ * the depth points from the bottom turns the printed lower factor into the
+ * upper one here.  These are the forms whose iteration counts equal the
+ * paper's SOR and SSOR tables.
  *
  * Status: 0 converged, 1 iteration limit reached, 2 breakdown, -1 memory.
  * ---------------------------------------------------------------------- */
+enum { ORC_PC_NONE = 0, ORC_PC_JACOBI = 1, ORC_PC_SOR = 2, ORC_PC_SSOR = 3 };
+
+typedef struct {
+    int kind;             /* ORC_PC_*                                        */
+    const double *dinv;   /* Jacobi: [n] reciprocals of diag(A)              */
+    const double *A;      /* SOR, SSOR: [n*n] assembled A, row-major         */
+    double omega;         /* SOR, SSOR relaxation parameter                  */
+} orc_prec;
 static double dot(int n, const double *a, const double *b)
 {
     double s = 0.0;
@@ -350,10 +370,37 @@ static double dot(int n, const double *a, const double *b)
 
 static double nrm2(int n, const double *a) { return sqrt(dot(n, a, a)); }
 
-static void precond(int n, const double *dinv, const double *v, double *z)
+/* z = P^-1 v; z and v must not alias for SOR and SSOR. */
+static void precond(int n, const orc_prec *pc, const double *v, double *z)
 {
-    int i;
-    for (i = 0; i < n; i++) z[i] = dinv ? dinv[i] * v[i] : v[i];
+    int i, j;
+    const double *A;
+    double om;
+    if (!pc || pc->kind == ORC_PC_NONE) {
+        for (i = 0; i < n; i++) z[i] = v[i];
+        return;
+    }
+    if (pc->kind == ORC_PC_JACOBI) {
+        for (i = 0; i < n; i++) z[i] = pc->dinv[i] * v[i];
+        return;
+    }
+    A = pc->A;
+    om = pc->omega;
+    /* (omega^-1 D + U) z = v, back substitution from the last unknown */
+    for (i = n - 1; i >= 0; i--) {
+        double sum = v[i];
+        for (j = i + 1; j < n; j++) sum -= A[(size_t)i * n + j] * z[j];
+        z[i] = sum / (A[(size_t)i * n + i] / om);
+    }
+    if (pc->kind != ORC_PC_SSOR) return;
+    /* then multiply by D, solve (omega^-1 D + L) z' = D z forward, and scale */
+    for (i = 0; i < n; i++) z[i] = A[(size_t)i * n + i] * z[i];
+    for (i = 0; i < n; i++) {
+        double sum = z[i];
+        for (j = 0; j < i; j++) sum -= A[(size_t)i * n + j] * z[j];
+        z[i] = sum / (A[(size_t)i * n + i] / om);
+    }
+    for (i = 0; i < n; i++) z[i] = z[i] * ((2.0 - om) / om);
 }
 
 static void residual(const orc_slab *s, const double *b, const double *x, double *r)
@@ -376,7 +423,7 @@ static void residual(const orc_slab *s, const double *b, const double *x, double
  * stopping test use the preconditioned residual ||P^-1 (b - A x)|| relative
  * to ||P^-1 b||.  Without a preconditioner the two variants coincide.
  */
-int orc_gmres(const orc_slab *s, const double *b, double *x, const double *dinv,
+int orc_gmres(const orc_slab *s, const double *b, double *x, const orc_prec *pc,
               int restart, double tol, int maxit, int *iters, int *matvecs,
               double *relres, double *hist, int hist_len, int left)
 {
@@ -395,9 +442,9 @@ int orc_gmres(const orc_slab *s, const double *b, double *x, const double *dinv,
     double *w = (double *)malloc(sizeof(double) * n);
     if (!V || !H || !cs || !sn || !g || !y || !r || !z || !w) { status = -1; goto done; }
 
-    left = left && dinv;
+    left = left && pc && pc->kind != ORC_PC_NONE;
     if (left) {
-        precond(n, dinv, b, z);
+        precond(n, pc, b, z);
         bnorm = nrm2(n, z);
     } else {
         bnorm = nrm2(n, b);
@@ -409,7 +456,7 @@ int orc_gmres(const orc_slab *s, const double *b, double *x, const double *dinv,
         goto done;
     }
     residual(s, b, x, r); nmv++;
-    if (left) { precond(n, dinv, r, z); memcpy(r, z, sizeof(double) * n); }
+    if (left) { precond(n, pc, r, z); memcpy(r, z, sizeof(double) * n); }
     beta = nrm2(n, r);
     if (hist && hist_len > 0) hist[0] = beta / bnorm;
     if (beta / bnorm < tol) { status = 0; goto done_res; }
@@ -424,9 +471,9 @@ int orc_gmres(const orc_slab *s, const double *b, double *x, const double *dinv,
             double hnext, resid, tmp, den;
             if (left) {
                 orc_apply(s, V + (size_t)j * n, z); nmv++;
-                precond(n, dinv, z, w);
+                precond(n, pc, z, w);
             } else {
-                precond(n, dinv, V + (size_t)j * n, z);
+                precond(n, pc, V + (size_t)j * n, z);
                 orc_apply(s, z, w); nmv++;
             }
             total++;
@@ -469,10 +516,10 @@ int orc_gmres(const orc_slab *s, const double *b, double *x, const double *dinv,
         for (j = 0; j < jj; j++)
             for (i = 0; i < n; i++) w[i] += y[j] * V[(size_t)j * n + i];
         if (left) memcpy(z, w, sizeof(double) * n);
-        else precond(n, dinv, w, z);
+        else precond(n, pc, w, z);
         for (i = 0; i < n; i++) x[i] += z[i];
         residual(s, b, x, r); nmv++;
-        if (left) { precond(n, dinv, r, z); memcpy(r, z, sizeof(double) * n); }
+        if (left) { precond(n, pc, r, z); memcpy(r, z, sizeof(double) * n); }
         beta = nrm2(n, r);
         if (beta / bnorm < tol) { status = 0; break; }
         if (beta == 0.0) { status = 0; break; }
@@ -491,7 +538,7 @@ done:
  * iters counts full steps (two applications of A each); a step that
  * converges on its half-way residual s counts as a full step.
  */
-int orc_bicgstab(const orc_slab *s, const double *b, double *x, const double *dinv,
+int orc_bicgstab(const orc_slab *s, const double *b, double *x, const orc_prec *pc,
                  double tol, int maxit, int *iters, int *matvecs, double *relres)
 {
     int n = 2 * s->ns, it, i, status = 1, nmv = 0;
@@ -521,7 +568,7 @@ int orc_bicgstab(const orc_slab *s, const double *b, double *x, const double *di
         if (rho == 0.0 || !isfinite(rho)) { status = 2; it--; break; }
         beta = (rho / rho_old) * (alpha / omega);
         for (i = 0; i < n; i++) p[i] = r[i] + beta * (p[i] - omega * v[i]);
-        precond(n, dinv, p, ph);
+        precond(n, pc, p, ph);
         orc_apply(s, ph, v); nmv++;
         rv = dot(n, rh, v);
         if (rv == 0.0 || !isfinite(rv)) { status = 2; it--; break; }
@@ -532,7 +579,7 @@ int orc_bicgstab(const orc_slab *s, const double *b, double *x, const double *di
             status = 0;
             break;
         }
-        precond(n, dinv, sv, sh);
+        precond(n, pc, sv, sh);
         orc_apply(s, sh, t); nmv++;
         tt = dot(n, t, t);
         if (tt == 0.0) { status = 2; break; }
@@ -566,7 +613,7 @@ done:
  * recursively updated residual after each step, and the returned relres is
  * recomputed from x.
  */
-int orc_cgs(const orc_slab *s, const double *b, double *x, const double *dinv,
+int orc_cgs(const orc_slab *s, const double *b, double *x, const orc_prec *pc,
             double tol, int maxit, int *iters, int *matvecs, double *relres)
 {
     int n = 2 * s->ns, it, i, status = 1, nmv = 0;
@@ -603,7 +650,7 @@ int orc_cgs(const orc_slab *s, const double *b, double *x, const double *dinv,
                 p[i] = u[i] + beta * (q[i] + beta * p[i]);
             }
         }
-        precond(n, dinv, p, ph);
+        precond(n, pc, p, ph);
         orc_apply(s, ph, v); nmv++;
         sig = dot(n, rh, v);
         if (sig == 0.0 || !isfinite(sig)) { status = 2; it--; break; }
@@ -612,7 +659,7 @@ int orc_cgs(const orc_slab *s, const double *b, double *x, const double *dinv,
             q[i] = u[i] - alpha * v[i];
             uq[i] = u[i] + q[i];
         }
-        precond(n, dinv, uq, uh);
+        precond(n, pc, uq, uh);
         for (i = 0; i < n; i++) x[i] += alpha * uh[i];
         orc_apply(s, uh, v); nmv++;              /* v now holds A P^-1 (u + q) */
         for (i = 0; i < n; i++) r[i] -= alpha * v[i];
@@ -635,7 +682,7 @@ done:
  * (eq. rich_iteration).  iters = number of updates applied when the
  * relative residual first drops below tol.
  */
-int orc_richardson(const orc_slab *s, const double *b, double *x, const double *dinv,
+int orc_richardson(const orc_slab *s, const double *b, double *x, const orc_prec *pc,
                    double tol, int maxit, int *iters, int *matvecs, double *relres)
 {
     int n = 2 * s->ns, it, i, status = 1, nmv = 0;
@@ -657,7 +704,7 @@ int orc_richardson(const orc_slab *s, const double *b, double *x, const double *
         if (rel < tol) { status = 0; break; }
         if (!isfinite(rel)) { status = 2; break; }   /* diverged */
         if (it == maxit) { status = 1; break; }
-        precond(n, dinv, r, z);
+        precond(n, pc, r, z);
         for (i = 0; i < n; i++) x[i] += z[i];
     }
     if (iters) *iters = it;

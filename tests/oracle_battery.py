@@ -125,6 +125,20 @@ def chk_paper_counts():
             and gl40[0]["iterations"] == 18)
 
 
+def chk_sor_ssor_counts():
+    """Tables tab:sor and tab:ssor at N_s = 40 (Richardson with omega = 1.5
+    counted as the paper's loop index; GMRES left-preconditioned)."""
+    p40 = W.paper_replica(40, scale="integrated", normalize=False)
+    out = []
+    for pc, rich, gm, cg in (("sor", 26, 17, 12), ("ssor", 20, 9, 7)):
+        _, r = O.richardson(p40, precond=pc, omega=1.5, tol=1e-6, maxit=10000)
+        _, g = O.gmres(p40, precond=pc, restart=0, tol=1e-6, maxit=1000, left=True)
+        _, c = O.cgs(p40, precond=pc, tol=1e-6, maxit=1000)
+        out += [r[0]["iterations"] + 1 == rich, g[0]["iterations"] == gm,
+                c[0]["iterations"] == cg]
+    return all(out)
+
+
 def chk_special_cases():
     p = W.config1_subgrid().with_(eps=np.array([1.0]))
     if np.abs(O.assemble(p) - np.eye(p.n_unknowns)).max() != 0.0:
@@ -135,7 +149,7 @@ def chk_special_cases():
 
 
 CHECKS = [chk_moments, chk_delo, chk_trapezoid, chk_implicit_euler, chk_linear_source, chk_dense,
-          chk_solvers_vs_lu, chk_paper_counts, chk_special_cases]
+          chk_solvers_vs_lu, chk_paper_counts, chk_sor_ssor_counts, chk_special_cases]
 
 
 def run():

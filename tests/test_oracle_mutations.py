@@ -59,14 +59,21 @@ MUTATIONS = [
     ("gmres_rotation_sign", "H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];",
      "H[(i + 1) * m + j] = sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];"),
     ("gmres_backsolve_transposed", "sum -= H[i * m + l] * y[l];", "sum -= H[l * m + i] * y[l];"),
-    ("gmres_update_unpreconditioned", "precond(n, dinv, w, z);\n        for (i = 0; i < n; i++) x[i] += z[i];",
-     "precond(n, dinv, w, z);\n        for (i = 0; i < n; i++) x[i] += w[i];"),
+    ("gmres_update_unpreconditioned", "precond(n, pc, w, z);\n        for (i = 0; i < n; i++) x[i] += z[i];",
+     "precond(n, pc, w, z);\n        for (i = 0; i < n; i++) x[i] += w[i];"),
     ("gmres_left_bnorm_unpreconditioned", "bnorm = nrm2(n, z);", "bnorm = nrm2(n, b);"),
     ("gmres_left_true_residual_restart",
-     "if (left) { precond(n, dinv, r, z); memcpy(r, z, sizeof(double) * n); }\n        beta",
-     "if (0) { precond(n, dinv, r, z); memcpy(r, z, sizeof(double) * n); }\n        beta"),
+     "if (left) { precond(n, pc, r, z); memcpy(r, z, sizeof(double) * n); }\n        beta",
+     "if (0) { precond(n, pc, r, z); memcpy(r, z, sizeof(double) * n); }\n        beta"),
     ("gmres_left_update_preconditioned", "if (left) memcpy(z, w, sizeof(double) * n);",
-     "if (left) precond(n, dinv, w, z);"),
+     "if (left) precond(n, pc, w, z);"),
+    ("sor_transposed_triangle", "for (j = i + 1; j < n; j++) sum -= A[(size_t)i * n + j] * z[j];",
+     "for (j = i + 1; j < n; j++) sum -= A[(size_t)j * n + i] * z[j];"),
+    ("sor_drops_omega", "z[i] = sum / (A[(size_t)i * n + i] / om);", "z[i] = sum / A[(size_t)i * n + i];"),
+    ("ssor_drops_D", "for (i = 0; i < n; i++) z[i] = A[(size_t)i * n + i] * z[i];", ""),
+    ("ssor_scale_inverted", "z[i] = z[i] * ((2.0 - om) / om);", "z[i] = z[i] * (om / (2.0 - om));"),
+    ("ssor_forward_uses_upper", "for (j = 0; j < i; j++) sum -= A[(size_t)i * n + j] * z[j];",
+     "for (j = 0; j < i; j++) sum -= A[(size_t)j * n + i] * z[j];"),
     ("bicgstab_beta", "beta = (rho / rho_old) * (alpha / omega);", "beta = (rho / rho_old) * (omega / alpha);"),
     ("bicgstab_omega", "omega = dot(n, t, sv) / tt;", "omega = dot(n, sv, sv) / tt;"),
     ("bicgstab_x_update", "x[i] += alpha * ph[i] + omega * sh[i];", "x[i] += alpha * p[i] + omega * sh[i];"),

@@ -428,3 +428,79 @@ def test_paper_unpreconditioned_cgs_count_small_grid():
     g = _G["no_preconditioner_cgs_ns20"]
     _, info = O.cgs(_replica(g["ns"]), precond=False, tol=1e-6, maxit=1000)
     assert info[0]["iterations"] == g["iterations"]
+
+
+# SOR and SSOR (Sect. 2.3, 4.2; Tables tab:sor and tab:ssor): relaxation 1.5 for
+# Richardson, none for the Krylov methods.
+_SOR_CASES = [(pc, method, ns, exp) for pc in ("sor", "ssor")
+              for method in ("richardson", "gmres", "bicgstab", "cgs")
+              for ns, exp in zip(_G[pc]["ns"], _G[pc][method])]
+
+
+@pytest.mark.parametrize("pc,method,ns,expected", _SOR_CASES)
+def test_paper_sor_ssor_counts(pc, method, ns, expected):
+    p = _replica(ns)
+    if method == "richardson":
+        _, info = O.richardson(p, precond=pc, omega=1.5, tol=1e-6, maxit=10000)
+        assert info[0]["iterations"] + 1 == expected
+        return
+    if method == "gmres":
+        _, info = O.gmres(p, precond=pc, restart=0, tol=1e-6, maxit=1000, left=True)
+    else:
+        _, info = getattr(O, method)(p, precond=pc, tol=1e-6, maxit=1000)
+    assert info[0]["status"] == "converged"
+    if method == "bicgstab":
+        assert expected <= info[0]["iterations"] <= expected + 1
+    else:
+        assert info[0]["iterations"] == expected
+
+
+@pytest.mark.parametrize("pc", ["sor", "ssor"])
+@pytest.mark.parametrize("omega", [0.7, 1.0, 1.5])
+def test_sor_ssor_preconditioner_is_the_textbook_matrix(pc, omega):
+    """P^-1 v from the oracle equals a dense solve with P built from the
+    triangles of the assembled A (Sect. 2.3), on the tiny grid."""
+    p = W.config1_subgrid()
+    A = O.assemble(p)
+    n = A.shape[0]
+    D = np.diag(np.diag(A))
+    L, U = np.tril(A, -1), np.triu(A, 1)
+    if pc == "sor":
+        P = D / omega + U
+    else:
+        P = omega / (2.0 - omega) * (D / omega + U) @ np.linalg.inv(D) @ (D / omega + L)
+    # one Richardson update from x = 0 is exactly P^-1 b
+    b = np.random.default_rng(5).uniform(-1, 1, n)
+    x, info = O.richardson(p, b=b, x0=np.zeros(n), precond=pc, omega=omega, tol=1e-300, maxit=1)
+    assert np.allclose(x, np.linalg.solve(P, b), rtol=1e-12, atol=1e-12 * np.abs(x).max())
+
+
+def test_sor_with_omega_one_is_gauss_seidel_on_the_upper_triangle():
+    """omega = 1: SOR is Gauss-Seidel (Sect. 2.3), here sweeping from the last
+    unknown up; SSOR is symmetric Gauss-Seidel, that sweep followed by D and a
+    forward sweep.  Written as explicit loops over the assembled A."""
+    p = W.config1_subgrid()
+    A = O.assemble(p)
+    n = A.shape[0]
+    b = np.random.default_rng(6).uniform(-1, 1, n)
+    x, _ = O.richardson(p, b=b, x0=np.zeros(n), precond="sor", omega=1.0, tol=1e-300, maxit=1)
+    ref = np.zeros(n)
+    for i in range(n - 1, -1, -1):     # Gauss-Seidel, last unknown first
+        ref[i] = (b[i] - A[i, i + 1:] @ ref[i + 1:]) / A[i, i]
+    assert np.allclose(x, ref, rtol=1e-13, atol=1e-14)
+    y, _ = O.richardson(p, b=b, x0=np.zeros(n), precond="ssor", omega=1.0, tol=1e-300, maxit=1)
+    z = np.diag(A) * ref
+    fw = np.zeros(n)
+    for i in range(n):                 # then forward, first unknown first
+        fw[i] = (z[i] - A[i, :i] @ fw[:i]) / A[i, i]
+    assert np.allclose(y, fw, rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("pc", ["sor", "ssor"])
+def test_sor_ssor_solvers_agree_with_LU(pc):
+    p = W.config1_subgrid()
+    ref = D.Dense(p).solve()
+    for solve in (O.gmres, O.bicgstab, O.cgs):
+        x, info = solve(p, precond=pc, tol=1e-13, maxit=2000)
+        assert info[0]["status"] == "converged"
+        assert np.max(np.abs(x - ref)) < 1e-10 * np.max(np.abs(ref))
