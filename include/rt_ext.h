@@ -54,6 +54,27 @@ int rt_plan_info(const rt_handle *h, int *chunk_L, int *n_blocks, long long *n_p
 int rt_sweep_config(const rt_handle *h, int fp32, int *waves, int *prefetch);
 
 /*
+ * Number of doubles of the assembled operator: the sum over slabs of
+ * (2 ns)^2.  Host only.
+ */
+int rt_assembled_size(const rt_handle *h, long long *count);
+
+/*
+ * Assemble A = Id - J Lambda T explicitly (Sect. 3.3 builds A column by
+ * column from Algorithm 1 applied to the unit vectors; Sect. 4.4 uses that a
+ * point source gives zero intensity upwind of it).  A_out is a caller-owned
+ * device array of rt_assembled_size doubles; slab s's (2 ns_s) x (2 ns_s)
+ * block is stored row-major at offset sum_{t<s} (2 ns_t)^2, rows and columns
+ * in the unknowns' order [s00(z_1), s20(z_1), s00(z_2), ...], so that
+ * A_s x_s = (rt_apply_op(x))_s up to rounding.  The first call on a handle
+ * also builds a coefficient table of sum_s (ns_s - 1) (n_mu / 2) n_nu (E, w)
+ * pairs (16 bytes each) kept until rt_destroy, plus, when one workgroup
+ * cannot hold a slab's rays, scratch of the size of A per extra ray slice.
+ * Stream-ordered on `stream`; RT_ENOMEM if a workspace allocation fails.
+ */
+int rt_assemble(rt_handle *h, double *A_out, void *stream);
+
+/*
  * Run the validation of rt_setup on (p, o) without touching any device:
  * RT_OK or RT_EINVAL with the message in rt_last_error().  o may be NULL.
  */

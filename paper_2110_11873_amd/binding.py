@@ -30,7 +30,7 @@ EXPORTS = ["rt_default_options", "rt_setup", "rt_destroy", "rt_num_unknowns", "r
            "rt_precond_jacobi", "rt_get_rhs", "rt_get_jacobi_diag", "rt_solve_gmres",
            "rt_solve_bicgstab", "rt_solve_richardson", "rt_solve_cgs", "rt_last_error",
            "rt_apply_op_fp32",
-           "rt_plan_info", "rt_sweep_config", "rt_validate"]
+           "rt_plan_info", "rt_sweep_config", "rt_validate", "rt_assembled_size", "rt_assemble"]
 
 
 class RTError(RuntimeError):
@@ -95,6 +95,8 @@ def lib():
                                    C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         L.rt_sweep_config.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.rt_validate.argtypes = [C.POINTER(rt_problem), C.POINTER(rt_options)]
+        L.rt_assembled_size.argtypes = [vp, C.POINTER(C.c_longlong)]
+        L.rt_assemble.argtypes = [vp, vp, vp]
         _ = dp
         _lib = L
     return _lib
@@ -177,6 +179,7 @@ class Handle:
         self._h = h
         self.n = lib().rt_num_unknowns(h)
         self.n_atm = int(pb.ns.shape[0])
+        self.ns = [int(n) for n in pb.ns]
 
     def close(self):
         if getattr(self, "_h", None):
@@ -245,6 +248,28 @@ class Handle:
         c = self.sweep_config(fp32)
         return "rt::sweep::sweep_kernel<%s, %d, %d, %d>" % (
             "float" if fp32 else "double", self.plan_info()["chunk"], c["waves"], c["prefetch"])
+
+    # -- dense route -------------------------------------------------------------
+    def assembled_size(self):
+        n = C.c_longlong()
+        _check(lib().rt_assembled_size(self._h, C.byref(n)))
+        return n.value
+
+    def assemble(self, out=None, stream=None):
+        """rt_assemble into a flat float64 tensor (allocated if out is None)."""
+        import torch
+        A = out if out is not None else torch.empty(self.assembled_size(), dtype=torch.float64,
+                                                    device="cuda")
+        _check(lib().rt_assemble(self._h, C.c_void_p(_ptr(A)), _stream(stream)))
+        return A
+
+    def dense_blocks(self, A):
+        """Views of the slabs' (2 ns) x (2 ns) blocks of a flat assembled A."""
+        out, off = [], 0
+        for n in self.ns:
+            out.append(A[off:off + 4 * n * n].view(2 * n, 2 * n))
+            off += 4 * n * n
+        return out
 
     # -- solvers ---------------------------------------------------------------
     def _solve(self, fn, b, x, stream):

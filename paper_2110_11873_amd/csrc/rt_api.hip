@@ -318,7 +318,8 @@ void rt_destroy(rt_handle *h) {
                     h->d_coef32, h->d_partial, h->d_diag,  h->d_dinv,   h->d_b,
                     h->d_V,     h->d_H,     h->d_cs,      h->d_sn,      h->d_g,      h->d_w,
                     h->d_r,     h->d_rh,    h->d_p,       h->d_v,       h->d_s,      h->d_t,
-                    h->d_cq,    h->d_state, h->d_active,  h->d_cycle,   h->d_count};
+                    h->d_cq,    h->d_state, h->d_active,  h->d_cycle,   h->d_count,
+                    h->d_ew,    h->d_asm_dg, h->d_asm_sc, h->d_asm_task};
     clear_graphs(h);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
     for (hipEvent_t e : h->gev)
@@ -381,7 +382,7 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
             delete h;
             return fail(RT_EINVAL, "options.chunk too short for ns (need 64 * chunk >= ns - 1)");
         }
-    long long coef = 0, part = 0, qt = 0;
+    long long coef = 0, part = 0, qt = 0, dense = 0, ew = 0;
     int blk = 0;
     // Waves per block and wave-batches per wave.  A block never mixes
     // directions.  Big batches: one block per (slab, direction), the fewest
@@ -420,6 +421,10 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
         d.coef_off = coef;
         d.part_off = part;
         d.q_off = qt;
+        d.a_off = dense;
+        d.ew_off = ew;
+        dense += 4LL * d.ns * d.ns;
+        ew += (long long)(d.ns - 1) * rays;
         d.eps = p->eps[a];
         d.xi = 1.0 - p->eps[a];
         d.W2 = p->W2[a];
@@ -452,6 +457,8 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     h->n_qt = qt;
     h->n_pairs = coef;
     h->n_partial = part;
+    h->n_dense = dense;
+    h->n_ew = ew;
 
     // ---- device memory
     std::vector<int> pt_atm(acc);
@@ -609,6 +616,18 @@ int rt_sweep_config(const rt_handle *h, int fp32, int *waves, int *prefetch) {
     if (waves) *waves = W;
     if (prefetch) *prefetch = pf ? 1 : 0;
     return RT_OK;
+}
+
+int rt_assembled_size(const rt_handle *h, long long *count) {
+    if (!h || !count) return fail(RT_EINVAL, "NULL handle or count");
+    *count = h->n_dense;
+    return RT_OK;
+}
+
+int rt_assemble(rt_handle *h, double *A_out, void *stream) {
+    if (!h || !A_out) return fail(RT_EINVAL, "NULL handle or output");
+    if (!aligned16(A_out)) return fail(RT_EINVAL, "output must be 16-byte aligned");
+    return assemble(h, A_out, (hipStream_t)stream);
 }
 
 // Validation only, without touching the device (tests of the error paths).

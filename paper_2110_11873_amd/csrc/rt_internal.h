@@ -41,6 +41,8 @@ struct AtmDesc {
     long long q_off;     // first entry of the slab's tile-ordered weights
     long long coef_off;  // first coefficient pair of the slab's tiles
     long long part_off;  // first partial sum of the slab's blocks
+    long long a_off;     // first entry of the slab's block of the assembled A
+    long long ew_off;    // first entry of the slab's rows of the assembly coefficient table
     double xi;      // 1 - eps
     double W2;      // polarizability
     double eps;     // thermalization
@@ -151,6 +153,10 @@ bool sweep_chunk_supported(int L, bool fp32);
 // compiled for.
 int chunk_len(int ns, int C, int L);
 
+// Dense assembly of A (rt_assemble.hip).  Writes every slab's (2 ns)^2 block,
+// row-major, at a_off; the coefficient table and scratch live in the handle.
+int assemble(rt_handle *h, double *A, hipStream_t s);
+
 // Krylov state kept on the device, one entry per slab.
 struct KState {
     double bnorm;     // ||b||
@@ -200,6 +206,15 @@ struct rt_handle {
     float2 *d_coef32 = nullptr;
     double *d_partial = nullptr;
     double *d_diag = nullptr, *d_dinv = nullptr, *d_b = nullptr;
+    long long n_dense = 0;        // entries of the assembled A: sum over slabs of (2 ns)^2
+    long long n_ew = 0;           // entries of the assembly coefficient table
+
+    // dense route (allocated on first use)
+    double2 *d_ew = nullptr;      // (E, w) per slab, interval and ray
+    double *d_asm_dg = nullptr;   // node-diagonal moments per slice and direction
+    double *d_asm_sc = nullptr;   // raw moments of ray slices after the first
+    void *d_asm_task = nullptr;   // assembly task list
+    int asm_tasks = 0, asm_rg = 0, asm_nw = 0, asm_cpm = 0, asm_slices = 0;
 
     // solver workspace (allocated on first use)
     int ws_restart = 0;
