@@ -63,6 +63,11 @@ extern "C" {
 #define RT_PREC_FP64 0
 #define RT_PREC_MIXED 1
 
+/* Preconditioners (Sect. 2.3); see rt_options.precond. */
+#define RT_PC_JACOBI 0
+#define RT_PC_SOR 1
+#define RT_PC_SSOR 2
+
 /* Largest supported depth grid per slab, and largest GMRES restart length. */
 #define RT_MAX_NS 2048
 #define RT_MAX_RESTART 128
@@ -147,6 +152,17 @@ typedef struct rt_problem {
  *              replayed, the host testing convergence between replays;
  *              0 = kernels launched one by one, GMRES also testing every
  *              check_every steps within a cycle (default: measured faster)
+ *  precond     preconditioner of every solver (Sect. 2.3), with A = D + L + U
+ *              split into its diagonal and strict lower and upper triangles
+ *              in the unknowns' order:
+ *              RT_PC_JACOBI (default)  P = D;
+ *              RT_PC_SOR               P = omega^-1 D + U;
+ *              RT_PC_SSOR              P = omega (2 - omega)^-1
+ *                                          (omega^-1 D + U) D^-1 (omega^-1 D + L).
+ *              SOR and SSOR need the assembled A (built on the device on the
+ *              first solve, (2 ns)^2 doubles per slab, kept by the handle)
+ *  omega       relaxation of SOR and SSOR, 0 < omega < 2 (1; the paper uses
+ *              1.5 for Richardson, 1 for the Krylov methods)
  */
 typedef struct rt_options {
     int precision;
@@ -162,6 +178,8 @@ typedef struct rt_options {
     int check_every;
     int sweep_waves;
     int graphs;
+    int precond;
+    double omega;
 } rt_options;
 
 /* Per-slab outcome of a solve. */

@@ -75,6 +75,27 @@ int rt_assembled_size(const rt_handle *h, long long *count);
 int rt_assemble(rt_handle *h, double *A_out, void *stream);
 
 /*
+ * Solve A x = b directly (the assembled route of Sect. 3.3 and 4.5): every
+ * slab's A is assembled (rt_assemble) and factored with partial pivoting by
+ * rows, PA = LU, on the first call; the factors are kept by the handle, so
+ * later calls only substitute.  b NULL means the handle's own right-hand side;
+ * x is output only.  info[i] (host, n_atm entries, or NULL) gets status RT_OK
+ * (RT_EBREAKDOWN if a pivot was exactly zero), iterations 0, matvecs 1 and the
+ * relative residual ||b - A x|| / ||b|| recomputed with the matrix-free FP64
+ * operator.  Workspace: (2 ns)^2 doubles per slab for the factors, plus those
+ * of rt_assemble.  Synchronizes the stream before returning.
+ */
+int rt_solve_lu(rt_handle *h, const double *b, double *x, rt_solve_info *info, void *stream);
+
+/*
+ * z = P^-1 v with the handle's preconditioner (options.precond, Sect. 2.3):
+ * Jacobi as rt_precond_jacobi; SOR and SSOR by triangular solves with the
+ * assembled A (built on the first call that needs it, see rt_assemble).
+ * Device vectors of length N; z == v allowed.  Stream-ordered.
+ */
+int rt_precond_apply(rt_handle *h, const double *v, double *z, void *stream);
+
+/*
  * Run the validation of rt_setup on (p, o) without touching any device:
  * RT_OK or RT_EINVAL with the message in rt_last_error().  o may be NULL.
  */

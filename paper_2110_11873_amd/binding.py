@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "librt.so")
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ENOCONV, RT_EBREAKDOWN = 0, -1, -2, -3, 1, 2
 RT_FS_DELO_LINEAR, RT_FS_TRAPEZOIDAL = 0, 1
 RT_PREC_FP64, RT_PREC_MIXED = 0, 1
+RT_PC_JACOBI, RT_PC_SOR, RT_PC_SSOR = 0, 1, 2
 RT_MAX_NS = 2048
 RT_MAX_RESTART = 128
 STATUS_NAMES = {RT_OK: "converged", RT_ENOCONV: "maxit", RT_EBREAKDOWN: "breakdown"}
@@ -30,7 +31,8 @@ EXPORTS = ["rt_default_options", "rt_setup", "rt_destroy", "rt_num_unknowns", "r
            "rt_precond_jacobi", "rt_get_rhs", "rt_get_jacobi_diag", "rt_solve_gmres",
            "rt_solve_bicgstab", "rt_solve_richardson", "rt_solve_cgs", "rt_last_error",
            "rt_apply_op_fp32",
-           "rt_plan_info", "rt_sweep_config", "rt_validate", "rt_assembled_size", "rt_assemble"]
+           "rt_plan_info", "rt_sweep_config", "rt_validate", "rt_assembled_size", "rt_assemble",
+           "rt_precond_apply", "rt_solve_lu"]
 
 
 class RTError(RuntimeError):
@@ -57,6 +59,7 @@ class rt_options(C.Structure):
         ("inner_rtol", C.c_double), ("inner_maxit", C.c_int), ("max_outer", C.c_int),
         ("chunk", C.c_int), ("wave_batches", C.c_int), ("prefetch", C.c_int),
         ("check_every", C.c_int), ("sweep_waves", C.c_int), ("graphs", C.c_int),
+        ("precond", C.c_int), ("omega", C.c_double),
     ]
 
 
@@ -83,11 +86,12 @@ def lib():
         L.rt_destroy.argtypes = [vp]
         L.rt_destroy.restype = None
         L.rt_num_unknowns.argtypes = [vp]
-        for f in ("rt_apply_op", "rt_apply_op_fp32", "rt_precond_jacobi"):
+        for f in ("rt_apply_op", "rt_apply_op_fp32", "rt_precond_jacobi", "rt_precond_apply"):
             getattr(L, f).argtypes = [vp, vp, vp, vp]
         for f in ("rt_get_rhs", "rt_get_jacobi_diag"):
             getattr(L, f).argtypes = [vp, vp, vp]
-        for f in ("rt_solve_gmres", "rt_solve_bicgstab", "rt_solve_richardson", "rt_solve_cgs"):
+        for f in ("rt_solve_gmres", "rt_solve_bicgstab", "rt_solve_richardson", "rt_solve_cgs",
+                  "rt_solve_lu"):
             getattr(L, f).argtypes = [vp, vp, vp, C.POINTER(rt_solve_info), vp]
         L.rt_last_error.argtypes = []
         L.rt_last_error.restype = C.c_char_p
@@ -221,6 +225,13 @@ class Handle:
                                        _stream(stream)))
         return out
 
+    def precond_apply(self, v, z=None, stream=None):
+        """z = P^-1 v with the handle's preconditioner (options.precond)."""
+        out = self._new() if z is None else z
+        _check(lib().rt_precond_apply(self._h, C.c_void_p(_ptr(v)), C.c_void_p(_ptr(out)),
+                                      _stream(stream)))
+        return out
+
     def get_rhs(self, stream=None):
         b = self._new()
         _check(lib().rt_get_rhs(self._h, C.c_void_p(_ptr(b)), _stream(stream)))
@@ -291,6 +302,10 @@ class Handle:
 
     def solve_cgs(self, x, b=None, stream=None):
         return self._solve("rt_solve_cgs", b, x, stream)
+
+    def solve_lu(self, x, b=None, stream=None):
+        """Direct solve with the LU factors of the assembled A (x is output only)."""
+        return self._solve("rt_solve_lu", b, x, stream)
 
 
 def setup(prob, options: Optional[rt_options] = None, autotune: bool = False, **kw) -> Handle:

@@ -145,6 +145,10 @@ int validate(const rt_problem *p, const rt_options *o, std::vector<double> &mu_p
         if (o->sweep_waves == 8 && o->chunk > 8)
             return fail(RT_EINVAL, "options.sweep_waves = 8 needs chunk <= 8");
         if (o->graphs != 0 && o->graphs != 1) return fail(RT_EINVAL, "options.graphs must be 0 or 1");
+        if (o->precond < RT_PC_JACOBI || o->precond > RT_PC_SSOR)
+            return fail(RT_EINVAL, "options.precond must be RT_PC_JACOBI, RT_PC_SOR or RT_PC_SSOR");
+        if (!(o->omega > 0.0 && o->omega < 2.0))
+            return fail(RT_EINVAL, "options.omega must lie in (0, 2)");
     }
     return RT_OK;
 }
@@ -303,6 +307,8 @@ void rt_default_options(rt_options *o) {
     o->prefetch = 0;
     o->sweep_waves = 0;
     o->graphs = 0;
+    o->precond = RT_PC_JACOBI;
+    o->omega = 1.0;
     o->check_every = 16;
 }
 
@@ -319,7 +325,8 @@ void rt_destroy(rt_handle *h) {
                     h->d_V,     h->d_H,     h->d_cs,      h->d_sn,      h->d_g,      h->d_w,
                     h->d_r,     h->d_rh,    h->d_p,       h->d_v,       h->d_s,      h->d_t,
                     h->d_cq,    h->d_state, h->d_active,  h->d_cycle,   h->d_count,
-                    h->d_ew,    h->d_asm_dg, h->d_asm_sc, h->d_asm_task};
+                    h->d_ew,    h->d_asm_dg, h->d_asm_sc, h->d_asm_task, h->d_A,
+                    h->d_pz,    h->d_ones,  h->d_LU,      h->d_piv,     h->d_sing};
     clear_graphs(h);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
     for (hipEvent_t e : h->gev)
@@ -616,6 +623,23 @@ int rt_sweep_config(const rt_handle *h, int fp32, int *waves, int *prefetch) {
     if (waves) *waves = W;
     if (prefetch) *prefetch = pf ? 1 : 0;
     return RT_OK;
+}
+
+int rt_solve_lu(rt_handle *h, const double *b, double *x, rt_solve_info *info, void *stream) {
+    if (!h || !x) return fail(RT_EINVAL, "NULL handle or x");
+    if (!aligned16(x) || (b && !aligned16(b))) return fail(RT_EINVAL, "vectors must be 16-byte aligned");
+    return run_solver(h, 4, b, x, info, (hipStream_t)stream);
+}
+
+int rt_precond_apply(rt_handle *h, const double *v, double *z, void *stream) {
+    if (!h || !v || !z) return fail(RT_EINVAL, "NULL handle or vector");
+    if (!aligned16(v) || !aligned16(z)) return fail(RT_EINVAL, "vectors must be 16-byte aligned");
+    const hipStream_t s = (hipStream_t)stream;
+    if (h->opt.precond == RT_PC_JACOBI)
+        return hip_check(launch_scale(v, h->d_dinv, z, h->n_unk, s), "rt_precond_apply");
+    const int rc = ensure_dense(h, s);
+    if (rc != RT_OK) return rc;
+    return hip_check(precond_tri(h, v, z, nullptr, s), "rt_precond_apply");
 }
 
 int rt_assembled_size(const rt_handle *h, long long *count) {

@@ -271,13 +271,14 @@ __global__ void assemble_diag_kernel(AsmArgs g, const int *pt_atm) {
 
 // Compiled variants: ray slots per wavefront and workgroup size.  Up to 24
 // slots the intensities and the loop's temporaries fit 128 VGPRs (16
-// wavefronts per workgroup); 52 to 80 slots fit 256 VGPRs (8 wavefronts).
-// Larger groups spill.
+// wavefronts per workgroup); 52 and 64 slots fit 256 VGPRs (8 wavefronts).
+// Every thread stages at most one slot's coefficients, so a wavefront holds
+// at most 64 slots.
 struct AsmVariant {
     int rg, nt;
 };
-constexpr AsmVariant kVariants[] = {{8, 1024}, {16, 1024}, {24, 1024},
-                                    {52, 512}, {64, 512},  {80, 512}};
+constexpr AsmVariant kVariants[] = {{8, 1024}, {16, 1024}, {24, 1024}, {52, 512}, {64, 512}};
+static_assert(kVariants[4].rg <= kWave, "one staged slot per thread");
 
 size_t asm_lds_bytes(int nw, int rg) {
     const size_t nrs = (size_t)nw * rg;
@@ -303,8 +304,7 @@ hipError_t launch_assemble(int rg, const AsmArgs &a, int ntasks, hipStream_t s) 
         case 16: return launch_variant<16, 1024>(a, ntasks, s);
         case 24: return launch_variant<24, 1024>(a, ntasks, s);
         case 52: return launch_variant<52, 512>(a, ntasks, s);
-        case 64: return launch_variant<64, 512>(a, ntasks, s);
-        default: return launch_variant<80, 512>(a, ntasks, s);
+        default: return launch_variant<64, 512>(a, ntasks, s);
     }
 }
 

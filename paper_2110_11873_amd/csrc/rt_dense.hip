@@ -1,0 +1,493 @@
+// rt_dense.hip -- kernels on the assembled A: the SOR and SSOR preconditioners
+// (Sect. 2.3) and their product form.
+//
+// With A = D + L + U (diagonal, strict lower and upper triangles in the
+// unknowns' order) the preconditioners are
+//   SOR   P = omega^-1 D + U,
+//   SSOR  P = omega (2 - omega)^-1 (omega^-1 D + U) D^-1 (omega^-1 D + L).
+// One workgroup per slab keeps the slab's vector (at most 2 RT_MAX_NS values)
+// in LDS and walks the triangle in blocks of 64 unknowns: the block's
+// diagonal 64 x 64 part is staged in LDS and solved by one wavefront, the
+// solved values are broadcast with readlane, and the rows still to come are
+// updated with the block's columns (one thread per row, reading each row's
+// 64 entries once).  Each triangle of A is read from memory once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "rt_internal.h"
+
+namespace rt {
+
+namespace {
+
+constexpr int kTriNT = 256;
+constexpr int kTriB = 64;
+constexpr int kTriPad = kTriB + 1;  // padded row of the staged block
+
+__device__ inline double readlane_d(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// r <- (omega^-1 D + T)^-1 r for T the strict upper (UP) or lower triangle
+// of the slab's A (row-major, N x N), r in LDS; UNIT: a unit diagonal instead
+// of omega^-1 D (the L factor of an LU factorization).
+template <bool UP, bool UNIT = false>
+__device__ void tri_sweep(const double *A, int N, double om, double *r, double *blk) {
+    const int tid = threadIdx.x;
+    const int nb = (N + kTriB - 1) / kTriB;
+    for (int bi = 0; bi < nb; ++bi) {
+        const int b = UP ? nb - 1 - bi : bi;
+        const int i0 = b * kTriB, n = min(kTriB, N - i0);
+        for (int e = tid; e < kTriB * kTriB; e += kTriNT) {
+            const int rr = e / kTriB, cc = e % kTriB;
+            blk[rr * kTriPad + cc] = (rr < n && cc < n) ? A[(long long)(i0 + rr) * N + i0 + cc] : 0.0;
+        }
+        __syncthreads();
+        if (tid < kWave) {
+            const int c = tid;
+            double val = c < n ? r[i0 + c] : 0.0;
+            const double dc = c < n ? (UNIT ? 1.0 : om / blk[c * kTriPad + c]) : 0.0;
+            for (int ii = 0; ii < n; ++ii) {
+                const int i = UP ? n - 1 - ii : ii;
+                const double zi = readlane_d(val * dc, i);
+                if (c == i) val = zi;
+                else if (UP ? c < i : c > i) val -= blk[c * kTriPad + i] * zi;
+            }
+            if (c < n) r[i0 + c] = val;
+        }
+        __syncthreads();
+        // the rows not yet solved: above the block (UP) or below it
+        const int lo = UP ? 0 : i0 + n, hi = UP ? i0 : N;
+        for (int l = lo + tid; l < hi; l += kTriNT) {
+            const double2 *row = reinterpret_cast<const double2 *>(A + (long long)l * N + i0);
+            double acc0 = 0.0, acc1 = 0.0;
+            for (int c2 = 0; c2 < n / 2; ++c2) {
+                const double2 v = row[c2];
+                acc0 = fma(v.x, r[i0 + 2 * c2], acc0);
+                acc1 = fma(v.y, r[i0 + 2 * c2 + 1], acc1);
+            }
+            r[l] -= acc0 + acc1;
+        }
+        __syncthreads();
+    }
+}
+
+struct TriArgs {
+    const AtmDesc *atm;
+    const double *A;     // assembled A
+    const double *in;
+    double *out;
+    const int *mask;     // optional per-slab activity mask
+    double omega;
+    int kind;            // RT_PC_SOR or RT_PC_SSOR
+};
+
+// out = P^-1 in.
+__global__ __launch_bounds__(kTriNT) void tri_solve_kernel(TriArgs a) {
+    extern __shared__ double sm[];
+    const int s = blockIdx.x;
+    if (a.mask && a.mask[s] == 0) return;
+    const AtmDesc at = a.atm[s];
+    const int N = 2 * at.ns;
+    const double *A = a.A + at.a_off;
+    const long long v0 = 2LL * at.doff;
+    double *blk = sm;                  // [64][65]
+    double *r = sm + kTriB * kTriPad;  // [N]
+    for (int i = threadIdx.x; i < N; i += kTriNT) r[i] = a.in[v0 + i];
+    __syncthreads();
+    tri_sweep<true>(A, N, a.omega, r, blk);
+    if (a.kind == RT_PC_SSOR) {
+        for (int i = threadIdx.x; i < N; i += kTriNT) r[i] *= A[(long long)i * N + i];
+        __syncthreads();
+        tri_sweep<false>(A, N, a.omega, r, blk);
+        const double sc = (2.0 - a.omega) / a.omega;
+        for (int i = threadIdx.x; i < N; i += kTriNT) r[i] *= sc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += kTriNT) a.out[v0 + i] = r[i];
+}
+
+// out = P in (the product form, for an initial guess).  One thread per row.
+__global__ __launch_bounds__(kTriNT) void tri_mult_kernel(TriArgs a) {
+    extern __shared__ double sm[];
+    const int s = blockIdx.x;
+    const AtmDesc at = a.atm[s];
+    const int N = 2 * at.ns;
+    const double *A = a.A + at.a_off;
+    const long long v0 = 2LL * at.doff;
+    const double om = a.omega;
+    double *x = sm;
+    for (int i = threadIdx.x; i < N; i += kTriNT) x[i] = a.in[v0 + i];
+    __syncthreads();
+    if (a.kind == RT_PC_SSOR) {
+        // t = D^-1 (omega^-1 D + L) x, parked in out (each thread reads back
+        // only its own rows), then copied over x once every row has read x
+        for (int i = threadIdx.x; i < N; i += kTriNT) {
+            const double *row = A + (long long)i * N;
+            double acc = row[i] / om * x[i];
+            for (int j = 0; j < i; ++j) acc = fma(row[j], x[j], acc);
+            a.out[v0 + i] = acc / row[i];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < N; i += kTriNT) x[i] = a.out[v0 + i];
+        __syncthreads();
+    }
+    const double sc = a.kind == RT_PC_SSOR ? om / (2.0 - om) : 1.0;
+    for (int i = threadIdx.x; i < N; i += kTriNT) {
+        const double *row = A + (long long)i * N;
+        double acc = row[i] / om * x[i];
+        for (int j = i + 1; j < N; ++j) acc = fma(row[j], x[j], acc);
+        a.out[v0 + i] = sc * acc;
+    }
+}
+
+__global__ void fill_kernel(double *v, long long n, double c) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        v[i] = c;
+}
+
+// --------------------------------------------------------------------------
+// Dense LU with partial pivoting (the direct route of Sect. 3.3 / 4.5: the
+// assembled A factored and solved), one workgroup per slab, right-looking in
+// panels of NB columns:
+//  * the panel's rows live in registers, R rows per thread; each column's
+//    pivot is the row of largest magnitude (ties: the lower index), found by
+//    a wave butterfly and one LDS pass; the pivot row and the row it replaces
+//    are exchanged through LDS, and the pivot row read from there eliminates
+//    the column below it -- two barriers per column;
+//  * the panel's row exchanges are then applied to the other columns (one
+//    thread per column, in order), U12 = L11^-1 A12 is solved one thread per
+//    column, and A22 -= L21 U12 streams the trailing rows with the column's
+//    U12 in registers and L21 staged in LDS 64 rows at a time.
+// piv[k] (slab-local) is the row exchanged with row k at step k, as LAPACK's
+// getrf returns it.  A zero pivot marks the slab singular.
+// --------------------------------------------------------------------------
+constexpr int kLuNT = 1024;
+constexpr int kLuRows = 64;  // L21 rows staged per pass of the trailing update
+constexpr int kLuNB = 8;     // panel width (16 spills the panel's registers)
+
+struct LuArgs {
+    const AtmDesc *atm;
+    double *LU;    // in: A; out: L (unit, strictly below the diagonal) and U
+    int *piv;      // at 2 doff + k
+    int *sing;     // per slab: 1 if a pivot was zero
+};
+
+template <int R, int NB>
+__global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g) {
+    constexpr int NW = kLuNT / kWave;
+    __shared__ double swp[2][2][NB];       // [buffer][row j, row p][column]
+    __shared__ double redv[2][NW];
+    __shared__ int redi[2][NW];
+    __shared__ int s_piv[NB];
+    __shared__ double L11[NB][NB + 1];
+    __shared__ double L21[kLuRows][NB];
+    const int slab = blockIdx.x;
+    const AtmDesc at = g.atm[slab];
+    const int N = 2 * at.ns;
+    double *A = g.LU + at.a_off;
+    int *piv = g.piv + 2LL * at.doff;
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    int singular = 0;
+    for (int k0 = 0; k0 < N; k0 += NB) {
+        const int nb = min(NB, N - k0);
+        double P[R][NB];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int r = k0 + tid + u * kLuNT;
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+                P[u][c] = (r < N && c < nb) ? A[(long long)r * N + k0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) {
+            if (jj < nb) {
+                const int j = k0 + jj, buf = jj & 1;
+                // pivot: largest |P[.][jj]| over rows >= j
+                double best = -1.0;
+                int bi = N;
+#pragma unroll
+                for (int u = 0; u < R; ++u) {
+                    const int r = k0 + tid + u * kLuNT;
+                    const double v = fabs(P[u][jj]);
+                    if (r >= j && r < N && (v > best || (v == best && r < bi))) {
+                        best = v;
+                        bi = r;
+                    }
+                }
+                for (int off = kWave / 2; off > 0; off >>= 1) {
+                    const double ov = __shfl_xor(best, off);
+                    const int oi = __shfl_xor(bi, off);
+                    if (ov > best || (ov == best && oi < bi)) {
+                        best = ov;
+                        bi = oi;
+                    }
+                }
+                if (lane == 0) {
+                    redv[buf][wave] = best;
+                    redi[buf][wave] = bi;
+                }
+                __syncthreads();
+                best = redv[buf][0];
+                bi = redi[buf][0];
+                for (int w = 1; w < NW; ++w) {
+                    const double ov = redv[buf][w];
+                    const int oi = redi[buf][w];
+                    if (ov > best || (ov == best && oi < bi)) {
+                        best = ov;
+                        bi = oi;
+                    }
+                }
+                const int p = bi;
+                // exchange rows j and p of the panel through LDS
+                const int oj = j - k0, op = p - k0;
+#pragma unroll
+                for (int u = 0; u < R; ++u) {
+                    const int lr = tid + u * kLuNT;
+                    if (lr == oj)
+#pragma unroll
+                        for (int c = 0; c < NB; ++c) swp[buf][0][c] = P[u][c];
+                    if (lr == op)
+#pragma unroll
+                        for (int c = 0; c < NB; ++c) swp[buf][1][c] = P[u][c];
+                }
+                if (tid == 0) s_piv[jj] = p;
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < R; ++u) {
+                    const int lr = tid + u * kLuNT;
+                    if (lr == oj)
+#pragma unroll
+                        for (int c = 0; c < NB; ++c) P[u][c] = swp[buf][1][c];
+                    else if (lr == op)
+#pragma unroll
+                        for (int c = 0; c < NB; ++c) P[u][c] = swp[buf][0][c];
+                }
+                // eliminate below the pivot (the pivot row is swp[buf][1])
+                const double pv = swp[buf][1][jj];
+                if (pv == 0.0) singular = 1;
+                const double rpv = pv != 0.0 ? 1.0 / pv : 0.0;
+#pragma unroll
+                for (int u = 0; u < R; ++u) {
+                    const int r = k0 + tid + u * kLuNT;
+                    if (r > j && r < N) {
+                        const double l = P[u][jj] * rpv;
+                        P[u][jj] = l;
+#pragma unroll
+                        for (int c = jj + 1; c < NB; ++c) P[u][c] = fma(-l, swp[buf][1][c], P[u][c]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int r = k0 + tid + u * kLuNT;
+            if (r < N)
+#pragma unroll
+                for (int c = 0; c < NB; ++c)
+                    if (c < nb) A[(long long)r * N + k0 + c] = P[u][c];
+        }
+        if (tid < nb) piv[k0 + tid] = s_piv[tid];
+        __syncthreads();
+        // the panel's row exchanges on the other columns, in order
+        for (int c = tid; c < N; c += kLuNT) {
+            if (c >= k0 && c < k0 + nb) continue;
+            for (int jj = 0; jj < nb; ++jj) {
+                const int p = s_piv[jj], j = k0 + jj;
+                if (p != j) {
+                    const double t = A[(long long)j * N + c];
+                    A[(long long)j * N + c] = A[(long long)p * N + c];
+                    A[(long long)p * N + c] = t;
+                }
+            }
+        }
+        for (int e = tid; e < NB * NB; e += kLuNT) {
+            const int r = e / NB, c = e % NB;
+            L11[r][c] = (r < nb && c < nb) ? A[(long long)(k0 + r) * N + k0 + c] : 0.0;
+        }
+        __syncthreads();
+        const int c0 = k0 + nb;
+        if (c0 >= N) break;
+        // U12 = L11^-1 A12 (unit lower L11), one thread per column
+        for (int c = c0 + tid; c < N; c += kLuNT) {
+            double u[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) u[i] = i < nb ? A[(long long)(k0 + i) * N + c] : 0.0;
+#pragma unroll
+            for (int i = 1; i < NB; ++i)
+#pragma unroll
+                for (int l = 0; l < i; ++l) u[i] = fma(-L11[i][l], u[l], u[i]);
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                if (i < nb) A[(long long)(k0 + i) * N + c] = u[i];
+        }
+        __syncthreads();
+        // A22 -= L21 U12
+        for (int cb = c0; cb < N; cb += kLuNT) {
+            const int c = cb + tid;
+            double u[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                u[i] = (c < N && i < nb) ? A[(long long)(k0 + i) * N + c] : 0.0;
+            for (int r0 = c0; r0 < N; r0 += kLuRows) {
+                const int nr = min(kLuRows, N - r0);
+                __syncthreads();
+                for (int e = tid; e < kLuRows * NB; e += kLuNT) {
+                    const int rr = e / NB, i = e % NB;
+                    L21[rr][i] = (rr < nr && i < nb) ? A[(long long)(r0 + rr) * N + k0 + i] : 0.0;
+                }
+                __syncthreads();
+                if (c < N) {
+                    for (int rr = 0; rr < nr; ++rr) {
+                        double a = A[(long long)(r0 + rr) * N + c];
+#pragma unroll
+                        for (int i = 0; i < NB; ++i) a = fma(-L21[rr][i], u[i], a);
+                        A[(long long)(r0 + rr) * N + c] = a;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) g.sing[slab] = singular;
+}
+
+// x = A^-1 b from the factors: row exchanges, L y = P b, U x = y.
+__global__ __launch_bounds__(kTriNT) void lu_solve_kernel(const AtmDesc *atm, const double *LU,
+                                                          const int *pivs, const double *b,
+                                                          double *x) {
+    extern __shared__ double sm[];
+    const int s = blockIdx.x;
+    const AtmDesc at = atm[s];
+    const int N = 2 * at.ns;
+    const double *A = LU + at.a_off;
+    const int *piv = pivs + 2LL * at.doff;
+    const long long v0 = 2LL * at.doff;
+    double *blk = sm;
+    double *r = sm + kTriB * kTriPad;
+    for (int i = threadIdx.x; i < N; i += kTriNT) r[i] = b[v0 + i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < N; ++k) {
+            const int p = piv[k];
+            if (p != k) {
+                const double t = r[k];
+                r[k] = r[p];
+                r[p] = t;
+            }
+        }
+    __syncthreads();
+    tri_sweep<false, true>(A, N, 1.0, r, blk);
+    tri_sweep<true, false>(A, N, 1.0, r, blk);
+    for (int i = threadIdx.x; i < N; i += kTriNT) x[v0 + i] = r[i];
+}
+
+size_t tri_lds(int ns_max) { return (size_t)(kTriB * kTriPad + 2 * ns_max) * sizeof(double); }
+
+template <typename K>
+hipError_t lds_limit(K kernel, size_t lds) {
+    if (lds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+TriArgs tri_args(const rt_handle *h, const double *in, double *out, const int *mask) {
+    TriArgs a{};
+    a.atm = h->d_atm;
+    a.A = h->d_A;
+    a.in = in;
+    a.out = out;
+    a.mask = mask;
+    a.omega = h->opt.omega;
+    a.kind = h->opt.precond;
+    return a;
+}
+
+}  // namespace
+
+hipError_t precond_tri(const rt_handle *h, const double *in, double *out, const int *mask,
+                       hipStream_t s) {
+    const size_t lds = tri_lds(h->ns_max);
+    hipError_t e = lds_limit(tri_solve_kernel, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tri_solve_kernel, dim3(h->n_atm), dim3(kTriNT), lds, s,
+                       tri_args(h, in, out, mask));
+    return hipGetLastError();
+}
+
+hipError_t precond_tri_mult(const rt_handle *h, const double *in, double *out, hipStream_t s) {
+    const size_t lds = (size_t)2 * h->ns_max * sizeof(double);
+    hipError_t e = lds_limit(tri_mult_kernel, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tri_mult_kernel, dim3(h->n_atm), dim3(kTriNT), lds, s,
+                       tri_args(h, in, out, nullptr));
+    return hipGetLastError();
+}
+
+hipError_t fill(double *v, long long n, double c, hipStream_t s) {
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, s, v, n, c);
+    return hipGetLastError();
+}
+
+int lu_factor(rt_handle *h, hipStream_t s) {
+    if (h->lu_ready) return RT_OK;
+    const size_t bytes = sizeof(double) * (size_t)std::max<long long>(h->n_dense, 1);
+    if (!h->d_LU) {
+        if (hipMalloc((void **)&h->d_LU, bytes) != hipSuccess ||
+            hipMalloc((void **)&h->d_piv, sizeof(int) * h->n_unk) != hipSuccess ||
+            hipMalloc((void **)&h->d_sing, sizeof(int) * h->n_atm) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(RT_ENOMEM, "device allocation of the LU factors failed");
+        }
+    }
+    int rc = h->dense_ready ? RT_OK : assemble(h, h->d_LU, s);
+    if (rc != RT_OK) return rc;
+    if (h->dense_ready &&
+        hipMemcpyAsync(h->d_LU, h->d_A, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(RT_EDEVICE, "copy of the assembled operator failed");
+    LuArgs g{h->d_atm, h->d_LU, h->d_piv, h->d_sing};
+    const int N = 2 * h->ns_max;
+    if (N <= kLuNT)
+        hipLaunchKernelGGL((lu_factor_kernel<1, kLuNB>), dim3(h->n_atm), dim3(kLuNT), 0, s, g);
+    else if (N <= 2 * kLuNT)
+        hipLaunchKernelGGL((lu_factor_kernel<2, kLuNB>), dim3(h->n_atm), dim3(kLuNT), 0, s, g);
+    else
+        hipLaunchKernelGGL((lu_factor_kernel<4, kLuNB>), dim3(h->n_atm), dim3(kLuNT), 0, s, g);
+    if (hipGetLastError() != hipSuccess) return fail(RT_EDEVICE, "LU factorization launch failed");
+    h->lu_ready = true;
+    return RT_OK;
+}
+
+hipError_t lu_solve(const rt_handle *h, const double *b, double *x, hipStream_t s) {
+    const size_t lds = tri_lds(h->ns_max);
+    hipError_t e = lds_limit(lu_solve_kernel, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(lu_solve_kernel, dim3(h->n_atm), dim3(kTriNT), lds, s,
+                       (const AtmDesc *)h->d_atm, (const double *)h->d_LU, (const int *)h->d_piv,
+                       b, x);
+    return hipGetLastError();
+}
+
+int ensure_dense(rt_handle *h, hipStream_t s) {
+    if (h->dense_ready) return RT_OK;
+    if (!h->d_A) {
+        if (hipMalloc((void **)&h->d_A, sizeof(double) * (size_t)std::max<long long>(h->n_dense, 1)) !=
+            hipSuccess) {
+            h->d_A = nullptr;
+            (void)hipGetLastError();
+            return fail(RT_ENOMEM, "device allocation of the assembled operator failed");
+        }
+    }
+    const int rc = assemble(h, h->d_A, s);
+    if (rc != RT_OK) return rc;
+    h->dense_ready = true;
+    return RT_OK;
+}
+
+}  // namespace rt

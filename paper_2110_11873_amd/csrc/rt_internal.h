@@ -157,6 +157,19 @@ int chunk_len(int ns, int C, int L);
 // row-major, at a_off; the coefficient table and scratch live in the handle.
 int assemble(rt_handle *h, double *A, hipStream_t s);
 
+// SOR / SSOR on the assembled A (rt_dense.hip): out = P^-1 in for the slabs
+// whose mask is set (all if NULL), and out = P in.  ensure_dense assembles the
+// handle's A on first use.
+hipError_t precond_tri(const rt_handle *h, const double *in, double *out, const int *mask,
+                       hipStream_t s);
+hipError_t precond_tri_mult(const rt_handle *h, const double *in, double *out, hipStream_t s);
+hipError_t fill(double *v, long long n, double c, hipStream_t s);
+int ensure_dense(rt_handle *h, hipStream_t s);
+// Dense LU with partial pivoting of every slab's assembled A (once per
+// handle), and x = A^-1 b from the factors.
+int lu_factor(rt_handle *h, hipStream_t s);
+hipError_t lu_solve(const rt_handle *h, const double *b, double *x, hipStream_t s);
+
 // Krylov state kept on the device, one entry per slab.
 struct KState {
     double bnorm;     // ||b||
@@ -215,6 +228,14 @@ struct rt_handle {
     double *d_asm_sc = nullptr;   // raw moments of ray slices after the first
     void *d_asm_task = nullptr;   // assembly task list
     int asm_tasks = 0, asm_rg = 0, asm_nw = 0, asm_cpm = 0, asm_slices = 0;
+    double *d_A = nullptr;        // the handle's assembled A (SOR, SSOR)
+    bool dense_ready = false;
+    double *d_pz = nullptr;       // P^-1 v for the triangular preconditioners
+    double *d_ones = nullptr;     // unit diagonal scaling of the Krylov updates
+    double *d_LU = nullptr;       // LU factors of the assembled A
+    int *d_piv = nullptr;         // their row exchanges
+    int *d_sing = nullptr;        // per slab: a zero pivot was met
+    bool lu_ready = false;
 
     // solver workspace (allocated on first use)
     int ws_restart = 0;

@@ -127,6 +127,8 @@ struct VecArgs {
     int max_outer;
     const double *partial;  // the sweep's per-block quadrature sums
     const double4 *Qs;      // per slab: sums over all rays of q, q T1, q (T1^2 + T2^2)
+    const double *zin;      // fused Arnoldi step: the sweep's input P^-1 v_j when the
+                            // preconditioner is not diagonal (NULL: v_j .* dinv)
 };
 
 // ---------------------------------------------------------------- counting
@@ -470,8 +472,16 @@ __global__ __launch_bounds__(NTF) void gm_arnoldi_fused_kernel(VecArgs a, int j)
                 vj0 = v0[t];
                 vj2 = v2[t];
             }
-        const double2 d = *reinterpret_cast<const double2 *>(a.dinv + e0);
-        const double z0 = vj0 * d.x, z2 = vj2 * d.y;
+        double z0, z2;
+        if (a.zin) {
+            const double2 z = *reinterpret_cast<const double2 *>(a.zin + e0);
+            z0 = z.x;
+            z2 = z.y;
+        } else {
+            const double2 d = *reinterpret_cast<const double2 *>(a.dinv + e0);
+            z0 = vj0 * d.x;
+            z2 = vj2 * d.y;
+        }
         const double4 Q = a.Qs[atm];
         J0 += z0 * Q.x + z2 * Q.y;
         J2 += z0 * Q.y + z2 * Q.z;
@@ -985,6 +995,14 @@ __global__ void relres_kernel(VecArgs a) {
     }
 }
 
+// Status of a direct solve: converged unless a pivot was zero.
+__global__ void direct_status_kernel(KState *st, const int *sing, int n_atm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_atm) return;
+    st[i].status = sing[i] ? RT_EBREAKDOWN : RT_OK;
+    st[i].iters = 0;
+}
+
 // Outer step of the mixed-precision refinement: r = b - A x in FP64 (A x in
 // a.w), test it; if the slab goes on, clear the correction d (a.s).
 __global__ void ir_residual_kernel(VecArgs a, int first) {
@@ -1071,6 +1089,10 @@ struct Driver {
     rt_handle *h;
     hipStream_t s;
     hipError_t err = hipSuccess;
+    // SOR or SSOR: the solvers run on y = P x with the operator A P^-1 and
+    // unit scaling in their updates (right preconditioning, the same iterates),
+    // and x = P^-1 y at the end.  Jacobi folds D^-1 into the sweep instead.
+    bool tri = false;
 
     bool ok(hipError_t e) {
         if (e != hipSuccess && err == hipSuccess) err = e;
@@ -1135,6 +1157,22 @@ struct Driver {
         ok(apply_operator(h, in, scale, out, mask, fp32, 0, s));
     }
 
+    // out = A P^-1 v
+    void prec_sweep(const double *v, double *out, const int *mask, bool fp32) {
+        if (tri) {
+            ok(precond_tri(h, v, h->d_pz, mask, s));
+            sweep(h->d_pz, nullptr, out, mask, fp32);
+        } else {
+            sweep(v, h->d_dinv, out, mask, fp32);
+        }
+    }
+
+    // the operator on the solver's iterate: A x (Jacobi) or A P^-1 y
+    void iter_sweep(const double *x, double *out, const int *mask, bool fp32) {
+        if (tri) prec_sweep(x, out, mask, fp32);
+        else sweep(x, nullptr, out, mask, fp32);
+    }
+
     // elements per thread for the largest slab: 2, 4, 8 or 16
     int ept() const {
         const int need = (2 * h->ns_max + NT - 1) / NT;
@@ -1148,11 +1186,16 @@ struct Driver {
     void arnoldi_step(const VecArgs &a, int j, bool fp32) {
         const double *vj = h->d_V + (long long)j * h->n_unk;
         if (fused()) {
-            ok(apply_sweep(h, vj, h->d_dinv, h->d_cycle, fp32, s));
+            if (tri) {
+                ok(precond_tri(h, vj, h->d_pz, h->d_cycle, s));
+                ok(apply_sweep(h, h->d_pz, nullptr, h->d_cycle, fp32, s));
+            } else {
+                ok(apply_sweep(h, vj, h->d_dinv, h->d_cycle, fp32, s));
+            }
             hipLaunchKernelGGL(gm_arnoldi_fused_kernel, dim3(h->n_atm), dim3(NTF), 0, s, a, j);
             ok(hipGetLastError());
         } else {
-            sweep(vj, h->d_dinv, h->d_w, h->d_cycle, fp32);
+            prec_sweep(vj, h->d_w, h->d_cycle, fp32);
             arnoldi(a, j);
         }
     }
@@ -1206,7 +1249,8 @@ struct Driver {
         a.w = h->d_w;
         a.b = b;
         a.x = x;
-        a.dinv = h->d_dinv;
+        a.dinv = tri ? h->d_ones : h->d_dinv;
+        a.zin = tri ? h->d_pz : nullptr;
         a.r = h->d_r;
         a.rh = h->d_rh;
         a.p = h->d_p;
@@ -1234,7 +1278,7 @@ struct Driver {
         VecArgs a = args(b, x, st, h->d_active, tol, maxit);
         const int m = h->ws_restart;
         const int check = std::max(1, h->opt.check_every);
-        if (!x_zero) sweep(x, nullptr, h->d_w, h->d_active, fp32);
+        if (!x_zero) iter_sweep(x, h->d_w, h->d_active, fp32);
         hipLaunchKernelGGL(gm_restart_kernel, dim3(nb), dim3(NT), 0, s, a, 1, x_zero ? 1 : 0,
                            accept_est ? 1 : 0);
         ok(hipGetLastError());
@@ -1242,7 +1286,7 @@ struct Driver {
         // ends), the update of x, and the restart with the explicit residual
         auto tail = [&]() {
             update(a);
-            sweep(x, nullptr, h->d_w, h->d_active, fp32);
+            iter_sweep(x, h->d_w, h->d_active, fp32);
             hipLaunchKernelGGL(gm_restart_kernel, dim3(nb), dim3(NT), 0, s, a, 0, 0,
                                accept_est ? 1 : 0);
             ok(hipGetLastError());
@@ -1271,14 +1315,14 @@ struct Driver {
         const int nb = h->n_atm;
         VecArgs a = args(b, x, st, h->d_active, tol, maxit);
         const int check = std::max(1, h->opt.check_every);
-        sweep(x, nullptr, h->d_w, h->d_active, false);
+        iter_sweep(x, h->d_w, h->d_active, false);
         hipLaunchKernelGGL(bi_start_kernel, dim3(nb), dim3(NT), 0, s, a);
         ok(hipGetLastError());
         auto step = [&]() {
             hipLaunchKernelGGL(bi_dir_kernel, dim3(nb), dim3(NT), 0, s, a);
-            sweep(h->d_p, h->d_dinv, h->d_v, h->d_active, false);
+            prec_sweep(h->d_p, h->d_v, h->d_active, false);
             hipLaunchKernelGGL(bi_half_kernel, dim3(nb), dim3(NT), 0, s, a);
-            sweep(h->d_s, h->d_dinv, h->d_t, h->d_active, false);
+            prec_sweep(h->d_s, h->d_t, h->d_active, false);
             hipLaunchKernelGGL(bi_full_kernel, dim3(nb), dim3(NT), 0, s, a);
             ok(hipGetLastError());
         };
@@ -1296,7 +1340,7 @@ struct Driver {
             }
         }
         // explicit final residual of every slab
-        sweep(x, nullptr, h->d_w, nullptr, false);
+        iter_sweep(x, h->d_w, nullptr, false);
         hipLaunchKernelGGL(relres_kernel, dim3(nb), dim3(NT), 0, s, a);
         ok(hipGetLastError());
     }
@@ -1305,14 +1349,14 @@ struct Driver {
         const int nb = h->n_atm;
         VecArgs a = args(b, x, st, h->d_active, tol, maxit);
         const int check = std::max(1, h->opt.check_every);
-        sweep(x, nullptr, h->d_w, h->d_active, false);
+        iter_sweep(x, h->d_w, h->d_active, false);
         hipLaunchKernelGGL(cg_start_kernel, dim3(nb), dim3(NT), 0, s, a);
         ok(hipGetLastError());
         auto step = [&]() {
             hipLaunchKernelGGL(cg_dir_kernel, dim3(nb), dim3(NT), 0, s, a);
-            sweep(h->d_p, h->d_dinv, h->d_v, h->d_active, false);
+            prec_sweep(h->d_p, h->d_v, h->d_active, false);
             hipLaunchKernelGGL(cg_half_kernel, dim3(nb), dim3(NT), 0, s, a);
-            sweep(h->d_s, h->d_dinv, h->d_t, h->d_active, false);
+            prec_sweep(h->d_s, h->d_t, h->d_active, false);
             hipLaunchKernelGGL(cg_full_kernel, dim3(nb), dim3(NT), 0, s, a);
             ok(hipGetLastError());
         };
@@ -1330,7 +1374,7 @@ struct Driver {
             }
         }
         // explicit final residual of every slab
-        sweep(x, nullptr, h->d_w, nullptr, false);
+        iter_sweep(x, h->d_w, nullptr, false);
         hipLaunchKernelGGL(relres_kernel, dim3(nb), dim3(NT), 0, s, a);
         ok(hipGetLastError());
     }
@@ -1340,7 +1384,7 @@ struct Driver {
         VecArgs a = args(b, x, st, h->d_active, tol, maxit);
         const int check = std::max(1, h->opt.check_every);
         auto step = [&](int first) {
-            sweep(x, nullptr, h->d_w, h->d_active, false);
+            iter_sweep(x, h->d_w, h->d_active, false);
             hipLaunchKernelGGL(ri_step_kernel, dim3(nb), dim3(NT), 0, s, a, first);
             ok(hipGetLastError());
         };
@@ -1372,7 +1416,7 @@ struct Driver {
                            outer_active, h->d_cycle, nb, (const int *)nullptr);
         ok(hipGetLastError());
         for (int k = 0; err == hipSuccess; ++k) {
-            sweep(x, nullptr, h->d_w, outer_active, false);
+            iter_sweep(x, h->d_w, outer_active, false);
             hipLaunchKernelGGL(ir_residual_kernel, dim3(nb), dim3(NT), 0, s, a, k == 0 ? 1 : 0);
             ok(hipGetLastError());
             if (count(outer_active) == 0) break;
@@ -1398,7 +1442,36 @@ int run_solver(rt_handle *h, int kind, const double *b, double *x, rt_solve_info
     Driver d{h, s};
     KState *st = h->d_state;
     KState *st_in = h->d_state + h->n_atm;
-    if (kind == 0 && h->opt.precision == RT_PREC_MIXED) {
+    if (kind == 4) {
+        // direct: LU of the assembled A, then the explicit FP64 residual
+        if ((rc = lu_factor(h, s)) != RT_OK) return rc;
+        d.ok(lu_solve(h, b, x, s));
+        d.init_state(st, nullptr);
+        d.sweep(x, nullptr, h->d_w, nullptr, false);
+        const VecArgs a = d.args(b, x, st, h->d_active, 0.0, 0);
+        hipLaunchKernelGGL(relres_kernel, dim3(h->n_atm), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL(direct_status_kernel, dim3((h->n_atm + 255) / 256), dim3(256), 0, s,
+                           st, (const int *)h->d_sing, h->n_atm);
+        d.ok(hipGetLastError());
+    }
+    d.tri = kind != 4 && h->opt.precond != RT_PC_JACOBI;
+    if (d.tri) {
+        // the assembled A, P^-1 workspace and unit scaling; then y0 = P x0
+        if ((rc = ensure_dense(h, s)) != RT_OK) return rc;
+        if (!h->d_pz) {
+            if (hipMalloc((void **)&h->d_pz, sizeof(double) * h->n_unk) != hipSuccess ||
+                hipMalloc((void **)&h->d_ones, sizeof(double) * h->n_unk) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(RT_ENOMEM, "preconditioner workspace allocation failed");
+            }
+            d.ok(fill(h->d_ones, h->n_unk, 1.0, s));
+        }
+        d.ok(precond_tri_mult(h, x, h->d_pz, s));
+        d.ok(hipMemcpyAsync(x, h->d_pz, sizeof(double) * h->n_unk, hipMemcpyDeviceToDevice, s));
+    }
+    if (kind == 4) {
+        // solved above
+    } else if (kind == 0 && h->opt.precision == RT_PREC_MIXED) {
         d.mixed_gmres(b, x, st, st_in);
     } else {
         d.init_state(st, nullptr);
@@ -1410,6 +1483,10 @@ int run_solver(rt_handle *h, int kind, const double *b, double *x, rt_solve_info
             d.cgs(b, x, st, h->opt.rtol, h->opt.maxit);
         else
             d.richardson(b, x, st, h->opt.rtol, h->opt.maxit);
+    }
+    if (d.tri) {  // x = P^-1 y
+        d.ok(precond_tri(h, x, h->d_pz, nullptr, s));
+        d.ok(hipMemcpyAsync(x, h->d_pz, sizeof(double) * h->n_unk, hipMemcpyDeviceToDevice, s));
     }
     std::vector<KState> hs(h->n_atm);
     d.ok(hipMemcpyAsync(hs.data(), st, sizeof(KState) * h->n_atm, hipMemcpyDeviceToHost, s));

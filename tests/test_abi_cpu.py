@@ -35,8 +35,9 @@ def test_library_exports_every_declared_symbol():
 def test_default_options():
     o = B.default_options()
     assert (o.precision, o.restart, o.maxit, o.rtol, o.inner_rtol, o.inner_maxit, o.max_outer,
-            o.chunk, o.wave_batches, o.prefetch, o.check_every, o.sweep_waves, o.graphs) == (
-                0, 30, 10000, 1e-10, 3e-4, 200, 30, 0, 0, 0, 16, 0, 0)
+            o.chunk, o.wave_batches, o.prefetch, o.check_every, o.sweep_waves, o.graphs,
+            o.precond, o.omega) == (
+                0, 30, 10000, 1e-10, 3e-4, 200, 30, 0, 0, 0, 16, 0, 0, B.RT_PC_JACOBI, 1.0)
 
 
 def test_valid_configs_pass_validation():
@@ -72,7 +73,10 @@ def test_invalid_options_rejected():
                      (dict(precision=9), "precision"), (dict(inner_rtol=2.0), "inner_rtol"),
                      (dict(inner_maxit=0), "inner_maxit"), (dict(wave_batches=-1), "wave_batches"),
                      (dict(prefetch=7), "prefetch"), (dict(sweep_waves=5), "sweep_waves"),
-                     (dict(sweep_waves=8, chunk=16), "sweep_waves"), (dict(graphs=2), "graphs")]:
+                     (dict(sweep_waves=8, chunk=16), "sweep_waves"), (dict(graphs=2), "graphs"),
+                     (dict(precond=3), "precond"), (dict(precond=-1), "precond"),
+                     (dict(omega=0.0), "omega"), (dict(omega=2.0), "omega"),
+                     (dict(precond=B.RT_PC_SSOR, omega=float("nan")), "omega")]:
         assert B.validate(p, B.default_options(**kw)) == B.RT_EINVAL, kw
         assert frag in B.last_error()
 

@@ -77,6 +77,19 @@ def test_assemble_config2_columns():
         assert np.abs(Ag[:, j] - O.apply(p, e)).max() <= ENTRY_TOL, j
 
 
+def test_assemble_config3_columns():
+    """1024 depth points, 201 frequencies x 16 |mu| (eight ray slices, 16
+    column blocks): sampled columns against the oracle's matvec of unit
+    vectors."""
+    p = W.config3()
+    (Ag,) = assembled_blocks(p)
+    n = p.n_unknowns
+    for j in (0, 1, 127, 128, 1023, 1024, 2046, 2047):
+        e = np.zeros(n)
+        e[j] = 1.0
+        assert np.abs(Ag[:, j] - O.apply(p, e)).max() <= ENTRY_TOL, j
+
+
 def test_assemble_batch_matches_operator_and_oracle():
     """Uneven batch: every slab's block times a random vector equals
     rt_apply_op, and sampled slabs equal the oracle's assembly."""
@@ -123,3 +136,183 @@ def test_assemble_full_batch_operator_property():
     assert worst <= 1e-12, worst
     for i, Ab in sample.items():
         assert np.abs(Ab - O.assemble(p.slab(i))).max() <= ENTRY_TOL, i
+
+
+# ------------------------------------------------------------ SOR and SSOR
+
+PCS = {"sor": B.RT_PC_SOR, "ssor": B.RT_PC_SSOR}
+
+
+def textbook_P(A, kind, om):
+    """P of Sect. 2.3 from the triangles of the oracle's assembled A."""
+    Dm = np.diag(np.diag(A))
+    L, U = np.tril(A, -1), np.triu(A, 1)
+    if kind == "sor":
+        return Dm / om + U
+    return om / (2.0 - om) * (Dm / om + U) @ np.diag(1.0 / np.diag(A)) @ (Dm / om + L)
+
+
+def backward_error(P, z, v):
+    """Normwise backward error of z as a solution of P z = v.  Substitution
+    is backward stable (|dP| <= n eps |P|), while the forward error also
+    carries P's condition number, large on optically thick slabs."""
+    return np.abs(P @ z - v).max() / (np.abs(P).sum(1).max() * np.abs(z).max() + np.abs(v).max())
+
+
+@pytest.mark.parametrize("kind", ["sor", "ssor"])
+@pytest.mark.parametrize("om", [0.7, 1.0, 1.5])
+def test_precond_apply_matches_textbook_P(kind, om):
+    for p in (W.config1(), W.paper_replica(140, scale="integrated", normalize=False)):
+        A = O.assemble(p)
+        v = W.random_vector(p.n_unknowns, 5)
+        with B.setup(p, precond=PCS[kind], omega=om) as h:
+            z = host(h.precond_apply(dev(v)))
+        P = textbook_P(A, kind, om)
+        assert backward_error(P, z, v) <= 1e-13, (p.name, kind, om)
+        ref = np.linalg.solve(P, v)
+        assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max(), (p.name, kind, om)
+
+
+@pytest.mark.parametrize("kind", ["sor", "ssor"])
+def test_precond_apply_batch(kind):
+    p = W.config4(24)
+    v = W.random_vector(p.n_unknowns, 6)
+    with B.setup(p, precond=PCS[kind]) as h:
+        z = host(h.precond_apply(dev(v)))
+    for i, s in enumerate(O._slices(p)):
+        if i not in (0, 11, 23):
+            continue
+        P = textbook_P(O.assemble(p.slab(i)), kind, 1.0)
+        assert backward_error(P, z[s], v[s]) <= 1e-13, i
+
+
+def _paper_x0(p):
+    x0 = np.zeros(p.n_unknowns)
+    x0[0::2] = 1.0
+    return x0
+
+
+@pytest.mark.parametrize("kind", ["sor", "ssor"])
+@pytest.mark.parametrize("ns", [20, 80, 140])
+def test_sor_ssor_gmres_bicgstab_cgs_counts(kind, ns):
+    """Right-preconditioned GMRES (no restart) takes the oracle's count;
+    BiCGSTAB and CGS take the counts of Tables tab:sor / tab:ssor (BiCGSTAB
+    within its half step), all from x0 = [1, 0, ...] to 1e-6."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "paper_iteration_counts.json")))[kind]
+    idx = g["ns"].index(ns)
+    p = W.paper_replica(ns, scale="integrated", normalize=False)
+    x0 = _paper_x0(p)
+    _, og = O.gmres(p, precond=kind, restart=0, tol=1e-6, maxit=1000)
+    with B.setup(p, precond=PCS[kind], rtol=1e-6, restart=100, maxit=1000) as h:
+        x = dev(x0)
+        rc, info = h.solve_gmres(x)
+        assert rc == 0 and abs(info[0].iterations - og[0]["iterations"]) <= 1
+        assert oracle_relres(p, host(x)) < 1e-6
+        x = dev(x0)
+        rc, info = h.solve_bicgstab(x)
+        assert rc == 0 and g["bicgstab"][idx] <= info[0].iterations <= g["bicgstab"][idx] + 1
+        assert oracle_relres(p, host(x)) < 1e-6
+        x = dev(x0)
+        rc, info = h.solve_cgs(x)
+        assert rc == 0 and abs(info[0].iterations - g["cgs"][idx]) <= 1
+        assert oracle_relres(p, host(x)) < 1e-6
+
+
+@pytest.mark.parametrize("kind", ["sor", "ssor"])
+def test_sor_ssor_richardson_paper_counts(kind):
+    """omega = 1.5 Richardson: the paper's count is the number of updates + 1."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "paper_iteration_counts.json")))[kind]
+    for ns, expected in zip(g["ns"][:3], g["richardson"][:3]):
+        p = W.paper_replica(ns, scale="integrated", normalize=False)
+        with B.setup(p, precond=PCS[kind], omega=1.5, rtol=1e-6, maxit=10000,
+                     check_every=1) as h:
+            x = dev(_paper_x0(p))
+            rc, info = h.solve_richardson(x)
+        assert rc == 0 and info[0].iterations + 1 == expected, (ns, info[0].iterations)
+
+
+@pytest.mark.parametrize("kind", ["sor", "ssor"])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_sor_ssor_batched_solves(kind, mixed):
+    """Batched uneven slabs, GMRES(30) to 1e-10 (FP64 and mixed precision)."""
+    p = W.config4(24)
+    prec = B.RT_PREC_MIXED if mixed else B.RT_PREC_FP64
+    with B.setup(p, precond=PCS[kind], precision=prec) as h:
+        x = dev(_paper_x0(p))
+        rc, info = h.solve_gmres(x)
+    assert rc == 0 and all(i.status == "converged" for i in info)
+    rr = oracle_relres(p, host(x))
+    assert rr.max() < 1e-10, rr.max()
+
+
+def oracle_relres(p, x, b=None):
+    b = O.rhs(p) if b is None else b
+    out = []
+    for i, s in enumerate(O._slices(p)):
+        r = b[s] - O.apply_slab(p, i, x[s])
+        out.append(np.linalg.norm(r) / np.linalg.norm(b[s]))
+    return np.array(out)
+
+
+# ------------------------------------------------------------------ LU route
+
+@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal", "implicit_euler"])
+def test_lu_subgrid_equals_lapack(fs):
+    """Partial pivoting by rows, as LAPACK's getrf: the same solution to a few
+    ulps of the condition number."""
+    p = W.config1_subgrid(fs)
+    ref = D.Dense(p).solve()
+    with B.setup(p) as h:
+        x = dev(np.zeros(p.n_unknowns))
+        rc, info = h.solve_lu(x)
+    assert rc == 0 and info[0].status == "converged" and info[0].relres < 1e-13
+    assert np.abs(host(x) - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("maker", [W.config1, lambda: W.paper_replica(
+    140, scale="integrated", normalize=False), W.config2])
+def test_lu_single_slab(maker):
+    p = maker()
+    with B.setup(p) as h:
+        x = dev(np.zeros(p.n_unknowns))
+        rc, info = h.solve_lu(x)
+        # the factors are reused for a second right-hand side
+        b2 = W.random_vector(p.n_unknowns, 8)
+        x2 = dev(np.zeros(p.n_unknowns))
+        rc2, info2 = h.solve_lu(x2, b=dev(b2))
+    assert rc == 0 and rc2 == 0
+    assert oracle_relres(p, host(x)).max() < 1e-12
+    # a random right-hand side gives ||x|| >> ||b|| on thick slabs: LU is
+    # backward stable, so the bound is on ||b - A x|| / (||A|| ||x|| + ||b||)
+    xh = host(x2)
+    r = b2 - O.apply(p, xh)
+    eta = np.abs(r).max() / (np.abs(O.assemble(p)).sum(1).max() * np.abs(xh).max() +
+                             np.abs(b2).max())
+    assert eta < 1e-14, eta
+    assert abs(info[0].relres - oracle_relres(p, host(x))[0]) < 1e-13
+
+
+def test_lu_batch():
+    p = W.config4(24)
+    with B.setup(p) as h:
+        x = dev(np.zeros(p.n_unknowns))
+        rc, info = h.solve_lu(x)
+    assert rc == 0 and all(i.status == "converged" for i in info)
+    rr = oracle_relres(p, host(x))
+    assert rr.max() < 1e-12, rr.max()
+
+
+def test_lu_config3_two_rows_per_thread():
+    """1024 depth points: 2048 unknowns, two panel rows per thread."""
+    p = W.config3()
+    with B.setup(p) as h:
+        x = dev(np.zeros(p.n_unknowns))
+        rc, info = h.solve_lu(x)
+    assert rc == 0
+    assert oracle_relres(p, host(x)).max() < 1e-12
