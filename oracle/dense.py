@@ -26,8 +26,9 @@ def _ray_matrices(tau, kappa, upward, fs):
     """Lambda (ns x ns) for one ray and the transmitted profile for unit
     incoming intensity.  Points are ordered along the ray, L I = M S with
     L unit lower bidiagonal (-a on the sub-diagonal), M holding the
-    coefficients of S_u (sub-diagonal) and S_k (diagonal); the entry row of
-    M is zero (zero incoming radiation)."""
+    coefficients of S_u (sub-diagonal), S_k (diagonal) and, for
+    DELO-parabolic, S_d (super-diagonal); the entry row of M is zero (zero
+    incoming radiation)."""
     ns = tau.shape[0]
     order = np.arange(ns)[::-1] if upward else np.arange(ns)
     t = tau[order]
@@ -35,7 +36,12 @@ def _ray_matrices(tau, kappa, upward, fs):
     M = np.zeros((ns, ns))
     for j in range(1, ns):
         d = kappa * abs(t[j] - t[j - 1])
-        if fs == 0:
+        if fs == 3 and j < ns - 1:
+            # DELO-parabolic: a third coefficient, on the downwind source
+            E, pu, pk, pd = O.delo_parabolic(d, kappa * abs(t[j + 1] - t[j]))
+            a, cu, ck = E, pu, pk
+            M[j, j + 1] = pd
+        elif fs in (0, 3):
             E, pu, pk = O.delo_linear(d)
             a, cu, ck = E, pu, pk
         elif fs == 2:

@@ -81,6 +81,8 @@ def lib():
             L.orc_delo_linear.argtypes = [C.c_double, D, D, D]
             L.orc_trapezoid.argtypes = [C.c_double, D, D]
             L.orc_implicit_euler.argtypes = [C.c_double, D, D]
+            L.orc_delo_parabolic.argtypes = [C.c_double, C.c_double, D, D, D, D]
+            L.orc_exp_moments.argtypes = [C.c_double, D]
             L.orc_ray.argtypes = [C.c_int, D, C.c_double, C.c_int, C.c_int, D, C.c_double, D]
             L.orc_weights.argtypes = [P, D]
             L.orc_apply.argtypes = [P, D, D]
@@ -155,6 +157,22 @@ def implicit_euler(d):
     a, b = C.c_double(), C.c_double()
     lib().orc_implicit_euler(float(d), C.byref(a), C.byref(b))
     return a.value, b.value
+
+
+def delo_parabolic(d, dd):
+    """(E, c_u, c_k, c_d) of a DELO-parabolic step with upwind optical step d
+    and downwind step dd."""
+    E, pu, pk, pd = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    lib().orc_delo_parabolic(float(d), float(dd), C.byref(E), C.byref(pu), C.byref(pk),
+                             C.byref(pd))
+    return E.value, pu.value, pk.value, pd.value
+
+
+def exp_moments(d):
+    """int_0^d t^n exp(-t) dt for n = 0, 1, 2."""
+    w = np.zeros(3)
+    lib().orc_exp_moments(float(d), _dp(w))
+    return w
 
 
 def ray(tau, kappa, upward, S, I_entry=0.0, fs=0):

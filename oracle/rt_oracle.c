@@ -126,6 +126,57 @@ void orc_implicit_euler(double d, double *a, double *b)
 }
 
 /* ------------------------------------------------------------------------
+ * DELO-parabolic step (Sect. 4.1 names it; the coefficients below are the
+ * exact integrals for this problem, which has no dichroism, so DELOPAR --
+ * which differs only in how it treats the dichroic term -- coincides with
+ * it).  With t the optical path measured from the current point k back
+ * towards the upwind point u (t = 0 at k, t = d at u, t = -dd at the
+ * downwind point d), S is the parabola through (d, S_u), (0, S_k),
+ * (-dd, S_d), and
+ *     I_k = E I_u + int_0^d S(t) exp(-t) dt = E I_u + pu S_u + pk S_k + pd S_d.
+ * With the moments w_n = int_0^d t^n exp(-t) dt of the Lagrange basis
+ *     L_u = t (t + dd) / (d (d + dd)),
+ *     L_k = (d - t)(t + dd) / (d dd),
+ *     L_d = t (t - d) / (dd (d + dd)):
+ *     pu = (w2 + dd w1) / (d (d + dd)),
+ *     pk = ((d - dd) w1 + d dd w0 - w2) / (d dd),
+ *     pd = (w2 - d w1) / (dd (d + dd)).
+ * The moments are 1 - E, 1 - (1 + d) E, 2 - (d^2 + 2 d + 2) E, or below
+ * d = 1 (where these cancel) their series
+ *     w_n = sum_{m>=0} (-1)^m d^(m+n+1) / (m! (m+n+1)).
+ * ---------------------------------------------------------------------- */
+void orc_exp_moments(double d, double *w)
+{
+    int n, m;
+    if (d < 1.0) {
+        for (n = 0; n < 3; n++) {
+            double term = 1.0, sum = 0.0;   /* term = d^m / m! */
+            for (m = 0; m <= 30; m++) {
+                double sgn = (m % 2 == 0) ? 1.0 : -1.0;
+                sum += sgn * term * pow(d, (double)(n + 1)) / (double)(m + n + 1);
+                term = term * d / (double)(m + 1);
+            }
+            w[n] = sum;
+        }
+    } else {
+        double e = exp(-d);
+        w[0] = -expm1(-d);
+        w[1] = 1.0 - (1.0 + d) * e;
+        w[2] = 2.0 - (d * d + 2.0 * d + 2.0) * e;
+    }
+}
+
+void orc_delo_parabolic(double d, double dd, double *E, double *pu, double *pk, double *pd)
+{
+    double w[3];
+    orc_exp_moments(d, w);
+    *E = exp(-d);
+    *pu = (w[2] + dd * w[1]) / (d * (d + dd));
+    *pk = ((d - dd) * w[1] + d * dd * w[0] - w[2]) / (d * dd);
+    *pd = (w[2] - d * w[1]) / (dd * (d + dd));
+}
+
+/* ------------------------------------------------------------------------
  * Formal solution along one ray (eqs. RTE_delo1/2 written in optical path
  * along the ray).  kappa = r_p / |mu|.  upward = 0: the ray enters at the
  * top (index 0) and moves to larger tau; upward = 1: it enters at the
@@ -140,7 +191,11 @@ void orc_ray(int ns, const double *tau, double kappa, int upward, int fs,
         for (k = 1; k < ns; k++) {
             int u = k - 1;
             double d = kappa * fabs(tau[k] - tau[u]);
-            if (fs == 0) {
+            if (fs == 3 && k < ns - 1) {      /* parabola through u, k, k + 1 */
+                double E, pu, pk, pd;
+                orc_delo_parabolic(d, kappa * fabs(tau[k + 1] - tau[k]), &E, &pu, &pk, &pd);
+                I[k] = E * I[u] + pu * S[u] + pk * S[k] + pd * S[k + 1];
+            } else if (fs == 0 || fs == 3) {  /* DELO-parabolic's last point: linear */
                 double E, pu, pk;
                 orc_delo_linear(d, &E, &pu, &pk);
                 I[k] = E * I[u] + pu * S[u] + pk * S[k];
@@ -159,7 +214,11 @@ void orc_ray(int ns, const double *tau, double kappa, int upward, int fs,
         for (k = ns - 2; k >= 0; k--) {
             int u = k + 1;
             double d = kappa * fabs(tau[k] - tau[u]);
-            if (fs == 0) {
+            if (fs == 3 && k > 0) {           /* parabola through u, k, k - 1 */
+                double E, pu, pk, pd;
+                orc_delo_parabolic(d, kappa * fabs(tau[k] - tau[k - 1]), &E, &pu, &pk, &pd);
+                I[k] = E * I[u] + pu * S[u] + pk * S[k] + pd * S[k - 1];
+            } else if (fs == 0 || fs == 3) {
                 double E, pu, pk;
                 orc_delo_linear(d, &E, &pu, &pk);
                 I[k] = E * I[u] + pu * S[u] + pk * S[k];

@@ -35,8 +35,9 @@ SEED_BASE = 211011873
 FS_DELO_LINEAR = 0
 FS_TRAPEZOIDAL = 1
 FS_IMPLICIT_EULER = 2
+FS_DELO_PARABOLIC = 3
 _FS_NAMES = {"delo_linear": FS_DELO_LINEAR, "trapezoidal": FS_TRAPEZOIDAL,
-             "implicit_euler": FS_IMPLICIT_EULER}
+             "implicit_euler": FS_IMPLICIT_EULER, "delo_parabolic": FS_DELO_PARABOLIC}
 
 
 @dataclasses.dataclass

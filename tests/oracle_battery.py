@@ -139,6 +139,35 @@ def chk_sor_ssor_counts():
     return all(out)
 
 
+def chk_delo_parabolic():
+    """DELO-parabolic: coefficients against their defining integrals, a
+    quadratic source integrated exactly, and the operator equal to the dense
+    route on the tiny grid."""
+    for d, dd in ((0.02, 0.05), (0.6, 0.4), (3.0, 9.0)):
+        E, pu, pk, pd = O.delo_parabolic(d, dd)
+        fs = (lambda t: t * (t + dd) / (d * (d + dd)), lambda t: (d - t) * (t + dd) / (d * dd),
+              lambda t: t * (t - d) / (dd * (d + dd)))
+        for got, f in zip((pu, pk, pd), fs):
+            ref = integrate.quad(lambda t: f(t) * np.exp(-t), 0.0, d, epsabs=0.0, epsrel=1e-13)[0]
+            if abs(got - ref) > 1e-12 * (1.0 - E):
+                return False
+    tau = np.logspace(-3, 1.5, 40)
+    s = tau - tau[0]
+    S = 0.3 + 0.7 * s + 0.05 * s * s
+    exact = S - (0.7 + 0.1 * s) + 0.1 - (0.3 - 0.7 + 0.1) * np.exp(-s)
+    I = O.ray(tau, 1.0, False, S, fs=3)
+    if np.abs(I[:-1] - exact[:-1]).max() > 1e-11:
+        return False
+    s_up = tau[-1] - tau
+    S = 0.3 + 0.7 * s_up + 0.05 * s_up * s_up
+    exact = S - (0.7 + 0.1 * s_up) + 0.1 - (0.3 - 0.7 + 0.1) * np.exp(-s_up)
+    I = O.ray(tau, 1.0, True, S, fs=3)
+    if np.abs(I[1:] - exact[1:]).max() > 1e-11:
+        return False
+    p = W.config1_subgrid("delo_parabolic")
+    return np.abs(O.assemble(p) - D.Dense(p).A).max() <= 1e-13
+
+
 def chk_special_cases():
     p = W.config1_subgrid().with_(eps=np.array([1.0]))
     if np.abs(O.assemble(p) - np.eye(p.n_unknowns)).max() != 0.0:
@@ -149,7 +178,8 @@ def chk_special_cases():
 
 
 CHECKS = [chk_moments, chk_delo, chk_trapezoid, chk_implicit_euler, chk_linear_source, chk_dense,
-          chk_solvers_vs_lu, chk_paper_counts, chk_sor_ssor_counts, chk_special_cases]
+          chk_solvers_vs_lu, chk_paper_counts, chk_sor_ssor_counts, chk_delo_parabolic,
+          chk_special_cases]
 
 
 def run():

@@ -74,6 +74,12 @@ MUTATIONS = [
     ("ssor_scale_inverted", "z[i] = z[i] * ((2.0 - om) / om);", "z[i] = z[i] * (om / (2.0 - om));"),
     ("ssor_forward_uses_upper", "for (j = 0; j < i; j++) sum -= A[(size_t)i * n + j] * z[j];",
      "for (j = 0; j < i; j++) sum -= A[(size_t)j * n + i] * z[j];"),
+    ("parab_pd_sign", "*pd = (w[2] - d * w[1])", "*pd = (d * w[1] - w[2])"),
+    ("parab_pu_uses_d", "*pu = (w[2] + dd * w[1])", "*pu = (w[2] + d * w[1])"),
+    ("parab_moment_series", "/ (double)(m + n + 1);", "/ (double)(m + n + 2);"),
+    ("parab_downwind_index", "pd * S[k + 1]", "pd * S[k]"),
+    ("parab_upward_downwind_step", "kappa * fabs(tau[k] - tau[k - 1])",
+     "kappa * fabs(tau[k + 1] - tau[k])"),
     ("bicgstab_beta", "beta = (rho / rho_old) * (alpha / omega);", "beta = (rho / rho_old) * (omega / alpha);"),
     ("bicgstab_omega", "omega = dot(n, t, sv) / tt;", "omega = dot(n, sv, sv) / tt;"),
     ("bicgstab_x_update", "x[i] += alpha * ph[i] + omega * sh[i];", "x[i] += alpha * p[i] + omega * sh[i];"),

@@ -138,6 +138,64 @@ def test_implicit_euler_is_first_order_and_L_stable():
     assert all(1.85 < r < 2.15 for r in rates), rates
 
 
+@pytest.mark.parametrize("d", [1e-7, 1e-3, 0.05, 0.7, 0.999, 1.0, 1.3, 5.0, 60.0])
+@pytest.mark.parametrize("ratio", [0.2, 1.0, 7.0])
+def test_delo_parabolic_coefficients_are_the_defining_integrals(d, ratio):
+    """DELO-parabolic (Sect. 4.1): c_u, c_k, c_d are the integrals of
+    exp(-t) against the quadratic Lagrange basis through t = d (upwind),
+    0 (current) and -dd (downwind), on [0, d]; they sum to 1 - E."""
+    dd = ratio * d
+    E, pu, pk, pd = O.delo_parabolic(d, dd)
+    basis = {
+        "u": lambda t: t * (t + dd) / (d * (d + dd)),
+        "k": lambda t: (d - t) * (t + dd) / (d * dd),
+        "d": lambda t: t * (t - d) / (dd * (d + dd)),
+    }
+    ref = {key: integrate.quad(lambda t, f=f: f(t) * math.exp(-t), 0.0, d, epsabs=0.0,
+                               epsrel=1e-13, limit=200)[0] for key, f in basis.items()}
+    scale = max(1.0 - math.exp(-d), 1e-300)
+    for key, got in (("u", pu), ("k", pk), ("d", pd)):
+        assert abs(got - ref[key]) <= 1e-12 * scale + 1e-300, (key, got, ref[key])
+    assert abs(pu + pk + pd - (-math.expm1(-d))) <= 1e-14 * scale
+    assert E == math.exp(-d)
+
+
+@pytest.mark.parametrize("kappa", [0.37, 1.0, 6.0])
+def test_delo_parabolic_exact_for_quadratic_source(kappa):
+    """With S quadratic in the ray's optical path s, I(s) = P(s) - P(0) e^{-s}
+    + I0 e^{-s} with P = S - S' + S'' solves dI/ds = S - I exactly; the
+    parabola through three nodes is S itself, so every point but the ray's
+    last (where the step is DELO-linear) is exact."""
+    tau = np.logspace(-3, 1.5, 40)
+    a, b, c = 0.3, 0.7, 0.05
+    for upward in (False, True):
+        s = kappa * (tau[-1] - tau) if upward else kappa * (tau - tau[0])
+        S = a + b * s + c * s * s
+        P = S - (b + 2 * c * s) + 2 * c
+        I0 = 0.4
+        exact = P - (a - b + 2 * c) * np.exp(-s) + I0 * np.exp(-s)
+        I = O.ray(tau, kappa, upward, S, I_entry=I0, fs=3)
+        # the upward ray ends at index 0, the downward one at the last index
+        inner = slice(1, len(tau)) if upward else slice(0, -1)
+        assert np.abs(I[inner] - exact[inner]).max() <= 1e-11 * np.abs(exact).max(), upward
+        last = 0 if upward else -1
+        assert abs(I[last] - exact[last]) <= 1e-2 * abs(exact[last])
+
+
+def test_delo_parabolic_is_third_order():
+    """Global error O(h^3) on a smooth source: it drops about eightfold when
+    the step halves (DELO-linear: fourfold)."""
+    errs = []
+    for n in [21, 41, 81, 161]:
+        tau = np.linspace(0.0, 4.0, n)
+        S = np.sin(tau)
+        I = O.ray(tau, 1.0, False, S, I_entry=0.0, fs=3)
+        exact = 0.5 * (np.sin(tau) - np.cos(tau)) + 0.5 * np.exp(-tau)
+        errs.append(np.abs(I - exact).max())
+    rates = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(6.5 < r < 9.5 for r in rates), rates
+
+
 # --------------------------------------------------------------------------
 # Formal solution along a ray (eqs. RTE_delo1/2, boundary conditions Sect. 3.1)
 # --------------------------------------------------------------------------
@@ -161,7 +219,7 @@ def test_delo_linear_exact_for_linear_source(kappa):
     assert np.abs(dn - ex_dn).max() <= 1e-12 * np.abs(ex_dn).max()
 
 
-@pytest.mark.parametrize("fs", [0, 1, 2])
+@pytest.mark.parametrize("fs", [0, 1, 2, 3])
 def test_constant_source_with_matching_inflow_is_stationary(fs):
     tau = np.logspace(-4, 8, 50)
     S = np.full(50, 0.8)
@@ -169,20 +227,24 @@ def test_constant_source_with_matching_inflow_is_stationary(fs):
     assert np.abs(I - 0.8).max() < 1e-14
 
 
-@pytest.mark.parametrize("fs", [0, 1, 2])
+@pytest.mark.parametrize("fs", [0, 1, 2, 3])
 def test_point_source_has_exact_upwind_zeros(fs):
     """A point-like source at z_j leaves the intensity zero on the upwind side
     of the ray and decaying on the downwind side (Sect. 4.4 run-time remarks;
     stated in z, here in tau: mu<0 rays are zero above the source, mu>0 rays
-    zero below it)."""
+    zero below it).  DELO-parabolic's parabola reaches one point further
+    upwind: the point just before the source sees it through c_d."""
     tau = np.logspace(-2, 3, 30)
     j = 13
     S = np.zeros(30)
     S[j] = 1.0
     dn = O.ray(tau, 1.0, False, S, fs=fs)
     up = O.ray(tau, 1.0, True, S, fs=fs)
-    assert np.all(dn[:j] == 0.0) and dn[j] > 0
-    assert np.all(up[j + 1:] == 0.0) and up[j] > 0
+    reach = 1 if fs == 3 else 0
+    assert np.all(dn[:j - reach] == 0.0) and dn[j] > 0
+    assert np.all(up[j + 1 + reach:] == 0.0) and up[j] > 0
+    if fs == 3:
+        assert dn[j - 1] != 0.0 and up[j + 1] != 0.0
     if fs in (0, 2):   # DELO, implicit Euler: nonnegative, decaying past the source's interval
         assert np.all(np.diff(dn[j + 1:]) <= 0) and np.all(dn[j:] >= 0)
         assert np.all(np.diff(up[:j]) >= 0) and np.all(up[:j + 1] >= 0)
@@ -192,9 +254,10 @@ def test_point_source_has_exact_upwind_zeros(fs):
 # The operator against an independently assembled dense route (Sect. 3.2-3.3)
 # --------------------------------------------------------------------------
 
-@pytest.fixture(scope="module", params=[0, 1, 2], ids=["delo", "trap", "euler"])
+@pytest.fixture(scope="module", params=[0, 1, 2, 3], ids=["delo", "trap", "euler", "parab"])
 def sub(request):
-    p = W.config1_subgrid(["delo_linear", "trapezoidal", "implicit_euler"][request.param])
+    p = W.config1_subgrid(["delo_linear", "trapezoidal", "implicit_euler",
+                           "delo_parabolic"][request.param])
     return p, D.Dense(p)
 
 
