@@ -55,6 +55,13 @@ extern "C" {
 #define RT_FS_DELO_LINEAR 0
 #define RT_FS_TRAPEZOIDAL 1
 #define RT_FS_IMPLICIT_EULER 2
+/* DELO-parabolic (Sect. 4.1): the source interpolated by the parabola through
+ * the upwind, current and downwind points of the ray, integrated exactly; the
+ * last point of a ray takes the DELO-linear step.  Without dichroism, as
+ * here, DELOPAR is the same step.  Its operator runs a ray-per-lane FP64
+ * sweep (also in RT_PREC_MIXED); rt_assemble, rt_solve_lu and the SOR/SSOR
+ * preconditioners are not available for it (RT_EINVAL). */
+#define RT_FS_DELO_PARABOLIC 3
 
 /* Arithmetic of the solves.  FP64: every step in FP64.  MIXED: an FP32
  * formal-solver sweep and quadrature inside an inner GMRES, with the outer

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librt.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ENOCONV, RT_EBREAKDOWN = 0, -1, -2, -3, 1, 2
-RT_FS_DELO_LINEAR, RT_FS_TRAPEZOIDAL = 0, 1
+RT_FS_DELO_LINEAR, RT_FS_TRAPEZOIDAL, RT_FS_IMPLICIT_EULER, RT_FS_DELO_PARABOLIC = 0, 1, 2, 3
 RT_PREC_FP64, RT_PREC_MIXED = 0, 1
 RT_PC_JACOBI, RT_PC_SOR, RT_PC_SSOR = 0, 1, 2
 RT_MAX_NS = 2048

@@ -117,11 +117,10 @@ int validate(const rt_problem *p, const rt_options *o, std::vector<double> &mu_p
     if (p->B)
         for (long long k = 0; k < total; ++k)
             if (!finite(p->B[k])) return fail(RT_EINVAL, idx("B", k) + " is not finite");
-    if (p->formal_solver != RT_FS_DELO_LINEAR && p->formal_solver != RT_FS_TRAPEZOIDAL &&
-        p->formal_solver != RT_FS_IMPLICIT_EULER)
+    if (p->formal_solver < RT_FS_DELO_LINEAR || p->formal_solver > RT_FS_DELO_PARABOLIC)
         return fail(RT_EINVAL,
-                    "formal_solver must be RT_FS_DELO_LINEAR, RT_FS_TRAPEZOIDAL or "
-                    "RT_FS_IMPLICIT_EULER");
+                    "formal_solver must be RT_FS_DELO_LINEAR, RT_FS_TRAPEZOIDAL, "
+                    "RT_FS_IMPLICIT_EULER or RT_FS_DELO_PARABOLIC");
     if (o) {
         if (o->precision != RT_PREC_FP64 && o->precision != RT_PREC_MIXED)
             return fail(RT_EINVAL, "options.precision must be RT_PREC_FP64 or RT_PREC_MIXED");
@@ -240,6 +239,7 @@ hipError_t apply_sweep(rt_handle *h, const double *in, const double *scale, cons
 
 hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, double *out,
                           const int *mask, bool fp32, int mode, hipStream_t s) {
+    if (h->fs == RT_FS_DELO_PARABOLIC) return apply_ray_operator(h, in, scale, out, mask, mode, s);
     const SweepArgs a = sweep_args(h, in, scale, out, mask, fp32, mode);
     int W;
     bool pf;
@@ -326,7 +326,8 @@ void rt_destroy(rt_handle *h) {
                     h->d_r,     h->d_rh,    h->d_p,       h->d_v,       h->d_s,      h->d_t,
                     h->d_cq,    h->d_state, h->d_active,  h->d_cycle,   h->d_count,
                     h->d_ew,    h->d_asm_dg, h->d_asm_sc, h->d_asm_task, h->d_A,
-                    h->d_pz,    h->d_ones,  h->d_LU,      h->d_piv,     h->d_sing};
+                    h->d_pz,    h->d_ones,  h->d_LU,      h->d_piv,     h->d_sing,
+                    h->d_rpart};
     clear_graphs(h);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
     for (hipEvent_t e : h->gev)
@@ -503,6 +504,8 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     RT_TRY(dalloc(&h->d_diag, h->n_unk));
     RT_TRY(dalloc(&h->d_dinv, h->n_unk));
     RT_TRY(dalloc(&h->d_b, h->n_unk));
+    if (h->fs == RT_FS_DELO_PARABOLIC)
+        RT_TRY(dalloc(&h->d_rpart, (size_t)ray_slots(h) * 2 * acc));
     RT_TRY(h2d(h->d_tau, p->tau, acc));
     RT_TRY(h2d(h->d_B, B.data(), acc));
     RT_TRY(h2d(h->d_opac, p->opac, nphi));
@@ -650,6 +653,8 @@ int rt_assembled_size(const rt_handle *h, long long *count) {
 
 int rt_assemble(rt_handle *h, double *A_out, void *stream) {
     if (!h || !A_out) return fail(RT_EINVAL, "NULL handle or output");
+    if (h->fs == RT_FS_DELO_PARABOLIC)
+        return fail(RT_EINVAL, "rt_assemble supports the two-point formal solvers only");
     if (!aligned16(A_out)) return fail(RT_EINVAL, "output must be 16-byte aligned");
     return assemble(h, A_out, (hipStream_t)stream);
 }

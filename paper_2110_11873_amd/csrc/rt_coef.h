@@ -96,4 +96,96 @@ __device__ inline void step_ew(int fs, double d, double &E, double &w) {
     w = E + cu;
 }
 
+// --------------------------------------------------------------------------
+// DELO-parabolic step (Sect. 4.1; without dichroism DELOPAR is the same
+// step).  t is the optical path from the current point back to the upwind
+// one (t = d there); the source is the parabola through the upwind, current
+// and downwind (t = -dd) points, and the coefficients are the integrals of
+// exp(-t) against its Lagrange basis:
+//   c_u = (w2 + dd w1) / (d (d + dd)),  c_k = ((d - dd) w1 + d dd w0 - w2) / (d dd),
+//   c_d = (w2 - d w1) / (dd (d + dd)),
+// with the moments w_n = int_0^d t^n exp(-t) dt: 1 - E, 1 - (1 + d) E,
+// 2 - (d^2 + 2d + 2) E, or below d = 1 their series
+// sum_m (-1)^m d^(m+n+1) / (m! (m+n+1)), summed by Horner's rule.
+// --------------------------------------------------------------------------
+namespace {
+
+constexpr int kMomentTerms = 22;  // d < 1: the last term is below 1e-21
+
+struct MomentSeries {
+    double c[3][kMomentTerms];
+};
+
+constexpr MomentSeries make_moment_series() {
+    MomentSeries s{};
+    double fact = 1.0;  // m!
+    for (int m = 0; m < kMomentTerms; ++m) {
+        if (m > 0) fact *= m;
+        const double sgn = (m % 2 == 0) ? 1.0 : -1.0;
+        for (int n = 0; n < 3; ++n) s.c[n][m] = sgn / (fact * (m + n + 1));
+    }
+    return s;
+}
+
+__constant__ MomentSeries c_moments = make_moment_series();
+
+}  // namespace
+
+__device__ inline void exp_moments(double d, double &E, double &w0, double &w1, double &w2) {
+    E = exp(-d);
+    if (d < 1.0) {
+        double p0 = c_moments.c[0][kMomentTerms - 1];
+        double p1 = c_moments.c[1][kMomentTerms - 1];
+        double p2 = c_moments.c[2][kMomentTerms - 1];
+#pragma unroll
+        for (int m = kMomentTerms - 2; m >= 0; --m) {
+            p0 = fma(p0, d, c_moments.c[0][m]);
+            p1 = fma(p1, d, c_moments.c[1][m]);
+            p2 = fma(p2, d, c_moments.c[2][m]);
+        }
+        w0 = p0 * d;
+        w1 = p1 * d * d;
+        w2 = p2 * d * d * d;
+    } else {
+        w0 = -expm1(-d);
+        w1 = 1.0 - (1.0 + d) * E;
+        w2 = 2.0 - (d * d + 2.0 * d + 2.0) * E;
+    }
+}
+
+__device__ inline void parabolic_coef(double d, double dd, double &E, double &cu, double &ck,
+                                      double &cd) {
+    double w0, w1, w2;
+    exp_moments(d, E, w0, w1, w2);
+    cu = (w2 + dd * w1) / (d * (d + dd));
+    ck = ((d - dd) * w1 + d * dd * w0 - w2) / (d * dd);
+    cd = (w2 - d * w1) / (dd * (d + dd));
+}
+
+// Step of a ray from its upwind point u to point k (optical step d), with the
+// downwind point's step dd when k is not the ray's last point: I_k = E I_u +
+// c_u S_u + c_k S_k + c_d S_dn (c_d = 0 but for DELO-parabolic).
+__device__ inline void ray_step(int fs, double d, double dd, bool has_dn, double &E,
+                                double &cu, double &ck, double &cd) {
+    cd = 0.0;
+    if (fs == RT_FS_DELO_PARABOLIC && has_dn) {
+        parabolic_coef(d, dd, E, cu, ck, cd);
+        return;
+    }
+    if (fs == RT_FS_TRAPEZOIDAL) {
+        const double h = 0.5 * d;
+        E = (1.0 - h) / (1.0 + h);
+        cu = ck = h / (1.0 + h);
+        return;
+    }
+    if (fs == RT_FS_IMPLICIT_EULER) {
+        E = 1.0 / (1.0 + d);
+        cu = 0.0;
+        ck = d / (1.0 + d);
+        return;
+    }
+    step_coef(RT_FS_DELO_LINEAR, d, cu, ck);
+    E = exp(-d);
+}
+
 }  // namespace rt

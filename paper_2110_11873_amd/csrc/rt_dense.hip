@@ -437,6 +437,8 @@ hipError_t fill(double *v, long long n, double c, hipStream_t s) {
 
 int lu_factor(rt_handle *h, hipStream_t s) {
     if (h->lu_ready) return RT_OK;
+    if (h->fs == RT_FS_DELO_PARABOLIC)
+        return fail(RT_EINVAL, "the LU route supports the two-point formal solvers only");
     const size_t bytes = sizeof(double) * (size_t)std::max<long long>(h->n_dense, 1);
     if (!h->d_LU) {
         if (hipMalloc((void **)&h->d_LU, bytes) != hipSuccess ||
@@ -476,6 +478,8 @@ hipError_t lu_solve(const rt_handle *h, const double *b, double *x, hipStream_t 
 
 int ensure_dense(rt_handle *h, hipStream_t s) {
     if (h->dense_ready) return RT_OK;
+    if (h->fs == RT_FS_DELO_PARABOLIC)
+        return fail(RT_EINVAL, "SOR and SSOR support the two-point formal solvers only");
     if (!h->d_A) {
         if (hipMalloc((void **)&h->d_A, sizeof(double) * (size_t)std::max<long long>(h->n_dense, 1)) !=
             hipSuccess) {

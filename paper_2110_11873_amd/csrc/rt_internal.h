@@ -219,6 +219,7 @@ struct rt_handle {
     float2 *d_coef32 = nullptr;
     double *d_partial = nullptr;
     double *d_diag = nullptr, *d_dinv = nullptr, *d_b = nullptr;
+    double *d_rpart = nullptr;    // ray-per-lane sweep: per-wavefront quadrature slots
     long long n_dense = 0;        // entries of the assembled A: sum over slabs of (2 ns)^2
     long long n_ew = 0;           // entries of the assembly coefficient table
 
@@ -272,6 +273,13 @@ hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, d
 // sums in h->d_partial for a consumer that applies the scattering step itself.
 hipError_t apply_sweep(rt_handle *h, const double *in, const double *scale, const int *mask,
                        bool fp32, hipStream_t s);
+
+// The operator with the ray-per-lane FP64 sweep (formal solvers with a
+// three-point stencil, rt_raysweep.hip): same contract as apply_operator.
+hipError_t apply_ray_operator(rt_handle *h, const double *in, const double *scale, double *out,
+                              const int *mask, int mode, hipStream_t s);
+// Quadrature slots per slab of that sweep (two per wavefront of rays).
+int ray_slots(const rt_handle *h);
 
 // Destroy the handle's captured solver graphs.
 void clear_graphs(rt_handle *h);

@@ -1180,7 +1180,9 @@ struct Driver {
     }
 
     // the fused Arnoldi step covers every slab and the restart length
-    bool fused() const { return h->ns_max <= NTF && h->ws_restart < MR; }
+    bool fused() const {
+        return h->ns_max <= NTF && h->ws_restart < MR && h->fs != RT_FS_DELO_PARABOLIC;
+    }
 
     // sweep of A P^-1 v_j, then the Arnoldi step (fused or not)
     void arnoldi_step(const VecArgs &a, int j, bool fp32) {
