@@ -89,6 +89,9 @@ def lib():
             L.orc_rhs.argtypes = [P, D]
             L.orc_diag.argtypes = [P, C.c_int, I, D]
             L.orc_assemble.argtypes = [P, D]
+            L.orc_apply_I.argtypes = [P, D, D]
+            L.orc_rhs_I.argtypes = [P, D]
+            L.orc_sigma_from_I.argtypes = [P, D, D]
             Q = C.POINTER(_Prec)
             L.orc_gmres.argtypes = [P, D, D, Q, C.c_int, C.c_double, C.c_int, I, I, D, D, C.c_int,
                                     C.c_int]
@@ -96,6 +99,7 @@ def lib():
             L.orc_richardson.argtypes = [P, D, D, Q, C.c_double, C.c_int, I, I, D]
             L.orc_cgs.argtypes = [P, D, D, Q, C.c_double, C.c_int, I, I, D]
             for f in ("orc_apply", "orc_rhs", "orc_diag", "orc_assemble", "orc_gmres",
+                      "orc_apply_I", "orc_rhs_I", "orc_sigma_from_I",
                       "orc_bicgstab", "orc_richardson", "orc_cgs"):
                 getattr(L, f).restype = C.c_int
             _lib = L
@@ -254,6 +258,41 @@ def assemble(prob, i=0):
     A = np.empty((n, n))
     lib().orc_assemble(v.ref, _dp(A))
     return A
+
+
+# ----------------------------------------------------------------------------
+# the field as unknown (eq. crd_linear_system2), one slab at a time; field
+# index ((st * nmu + m) * nnu + p) * ns + k, st = 0 for I, 1 for Q
+# ----------------------------------------------------------------------------
+
+def field_size(prob, i=0):
+    return 2 * int(prob.ns[i]) * len(prob.mu) * len(prob.w_nu)
+
+
+def apply_I(prob, field, i=0):
+    """(Id - Lambda T J) I for slab i."""
+    v = _SlabView(prob, i)
+    f = np.ascontiguousarray(field, dtype=np.float64)
+    out = np.empty_like(f)
+    lib().orc_apply_I(v.ref, _dp(f), _dp(out))
+    return out
+
+
+def rhs_I(prob, i=0):
+    """Lambda T c + t for slab i."""
+    v = _SlabView(prob, i)
+    out = np.empty(field_size(prob, i))
+    lib().orc_rhs_I(v.ref, _dp(out))
+    return out
+
+
+def sigma_from_I(prob, field, i=0):
+    """sigma = J I + c for slab i."""
+    v = _SlabView(prob, i)
+    f = np.ascontiguousarray(field, dtype=np.float64)
+    out = np.empty(2 * int(prob.ns[i]))
+    lib().orc_sigma_from_I(v.ref, _dp(f), _dp(out))
+    return out
 
 
 # ----------------------------------------------------------------------------

@@ -313,6 +313,113 @@ int orc_apply(const orc_slab *s, const double *sin, double *sout)
 }
 
 /* ------------------------------------------------------------------------
+ * The alternative formulation with the Stokes field as unknown (eq.
+ * crd_linear_system2): (Id - Lambda T J) I = Lambda T c + t, and sigma =
+ * J I + c.  Field index ((st * nmu + m) * nnu + p) * ns + k, st = 0 for I,
+ * 1 for Q.  J maps the field to xi [J00, W2 J20] (eqs. J00/J02, S00/S02),
+ * T the multipolar components to the source functions, Lambda is the formal
+ * solution with zero incoming radiation, t the transmitted field.
+ * ---------------------------------------------------------------------- */
+static void field_J(const orc_slab *s, const double *q, const double *F, double *sig)
+{
+    int ns = s->ns, nmu = s->nmu, nnu = s->nnu, k, m, p;
+    double xi = 1.0 - s->eps;
+    for (k = 0; k < 2 * ns; k++) sig[k] = 0.0;
+    for (m = 0; m < nmu; m++) {
+        double t1, t2;
+        orc_t20(s->mu[m], &t1, &t2);
+        for (p = 0; p < nnu; p++) {
+            const double *I = F + ((size_t)(0 * nmu + m) * nnu + p) * ns;
+            const double *Q = F + ((size_t)(1 * nmu + m) * nnu + p) * ns;
+            double w = q[m * nnu + p];
+            for (k = 0; k < ns; k++) {
+                sig[2 * k] += w * I[k];
+                sig[2 * k + 1] += w * (t1 * I[k] + t2 * Q[k]);
+            }
+        }
+    }
+    for (k = 0; k < ns; k++) {
+        sig[2 * k] *= xi;
+        sig[2 * k + 1] *= xi * s->W2;
+    }
+}
+
+/* F = Lambda T sig, plus the transmitted field t when with_t is set. */
+static int field_from_sigma(const orc_slab *s, const double *sig, int with_t, double *F)
+{
+    int ns = s->ns, nmu = s->nmu, nnu = s->nnu, k, m, p;
+    double *SI = (double *)malloc(sizeof(double) * ns);
+    double *SQ = (double *)malloc(sizeof(double) * ns);
+    if (!SI || !SQ) { free(SI); free(SQ); return -1; }
+    for (m = 0; m < nmu; m++) {
+        double t1, t2;
+        int upward = s->mu[m] > 0.0;
+        orc_t20(s->mu[m], &t1, &t2);
+        for (k = 0; k < ns; k++) {
+            SI[k] = sig[2 * k] + t1 * sig[2 * k + 1];
+            SQ[k] = t2 * sig[2 * k + 1];
+        }
+        for (p = 0; p < nnu; p++) {
+            double kappa = s->opac[p] / fabs(s->mu[m]);
+            double inflow = (with_t && upward) ? s->Ibot : 0.0;
+            orc_ray(ns, s->tau, kappa, upward, s->fs, SI, inflow,
+                    F + ((size_t)(0 * nmu + m) * nnu + p) * ns);
+            orc_ray(ns, s->tau, kappa, upward, s->fs, SQ, 0.0,
+                    F + ((size_t)(1 * nmu + m) * nnu + p) * ns);
+        }
+    }
+    free(SI); free(SQ);
+    return 0;
+}
+
+/* Iout = Iin - Lambda T J Iin. */
+int orc_apply_I(const orc_slab *s, const double *Iin, double *Iout)
+{
+    size_t n = (size_t)2 * s->ns * s->nmu * s->nnu, i;
+    double *q = (double *)malloc(sizeof(double) * s->nmu * s->nnu);
+    double *sig = (double *)malloc(sizeof(double) * 2 * s->ns);
+    double *F = (double *)malloc(sizeof(double) * n);
+    int rc = -1;
+    if (q && sig && F) {
+        orc_weights(s, q);
+        field_J(s, q, Iin, sig);
+        rc = field_from_sigma(s, sig, 0, F);
+        for (i = 0; i < n && rc == 0; i++) Iout[i] = Iin[i] - F[i];
+    }
+    free(q); free(sig); free(F);
+    return rc;
+}
+
+/* bI = Lambda T c + t, c = [eps B, 0]. */
+int orc_rhs_I(const orc_slab *s, double *bI)
+{
+    int k;
+    double *c = (double *)malloc(sizeof(double) * 2 * s->ns);
+    int rc;
+    if (!c) return -1;
+    for (k = 0; k < s->ns; k++) {
+        c[2 * k] = s->eps * s->B[k];
+        c[2 * k + 1] = 0.0;
+    }
+    rc = field_from_sigma(s, c, 1, bI);
+    free(c);
+    return rc;
+}
+
+/* sigma = J I + c. */
+int orc_sigma_from_I(const orc_slab *s, const double *I, double *sigma)
+{
+    int k;
+    double *q = (double *)malloc(sizeof(double) * s->nmu * s->nnu);
+    if (!q) return -1;
+    orc_weights(s, q);
+    field_J(s, q, I, sigma);
+    for (k = 0; k < s->ns; k++) sigma[2 * k] += s->eps * s->B[k];
+    free(q);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
  * Right-hand side b = J t + c (eq. crd_linear_system): t is the radiation
  * transmitted from the boundaries (S = 0, I = Ibot entering at the bottom
  * for mu > 0, I = 0 entering at the top, Q = 0 everywhere), c = [eps B, 0].

@@ -168,6 +168,18 @@ def chk_delo_parabolic():
     return np.abs(O.assemble(p) - D.Dense(p).A).max() <= 1e-13
 
 
+def chk_field_formulation():
+    """Field-unknown operator, right-hand side and sigma recovery (eq.
+    crd_linear_system2) against the dense route."""
+    p = W.config1_subgrid()
+    d = D.Dense(p)
+    K = np.eye(d.Lam.shape[0]) - d.Lam @ d.T @ d.J
+    f = np.random.default_rng(0).uniform(-1, 1, K.shape[0])
+    return (np.abs(O.apply_I(p, f) - K @ f).max() <= 1e-13
+            and np.abs(O.rhs_I(p) - (d.Lam @ d.T @ d.c + d.t)).max() <= 1e-14
+            and np.abs(O.sigma_from_I(p, f) - (d.J @ f + d.c)).max() <= 1e-13)
+
+
 def chk_special_cases():
     p = W.config1_subgrid().with_(eps=np.array([1.0]))
     if np.abs(O.assemble(p) - np.eye(p.n_unknowns)).max() != 0.0:
@@ -179,7 +191,7 @@ def chk_special_cases():
 
 CHECKS = [chk_moments, chk_delo, chk_trapezoid, chk_implicit_euler, chk_linear_source, chk_dense,
           chk_solvers_vs_lu, chk_paper_counts, chk_sor_ssor_counts, chk_delo_parabolic,
-          chk_special_cases]
+          chk_field_formulation, chk_special_cases]
 
 
 def run():

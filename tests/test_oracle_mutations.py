@@ -80,6 +80,11 @@ MUTATIONS = [
     ("parab_downwind_index", "pd * S[k + 1]", "pd * S[k]"),
     ("parab_upward_downwind_step", "kappa * fabs(tau[k] - tau[k - 1])",
      "kappa * fabs(tau[k + 1] - tau[k])"),
+    ("field_J_drops_xi", "        sig[2 * k] *= xi;\n", ""),
+    ("field_rhs_no_inflow", "double inflow = (with_t && upward) ? s->Ibot : 0.0;",
+     "double inflow = 0.0;"),
+    ("field_apply_sign", "Iout[i] = Iin[i] - F[i];", "Iout[i] = Iin[i] + F[i];"),
+    ("field_sigma_drops_c", "for (k = 0; k < s->ns; k++) sigma[2 * k] += s->eps * s->B[k];", ""),
     ("bicgstab_beta", "beta = (rho / rho_old) * (alpha / omega);", "beta = (rho / rho_old) * (omega / alpha);"),
     ("bicgstab_omega", "omega = dot(n, t, sv) / tt;", "omega = dot(n, sv, sv) / tt;"),
     ("bicgstab_x_update", "x[i] += alpha * ph[i] + omega * sh[i];", "x[i] += alpha * p[i] + omega * sh[i];"),

@@ -283,6 +283,24 @@ def test_I_formulation_gives_same_sigma(sub):
     assert np.abs(s1 - s2).max() <= 1e-12 * np.abs(s1).max()
 
 
+def test_field_formulation_equals_dense(sub):
+    """The field-unknown operator, right-hand side and sigma = J I + c of eq.
+    crd_linear_system2 against the dense route's explicit matrices; and the
+    field I = Lambda T sigma* + t of the sigma solution solves it."""
+    p, d = sub
+    K = np.eye(d.Lam.shape[0]) - d.Lam @ d.T @ d.J
+    for seed in range(2):
+        f = np.random.default_rng(seed).uniform(-1, 1, K.shape[0])
+        assert np.abs(O.apply_I(p, f) - K @ f).max() <= 1e-13 * np.abs(f).max()
+        assert np.abs(O.sigma_from_I(p, f) - (d.J @ f + d.c)).max() <= 1e-13
+    bI = O.rhs_I(p)
+    assert np.abs(bI - (d.Lam @ d.T @ d.c + d.t)).max() <= 1e-14
+    sig = d.solve()
+    Istar = d.Lam @ d.T @ sig + d.t
+    assert np.abs(O.apply_I(p, Istar) - bI).max() <= 1e-11 * np.abs(bI).max()
+    assert np.abs(O.sigma_from_I(p, Istar) - sig).max() <= 1e-11 * np.abs(sig).max()
+
+
 def test_solvers_agree_with_LU(sub):
     p, d = sub
     ref = d.solve()
