@@ -96,6 +96,27 @@ int rt_solve_lu(rt_handle *h, const double *b, double *x, rt_solve_info *info, v
 int rt_precond_apply(rt_handle *h, const double *v, double *z, void *stream);
 
 /*
+ * The Stokes field as unknown (eq. crd_linear_system2): (Id - Lambda T J) I =
+ * Lambda T c + t, whose solution gives sigma = J I + c.  A field vector holds,
+ * per slab (slabs concatenated in ns order), I then Q at every depth, every mu
+ * of the caller's mu array and every frequency:
+ *   index  2 n_mu n_nu doff_s + ((st ns_s + k) n_mu + m) n_nu + p,  st = 0 (I), 1 (Q),
+ * so that a depth's rays are contiguous.  J maps a field to xi [J00, W2 J20]
+ * (eqs. J00/J02 with S00/S02), T the multipolar components to the source
+ * functions, Lambda is the formal solution with zero incoming radiation and t
+ * the transmitted field (I_bot entering at the bottom for mu > 0).
+ * rt_field_size: the number of doubles of a field, 2 n_mu n_nu sum ns.
+ * rt_apply_op_field: I_out = (Id - Lambda T J) I_in; device arrays that must
+ *   not alias.  rt_get_rhs_field: b_field = Lambda T c + t.
+ * rt_sigma_from_field: sigma (length N) = J I + c.
+ * All FP64 and stream-ordered (the formal solver runs one lane per ray).
+ */
+int rt_field_size(const rt_handle *h, long long *count);
+int rt_apply_op_field(rt_handle *h, const double *I_in, double *I_out, void *stream);
+int rt_get_rhs_field(rt_handle *h, double *b_field, void *stream);
+int rt_sigma_from_field(rt_handle *h, const double *I, double *sigma, void *stream);
+
+/*
  * Run the validation of rt_setup on (p, o) without touching any device:
  * RT_OK or RT_EINVAL with the message in rt_last_error().  o may be NULL.
  */

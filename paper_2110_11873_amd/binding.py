@@ -32,7 +32,8 @@ EXPORTS = ["rt_default_options", "rt_setup", "rt_destroy", "rt_num_unknowns", "r
            "rt_solve_bicgstab", "rt_solve_richardson", "rt_solve_cgs", "rt_last_error",
            "rt_apply_op_fp32",
            "rt_plan_info", "rt_sweep_config", "rt_validate", "rt_assembled_size", "rt_assemble",
-           "rt_precond_apply", "rt_solve_lu"]
+           "rt_precond_apply", "rt_solve_lu", "rt_field_size", "rt_apply_op_field",
+           "rt_get_rhs_field", "rt_sigma_from_field"]
 
 
 class RTError(RuntimeError):
@@ -100,6 +101,10 @@ def lib():
         L.rt_sweep_config.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.rt_validate.argtypes = [C.POINTER(rt_problem), C.POINTER(rt_options)]
         L.rt_assembled_size.argtypes = [vp, C.POINTER(C.c_longlong)]
+        L.rt_field_size.argtypes = [vp, C.POINTER(C.c_longlong)]
+        L.rt_apply_op_field.argtypes = [vp, vp, vp, vp]
+        L.rt_get_rhs_field.argtypes = [vp, vp, vp]
+        L.rt_sigma_from_field.argtypes = [vp, vp, vp, vp]
         L.rt_assemble.argtypes = [vp, vp, vp]
         _ = dp
         _lib = L
@@ -259,6 +264,36 @@ class Handle:
         c = self.sweep_config(fp32)
         return "rt::sweep::sweep_kernel<%s, %d, %d, %d>" % (
             "float" if fp32 else "double", self.plan_info()["chunk"], c["waves"], c["prefetch"])
+
+    # -- the field as unknown ------------------------------------------------------
+    def field_size(self):
+        n = C.c_longlong()
+        _check(lib().rt_field_size(self._h, C.byref(n)))
+        return n.value
+
+    def _new_field(self):
+        import torch
+        return torch.empty(self.field_size(), dtype=torch.float64, device="cuda")
+
+    def apply_op_field(self, I_in, I_out=None, stream=None):
+        """(Id - Lambda T J) I (rt_apply_op_field)."""
+        out = self._new_field() if I_out is None else I_out
+        _check(lib().rt_apply_op_field(self._h, C.c_void_p(_ptr(I_in)), C.c_void_p(_ptr(out)),
+                                       _stream(stream)))
+        return out
+
+    def get_rhs_field(self, stream=None):
+        """Lambda T c + t (rt_get_rhs_field)."""
+        b = self._new_field()
+        _check(lib().rt_get_rhs_field(self._h, C.c_void_p(_ptr(b)), _stream(stream)))
+        return b
+
+    def sigma_from_field(self, I, stream=None):
+        """sigma = J I + c (rt_sigma_from_field)."""
+        out = self._new()
+        _check(lib().rt_sigma_from_field(self._h, C.c_void_p(_ptr(I)), C.c_void_p(_ptr(out)),
+                                         _stream(stream)))
+        return out
 
     # -- dense route -------------------------------------------------------------
     def assembled_size(self):

@@ -41,7 +41,7 @@ std::string idx(const char *name, long long i) {
 // Validation of the problem and options.  Pure host code: no HIP call.
 // On success fills the positive half of the symmetric direction set.
 int validate(const rt_problem *p, const rt_options *o, std::vector<double> &mu_pos,
-             std::vector<double> &w_pos) {
+             std::vector<double> &w_pos, std::vector<int> *mu_index = nullptr) {
     if (!p) return fail(RT_EINVAL, "problem is NULL");
     if (p->n_atm < 1) return fail(RT_EINVAL, "n_atm must be >= 1");
     if (!p->ns || !p->tau || !p->mu || !p->w_mu || !p->w_nu || !p->phi || !p->opac || !p->eps ||
@@ -92,6 +92,11 @@ int validate(const rt_problem *p, const rt_options *o, std::vector<double> &mu_p
             return fail(RT_EINVAL, "w_mu must be equal for mu and -mu");
         mu_pos[i] = mp;
         w_pos[i] = p->w_mu[hi];
+        if (mu_index) {  // where the pair sits in the caller's mu array
+            mu_index->resize(2 * M);
+            (*mu_index)[2 * i] = lo;
+            (*mu_index)[2 * i + 1] = hi;
+        }
     }
     if (p->n_nu < 1 || p->n_nu > (1 << 20)) return fail(RT_EINVAL, "n_nu must be >= 1");
     for (int q = 0; q < p->n_nu; ++q)
@@ -327,7 +332,7 @@ void rt_destroy(rt_handle *h) {
                     h->d_cq,    h->d_state, h->d_active,  h->d_cycle,   h->d_count,
                     h->d_ew,    h->d_asm_dg, h->d_asm_sc, h->d_asm_task, h->d_A,
                     h->d_pz,    h->d_ones,  h->d_LU,      h->d_piv,     h->d_sing,
-                    h->d_rpart};
+                    h->d_rpart, h->d_mu_idx, h->d_fsig};
     clear_graphs(h);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
     for (hipEvent_t e : h->gev)
@@ -345,7 +350,8 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     rt_default_options(&opt);
     if (o) opt = *o;
     std::vector<double> mu_pos, w_pos;
-    int rc = validate(p, &opt, mu_pos, w_pos);
+    std::vector<int> mu_index;
+    int rc = validate(p, &opt, mu_pos, w_pos, &mu_index);
     if (rc != RT_OK) return rc;
 
     // ---- device
@@ -488,6 +494,8 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     RT_TRY(dalloc(&h->d_opac, nphi));
     RT_TRY(dalloc(&h->d_phi, nphi));
     RT_TRY(dalloc(&h->d_mu_pos, h->M));
+    RT_TRY(dalloc(&h->d_mu_idx, (size_t)2 * h->M));
+    RT_TRY(dalloc(&h->d_fsig, (size_t)2 * acc));
     RT_TRY(dalloc(&h->d_w_pos, h->M));
     RT_TRY(dalloc(&h->d_w_nu, h->n_nu));
     RT_TRY(dalloc(&h->d_pt_atm, acc));
@@ -511,6 +519,7 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     RT_TRY(h2d(h->d_opac, p->opac, nphi));
     RT_TRY(h2d(h->d_phi, p->phi, nphi));
     RT_TRY(h2d(h->d_mu_pos, mu_pos.data(), h->M));
+    RT_TRY(h2d(h->d_mu_idx, mu_index.data(), (size_t)2 * h->M));
     RT_TRY(h2d(h->d_w_pos, w_pos.data(), h->M));
     RT_TRY(h2d(h->d_w_nu, p->w_nu, h->n_nu));
     RT_TRY(h2d(h->d_pt_atm, pt_atm.data(), acc));
@@ -657,6 +666,28 @@ int rt_assemble(rt_handle *h, double *A_out, void *stream) {
         return fail(RT_EINVAL, "rt_assemble supports the two-point formal solvers only");
     if (!aligned16(A_out)) return fail(RT_EINVAL, "output must be 16-byte aligned");
     return assemble(h, A_out, (hipStream_t)stream);
+}
+
+int rt_field_size(const rt_handle *h, long long *count) {
+    if (!h || !count) return fail(RT_EINVAL, "NULL handle or count");
+    *count = 2LL * h->n_mu * h->n_nu * h->ns_total;
+    return RT_OK;
+}
+
+int rt_apply_op_field(rt_handle *h, const double *I_in, double *I_out, void *stream) {
+    if (!h || !I_in || !I_out) return fail(RT_EINVAL, "NULL handle or vector");
+    if (I_in == I_out) return fail(RT_EINVAL, "I_in and I_out must not alias");
+    return hip_check(apply_field_operator(h, I_in, I_out, (hipStream_t)stream), "rt_apply_op_field");
+}
+
+int rt_get_rhs_field(rt_handle *h, double *b_field, void *stream) {
+    if (!h || !b_field) return fail(RT_EINVAL, "NULL handle or vector");
+    return hip_check(field_rhs(h, b_field, (hipStream_t)stream), "rt_get_rhs_field");
+}
+
+int rt_sigma_from_field(rt_handle *h, const double *I, double *sigma, void *stream) {
+    if (!h || !I || !sigma) return fail(RT_EINVAL, "NULL handle or vector");
+    return hip_check(field_sigma(h, I, sigma, 1, (hipStream_t)stream), "rt_sigma_from_field");
 }
 
 // Validation only, without touching the device (tests of the error paths).

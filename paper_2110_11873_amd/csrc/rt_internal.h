@@ -220,6 +220,8 @@ struct rt_handle {
     double *d_partial = nullptr;
     double *d_diag = nullptr, *d_dinv = nullptr, *d_b = nullptr;
     double *d_rpart = nullptr;    // ray-per-lane sweep: per-wavefront quadrature slots
+    int *d_mu_idx = nullptr;      // per |mu| index m: caller's index of -mu (2m) and +mu (2m+1)
+    double *d_fsig = nullptr;     // field formulation: J I, 2 values per depth point
     long long n_dense = 0;        // entries of the assembled A: sum over slabs of (2 ns)^2
     long long n_ew = 0;           // entries of the assembly coefficient table
 
@@ -278,6 +280,11 @@ hipError_t apply_sweep(rt_handle *h, const double *in, const double *scale, cons
 // three-point stencil, rt_raysweep.hip): same contract as apply_operator.
 hipError_t apply_ray_operator(rt_handle *h, const double *in, const double *scale, double *out,
                               const int *mask, int mode, hipStream_t s);
+// The field as unknown (eq. crd_linear_system2, rt_field.hip): out = (Id -
+// Lambda T J) in; b = Lambda T c + t; sigma = J I (+ c when with_c).
+hipError_t apply_field_operator(rt_handle *h, const double *in, double *out, hipStream_t s);
+hipError_t field_rhs(rt_handle *h, double *b, hipStream_t s);
+hipError_t field_sigma(rt_handle *h, const double *I, double *sigma, int with_c, hipStream_t s);
 // Quadrature slots per slab of that sweep (two per wavefront of rays).
 int ray_slots(const rt_handle *h);
 
