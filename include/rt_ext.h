@@ -117,6 +117,22 @@ int rt_get_rhs_field(rt_handle *h, double *b_field, void *stream);
 int rt_sigma_from_field(rt_handle *h, const double *I, double *sigma, void *stream);
 
 /*
+ * Solve the field system with unpreconditioned GMRES(options.restart)
+ * (Sect. 2.1; Sect. 3.2 expects this larger, sparser system to suit Krylov
+ * methods).  Each slab is its own system, tested on ||b - K I|| / ||b|| <
+ * options.rtol within options.maxit Arnoldi steps.  b_field NULL means the
+ * handle's own Lambda T c + t; I (device, rt_field_size doubles) holds the
+ * initial guess and receives the solution; b_field and I must not alias.
+ * info[i] (host, n_atm entries, or NULL): status (RT_OK or RT_ENOCONV),
+ * Arnoldi steps, the batch's operator applications (an upper bound for the
+ * slab) and the explicit relative residual.  Workspace of (restart + 2)
+ * fields is allocated for the call and released; RT_ENOMEM if it does not
+ * fit.  Synchronizes the stream.
+ */
+int rt_solve_field_gmres(rt_handle *h, const double *b_field, double *I, rt_solve_info *info,
+                         void *stream);
+
+/*
  * Run the validation of rt_setup on (p, o) without touching any device:
  * RT_OK or RT_EINVAL with the message in rt_last_error().  o may be NULL.
  */

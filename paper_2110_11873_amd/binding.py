@@ -33,7 +33,7 @@ EXPORTS = ["rt_default_options", "rt_setup", "rt_destroy", "rt_num_unknowns", "r
            "rt_apply_op_fp32",
            "rt_plan_info", "rt_sweep_config", "rt_validate", "rt_assembled_size", "rt_assemble",
            "rt_precond_apply", "rt_solve_lu", "rt_field_size", "rt_apply_op_field",
-           "rt_get_rhs_field", "rt_sigma_from_field"]
+           "rt_get_rhs_field", "rt_sigma_from_field", "rt_solve_field_gmres"]
 
 
 class RTError(RuntimeError):
@@ -92,7 +92,7 @@ def lib():
         for f in ("rt_get_rhs", "rt_get_jacobi_diag"):
             getattr(L, f).argtypes = [vp, vp, vp]
         for f in ("rt_solve_gmres", "rt_solve_bicgstab", "rt_solve_richardson", "rt_solve_cgs",
-                  "rt_solve_lu"):
+                  "rt_solve_lu", "rt_solve_field_gmres"):
             getattr(L, f).argtypes = [vp, vp, vp, C.POINTER(rt_solve_info), vp]
         L.rt_last_error.argtypes = []
         L.rt_last_error.restype = C.c_char_p
@@ -287,6 +287,11 @@ class Handle:
         b = self._new_field()
         _check(lib().rt_get_rhs_field(self._h, C.c_void_p(_ptr(b)), _stream(stream)))
         return b
+
+    def solve_field_gmres(self, I, b_field=None, stream=None):
+        """Unpreconditioned GMRES on the field system (I: initial guess in,
+        solution out)."""
+        return self._solve("rt_solve_field_gmres", b_field, I, stream)
 
     def sigma_from_field(self, I, stream=None):
         """sigma = J I + c (rt_sigma_from_field)."""

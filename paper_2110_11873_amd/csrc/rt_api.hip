@@ -685,6 +685,13 @@ int rt_get_rhs_field(rt_handle *h, double *b_field, void *stream) {
     return hip_check(field_rhs(h, b_field, (hipStream_t)stream), "rt_get_rhs_field");
 }
 
+int rt_solve_field_gmres(rt_handle *h, const double *b_field, double *I, rt_solve_info *info,
+                         void *stream) {
+    if (!h || !I) return fail(RT_EINVAL, "NULL handle or I");
+    if (b_field == I) return fail(RT_EINVAL, "b_field and I must not alias");
+    return solve_field_gmres(h, b_field, I, info, (hipStream_t)stream);
+}
+
 int rt_sigma_from_field(rt_handle *h, const double *I, double *sigma, void *stream) {
     if (!h || !I || !sigma) return fail(RT_EINVAL, "NULL handle or vector");
     return hip_check(field_sigma(h, I, sigma, 1, (hipStream_t)stream), "rt_sigma_from_field");

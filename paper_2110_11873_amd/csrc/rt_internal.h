@@ -285,6 +285,10 @@ hipError_t apply_ray_operator(rt_handle *h, const double *in, const double *scal
 hipError_t apply_field_operator(rt_handle *h, const double *in, double *out, hipStream_t s);
 hipError_t field_rhs(rt_handle *h, double *b, hipStream_t s);
 hipError_t field_sigma(rt_handle *h, const double *I, double *sigma, int with_c, hipStream_t s);
+// GMRES(restart) on the field system, unpreconditioned, batched over slabs
+// (rt_fieldsolve.hip); b NULL: the handle's own Lambda T c + t.
+int solve_field_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *info,
+                      hipStream_t s);
 // Quadrature slots per slab of that sweep (two per wavefront of rays).
 int ray_slots(const rt_handle *h);
 

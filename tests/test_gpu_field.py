@@ -95,3 +95,52 @@ def test_field_batch():
         ref = O.apply_I(p.slab(i), fo)
         scale = np.abs(fi).max() + np.abs(fo - ref).max()
         assert np.abs(to_oracle_order(p, yi, i) - ref).max() / scale <= 1e-12, i
+
+
+# ------------------------------------------------------------- field GMRES
+
+@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal", "implicit_euler", "delo_parabolic"])
+def test_field_gmres_matches_dense_field_solution(fs):
+    p = W.config1_subgrid(fs)
+    sig_ref, I_ref = D.Dense(p).solve_I_formulation()
+    with B.setup(p, rtol=1e-13, restart=40, maxit=2000) as h:
+        I = dev(np.zeros(h.field_size()))
+        rc, info = h.solve_field_gmres(I)
+        sig = host(h.sigma_from_field(I))
+    assert rc == 0 and info[0].status == "converged" and info[0].relres < 1e-13
+    Ig = to_oracle_order(p, host(I), 0)
+    assert np.abs(Ig - I_ref).max() <= 1e-10 * np.abs(I_ref).max()
+    assert np.abs(sig - sig_ref).max() <= 1e-10 * np.abs(sig_ref).max()
+
+
+def test_field_gmres_config1_oracle_residual():
+    p = W.config1()
+    with B.setup(p, rtol=1e-10, restart=30, maxit=5000) as h:
+        I = dev(np.zeros(h.field_size()))
+        rc, info = h.solve_field_gmres(I)
+        b = host(h.get_rhs_field())
+    assert rc == 0
+    Io, bo = to_oracle_order(p, host(I), 0), to_oracle_order(p, b, 0)
+    r = O.rhs_I(p) - O.apply_I(p, Io)
+    assert np.abs(bo - O.rhs_I(p)).max() <= 1e-12 * np.abs(bo).max()
+    assert np.linalg.norm(r) / np.linalg.norm(O.rhs_I(p)) < 1e-10
+    assert abs(info[0].relres - np.linalg.norm(r) / np.linalg.norm(O.rhs_I(p))) < 1e-11
+
+
+def test_field_gmres_batch_per_slab():
+    """Uneven slabs converge independently; the maxit limit is honoured."""
+    p = W.config4(3)
+    with B.setup(p, rtol=1e-10, restart=30, maxit=5000) as h:
+        I = dev(np.zeros(h.field_size()))
+        rc, info = h.solve_field_gmres(I)
+        If = host(I)
+    with B.setup(p, rtol=1e-14, restart=10, maxit=7) as h:
+        I2 = dev(np.zeros(h.field_size()))
+        rc2, info2 = h.solve_field_gmres(I2)
+    assert rc == 0 and all(i.status == "converged" for i in info)
+    for i, fi in enumerate(slab_fields(p, If)):
+        ps = p.slab(i)
+        fo = to_oracle_order(p, fi, i)
+        r = O.rhs_I(ps) - O.apply_I(ps, fo)
+        assert np.linalg.norm(r) / np.linalg.norm(O.rhs_I(ps)) < 1e-10, i
+    assert rc2 == B.RT_ENOCONV and all(i.iterations == 7 for i in info2)
