@@ -42,9 +42,17 @@ __device__ void tri_sweep(const double *A, int N, double om, double *r, double *
     for (int bi = 0; bi < nb; ++bi) {
         const int b = UP ? nb - 1 - bi : bi;
         const int i0 = b * kTriB, n = min(kTriB, N - i0);
-        for (int e = tid; e < kTriB * kTriB; e += kTriNT) {
-            const int rr = e / kTriB, cc = e % kTriB;
-            blk[rr * kTriPad + cc] = (rr < n && cc < n) ? A[(long long)(i0 + rr) * N + i0 + cc] : 0.0;
+        // all of a thread's loads in flight at once (a fixed trip count)
+        double stage[kTriB * kTriB / kTriNT];
+#pragma unroll
+        for (int t = 0; t < kTriB * kTriB / kTriNT; ++t) {
+            const int e = tid + t * kTriNT, rr = e / kTriB, cc = e % kTriB;
+            stage[t] = (rr < n && cc < n) ? A[(long long)(i0 + rr) * N + i0 + cc] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < kTriB * kTriB / kTriNT; ++t) {
+            const int e = tid + t * kTriNT;
+            blk[(e / kTriB) * kTriPad + e % kTriB] = stage[t];
         }
         __syncthreads();
         if (tid < kWave) {
@@ -65,10 +73,21 @@ __device__ void tri_sweep(const double *A, int N, double om, double *r, double *
         for (int l = lo + tid; l < hi; l += kTriNT) {
             const double2 *row = reinterpret_cast<const double2 *>(A + (long long)l * N + i0);
             double acc0 = 0.0, acc1 = 0.0;
-            for (int c2 = 0; c2 < n / 2; ++c2) {
-                const double2 v = row[c2];
-                acc0 = fma(v.x, r[i0 + 2 * c2], acc0);
-                acc1 = fma(v.y, r[i0 + 2 * c2 + 1], acc1);
+            if (n == kTriB) {  // a full block: the row's 32 loads issued together
+                double2 v[kTriB / 2];
+#pragma unroll
+                for (int c2 = 0; c2 < kTriB / 2; ++c2) v[c2] = row[c2];
+#pragma unroll
+                for (int c2 = 0; c2 < kTriB / 2; ++c2) {
+                    acc0 = fma(v[c2].x, r[i0 + 2 * c2], acc0);
+                    acc1 = fma(v[c2].y, r[i0 + 2 * c2 + 1], acc1);
+                }
+            } else {
+                for (int c2 = 0; c2 < n / 2; ++c2) {
+                    const double2 v = row[c2];
+                    acc0 = fma(v.x, r[i0 + 2 * c2], acc0);
+                    acc1 = fma(v.y, r[i0 + 2 * c2 + 1], acc1);
+                }
             }
             r[l] -= acc0 + acc1;
         }
@@ -343,11 +362,18 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g) {
                 }
                 __syncthreads();
                 if (c < N) {
-                    for (int rr = 0; rr < nr; ++rr) {
-                        double a = A[(long long)(r0 + rr) * N + c];
+                    // eight rows' loads in flight at a time
+                    for (int rr0 = 0; rr0 < nr; rr0 += 8) {
+                        double a[8];
 #pragma unroll
-                        for (int i = 0; i < NB; ++i) a = fma(-L21[rr][i], u[i], a);
-                        A[(long long)(r0 + rr) * N + c] = a;
+                        for (int t = 0; t < 8; ++t)
+                            a[t] = rr0 + t < nr ? A[(long long)(r0 + rr0 + t) * N + c] : 0.0;
+#pragma unroll
+                        for (int t = 0; t < 8; ++t) {
+#pragma unroll
+                            for (int i = 0; i < NB; ++i) a[t] = fma(-L21[rr0 + t][i], u[i], a[t]);
+                            if (rr0 + t < nr) A[(long long)(r0 + rr0 + t) * N + c] = a[t];
+                        }
                     }
                 }
             }
