@@ -147,3 +147,56 @@ class Dense:
         rhs = self.Lam @ self.T @ self.c + self.t
         I = sla.lu_solve(sla.lu_factor(K), rhs)
         return self.J @ I + self.c, I
+
+
+def redistribution_matrix_A(prob, R, i=0):
+    """Explicit A of the redistribution variant on a tiny grid: unknowns
+    (k * n_nu + p) * 2 + K, A = Id - C Jm Lambda T with T the per-frequency
+    source map, Lambda the per-ray blocks of _ray_matrices, Jm the
+    monochromatic angle quadrature and C the redistribution
+    sum_p' R(p, p') w_p' (.) / phi_p with xi W_K."""
+    ns = int(prob.ns[i])
+    off = prob.offsets
+    tau = prob.tau[off[i]:off[i + 1]]
+    mu, wmu = prob.mu, prob.w_mu
+    wnu, phi, opac = prob.w_nu, prob.phi[i], prob.opac[i]
+    nmu, nnu = mu.shape[0], wnu.shape[0]
+    xi, W2 = 1.0 - float(prob.eps[i]), float(prob.W2[i])
+    t1 = np.sqrt(2.0) * (3.0 * mu ** 2 - 1.0) / 4.0
+    t2 = np.sqrt(2.0) * (3.0 * mu ** 2 - 3.0) / 4.0
+    nsig, nfld = 2 * ns * nnu, 2 * ns * nmu * nnu
+
+    def sidx(k, p, K):
+        return (k * nnu + p) * 2 + K
+
+    def fidx(st, m, p, k):
+        return ((st * nmu + m) * nnu + p) * ns + k
+
+    T = np.zeros((nfld, nsig))   # sources, laid out like the field
+    for m in range(nmu):
+        for p in range(nnu):
+            for k in range(ns):
+                T[fidx(0, m, p, k), sidx(k, p, 0)] = 1.0
+                T[fidx(0, m, p, k), sidx(k, p, 1)] = t1[m]
+                T[fidx(1, m, p, k), sidx(k, p, 1)] = t2[m]
+    Lam = np.zeros((nfld, nfld))
+    for m in range(nmu):
+        for p in range(nnu):
+            Lr, _ = _ray_matrices(tau, opac[p] / abs(mu[m]), mu[m] > 0, int(prob.formal_solver))
+            for st in range(2):
+                r0 = fidx(st, m, p, 0)
+                Lam[r0:r0 + ns, r0:r0 + ns] = Lr
+    Jm = np.zeros((nsig, nfld))
+    for m in range(nmu):
+        for p in range(nnu):
+            for k in range(ns):
+                Jm[sidx(k, p, 0), fidx(0, m, p, k)] = 0.5 * wmu[m]
+                Jm[sidx(k, p, 1), fidx(0, m, p, k)] = 0.5 * wmu[m] * t1[m]
+                Jm[sidx(k, p, 1), fidx(1, m, p, k)] = 0.5 * wmu[m] * t2[m]
+    Cm = np.zeros((nsig, nsig))
+    for k in range(ns):
+        for p in range(nnu):
+            for q in range(nnu):
+                Cm[sidx(k, p, 0), sidx(k, q, 0)] = xi * R[p, q] * wnu[q] / phi[p]
+                Cm[sidx(k, p, 1), sidx(k, q, 1)] = xi * W2 * R[p, q] * wnu[q] / phi[p]
+    return np.eye(nsig) - Cm @ Jm @ Lam @ T

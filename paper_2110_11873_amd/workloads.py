@@ -245,3 +245,28 @@ CONFIGS = {
     "c3": config3,
     "c4": config4,
 }
+
+
+# ----------------------------------------------------------------------------
+# frequency redistribution (the benchmark's fifth configuration)
+# ----------------------------------------------------------------------------
+
+def redistribution_matrix(x, w_nu, phi, gamma):
+    """Synthetic redistribution kernel R(x, x') = (1 - gamma) phi(x) phi(x') +
+    gamma phi(x') exp(-(x - x')^2 / 2) / sqrt(2 pi), each column scaled so that
+    sum_x w_x R(x, x') = phi(x') (the discrete form of int R dx = phi(x'))."""
+    x = np.asarray(x, dtype=np.float64)
+    w_nu = np.asarray(w_nu, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    g = np.exp(-0.5 * (x[:, None] - x[None, :]) ** 2) / math.sqrt(2.0 * math.pi)
+    R = (1.0 - gamma) * np.outer(phi, phi) + gamma * phi[None, :] * g
+    col = (w_nu[:, None] * R).sum(axis=0)
+    return R * (phi / col)[None, :]
+
+
+def config5(gamma: float = 0.5, ns: int = 256, n_mu: int = 32, n_nu: int = 256):
+    """Redistribution: Ns=256, tau in [1e-4, 1e8], 32 mu, 256 nu on [-12, 12], a=1e-3,
+    eps=1e-4, W2=0.5, R with gamma = 0.5.  Returns (problem, R)."""
+    p = make_slabs([ns], [(1e-4, 1e8)], n_mu, n_nu, 12.0, [1e-3], [1e-4], [0.5],
+                   name=f"c5_ns{ns}_mu{n_mu}_nu{n_nu}_gamma{gamma}")
+    return p, redistribution_matrix(p.x, p.w_nu, p.phi[0], gamma)

@@ -585,3 +585,40 @@ def test_sor_ssor_solvers_agree_with_LU(pc):
         x, info = solve(p, precond=pc, tol=1e-13, maxit=2000)
         assert info[0]["status"] == "converged"
         assert np.max(np.abs(x - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+# --------------------------------------------------------------------------
+# Frequency redistribution (the benchmark's fifth configuration)
+# --------------------------------------------------------------------------
+
+from oracle import redistrib as RDO  # noqa: E402
+
+
+def test_redistribution_columns_are_normalized():
+    p, R = W.config5(ns=8, n_mu=4, n_nu=31)
+    assert np.abs((p.w_nu[:, None] * R).sum(0) - p.phi[0]).max() <= 1e-15
+
+
+@pytest.mark.parametrize("fs", ["delo_linear", "delo_parabolic"])
+def test_redistribution_gamma0_is_complete_redistribution(fs):
+    """gamma = 0: R proportional to phi phi', and a frequency-independent
+    sigma gives the CRD operator (and right-hand side) at every frequency."""
+    p = W.config1_subgrid(fs)
+    R0 = W.redistribution_matrix(p.x, p.w_nu, p.phi[0], 0.0)
+    ns, nnu = int(p.ns[0]), len(p.w_nu)
+    s = W.random_vector(2 * ns, 3)
+    sig = np.repeat(s.reshape(ns, 1, 2), nnu, axis=1).ravel()
+    y = RDO.apply(p, R0, sig).reshape(ns, nnu, 2)
+    assert np.abs(y - O.apply(p, s).reshape(ns, 2)[:, None, :]).max() <= 1e-13
+    b = RDO.rhs(p, R0).reshape(ns, nnu, 2)
+    assert np.abs(b - O.rhs(p).reshape(ns, 2)[:, None, :]).max() <= 1e-13
+
+
+@pytest.mark.parametrize("gamma", [0.0, 0.5, 1.0])
+def test_redistribution_operator_equals_dense_route(gamma):
+    p = W.config1_subgrid()
+    R = W.redistribution_matrix(p.x, p.w_nu, p.phi[0], gamma)
+    A = D.redistribution_matrix_A(p, R)
+    for seed in range(2):
+        v = np.random.default_rng(seed).uniform(-1, 1, A.shape[0])
+        assert np.abs(RDO.apply(p, R, v) - A @ v).max() <= 1e-13 * np.abs(v).max()
