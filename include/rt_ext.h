@@ -133,6 +133,35 @@ int rt_solve_field_gmres(rt_handle *h, const double *b_field, double *I, rt_solv
                          void *stream);
 
 /*
+ * Frequency redistribution (an extension of the paper's complete
+ * redistribution, CRD, of Sect. 3.1: the emission at frequency p is
+ * sum_q R(p, q) w_q J_q / phi_p instead of phi_p times the frequency-
+ * integrated J).  The unknown is sigma^K(k, p) per depth and frequency,
+ * laid out 2 n_nu doff_s + (k n_nu + p) 2 + K (K = 0: s00, 1: s20), and
+ *   S_I = s00(k, p) + T1 s20(k, p),  S_Q = T2 s20(k, p);
+ *   J^K_p(k) = the angle quadrature of eqs. J00/J02 at frequency p;
+ *   (A sigma)^K(k, p) = sigma^K(k, p) - xi W_K sum_q R(p, q) w_q J^K_q(k) / phi_p,
+ * W_0 = 1, W_2 = W2; b is the same contraction of the transmitted field plus
+ * [eps B, 0].  R proportional to phi(p) phi(q) gives back CRD at every p.
+ * rt_set_redistribution: R (host, n_atm x n_nu x n_nu, R[s][p][q] row-major;
+ *   copied, finite) for the handle's slabs; enables the calls below (RT_EINVAL
+ *   before).  The contraction runs on the FP64 matrix cores.
+ * rt_prd_size: 2 n_nu sum ns doubles.
+ * rt_apply_op_prd / rt_get_rhs_prd / rt_get_jacobi_diag_prd: A sigma, b,
+ *   diag(A) (device arrays, stream-ordered).
+ * rt_solve_prd_gmres: Jacobi-preconditioned (from the right) GMRES(restart)
+ *   in FP64 to options.rtol; b NULL means the handle's own b; x holds the
+ *   initial guess and receives the solution; info as for rt_solve_gmres.
+ */
+int rt_set_redistribution(rt_handle *h, const double *R);
+int rt_prd_size(const rt_handle *h, long long *count);
+int rt_apply_op_prd(rt_handle *h, const double *sigma_in, double *sigma_out, void *stream);
+int rt_get_rhs_prd(rt_handle *h, double *b, void *stream);
+int rt_get_jacobi_diag_prd(rt_handle *h, double *d, void *stream);
+int rt_solve_prd_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *info,
+                       void *stream);
+
+/*
  * Run the validation of rt_setup on (p, o) without touching any device:
  * RT_OK or RT_EINVAL with the message in rt_last_error().  o may be NULL.
  */

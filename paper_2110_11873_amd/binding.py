@@ -33,7 +33,9 @@ EXPORTS = ["rt_default_options", "rt_setup", "rt_destroy", "rt_num_unknowns", "r
            "rt_apply_op_fp32",
            "rt_plan_info", "rt_sweep_config", "rt_validate", "rt_assembled_size", "rt_assemble",
            "rt_precond_apply", "rt_solve_lu", "rt_field_size", "rt_apply_op_field",
-           "rt_get_rhs_field", "rt_sigma_from_field", "rt_solve_field_gmres"]
+           "rt_get_rhs_field", "rt_sigma_from_field", "rt_solve_field_gmres",
+           "rt_set_redistribution", "rt_prd_size", "rt_apply_op_prd", "rt_get_rhs_prd",
+           "rt_get_jacobi_diag_prd", "rt_solve_prd_gmres"]
 
 
 class RTError(RuntimeError):
@@ -92,7 +94,7 @@ def lib():
         for f in ("rt_get_rhs", "rt_get_jacobi_diag"):
             getattr(L, f).argtypes = [vp, vp, vp]
         for f in ("rt_solve_gmres", "rt_solve_bicgstab", "rt_solve_richardson", "rt_solve_cgs",
-                  "rt_solve_lu", "rt_solve_field_gmres"):
+                  "rt_solve_lu", "rt_solve_field_gmres", "rt_solve_prd_gmres"):
             getattr(L, f).argtypes = [vp, vp, vp, C.POINTER(rt_solve_info), vp]
         L.rt_last_error.argtypes = []
         L.rt_last_error.restype = C.c_char_p
@@ -102,6 +104,11 @@ def lib():
         L.rt_validate.argtypes = [C.POINTER(rt_problem), C.POINTER(rt_options)]
         L.rt_assembled_size.argtypes = [vp, C.POINTER(C.c_longlong)]
         L.rt_field_size.argtypes = [vp, C.POINTER(C.c_longlong)]
+        L.rt_set_redistribution.argtypes = [vp, C.POINTER(C.c_double)]
+        L.rt_prd_size.argtypes = [vp, C.POINTER(C.c_longlong)]
+        L.rt_apply_op_prd.argtypes = [vp, vp, vp, vp]
+        L.rt_get_rhs_prd.argtypes = [vp, vp, vp]
+        L.rt_get_jacobi_diag_prd.argtypes = [vp, vp, vp]
         L.rt_apply_op_field.argtypes = [vp, vp, vp, vp]
         L.rt_get_rhs_field.argtypes = [vp, vp, vp]
         L.rt_sigma_from_field.argtypes = [vp, vp, vp, vp]
@@ -264,6 +271,40 @@ class Handle:
         c = self.sweep_config(fp32)
         return "rt::sweep::sweep_kernel<%s, %d, %d, %d>" % (
             "float" if fp32 else "double", self.plan_info()["chunk"], c["waves"], c["prefetch"])
+
+    # -- frequency redistribution -------------------------------------------------
+    def set_redistribution(self, R):
+        """R: (n_atm, n_nu, n_nu) or (n_nu, n_nu) host array, R[s][p][q]."""
+        R = np.ascontiguousarray(R, dtype=np.float64)
+        _check(lib().rt_set_redistribution(self._h, R.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def prd_size(self):
+        n = C.c_longlong()
+        _check(lib().rt_prd_size(self._h, C.byref(n)))
+        return n.value
+
+    def _new_prd(self):
+        import torch
+        return torch.empty(self.prd_size(), dtype=torch.float64, device="cuda")
+
+    def apply_op_prd(self, sigma_in, sigma_out=None, stream=None):
+        out = self._new_prd() if sigma_out is None else sigma_out
+        _check(lib().rt_apply_op_prd(self._h, C.c_void_p(_ptr(sigma_in)), C.c_void_p(_ptr(out)),
+                                     _stream(stream)))
+        return out
+
+    def get_rhs_prd(self, stream=None):
+        b = self._new_prd()
+        _check(lib().rt_get_rhs_prd(self._h, C.c_void_p(_ptr(b)), _stream(stream)))
+        return b
+
+    def get_jacobi_diag_prd(self, stream=None):
+        d = self._new_prd()
+        _check(lib().rt_get_jacobi_diag_prd(self._h, C.c_void_p(_ptr(d)), _stream(stream)))
+        return d
+
+    def solve_prd_gmres(self, x, b=None, stream=None):
+        return self._solve("rt_solve_prd_gmres", b, x, stream)
 
     # -- the field as unknown ------------------------------------------------------
     def field_size(self):

@@ -332,7 +332,8 @@ void rt_destroy(rt_handle *h) {
                     h->d_cq,    h->d_state, h->d_active,  h->d_cycle,   h->d_count,
                     h->d_ew,    h->d_asm_dg, h->d_asm_sc, h->d_asm_task, h->d_A,
                     h->d_pz,    h->d_ones,  h->d_LU,      h->d_piv,     h->d_sing,
-                    h->d_rpart, h->d_mu_idx, h->d_fsig};
+                    h->d_rpart, h->d_mu_idx, h->d_fsig, h->d_Rw,   h->d_prd_Jm,
+                    h->d_prd_J, h->d_prd_diag, h->d_prd_dinv};
     clear_graphs(h);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
     for (hipEvent_t e : h->gev)
@@ -690,6 +691,65 @@ int rt_solve_field_gmres(rt_handle *h, const double *b_field, double *I, rt_solv
     if (!h || !I) return fail(RT_EINVAL, "NULL handle or I");
     if (b_field == I) return fail(RT_EINVAL, "b_field and I must not alias");
     return solve_field_gmres(h, b_field, I, info, (hipStream_t)stream);
+}
+
+int rt_set_redistribution(rt_handle *h, const double *R) {
+    if (!h || !R) return fail(RT_EINVAL, "NULL handle or R");
+    const long long n = (long long)h->n_atm * h->n_nu * h->n_nu;
+    for (long long e = 0; e < n; ++e)
+        if (!std::isfinite(R[e])) return fail(RT_EINVAL, "R must be finite");
+    // R(p, q) w_q, the form the contraction uses
+    std::vector<double> w_nu(h->n_nu), Rw(n);
+    if (hipMemcpy(w_nu.data(), h->d_w_nu, sizeof(double) * h->n_nu, hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return fail(RT_EDEVICE, "reading the frequency weights failed");
+    for (long long e = 0; e < n; ++e) Rw[e] = R[e] * w_nu[e % h->n_nu];
+    if (!h->d_Rw && hipMalloc((void **)&h->d_Rw, sizeof(double) * n) != hipSuccess) {
+        h->d_Rw = nullptr;
+        (void)hipGetLastError();
+        return fail(RT_ENOMEM, "device allocation of R failed");
+    }
+    if (hipMemcpy(h->d_Rw, Rw.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(RT_EDEVICE, "upload of R failed");
+    h->prd_ready = false;  // the diagonal depends on R
+    return RT_OK;
+}
+
+int rt_prd_size(const rt_handle *h, long long *count) {
+    if (!h || !count) return fail(RT_EINVAL, "NULL handle or count");
+    *count = 2LL * h->n_nu * h->ns_total;
+    return RT_OK;
+}
+
+int rt_apply_op_prd(rt_handle *h, const double *sigma_in, double *sigma_out, void *stream) {
+    if (!h || !sigma_in || !sigma_out) return fail(RT_EINVAL, "NULL handle or vector");
+    const int rc = ensure_prd(h, (hipStream_t)stream);
+    if (rc != RT_OK) return rc;
+    return hip_check(apply_prd_operator(h, sigma_in, sigma_out, (hipStream_t)stream),
+                     "rt_apply_op_prd");
+}
+
+int rt_get_rhs_prd(rt_handle *h, double *b, void *stream) {
+    if (!h || !b) return fail(RT_EINVAL, "NULL handle or vector");
+    const int rc = ensure_prd(h, (hipStream_t)stream);
+    if (rc != RT_OK) return rc;
+    return hip_check(apply_prd_operator(h, nullptr, b, (hipStream_t)stream), "rt_get_rhs_prd");
+}
+
+int rt_get_jacobi_diag_prd(rt_handle *h, double *d, void *stream) {
+    if (!h || !d) return fail(RT_EINVAL, "NULL handle or vector");
+    const int rc = ensure_prd(h, (hipStream_t)stream);
+    if (rc != RT_OK) return rc;
+    return hip_check(hipMemcpyAsync(d, h->d_prd_diag, sizeof(double) * 2 * h->n_nu * h->ns_total,
+                                    hipMemcpyDeviceToDevice, (hipStream_t)stream),
+                     "rt_get_jacobi_diag_prd");
+}
+
+int rt_solve_prd_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *info,
+                       void *stream) {
+    if (!h || !x) return fail(RT_EINVAL, "NULL handle or x");
+    if (b == x) return fail(RT_EINVAL, "b and x must not alias");
+    return solve_prd_gmres(h, b, x, info, (hipStream_t)stream);
 }
 
 int rt_sigma_from_field(rt_handle *h, const double *I, double *sigma, void *stream) {

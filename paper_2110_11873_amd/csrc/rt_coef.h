@@ -188,4 +188,27 @@ __device__ inline void ray_step(int fs, double d, double dd, bool has_dn, double
     E = exp(-d);
 }
 
+// Lambda(k, k) of one DELO-parabolic ray through depth k, walking toward
+// larger depth indices (step = 1) or smaller (step = -1): the source at k
+// enters I_k through c_k of the step into k and, through c_d of the step into
+// the point before k (when that point is not the ray's entry), I there,
+// which reaches k with the factor E of the step into k.
+__device__ inline double parabolic_diag(const double *tau, int ns, int k, double kap, int step) {
+    const int i = step > 0 ? k : ns - 1 - k;  // position along the ray
+    if (i == 0) return 0.0;
+    const int u = k - step, dn = k + step;
+    const bool has_dn = i < ns - 1;
+    double E, cu, ck, cd;
+    ray_step(RT_FS_DELO_PARABOLIC, kap * fabs(tau[k] - tau[u]),
+             has_dn ? kap * fabs(tau[dn] - tau[k]) : 1.0, has_dn, E, cu, ck, cd);
+    double lam = ck;
+    if (i >= 2) {
+        double E2, cu2, ck2, cd2;
+        ray_step(RT_FS_DELO_PARABOLIC, kap * fabs(tau[u] - tau[u - step]),
+                 kap * fabs(tau[k] - tau[u]), true, E2, cu2, ck2, cd2);
+        lam += E * cd2;
+    }
+    return lam;
+}
+
 }  // namespace rt

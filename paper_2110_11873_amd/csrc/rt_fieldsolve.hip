@@ -1,5 +1,6 @@
-// rt_fieldsolve.hip -- GMRES(m) (Sect. 2.1) on the field-unknown system
-// (Id - Lambda T J) I = Lambda T c + t (eq. crd_linear_system2).
+// rt_fieldsolve.hip -- GMRES(m) (Sect. 2.1) for the long-vector systems: the
+// field-unknown system (Id - Lambda T J) I = Lambda T c + t (eq.
+// crd_linear_system2) and the frequency-redistribution variant.
 //
 // The slabs are independent, so each slab's segment of the field vector is
 // its own system with its own basis rows, Hessenberg matrix, Givens
@@ -9,11 +10,13 @@
 // a chunk of one slab's segment for all basis rows at once, and a second
 // pass adds the chunks in chunk order (deterministic).  No preconditioner:
 // the field system is the one Sect. 3.2 calls more favourable to Krylov
-// methods.
+// methods.  The redistribution variant uses the same solver with its own
+// operator and a Jacobi scaling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -228,13 +231,27 @@ __global__ void fs_keep_bnorm_kernel(FsArgs a) {
     a.resid[s] = a.h[(long long)s * (a.m + 1)];
 }
 
+// out = d .* in over the whole vector (Jacobi scaling of the generic solve).
+__global__ void fs_mul_kernel(const double *d, const double *in, double *out, long long n,
+                              int divide) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x)
+        out[e] = divide ? in[e] / d[e] : d[e] * in[e];
+}
+
 }  // namespace
 
-int solve_field_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *info,
-                      hipStream_t st) {
+// GMRES(restart) for a block-diagonal operator whose slab s owns `per`
+// entries per depth point; dinv (optional) preconditions from the right by
+// diag(dinv): the solve runs on y with x = dinv .* y, starting from y0 =
+// x0 ./ dinv, so that the residual tested is still b - A x.
+int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *, double *)> &op,
+                    long long per, const double *b_in,
+                    const std::function<hipError_t(double *)> &own_rhs, double *x,
+                    const double *dinv, rt_solve_info *info, hipStream_t st) {
     const int m = h->opt.restart, n_atm = h->n_atm;
-    const long long per = 2LL * h->n_mu * h->n_nu;
     const long long N = per * h->ns_total;
+    const double *b = b_in;
     std::vector<long long> off(n_atm + 1, 0);
     int nchunk = 1;
     for (int s = 0; s < n_atm; ++s) {
@@ -266,6 +283,7 @@ int solve_field_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *i
     a.V = (double *)get(sizeof(double) * (size_t)(m + 1) * N);
     double *w = (double *)get(sizeof(double) * N);
     double *bown = b ? nullptr : (double *)get(sizeof(double) * N);
+    double *tmp = dinv ? (double *)get(sizeof(double) * N) : nullptr;
     a.part = (double *)get(sizeof(double) * (size_t)n_atm * nchunk * (m + 1));
     a.h = (double *)get(sizeof(double) * (size_t)n_atm * (m + 1));
     a.H = (double *)get(sizeof(double) * (size_t)n_atm * (m + 1) * m);
@@ -282,12 +300,12 @@ int solve_field_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *i
     for (void *p : bufs)
         if (!p) {
             release();
-            return fail(RT_ENOMEM, "field GMRES workspace allocation failed");
+            return fail(RT_ENOMEM, "GMRES workspace allocation failed");
         }
-    if (!a.off || !a.V || !w || (!b && !bown) || !a.part || !a.h || !a.H || !a.cs || !a.sn ||
+    if (!a.off || !a.V || !w || (!b && !bown) || (dinv && !tmp) || !a.part || !a.h || !a.H || !a.cs || !a.sn ||
         !a.g || !a.bnorm || !a.beta || !a.resid || !a.active || !a.done || !a.jj || !a.iters) {
         release();
-        return fail(RT_ENOMEM, "field GMRES workspace allocation failed");
+        return fail(RT_ENOMEM, "GMRES workspace allocation failed");
     }
     hipError_t err = hipSuccess;
     auto ok = [&](hipError_t e) {
@@ -297,9 +315,18 @@ int solve_field_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *i
     ok(hipMemcpyAsync((void *)a.off, off.data(), sizeof(long long) * (n_atm + 1),
                       hipMemcpyHostToDevice, st));
     if (!b) {
-        ok(field_rhs(h, bown, st));
+        ok(own_rhs(bown));
         b = bown;
     }
+    const int mgrid = (int)std::min<long long>((N + 255) / 256, 4096);
+    // the preconditioned operator A diag(dinv), on y = x ./ dinv
+    auto apply = [&](const double *v, double *out) {
+        if (!dinv) return op(v, out);
+        hipLaunchKernelGGL(fs_mul_kernel, dim3(mgrid), dim3(256), 0, st, dinv, v, tmp, N, 0);
+        hipError_t e = hipGetLastError();
+        return e != hipSuccess ? e : op(tmp, out);
+    };
+    if (dinv) hipLaunchKernelGGL(fs_mul_kernel, dim3(mgrid), dim3(256), 0, st, dinv, (const double *)x, x, N, 1);
     const dim3 seg(nchunk, n_atm), blk(kFsNT);
     const int tb = 64, tg = (n_atm + tb - 1) / tb;
     std::vector<int> act(n_atm);
@@ -318,7 +345,7 @@ int solve_field_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *i
     bool first = true;
     int napply = 0;
     while (ok(hipGetLastError())) {
-        ok(apply_field_operator(h, x, w, st));
+        ok(apply(x, w));
         ++napply;
         hipLaunchKernelGGL(fs_residual_kernel, seg, blk, 0, st, a, b, (const double *)w);
         hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)a.V, 1,
@@ -332,7 +359,7 @@ int solve_field_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *i
         hipLaunchKernelGGL(fs_scale_kernel, seg, blk, 0, st, a, (const double *)a.V, -1);
         for (int j = 0; j < m && err == hipSuccess; ++j) {
             const double *vj = a.V + (long long)j * N;
-            ok(apply_field_operator(h, vj, w, st));
+            ok(apply(vj, w));
             ++napply;
             for (int pass = 0; pass < 2; ++pass) {
                 hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)w, j + 1,
@@ -362,8 +389,9 @@ int solve_field_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *i
         hipLaunchKernelGGL(fs_backsolve_kernel, dim3(tg), dim3(tb), 0, st, a);
         hipLaunchKernelGGL(fs_update_kernel, seg, blk, 0, st, a, x);
     }
-    // final explicit residuals
-    ok(apply_field_operator(h, x, w, st));
+    // back to x = dinv .* y, then the final explicit residuals b - A x
+    if (dinv) hipLaunchKernelGGL(fs_mul_kernel, dim3(mgrid), dim3(256), 0, st, dinv, (const double *)x, x, N, 0);
+    ok(op(x, w));
     hipLaunchKernelGGL(fs_init_kernel, dim3(tg), dim3(tb), 0, st, a);
     hipLaunchKernelGGL(fs_residual_kernel, seg, blk, 0, st, a, b, (const double *)w);
     hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)a.V, 1,
@@ -376,7 +404,7 @@ int solve_field_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *i
     ok(hipMemcpyAsync(its.data(), a.iters, sizeof(int) * n_atm, hipMemcpyDeviceToHost, st));
     ok(hipStreamSynchronize(st));
     release();
-    if (err != hipSuccess) return fail(RT_EDEVICE, std::string("field GMRES: ") + hipGetErrorString(err));
+    if (err != hipSuccess) return fail(RT_EDEVICE, std::string("GMRES: ") + hipGetErrorString(err));
     int worst = RT_OK;
     for (int s = 0; s < n_atm; ++s) {
         const double rel = bn[s] > 0.0 ? std::sqrt(hh[(size_t)s * (m + 1)]) / bn[s] : 0.0;
@@ -390,8 +418,16 @@ int solve_field_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *i
             info[s].relres = rel;
         }
     }
-    if (worst != RT_OK) set_error("field GMRES did not reach rtol within the iteration limit");
+    if (worst != RT_OK) set_error("GMRES did not reach rtol within the iteration limit");
     return worst;
+}
+
+int solve_field_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *info,
+                      hipStream_t st) {
+    return solve_seg_gmres(
+        h, [&](const double *in, double *out) { return apply_field_operator(h, in, out, st); },
+        2LL * h->n_mu * h->n_nu, b, [&](double *bo) { return field_rhs(h, bo, st); }, x, nullptr,
+        info, st);
 }
 
 }  // namespace rt

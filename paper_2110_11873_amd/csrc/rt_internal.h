@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -222,6 +223,11 @@ struct rt_handle {
     double *d_rpart = nullptr;    // ray-per-lane sweep: per-wavefront quadrature slots
     int *d_mu_idx = nullptr;      // per |mu| index m: caller's index of -mu (2m) and +mu (2m+1)
     double *d_fsig = nullptr;     // field formulation: J I, 2 values per depth point
+    double *d_Rw = nullptr;       // redistribution: R(p, q) w_q per slab
+    double *d_prd_Jm = nullptr;   // per-|mu| monochromatic quadrature slots
+    double *d_prd_J = nullptr;    // monochromatic J per depth and frequency
+    double *d_prd_diag = nullptr, *d_prd_dinv = nullptr;
+    bool prd_ready = false;
     long long n_dense = 0;        // entries of the assembled A: sum over slabs of (2 ns)^2
     long long n_ew = 0;           // entries of the assembly coefficient table
 
@@ -289,6 +295,19 @@ hipError_t field_sigma(rt_handle *h, const double *I, double *sigma, int with_c,
 // (rt_fieldsolve.hip); b NULL: the handle's own Lambda T c + t.
 int solve_field_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *info,
                       hipStream_t s);
+// The generic form: any block-diagonal operator with `per` entries per depth
+// point, own_rhs filling b when b is NULL, optional right Jacobi scaling.
+int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *, double *)> &op,
+                    long long per, const double *b,
+                    const std::function<hipError_t(double *)> &own_rhs, double *x,
+                    const double *dinv, rt_solve_info *info, hipStream_t st);
+// The frequency-redistribution variant (rt_prd.hip): out = A in, or the
+// right-hand side when in is NULL; its Jacobi diagonal; workspace set-up.
+hipError_t apply_prd_operator(const rt_handle *h, const double *in, double *out, hipStream_t s);
+hipError_t prd_diag(const rt_handle *h, double *diag, double *dinv, hipStream_t s);
+int ensure_prd(rt_handle *h, hipStream_t s);
+int solve_prd_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *info,
+                    hipStream_t s);
 // Quadrature slots per slab of that sweep (two per wavefront of rays).
 int ray_slots(const rt_handle *h);
 
