@@ -229,7 +229,8 @@ def cpu_baseline(p, dinv, n_sample=8):
 def routes(steps):
     """The rows beside the hot path, timed on the GPU (one JSON line): the
     dense route (assembly, LU, SOR/SSOR-GMRES) on the 512-slab batch, the
-    DELO-parabolic operator and solve, and the field-unknown system; plus the
+    DELO-parabolic operator and solve, the field-unknown system and the
+    frequency-redistribution system; plus the
     unpreconditioned GMRES counts of both formulations on the paper's grids."""
     import torch
     from paper_2110_11873_amd import binding as B
@@ -297,6 +298,24 @@ def routes(steps):
         out["c2_field_gmres_ms"] = 1e3 * (time.perf_counter() - t0)
         out["c2_field_gmres_iterations"] = info[0].iterations
         out["c2_field_gmres_relres"] = info[0].relres
+    # frequency redistribution (256 depths, 32 mu, 256 nu, gamma = 0.5)
+    p5, R5 = W.config5()
+    with B.setup(p5, rtol=1e-9, restart=30, maxit=5000) as h:
+        h.set_redistribution(R5)
+        v = torch.from_numpy(np.random.default_rng(0).uniform(-1, 1, h.prd_size())).cuda()
+        o5 = torch.empty_like(v)
+        out["c5_prd_size"] = v.numel()
+        out["c5_prd_matvec_us"] = 1e3 * ev_ms(lambda: h.apply_op_prd(v, o5), 50)
+        x5 = torch.zeros_like(v)
+        h.solve_prd_gmres(x5)  # first call sets up the workspace and diagonal
+        x5.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = h.solve_prd_gmres(x5)
+        torch.cuda.synchronize()
+        out["c5_prd_gmres_ms"] = 1e3 * (time.perf_counter() - t0)
+        out["c5_prd_gmres_iterations"] = info[0].iterations
+        out["c5_prd_gmres_relres"] = info[0].relres
     counts = {"ns": [], "sigma_gmres": [], "field_gmres": []}
     for ns in (20, 40, 60, 80, 100, 120, 140):
         r = W.paper_replica(ns, scale="integrated", normalize=False)

@@ -698,12 +698,16 @@ int rt_set_redistribution(rt_handle *h, const double *R) {
     const long long n = (long long)h->n_atm * h->n_nu * h->n_nu;
     for (long long e = 0; e < n; ++e)
         if (!std::isfinite(R[e])) return fail(RT_EINVAL, "R must be finite");
-    // R(p, q) w_q, the form the contraction uses
-    std::vector<double> w_nu(h->n_nu), Rw(n);
-    if (hipMemcpy(w_nu.data(), h->d_w_nu, sizeof(double) * h->n_nu, hipMemcpyDeviceToHost) !=
+    // R(p, q) w_q stored transposed ([slab][q][p]), the form the contraction reads
+    const int nnu = h->n_nu;
+    std::vector<double> w_nu(nnu), Rw(n);
+    if (hipMemcpy(w_nu.data(), h->d_w_nu, sizeof(double) * nnu, hipMemcpyDeviceToHost) !=
         hipSuccess)
         return fail(RT_EDEVICE, "reading the frequency weights failed");
-    for (long long e = 0; e < n; ++e) Rw[e] = R[e] * w_nu[e % h->n_nu];
+    for (long long s0 = 0; s0 < n; s0 += (long long)nnu * nnu)
+        for (int pp = 0; pp < nnu; ++pp)
+            for (int q = 0; q < nnu; ++q)
+                Rw[s0 + (long long)q * nnu + pp] = R[s0 + (long long)pp * nnu + q] * w_nu[q];
     if (!h->d_Rw && hipMalloc((void **)&h->d_Rw, sizeof(double) * n) != hipSuccess) {
         h->d_Rw = nullptr;
         (void)hipGetLastError();

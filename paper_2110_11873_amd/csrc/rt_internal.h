@@ -223,9 +223,9 @@ struct rt_handle {
     double *d_rpart = nullptr;    // ray-per-lane sweep: per-wavefront quadrature slots
     int *d_mu_idx = nullptr;      // per |mu| index m: caller's index of -mu (2m) and +mu (2m+1)
     double *d_fsig = nullptr;     // field formulation: J I, 2 values per depth point
-    double *d_Rw = nullptr;       // redistribution: R(p, q) w_q per slab
-    double *d_prd_Jm = nullptr;   // per-|mu| monochromatic quadrature slots
-    double *d_prd_J = nullptr;    // monochromatic J per depth and frequency
+    double *d_Rw = nullptr;       // redistribution: R(p, q) w_q per slab, [q][p]
+    double *d_prd_Jm = nullptr;   // per-|mu| quadrature stage (when not in LDS)
+    double *d_prd_J = nullptr;    // monochromatic J, frequency-major [p][k][K]
     double *d_prd_diag = nullptr, *d_prd_dinv = nullptr;
     bool prd_ready = false;
     long long n_dense = 0;        // entries of the assembled A: sum over slabs of (2 ns)^2

@@ -2,24 +2,34 @@
 //
 // The unknown is sigma^K(k, p) per depth and frequency (K = 0, 2), laid out
 // ((doff + k) n_nu + p) 2 + K.  One application:
-//  * prd_sweep_kernel: one lane per (|mu|, nu) ray solves both directions in
-//    FP64 on the sources S_I = s0(k, p) + T1 s2(k, p), S_Q = T2 s2(k, p) (two
-//    linear recurrences, step coefficients recomputed), and writes its
-//    |mu|'s share of the monochromatic quadrature
+//  * prd_sweep_kernel, one workgroup per (frequency p, slab): every (|mu|, p)
+//    ray is solved in both directions in FP64 on the sources
+//    S_I = s0(k, p) + T1 s2(k, p), S_Q = T2 s2(k, p).  The intensity obeys a
+//    linear recurrence along the ray, so each ray is cut into depth chunks
+//    (one lane per (chunk, |mu|)): a first pass gives every chunk its affine
+//    map (the product of the attenuation factors and the response to zero
+//    entering intensity), a fold over the preceding chunks gives each chunk
+//    its entering intensity, and a second pass writes the lane's share of the
+//    monochromatic quadrature
 //      J0_p(k) = sum_mu (w_mu / 2) I,  J2_p(k) = sum_mu (w_mu / 2) (T1 I + T2 Q)
-//    (eqs. J00/J02 before the frequency integral) to a slot per |mu|;
-//  * prd_jsum_kernel adds the |mu| slots in order;
+//    (eqs. J00/J02 before the frequency integral) per |mu| to a stage; the
+//    stage is then summed over |mu| in order into J, frequency-major
+//    (J[p][k][K]).  The stage lives in LDS when it fits, else in a global
+//    buffer private to the workgroup;
 //  * prd_contract_kernel: the redistribution Jt(p, c) = sum_q R(p, q) w_q
 //    J(q, c) over the columns c = (k, K) of a slab -- a dense product, on
 //    the FP64 matrix cores (v_mfma_f64_16x16x4: one wavefront per 16 x 16
-//    tile of Jt, four q per instruction) -- with the scattering step fused
-//    into its output: sigma_out = sigma_in - xi W_K Jt / phi_p (operator) or
+//    tile of Jt, four q per instruction, both operands read along
+//    contiguous rows: R w is stored transposed, J frequency-major) -- with
+//    the scattering step fused into its output:
+//    sigma_out = sigma_in - xi W_K Jt / phi_p (operator) or
 //    xi W_K Jt / phi_p + eps B (K = 0) (right-hand side).
 // With R proportional to phi(p) phi(q) this is the complete-redistribution
-// operator at every frequency.  Deterministic: no atomics.
+// operator at every frequency.  Deterministic: no atomics, fixed orders.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "rt_coef.h"
 #include "rt_internal.h"
@@ -29,6 +39,7 @@ namespace rt {
 namespace {
 
 constexpr int kPrdNT = 256;
+constexpr size_t kPrdLdsMax = 64 * 1024;
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 struct PrdArgs {
@@ -36,56 +47,83 @@ struct PrdArgs {
     const int *pt_atm;
     const double *tau, *opac, *mu_pos, *w_pos, *B, *phi;
     const double2 *dirc;  // per |mu|: (T1, T1^2 + T2^2)
-    const double *Rw;     // [n_atm][n_nu][n_nu]: R(p, q) w_q
+    const double *RwT;    // [n_atm][n_nu (q)][n_nu (p)]: R(p, q) w_q
     const double *sig_in; // NULL: right-hand side (zero source, bottom inflow)
     double *sig_out;
-    double *Jm;           // [M][ns_total][n_nu][2]
-    double *J;            // [ns_total][n_nu][2]
-    int fs, M, n_nu, ns_total;
+    double *stage;        // global stage (when the LDS one does not fit)
+    double *J;            // [n_nu][ns_total][2]
+    int fs, M, n_nu, ns_total, nch;
 };
 
+// Lanes per (|mu|, chunk): M |mu| values times nch chunks <= kPrdNT.
+int prd_chunks(const rt_handle *h) { return std::max(1, std::min(kPrdNT / h->M, h->ns_max)); }
+
+size_t prd_stage_bytes(const rt_handle *h) { return (size_t)2 * h->M * h->ns_max * sizeof(double); }
+
+size_t prd_carry_bytes(const rt_handle *h) {
+    return (size_t)2 * prd_chunks(h) * h->M * 3 * sizeof(double);
+}
+
+bool prd_global_stage(const rt_handle *h) {
+    return std::max(prd_stage_bytes(h), prd_carry_bytes(h)) > kPrdLdsMax;
+}
+
+// Stage slot of (depth j, |mu| m), rotated by j so that the in-order sum over
+// m, one lane per depth, spreads over the LDS banks.
+__device__ inline int stage_slot(int j, int m, int M) { return j * M + (m + j) % M; }
+
+template <bool kGlobalStage>
 __global__ __launch_bounds__(kPrdNT) void prd_sweep_kernel(PrdArgs a) {
-    const int slab = blockIdx.y;
+    extern __shared__ double lds[];
+    const int p = blockIdx.x, slab = blockIdx.y;
     const AtmDesc at = a.atm[slab];
-    const int r = blockIdx.x * kPrdNT + threadIdx.x;
-    if (r >= a.M * a.n_nu) return;
-    const int mp = r / a.n_nu, p = r % a.n_nu, ns = at.ns;
+    const int M = a.M, nch = a.nch, ns = at.ns, t = threadIdx.x;
+    const bool active = t < M * nch;
+    const int mp = active ? t % M : 0, c = active ? t / M : 0;
+    const int L = (ns + nch - 1) / nch;
+    const int j0 = std::min(c * L, ns), j1 = std::min(j0 + L, ns);
+    double *stage = kGlobalStage ? a.stage + 2 * ((long long)p * a.ns_total + at.doff) * M : lds;
+    double *carry = lds;  // [2][nch][M][3]; in LDS mode it aliases the stage
     const double kap = a.opac[(long long)slab * a.n_nu + p] / a.mu_pos[mp];
     const double wq = 0.5 * a.w_pos[mp];
     const double t1 = a.dirc[mp].x, t12 = a.dirc[mp].y;
     const double *tau = a.tau + at.doff;
-    auto src = [&](int k, double &s0, double &s2) {
+    auto src = [&](int j, double &s0, double &s2) {
         if (a.sig_in) {
             const double2 v = *reinterpret_cast<const double2 *>(
-                a.sig_in + 2 * ((long long)(at.doff + k) * a.n_nu + p));
+                a.sig_in + 2 * ((long long)(at.doff + j) * a.n_nu + p));
             s0 = v.x;
             s2 = v.y;
         } else {
             s0 = s2 = 0.0;
         }
     };
-    auto slot = [&](int k) {
-        return reinterpret_cast<double2 *>(
-            a.Jm + 2 * (((long long)mp * a.ns_total + at.doff + k) * a.n_nu + p));
+    auto bnd = [&](int dir) { return (!a.sig_in && dir == 1) ? at.Ibot : 0.0; };
+    // ray points [r0, r1) of this lane's chunk in direction dir (point k of
+    // the ray is depth k going down, depth ns - 1 - k going up)
+    auto range = [&](int dir, int &r0, int &r1) {
+        r0 = dir == 0 ? j0 : ns - j1;
+        r1 = dir == 0 ? j1 : ns - j0;
     };
-    for (int dir = 0; dir < 2; ++dir) {
+    auto emit = [&](int dir, int k, double X, double Y) {
+        const int j = dir == 0 ? k : ns - 1 - k;
+        double2 v = make_double2(wq * fma(t1, Y, X), wq * fma(t12, Y, t1 * X));
+        double2 *d = reinterpret_cast<double2 *>(stage + 2 * stage_slot(j, mp, M));
+        if (dir == 1) {
+            const double2 o = *d;
+            v.x += o.x;
+            v.y += o.y;
+        }
+        *d = v;
+    };
+    // steps kb..r1-1 of direction dir from (X, Y) at point kb - 1; alpha
+    // collects the product of the attenuation factors
+    auto run = [&](int dir, int kb, int r1, double &X, double &Y, double &alpha, auto EMIT) {
         auto pt = [&](int k) { return dir == 0 ? k : ns - 1 - k; };
-        auto put = [&](int k, double X, double Y) {
-            double2 c = make_double2(wq * fma(t1, Y, X), wq * fma(t12, Y, t1 * X));
-            double2 *d = slot(pt(k));
-            if (dir == 1) {
-                const double2 o = *d;
-                c.x += o.x;
-                c.y += o.y;
-            }
-            *d = c;
-        };
-        double X = (!a.sig_in && dir == 1) ? at.Ibot : 0.0, Y = 0.0;
-        put(0, X, Y);
         double su0, su2, sk0, sk2;
-        src(pt(0), su0, su2);
-        src(pt(1), sk0, sk2);
-        for (int k = 1; k < ns; ++k) {
+        src(pt(kb - 1), su0, su2);
+        src(pt(kb), sk0, sk2);
+        for (int k = kb; k < r1; ++k) {
             const bool has_dn = k + 1 < ns;
             double sd0 = 0.0, sd2 = 0.0;
             if (has_dn) src(pt(k + 1), sd0, sd2);
@@ -95,34 +133,83 @@ __global__ __launch_bounds__(kPrdNT) void prd_sweep_kernel(PrdArgs a) {
             ray_step(a.fs, d, dd, has_dn, E, cu, ck, cd);
             X = E * X + cu * su0 + ck * sk0 + cd * sd0;
             Y = E * Y + cu * su2 + ck * sk2 + cd * sd2;
-            put(k, X, Y);
+            alpha *= E;
+            if constexpr (decltype(EMIT)::value) emit(dir, k, X, Y);
             su0 = sk0;
             su2 = sk2;
             sk0 = sd0;
             sk2 = sd2;
         }
+    };
+    // pass 1: each chunk's affine map X_out = alpha X_in + (bx, by)
+    double map[2][3];
+    if (active) {
+        for (int dir = 0; dir < 2; ++dir) {
+            int r0, r1;
+            range(dir, r0, r1);
+            double X = 0.0, Y = 0.0, alpha = 1.0;
+            if (r0 < r1) {
+                if (r0 == 0) X = bnd(dir);
+                if (std::max(r0, 1) < r1) run(dir, std::max(r0, 1), r1, X, Y, alpha, std::false_type{});
+                if (r0 == 0) alpha = 0.0;  // the boundary fixes this chunk's exit
+            }
+            map[dir][0] = alpha;
+            map[dir][1] = X;
+            map[dir][2] = Y;
+        }
     }
-}
-
-// J(kk, p) = sum over |mu| (in order) of the slots.  One thread per (kk, p).
-__global__ void prd_jsum_kernel(PrdArgs a) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (long long)a.ns_total * a.n_nu) return;
-    double2 s = make_double2(0.0, 0.0);
-    for (int mp = 0; mp < a.M; ++mp) {
-        const double2 v =
-            *reinterpret_cast<const double2 *>(a.Jm + 2 * ((long long)mp * a.ns_total * a.n_nu + e));
-        s.x += v.x;
-        s.y += v.y;
+    if (active)
+        for (int dir = 0; dir < 2; ++dir)
+            for (int e = 0; e < 3; ++e) carry[((dir * nch + c) * M + mp) * 3 + e] = map[dir][e];
+    __syncthreads();
+    // fold the preceding chunks (in ray order) into the entering intensity
+    double Xin[2] = {0.0, 0.0}, Yin[2] = {0.0, 0.0};
+    if (active) {
+        for (int dir = 0; dir < 2; ++dir) {
+            const int n = dir == 0 ? c : nch - 1 - c;
+            for (int i = 0; i < n; ++i) {
+                const int cc = dir == 0 ? i : nch - 1 - i;
+                const double *m = carry + ((dir * nch + cc) * M + mp) * 3;
+                Xin[dir] = m[0] * Xin[dir] + m[1];
+                Yin[dir] = m[0] * Yin[dir] + m[2];
+            }
+        }
     }
-    *reinterpret_cast<double2 *>(a.J + 2 * e) = s;
+    __syncthreads();  // LDS mode: the maps are read before the stage is written
+    // pass 2: the chunk again from its entering intensity, to the stage
+    if (active) {
+        for (int dir = 0; dir < 2; ++dir) {
+            int r0, r1;
+            range(dir, r0, r1);
+            if (r0 >= r1) continue;
+            double X = Xin[dir], Y = Yin[dir], alpha = 1.0;
+            if (r0 == 0) {
+                X = bnd(dir);
+                Y = 0.0;
+                emit(dir, 0, X, Y);
+            }
+            if (std::max(r0, 1) < r1) run(dir, std::max(r0, 1), r1, X, Y, alpha, std::true_type{});
+        }
+    }
+    __syncthreads();
+    // J[p][k][K] = sum over |mu| in order
+    double *Jo = a.J + 2 * ((long long)p * a.ns_total + at.doff);
+    for (int e = t; e < 2 * ns; e += kPrdNT) {
+        const int j = e >> 1, K = e & 1;
+        double s = 0.0;
+        for (int m = 0; m < M; ++m) s += stage[2 * stage_slot(j, m, M) + K];
+        Jo[e] = s;
+    }
 }
 
 // One wavefront per 16 x 16 tile of Jt (rows p, columns c = 2k + K) of one
 // slab.  Lane l feeds A[l % 16][l / 16] = Rw(p0 + l % 16, q0 + l / 16) and
-// B[l / 16][l % 16] = J(q0 + l / 16, c0 + l % 16); result register r of lane
-// l is Jt(p0 + 4 r + l / 16, c0 + l % 16).
+// B[l / 16][l % 16] = J(q0 + l / 16, c0 + l % 16), each 16 lanes reading 16
+// consecutive doubles; result register r of lane l is
+// Jt(p0 + 4 r + l / 16, c0 + l % 16).  Eight q-steps of loads are issued
+// before their products.
 __global__ __launch_bounds__(kPrdNT) void prd_contract_kernel(PrdArgs a) {
+    constexpr int U = 8;
     const int slab = blockIdx.z;
     const AtmDesc at = a.atm[slab];
     const int lane = threadIdx.x % kWave;
@@ -130,17 +217,23 @@ __global__ __launch_bounds__(kPrdNT) void prd_contract_kernel(PrdArgs a) {
     const int p0 = blockIdx.y * 16, c0 = ctile * 16;
     const int ncol = 2 * at.ns, nnu = a.n_nu;
     if (c0 >= ncol) return;
-    const double *Rw = a.Rw + (long long)slab * nnu * nnu;
+    const double *RwT = a.RwT + (long long)slab * nnu * nnu;
     const int pa = p0 + lane % 16, kq = lane / 16;      // A operand
     const int cb = c0 + lane % 16;                      // B operand column
-    const double *Jcol = a.J + 2LL * (long long)at.doff * nnu + (cb % 2);
-    const int kb = cb / 2;
+    const double *Jb = a.J + 2LL * at.doff;
+    const long long js = 2LL * a.ns_total;              // J row stride (one q)
+    const bool arow = pa < nnu, bcol = cb < ncol;
     v4d acc = {0.0, 0.0, 0.0, 0.0};
-    for (int q0 = 0; q0 < nnu; q0 += 4) {
-        const int q = q0 + kq;
-        const double av = (pa < nnu && q < nnu) ? Rw[(long long)pa * nnu + q] : 0.0;
-        const double bv = (cb < ncol && q < nnu) ? Jcol[2 * ((long long)kb * nnu + q)] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    for (int q0 = 0; q0 < nnu; q0 += 4 * U) {
+        double av[U], bv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = q0 + 4 * u + kq;
+            av[u] = (arow && q < nnu) ? RwT[(long long)q * nnu + pa] : 0.0;
+            bv[u] = (bcol && q < nnu) ? Jb[q * js + cb] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
     }
     const int c = c0 + lane % 16;
     if (c >= ncol) return;
@@ -190,7 +283,7 @@ __global__ void prd_diag_kernel(PrdArgs a, double *diag, double *dinv) {
         s0 += wq * lam;
         s2 += wq * a.dirc[mp].y * lam;
     }
-    const double g = a.Rw[((long long)slab * a.n_nu + p) * a.n_nu + p] / a.phi[(long long)slab * a.n_nu + p];
+    const double g = a.RwT[((long long)slab * a.n_nu + p) * a.n_nu + p] / a.phi[(long long)slab * a.n_nu + p];
     const double d0 = 1.0 - at.xi * g * s0, d2 = 1.0 - at.xi * at.W2 * g * s2;
     diag[2 * e] = d0;
     diag[2 * e + 1] = d2;
@@ -209,15 +302,16 @@ PrdArgs prd_args(const rt_handle *h, const double *in, double *out) {
     a.B = h->d_B;
     a.phi = h->d_phi;
     a.dirc = h->d_dirc;
-    a.Rw = h->d_Rw;
+    a.RwT = h->d_Rw;
     a.sig_in = in;
     a.sig_out = out;
-    a.Jm = h->d_prd_Jm;
+    a.stage = h->d_prd_Jm;
     a.J = h->d_prd_J;
     a.fs = h->fs;
     a.M = h->M;
     a.n_nu = h->n_nu;
     a.ns_total = h->ns_total;
+    a.nch = prd_chunks(h);
     return a;
 }
 
@@ -225,14 +319,14 @@ PrdArgs prd_args(const rt_handle *h, const double *in, double *out) {
 
 hipError_t apply_prd_operator(const rt_handle *h, const double *in, double *out, hipStream_t s) {
     const PrdArgs a = prd_args(h, in, out);
-    const int R = h->M * h->n_nu;
-    hipLaunchKernelGGL(prd_sweep_kernel, dim3((R + kPrdNT - 1) / kPrdNT, h->n_atm), dim3(kPrdNT),
-                       0, s, a);
+    const dim3 grid(h->n_nu, h->n_atm);
+    if (prd_global_stage(h))
+        hipLaunchKernelGGL(prd_sweep_kernel<true>, grid, dim3(kPrdNT), prd_carry_bytes(h), s, a);
+    else
+        hipLaunchKernelGGL(prd_sweep_kernel<false>, grid, dim3(kPrdNT),
+                           std::max(prd_stage_bytes(h), prd_carry_bytes(h)), s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const long long npts = (long long)h->ns_total * h->n_nu;
-    hipLaunchKernelGGL(prd_jsum_kernel, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     const int ctiles = (2 * h->ns_max + 15) / 16, per = kPrdNT / kWave;
     hipLaunchKernelGGL(prd_contract_kernel,
                        dim3((ctiles + per - 1) / per, (h->n_nu + 15) / 16, h->n_atm), dim3(kPrdNT),
@@ -261,7 +355,8 @@ int ensure_prd(rt_handle *h, hipStream_t s) {
         }
         return true;
     };
-    if (!get(&h->d_prd_Jm, 2LL * h->M * npts) || !get(&h->d_prd_J, 2 * npts) ||
+    if (h->M > kPrdNT) return fail(RT_EINVAL, "redistribution: at most 512 angle nodes");
+    if ((prd_global_stage(h) && !get(&h->d_prd_Jm, 2LL * h->M * npts)) || !get(&h->d_prd_J, 2 * npts) ||
         !get(&h->d_prd_diag, 2 * npts) || !get(&h->d_prd_dinv, 2 * npts))
         return fail(RT_ENOMEM, "redistribution workspace allocation failed");
     if (prd_diag(h, h->d_prd_diag, h->d_prd_dinv, s) != hipSuccess)

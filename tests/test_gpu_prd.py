@@ -99,6 +99,50 @@ def test_prd_config5_full_operator():
     assert rel < 1e-9, rel
 
 
+def _batch_case(ns_list, n_mu, n_nu, fs, gamma, seed):
+    ranges = [(1e-3, 1e5), (1e-4, 1e8), (1e-2, 1e4)]
+    n = len(ns_list)
+    p = W.make_slabs(ns_list, [ranges[i % 3] for i in range(n)], n_mu, n_nu, 6.0,
+                     [1e-3 * (i + 1) for i in range(n)], [1e-2 / (i + 1) for i in range(n)],
+                     [0.5 - 0.1 * i for i in range(n)], formal_solver=fs)
+    R = np.stack([W.redistribution_matrix(p.x, p.w_nu, p.phi[i], gamma) for i in range(n)])
+    v = np.random.default_rng(seed).uniform(-1, 1, 2 * n_nu * int(np.sum(ns_list)))
+    return p, R, v
+
+
+def _check_batch(p, R, v):
+    nnu = len(p.w_nu)
+    with B.setup(p) as h:
+        h.set_redistribution(R)
+        y = host(h.apply_op_prd(dev(v)))
+        b = host(h.get_rhs_prd())
+    off = 0
+    for i, ns in enumerate(int(n) for n in p.ns):
+        seg = slice(2 * nnu * off, 2 * nnu * (off + ns))
+        assert normwise(RDO.apply(p, R[i], v[seg], i=i), y[seg], v[seg]) <= 1e-12, i
+        rb = RDO.rhs(p, R[i], i=i)
+        assert np.abs(b[seg] - rb).max() <= 1e-12 * np.abs(rb).max(), i
+        off += ns
+
+
+@pytest.mark.parametrize("fs", ["delo_linear", "delo_parabolic"])
+def test_prd_uneven_batch(fs):
+    """Three slabs of 7, 23 and 40 depths with their own R, profiles and
+    parameters: per-slab depth chunks (some empty) and slab offsets."""
+    _check_batch(*_batch_case([7, 23, 40], 8, 12, fs, 0.5, 5))
+
+
+def test_prd_long_rays_global_stage():
+    """700 depths x 16 |mu|: the per-frequency quadrature stage exceeds the
+    LDS budget and lives in global memory; a 300-depth slab beside it."""
+    _check_batch(*_batch_case([700, 300], 32, 6, "delo_linear", 0.5, 6))
+
+
+def test_prd_tiny_slabs():
+    """2-, 3- and 5-depth slabs: chunks of one point and empty chunks."""
+    _check_batch(*_batch_case([2, 3, 5], 4, 3, "delo_linear", 0.3, 7))
+
+
 def test_prd_requires_R():
     p = W.config1_subgrid()
     with B.setup(p) as h:
