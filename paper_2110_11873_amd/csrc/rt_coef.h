@@ -184,8 +184,19 @@ __device__ inline void ray_step(int fs, double d, double dd, bool has_dn, double
         ck = d / (1.0 + d);
         return;
     }
-    step_coef(RT_FS_DELO_LINEAR, d, cu, ck);
-    E = exp(-d);
+    // DELO-linear with one exponential: below d = 0.1 the series gives c_u
+    // and c_k and E = 1 - (c_u + c_k) (a constant source is transmitted
+    // exactly, so c_u + c_k = 1 - E); above it 1 - E >= 0.095 carries no
+    // cancellation.
+    if (d < 0.1) {
+        step_coef(RT_FS_DELO_LINEAR, d, cu, ck);
+        E = 1.0 - (cu + ck);
+    } else {
+        E = exp(-d);
+        const double w0 = 1.0 - E;
+        cu = (w0 - d * E) / d;
+        ck = w0 - cu;
+    }
 }
 
 // Lambda(k, k) of one DELO-parabolic ray through depth k, walking toward

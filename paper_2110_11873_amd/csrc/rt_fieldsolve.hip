@@ -8,7 +8,7 @@
 // slabs advance in lock step and a converged slab stops updating.  Classical
 // Gram-Schmidt applied twice, with segmented reductions: each workgroup sums
 // a chunk of one slab's segment for all basis rows at once, and a second
-// pass adds the chunks in chunk order (deterministic).  No preconditioner:
+// pass adds the chunks in a fixed order (deterministic).  No preconditioner:
 // the field system is the one Sect. 3.2 calls more favourable to Krylov
 // methods.  The redistribution variant uses the same solver with its own
 // operator and a Jacobi scaling.
@@ -27,7 +27,9 @@ namespace rt {
 namespace {
 
 constexpr int kFsNT = 256;
-constexpr int kFsChunk = 8192;  // field entries per workgroup in the reductions
+constexpr int kFsChunk = 1024;  // vector entries per workgroup
+constexpr int kFsPerThread = kFsChunk / kFsNT;
+constexpr int kFsPerLane = kFsChunk / kWave;
 
 struct FsArgs {
     const long long *off;  // [n_atm + 1] first entry of each slab's segment
@@ -50,38 +52,47 @@ __device__ inline bool working(const FsArgs &a, int s) { return a.active[s] && !
 
 // part[s][c][i] = sum over chunk c of slab s of x[e] * V_i[e] (i < nv), or of
 // x[e]^2 when V is NULL.  mode 1: all active slabs (restart); 0: working ones.
+// Each lane keeps its entries of x in registers and every wavefront reduces
+// whole rows (rows w, w + 4, ...) with a butterfly: no LDS, no barrier.
 __global__ __launch_bounds__(kFsNT) void fs_dots_kernel(FsArgs a, const double *x, int nv,
                                                          const double *V, int mode) {
-    __shared__ double red[kFsNT / kWave];
     const int s = blockIdx.y, c = blockIdx.x;
     if (!(mode ? a.active[s] : working(a, s))) return;
     const long long lo = a.off[s] + (long long)c * kFsChunk;
     const long long hi = std::min(a.off[s + 1], lo + kFsChunk);
-    for (int i = 0; i < nv; ++i) {
+    const int lane = threadIdx.x % kWave;
+    double xv[kFsPerLane];
+#pragma unroll
+    for (int u = 0; u < kFsPerLane; ++u) {
+        const long long e = lo + lane + (long long)u * kWave;
+        xv[u] = e < hi ? x[e] : 0.0;
+    }
+    for (int i = threadIdx.x / kWave; i < nv; i += kFsNT / kWave) {
+        const double *Vi = V ? V + (long long)i * a.N : x;
         double acc = 0.0;
-        if (lo < hi)
-            for (long long e = lo + threadIdx.x; e < hi; e += kFsNT)
-                acc = fma(x[e], V ? V[(long long)i * a.N + e] : x[e], acc);
-        for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int w = 0; w < kFsNT / kWave; ++w) t += red[w];
-            a.part[((long long)s * a.nchunk + c) * (a.m + 1) + i] = t;
+#pragma unroll
+        for (int u = 0; u < kFsPerLane; ++u) {
+            const long long e = lo + lane + (long long)u * kWave;
+            acc = fma(xv[u], V ? (e < hi ? Vi[e] : 0.0) : xv[u], acc);
         }
-        __syncthreads();
+        for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) a.part[((long long)s * a.nchunk + c) * (a.m + 1) + i] = acc;
     }
 }
 
-// h[s][i] = sum over chunks (in order) of part[s][c][i].
-__global__ void fs_reduce_kernel(FsArgs a, int nv, int mode) {
+// h[s][i] = sum over the chunks of part[s][c][i]: one wavefront per row i,
+// lane l adding chunks l, l + 64, ... in order, then a butterfly (a fixed
+// order for a given chunk count: deterministic).
+__global__ __launch_bounds__(1024) void fs_reduce_kernel(FsArgs a, int nv, int mode) {
     const int s = blockIdx.x;
     if (!(mode ? a.active[s] : working(a, s))) return;
-    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    const int lane = threadIdx.x % kWave;
+    const double *ps = a.part + (long long)s * a.nchunk * (a.m + 1);
+    for (int i = threadIdx.x / kWave; i < nv; i += blockDim.x / kWave) {
         double t = 0.0;
-        for (int c = 0; c < a.nchunk; ++c) t += a.part[((long long)s * a.nchunk + c) * (a.m + 1) + i];
-        a.h[(long long)s * (a.m + 1) + i] = t;
+        for (int c = lane; c < a.nchunk; c += kWave) t += ps[(long long)c * (a.m + 1) + i];
+        for (int o = kWave / 2; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        if (lane == 0) a.h[(long long)s * (a.m + 1) + i] = t;
     }
 }
 
@@ -94,10 +105,25 @@ __global__ __launch_bounds__(kFsNT) void fs_axpy_kernel(FsArgs a, double *w, int
     const double *hs = a.h + (long long)s * (a.m + 1);
     const long long lo = a.off[s] + (long long)blockIdx.x * kFsChunk;
     const long long hi = std::min(a.off[s + 1], lo + kFsChunk);
-    for (long long e = lo + threadIdx.x; e < hi; e += kFsNT) {
-        double v = w[e];
-        for (int i = 0; i < nv; ++i) v = fma(-hs[i], a.V[(long long)i * a.N + e], v);
-        w[e] = v;
+    double v[kFsPerThread];
+#pragma unroll
+    for (int u = 0; u < kFsPerThread; ++u) {
+        const long long e = lo + threadIdx.x + (long long)u * kFsNT;
+        v[u] = e < hi ? w[e] : 0.0;
+    }
+    for (int i = 0; i < nv; ++i) {
+        const double c = -hs[i];
+        const double *Vi = a.V + (long long)i * a.N;
+#pragma unroll
+        for (int u = 0; u < kFsPerThread; ++u) {
+            const long long e = lo + threadIdx.x + (long long)u * kFsNT;
+            if (e < hi) v[u] = fma(c, Vi[e], v[u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kFsPerThread; ++u) {
+        const long long e = lo + threadIdx.x + (long long)u * kFsNT;
+        if (e < hi) w[e] = v[u];
     }
     if (blockIdx.x == 0 && threadIdx.x < nv) {
         double *Hc = a.H + (long long)s * (a.m + 1) * a.m + (long long)threadIdx.x * a.m + j;
@@ -175,10 +201,24 @@ __global__ __launch_bounds__(kFsNT) void fs_update_kernel(FsArgs a, double *x) {
     const int n = a.jj[s];
     const long long lo = a.off[s] + (long long)blockIdx.x * kFsChunk;
     const long long hi = std::min(a.off[s + 1], lo + kFsChunk);
-    for (long long e = lo + threadIdx.x; e < hi; e += kFsNT) {
-        double v = x[e];
-        for (int i = 0; i < n; ++i) v = fma(y[i], a.V[(long long)i * a.N + e], v);
-        x[e] = v;
+    double v[kFsPerThread];
+#pragma unroll
+    for (int u = 0; u < kFsPerThread; ++u) {
+        const long long e = lo + threadIdx.x + (long long)u * kFsNT;
+        v[u] = e < hi ? x[e] : 0.0;
+    }
+    for (int i = 0; i < n; ++i) {
+        const double *Vi = a.V + (long long)i * a.N;
+#pragma unroll
+        for (int u = 0; u < kFsPerThread; ++u) {
+            const long long e = lo + threadIdx.x + (long long)u * kFsNT;
+            if (e < hi) v[u] = fma(y[i], Vi[e], v[u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kFsPerThread; ++u) {
+        const long long e = lo + threadIdx.x + (long long)u * kFsNT;
+        if (e < hi) x[e] = v[u];
     }
 }
 
@@ -340,7 +380,7 @@ int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *,
     hipLaunchKernelGGL(fs_init_kernel, dim3(tg), dim3(tb), 0, st, a);
     // ||b||, then r = b - K x
     hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, b, 1, (const double *)nullptr, 1);
-    hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(64), 0, st, a, 1, 1);
+    hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, 1, 1);
     hipLaunchKernelGGL(fs_keep_bnorm_kernel, dim3(tg), dim3(tb), 0, st, a);
     bool first = true;
     int napply = 0;
@@ -350,7 +390,7 @@ int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *,
         hipLaunchKernelGGL(fs_residual_kernel, seg, blk, 0, st, a, b, (const double *)w);
         hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)a.V, 1,
                            (const double *)nullptr, 1);
-        hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(64), 0, st, a, 1, 1);
+        hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, 1, 1);
         hipLaunchKernelGGL(fs_restart_kernel, dim3(tg), dim3(tb), 0, st, a, first ? 1 : 0,
                            h->opt.maxit);
         first = false;
@@ -364,13 +404,13 @@ int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *,
             for (int pass = 0; pass < 2; ++pass) {
                 hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)w, j + 1,
                                    (const double *)a.V, 0);
-                hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(64), 0, st, a, j + 1, 0);
+                hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, j + 1, 0);
                 hipLaunchKernelGGL(fs_axpy_kernel, seg, blk, 0, st, a, w, j + 1, j,
                                    pass == 0 ? 1 : 0);
             }
             hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)w, 1,
                                (const double *)nullptr, 0);
-            hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(64), 0, st, a, 1, 0);
+            hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, 1, 0);
             hipLaunchKernelGGL(fs_givens_kernel, dim3(tg), dim3(tb), 0, st, a, j);
             hipLaunchKernelGGL(fs_scale_kernel, seg, blk, 0, st, a, (const double *)w, j);
             ok(hipGetLastError());
@@ -396,7 +436,7 @@ int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *,
     hipLaunchKernelGGL(fs_residual_kernel, seg, blk, 0, st, a, b, (const double *)w);
     hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)a.V, 1,
                        (const double *)nullptr, 1);
-    hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(64), 0, st, a, 1, 1);
+    hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, 1, 1);
     std::vector<double> hh((size_t)n_atm * (m + 1)), bn(n_atm);
     std::vector<int> its(n_atm);
     ok(hipMemcpyAsync(hh.data(), a.h, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, st));

@@ -18,7 +18,7 @@
 //    buffer private to the workgroup;
 //  * prd_contract_kernel: the redistribution Jt(p, c) = sum_q R(p, q) w_q
 //    J(q, c) over the columns c = (k, K) of a slab -- a dense product, on
-//    the FP64 matrix cores (v_mfma_f64_16x16x4: one wavefront per 16 x 16
+//    the FP64 matrix cores (v_mfma_f64_16x16x4: one workgroup per 16 x 16
 //    tile of Jt, four q per instruction, both operands read along
 //    contiguous rows: R w is stored transposed, J frequency-major) -- with
 //    the scattering step fused into its output:
@@ -38,7 +38,8 @@ namespace rt {
 
 namespace {
 
-constexpr int kPrdNT = 256;
+constexpr int kPrdNT = 256;       // contraction
+constexpr int kPrdSweepNT = 512;  // sweep: lanes per (|mu|, chunk)
 constexpr size_t kPrdLdsMax = 64 * 1024;
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -55,8 +56,8 @@ struct PrdArgs {
     int fs, M, n_nu, ns_total, nch;
 };
 
-// Lanes per (|mu|, chunk): M |mu| values times nch chunks <= kPrdNT.
-int prd_chunks(const rt_handle *h) { return std::max(1, std::min(kPrdNT / h->M, h->ns_max)); }
+// Lanes per (|mu|, chunk): M |mu| values times nch chunks <= kPrdSweepNT.
+int prd_chunks(const rt_handle *h) { return std::max(1, std::min(kPrdSweepNT / h->M, h->ns_max)); }
 
 size_t prd_stage_bytes(const rt_handle *h) { return (size_t)2 * h->M * h->ns_max * sizeof(double); }
 
@@ -73,7 +74,7 @@ bool prd_global_stage(const rt_handle *h) {
 __device__ inline int stage_slot(int j, int m, int M) { return j * M + (m + j) % M; }
 
 template <bool kGlobalStage>
-__global__ __launch_bounds__(kPrdNT) void prd_sweep_kernel(PrdArgs a) {
+__global__ __launch_bounds__(kPrdSweepNT) void prd_sweep_kernel(PrdArgs a) {
     extern __shared__ double lds[];
     const int p = blockIdx.x, slab = blockIdx.y;
     const AtmDesc at = a.atm[slab];
@@ -117,28 +118,45 @@ __global__ __launch_bounds__(kPrdNT) void prd_sweep_kernel(PrdArgs a) {
         *d = v;
     };
     // steps kb..r1-1 of direction dir from (X, Y) at point kb - 1; alpha
-    // collects the product of the attenuation factors
+    // collects the product of the attenuation factors.  Sources and depths
+    // of point k + 1 + kAhead are loaded at step k (a register queue), so the
+    // loads overlap the coefficient arithmetic of the steps before.
     auto run = [&](int dir, int kb, int r1, double &X, double &Y, double &alpha, auto EMIT) {
+        constexpr int kAhead = 2;
         auto pt = [&](int k) { return dir == 0 ? k : ns - 1 - k; };
-        double su0, su2, sk0, sk2;
-        src(pt(kb - 1), su0, su2);
-        src(pt(kb), sk0, sk2);
+        double qs0[kAhead + 2], qs2[kAhead + 2], qt[kAhead + 2];  // points kb - 1 .. kb + kAhead
+#pragma unroll
+        for (int i = 0; i < kAhead + 2; ++i) {
+            const int k = kb - 1 + i;
+            qs0[i] = qs2[i] = qt[i] = 0.0;
+            if (k < ns) {
+                src(pt(k), qs0[i], qs2[i]);
+                qt[i] = tau[pt(k)];
+            }
+        }
         for (int k = kb; k < r1; ++k) {
+            // the queue holds points k - 1 .. k + kAhead
             const bool has_dn = k + 1 < ns;
-            double sd0 = 0.0, sd2 = 0.0;
-            if (has_dn) src(pt(k + 1), sd0, sd2);
-            const double d = kap * fabs(tau[pt(k)] - tau[pt(k - 1)]);
-            const double dd = has_dn ? kap * fabs(tau[pt(k + 1)] - tau[pt(k)]) : 1.0;
+            const double d = kap * fabs(qt[1] - qt[0]);
+            const double dd = has_dn ? kap * fabs(qt[2] - qt[1]) : 1.0;
             double E, cu, ck, cd;
             ray_step(a.fs, d, dd, has_dn, E, cu, ck, cd);
-            X = E * X + cu * su0 + ck * sk0 + cd * sd0;
-            Y = E * Y + cu * su2 + ck * sk2 + cd * sd2;
+            X = E * X + cu * qs0[0] + ck * qs0[1] + cd * qs0[2];
+            Y = E * Y + cu * qs2[0] + ck * qs2[1] + cd * qs2[2];
             alpha *= E;
             if constexpr (decltype(EMIT)::value) emit(dir, k, X, Y);
-            su0 = sk0;
-            su2 = sk2;
-            sk0 = sd0;
-            sk2 = sd2;
+#pragma unroll
+            for (int i = 0; i < kAhead + 1; ++i) {
+                qs0[i] = qs0[i + 1];
+                qs2[i] = qs2[i + 1];
+                qt[i] = qt[i + 1];
+            }
+            const int kn = k + 1 + kAhead;
+            qs0[kAhead + 1] = qs2[kAhead + 1] = qt[kAhead + 1] = 0.0;
+            if (kn < ns && kn <= r1) {
+                src(pt(kn), qs0[kAhead + 1], qs2[kAhead + 1]);
+                qt[kAhead + 1] = tau[pt(kn)];
+            }
         }
     };
     // pass 1: each chunk's affine map X_out = alpha X_in + (bx, by)
@@ -194,7 +212,7 @@ __global__ __launch_bounds__(kPrdNT) void prd_sweep_kernel(PrdArgs a) {
     __syncthreads();
     // J[p][k][K] = sum over |mu| in order
     double *Jo = a.J + 2 * ((long long)p * a.ns_total + at.doff);
-    for (int e = t; e < 2 * ns; e += kPrdNT) {
+    for (int e = t; e < 2 * ns; e += kPrdSweepNT) {
         const int j = e >> 1, K = e & 1;
         double s = 0.0;
         for (int m = 0; m < M; ++m) s += stage[2 * stage_slot(j, m, M) + K];
@@ -202,21 +220,23 @@ __global__ __launch_bounds__(kPrdNT) void prd_sweep_kernel(PrdArgs a) {
     }
 }
 
-// One wavefront per 16 x 16 tile of Jt (rows p, columns c = 2k + K) of one
-// slab.  Lane l feeds A[l % 16][l / 16] = Rw(p0 + l % 16, q0 + l / 16) and
+// One workgroup per 16 x 16 tile of Jt (rows p, columns c = 2k + K) of one
+// slab; its four wavefronts take the q-steps q0 = 4 (w + 4 t), and their
+// accumulators are added in wavefront order through LDS.  Lane l feeds
+// A[l % 16][l / 16] = Rw(p0 + l % 16, q0 + l / 16) and
 // B[l / 16][l % 16] = J(q0 + l / 16, c0 + l % 16), each 16 lanes reading 16
 // consecutive doubles; result register r of lane l is
 // Jt(p0 + 4 r + l / 16, c0 + l % 16).  Eight q-steps of loads are issued
 // before their products.
 __global__ __launch_bounds__(kPrdNT) void prd_contract_kernel(PrdArgs a) {
-    constexpr int U = 8;
+    constexpr int U = 8, NW = kPrdNT / kWave;
+    __shared__ v4d red[NW - 1][kWave];
     const int slab = blockIdx.z;
     const AtmDesc at = a.atm[slab];
-    const int lane = threadIdx.x % kWave;
-    const int ctile = blockIdx.x * (kPrdNT / kWave) + threadIdx.x / kWave;
-    const int p0 = blockIdx.y * 16, c0 = ctile * 16;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    const int p0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
     const int ncol = 2 * at.ns, nnu = a.n_nu;
-    if (c0 >= ncol) return;
+    if (c0 >= ncol) return;  // the whole workgroup
     const double *RwT = a.RwT + (long long)slab * nnu * nnu;
     const int pa = p0 + lane % 16, kq = lane / 16;      // A operand
     const int cb = c0 + lane % 16;                      // B operand column
@@ -224,17 +244,22 @@ __global__ __launch_bounds__(kPrdNT) void prd_contract_kernel(PrdArgs a) {
     const long long js = 2LL * a.ns_total;              // J row stride (one q)
     const bool arow = pa < nnu, bcol = cb < ncol;
     v4d acc = {0.0, 0.0, 0.0, 0.0};
-    for (int q0 = 0; q0 < nnu; q0 += 4 * U) {
+    for (int q0 = 4 * wv; q0 < nnu; q0 += 4 * NW * U) {
         double av[U], bv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int q = q0 + 4 * u + kq;
+            const int q = q0 + 4 * NW * u + kq;
             av[u] = (arow && q < nnu) ? RwT[(long long)q * nnu + pa] : 0.0;
             bv[u] = (bcol && q < nnu) ? Jb[q * js + cb] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
     }
+    if (wv > 0) red[wv - 1][lane] = acc;
+    __syncthreads();
+    if (wv > 0) return;
+#pragma unroll
+    for (int w = 0; w < NW - 1; ++w) acc += red[w][lane];
     const int c = c0 + lane % 16;
     if (c >= ncol) return;
     const int k = c / 2, K = c % 2;
@@ -321,15 +346,15 @@ hipError_t apply_prd_operator(const rt_handle *h, const double *in, double *out,
     const PrdArgs a = prd_args(h, in, out);
     const dim3 grid(h->n_nu, h->n_atm);
     if (prd_global_stage(h))
-        hipLaunchKernelGGL(prd_sweep_kernel<true>, grid, dim3(kPrdNT), prd_carry_bytes(h), s, a);
+        hipLaunchKernelGGL(prd_sweep_kernel<true>, grid, dim3(kPrdSweepNT), prd_carry_bytes(h), s,
+                           a);
     else
-        hipLaunchKernelGGL(prd_sweep_kernel<false>, grid, dim3(kPrdNT),
+        hipLaunchKernelGGL(prd_sweep_kernel<false>, grid, dim3(kPrdSweepNT),
                            std::max(prd_stage_bytes(h), prd_carry_bytes(h)), s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int ctiles = (2 * h->ns_max + 15) / 16, per = kPrdNT / kWave;
     hipLaunchKernelGGL(prd_contract_kernel,
-                       dim3((ctiles + per - 1) / per, (h->n_nu + 15) / 16, h->n_atm), dim3(kPrdNT),
+                       dim3((2 * h->ns_max + 15) / 16, (h->n_nu + 15) / 16, h->n_atm), dim3(kPrdNT),
                        0, s, a);
     return hipGetLastError();
 }
@@ -355,7 +380,7 @@ int ensure_prd(rt_handle *h, hipStream_t s) {
         }
         return true;
     };
-    if (h->M > kPrdNT) return fail(RT_EINVAL, "redistribution: at most 512 angle nodes");
+    if (h->M > kPrdSweepNT) return fail(RT_EINVAL, "redistribution: at most 1024 angle nodes");
     if ((prd_global_stage(h) && !get(&h->d_prd_Jm, 2LL * h->M * npts)) || !get(&h->d_prd_J, 2 * npts) ||
         !get(&h->d_prd_diag, 2 * npts) || !get(&h->d_prd_dinv, 2 * npts))
         return fail(RT_ENOMEM, "redistribution workspace allocation failed");
