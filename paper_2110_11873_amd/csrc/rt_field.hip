@@ -2,17 +2,23 @@
 // (Id - Lambda T J) I = Lambda T c + t, and sigma = J I + c.
 //
 // Two passes per application:
-//  * field_quad_kernel: one wavefront per depth point sums the field over all
+//  * field_quad_kernel: one workgroup per depth point sums the field over all
 //    rays into J I = xi [J00, W2 J20] (eqs. J00/J02, S00/S02); a depth's rays
 //    are contiguous in the field, so the reads are coalesced;
-//  * field_sweep_kernel: one lane per (|mu|, nu) ray runs the formal solver
-//    downward and upward on the sources T (J I) (two linear recurrences, on
-//    s00 and s20, combined with the T factors per point), and writes the I
-//    and Q field -- subtracted from the input for the operator.  The step
+//  * field_sweep_kernel: the formal solver along every (|mu|, nu) ray,
+//    downward and upward, on the sources T (J I) (two linear recurrences, on
+//    s00 and s20, combined with the T factors per point), writing the I and Q
+//    field -- subtracted from the input for the operator.  The step
 //    coefficients are recomputed from tau (every formal solver, including
-//    the three-point DELO-parabolic step).
+//    the three-point DELO-parabolic step).  When there are few rays (a
+//    single slab) each ray is cut into depth chunks, one lane each: the
+//    chunk's affine map from zero entering intensity, a fold over the chunks
+//    before it in LDS, and a second pass from the true entering intensity.
 // Both are FP64 and deterministic (fixed-order butterflies, no atomics).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
 
 #include "rt_coef.h"
 #include "rt_internal.h"
@@ -35,16 +41,20 @@ struct FieldArgs {
     const double *sig;     // sweep sources (NULL: c = [eps B, 0])
     double *sig_out;       // quadrature output
     int fs, M, n_mu, n_nu, ns_total;
+    int nch;               // sweep: depth chunks per ray (a power of two <= kFieldNT)
     int with_c;            // quadrature: add c;  sweep: rhs mode (sources c, bottom inflow)
     int sub;               // sweep: write fin - field
 };
 
 __device__ inline double t2_of(double mu) { return sqrt(2.0) * (3.0 * mu * mu - 3.0) / 4.0; }
 
+// One workgroup per depth point: its lanes take the rays in turn, each
+// wavefront reduces by butterfly, and the wavefronts' sums are added in
+// wavefront order.
 __global__ __launch_bounds__(kFieldNT) void field_quad_kernel(FieldArgs a) {
-    const int kk = blockIdx.x * (kFieldNT / kWave) + threadIdx.x / kWave;
-    const int lane = threadIdx.x % kWave;
-    if (kk >= a.ns_total) return;
+    __shared__ double2 part[kFieldNT / kWave];
+    const int kk = blockIdx.x;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
     const AtmDesc at = a.atm[a.pt_atm[kk]];
     const int k = kk - at.doff, ns = at.ns;
     const long long base = 2LL * a.n_mu * a.n_nu * at.doff;
@@ -52,7 +62,7 @@ __global__ __launch_bounds__(kFieldNT) void field_quad_kernel(FieldArgs a) {
     const double *FQ = a.fin + base + (long long)(ns + k) * a.n_mu * a.n_nu;
     double J0 = 0.0, J2 = 0.0;
     const int nr = a.n_mu * a.n_nu;
-    for (int r = lane; r < nr; r += kWave) {
+    for (int r = threadIdx.x; r < nr; r += kFieldNT) {
         // r runs over (|mu| index, direction, frequency)
         const int mp = r / (2 * a.n_nu), dir = (r / a.n_nu) % 2, p = r % a.n_nu;
         const long long e = (long long)a.mu_idx[2 * mp + dir] * a.n_nu + p;
@@ -66,19 +76,34 @@ __global__ __launch_bounds__(kFieldNT) void field_quad_kernel(FieldArgs a) {
         J0 += __shfl_xor(J0, off);
         J2 += __shfl_xor(J2, off);
     }
-    if (lane == 0) {
+    if (lane == 0) part[wv] = make_double2(J0, J2);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        J0 = J2 = 0.0;
+        for (int w = 0; w < kFieldNT / kWave; ++w) {
+            J0 += part[w].x;
+            J2 += part[w].y;
+        }
         a.sig_out[2LL * kk] = at.xi * J0 + (a.with_c ? at.eps * a.B[kk] : 0.0);
         a.sig_out[2LL * kk + 1] = at.xi * at.W2 * J2;
     }
 }
 
+// Lane t of a workgroup: ray g = t % G of the workgroup's G rays
+// (consecutive frequencies, for coalesced field writes) and depth chunk
+// c = t / G, with G * nch = kFieldNT.
 __global__ __launch_bounds__(kFieldNT) void field_sweep_kernel(FieldArgs a) {
+    __shared__ double carry[2 * kFieldNT * 3];  // [dir][chunk][ray][alpha, bx, by]
     const int slab = blockIdx.y;
     const AtmDesc at = a.atm[slab];
-    const int r = blockIdx.x * kFieldNT + threadIdx.x;
-    if (r >= a.M * a.n_nu) return;
-    const int mp = r / a.n_nu, p = r % a.n_nu;
+    const int nch = a.nch, G = kFieldNT / nch, t = threadIdx.x;
+    const int g = t % G, c = t / G;
+    const int r = blockIdx.x * G + g;
+    const bool active = r < a.M * a.n_nu;
+    const int mp = active ? r / a.n_nu : 0, p = active ? r % a.n_nu : 0;
     const int ns = at.ns;
+    const int L = (ns + nch - 1) / nch;
+    const int j0 = std::min(c * L, ns), j1 = std::min(j0 + L, ns);
     const double kap = a.opac[(long long)slab * a.n_nu + p] / a.mu_pos[mp];
     const double t1 = a.dirc[mp].x, t2 = t2_of(a.mu_pos[mp]);
     const double *tau = a.tau + at.doff;
@@ -94,35 +119,105 @@ __global__ __launch_bounds__(kFieldNT) void field_sweep_kernel(FieldArgs a) {
             s2 = 0.0;
         }
     };
-    for (int dir = 0; dir < 2; ++dir) {
+    auto bnd = [&](int dir) { return (!a.sig && a.with_c && dir == 1) ? at.Ibot : 0.0; };
+    auto range = [&](int dir, int &r0, int &r1) {
+        r0 = dir == 0 ? j0 : ns - j1;
+        r1 = dir == 0 ? j1 : ns - j0;
+    };
+    auto put = [&](int dir, int k, double X, double Y) {
         const long long col = (long long)a.mu_idx[2 * mp + dir] * a.n_nu + p;
+        const int j = dir == 0 ? k : ns - 1 - k;
+        const long long e = base + (long long)j * a.n_mu * a.n_nu + col;
+        const double I = fma(t1, Y, X), Q = t2 * Y;
+        a.fout[e] = a.sub ? a.fin[e] - I : I;
+        a.fout[e + plane] = a.sub ? a.fin[e + plane] - Q : Q;
+    };
+    // steps kb..r1-1 of direction dir from (X, Y) at point kb - 1, with a
+    // register queue of the sources and depths two points ahead
+    auto run = [&](int dir, int kb, int r1, double &X, double &Y, double &alpha, auto EMIT) {
+        constexpr int kAhead = 2;
         auto pt = [&](int k) { return dir == 0 ? k : ns - 1 - k; };
-        auto put = [&](int k, double X, double Y) {
-            const long long e = base + (long long)pt(k) * a.n_mu * a.n_nu + col;
-            const double I = fma(t1, Y, X), Q = t2 * Y;
-            a.fout[e] = a.sub ? a.fin[e] - I : I;
-            a.fout[e + plane] = a.sub ? a.fin[e + plane] - Q : Q;
-        };
-        double X = (!a.sig && a.with_c && dir == 1) ? at.Ibot : 0.0, Y = 0.0;
-        put(0, X, Y);
-        double su0, su2, sk0, sk2;
-        src(pt(0), su0, su2);
-        src(pt(1), sk0, sk2);
-        for (int k = 1; k < ns; ++k) {
+        double qs0[kAhead + 2], qs2[kAhead + 2], qt[kAhead + 2];  // points kb - 1 .. kb + kAhead
+#pragma unroll
+        for (int i = 0; i < kAhead + 2; ++i) {
+            const int k = kb - 1 + i;
+            qs0[i] = qs2[i] = qt[i] = 0.0;
+            if (k < ns) {
+                src(pt(k), qs0[i], qs2[i]);
+                qt[i] = tau[pt(k)];
+            }
+        }
+        for (int k = kb; k < r1; ++k) {
             const bool has_dn = k + 1 < ns;
-            double sd0 = 0.0, sd2 = 0.0;
-            if (has_dn) src(pt(k + 1), sd0, sd2);
-            const double d = kap * fabs(tau[pt(k)] - tau[pt(k - 1)]);
-            const double dd = has_dn ? kap * fabs(tau[pt(k + 1)] - tau[pt(k)]) : 1.0;
+            const double d = kap * fabs(qt[1] - qt[0]);
+            const double dd = has_dn ? kap * fabs(qt[2] - qt[1]) : 1.0;
             double E, cu, ck, cd;
             ray_step(a.fs, d, dd, has_dn, E, cu, ck, cd);
-            X = E * X + cu * su0 + ck * sk0 + cd * sd0;
-            Y = E * Y + cu * su2 + ck * sk2 + cd * sd2;
-            put(k, X, Y);
-            su0 = sk0;
-            su2 = sk2;
-            sk0 = sd0;
-            sk2 = sd2;
+            X = E * X + cu * qs0[0] + ck * qs0[1] + cd * qs0[2];
+            Y = E * Y + cu * qs2[0] + ck * qs2[1] + cd * qs2[2];
+            alpha *= E;
+            if constexpr (decltype(EMIT)::value) put(dir, k, X, Y);
+#pragma unroll
+            for (int i = 0; i < kAhead + 1; ++i) {
+                qs0[i] = qs0[i + 1];
+                qs2[i] = qs2[i + 1];
+                qt[i] = qt[i + 1];
+            }
+            const int kn = k + 1 + kAhead;
+            qs0[kAhead + 1] = qs2[kAhead + 1] = qt[kAhead + 1] = 0.0;
+            if (kn < ns && kn <= r1) {
+                src(pt(kn), qs0[kAhead + 1], qs2[kAhead + 1]);
+                qt[kAhead + 1] = tau[pt(kn)];
+            }
+        }
+    };
+    double Xin[2] = {0.0, 0.0}, Yin[2] = {0.0, 0.0};
+    if (nch > 1) {
+        // pass 1: each chunk's affine map X_out = alpha X_in + (bx, by)
+        if (active) {
+            for (int dir = 0; dir < 2; ++dir) {
+                int r0, r1;
+                range(dir, r0, r1);
+                double X = 0.0, Y = 0.0, alpha = 1.0;
+                if (r0 < r1) {
+                    if (r0 == 0) X = bnd(dir);
+                    if (std::max(r0, 1) < r1)
+                        run(dir, std::max(r0, 1), r1, X, Y, alpha, std::false_type{});
+                    if (r0 == 0) alpha = 0.0;  // the boundary fixes this chunk's exit
+                }
+                double *m = carry + ((dir * nch + c) * G + g) * 3;
+                m[0] = alpha;
+                m[1] = X;
+                m[2] = Y;
+            }
+        }
+        __syncthreads();
+        // fold the preceding chunks (in ray order) into the entering intensity
+        if (active) {
+            for (int dir = 0; dir < 2; ++dir) {
+                const int n = dir == 0 ? c : nch - 1 - c;
+                for (int i = 0; i < n; ++i) {
+                    const int cc = dir == 0 ? i : nch - 1 - i;
+                    const double *m = carry + ((dir * nch + cc) * G + g) * 3;
+                    Xin[dir] = m[0] * Xin[dir] + m[1];
+                    Yin[dir] = m[0] * Yin[dir] + m[2];
+                }
+            }
+        }
+    }
+    // pass 2 (the only pass with one chunk): from the entering intensity
+    if (active) {
+        for (int dir = 0; dir < 2; ++dir) {
+            int r0, r1;
+            range(dir, r0, r1);
+            if (r0 >= r1) continue;
+            double X = Xin[dir], Y = Yin[dir], alpha = 1.0;
+            if (r0 == 0) {
+                X = bnd(dir);
+                Y = 0.0;
+                put(dir, 0, X, Y);
+            }
+            if (std::max(r0, 1) < r1) run(dir, std::max(r0, 1), r1, X, Y, alpha, std::true_type{});
         }
     }
 }
@@ -143,20 +238,23 @@ FieldArgs field_args(const rt_handle *h) {
     a.n_mu = h->n_mu;
     a.n_nu = h->n_nu;
     a.ns_total = h->ns_total;
+    // chunks per ray: doubled (up to 64) until about 64k lanes are busy
+    const long long rays = (long long)h->M * h->n_nu * h->n_atm;
+    int nch = 1;
+    while (nch < 64 && rays * nch < 65536) nch *= 2;
+    a.nch = nch;
     return a;
 }
 
 hipError_t launch_quad(const FieldArgs &a, hipStream_t s) {
-    const int per = kFieldNT / kWave;
-    hipLaunchKernelGGL(field_quad_kernel, dim3((a.ns_total + per - 1) / per), dim3(kFieldNT), 0, s,
-                       a);
+    hipLaunchKernelGGL(field_quad_kernel, dim3(a.ns_total), dim3(kFieldNT), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_field_sweep(const rt_handle *h, const FieldArgs &a, hipStream_t s) {
-    const int R = h->M * h->n_nu;
-    hipLaunchKernelGGL(field_sweep_kernel, dim3((R + kFieldNT - 1) / kFieldNT, h->n_atm),
-                       dim3(kFieldNT), 0, s, a);
+    const int R = h->M * h->n_nu, G = kFieldNT / a.nch;
+    hipLaunchKernelGGL(field_sweep_kernel, dim3((R + G - 1) / G, h->n_atm), dim3(kFieldNT), 0, s,
+                       a);
     return hipGetLastError();
 }
 
