@@ -316,6 +316,21 @@ def routes(steps):
         out["c5_prd_gmres_ms"] = 1e3 * (time.perf_counter() - t0)
         out["c5_prd_gmres_iterations"] = info[0].iterations
         out["c5_prd_gmres_relres"] = info[0].relres
+        out["c5_prd_bf16x3_matvec_us"] = 1e3 * ev_ms(lambda: h.apply_op_prd_bf16x3(v, o5), 50)
+    # the mixed solve: FP64 refinement around BF16x3 inner GMRES
+    with B.setup(p5, rtol=1e-9, restart=30, maxit=5000, precision=B.RT_PREC_MIXED) as h:
+        h.set_redistribution(R5)
+        x5 = torch.zeros(h.prd_size(), dtype=torch.float64, device="cuda")
+        h.solve_prd_gmres(x5)
+        x5.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = h.solve_prd_gmres(x5)
+        torch.cuda.synchronize()
+        out["c5_prd_mixed_ms"] = 1e3 * (time.perf_counter() - t0)
+        out["c5_prd_mixed_iterations"] = info[0].iterations
+        out["c5_prd_mixed_outer_steps"] = info[0].outer_steps
+        out["c5_prd_mixed_relres"] = info[0].relres
     counts = {"ns": [], "sigma_gmres": [], "field_gmres": []}
     for ns in (20, 40, 60, 80, 100, 120, 140):
         r = W.paper_replica(ns, scale="integrated", normalize=False)

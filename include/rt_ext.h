@@ -145,17 +145,29 @@ int rt_solve_field_gmres(rt_handle *h, const double *b_field, double *I, rt_solv
  * [eps B, 0].  R proportional to phi(p) phi(q) gives back CRD at every p.
  * rt_set_redistribution: R (host, n_atm x n_nu x n_nu, R[s][p][q] row-major;
  *   copied, finite) for the handle's slabs; enables the calls below (RT_EINVAL
- *   before).  The contraction runs on the FP64 matrix cores.
+ *   before).  The contraction runs on the FP64 matrix cores (and on the BF16
+ *   ones in the calls so named).
  * rt_prd_size: 2 n_nu sum ns doubles.
  * rt_apply_op_prd / rt_get_rhs_prd / rt_get_jacobi_diag_prd: A sigma, b,
  *   diag(A) (device arrays, stream-ordered).
+ * rt_apply_op_prd_bf16x3: A sigma with the contraction on the BF16 matrix
+ *   cores: R w and J are each split into bf16 hi + lo (about 16 significant
+ *   bits), the products hi.hi, hi.lo and lo.hi are accumulated in FP32 and
+ *   added in FP64; normwise error about 1e-5 of |sigma| + |xi J~ / phi|.
+ *   Same arguments as rt_apply_op_prd.
  * rt_solve_prd_gmres: Jacobi-preconditioned (from the right) GMRES(restart)
- *   in FP64 to options.rtol; b NULL means the handle's own b; x holds the
- *   initial guess and receives the solution; info as for rt_solve_gmres.
+ *   to options.rtol; b NULL means the handle's own b; x holds the initial
+ *   guess and receives the solution; info as for rt_solve_gmres.  FP64:
+ *   FP64 operator throughout.  MIXED: FP64 iterative refinement, r = b - A x
+ *   with the FP64 operator, an inner GMRES on the BF16x3 operator to
+ *   options.inner_rtol (inner_maxit steps at most), x += d, until
+ *   ||r|| < rtol ||b|| per slab; iterations counts the inner steps,
+ *   outer_steps the refinement steps.  Synchronizes the stream.
  */
 int rt_set_redistribution(rt_handle *h, const double *R);
 int rt_prd_size(const rt_handle *h, long long *count);
 int rt_apply_op_prd(rt_handle *h, const double *sigma_in, double *sigma_out, void *stream);
+int rt_apply_op_prd_bf16x3(rt_handle *h, const double *sigma_in, double *sigma_out, void *stream);
 int rt_get_rhs_prd(rt_handle *h, double *b, void *stream);
 int rt_get_jacobi_diag_prd(rt_handle *h, double *d, void *stream);
 int rt_solve_prd_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *info,

@@ -34,7 +34,7 @@ EXPORTS = ["rt_default_options", "rt_setup", "rt_destroy", "rt_num_unknowns", "r
            "rt_plan_info", "rt_sweep_config", "rt_validate", "rt_assembled_size", "rt_assemble",
            "rt_precond_apply", "rt_solve_lu", "rt_field_size", "rt_apply_op_field",
            "rt_get_rhs_field", "rt_sigma_from_field", "rt_solve_field_gmres",
-           "rt_set_redistribution", "rt_prd_size", "rt_apply_op_prd", "rt_get_rhs_prd",
+           "rt_set_redistribution", "rt_prd_size", "rt_apply_op_prd", "rt_apply_op_prd_bf16x3", "rt_get_rhs_prd",
            "rt_get_jacobi_diag_prd", "rt_solve_prd_gmres"]
 
 
@@ -107,6 +107,7 @@ def lib():
         L.rt_set_redistribution.argtypes = [vp, C.POINTER(C.c_double)]
         L.rt_prd_size.argtypes = [vp, C.POINTER(C.c_longlong)]
         L.rt_apply_op_prd.argtypes = [vp, vp, vp, vp]
+        L.rt_apply_op_prd_bf16x3.argtypes = [vp, vp, vp, vp]
         L.rt_get_rhs_prd.argtypes = [vp, vp, vp]
         L.rt_get_jacobi_diag_prd.argtypes = [vp, vp, vp]
         L.rt_apply_op_field.argtypes = [vp, vp, vp, vp]
@@ -291,6 +292,12 @@ class Handle:
         out = self._new_prd() if sigma_out is None else sigma_out
         _check(lib().rt_apply_op_prd(self._h, C.c_void_p(_ptr(sigma_in)), C.c_void_p(_ptr(out)),
                                      _stream(stream)))
+        return out
+
+    def apply_op_prd_bf16x3(self, sigma_in, sigma_out=None, stream=None):
+        out = self._new_prd() if sigma_out is None else sigma_out
+        _check(lib().rt_apply_op_prd_bf16x3(self._h, C.c_void_p(_ptr(sigma_in)),
+                                            C.c_void_p(_ptr(out)), _stream(stream)))
         return out
 
     def get_rhs_prd(self, stream=None):

@@ -332,7 +332,7 @@ void rt_destroy(rt_handle *h) {
                     h->d_cq,    h->d_state, h->d_active,  h->d_cycle,   h->d_count,
                     h->d_ew,    h->d_asm_dg, h->d_asm_sc, h->d_asm_task, h->d_A,
                     h->d_pz,    h->d_ones,  h->d_LU,      h->d_piv,     h->d_sing,
-                    h->d_rpart, h->d_mu_idx, h->d_fsig, h->d_Rw,   h->d_prd_Jm,
+                    h->d_rpart, h->d_mu_idx, h->d_fsig, h->d_Rw,   h->d_Rw_bf, h->d_prd_Jm,
                     h->d_prd_J, h->d_prd_diag, h->d_prd_dinv};
     clear_graphs(h);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
@@ -715,6 +715,42 @@ int rt_set_redistribution(rt_handle *h, const double *R) {
     }
     if (hipMemcpy(h->d_Rw, Rw.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess)
         return fail(RT_EDEVICE, "upload of R failed");
+    // the bf16 split of R(p, q) w_q, row-major with zero-padded rows: hi =
+    // bf16(x), lo = bf16(x - hi), both rounded to nearest even from FP32
+    const int nqp = (nnu + 31) / 32 * 32;
+    const long long nbf = (long long)h->n_atm * nnu * nqp;
+    auto to_bf16 = [](float f) {
+        unsigned u;
+        std::memcpy(&u, &f, sizeof u);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (unsigned short)(u >> 16);
+    };
+    auto from_bf16 = [](unsigned short b) {
+        const unsigned u = (unsigned)b << 16;
+        float f;
+        std::memcpy(&f, &u, sizeof f);
+        return f;
+    };
+    std::vector<unsigned short> bf(2 * nbf, 0);
+    for (int a = 0; a < h->n_atm; ++a)
+        for (int pp = 0; pp < nnu; ++pp)
+            for (int q = 0; q < nnu; ++q) {
+                const long long s0 = (long long)a * nnu * nnu;
+                const float x = (float)Rw[s0 + (long long)q * nnu + pp];
+                const unsigned short hi = to_bf16(x);
+                const long long e = ((long long)a * nnu + pp) * nqp + q;
+                bf[e] = hi;
+                bf[nbf + e] = to_bf16(x - from_bf16(hi));
+            }
+    if (!h->d_Rw_bf && hipMalloc((void **)&h->d_Rw_bf, sizeof(unsigned short) * 2 * nbf) != hipSuccess) {
+        h->d_Rw_bf = nullptr;
+        (void)hipGetLastError();
+        return fail(RT_ENOMEM, "device allocation of the bf16 split of R failed");
+    }
+    h->prd_nqp = nqp;
+    if (hipMemcpy(h->d_Rw_bf, bf.data(), sizeof(unsigned short) * 2 * nbf, hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return fail(RT_EDEVICE, "upload of the bf16 split of R failed");
     h->prd_ready = false;  // the diagonal depends on R
     return RT_OK;
 }
@@ -731,6 +767,14 @@ int rt_apply_op_prd(rt_handle *h, const double *sigma_in, double *sigma_out, voi
     if (rc != RT_OK) return rc;
     return hip_check(apply_prd_operator(h, sigma_in, sigma_out, (hipStream_t)stream),
                      "rt_apply_op_prd");
+}
+
+int rt_apply_op_prd_bf16x3(rt_handle *h, const double *sigma_in, double *sigma_out, void *stream) {
+    if (!h || !sigma_in || !sigma_out) return fail(RT_EINVAL, "NULL handle or vector");
+    const int rc = ensure_prd(h, (hipStream_t)stream);
+    if (rc != RT_OK) return rc;
+    return hip_check(apply_prd_operator(h, sigma_in, sigma_out, (hipStream_t)stream, true),
+                     "rt_apply_op_prd_bf16x3");
 }
 
 int rt_get_rhs_prd(rt_handle *h, double *b, void *stream) {

@@ -271,12 +271,20 @@ __global__ void fs_keep_bnorm_kernel(FsArgs a) {
     a.resid[s] = a.h[(long long)s * (a.m + 1)];
 }
 
-// out = d .* in over the whole vector (Jacobi scaling of the generic solve).
+// out = d .* in (mode 0), in ./ d (1) or out + in (2) over the whole vector
+// (the Jacobi scaling of the generic solve; the refinement update).
 __global__ void fs_mul_kernel(const double *d, const double *in, double *out, long long n,
-                              int divide) {
+                              int mode) {
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (long long)gridDim.x * blockDim.x)
-        out[e] = divide ? in[e] / d[e] : d[e] * in[e];
+        out[e] = mode == 2 ? out[e] + in[e] : mode == 1 ? in[e] / d[e] : d[e] * in[e];
+}
+
+// r = b - w over the whole vector.
+__global__ void fs_axpby_kernel(const double *b, const double *w, double *r, long long n) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x)
+        r[e] = b[e] - w[e];
 }
 
 }  // namespace
@@ -289,6 +297,15 @@ int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *,
                     long long per, const double *b_in,
                     const std::function<hipError_t(double *)> &own_rhs, double *x,
                     const double *dinv, rt_solve_info *info, hipStream_t st) {
+    return solve_seg_gmres_tol(h, op, per, b_in, own_rhs, x, dinv, h->opt.rtol, h->opt.maxit, info,
+                               st);
+}
+
+int solve_seg_gmres_tol(rt_handle *h, const std::function<hipError_t(const double *, double *)> &op,
+                        long long per, const double *b_in,
+                        const std::function<hipError_t(double *)> &own_rhs, double *x,
+                        const double *dinv, double rtol, int maxit, rt_solve_info *info,
+                        hipStream_t st) {
     const int m = h->opt.restart, n_atm = h->n_atm;
     const long long N = per * h->ns_total;
     const double *b = b_in;
@@ -317,8 +334,8 @@ int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *,
     a.nchunk = nchunk;
     a.m = m;
     a.N = N;
-    a.tol = h->opt.rtol;
-    a.maxit = h->opt.maxit;
+    a.tol = rtol;
+    a.maxit = maxit;
     a.off = (long long *)get(sizeof(long long) * (n_atm + 1));
     a.V = (double *)get(sizeof(double) * (size_t)(m + 1) * N);
     double *w = (double *)get(sizeof(double) * N);
@@ -391,8 +408,7 @@ int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *,
         hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)a.V, 1,
                            (const double *)nullptr, 1);
         hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, 1, 1);
-        hipLaunchKernelGGL(fs_restart_kernel, dim3(tg), dim3(tb), 0, st, a, first ? 1 : 0,
-                           h->opt.maxit);
+        hipLaunchKernelGGL(fs_restart_kernel, dim3(tg), dim3(tb), 0, st, a, first ? 1 : 0, maxit);
         first = false;
         if (!any_active(a.active)) break;
         // v_0 = r / beta (h[s][1] holds beta)
@@ -448,7 +464,7 @@ int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *,
     int worst = RT_OK;
     for (int s = 0; s < n_atm; ++s) {
         const double rel = bn[s] > 0.0 ? std::sqrt(hh[(size_t)s * (m + 1)]) / bn[s] : 0.0;
-        const int status = rel < h->opt.rtol ? RT_OK : RT_ENOCONV;
+        const int status = rel < rtol ? RT_OK : RT_ENOCONV;
         worst = std::max(worst, status);
         if (info) {
             info[s].status = status;
@@ -459,6 +475,133 @@ int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *,
         }
     }
     if (worst != RT_OK) set_error("GMRES did not reach rtol within the iteration limit");
+    return worst;
+}
+
+int solve_seg_refined(rt_handle *h, const std::function<hipError_t(const double *, double *)> &op,
+                      const std::function<hipError_t(const double *, double *)> &op_lo,
+                      long long per, const double *b_in,
+                      const std::function<hipError_t(double *)> &own_rhs, double *x,
+                      const double *dinv, rt_solve_info *info, hipStream_t st) {
+    const int n_atm = h->n_atm;
+    const long long N = per * h->ns_total;
+    std::vector<long long> off(n_atm + 1, 0);
+    int nchunk = 1;
+    for (int s = 0; s < n_atm; ++s) {
+        off[s + 1] = off[s] + per * h->ns[s];
+        nchunk = std::max<int>(nchunk, (int)((per * h->ns[s] + kFsChunk - 1) / kFsChunk));
+    }
+    std::vector<void *> bufs;
+    auto get = [&](size_t bytes) -> void * {
+        void *p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        bufs.push_back(p);
+        return p;
+    };
+    auto release = [&]() {
+        for (void *p : bufs) (void)hipFree(p);
+    };
+    // per-slab squared norms through the segmented reductions (m = 0: one row)
+    FsArgs a{};
+    a.n_atm = n_atm;
+    a.nchunk = nchunk;
+    a.m = 0;
+    a.N = N;
+    a.off = (long long *)get(sizeof(long long) * (n_atm + 1));
+    a.part = (double *)get(sizeof(double) * (size_t)n_atm * nchunk);
+    a.h = (double *)get(sizeof(double) * n_atm);
+    a.active = (int *)get(sizeof(int) * n_atm);
+    double *bown = b_in ? nullptr : (double *)get(sizeof(double) * N);
+    double *r = (double *)get(sizeof(double) * N);
+    double *d = (double *)get(sizeof(double) * N);
+    double *w = (double *)get(sizeof(double) * N);
+    if (!a.off || !a.part || !a.h || !a.active || (!b_in && !bown) || !r || !d || !w) {
+        release();
+        return fail(RT_ENOMEM, "refinement workspace allocation failed");
+    }
+    hipError_t err = hipSuccess;
+    auto ok = [&](hipError_t e) {
+        if (e != hipSuccess && err == hipSuccess) err = e;
+        return err == hipSuccess;
+    };
+    const std::vector<int> ones(n_atm, 1);
+    ok(hipMemcpyAsync((void *)a.off, off.data(), sizeof(long long) * (n_atm + 1),
+                      hipMemcpyHostToDevice, st));
+    ok(hipMemcpyAsync(a.active, ones.data(), sizeof(int) * n_atm, hipMemcpyHostToDevice, st));
+    const double *b = b_in;
+    if (!b) {
+        ok(own_rhs(bown));
+        b = bown;
+    }
+    const dim3 seg(nchunk, n_atm), blk(kFsNT);
+    const int mgrid = (int)std::min<long long>((N + 255) / 256, 4096);
+    auto norms = [&](const double *v, std::vector<double> &out) {
+        hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, v, 1, (const double *)nullptr, 1);
+        hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, 1, 1);
+        ok(hipGetLastError());
+        out.resize(n_atm);
+        ok(hipMemcpyAsync(out.data(), a.h, sizeof(double) * n_atm, hipMemcpyDeviceToHost, st));
+        ok(hipStreamSynchronize(st));
+        for (double &v2 : out) v2 = std::sqrt(v2);
+    };
+    std::vector<double> bn, rn;
+    norms(b, bn);
+    std::vector<int> its(n_atm, 0);
+    const double rtol = h->opt.rtol;
+    int outer = 0, napply = 0, total = 0;
+    bool done = false;
+    while (err == hipSuccess) {
+        // r = b - A x (FP64)
+        ok(op(x, w));
+        ++napply;
+        hipLaunchKernelGGL(fs_axpby_kernel, dim3(mgrid), dim3(256), 0, st, b, (const double *)w, r,
+                           N);
+        norms(r, rn);
+        done = true;
+        for (int s = 0; s < n_atm; ++s)
+            if (!(bn[s] == 0.0 || rn[s] < rtol * bn[s])) done = false;
+        if (done || err != hipSuccess || total >= h->opt.maxit) break;
+        // d from the cheaper operator, from zero; slabs already converged
+        // carry a tiny r and change x by a tiny d
+        ok(hipMemsetAsync(d, 0, sizeof(double) * N, st));
+        std::vector<rt_solve_info> in(n_atm);
+        const int rc = solve_seg_gmres_tol(h, op_lo, per, r, own_rhs, d, dinv, h->opt.inner_rtol,
+                                           h->opt.inner_maxit, in.data(), st);
+        if (rc != RT_OK && rc != RT_ENOCONV) {
+            release();
+            return rc;
+        }
+        int most = 0;
+        for (int s = 0; s < n_atm; ++s) {
+            its[s] += in[s].iterations;
+            most = std::max(most, in[s].iterations);
+            napply += in[s].matvecs;
+        }
+        total += std::max(most, 1);  // every step counts toward maxit
+        hipLaunchKernelGGL(fs_mul_kernel, dim3(mgrid), dim3(256), 0, st, (const double *)nullptr,
+                           (const double *)d, x, N, 2);
+        ok(hipGetLastError());
+        ++outer;
+    }
+    release();
+    if (err != hipSuccess) return fail(RT_EDEVICE, std::string("refinement: ") + hipGetErrorString(err));
+    int worst = RT_OK;
+    for (int s = 0; s < n_atm; ++s) {
+        const double rel = bn[s] > 0.0 ? rn[s] / bn[s] : 0.0;
+        const int status = rel < rtol ? RT_OK : RT_ENOCONV;
+        worst = std::max(worst, status);
+        if (info) {
+            info[s].status = status;
+            info[s].iterations = its[s];
+            info[s].matvecs = napply;
+            info[s].outer_steps = outer;
+            info[s].relres = rel;
+        }
+    }
+    if (worst != RT_OK) set_error("refinement did not reach rtol within the iteration limit");
     return worst;
 }
 

@@ -224,6 +224,8 @@ struct rt_handle {
     int *d_mu_idx = nullptr;      // per |mu| index m: caller's index of -mu (2m) and +mu (2m+1)
     double *d_fsig = nullptr;     // field formulation: J I, 2 values per depth point
     double *d_Rw = nullptr;       // redistribution: R(p, q) w_q per slab, [q][p]
+    unsigned short *d_Rw_bf = nullptr;  // R w split in bf16 hi, lo: [2][slab][p][prd_nqp]
+    int prd_nqp = 0;              // padded row length of the bf16 split (multiple of 32)
     double *d_prd_Jm = nullptr;   // per-|mu| quadrature stage (when not in LDS)
     double *d_prd_J = nullptr;    // monochromatic J, frequency-major [p][k][K]
     double *d_prd_diag = nullptr, *d_prd_dinv = nullptr;
@@ -301,9 +303,26 @@ int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *,
                     long long per, const double *b,
                     const std::function<hipError_t(double *)> &own_rhs, double *x,
                     const double *dinv, rt_solve_info *info, hipStream_t st);
+// The same with an explicit tolerance and iteration limit (the inner solves
+// of the refinement below).
+int solve_seg_gmres_tol(rt_handle *h, const std::function<hipError_t(const double *, double *)> &op,
+                        long long per, const double *b,
+                        const std::function<hipError_t(double *)> &own_rhs, double *x,
+                        const double *dinv, double rtol, int maxit, rt_solve_info *info,
+                        hipStream_t st);
+// FP64 iterative refinement: r = b - A x with op, d from GMRES(m) on op_lo to
+// inner_rtol, x += d, until every slab's ||r|| < rtol ||b|| (or maxit inner
+// steps in total).
+int solve_seg_refined(rt_handle *h, const std::function<hipError_t(const double *, double *)> &op,
+                      const std::function<hipError_t(const double *, double *)> &op_lo,
+                      long long per, const double *b,
+                      const std::function<hipError_t(double *)> &own_rhs, double *x,
+                      const double *dinv, rt_solve_info *info, hipStream_t st);
+
 // The frequency-redistribution variant (rt_prd.hip): out = A in, or the
 // right-hand side when in is NULL; its Jacobi diagonal; workspace set-up.
-hipError_t apply_prd_operator(const rt_handle *h, const double *in, double *out, hipStream_t s);
+hipError_t apply_prd_operator(const rt_handle *h, const double *in, double *out, hipStream_t s,
+                              bool bf16x3 = false);
 hipError_t prd_diag(const rt_handle *h, double *diag, double *dinv, hipStream_t s);
 int ensure_prd(rt_handle *h, hipStream_t s);
 int solve_prd_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *info,

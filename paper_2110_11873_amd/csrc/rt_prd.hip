@@ -23,7 +23,9 @@
 //    contiguous rows: R w is stored transposed, J frequency-major) -- with
 //    the scattering step fused into its output:
 //    sigma_out = sigma_in - xi W_K Jt / phi_p (operator) or
-//    xi W_K Jt / phi_p + eps B (K = 0) (right-hand side).
+//    xi W_K Jt / phi_p + eps B (K = 0) (right-hand side);
+//  * prd_contract_bf16x3_kernel: the same on the BF16 matrix cores with a
+//    hi/lo split of both operands (the inner operator of the mixed solve).
 // With R proportional to phi(p) phi(q) this is the complete-redistribution
 // operator at every frequency.  Deterministic: no atomics, fixed orders.
 #include <hip/hip_runtime.h>
@@ -42,6 +44,9 @@ constexpr int kPrdNT = 256;       // contraction
 constexpr int kPrdSweepNT = 512;  // sweep: lanes per (|mu|, chunk)
 constexpr size_t kPrdLdsMax = 64 * 1024;
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct PrdArgs {
     const AtmDesc *atm;
@@ -49,6 +54,9 @@ struct PrdArgs {
     const double *tau, *opac, *mu_pos, *w_pos, *B, *phi;
     const double2 *dirc;  // per |mu|: (T1, T1^2 + T2^2)
     const double *RwT;    // [n_atm][n_nu (q)][n_nu (p)]: R(p, q) w_q
+    const unsigned short *Rbf;  // its bf16 split: [hi, lo][n_atm][n_nu (p)][nqp (q)]
+    long long nbf;        // entries per half of Rbf
+    int nqp;
     const double *sig_in; // NULL: right-hand side (zero source, bottom inflow)
     double *sig_out;
     double *stage;        // global stage (when the LDS one does not fit)
@@ -277,6 +285,88 @@ __global__ __launch_bounds__(kPrdNT) void prd_contract_kernel(PrdArgs a) {
     }
 }
 
+// The same contraction on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16):
+// R w (split on the host) and J (split here from FP64 through FP32) are each
+// hi + lo in bf16, about 16 significant bits, and J~ = Rh Jh + (Rh Jl + Rl Jh)
+// with the two groups in separate FP32 accumulators, added in FP64 (the
+// dropped Rl Jl is below 2^-16 of the product).  One workgroup per 16 x 16
+// tile, its four wavefronts on interleaved groups of 32 q, added in
+// wavefront order.  Lane l feeds A[l % 16][8 (l / 16) + i] and
+// B[8 (l / 16) + i][l % 16], i = 0..7 (q contiguous per lane: the order of
+// q inside an instruction only has to agree between A and B); result
+// register r of lane l is D[4 (l / 16) + r][l % 16].
+__global__ __launch_bounds__(kPrdNT) void prd_contract_bf16x3_kernel(PrdArgs a) {
+    constexpr int NW = kPrdNT / kWave;
+    __shared__ f32x4 red[2][NW - 1][kWave];
+    const int slab = blockIdx.z;
+    const AtmDesc at = a.atm[slab];
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    const int p0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
+    const int ncol = 2 * at.ns, nnu = a.n_nu;
+    if (c0 >= ncol) return;  // the whole workgroup
+    const unsigned short *Rh = a.Rbf + (long long)slab * nnu * a.nqp;
+    const unsigned short *Rl = Rh + a.nbf;
+    const int pa = p0 + lane % 16, g = lane / 16;
+    const int cb = c0 + lane % 16;
+    const double *Jb = a.J + 2LL * at.doff;
+    const long long js = 2LL * a.ns_total;
+    const bool arow = pa < nnu, bcol = cb < ncol;
+    f32x4 big = {0.f, 0.f, 0.f, 0.f}, small = {0.f, 0.f, 0.f, 0.f};
+    for (int q0 = 32 * wv; q0 < nnu; q0 += 32 * NW) {
+        const int qa = q0 + 8 * g;  // rows are padded to a multiple of 32: qa + 8 <= nqp
+        u16x8 uh = {0, 0, 0, 0, 0, 0, 0, 0}, ul = uh;
+        if (arow) {
+            uh = *reinterpret_cast<const u16x8 *>(Rh + (long long)pa * a.nqp + qa);
+            ul = *reinterpret_cast<const u16x8 *>(Rl + (long long)pa * a.nqp + qa);
+        }
+        double jv[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            jv[i] = (bcol && qa + i < nnu) ? Jb[(qa + i) * js + cb] : 0.0;
+        bf16x8 bh, bl;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float f = (float)jv[i];
+            const __bf16 hi = (__bf16)f;
+            bh[i] = hi;
+            bl[i] = (__bf16)(f - (float)hi);
+        }
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, uh), al = __builtin_bit_cast(bf16x8, ul);
+        big = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, big, 0, 0, 0);
+        small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, small, 0, 0, 0);
+        small = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, small, 0, 0, 0);
+    }
+    if (wv > 0) {
+        red[0][wv - 1][lane] = big;
+        red[1][wv - 1][lane] = small;
+    }
+    __syncthreads();
+    if (wv > 0) return;
+    double acc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = (double)big[r] + (double)small[r];
+#pragma unroll
+    for (int w = 0; w < NW - 1; ++w)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            acc[r] += (double)red[0][w][lane][r] + (double)red[1][w][lane][r];
+    const int c = c0 + lane % 16;
+    if (c >= ncol) return;
+    const int k = c / 2, K = c % 2;
+    const double wk = K == 0 ? at.xi : at.xi * at.W2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int p = p0 + 4 * g + r;
+        if (p >= nnu) continue;
+        const long long e = 2 * ((long long)(at.doff + k) * nnu + p) + K;
+        const double t = wk * acc[r] / a.phi[(long long)slab * nnu + p];
+        if (a.sig_in)
+            a.sig_out[e] = a.sig_in[e] - t;
+        else
+            a.sig_out[e] = t + (K == 0 ? at.eps * a.B[at.doff + k] : 0.0);
+    }
+}
+
 // Jacobi diagonal: sigma^K(k, p) reaches itself through the rays' Lambda(k, k),
 // the monochromatic quadrature and R(p, p) w_p.  One thread per (kk, p).
 __global__ void prd_diag_kernel(PrdArgs a, double *diag, double *dinv) {
@@ -328,6 +418,9 @@ PrdArgs prd_args(const rt_handle *h, const double *in, double *out) {
     a.phi = h->d_phi;
     a.dirc = h->d_dirc;
     a.RwT = h->d_Rw;
+    a.Rbf = h->d_Rw_bf;
+    a.nqp = h->prd_nqp;
+    a.nbf = (long long)h->n_atm * h->n_nu * h->prd_nqp;
     a.sig_in = in;
     a.sig_out = out;
     a.stage = h->d_prd_Jm;
@@ -342,7 +435,8 @@ PrdArgs prd_args(const rt_handle *h, const double *in, double *out) {
 
 }  // namespace
 
-hipError_t apply_prd_operator(const rt_handle *h, const double *in, double *out, hipStream_t s) {
+hipError_t apply_prd_operator(const rt_handle *h, const double *in, double *out, hipStream_t s,
+                              bool bf16x3) {
     const PrdArgs a = prd_args(h, in, out);
     const dim3 grid(h->n_nu, h->n_atm);
     if (prd_global_stage(h))
@@ -353,9 +447,11 @@ hipError_t apply_prd_operator(const rt_handle *h, const double *in, double *out,
                            std::max(prd_stage_bytes(h), prd_carry_bytes(h)), s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(prd_contract_kernel,
-                       dim3((2 * h->ns_max + 15) / 16, (h->n_nu + 15) / 16, h->n_atm), dim3(kPrdNT),
-                       0, s, a);
+    const dim3 tiles((2 * h->ns_max + 15) / 16, (h->n_nu + 15) / 16, h->n_atm);
+    if (bf16x3)
+        hipLaunchKernelGGL(prd_contract_bf16x3_kernel, tiles, dim3(kPrdNT), 0, s, a);
+    else
+        hipLaunchKernelGGL(prd_contract_kernel, tiles, dim3(kPrdNT), 0, s, a);
     return hipGetLastError();
 }
 
@@ -394,10 +490,14 @@ int solve_prd_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *inf
                     hipStream_t st) {
     const int rc = ensure_prd(h, st);
     if (rc != RT_OK) return rc;
-    return solve_seg_gmres(
-        h, [&](const double *in, double *out) { return apply_prd_operator(h, in, out, st); },
-        2LL * h->n_nu, b, [&](double *bo) { return apply_prd_operator(h, nullptr, bo, st); }, x,
-        h->d_prd_dinv, info, st);
+    auto op = [&](const double *in, double *out) { return apply_prd_operator(h, in, out, st); };
+    auto rhs = [&](double *bo) { return apply_prd_operator(h, nullptr, bo, st); };
+    if (h->opt.precision == RT_PREC_MIXED)
+        return solve_seg_refined(
+            h, op,
+            [&](const double *in, double *out) { return apply_prd_operator(h, in, out, st, true); },
+            2LL * h->n_nu, b, rhs, x, h->d_prd_dinv, info, st);
+    return solve_seg_gmres(h, op, 2LL * h->n_nu, b, rhs, x, h->d_prd_dinv, info, st);
 }
 
 }  // namespace rt

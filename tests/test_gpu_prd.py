@@ -143,6 +143,60 @@ def test_prd_tiny_slabs():
     _check_batch(*_batch_case([2, 3, 5], 4, 3, "delo_linear", 0.3, 7))
 
 
+# BF16x3 contraction: each operand split into bf16 hi + lo carries about 16
+# significant bits (relative error <= 2^-17 each, from FP32), the dropped
+# lo.lo term is below 2^-16 of a product, and 256 FP32 additions add at most
+# 256 * 2^-24 relative to the sum of |products| (R w >= 0 and the largest J
+# terms dominate): together below 2e-5 of |xi J~ / phi|, so normwise (as in
+# the FP64 tests) below 2e-5.
+BF16X3_TOL = 2e-5
+
+
+@pytest.mark.parametrize("fs", ["delo_linear", "delo_parabolic"])
+def test_prd_bf16x3_operator_against_oracle(fs):
+    p, R, v = _batch_case([7, 23, 40], 8, 12, fs, 0.5, 8)
+    nnu = len(p.w_nu)
+    with B.setup(p) as h:
+        h.set_redistribution(R)
+        y = host(h.apply_op_prd_bf16x3(dev(v)))
+        y64 = host(h.apply_op_prd(dev(v)))
+    off = 0
+    for i, ns in enumerate(int(n) for n in p.ns):
+        seg = slice(2 * nnu * off, 2 * nnu * (off + ns))
+        ref = RDO.apply(p, R[i], v[seg], i=i)
+        assert normwise(ref, y[seg], v[seg]) <= BF16X3_TOL, i
+        off += ns
+    # it is the BF16 path: not bit-equal to the FP64 contraction
+    assert np.abs(y - y64).max() > 0.0
+
+
+def test_prd_bf16x3_config5_operator():
+    p, R = W.config5()
+    v = np.random.default_rng(9).uniform(-1, 1, 2 * 256 * 256)
+    with B.setup(p) as h:
+        h.set_redistribution(R)
+        y = host(h.apply_op_prd_bf16x3(dev(v)))
+    assert normwise(RDO.apply(p, R, v), y, v) <= BF16X3_TOL
+
+
+@pytest.mark.parametrize("shape", [(64, 16, 64), (256, 32, 256)])
+def test_prd_mixed_refinement_solve(shape):
+    """MIXED: FP64 refinement around BF16x3 inner solves reaches 1e-9 by the
+    oracle's FP64 residual."""
+    ns, n_mu, n_nu = shape
+    p, R = W.config5(ns=ns, n_mu=n_mu, n_nu=n_nu)
+    with B.setup(p, rtol=1e-9, restart=30, maxit=5000, precision=B.RT_PREC_MIXED) as h:
+        h.set_redistribution(R)
+        x = dev(np.zeros(h.prd_size()))
+        rc, info = h.solve_prd_gmres(x)
+        xs = host(x)
+    assert rc == 0 and info[0].status == "converged", info
+    assert info[0].outer_steps >= 2
+    b = RDO.rhs(p, R)
+    rel = np.linalg.norm(b - RDO.apply(p, R, xs)) / np.linalg.norm(b)
+    assert rel < 1e-9, rel
+
+
 def test_prd_requires_R():
     p = W.config1_subgrid()
     with B.setup(p) as h:
