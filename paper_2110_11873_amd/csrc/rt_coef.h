@@ -42,7 +42,9 @@ constexpr SeriesCoef make_series() {
     return s;
 }
 
-__constant__ SeriesCoef c_series = make_series();
+// compile-time tables: immutable, so the compiler folds each coefficient into
+// the instruction that uses it instead of keeping the table in registers
+constexpr SeriesCoef c_series = make_series();
 
 }  // namespace
 
@@ -105,66 +107,65 @@ __device__ inline void step_ew(int fs, double d, double &E, double &w) {
 //   c_u = (w2 + dd w1) / (d (d + dd)),  c_k = ((d - dd) w1 + d dd w0 - w2) / (d dd),
 //   c_d = (w2 - d w1) / (dd (d + dd)),
 // with the moments w_n = int_0^d t^n exp(-t) dt: 1 - E, 1 - (1 + d) E,
-// 2 - (d^2 + 2d + 2) E, or below d = 1 their series
-// sum_m (-1)^m d^(m+n+1) / (m! (m+n+1)), summed by Horner's rule.
+// 2 - (d^2 + 2d + 2) E, or below d = 1 the incomplete-gamma series of w_2
+// and a downward recurrence (exp_moments).
 // --------------------------------------------------------------------------
 namespace {
 
-constexpr int kMomentTerms = 22;  // d < 1: the last term is below 1e-21
+constexpr int kGammaTerms = 20;  // d < 1: 2 / 22! ~ 1.8e-21 of the leading 1/3
 
-struct MomentSeries {
-    double c[3][kMomentTerms];
+// c[k] = 2 / (k + 3)!: gamma(3, d) = d^3 e^-d sum_k c[k] d^k (all terms positive)
+struct GammaSeries {
+    double c[kGammaTerms];
 };
 
-constexpr MomentSeries make_moment_series() {
-    MomentSeries s{};
-    double fact = 1.0;  // m!
-    for (int m = 0; m < kMomentTerms; ++m) {
-        if (m > 0) fact *= m;
-        const double sgn = (m % 2 == 0) ? 1.0 : -1.0;
-        for (int n = 0; n < 3; ++n) s.c[n][m] = sgn / (fact * (m + n + 1));
+constexpr GammaSeries make_gamma_series() {
+    GammaSeries s{};
+    double fact = 6.0;  // (k + 3)!
+    for (int k = 0; k < kGammaTerms; ++k) {
+        if (k > 0) fact *= (k + 3);
+        s.c[k] = 2.0 / fact;
     }
     return s;
 }
 
-__constant__ MomentSeries c_moments = make_moment_series();
+constexpr GammaSeries c_gamma3 = make_gamma_series();
 
 }  // namespace
 
+// E = e^-d and the moments w_n = int_0^d t^n e^-t dt = gamma(n + 1, d),
+// n = 0, 1, 2.  Below d = 1: gamma(3, d) from its positive series, then the
+// stable downward recurrence gamma(s, d) = (gamma(s + 1, d) + d^s e^-d) / s;
+// above: the closed forms, free of cancellation there.
 __device__ inline void exp_moments(double d, double &E, double &w0, double &w1, double &w2) {
     E = exp(-d);
     if (d < 1.0) {
-        double p0 = c_moments.c[0][kMomentTerms - 1];
-        double p1 = c_moments.c[1][kMomentTerms - 1];
-        double p2 = c_moments.c[2][kMomentTerms - 1];
+        double sr = c_gamma3.c[kGammaTerms - 1];
 #pragma unroll
-        for (int m = kMomentTerms - 2; m >= 0; --m) {
-            p0 = fma(p0, d, c_moments.c[0][m]);
-            p1 = fma(p1, d, c_moments.c[1][m]);
-            p2 = fma(p2, d, c_moments.c[2][m]);
-        }
-        w0 = p0 * d;
-        w1 = p1 * d * d;
-        w2 = p2 * d * d * d;
+        for (int k = kGammaTerms - 2; k >= 0; --k) sr = fma(sr, d, c_gamma3.c[k]);
+        const double dE = d * E;
+        w2 = d * d * dE * sr;
+        w1 = 0.5 * fma(d, dE, w2);
+        w0 = w1 + dE;
     } else {
-        w0 = -expm1(-d);
+        w0 = 1.0 - E;
         w1 = 1.0 - (1.0 + d) * E;
         w2 = 2.0 - (d * d + 2.0 * d + 2.0) * E;
     }
 }
 
+// Quadratic (DELO-parabolic) step coefficients from the moments, with one
+// reciprocal of d dd (d + dd).
 __device__ inline void parabolic_coef(double d, double dd, double &E, double &cu, double &ck,
                                       double &cd) {
     double w0, w1, w2;
     exp_moments(d, E, w0, w1, w2);
-    cu = (w2 + dd * w1) / (d * (d + dd));
-    ck = ((d - dd) * w1 + d * dd * w0 - w2) / (d * dd);
-    cd = (w2 - d * w1) / (dd * (d + dd));
+    const double s = d + dd, inv = 1.0 / (d * dd * s);
+    cu = (w2 + dd * w1) * dd * inv;
+    ck = ((d - dd) * w1 + d * dd * w0 - w2) * s * inv;
+    cd = (w2 - d * w1) * d * inv;
 }
 
-// Step of a ray from its upwind point u to point k (optical step d), with the
-// downwind point's step dd when k is not the ray's last point: I_k = E I_u +
-// c_u S_u + c_k S_k + c_d S_dn (c_d = 0 but for DELO-parabolic).
 __device__ inline void ray_step(int fs, double d, double dd, bool has_dn, double &E,
                                 double &cu, double &ck, double &cd) {
     cd = 0.0;
