@@ -71,11 +71,30 @@ def test_operator_rhs_diag(maker):
 
 
 def test_batched_operator():
+    """8 uneven slabs: few rays, so each ray is cut into depth chunks."""
     p = W.config4(8).with_(formal_solver=W.FS_DELO_PARABOLIC)
     v = W.random_vector(p.n_unknowns, 2)
     with B.setup(p) as h:
         y = host(h.apply_op(dev(v)))
     assert normwise(p, v, y) <= 1e-12
+
+
+def test_many_slab_operator_unchunked():
+    """160 small slabs x 13 groups of 64 rays: enough wavefronts that each ray
+    is one lane from top to bottom (the path of the 512-slab batch)."""
+    rng = np.random.default_rng(12)
+    n = 160
+    ns = [int(v) for v in rng.integers(2, 12, n)]
+    p = W.make_slabs(ns, [(1e-4, float(10 ** rng.uniform(4, 8))) for _ in range(n)], 16, 101, 10.0,
+                     list(10 ** rng.uniform(-4, -2, n)), list(10 ** rng.uniform(-6, -2, n)),
+                     list(rng.uniform(0, 0.7, n)), formal_solver=FS)
+    v = W.random_vector(p.n_unknowns, 3)
+    with B.setup(p) as h:
+        y = host(h.apply_op(dev(v)))
+        b = host(h.get_rhs())
+    assert normwise(p, v, y) <= 1e-12
+    rb = O.rhs(p)
+    assert np.abs(b - rb).max() <= 1e-12 * np.abs(rb).max()
 
 
 @pytest.mark.parametrize("kind,maker", [("gmres", W.config2), ("bicgstab", W.config2),
