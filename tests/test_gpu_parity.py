@@ -422,6 +422,27 @@ def test_edge_cases_zero_rhs_maxit_and_exact_start():
         assert np.abs(x[0::2] - 1.0).max() < 1e-14 and np.abs(x[1::2]).max() < 1e-14
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_maximum_depth_and_restart(mixed):
+    """RT_MAX_NS = 2048 depth points with GMRES(RT_MAX_RESTART = 128): the
+    operator, right-hand side and a solve beside a 97-point slab (general
+    Arnoldi path, longest cycle)."""
+    ns = [B.RT_MAX_NS, 97]
+    p = W.make_slabs(ns, [(1e-4, 1e8), (1e-2, 1e4)], 4, 9, 5.0, [1e-3, 1e-2], [1e-4, 1e-2],
+                     [0.5, 0.3])
+    prec = B.RT_PREC_MIXED if mixed else B.RT_PREC_FP64
+    with B.setup(p, rtol=1e-10, restart=B.RT_MAX_RESTART, maxit=20000, precision=prec) as h:
+        if not mixed:
+            check_apply(p, h, seeds=(4,))
+            b = host(h.get_rhs())
+            rb = O.rhs(p)
+            assert np.abs(b - rb).max() <= MATVEC_TOL * np.abs(rb).max()
+        rc, info, x = _solve(h, "gmres", p)
+    assert rc == 0 and all(i.status == "converged" for i in info), info
+    rr = oracle_relres(p, x)
+    assert rr.max() < 1e-10, rr
+
+
 def test_invalid_inputs_rejected_before_device_use():
     p = W.config1()
     with pytest.raises(B.RTError) as e:
