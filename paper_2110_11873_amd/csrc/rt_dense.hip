@@ -9,8 +9,8 @@
 // in LDS and walks the triangle in blocks of 64 unknowns: the block's
 // diagonal 64 x 64 part is staged in LDS and solved by one wavefront, the
 // solved values are broadcast with readlane, and the rows still to come are
-// updated with the block's columns (one thread per row, reading each row's
-// 64 entries once).  Each triangle of A is read from memory once.
+// updated with the block's columns (16 lanes per row, each row's 64 entries
+// read once, contiguously).  Each triangle of A is read from memory once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +22,7 @@ namespace rt {
 namespace {
 
 constexpr int kTriNT = 256;
+constexpr int kTriPass = 4;  // 16-row passes of the update loaded together
 constexpr int kTriB = 64;
 constexpr int kTriPad = kTriB + 1;  // padded row of the staged block
 
@@ -39,57 +40,98 @@ template <bool UP, bool UNIT = false>
 __device__ void tri_sweep(const double *A, int N, double om, double *r, double *blk) {
     const int tid = threadIdx.x;
     const int nb = (N + kTriB - 1) / kTriB;
-    for (int bi = 0; bi < nb; ++bi) {
-        const int b = UP ? nb - 1 - bi : bi;
+    constexpr int kStage = kTriB * kTriB / kTriNT;
+    // a block's diagonal part, loaded into registers (all loads in flight
+    // together); the next block's is loaded before this block's update
+    auto load_diag = [&](int b, double *stage) {
         const int i0 = b * kTriB, n = min(kTriB, N - i0);
-        // all of a thread's loads in flight at once (a fixed trip count)
-        double stage[kTriB * kTriB / kTriNT];
 #pragma unroll
-        for (int t = 0; t < kTriB * kTriB / kTriNT; ++t) {
+        for (int t = 0; t < kStage; ++t) {
             const int e = tid + t * kTriNT, rr = e / kTriB, cc = e % kTriB;
             stage[t] = (rr < n && cc < n) ? A[(long long)(i0 + rr) * N + i0 + cc] : 0.0;
         }
+    };
+    double stage[kStage];
+    load_diag(UP ? nb - 1 : 0, stage);
+    for (int bi = 0; bi < nb; ++bi) {
+        const int b = UP ? nb - 1 - bi : bi;
+        const int i0 = b * kTriB, n = min(kTriB, N - i0);
 #pragma unroll
-        for (int t = 0; t < kTriB * kTriB / kTriNT; ++t) {
+        for (int t = 0; t < kStage; ++t) {
             const int e = tid + t * kTriNT;
             blk[(e / kTriB) * kTriPad + e % kTriB] = stage[t];
         }
         __syncthreads();
+        if (bi + 1 < nb) load_diag(UP ? b - 1 : b + 1, stage);
         if (tid < kWave) {
             const int c = tid;
             double val = c < n ? r[i0 + c] : 0.0;
             const double dc = c < n ? (UNIT ? 1.0 : om / blk[c * kTriPad + c]) : 0.0;
-            for (int ii = 0; ii < n; ++ii) {
-                const int i = UP ? n - 1 - ii : ii;
-                const double zi = readlane_d(val * dc, i);
-                if (c == i) val = zi;
-                else if (UP ? c < i : c > i) val -= blk[c * kTriPad + i] * zi;
+            if (n == kTriB) {
+                // a full block: eight steps at a time, their LDS reads issued first
+                for (int i8 = 0; i8 < kTriB; i8 += 8) {
+                    double col[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int i = UP ? kTriB - 1 - (i8 + u) : i8 + u;
+                        col[u] = blk[c * kTriPad + i];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int i = UP ? kTriB - 1 - (i8 + u) : i8 + u;
+                        const double zi = readlane_d(val * dc, i);
+                        if (c == i) val = zi;
+                        else if (UP ? c < i : c > i) val -= col[u] * zi;
+                    }
+                }
+            } else {
+                for (int ii = 0; ii < n; ++ii) {
+                    const int i = UP ? n - 1 - ii : ii;
+                    const double zi = readlane_d(val * dc, i);
+                    if (c == i) val = zi;
+                    else if (UP ? c < i : c > i) val -= blk[c * kTriPad + i] * zi;
+                }
             }
             if (c < n) r[i0 + c] = val;
         }
         __syncthreads();
-        // the rows not yet solved: above the block (UP) or below it
+        // the rows not yet solved (above the block for UP, else below) less
+        // the block's columns times its solution: thread (row q, group g)
+        // takes columns 4g .. 4g + 3, so each row's 64 entries are read by 16
+        // neighbouring lanes (512 contiguous bytes), and the 16 partial sums
+        // are added by butterfly; kTriPass passes of kTriNT / 16 rows each
+        // are loaded together
         const int lo = UP ? 0 : i0 + n, hi = UP ? i0 : N;
-        for (int l = lo + tid; l < hi; l += kTriNT) {
-            const double2 *row = reinterpret_cast<const double2 *>(A + (long long)l * N + i0);
-            double acc0 = 0.0, acc1 = 0.0;
-            if (n == kTriB) {  // a full block: the row's 32 loads issued together
-                double2 v[kTriB / 2];
+        const int q = tid >> 4, g = tid & 15, c0 = 4 * g;
+        double x[4];
 #pragma unroll
-                for (int c2 = 0; c2 < kTriB / 2; ++c2) v[c2] = row[c2];
+        for (int u = 0; u < 4; ++u) x[u] = c0 + u < n ? r[i0 + c0 + u] : 0.0;
+        for (int l0 = lo; l0 < hi; l0 += kTriPass * (kTriNT / 16)) {
+            double acc[kTriPass];
 #pragma unroll
-                for (int c2 = 0; c2 < kTriB / 2; ++c2) {
-                    acc0 = fma(v[c2].x, r[i0 + 2 * c2], acc0);
-                    acc1 = fma(v[c2].y, r[i0 + 2 * c2 + 1], acc1);
-                }
-            } else {
-                for (int c2 = 0; c2 < n / 2; ++c2) {
-                    const double2 v = row[c2];
-                    acc0 = fma(v.x, r[i0 + 2 * c2], acc0);
-                    acc1 = fma(v.y, r[i0 + 2 * c2 + 1], acc1);
+            for (int pass = 0; pass < kTriPass; ++pass) {
+                const int l = l0 + pass * (kTriNT / 16) + q;
+                acc[pass] = 0.0;
+                if (l < hi) {
+                    const double *row = A + (long long)l * N + i0 + c0;
+                    if (c0 + 3 < n) {
+                        const double2 v0 = reinterpret_cast<const double2 *>(row)[0];
+                        const double2 v1 = reinterpret_cast<const double2 *>(row)[1];
+                        acc[pass] = fma(v0.x, x[0], fma(v0.y, x[1], fma(v1.x, x[2], v1.y * x[3])));
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (c0 + u < n) acc[pass] = fma(row[u], x[u], acc[pass]);
+                    }
                 }
             }
-            r[l] -= acc0 + acc1;
+#pragma unroll
+            for (int pass = 0; pass < kTriPass; ++pass) {
+                double v = acc[pass];
+                for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
+                const int l = l0 + pass * (kTriNT / 16) + q;
+                if (g == 0 && l < hi) r[l] -= v;
+            }
         }
         __syncthreads();
     }
