@@ -566,7 +566,7 @@ int solve_seg_refined(rt_handle *h, const std::function<hipError_t(const double 
         if (done || err != hipSuccess || total >= h->opt.maxit) break;
         // d from the cheaper operator, from zero; slabs already converged
         // carry a tiny r and change x by a tiny d
-        ok(hipMemsetAsync(d, 0, sizeof(double) * N, st));
+        ok(fill(d, N, 0.0, st));
         std::vector<rt_solve_info> in(n_atm);
         const int rc = solve_seg_gmres_tol(h, op_lo, per, r, own_rhs, d, dinv, h->opt.inner_rtol,
                                            h->opt.inner_maxit, in.data(), st);
