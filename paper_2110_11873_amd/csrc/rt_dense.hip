@@ -224,13 +224,17 @@ __global__ void fill_kernel(double *v, long long n, double c) {
 //  * the panel's row exchanges are then applied to the other columns (one
 //    thread per column, in order), U12 = L11^-1 A12 is solved one thread per
 //    column, and A22 -= L21 U12 streams the trailing rows with the column's
-//    U12 in registers and L21 staged in LDS 64 rows at a time.
+//    U12 in registers and L21 staged in LDS 64 rows at a time -- within the
+//    panel's outer block of 32 columns; once the block is factored, the
+//    columns beyond it get U12 from the block's 32 x 32 unit lower triangle
+//    and one rank-32 update (a quarter of the rank-8 passes' traffic).
 // piv[k] (slab-local) is the row exchanged with row k at step k, as LAPACK's
 // getrf returns it.  A zero pivot marks the slab singular.
 // --------------------------------------------------------------------------
-constexpr int kLuNT = 1024;
+constexpr int kLuNT = 512;   // 256 VGPRs per lane for the rank-32 pass
 constexpr int kLuRows = 64;  // L21 rows staged per pass of the trailing update
 constexpr int kLuNB = 8;     // panel width (16 spills the panel's registers)
+constexpr int kLuBB = 32;    // outer block: its trailing update is one rank-32 pass
 
 struct LuArgs {
     const AtmDesc *atm;
@@ -248,6 +252,10 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g) {
     __shared__ int s_piv[NB];
     __shared__ double L11[NB][NB + 1];
     __shared__ double L21[kLuRows][NB];
+    __shared__ double Lb[kLuBB][kLuBB + 1];   // the outer block's unit lower L11
+    __shared__ double Lb21[kLuRows][kLuBB];   // its L21, staged rows
+    __shared__ double Ub[NB][kLuBB];          // a panel's U12 on the rest of its block
+    static_assert(kLuBB % NB == 0, "the outer block is whole panels");
     const int slab = blockIdx.x;
     const AtmDesc at = g.atm[slab];
     const int N = 2 * at.ns;
@@ -257,6 +265,7 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g) {
     int singular = 0;
     for (int k0 = 0; k0 < N; k0 += NB) {
         const int nb = min(NB, N - k0);
+        const int K0 = k0 / kLuBB * kLuBB, cend = min(K0 + kLuBB, N);  // this panel's outer block
         double P[R][NB];
 #pragma unroll
         for (int u = 0; u < R; ++u) {
@@ -374,8 +383,9 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g) {
         __syncthreads();
         const int c0 = k0 + nb;
         if (c0 >= N) break;
-        // U12 = L11^-1 A12 (unit lower L11), one thread per column
-        for (int c = c0 + tid; c < N; c += kLuNT) {
+        // U12 = L11^-1 A12 (unit lower L11), one thread per column, on the
+        // rest of the outer block (the columns beyond it wait for the block)
+        for (int c = c0 + tid; c < cend; c += kLuNT) {
             double u[NB];
 #pragma unroll
             for (int i = 0; i < NB; ++i) u[i] = i < nb ? A[(long long)(k0 + i) * N + c] : 0.0;
@@ -388,32 +398,74 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g) {
                 if (i < nb) A[(long long)(k0 + i) * N + c] = u[i];
         }
         __syncthreads();
-        // A22 -= L21 U12
-        for (int cb = c0; cb < N; cb += kLuNT) {
-            const int c = cb + tid;
-            double u[NB];
+        // A22 -= L21 U12 on the rest of the outer block (at most kLuBB - NB
+        // columns): U12 staged in LDS, one thread per trailing row, the row's
+        // L21 and block entries loaded together
+        __syncthreads();
+        for (int e = tid; e < NB * kLuBB; e += kLuNT) {
+            const int i = e / kLuBB, cc = e % kLuBB, c = c0 + cc;
+            Ub[i][cc] = (i < nb && c < cend) ? A[(long long)(k0 + i) * N + c] : 0.0;
+        }
+        __syncthreads();
+        for (int r = c0 + tid; r < N; r += kLuNT) {
+            // a compiler-only barrier: Ub is read from LDS per row rather than
+            // kept in registers across the loop
+            asm volatile("" ::: "memory");
+            double l[NB], v[kLuBB - NB];
+            const double *row = A + (long long)r * N;
 #pragma unroll
-            for (int i = 0; i < NB; ++i)
-                u[i] = (c < N && i < nb) ? A[(long long)(k0 + i) * N + c] : 0.0;
-            for (int r0 = c0; r0 < N; r0 += kLuRows) {
+            for (int i = 0; i < NB; ++i) l[i] = i < nb ? row[k0 + i] : 0.0;
+#pragma unroll
+            for (int cc = 0; cc < kLuBB - NB; ++cc) v[cc] = c0 + cc < cend ? row[c0 + cc] : 0.0;
+#pragma unroll
+            for (int cc = 0; cc < kLuBB - NB; ++cc) {
+#pragma unroll
+                for (int i = 0; i < NB; ++i) v[cc] = fma(-l[i], Ub[i][cc], v[cc]);
+                if (c0 + cc < cend) A[(long long)r * N + c0 + cc] = v[cc];
+            }
+        }
+        __syncthreads();
+        if (c0 < cend || cend >= N) continue;
+        // the outer block is factored: U12 = Lb^-1 A12 and A22 -= Lb21 U12 on
+        // the columns beyond it, one rank-32 pass (each trailing element read
+        // and written once per 32 columns)
+        for (int e = tid; e < kLuBB * kLuBB; e += kLuNT) {
+            const int r = e / kLuBB, c = e % kLuBB;
+            Lb[r][c] = A[(long long)(K0 + r) * N + K0 + c];
+        }
+        __syncthreads();
+        for (int cb = cend; cb < N; cb += kLuNT) {
+            const int c = cb + tid;
+            double u[kLuBB];
+#pragma unroll
+            for (int i = 0; i < kLuBB; ++i) u[i] = c < N ? A[(long long)(K0 + i) * N + c] : 0.0;
+#pragma unroll
+            for (int i = 1; i < kLuBB; ++i)
+#pragma unroll
+                for (int l = 0; l < i; ++l) u[i] = fma(-Lb[i][l], u[l], u[i]);
+            if (c < N)
+#pragma unroll
+                for (int i = 0; i < kLuBB; ++i) A[(long long)(K0 + i) * N + c] = u[i];
+            for (int r0 = cend; r0 < N; r0 += kLuRows) {
                 const int nr = min(kLuRows, N - r0);
                 __syncthreads();
-                for (int e = tid; e < kLuRows * NB; e += kLuNT) {
-                    const int rr = e / NB, i = e % NB;
-                    L21[rr][i] = (rr < nr && i < nb) ? A[(long long)(r0 + rr) * N + k0 + i] : 0.0;
+                for (int e = tid; e < kLuRows * kLuBB; e += kLuNT) {
+                    const int rr = e / kLuBB, i = e % kLuBB;
+                    Lb21[rr][i] = rr < nr ? A[(long long)(r0 + rr) * N + K0 + i] : 0.0;
                 }
                 __syncthreads();
                 if (c < N) {
-                    // eight rows' loads in flight at a time
-                    for (int rr0 = 0; rr0 < nr; rr0 += 8) {
-                        double a[8];
+                    // 32 rows' loads in flight together (the stores of a
+                    // batch come before the next batch's loads)
+                    for (int rr0 = 0; rr0 < nr; rr0 += 32) {
+                        double a[32];
 #pragma unroll
-                        for (int t = 0; t < 8; ++t)
+                        for (int t = 0; t < 32; ++t)
                             a[t] = rr0 + t < nr ? A[(long long)(r0 + rr0 + t) * N + c] : 0.0;
 #pragma unroll
-                        for (int t = 0; t < 8; ++t) {
+                        for (int t = 0; t < 32; ++t) {
 #pragma unroll
-                            for (int i = 0; i < NB; ++i) a[t] = fma(-L21[rr0 + t][i], u[i], a[t]);
+                            for (int i = 0; i < kLuBB; ++i) a[t] = fma(-Lb21[rr0 + t][i], u[i], a[t]);
                             if (rr0 + t < nr) A[(long long)(r0 + rr0 + t) * N + c] = a[t];
                         }
                     }
@@ -527,8 +579,10 @@ int lu_factor(rt_handle *h, hipStream_t s) {
         hipLaunchKernelGGL((lu_factor_kernel<1, kLuNB>), dim3(h->n_atm), dim3(kLuNT), 0, s, g);
     else if (N <= 2 * kLuNT)
         hipLaunchKernelGGL((lu_factor_kernel<2, kLuNB>), dim3(h->n_atm), dim3(kLuNT), 0, s, g);
-    else
+    else if (N <= 4 * kLuNT)
         hipLaunchKernelGGL((lu_factor_kernel<4, kLuNB>), dim3(h->n_atm), dim3(kLuNT), 0, s, g);
+    else
+        hipLaunchKernelGGL((lu_factor_kernel<8, kLuNB>), dim3(h->n_atm), dim3(kLuNT), 0, s, g);
     if (hipGetLastError() != hipSuccess) return fail(RT_EDEVICE, "LU factorization launch failed");
     h->lu_ready = true;
     return RT_OK;

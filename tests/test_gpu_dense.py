@@ -309,8 +309,20 @@ def test_lu_batch():
 
 
 def test_lu_config3_two_rows_per_thread():
-    """1024 depth points: 2048 unknowns, two panel rows per thread."""
+    """1024 depth points: 2048 unknowns, four panel rows per thread."""
     p = W.config3()
+    with B.setup(p) as h:
+        x = dev(np.zeros(p.n_unknowns))
+        rc, info = h.solve_lu(x)
+    assert rc == 0
+    assert oracle_relres(p, host(x)).max() < 1e-12
+
+
+def test_lu_maximum_slab():
+    """RT_MAX_NS depth points (4096 unknowns: eight panel rows per thread, 127
+    rank-32 block updates) beside a 33-point slab (a partial outer block)."""
+    p = W.make_slabs([B.RT_MAX_NS, 33], [(1e-4, 1e8), (1e-2, 1e4)], 4, 5, 5.0, [1e-3, 1e-3],
+                     [1e-4, 1e-2], [0.5, 0.2])
     with B.setup(p) as h:
         x = dev(np.zeros(p.n_unknowns))
         rc, info = h.solve_lu(x)
