@@ -36,7 +36,7 @@ __device__ inline double readlane_d(double v, int lane) {
 // r <- (omega^-1 D + T)^-1 r for T the strict upper (UP) or lower triangle
 // of the slab's A (row-major, N x N), r in LDS; UNIT: a unit diagonal instead
 // of omega^-1 D (the L factor of an LU factorization).
-template <bool UP, bool UNIT = false>
+template <bool UP, bool UNIT = false, bool ROWWISE = false>
 __device__ void tri_sweep(const double *A, int N, double om, double *r, double *blk) {
     const int tid = threadIdx.x;
     const int nb = (N + kTriB - 1) / kTriB;
@@ -52,23 +52,27 @@ __device__ void tri_sweep(const double *A, int N, double om, double *r, double *
         }
     };
     double stage[kStage];
-    load_diag(UP ? nb - 1 : 0, stage);
+    if constexpr (!ROWWISE) load_diag(UP ? nb - 1 : 0, stage);
     for (int bi = 0; bi < nb; ++bi) {
         const int b = UP ? nb - 1 - bi : bi;
         const int i0 = b * kTriB, n = min(kTriB, N - i0);
+        if constexpr (ROWWISE) load_diag(b, stage);  // no registers to spare during the update
 #pragma unroll
         for (int t = 0; t < kStage; ++t) {
             const int e = tid + t * kTriNT;
             blk[(e / kTriB) * kTriPad + e % kTriB] = stage[t];
         }
         __syncthreads();
-        if (bi + 1 < nb) load_diag(UP ? b - 1 : b + 1, stage);
+        if constexpr (!ROWWISE)
+            if (bi + 1 < nb) load_diag(UP ? b - 1 : b + 1, stage);
         if (tid < kWave) {
             const int c = tid;
             double val = c < n ? r[i0 + c] : 0.0;
             const double dc = c < n ? (UNIT ? 1.0 : om / blk[c * kTriPad + c]) : 0.0;
             if (n == kTriB) {
                 // a full block: eight steps at a time, their LDS reads issued first
+                // (the outer loop stays rolled: one group's reads in registers)
+#pragma unroll 1
                 for (int i8 = 0; i8 < kTriB; i8 += 8) {
                     double col[8];
 #pragma unroll
@@ -95,42 +99,68 @@ __device__ void tri_sweep(const double *A, int N, double om, double *r, double *
             if (c < n) r[i0 + c] = val;
         }
         __syncthreads();
-        // the rows not yet solved (above the block for UP, else below) less
-        // the block's columns times its solution: thread (row q, group g)
-        // takes columns 4g .. 4g + 3, so each row's 64 entries are read by 16
-        // neighbouring lanes (512 contiguous bytes), and the 16 partial sums
-        // are added by butterfly; kTriPass passes of kTriNT / 16 rows each
-        // are loaded together
         const int lo = UP ? 0 : i0 + n, hi = UP ? i0 : N;
-        const int q = tid >> 4, g = tid & 15, c0 = 4 * g;
-        double x[4];
+        if constexpr (ROWWISE) {
+            // one thread per row, each row's 64 entries loaded together: the
+            // most bytes in flight per thread (a lone large slab)
+            for (int l = lo + tid; l < hi; l += kTriNT) {
+                const double2 *row = reinterpret_cast<const double2 *>(A + (long long)l * N + i0);
+                double acc0 = 0.0, acc1 = 0.0;
+                if (n == kTriB) {
+                    double2 v[kTriB / 2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) x[u] = c0 + u < n ? r[i0 + c0 + u] : 0.0;
-        for (int l0 = lo; l0 < hi; l0 += kTriPass * (kTriNT / 16)) {
-            double acc[kTriPass];
+                    for (int c2 = 0; c2 < kTriB / 2; ++c2) v[c2] = row[c2];
 #pragma unroll
-            for (int pass = 0; pass < kTriPass; ++pass) {
-                const int l = l0 + pass * (kTriNT / 16) + q;
-                acc[pass] = 0.0;
-                if (l < hi) {
-                    const double *row = A + (long long)l * N + i0 + c0;
-                    if (c0 + 3 < n) {
-                        const double2 v0 = reinterpret_cast<const double2 *>(row)[0];
-                        const double2 v1 = reinterpret_cast<const double2 *>(row)[1];
-                        acc[pass] = fma(v0.x, x[0], fma(v0.y, x[1], fma(v1.x, x[2], v1.y * x[3])));
-                    } else {
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            if (c0 + u < n) acc[pass] = fma(row[u], x[u], acc[pass]);
+                    for (int c2 = 0; c2 < kTriB / 2; ++c2) {
+                        acc0 = fma(v[c2].x, r[i0 + 2 * c2], acc0);
+                        acc1 = fma(v[c2].y, r[i0 + 2 * c2 + 1], acc1);
+                    }
+                } else {
+                    for (int c2 = 0; c2 < n / 2; ++c2) {
+                        const double2 v = row[c2];
+                        acc0 = fma(v.x, r[i0 + 2 * c2], acc0);
+                        acc1 = fma(v.y, r[i0 + 2 * c2 + 1], acc1);
                     }
                 }
+                r[l] -= acc0 + acc1;
             }
+        } else {
+            // the rows not yet solved (above the block for UP, else below) less
+            // the block's columns times its solution: thread (row q, group g)
+            // takes columns 4g .. 4g + 3, so each row's 64 entries are read by 16
+            // neighbouring lanes (512 contiguous bytes), and the 16 partial sums
+            // are added by butterfly; kTriPass passes of kTriNT / 16 rows each
+            // are loaded together
+            const int q = tid >> 4, g = tid & 15, c0 = 4 * g;
+            double x[4];
 #pragma unroll
-            for (int pass = 0; pass < kTriPass; ++pass) {
-                double v = acc[pass];
-                for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
-                const int l = l0 + pass * (kTriNT / 16) + q;
-                if (g == 0 && l < hi) r[l] -= v;
+            for (int u = 0; u < 4; ++u) x[u] = c0 + u < n ? r[i0 + c0 + u] : 0.0;
+            for (int l0 = lo; l0 < hi; l0 += kTriPass * (kTriNT / 16)) {
+                double acc[kTriPass];
+#pragma unroll
+                for (int pass = 0; pass < kTriPass; ++pass) {
+                    const int l = l0 + pass * (kTriNT / 16) + q;
+                    acc[pass] = 0.0;
+                    if (l < hi) {
+                        const double *row = A + (long long)l * N + i0 + c0;
+                        if (c0 + 3 < n) {
+                            const double2 v0 = reinterpret_cast<const double2 *>(row)[0];
+                            const double2 v1 = reinterpret_cast<const double2 *>(row)[1];
+                            acc[pass] = fma(v0.x, x[0], fma(v0.y, x[1], fma(v1.x, x[2], v1.y * x[3])));
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                if (c0 + u < n) acc[pass] = fma(row[u], x[u], acc[pass]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int pass = 0; pass < kTriPass; ++pass) {
+                    double v = acc[pass];
+                    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
+                    const int l = l0 + pass * (kTriNT / 16) + q;
+                    if (g == 0 && l < hi) r[l] -= v;
+                }
             }
         }
         __syncthreads();
@@ -148,6 +178,7 @@ struct TriArgs {
 };
 
 // out = P^-1 in.
+template <bool ROWWISE>
 __global__ __launch_bounds__(kTriNT) void tri_solve_kernel(TriArgs a) {
     extern __shared__ double sm[];
     const int s = blockIdx.x;
@@ -160,11 +191,11 @@ __global__ __launch_bounds__(kTriNT) void tri_solve_kernel(TriArgs a) {
     double *r = sm + kTriB * kTriPad;  // [N]
     for (int i = threadIdx.x; i < N; i += kTriNT) r[i] = a.in[v0 + i];
     __syncthreads();
-    tri_sweep<true>(A, N, a.omega, r, blk);
+    tri_sweep<true, false, ROWWISE>(A, N, a.omega, r, blk);
     if (a.kind == RT_PC_SSOR) {
         for (int i = threadIdx.x; i < N; i += kTriNT) r[i] *= A[(long long)i * N + i];
         __syncthreads();
-        tri_sweep<false>(A, N, a.omega, r, blk);
+        tri_sweep<false, false, ROWWISE>(A, N, a.omega, r, blk);
         const double sc = (2.0 - a.omega) / a.omega;
         for (int i = threadIdx.x; i < N; i += kTriNT) r[i] *= sc;
     }
@@ -478,6 +509,7 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g) {
 }
 
 // x = A^-1 b from the factors: row exchanges, L y = P b, U x = y.
+template <bool ROWWISE>
 __global__ __launch_bounds__(kTriNT) void lu_solve_kernel(const AtmDesc *atm, const double *LU,
                                                           const int *pivs, const double *b,
                                                           double *x) {
@@ -502,8 +534,8 @@ __global__ __launch_bounds__(kTriNT) void lu_solve_kernel(const AtmDesc *atm, co
             }
         }
     __syncthreads();
-    tri_sweep<false, true>(A, N, 1.0, r, blk);
-    tri_sweep<true, false>(A, N, 1.0, r, blk);
+    tri_sweep<false, true, ROWWISE>(A, N, 1.0, r, blk);
+    tri_sweep<true, false, ROWWISE>(A, N, 1.0, r, blk);
     for (int i = threadIdx.x; i < N; i += kTriNT) x[v0 + i] = r[i];
 }
 
@@ -528,15 +560,26 @@ TriArgs tri_args(const rt_handle *h, const double *in, double *out, const int *m
     return a;
 }
 
+// Few slabs (fewer workgroups than CUs): each workgroup's own loads in flight
+// decide its speed, so one thread per row with the row's 64 entries loaded
+// together; many slabs: the coalesced 16-lanes-per-row update.
+bool tri_rowwise(const rt_handle *h) { return h->n_atm < 256; }
+
 }  // namespace
 
 hipError_t precond_tri(const rt_handle *h, const double *in, double *out, const int *mask,
                        hipStream_t s) {
     const size_t lds = tri_lds(h->ns_max);
-    hipError_t e = lds_limit(tri_solve_kernel, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(tri_solve_kernel, dim3(h->n_atm), dim3(kTriNT), lds, s,
-                       tri_args(h, in, out, mask));
+    const TriArgs a = tri_args(h, in, out, mask);
+    if (tri_rowwise(h)) {
+        hipError_t e = lds_limit(tri_solve_kernel<true>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(tri_solve_kernel<true>, dim3(h->n_atm), dim3(kTriNT), lds, s, a);
+    } else {
+        hipError_t e = lds_limit(tri_solve_kernel<false>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(tri_solve_kernel<false>, dim3(h->n_atm), dim3(kTriNT), lds, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -590,11 +633,20 @@ int lu_factor(rt_handle *h, hipStream_t s) {
 
 hipError_t lu_solve(const rt_handle *h, const double *b, double *x, hipStream_t s) {
     const size_t lds = tri_lds(h->ns_max);
-    hipError_t e = lds_limit(lu_solve_kernel, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(lu_solve_kernel, dim3(h->n_atm), dim3(kTriNT), lds, s,
-                       (const AtmDesc *)h->d_atm, (const double *)h->d_LU, (const int *)h->d_piv,
-                       b, x);
+    const AtmDesc *atm = h->d_atm;
+    const double *LU = h->d_LU;
+    const int *piv = h->d_piv;
+    if (tri_rowwise(h)) {
+        hipError_t e = lds_limit(lu_solve_kernel<true>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(lu_solve_kernel<true>, dim3(h->n_atm), dim3(kTriNT), lds, s, atm, LU, piv,
+                           b, x);
+    } else {
+        hipError_t e = lds_limit(lu_solve_kernel<false>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(lu_solve_kernel<false>, dim3(h->n_atm), dim3(kTriNT), lds, s, atm, LU,
+                           piv, b, x);
+    }
     return hipGetLastError();
 }
 

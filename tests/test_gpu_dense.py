@@ -186,6 +186,29 @@ def test_precond_apply_batch(kind):
         assert backward_error(P, z[s], v[s]) <= 1e-13, i
 
 
+def _many_small_slabs(seed):
+    """300 small slabs: enough workgroups for the coalesced triangular update."""
+    rng = np.random.default_rng(seed)
+    n = 300
+    ns = [int(v) for v in rng.integers(2, 48, n)]
+    return W.make_slabs(ns, [(1e-3, float(10 ** rng.uniform(3, 6))) for _ in range(n)], 4, 5, 5.0,
+                        list(10 ** rng.uniform(-4, -2, n)), list(10 ** rng.uniform(-4, -2, n)),
+                        list(rng.uniform(0, 0.7, n)))
+
+
+@pytest.mark.parametrize("kind", ["sor", "ssor"])
+def test_precond_apply_many_slabs(kind):
+    p = _many_small_slabs(21)
+    v = W.random_vector(p.n_unknowns, 7)
+    with B.setup(p, precond=PCS[kind]) as h:
+        z = host(h.precond_apply(dev(v)))
+    for i, s in enumerate(O._slices(p)):
+        if i not in (0, 1, 150, 298, 299):
+            continue
+        P = textbook_P(O.assemble(p.slab(i)), kind, 1.0)
+        assert backward_error(P, z[s], v[s]) <= 1e-13, i
+
+
 def _paper_x0(p):
     x0 = np.zeros(p.n_unknowns)
     x0[0::2] = 1.0
@@ -327,4 +350,14 @@ def test_lu_maximum_slab():
         x = dev(np.zeros(p.n_unknowns))
         rc, info = h.solve_lu(x)
     assert rc == 0
+    assert oracle_relres(p, host(x)).max() < 1e-12
+
+
+def test_lu_many_slabs():
+    """300 small slabs: the coalesced triangular sweeps of the LU solve."""
+    p = _many_small_slabs(22)
+    with B.setup(p) as h:
+        x = dev(np.zeros(p.n_unknowns))
+        rc, info = h.solve_lu(x)
+    assert rc == 0 and all(i.status == "converged" for i in info)
     assert oracle_relres(p, host(x)).max() < 1e-12
