@@ -197,6 +197,29 @@ def test_prd_mixed_refinement_solve(shape):
     assert rel < 1e-9, rel
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_prd_batch_solve_per_slab(precision):
+    """Three uneven slabs with their own R: each slab's solve (FP64 GMRES, or
+    the refinement around BF16x3 inner solves) reaches 1e-9 by the oracle's
+    residual of that slab."""
+    p, R, _ = _batch_case([7, 23, 40], 8, 12, "delo_linear", 0.5, 10)
+    nnu = len(p.w_nu)
+    prec = B.RT_PREC_MIXED if precision == "mixed" else B.RT_PREC_FP64
+    with B.setup(p, rtol=1e-9, restart=30, maxit=5000, precision=prec) as h:
+        h.set_redistribution(R)
+        x = dev(np.zeros(h.prd_size()))
+        rc, info = h.solve_prd_gmres(x)
+        xs = host(x)
+    assert rc == 0 and all(i.status == "converged" for i in info), info
+    off = 0
+    for i, ns in enumerate(int(n) for n in p.ns):
+        seg = slice(2 * nnu * off, 2 * nnu * (off + ns))
+        b = RDO.rhs(p, R[i], i=i)
+        rel = np.linalg.norm(b - RDO.apply(p, R[i], xs[seg], i=i)) / np.linalg.norm(b)
+        assert rel < 1e-9, (i, rel)
+        off += ns
+
+
 def test_prd_requires_R():
     p = W.config1_subgrid()
     with B.setup(p) as h:
