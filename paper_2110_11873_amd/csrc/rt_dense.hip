@@ -266,6 +266,7 @@ constexpr int kLuNT = 512;   // 256 VGPRs per lane for the rank-32 pass
 constexpr int kLuRows = 64;  // L21 rows staged per pass of the trailing update
 constexpr int kLuNB = 8;     // panel width (16 spills the panel's registers)
 constexpr int kLuBB = 32;    // outer block: its trailing update is one rank-32 pass
+constexpr int kLuSplitSlabs = 32;  // batches up to this many slabs: multi-workgroup updates
 
 struct LuArgs {
     const AtmDesc *atm;
@@ -274,8 +275,8 @@ struct LuArgs {
     int *sing;     // per slab: 1 if a pivot was zero
 };
 
-template <int R, int NB>
-__global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g) {
+template <int R, int NB, bool SPLIT = false>
+__global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g, int K0s = 0) {
     constexpr int NW = kLuNT / kWave;
     __shared__ double swp[2][2][NB];       // [buffer][row j, row p][column]
     __shared__ double redv[2][NW];
@@ -294,7 +295,12 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g) {
     int *piv = g.piv + 2LL * at.doff;
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     int singular = 0;
-    for (int k0 = 0; k0 < N; k0 += NB) {
+    // SPLIT: only the outer block at K0s (its swaps and updates confined to
+    // the block's columns); the columns outside it are done by the
+    // multi-workgroup kernels below
+    if (SPLIT && K0s >= N) return;
+    if (SPLIT && K0s == 0 && tid == 0) g.sing[slab] = 0;
+    for (int k0 = SPLIT ? K0s : 0; k0 < (SPLIT ? min(K0s + kLuBB, N) : N); k0 += NB) {
         const int nb = min(NB, N - k0);
         const int K0 = k0 / kLuBB * kLuBB, cend = min(K0 + kLuBB, N);  // this panel's outer block
         double P[R][NB];
@@ -396,7 +402,7 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g) {
         if (tid < nb) piv[k0 + tid] = s_piv[tid];
         __syncthreads();
         // the panel's row exchanges on the other columns, in order
-        for (int c = tid; c < N; c += kLuNT) {
+        for (int c = (SPLIT ? K0 : 0) + tid; c < (SPLIT ? cend : N); c += kLuNT) {
             if (c >= k0 && c < k0 + nb) continue;
             for (int jj = 0; jj < nb; ++jj) {
                 const int p = s_piv[jj], j = k0 + jj;
@@ -456,7 +462,7 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g) {
             }
         }
         __syncthreads();
-        if (c0 < cend || cend >= N) continue;
+        if (SPLIT || c0 < cend || cend >= N) continue;
         // the outer block is factored: U12 = Lb^-1 A12 and A22 -= Lb21 U12 on
         // the columns beyond it, one rank-32 pass (each trailing element read
         // and written once per 32 columns)
@@ -505,7 +511,105 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g) {
         }
         __syncthreads();
     }
-    if (tid == 0) g.sing[slab] = singular;
+    if (tid == 0) {
+        if (!SPLIT) g.sing[slab] = singular;
+        else if (singular) g.sing[slab] = 1;
+    }
+}
+
+// Multi-workgroup completion of outer block K0 (few large slabs), after
+// lu_factor_kernel<..., true> has factored the block's columns:
+//  * lu_swap_u12_kernel, one wavefront per (slab, 64-column tile): the
+//    block's row exchanges, in order, on every column outside the block, then
+//    U12 = Lb^-1 A12 for the tile's columns right of the block;
+//  * lu_rank32_kernel, one workgroup per (slab, 64-column tile, 128-row
+//    tile): A22 -= L21 U12 with U12 and L21 staged in LDS.
+constexpr int kLuTileC = 64, kLuTileR = 128;
+
+__global__ __launch_bounds__(kWave) void lu_swap_u12_kernel(LuArgs g, int K0) {
+    __shared__ double Lb[kLuBB][kLuBB + 1];
+    __shared__ int sp[kLuBB];
+    const int slab = blockIdx.y;
+    const AtmDesc at = g.atm[slab];
+    const int N = 2 * at.ns;
+    if (K0 >= N) return;
+    const int t0 = blockIdx.x * kLuTileC;
+    if (t0 >= N) return;
+    double *A = g.LU + at.a_off;
+    const int *piv = g.piv + 2LL * at.doff;
+    const int cend = min(K0 + kLuBB, N), nbk = cend - K0, tid = threadIdx.x;
+    if (tid < nbk) sp[tid] = piv[K0 + tid];
+    for (int e = tid; e < kLuBB * kLuBB; e += kWave) {
+        const int r = e / kLuBB, c = e % kLuBB;
+        Lb[r][c] = (r < nbk && c < nbk) ? A[(long long)(K0 + r) * N + K0 + c] : 0.0;
+    }
+    __syncthreads();
+    const int c = t0 + tid;
+    if (c >= N || (c >= K0 && c < cend)) return;
+    for (int i = 0; i < nbk; ++i) {
+        const int p = sp[i], j = K0 + i;
+        if (p != j) {
+            const double t = A[(long long)j * N + c];
+            A[(long long)j * N + c] = A[(long long)p * N + c];
+            A[(long long)p * N + c] = t;
+        }
+    }
+    if (c < cend) return;  // left of the block: the exchanges only
+    // right of the block: there are such columns only when the block is
+    // whole (nbk = kLuBB), so no row guards
+    double u[kLuBB];
+#pragma unroll
+    for (int i = 0; i < kLuBB; ++i) u[i] = A[(long long)(K0 + i) * N + c];
+#pragma unroll
+    for (int i = 1; i < kLuBB; ++i)
+#pragma unroll
+        for (int l = 0; l < i; ++l) u[i] = fma(-Lb[i][l], u[l], u[i]);
+#pragma unroll
+    for (int i = 0; i < kLuBB; ++i) A[(long long)(K0 + i) * N + c] = u[i];
+}
+
+__global__ __launch_bounds__(256) void lu_rank32_kernel(LuArgs g, int K0) {
+    __shared__ double U[kLuBB][kLuTileC];
+    __shared__ double L[kLuTileR][kLuBB + 1];
+    const int slab = blockIdx.z;
+    const AtmDesc at = g.atm[slab];
+    const int N = 2 * at.ns, cend = K0 + kLuBB;
+    if (cend >= N) return;  // no trailing matrix (or the last, partial block)
+    const int t0 = cend + blockIdx.x * kLuTileC, r0 = cend + blockIdx.y * kLuTileR;
+    if (t0 >= N || r0 >= N) return;
+    double *A = g.LU + at.a_off;
+    const int tid = threadIdx.x, cl = tid % kLuTileC, rg = tid / kLuTileC;  // 4 row lanes
+    for (int e = tid; e < kLuBB * kLuTileC; e += 256) {
+        const int i = e / kLuTileC, cc = e % kLuTileC;
+        U[i][cc] = t0 + cc < N ? A[(long long)(K0 + i) * N + t0 + cc] : 0.0;
+    }
+    const int nr = min(kLuTileR, N - r0);
+    for (int e = tid; e < kLuTileR * kLuBB; e += 256) {
+        const int rr = e / kLuBB, i = e % kLuBB;
+        L[rr][i] = rr < nr ? A[(long long)(r0 + rr) * N + K0 + i] : 0.0;
+    }
+    __syncthreads();
+    const int c = t0 + cl;
+    if (c >= N) return;
+    double u[kLuBB];
+#pragma unroll
+    for (int i = 0; i < kLuBB; ++i) u[i] = U[i][cl];
+    // rows rg, rg + 4, ...: 16 of them loaded together, twice
+    for (int h = 0; h < kLuTileR / 4; h += 16) {
+        double a[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int rr = rg + 4 * (h + t);
+            a[t] = rr < nr ? A[(long long)(r0 + rr) * N + c] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int rr = rg + 4 * (h + t);
+#pragma unroll
+            for (int i = 0; i < kLuBB; ++i) a[t] = fma(-L[rr][i], u[i], a[t]);
+            if (rr < nr) A[(long long)(r0 + rr) * N + c] = a[t];
+        }
+    }
 }
 
 // x = A^-1 b from the factors: row exchanges, L y = P b, U x = y.
@@ -618,6 +722,30 @@ int lu_factor(rt_handle *h, hipStream_t s) {
         return fail(RT_EDEVICE, "copy of the assembled operator failed");
     LuArgs g{h->d_atm, h->d_LU, h->d_piv, h->d_sing};
     const int N = 2 * h->ns_max;
+    if (h->n_atm <= kLuSplitSlabs && N > kLuBB) {
+        // few slabs: each 32-column block factored by one workgroup per slab,
+        // the rest of the matrix updated by workgroups over column and row tiles
+        for (int K0 = 0; K0 < N; K0 += kLuBB) {
+            if (N <= kLuNT)
+                hipLaunchKernelGGL((lu_factor_kernel<1, kLuNB, true>), dim3(h->n_atm), dim3(kLuNT), 0, s, g, K0);
+            else if (N <= 2 * kLuNT)
+                hipLaunchKernelGGL((lu_factor_kernel<2, kLuNB, true>), dim3(h->n_atm), dim3(kLuNT), 0, s, g, K0);
+            else if (N <= 4 * kLuNT)
+                hipLaunchKernelGGL((lu_factor_kernel<4, kLuNB, true>), dim3(h->n_atm), dim3(kLuNT), 0, s, g, K0);
+            else
+                hipLaunchKernelGGL((lu_factor_kernel<8, kLuNB, true>), dim3(h->n_atm), dim3(kLuNT), 0, s, g, K0);
+            hipLaunchKernelGGL(lu_swap_u12_kernel, dim3((N + kLuTileC - 1) / kLuTileC, h->n_atm),
+                               dim3(kWave), 0, s, g, K0);
+            const int rest = N - K0 - kLuBB;
+            if (rest > 0)
+                hipLaunchKernelGGL(lu_rank32_kernel,
+                                   dim3((rest + kLuTileC - 1) / kLuTileC, (rest + kLuTileR - 1) / kLuTileR, h->n_atm),
+                                   dim3(256), 0, s, g, K0);
+            if (hipGetLastError() != hipSuccess) return fail(RT_EDEVICE, "LU factorization launch failed");
+        }
+        h->lu_ready = true;
+        return RT_OK;
+    }
     if (N <= kLuNT)
         hipLaunchKernelGGL((lu_factor_kernel<1, kLuNB>), dim3(h->n_atm), dim3(kLuNT), 0, s, g);
     else if (N <= 2 * kLuNT)

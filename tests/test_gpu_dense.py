@@ -298,6 +298,20 @@ def test_lu_subgrid_equals_lapack(fs):
     assert np.abs(host(x) - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal"])
+def test_lu_config1_equals_lapack_multi_workgroup(fs):
+    """80 unknowns: three 32-column blocks, each finished by the
+    multi-workgroup exchange and update kernels; the solution agrees with
+    LAPACK's getrf route to a few ulps of the condition number."""
+    p = W.config1(fs)
+    ref = D.Dense(p).solve()
+    with B.setup(p) as h:
+        x = dev(np.zeros(p.n_unknowns))
+        rc, info = h.solve_lu(x)
+    assert rc == 0 and info[0].status == "converged" and info[0].relres < 1e-13
+    assert np.abs(host(x) - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("maker", [W.config1, lambda: W.paper_replica(
     140, scale="integrated", normalize=False), W.config2])
 def test_lu_single_slab(maker):
