@@ -251,7 +251,7 @@ hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, d
     sweep_config(h, fp32, &W, &pf);
     hipError_t e = launch_sweep(h->L, W, pf, fp32, a, h->n_blocks, h->ns_max, s);
     if (e != hipSuccess) return e;
-    return launch_finalize(a, h->d_pt_atm, h->ns_total, s);
+    return launch_finalize(a, h->n_atm, h->ns_max, s);
 }
 
 void clear_graphs(rt_handle *h) {

@@ -136,7 +136,7 @@ hipError_t launch_sweep_f64(int L, int W, bool pf, const SweepArgs &a, int nbloc
 // Launch configuration of the sweep for a handle: waves per block and whether
 // the next ray batch is loaded during the current one.
 void sweep_config(const rt_handle *h, bool fp32, int *W, bool *pf);
-hipError_t launch_finalize(const SweepArgs &a, const int *pt_atm, int npts, hipStream_t s);
+hipError_t launch_finalize(const SweepArgs &a, int n_atm, int ns_max, hipStream_t s);
 hipError_t launch_coef_build(int nblocks, int W, const AtmDesc *atm, const BlockDesc *blk,
                              const double *tau, const double *opac, const double *mu_pos, int fs,
                              const double *qray, double2 *coef64, float2 *coef32, double *qtile,

@@ -220,13 +220,15 @@ int chunk_len(int ns, int C, int L) {
 //   mode 1: sigma_out = xi [J00, W2 J20] + [eps B, 0].
 // One thread per depth point.
 // --------------------------------------------------------------------------
-__global__ void finalize_kernel(SweepArgs a, const int *pt_atm, int npts) {
-    const int kk = blockIdx.x * blockDim.x + threadIdx.x;
-    if (kk >= npts) return;
-    const int atm = pt_atm[kk];
+// One workgroup per (256 depth points, slab): the slab's descriptor is a
+// uniform load, so the partial sums are one memory round trip from the start.
+__global__ void finalize_kernel(SweepArgs a) {
+    const int atm = blockIdx.y;
     if (a.mask && a.mask[atm] == 0) return;
     const AtmDesc at = a.atm[atm];
-    const int k = kk - at.doff;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= at.ns) return;
+    const int kk = at.doff + k;
     const long long stride = 2LL * at.ns;
     const double *pJ = a.partial + at.part_off + 2 * k;
     double J0 = 0.0, J2 = 0.0;
@@ -286,9 +288,9 @@ void sweep_config(const rt_handle *h, bool fp32, int *W, bool *pf) {
     *pf = (h->opt.prefetch >= 2) && h->L <= 8;
 }
 
-hipError_t launch_finalize(const SweepArgs &a, const int *pt_atm, int npts, hipStream_t s) {
-    if (npts <= 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_kernel, dim3((npts + 255) / 256), dim3(256), 0, s, a, pt_atm, npts);
+hipError_t launch_finalize(const SweepArgs &a, int n_atm, int ns_max, hipStream_t s) {
+    if (n_atm <= 0 || ns_max <= 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3((ns_max + 255) / 256, n_atm), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
