@@ -469,6 +469,34 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
         return (long long)x.wb_count * h->atm_h[x.atm].Leff >
                (long long)y.wb_count * h->atm_h[y.atm].Leff;
     });
+    {
+        // XCD-aware order: workgroups are handed to the 8 XCDs in turn by
+        // index, and the blocks of one slab stage the same sources, so each
+        // slab's run of blocks goes to one XCD (indices 8 apart, one L2) and
+        // consecutive runs to consecutive XCDs -- the longest-first order
+        // kept per group of 8 runs.  Applied when the runs fill the XCDs
+        // evenly (equal-size runs, a multiple of 8 of them).
+        constexpr int kXcd = 8;
+        std::vector<std::vector<BlockDesc>> q(kXcd);
+        size_t i = 0;
+        int run = 0;
+        while (i < h->blk_h.size()) {
+            size_t j = i;
+            while (j < h->blk_h.size() && h->blk_h[j].atm == h->blk_h[i].atm) ++j;
+            for (size_t k = i; k < j; ++k) q[run % kXcd].push_back(h->blk_h[k]);
+            ++run;
+            i = j;
+        }
+        bool even = true;
+        for (int x = 1; x < kXcd; ++x) even = even && q[x].size() == q[0].size();
+        if (even && !q[0].empty()) {
+            std::vector<BlockDesc> out;
+            out.reserve(h->blk_h.size());
+            for (size_t k = 0; k < q[0].size(); ++k)
+                for (int x = 0; x < kXcd; ++x) out.push_back(q[x][k]);
+            h->blk_h.swap(out);
+        }
+    }
     h->n_qt = qt;
     h->n_pairs = coef;
     h->n_partial = part;
