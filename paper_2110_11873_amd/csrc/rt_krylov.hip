@@ -108,6 +108,63 @@ __device__ inline int scatter_index(int lane) {
            ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
 }
 
+// The same for 16 values with 20 shuffles: lane l ends with the sum of value
+// ((l>>5)&1)*8 + ((l>>4)&1)*4 + ((l>>3)&1)*2 + ((l>>2)&1); lanes l, l^1, l^2
+// and l^3 hold the same value.
+__device__ inline double wave_reduce_scatter16(double (&v)[16]) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const bool up = lane & 32;
+        const double send = up ? v[t] : v[t + 8];
+        const double keep = up ? v[t + 8] : v[t];
+        v[t] = keep + __shfl_xor(send, 32);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const bool up = lane & 16;
+        const double send = up ? v[t] : v[t + 4];
+        const double keep = up ? v[t + 4] : v[t];
+        v[t] = keep + __shfl_xor(send, 16);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const bool up = lane & 8;
+        const double send = up ? v[t] : v[t + 2];
+        const double keep = up ? v[t + 2] : v[t];
+        v[t] = keep + __shfl_xor(send, 8);
+    }
+    {
+        const bool up = lane & 4;
+        const double send = up ? v[0] : v[1];
+        const double keep = up ? v[1] : v[0];
+        v[0] = keep + __shfl_xor(send, 4);
+    }
+    const double s = v[0] + __shfl_xor(v[0], 2);
+    return s + __shfl_xor(s, 1);
+}
+
+__device__ inline int scatter_index16(int lane) {
+    return ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 +
+           ((lane >> 2) & 1);
+}
+
+// Scatter-reduce K in {16, 32} per-lane values; the lanes that store a sum
+// and the value index each of them holds.
+template <int K>
+__device__ inline double wave_reduce_scatter(double (&v)[K]) {
+    if constexpr (K == 32) return wave_reduce_scatter32(v);
+    else return wave_reduce_scatter16(v);
+}
+template <int K>
+__device__ inline bool scatter_writer(int lane) {
+    return K == 32 ? (lane & 1) == 0 : (lane & 3) == 0;
+}
+template <int K>
+__device__ inline int scatter_slot(int lane) {
+    return K == 32 ? scatter_index(lane) : scatter_index16(lane);
+}
+
 struct VecArgs {
     const AtmDesc *atm;
     long long N;         // total unknowns (row stride of the basis)
@@ -393,7 +450,9 @@ __global__ __launch_bounds__(NT) void gm_arnoldi_kernel(VecArgs a, int j) {
 }
 
 // The same step for slabs of at most NTF points and restarts m < MR, with the
-// operator's last pass fused in and the basis held in registers:
+// operator's last pass fused in and the basis held in registers (MR_ rows:
+// steps j < 16 hold half the rows, which halves the basis registers and lets
+// two 512-thread workgroups share a CU):
 //  * w = A P^-1 v_j is formed here from the sweep's per-block quadrature sums
 //    (the finalize pass: J = sum of the slab's block slots in block order plus
 //    the source part Q S, w = z - xi [J00, W2 J20], z = P^-1 v_j), so w is
@@ -414,12 +473,14 @@ __device__ inline double block_sum_f(double a, double *red) {
     return a;
 }
 
+template <int MR_>
 __global__ __launch_bounds__(NTF) void gm_arnoldi_fused_kernel(VecArgs a, int j) {
-    __shared__ double red[32 * NWF];
-    __shared__ double hp[MR];
-    __shared__ double hsum[MR];
+    static_assert(MR_ == 16 || MR_ == 32, "basis rows held in registers");
+    __shared__ double red[MR_ * NWF];
+    __shared__ double hp[MR_];
+    __shared__ double hsum[MR_];
     __shared__ double red2[NWF];
-    __shared__ double scs[MR], ssn[MR];
+    __shared__ double scs[MR_], ssn[MR_];
     const int atm = blockIdx.x;
     if (!a.cycle[atm]) return;
     const AtmDesc at = a.atm[atm];
@@ -433,17 +494,32 @@ __global__ __launch_bounds__(NTF) void gm_arnoldi_fused_kernel(VecArgs a, int j)
     const long long e0 = 2LL * (at.doff + k);
 
     // basis rows 0..j at this point (zero beyond)
-    double v0[MR], v2[MR];
+    double v0[MR_], v2[MR_];
+    if constexpr (MR_ == 32) {
 #pragma unroll
-    for (int t = 0; t < MR; ++t) {
-        v0[t] = v2[t] = 0.0;
-        if (on && t <= j) {
-            const double2 x = *reinterpret_cast<const double2 *>(a.V + (long long)t * a.N + e0);
-            v0[t] = x.x;
-            v2[t] = x.y;
+        for (int t = 0; t < MR_; ++t) {
+            v0[t] = v2[t] = 0.0;
+            if (on && t <= j) {
+                const double2 x = *reinterpret_cast<const double2 *>(a.V + (long long)t * a.N + e0);
+                v0[t] = x.x;
+                v2[t] = x.y;
+            }
+        }
+    } else {
+        // branch-free: rows past j re-read row j, points past the slab read
+        // its first point, and both are replaced by zero (a branch per row
+        // would copy the whole register array at every join)
+        const long long eb = on ? e0 : 2LL * at.doff;
+#pragma unroll
+        for (int t = 0; t < MR_; ++t) {
+            const double2 x =
+                *reinterpret_cast<const double2 *>(a.V + (long long)min(t, j) * a.N + eb);
+            const bool use = on && t <= j;
+            v0[t] = use ? x.x : 0.0;
+            v2[t] = use ? x.y : 0.0;
         }
     }
-    if (tid < MR) hsum[tid] = 0.0;
+    if (tid < MR_) hsum[tid] = 0.0;
 
     // w = A P^-1 v_j; the block slots are read 8 at a time, all loads of a
     // group in flight together (addresses clamped, extra values unused)
@@ -467,7 +543,7 @@ __global__ __launch_bounds__(NTF) void gm_arnoldi_fused_kernel(VecArgs a, int j)
         }
         double vj0 = 0.0, vj2 = 0.0;
 #pragma unroll
-        for (int t = 0; t < MR; ++t)
+        for (int t = 0; t < MR_; ++t)
             if (t == j) {
                 vj0 = v0[t];
                 vj2 = v2[t];
@@ -491,13 +567,13 @@ __global__ __launch_bounds__(NTF) void gm_arnoldi_fused_kernel(VecArgs a, int j)
 
     // classical Gram-Schmidt, twice
     for (int pass = 0; pass < 2; ++pass) {
-        double part[32];
+        double part[MR_];
 #pragma unroll
-        for (int t = 0; t < MR; ++t) part[t] = v0[t] * w0 + v2[t] * w2;
-        const double sum = wave_reduce_scatter32(part);
-        if ((lane & 1) == 0) red[scatter_index(lane) * NWF + wave] = sum;
+        for (int t = 0; t < MR_; ++t) part[t] = v0[t] * w0 + v2[t] * w2;
+        const double sum = wave_reduce_scatter<MR_>(part);
+        if (scatter_writer<MR_>(lane)) red[scatter_slot<MR_>(lane) * NWF + wave] = sum;
         __syncthreads();
-        if (tid < MR) {
+        if (tid < MR_) {
             double s = 0.0;
             for (int w = 0; w < NWF; ++w) s += red[tid * NWF + w];
             hp[tid] = s;
@@ -505,7 +581,7 @@ __global__ __launch_bounds__(NTF) void gm_arnoldi_fused_kernel(VecArgs a, int j)
         }
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < MR; ++t) {
+        for (int t = 0; t < MR_; ++t) {
             const double h = hp[t];  // zero for t > j
             w0 -= h * v0[t];
             w2 -= h * v2[t];
@@ -520,7 +596,7 @@ __global__ __launch_bounds__(NTF) void gm_arnoldi_fused_kernel(VecArgs a, int j)
     }
     // the earlier rotations (read into LDS at the start, ordered by the
     // block sums' barriers) are applied by one thread in registers
-    if (tid == 0) hessenberg_column_regs<MR>(a, atm, j, hsum, scs, ssn, hn);
+    if (tid == 0) hessenberg_column_regs<MR_>(a, atm, j, hsum, scs, ssn, hn);
 
 }
 
@@ -1194,7 +1270,10 @@ struct Driver {
             } else {
                 ok(apply_sweep(h, vj, h->d_dinv, h->d_cycle, fp32, s));
             }
-            hipLaunchKernelGGL(gm_arnoldi_fused_kernel, dim3(h->n_atm), dim3(NTF), 0, s, a, j);
+            if (j < 16)
+                hipLaunchKernelGGL(gm_arnoldi_fused_kernel<16>, dim3(h->n_atm), dim3(NTF), 0, s, a, j);
+            else
+                hipLaunchKernelGGL(gm_arnoldi_fused_kernel<MR>, dim3(h->n_atm), dim3(NTF), 0, s, a, j);
             ok(hipGetLastError());
         } else {
             prec_sweep(vj, h->d_w, h->d_cycle, fp32);
