@@ -259,12 +259,14 @@ def test_solvers_config2(fs, kind):
         assert abs(info[0].iterations - oi[0]["iterations"]) <= max(3, oi[0]["iterations"] // 4)
 
 
-@pytest.mark.parametrize("restart", [30, 31, 32, 40])
+@pytest.mark.parametrize("restart", [8, 16, 17, 30, 31, 32, 40])
 def test_gmres_arnoldi_paths(restart):
     """Restarts below 32 use the Arnoldi step fused with the operator's last
-    pass (basis in registers); longer ones the general step.  Both must reach
-    the oracle's residual on a batch of uneven slabs, with iteration counts
-    close to the oracle running GMRES(restart) on each slab."""
+    pass (basis in registers): steps j < 16 hold 16 rows, later steps 32, so
+    restarts 8 and 16 run only the 16-row step and 17 switches at its last
+    step.  Longer restarts use the general step.  All must reach the oracle's
+    residual on a batch of uneven slabs, with iteration counts close to the
+    oracle running GMRES(restart) on each slab."""
     ns = [40, 97, 200, 511]
     p = W.make_slabs(ns, [(1e-3, 1e5)] * len(ns), 8, 21, 6.0, [1e-3] * len(ns),
                      [1e-3, 1e-2, 1e-4, 1e-3], [0.6, 0.0, 0.3, 0.5])
