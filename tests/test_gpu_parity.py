@@ -266,7 +266,13 @@ def test_gmres_arnoldi_paths(restart):
     restarts 8 and 16 run only the 16-row step and 17 switches at its last
     step.  Longer restarts use the general step.  All must reach the oracle's
     residual on a batch of uneven slabs, with iteration counts close to the
-    oracle running GMRES(restart) on each slab."""
+    oracle running GMRES(restart) on each slab.
+
+    Below restart 30 the counts of the two stiff slabs depend on rounding:
+    the oracle itself, with x0 perturbed by 1e-15 relative, takes 138..179
+    steps at restart 8 on the 511-point slab (148 unperturbed) and 124..175
+    on the 200-point slab, against +-1 at restart 30.  Those restarts get a
+    30% band; the residual bound is the same for all."""
     ns = [40, 97, 200, 511]
     p = W.make_slabs(ns, [(1e-3, 1e5)] * len(ns), 8, 21, 6.0, [1e-3] * len(ns),
                      [1e-3, 1e-2, 1e-4, 1e-3], [0.6, 0.0, 0.3, 0.5])
@@ -278,7 +284,8 @@ def test_gmres_arnoldi_paths(restart):
     for i in range(len(ns)):
         _, oi = O.gmres(p.slab(i), tol=1e-10, restart=restart)
         it = oi[0]["iterations"]
-        assert abs(info[i].iterations - it) <= max(2, it // 20), (i, info[i].iterations, it)
+        band = max(2, it // 20) if restart >= 30 else max(2, it * 3 // 10)
+        assert abs(info[i].iterations - it) <= band, (i, info[i].iterations, it)
 
 
 @pytest.mark.parametrize("kind,mixed", [("gmres", False), ("gmres", True), ("bicgstab", False),
