@@ -217,8 +217,8 @@ int hip_check(hipError_t e, const char *what) {
 static SweepArgs sweep_args(rt_handle *h, const double *in, const double *scale, double *out,
                             const int *mask, bool fp32, int mode) {
     SweepArgs a{};
-    a.atm = h->d_atm;
-    a.blk = h->d_blk;
+    a.atm = plan_atm(h);
+    a.blk = plan_blk(h);
     a.coef = fp32 ? (const void *)h->d_coef32 : (const void *)h->d_coef64;
     a.q = h->d_qt;
     a.dirc = h->d_dirc;
@@ -239,7 +239,7 @@ hipError_t apply_sweep(rt_handle *h, const double *in, const double *scale, cons
     int W;
     bool pf;
     sweep_config(h, fp32, &W, &pf);
-    return launch_sweep(h->L, W, pf, fp32, a, h->n_blocks, h->ns_max, s);
+    return launch_sweep(h->L, W, pf, fp32, a, plan_blocks(h), h->ns_max, s);
 }
 
 hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, double *out,
@@ -249,7 +249,7 @@ hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, d
     int W;
     bool pf;
     sweep_config(h, fp32, &W, &pf);
-    hipError_t e = launch_sweep(h->L, W, pf, fp32, a, h->n_blocks, h->ns_max, s);
+    hipError_t e = launch_sweep(h->L, W, pf, fp32, a, plan_blocks(h), h->ns_max, s);
     if (e != hipSuccess) return e;
     return launch_finalize(a, h->n_atm, h->ns_max, s);
 }
@@ -325,6 +325,7 @@ void rt_destroy(rt_handle *h) {
     if (!h) return;
     void *ptrs[] = {h->d_tau,   h->d_B,     h->d_opac,    h->d_phi,     h->d_mu_pos, h->d_w_pos,
                     h->d_w_nu,  h->d_pt_atm, h->d_atm,    h->d_blk,     h->d_rayc,   h->d_coef64,
+                    h->d_atm_tail, h->d_blk_tail,
                     h->d_q,     h->d_qt,      h->d_dirc,    h->d_Qs,
                     h->d_coef32, h->d_partial, h->d_diag,  h->d_dinv,   h->d_b,
                     h->d_V,     h->d_H,     h->d_cs,      h->d_sn,      h->d_g,      h->d_w,
@@ -397,8 +398,10 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
             delete h;
             return fail(RT_EINVAL, "options.chunk too short for ns (need 64 * chunk >= ns - 1)");
         }
-    long long coef = 0, part = 0, qt = 0, dense = 0, ew = 0;
-    int blk = 0;
+    long long coef = 0, part = 0, qt = 0, dense = 0, ew = 0, part_t = 0;
+    int blk = 0, blk_t = 0;
+    std::vector<AtmDesc> atm_t(h->n_atm);
+    std::vector<BlockDesc> blk_t_h;
     // Waves per block and wave-batches per wave.  A block never mixes
     // directions.  Big batches: one block per (slab, direction), the fewest
     // partial sums; small problems: about 48 blocks in all, for parallelism.
@@ -456,6 +459,31 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
             }
         }
         h->NB = nb;
+        // the tail plan: the same tiles, at most kTailWb wave-batches per
+        // wave (a plan the caller fixed is kept for every cycle)
+        {
+            const int nbt = opt.wave_batches > 0 ? nb : std::min(nb, kTailWb);
+            const int wbt = h->W * nbt;
+            const int bpd = (d.nwb + wbt - 1) / wbt;
+            AtmDesc dt = d;
+            dt.nblk = h->M * bpd;
+            dt.blk_first = blk_t;
+            dt.part_off = part_t;
+            for (int m = 0; m < h->M; ++m) {
+                for (int bb = 0; bb < bpd; ++bb) {
+                    BlockDesc bd{};
+                    bd.atm = a;
+                    bd.m = m;
+                    bd.wb_first = bb * wbt;
+                    bd.wb_count = std::min(wbt, d.nwb - bd.wb_first);
+                    bd.slot = m * bpd + bb;
+                    blk_t_h.push_back(bd);
+                }
+            }
+            blk_t += dt.nblk;
+            part_t += (long long)dt.nblk * 2 * d.ns;
+            atm_t[a] = dt;
+        }
         blk += d.nblk;
         coef += (long long)h->M * d.nwb * d.bstride;
         qt += (long long)h->M * d.nwb * d.G;
@@ -465,41 +493,51 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     h->n_blocks = blk;
     // longest blocks first (work ~ wave-batches x chunk length, the same
     // lane count per batch); ties keep slab order
-    std::stable_sort(h->blk_h.begin(), h->blk_h.end(), [&](const BlockDesc &x, const BlockDesc &y) {
-        return (long long)x.wb_count * h->atm_h[x.atm].Leff >
-               (long long)y.wb_count * h->atm_h[y.atm].Leff;
-    });
-    {
-        // XCD-aware order: workgroups are handed to the 8 XCDs in turn by
-        // index, and the blocks of one slab stage the same sources, so each
-        // slab's run of blocks goes to one XCD (indices 8 apart, one L2) and
-        // consecutive runs to consecutive XCDs -- the longest-first order
-        // kept per group of 8 runs.  Applied when the runs fill the XCDs
-        // evenly (equal-size runs, a multiple of 8 of them).
-        constexpr int kXcd = 8;
-        std::vector<std::vector<BlockDesc>> q(kXcd);
-        size_t i = 0;
-        int run = 0;
-        while (i < h->blk_h.size()) {
-            size_t j = i;
-            while (j < h->blk_h.size() && h->blk_h[j].atm == h->blk_h[i].atm) ++j;
-            for (size_t k = i; k < j; ++k) q[run % kXcd].push_back(h->blk_h[k]);
-            ++run;
-            i = j;
+    auto order_blocks = [&](std::vector<BlockDesc> &list) {
+        std::stable_sort(list.begin(), list.end(), [&](const BlockDesc &x, const BlockDesc &y) {
+            return (long long)x.wb_count * h->atm_h[x.atm].Leff >
+                   (long long)y.wb_count * h->atm_h[y.atm].Leff;
+        });
+        {
+            // XCD-aware order: workgroups are handed to the 8 XCDs in turn by
+            // index, and the blocks of one slab stage the same sources, so each
+            // slab's run of blocks goes to one XCD (indices 8 apart, one L2) and
+            // consecutive runs to consecutive XCDs -- the longest-first order
+            // kept per group of 8 runs.  Applied when the runs fill the XCDs
+            // evenly (equal-size runs, a multiple of 8 of them).
+            constexpr int kXcd = 8;
+            std::vector<std::vector<BlockDesc>> q(kXcd);
+            size_t i = 0;
+            int run = 0;
+            while (i < list.size()) {
+                size_t j = i;
+                while (j < list.size() && list[j].atm == list[i].atm) ++j;
+                for (size_t k = i; k < j; ++k) q[run % kXcd].push_back(list[k]);
+                ++run;
+                i = j;
+            }
+            bool even = true;
+            for (int x = 1; x < kXcd; ++x) even = even && q[x].size() == q[0].size();
+            if (even && !q[0].empty()) {
+                std::vector<BlockDesc> out;
+                out.reserve(list.size());
+                for (size_t k = 0; k < q[0].size(); ++k)
+                    for (int x = 0; x < kXcd; ++x) out.push_back(q[x][k]);
+                list.swap(out);
+            }
         }
-        bool even = true;
-        for (int x = 1; x < kXcd; ++x) even = even && q[x].size() == q[0].size();
-        if (even && !q[0].empty()) {
-            std::vector<BlockDesc> out;
-            out.reserve(h->blk_h.size());
-            for (size_t k = 0; k < q[0].size(); ++k)
-                for (int x = 0; x < kXcd; ++x) out.push_back(q[x][k]);
-            h->blk_h.swap(out);
-        }
+    };
+    order_blocks(h->blk_h);
+    // the tail plan only where it differs (not for the three-point solver,
+    // whose operator does not use the sweep blocks)
+    const bool tail_plan = blk_t != blk && h->fs != RT_FS_DELO_PARABOLIC;
+    if (tail_plan) {
+        order_blocks(blk_t_h);
+        h->n_blocks_tail = blk_t;
     }
     h->n_qt = qt;
     h->n_pairs = coef;
-    h->n_partial = part;
+    h->n_partial = tail_plan ? std::max(part, part_t) : part;
     h->n_dense = dense;
     h->n_ew = ew;
 
@@ -554,6 +592,12 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     RT_TRY(h2d(h->d_pt_atm, pt_atm.data(), acc));
     RT_TRY(h2d(h->d_atm, h->atm_h.data(), h->n_atm));
     RT_TRY(h2d(h->d_blk, h->blk_h.data(), h->n_blocks));
+    if (tail_plan) {
+        RT_TRY(dalloc(&h->d_atm_tail, h->n_atm));
+        RT_TRY(dalloc(&h->d_blk_tail, h->n_blocks_tail));
+        RT_TRY(h2d(h->d_atm_tail, atm_t.data(), h->n_atm));
+        RT_TRY(h2d(h->d_blk_tail, blk_t_h.data(), h->n_blocks_tail));
+    }
 
     // ---- precompute: ray constants, tile coefficients, D and D^-1, b
     hipStream_t s = nullptr;

@@ -114,6 +114,12 @@ __host__ __device__ inline int lane_slot(int lane, int C) {
 // get identity-padded chunks rather than fewer of them, so the sweep has one
 // lane layout per chunk count it is compiled for).
 constexpr int kMinChunks = 8;
+// The tail plan: GMRES cycles that start with at most kTailSlabs slabs still
+// iterating sweep with at most kTailWb wave-batches per wave, so those slabs
+// spread over more workgroups (the main plan, made for the whole batch, gives
+// a long slab one workgroup per direction).
+constexpr int kTailSlabs = 64;
+constexpr int kTailWb = 8;
 
 // Chunk lengths compiled for a plan of longest chunk L: L/2+1 .. L for L <= 8,
 // L/2 + L/8, L/2 + 2L/8, .. L for L >= 16.  A slab's chunk length is
@@ -203,6 +209,11 @@ struct rt_handle {
     int NB = 1;                // wave-batches per wave (per block: W * NB)
     int n_blocks = 0;
     long long n_pairs = 0, n_partial = 0;
+    // the tail plan over the same coefficient tiles (none when it would equal
+    // the main plan); plan_tail selects it for the sweeps, their finalize pass
+    // and the fused Arnoldi step, which all read the slab table it points to
+    int n_blocks_tail = 0;
+    bool plan_tail = false;
 
     // device copies of the problem
     double *d_tau = nullptr, *d_B = nullptr, *d_opac = nullptr, *d_phi = nullptr;
@@ -210,6 +221,8 @@ struct rt_handle {
     int *d_pt_atm = nullptr;
     rt::AtmDesc *d_atm = nullptr;
     rt::BlockDesc *d_blk = nullptr;
+    rt::AtmDesc *d_atm_tail = nullptr;  // nblk, blk_first, part_off of the tail plan
+    rt::BlockDesc *d_blk_tail = nullptr;
     rt::RayConst *d_rayc = nullptr;
     double *d_q = nullptr;        // per ray quadrature weight
     double *d_qt = nullptr;       // tile-ordered, zero-padded quadrature weights
@@ -275,6 +288,16 @@ struct rt_handle {
 };
 
 namespace rt {
+
+// The slab table, block list and block count of the plan the sweeps use now.
+inline const AtmDesc *plan_atm(const rt_handle *h) {
+    return h->plan_tail ? h->d_atm_tail : h->d_atm;
+}
+inline const BlockDesc *plan_blk(const rt_handle *h) {
+    return h->plan_tail ? h->d_blk_tail : h->d_blk;
+}
+inline int plan_blocks(const rt_handle *h) { return h->plan_tail ? h->n_blocks_tail : h->n_blocks; }
+
 // sigma_out = A (scale .* sigma_in) for the slabs whose mask is set (all if
 // mask is NULL): the sweep, then the finalize pass.  mode as in SweepArgs.
 hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, double *out,

@@ -1372,11 +1372,19 @@ struct Driver {
                                accept_est ? 1 : 0);
             ok(hipGetLastError());
         };
-        const std::vector<unsigned long long> key = {
+        // the last entry is the block plan the cycle was captured with
+        std::vector<unsigned long long> key = {
             0, bits(b), bits(x), bits(st), bits(tol), (unsigned long long)maxit, fp32 ? 1ull : 0ull,
-            accept_est ? 1ull : 0ull};
+            accept_est ? 1ull : 0ull, 0};
         while (err == hipSuccess) {
-            if (count(h->d_active) == 0) break;
+            const int act = count(h->d_active);
+            if (act == 0) break;
+            // a cycle that starts with few slabs still iterating sweeps with
+            // the tail plan; the choice is made here only, so eager launches
+            // and graph replays take the same plan in every cycle
+            h->plan_tail = h->n_blocks_tail > 0 && act <= kTailSlabs;
+            a.atm = plan_atm(h);
+            key.back() = h->plan_tail ? 1 : 0;
             if (h->opt.graphs) {
                 graph(key, [&]() {
                     for (int j = 0; j < m; ++j) arnoldi_step(a, j, fp32);
@@ -1390,6 +1398,7 @@ struct Driver {
                 tail();
             }
         }
+        h->plan_tail = false;
     }
 
     void bicgstab(const double *b, double *x, KState *st, double tol, int maxit) {

@@ -371,6 +371,38 @@ def test_batched_gmres_per_slab_status():
     assert oracle_relres(sub, x).max() < 1e-9
 
 
+def _c4_subset(step):
+    p = W.config4(n_slabs=512)
+    sel = list(range(0, 512, step))
+    sub = W.make_slabs([int(p.ns[i]) for i in sel],
+                       [(p.tau[p.offsets[i]], p.tau[p.offsets[i + 1] - 1]) for i in sel],
+                       p.n_mu, p.n_nu, 10.0, [0.0] * len(sel), list(p.eps[sel]), list(p.W2[sel]))
+    return sub.with_(phi=p.phi[sel].copy(), opac=p.opac[sel].copy())
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_gmres_tail_plan(mixed):
+    """A GMRES cycle that starts with at most 64 slabs iterating sweeps with
+    the tail plan (at most 8 wave-batches per wave, more workgroups per
+    slab, the same coefficient tiles).  14 slabs of the 512-slab batch (Ns up
+    to 512, 16 mu x 101 nu) take it from the first cycle; with the plan fixed
+    by the caller (wave_batches) every cycle keeps the one plan.  Both reach
+    the oracle's residual with iteration counts within rounding of each
+    other."""
+    sub = _c4_subset(37)
+    prec = B.RT_PREC_MIXED if mixed else B.RT_PREC_FP64
+    out = {}
+    for fixed in (False, True):
+        kw = {"wave_batches": 26} if fixed else {}
+        with B.setup(sub, rtol=1e-9, maxit=20000, precision=prec, **kw) as h:
+            rc, info, x = _solve(h, "gmres", sub)
+        assert all(i.status == "converged" for i in info), (fixed, info)
+        assert oracle_relres(sub, x).max() < 1e-9, fixed
+        out[fixed] = [i.iterations for i in info]
+    for a, b in zip(out[False], out[True]):
+        assert abs(a - b) <= max(2, b // 20), out
+
+
 def test_paper_richardson_counts_on_gpu():
     """The GPU's Jacobi-Richardson reproduces the paper's printed counts
     (tab:jacobi, Richardson row; printed value = updates + 1)."""
