@@ -118,7 +118,7 @@ constexpr int kMinChunks = 8;
 // iterating sweep with at most kTailWb wave-batches per wave, so those slabs
 // spread over more workgroups (the main plan, made for the whole batch, gives
 // a long slab one workgroup per direction).
-constexpr int kTailSlabs = 64;
+constexpr int kTailSlabs = 128;
 constexpr int kTailWb = 8;
 
 // Chunk lengths compiled for a plan of longest chunk L: L/2+1 .. L for L <= 8,

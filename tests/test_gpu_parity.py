@@ -382,7 +382,7 @@ def _c4_subset(step):
 
 @pytest.mark.parametrize("mixed", [False, True])
 def test_gmres_tail_plan(mixed):
-    """A GMRES cycle that starts with at most 64 slabs iterating sweeps with
+    """A GMRES cycle that starts with at most 128 slabs iterating sweeps with
     the tail plan (at most 8 wave-batches per wave, more workgroups per
     slab, the same coefficient tiles).  14 slabs of the 512-slab batch (Ns up
     to 512, 16 mu x 101 nu) take it from the first cycle; with the plan fixed
