@@ -146,7 +146,10 @@ typedef struct rt_problem {
  *  chunk       formal-solver sweep chunk length: 0 = choose automatically,
  *              else one of 4, 8, 16, 32
  *  wave_batches  ray batches each wavefront of the sweep handles in turn:
- *              0 = choose automatically, else 1..64
+ *              0 = choose automatically, else 1..64.  When automatic, a
+ *              GMRES cycle that starts with at most 128 slabs iterating
+ *              sweeps with at most 8 per wavefront (more workgroups per
+ *              slab); a fixed value holds for every cycle
  *  prefetch    step coefficients of the next ray batch loaded while the
  *              current one is swept: 0 = automatic, 1 = no, 2 or 3 = yes
  *              (yes is available for chunk lengths up to 8)
