@@ -324,6 +324,33 @@ def test_graph_replays_match_eager_launches(kind, mixed):
                 assert np.array_equal(host(y), host(h.apply_op(v)))
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_graph_replays_tail_plan(mixed):
+    """GMRES cycles on the tail plan (14 slabs of the 512-slab batch, fewer
+    than 128 iterating from the first cycle) captured in graphs and replayed
+    match eager launches bit for bit, and the operator applied after a solve
+    (main plan again) matches the one applied before it."""
+    sub = _c4_subset(37)
+    kw = dict(rtol=1e-9, maxit=20000)
+    if mixed:
+        kw["precision"] = B.RT_PREC_MIXED
+    v = dev(W.random_vector(sub.n_unknowns, 4))
+    with B.setup(sub, graphs=0, **kw) as h:
+        y0 = host(h.apply_op(v))
+        rc, info, xr = _solve(h, "gmres", sub)
+        itr = [i.iterations for i in info]
+        assert np.array_equal(host(h.apply_op(v)), y0)
+    with B.setup(sub, graphs=1, **kw) as h:
+        x0 = dev(W.initial_guess(sub))
+        x = torch.empty_like(x0)
+        for rep in range(2):
+            x.copy_(x0)
+            rc, info = h.solve_gmres(x)
+            assert [i.iterations for i in info] == itr, rep
+            assert np.array_equal(host(x), xr), (rep, np.abs(host(x) - xr).max())
+            assert np.array_equal(host(h.apply_op(v)), y0), rep
+
+
 def test_richardson_config2_delo():
     p = W.config2()
     with B.setup(p, rtol=1e-10, maxit=200000) as h:
