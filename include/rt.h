@@ -75,6 +75,28 @@ extern "C" {
 #define RT_PC_SOR 1
 #define RT_PC_SSOR 2
 
+/* Where the formal-solver sweep takes each ray-interval's step coefficients
+ * from (rt_options.coef_mode).  Every formal solver here steps the deviation
+ * D = I - S as D_k = E D_u + w (S_u - S_k) with w = (1 - E) / d, d the optical
+ * step r_p |tau_k - tau_u| / |mu| (Sect. 4.1).
+ *  RT_COEF_PAIRS      (E, w) per ray-interval, built at setup in FP64 and
+ *                     FP32, streamed by every application (16 or 8 bytes);
+ *  RT_COEF_STREAM_W   w alone streamed (8 or 4 bytes), E = 1 - w d derived
+ *                     from d = kappa dtau, kappa = r_p / |mu| per ray and
+ *                     dtau per interval;
+ *  RT_COEF_RECOMPUTE  E and w both computed in the sweep from d (one
+ *                     exponential per ray-interval for DELO-linear, one
+ *                     reciprocal for the trapezoidal rule and implicit Euler);
+ *  RT_COEF_RECOMPUTE_FP32  FP32 sweeps recompute, FP64 sweeps stream w;
+ *  RT_COEF_AUTO       the library's choice (RT_COEF_STREAM_W).
+ * Results agree to rounding between modes.  Setup builds only the tiles
+ * the handle's modes stream. */
+#define RT_COEF_AUTO 0
+#define RT_COEF_PAIRS 1
+#define RT_COEF_STREAM_W 2
+#define RT_COEF_RECOMPUTE 3
+#define RT_COEF_RECOMPUTE_FP32 4
+
 /* Largest supported depth grid per slab, and largest GMRES restart length. */
 #define RT_MAX_NS 2048
 #define RT_MAX_RESTART 128
@@ -173,6 +195,8 @@ typedef struct rt_problem {
  *              first solve, (2 ns)^2 doubles per slab, kept by the handle)
  *  omega       relaxation of SOR and SSOR, 0 < omega < 2 (1; the paper uses
  *              1.5 for Richardson, 1 for the Krylov methods)
+ *  coef_mode   where the sweep takes its step coefficients from: one of the
+ *              RT_COEF_* values above (RT_COEF_AUTO)
  */
 typedef struct rt_options {
     int precision;
@@ -190,6 +214,7 @@ typedef struct rt_options {
     int graphs;
     int precond;
     double omega;
+    int coef_mode;
 } rt_options;
 
 /* Per-slab outcome of a solve. */

@@ -54,6 +54,14 @@ int rt_plan_info(const rt_handle *h, int *chunk_L, int *n_blocks, long long *n_p
 int rt_sweep_config(const rt_handle *h, int fp32, int *waves, int *prefetch);
 
 /*
+ * Where the FP32 (fp32 != 0) or FP64 sweep of this handle takes its step
+ * coefficients from, as resolved from options.coef_mode at setup: 0 = (E, w)
+ * pairs streamed, 1 = w streamed and E derived, 2 = both computed in the
+ * sweep.  Host only.
+ */
+int rt_sweep_coef_mode(const rt_handle *h, int fp32, int *mode);
+
+/*
  * Number of doubles of the assembled operator: the sum over slabs of
  * (2 ns)^2.  Host only.
  */

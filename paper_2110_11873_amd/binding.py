@@ -22,6 +22,8 @@ RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_ENOCONV, RT_EBREAKDOWN = 0, -1, -2, 
 RT_FS_DELO_LINEAR, RT_FS_TRAPEZOIDAL, RT_FS_IMPLICIT_EULER, RT_FS_DELO_PARABOLIC = 0, 1, 2, 3
 RT_PREC_FP64, RT_PREC_MIXED = 0, 1
 RT_PC_JACOBI, RT_PC_SOR, RT_PC_SSOR = 0, 1, 2
+RT_COEF_AUTO, RT_COEF_PAIRS, RT_COEF_STREAM_W, RT_COEF_RECOMPUTE, RT_COEF_RECOMPUTE_FP32 = \
+    0, 1, 2, 3, 4
 RT_MAX_NS = 2048
 RT_MAX_RESTART = 128
 STATUS_NAMES = {RT_OK: "converged", RT_ENOCONV: "maxit", RT_EBREAKDOWN: "breakdown"}
@@ -31,7 +33,7 @@ EXPORTS = ["rt_default_options", "rt_setup", "rt_destroy", "rt_num_unknowns", "r
            "rt_precond_jacobi", "rt_get_rhs", "rt_get_jacobi_diag", "rt_solve_gmres",
            "rt_solve_bicgstab", "rt_solve_richardson", "rt_solve_cgs", "rt_last_error",
            "rt_apply_op_fp32",
-           "rt_plan_info", "rt_sweep_config", "rt_validate", "rt_assembled_size", "rt_assemble",
+           "rt_plan_info", "rt_sweep_config", "rt_sweep_coef_mode", "rt_validate", "rt_assembled_size", "rt_assemble",
            "rt_precond_apply", "rt_solve_lu", "rt_field_size", "rt_apply_op_field",
            "rt_get_rhs_field", "rt_sigma_from_field", "rt_solve_field_gmres",
            "rt_set_redistribution", "rt_prd_size", "rt_apply_op_prd", "rt_apply_op_prd_bf16x3", "rt_get_rhs_prd",
@@ -62,7 +64,7 @@ class rt_options(C.Structure):
         ("inner_rtol", C.c_double), ("inner_maxit", C.c_int), ("max_outer", C.c_int),
         ("chunk", C.c_int), ("wave_batches", C.c_int), ("prefetch", C.c_int),
         ("check_every", C.c_int), ("sweep_waves", C.c_int), ("graphs", C.c_int),
-        ("precond", C.c_int), ("omega", C.c_double),
+        ("precond", C.c_int), ("omega", C.c_double), ("coef_mode", C.c_int),
     ]
 
 
@@ -101,6 +103,7 @@ def lib():
         L.rt_plan_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                    C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         L.rt_sweep_config.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.rt_sweep_coef_mode.argtypes = [vp, C.c_int, C.POINTER(C.c_int)]
         L.rt_validate.argtypes = [C.POINTER(rt_problem), C.POINTER(rt_options)]
         L.rt_assembled_size.argtypes = [vp, C.POINTER(C.c_longlong)]
         L.rt_field_size.argtypes = [vp, C.POINTER(C.c_longlong)]
@@ -263,15 +266,19 @@ class Handle:
         return dict(chunk=L.value, blocks=nb.value, pairs=npairs.value, intervals=nint.value)
 
     def sweep_config(self, fp32=False):
-        w, pf = C.c_int(), C.c_int()
+        """Waves per sweep workgroup, prefetch (0/1) and the coefficient mode
+        (0 pairs streamed, 1 w streamed, 2 computed in the sweep)."""
+        w, pf, cm = C.c_int(), C.c_int(), C.c_int()
         _check(lib().rt_sweep_config(self._h, 1 if fp32 else 0, C.byref(w), C.byref(pf)))
-        return dict(waves=w.value, prefetch=pf.value)
+        _check(lib().rt_sweep_coef_mode(self._h, 1 if fp32 else 0, C.byref(cm)))
+        return dict(waves=w.value, prefetch=pf.value, coef_mode=cm.value)
 
     def sweep_kernel_name(self, fp32=False):
         """The sweep kernel rt_apply_op(_fp32) launches, as profilers name it."""
         c = self.sweep_config(fp32)
-        return "rt::sweep::sweep_kernel<%s, %d, %d, %d>" % (
-            "float" if fp32 else "double", self.plan_info()["chunk"], c["waves"], c["prefetch"])
+        return "rt::sweep::sweep_kernel<%s, %d, %d, %d, %d>" % (
+            "float" if fp32 else "double", self.plan_info()["chunk"], c["waves"], c["prefetch"],
+            c["coef_mode"])
 
     # -- frequency redistribution -------------------------------------------------
     def set_redistribution(self, R):

@@ -18,7 +18,9 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "librt.so")
-SOURCES = ["rt_api.hip", "rt_sweep.hip", "rt_sweep_f32.hip", "rt_sweep_f64.hip", "rt_krylov.hip",
+SOURCES = ["rt_api.hip", "rt_sweep.hip", "rt_sweep_f32.hip", "rt_sweep_f64.hip",
+           "rt_sweep_f32_w.hip", "rt_sweep_f64_w.hip", "rt_sweep_f32_rc.hip", "rt_sweep_f64_rc.hip",
+           "rt_krylov.hip",
            "rt_assemble.hip", "rt_dense.hip", "rt_raysweep.hip", "rt_field.hip",
            "rt_fieldsolve.hip", "rt_prd.hip"]
 OBJDIR = os.path.join(PKG, "_build")

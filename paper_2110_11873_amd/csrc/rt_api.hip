@@ -153,8 +153,24 @@ int validate(const rt_problem *p, const rt_options *o, std::vector<double> &mu_p
             return fail(RT_EINVAL, "options.precond must be RT_PC_JACOBI, RT_PC_SOR or RT_PC_SSOR");
         if (!(o->omega > 0.0 && o->omega < 2.0))
             return fail(RT_EINVAL, "options.omega must lie in (0, 2)");
+        if (o->coef_mode < RT_COEF_AUTO || o->coef_mode > RT_COEF_RECOMPUTE_FP32)
+            return fail(RT_EINVAL, "options.coef_mode must be one of the RT_COEF_* values");
     }
     return RT_OK;
+}
+
+// Coefficient modes (kCoef*) of the FP64 and FP32 sweeps for options.coef_mode.
+void resolve_coef_modes(int coef_mode, int *cm64, int *cm32) {
+    switch (coef_mode) {
+        case RT_COEF_PAIRS: *cm64 = *cm32 = kCoefPairs; return;
+        case RT_COEF_RECOMPUTE: *cm64 = *cm32 = kCoefRecompute; return;
+        case RT_COEF_RECOMPUTE_FP32:
+            *cm64 = kCoefW;
+            *cm32 = kCoefRecompute;
+            return;
+        default:  // RT_COEF_STREAM_W and RT_COEF_AUTO
+            *cm64 = *cm32 = kCoefW;
+    }
 }
 
 int chunks_for(int ns, int L) {
@@ -219,8 +235,13 @@ static SweepArgs sweep_args(rt_handle *h, const double *in, const double *scale,
     SweepArgs a{};
     a.atm = plan_atm(h);
     a.blk = plan_blk(h);
-    a.coef = fp32 ? (const void *)h->d_coef32 : (const void *)h->d_coef64;
+    const int cm = coef_mode_of(h, fp32);
+    a.coef = cm == kCoefPairs ? (fp32 ? (const void *)h->d_coef32 : (const void *)h->d_coef64)
+                              : (fp32 ? (const void *)h->d_w32 : (const void *)h->d_w64);
     a.q = h->d_qt;
+    a.kt = h->d_kt;
+    a.dtau = h->d_dtau;
+    a.fs = h->fs;
     a.dirc = h->d_dirc;
     a.Qs = h->d_Qs;
     a.sig_in = in;
@@ -239,7 +260,8 @@ hipError_t apply_sweep(rt_handle *h, const double *in, const double *scale, cons
     int W;
     bool pf;
     sweep_config(h, fp32, &W, &pf);
-    return launch_sweep(h->L, W, pf, fp32, a, plan_blocks(h), h->ns_max, s);
+    return launch_sweep(h->L, W, pf, fp32, coef_mode_of(h, fp32), a, plan_blocks(h), h->ns_max,
+                        s);
 }
 
 hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, double *out,
@@ -249,7 +271,8 @@ hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, d
     int W;
     bool pf;
     sweep_config(h, fp32, &W, &pf);
-    hipError_t e = launch_sweep(h->L, W, pf, fp32, a, plan_blocks(h), h->ns_max, s);
+    hipError_t e = launch_sweep(h->L, W, pf, fp32, coef_mode_of(h, fp32), a, plan_blocks(h),
+                                h->ns_max, s);
     if (e != hipSuccess) return e;
     return launch_finalize(a, h->n_atm, h->ns_max, s);
 }
@@ -315,6 +338,7 @@ void rt_default_options(rt_options *o) {
     o->precond = RT_PC_JACOBI;
     o->omega = 1.0;
     o->check_every = 16;
+    o->coef_mode = RT_COEF_AUTO;
 }
 
 const char *rt_last_error(void) { return g_err.c_str(); }
@@ -334,7 +358,8 @@ void rt_destroy(rt_handle *h) {
                     h->d_ew,    h->d_asm_dg, h->d_asm_sc, h->d_asm_task, h->d_A,
                     h->d_pz,    h->d_ones,  h->d_LU,      h->d_piv,     h->d_sing,
                     h->d_rpart, h->d_mu_idx, h->d_fsig, h->d_Rw,   h->d_Rw_bf, h->d_prd_Jm,
-                    h->d_prd_J, h->d_prd_diag, h->d_prd_dinv};
+                    h->d_prd_J, h->d_prd_diag, h->d_prd_dinv, h->d_w64, h->d_w32, h->d_kt,
+                    h->d_dtau};
     clear_graphs(h);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
     for (hipEvent_t e : h->gev)
@@ -373,6 +398,7 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     rt_handle *h = new rt_handle();
     h->device = dev;
     h->opt = opt;
+    resolve_coef_modes(opt.coef_mode, &h->cm64, &h->cm32);
     h->n_atm = p->n_atm;
     h->n_mu = p->n_mu;
     h->M = p->n_mu / 2;
@@ -573,8 +599,22 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     RT_TRY(dalloc(&h->d_qt, (size_t)h->n_qt));
     RT_TRY(dalloc(&h->d_dirc, (size_t)h->M));
     RT_TRY(dalloc(&h->d_Qs, (size_t)h->n_atm));
-    RT_TRY(dalloc(&h->d_coef64, h->n_pairs));
-    RT_TRY(dalloc(&h->d_coef32, h->n_pairs));
+    // the coefficient tiles the handle's sweeps stream, (kappa, 1 / kappa) per
+    // ray and the depth steps for those that derive coefficients
+    if (h->cm64 == kCoefPairs) RT_TRY(dalloc(&h->d_coef64, h->n_pairs));
+    if (h->cm32 == kCoefPairs) RT_TRY(dalloc(&h->d_coef32, h->n_pairs));
+    if (h->cm64 == kCoefW) RT_TRY(dalloc(&h->d_w64, h->n_pairs));
+    if (h->cm32 == kCoefW) RT_TRY(dalloc(&h->d_w32, h->n_pairs));
+    const bool derive = h->cm64 != kCoefPairs || h->cm32 != kCoefPairs;
+    if (derive) {
+        RT_TRY(dalloc(&h->d_kt, (size_t)h->n_qt));
+        RT_TRY(dalloc(&h->d_dtau, acc));
+        std::vector<double> dtau(acc, 0.0);
+        for (int a = 0; a < h->n_atm; ++a)
+            for (int k = 0; k + 1 < h->ns[a]; ++k)
+                dtau[h->doff[a] + k] = p->tau[h->doff[a] + k + 1] - p->tau[h->doff[a] + k];
+        RT_TRY(h2d(h->d_dtau, dtau.data(), acc));
+    }
     RT_TRY(dalloc(&h->d_partial, std::max<long long>(h->n_partial, 1)));
     RT_TRY(dalloc(&h->d_diag, h->n_unk));
     RT_TRY(dalloc(&h->d_dinv, h->n_unk));
@@ -607,7 +647,7 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
                      "ray setup launch"));
     RT_TRY(hip_check(launch_coef_build(h->n_blocks, h->W, h->d_atm, h->d_blk, h->d_tau, h->d_opac,
                                        h->d_mu_pos, h->fs, h->d_q, h->d_coef64, h->d_coef32,
-                                       h->d_qt, s),
+                                       h->d_w64, h->d_w32, h->d_qt, h->d_kt, s),
                      "coefficient launch"));
     RT_TRY(hip_check(launch_diag(acc, h->d_pt_atm, h->d_atm, h->d_tau, h->d_opac, h->d_mu_pos,
                                  h->d_rayc, h->M, h->n_nu, h->fs, h->d_diag, h->d_dinv, s),
@@ -707,6 +747,12 @@ int rt_sweep_config(const rt_handle *h, int fp32, int *waves, int *prefetch) {
     sweep_config(h, fp32 != 0, &W, &pf);
     if (waves) *waves = W;
     if (prefetch) *prefetch = pf ? 1 : 0;
+    return RT_OK;
+}
+
+int rt_sweep_coef_mode(const rt_handle *h, int fp32, int *mode) {
+    if (!h || !mode) return fail(RT_EINVAL, "NULL handle or output");
+    *mode = coef_mode_of(h, fp32 != 0);
     return RT_OK;
 }
 

@@ -70,11 +70,21 @@ struct RayConst {
     double q, qt1, qt12, pad;
 };
 
+// Where the sweep takes a step's coefficients (E, w) from: both streamed
+// from the tiles, w streamed and E = 1 - w d derived, or both computed from
+// the optical step d = kappa dtau (kappa = r_p / |mu| per ray, dtau per
+// interval).
+constexpr int kCoefPairs = 0;
+constexpr int kCoefW = 1;
+constexpr int kCoefRecompute = 2;
+
 struct SweepArgs {
     const AtmDesc *atm;
     const BlockDesc *blk;
-    const void *coef;        // tile-ordered step coefficients (T pairs)
+    const void *coef;        // tile-ordered step coefficients: (E, w) pairs or w (type T)
     const double *q;         // tile-ordered quadrature weights (see q_off)
+    const double2 *kt;       // tile-ordered (kappa, 1 / kappa) per ray, as q
+    const double *dtau;      // per depth point: tau_{k+1} - tau_k (0 at a slab's last point)
     const double2 *dirc;     // per direction: (T1, T1^2 + T2^2)
     const double4 *Qs;       // per slab: sums over all rays of q, q T1, q (T1^2 + T2^2)
     const double *sig_in;    // FP64 input, NULL = zero source
@@ -89,6 +99,7 @@ struct SweepArgs {
     int rows;                // 1: one LDS row per wave (W * 2 ns_max values),
                              // 0: one shared row filled wave after wave
     int src_lds;             // byte offset of the sources in the sweep's LDS (set at launch)
+    int fs;                  // formal solver (coefficients computed in the sweep)
 };
 
 // --------------------------------------------------------------------------
@@ -133,20 +144,30 @@ int sweep_waves(int L, bool fp32);
 
 // Launch helpers (rt_sweep.hip).  launch_sweep writes the per-block partial
 // quadrature sums; launch_finalize turns them into sigma_out.
-hipError_t launch_sweep(int L, int W, bool pf, bool fp32, const SweepArgs &a, int nblocks,
-                        int ns_max, hipStream_t s);
-hipError_t launch_sweep_f32(int L, int W, bool pf, const SweepArgs &a, int nblocks, int ns_max,
-                            hipStream_t s);
-hipError_t launch_sweep_f64(int L, int W, bool pf, const SweepArgs &a, int nblocks, int ns_max,
-                            hipStream_t s);
+hipError_t launch_sweep(int L, int W, bool pf, bool fp32, int cm, const SweepArgs &a,
+                        int nblocks, int ns_max, hipStream_t s);
+#define RT_SWEEP_LAUNCHER(name)                                                              \
+    hipError_t name(int L, int W, bool pf, const SweepArgs &a, int nblocks, int ns_max, \
+                    hipStream_t s)
+RT_SWEEP_LAUNCHER(launch_sweep_f32);
+RT_SWEEP_LAUNCHER(launch_sweep_f64);
+RT_SWEEP_LAUNCHER(launch_sweep_f32_w);
+RT_SWEEP_LAUNCHER(launch_sweep_f64_w);
+RT_SWEEP_LAUNCHER(launch_sweep_f32_rc);
+RT_SWEEP_LAUNCHER(launch_sweep_f64_rc);
+#undef RT_SWEEP_LAUNCHER
+// The coefficient mode (kCoef*) of a handle's FP32 or FP64 sweeps.
+int coef_mode_of(const rt_handle *h, bool fp32);
 // Launch configuration of the sweep for a handle: waves per block and whether
 // the next ray batch is loaded during the current one.
 void sweep_config(const rt_handle *h, bool fp32, int *W, bool *pf);
 hipError_t launch_finalize(const SweepArgs &a, int n_atm, int ns_max, hipStream_t s);
+// Tile-ordered step coefficients of the modes that stream them (any output
+// may be NULL: not built), the tile-ordered weights and (kappa, 1 / kappa).
 hipError_t launch_coef_build(int nblocks, int W, const AtmDesc *atm, const BlockDesc *blk,
                              const double *tau, const double *opac, const double *mu_pos, int fs,
-                             const double *qray, double2 *coef64, float2 *coef32, double *qtile,
-                             hipStream_t s);
+                             const double *qray, double2 *coef64, float2 *coef32, double *w64,
+                             float *w32, double *qtile, double2 *ktile, hipStream_t s);
 hipError_t launch_ray_setup(int n_atm, const AtmDesc *atm, const double *mu_pos,
                             const double *w_pos, int M, const double *w_nu, const double *phi,
                             int n_nu, int normalize, RayConst *rayc, double *q, double2 *dirc,
@@ -229,8 +250,15 @@ struct rt_handle {
     long long n_qt = 0;
     double2 *d_dirc = nullptr;    // per direction (T1, T1^2 + T2^2)
     double4 *d_Qs = nullptr;      // per slab quadrature moments (Q0, Q1, Q2)
+    // step coefficients of the sweeps, by coefficient mode: (E, w) pairs or w
+    // alone, in FP64 and FP32 (only those the handle's modes read are built)
     double2 *d_coef64 = nullptr;
     float2 *d_coef32 = nullptr;
+    double *d_w64 = nullptr;
+    float *d_w32 = nullptr;
+    double2 *d_kt = nullptr;      // tile-ordered (kappa, 1 / kappa) per ray
+    double *d_dtau = nullptr;     // tau_{k+1} - tau_k per depth point
+    int cm64 = 0, cm32 = 0;       // coefficient modes of the FP64 and FP32 sweeps
     double *d_partial = nullptr;
     double *d_diag = nullptr, *d_dinv = nullptr, *d_b = nullptr;
     double *d_rpart = nullptr;    // ray-per-lane sweep: per-wavefront quadrature slots

@@ -108,48 +108,56 @@ __global__ void ray_setup_kernel(const AtmDesc *atm, const double *mu_pos, const
 // Tile-ordered coefficients.  The lane `lane` of wave-batch b of direction m
 // holds chunk c = lane_chunk(lane, C) of ray p = b*G + g, g = lane_slot(lane,
 // C); the chunk starts at interval s0 = c (Leff - 1) + min(c, nlong) and has
-// Leff intervals if c < nlong, else Leff - 1.  The pair (E, w) of its step i
-// lives at
+// Leff intervals if c < nlong, else Leff - 1.  The coefficients of its step i
+// live at
 //   coef_off + (m * nwb + b) * bstride + i * 64 + lane          (i < Leff - 1)
 //   coef_off + (m * nwb + b) * bstride + (Leff - 1) * 64 + g * nlong + c
 //                                                       (i = Leff - 1, c < nlong)
-// so a wavefront reads each step as 64 consecutive pairs, and the last step
-// only for the chunks that have one.  Padding (frequencies beyond the last,
-// intervals beyond ns - 2) is (1, 1): the step leaves I unchanged, and the
-// source beyond the slab is zero.  The rays' quadrature weights are laid out
-// by slot (q_off + (m*nwb + b)*G + slot), zero for padding rays, so the sweep
-// never masks a loaded value.
+// so a wavefront reads each step as 64 consecutive entries, and the last step
+// only for the chunks that have one.  An entry is the pair (E, w) or w alone
+// (the sweep then derives E = 1 - w d).  Padding (frequencies beyond the
+// last, intervals beyond ns - 2) is E = w = 1: the step leaves I unchanged,
+// and the source beyond the slab is zero.  The rays' quadrature weights and
+// (kappa, 1 / kappa) are laid out by slot (q_off + (m*nwb + b)*G + slot),
+// zero for padding rays, so the sweep never masks a loaded value.
 // --------------------------------------------------------------------------
 __global__ void coef_build_kernel(int W, const AtmDesc *atm, const BlockDesc *blk,
                                   const double *tau, const double *opac, const double *mu_pos,
                                   int fs, const double *qray, double2 *coef64, float2 *coef32,
-                                  double *qtile) {
+                                  double *w64, float *w32, double *qtile, double2 *ktile) {
     const BlockDesc bd = blk[blockIdx.x];
     const AtmDesc at = atm[bd.atm];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int c = lane_chunk(lane, at.C), g = lane_slot(lane, at.C);
     const int s0 = c * (at.Leff - 1) + min(c, at.nlong);
     const bool longc = c < at.nlong;
+    const bool any = coef64 || coef32 || w64 || w32;
     for (int b = bd.wb_first + wave; b < bd.wb_first + bd.wb_count; b += W) {
         const int p = b * at.G + g;
-        if (c == 0)  // quadrature weight of the ray, zero for padding rays
-            qtile[at.q_off + ((long long)bd.m * at.nwb + b) * at.G + g] =
-                (p < at.n_nu) ? qray[at.ray_off + (long long)bd.m * at.n_nu + p] : 0.0;
+        const double kap =
+            (p < at.n_nu) ? opac[(long long)bd.atm * at.n_nu + p] / mu_pos[bd.m] : 0.0;
+        if (c == 0) {  // per ray: weight, kappa and 1 / kappa (zero for padding rays)
+            const long long r = at.q_off + ((long long)bd.m * at.nwb + b) * at.G + g;
+            qtile[r] = (p < at.n_nu) ? qray[at.ray_off + (long long)bd.m * at.n_nu + p] : 0.0;
+            if (ktile) ktile[r] = make_double2(kap, (p < at.n_nu) ? 1.0 / kap : 0.0);
+        }
+        if (!any) continue;
         for (int i = 0; i < at.Leff; ++i) {
             const bool last = i == at.Leff - 1;
             if (last && !longc) continue;
             const int j = s0 + i;
             double E = 1.0, w = 1.0;
             if (p < at.n_nu && j < at.ns - 1) {
-                const double kap = opac[(long long)bd.atm * at.n_nu + p] / mu_pos[bd.m];
                 const double d = kap * (tau[at.doff + j + 1] - tau[at.doff + j]);
                 step_ew(fs, d, E, w);
             }
             const long long e = at.coef_off + ((long long)bd.m * at.nwb + b) * at.bstride +
                                 (last ? (long long)(at.Leff - 1) * kWave + g * at.nlong + c
                                       : (long long)i * kWave + lane);
-            coef64[e] = make_double2(E, w);
-            coef32[e] = make_float2((float)E, (float)w);
+            if (coef64) coef64[e] = make_double2(E, w);
+            if (coef32) coef32[e] = make_float2((float)E, (float)w);
+            if (w64) w64[e] = w;
+            if (w32) w32[e] = (float)w;
         }
     }
 }
@@ -299,20 +307,32 @@ bool sweep_chunk_supported(int L, bool fp32) {
     return L == 4 || L == 8 || L == 16 || L == 32;
 }
 
-hipError_t launch_sweep(int L, int W, bool pf, bool fp32, const SweepArgs &a, int nblocks,
-                        int ns_max, hipStream_t s) {
+hipError_t launch_sweep(int L, int W, bool pf, bool fp32, int cm, const SweepArgs &a,
+                        int nblocks, int ns_max, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
-    return fp32 ? launch_sweep_f32(L, W, pf, a, nblocks, ns_max, s)
-                : launch_sweep_f64(L, W, pf, a, nblocks, ns_max, s);
+    switch (cm) {
+        case kCoefPairs:
+            return fp32 ? launch_sweep_f32(L, W, pf, a, nblocks, ns_max, s)
+                        : launch_sweep_f64(L, W, pf, a, nblocks, ns_max, s);
+        case kCoefW:
+            return fp32 ? launch_sweep_f32_w(L, W, pf, a, nblocks, ns_max, s)
+                        : launch_sweep_f64_w(L, W, pf, a, nblocks, ns_max, s);
+        case kCoefRecompute:
+            return fp32 ? launch_sweep_f32_rc(L, W, pf, a, nblocks, ns_max, s)
+                        : launch_sweep_f64_rc(L, W, pf, a, nblocks, ns_max, s);
+    }
+    return hipErrorInvalidValue;
 }
+
+int coef_mode_of(const rt_handle *h, bool fp32) { return fp32 ? h->cm32 : h->cm64; }
 
 hipError_t launch_coef_build(int nblocks, int W, const AtmDesc *atm, const BlockDesc *blk,
                              const double *tau, const double *opac, const double *mu_pos, int fs,
-                             const double *qray, double2 *coef64, float2 *coef32, double *qtile,
-                             hipStream_t s) {
+                             const double *qray, double2 *coef64, float2 *coef32, double *w64,
+                             float *w32, double *qtile, double2 *ktile, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(coef_build_kernel, dim3(nblocks), dim3(kWave * W), 0, s, W, atm, blk, tau,
-                       opac, mu_pos, fs, qray, coef64, coef32, qtile);
+                       opac, mu_pos, fs, qray, coef64, coef32, w64, w32, qtile, ktile);
     return hipGetLastError();
 }
 

@@ -1,0 +1,12 @@
+// rt_sweep_f32_rc.hip -- the fused sweep instantiated for float arithmetic,
+// step coefficients computed in the sweep.
+#include "rt_sweep_kernel.h"
+
+namespace rt {
+
+hipError_t launch_sweep_f32_rc(int L, int W, bool pf, const SweepArgs &a, int nblocks, int ns_max,
+                               hipStream_t s) {
+    return sweep::launch_any<float, kCoefRecompute>(L, W, pf, a, nblocks, ns_max, s);
+}
+
+}  // namespace rt

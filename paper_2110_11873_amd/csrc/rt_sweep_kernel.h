@@ -10,12 +10,18 @@
 // 64) and chunk length LE (one of the lengths chunk_len allows for L): every
 // loop over a chunk and every lane-scan level is straight-line code.  W: waves
 // per block.  PF: 1 = the next ray batch of a wave is loaded while the
-// current one is computed.  Each block writes the 2 ns quadrature sums of its
-// rays to its own slot of `partial`; the finalize pass adds the slots of a
-// slab in block order and applies sigma_out = z - xi [J00, W2 J20].
+// current one is computed.  CM: where a step's coefficients (E, w) come from
+// (kCoefPairs: both streamed from the tiles; kCoefW: w streamed, E = 1 - w d
+// derived; kCoefRecompute: both computed from d), d = kappa dtau the optical
+// step of the interval, kappa = r_p / |mu| per ray, dtau per interval.  Each
+// block writes the 2 ns quadrature sums of its rays to its own slot of
+// `partial`; the finalize pass adds the slots of a slab in block order and
+// applies sigma_out = z - xi [J00, W2 J20].
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "rt_internal.h"
 
@@ -50,6 +56,69 @@ __device__ inline void load_pair(__amdgpu_buffer_rsrc_t r, int voff, int soff, d
 __device__ inline double load_f64(__amdgpu_buffer_rsrc_t r, int voff) {
     const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0);
     return __hiloint2double((int)v.y, (int)v.x);
+}
+// single coefficients (the w-only tiles)
+__device__ inline void load_pair(__amdgpu_buffer_rsrc_t r, int voff, int soff, float &o) {
+    o = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ inline void load_pair(__amdgpu_buffer_rsrc_t r, int voff, int soff, double &o) {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    o = __hiloint2double((int)v.y, (int)v.x);
+}
+__device__ inline double2 load_f64x2(__amdgpu_buffer_rsrc_t r, int voff) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
+    return make_double2(__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z));
+}
+
+// --------------------------------------------------------------------------
+// Step coefficients computed in the sweep (kCoefRecompute), from the optical
+// step d of the interval and its reciprocal rd.  Every formal solver here
+// has w = (1 - E) / d:
+//   DELO-linear  E = e^{-d},               w = (1 - e^{-d}) / d;
+//   trapezoidal  E = (1 - d/2)/(1 + d/2),  w = 1 / (1 + d/2);
+//   implicit Euler E = w = 1 / (1 + d).
+// Below d = 0.1 the DELO-linear w comes from its Taylor series
+// sum_{n>=0} (-d)^n / (n+1)!, 6 terms in FP32 and 11 in FP64 (the first
+// omitted term is below 3e-10 and 3e-20 relative there).
+// --------------------------------------------------------------------------
+template <typename T>
+struct WSeries;
+template <>
+struct WSeries<float> {
+    static constexpr int n = 6;
+};
+template <>
+struct WSeries<double> {
+    static constexpr int n = 11;
+};
+struct WSeriesCoef {
+    double c[12];
+};
+constexpr WSeriesCoef make_w_series() {
+    WSeriesCoef s{};
+    double fact = 1.0;  // (n + 1)!
+    for (int n = 0; n < 12; ++n) {
+        fact *= (n + 1);
+        s.c[n] = ((n % 2 == 0) ? 1.0 : -1.0) / fact;
+    }
+    return s;
+}
+constexpr WSeriesCoef c_w_series = make_w_series();
+
+__device__ inline float exp_neg(float d) { return __expf(-d); }
+__device__ inline double exp_neg(double d) { return exp(-d); }
+__device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double recip(double x) { return 1.0 / x; }
+
+template <typename T>
+__device__ inline void delo_ew(T d, T rd, T &E, T &w) {
+    constexpr int n = WSeries<T>::n;
+    T s = (T)c_w_series.c[n - 1];
+#pragma unroll
+    for (int t = n - 2; t >= 0; --t) s = fma(s, d, (T)c_w_series.c[t]);
+    E = exp_neg(d);
+    const T big = ((T)1 - E) * rd;
+    w = d < (T)0.1 ? s : big;
 }
 
 // --------------------------------------------------------------------------
@@ -215,11 +284,13 @@ __device__ inline T from_next(T v, T old, int c) {
 
 // One wave's share of a block: the ray batches wb_first + wave + t * W of
 // direction bd.m of slab bd.atm, whose chunk count is C and chunk length LE.
-template <typename T, int LE, int C, int W, int PF>
+template <typename T, int LE, int C, int W, int PF, int CM>
 __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &bd,
                                            const AtmDesc &at, int wave, int lane, T *sacc,
                                            const T *src) {
     using P2 = typename Pair<T>::type;
+    // one tile entry: the (E, w) pair, or w alone
+    using Ent = typename std::conditional<CM == kCoefPairs, P2, T>::type;
     const int ns = at.ns;
     const int c = lane_chunk(lane, C), g = lane_slot(lane, C);
     // the chunk: first depth point s0, len = LE or LE - 1 intervals (a short
@@ -258,6 +329,21 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
     }
     const T top0 = src[0], top2 = src[1], bot0 = src[2 * (ns - 1)], bot2 = src[2 * (ns - 1) + 1];
 
+    // the optical-depth steps dtau of the chunk's intervals (and their
+    // reciprocals), for the modes that derive coefficients: zero for the
+    // zero-length step of a short chunk and for steps past the bottom, whose
+    // d = 0 makes them the identity (E = w = 1)
+    T dt[LE], rdt[LE];
+    if constexpr (CM != kCoefPairs) {
+#pragma unroll
+        for (int i = 0; i < LE; ++i) {
+            const int j = s0 + i;
+            const bool on = i < len && j < ns - 1;
+            dt[i] = on ? (T)a.dtau[at.doff + min(j, ns - 2)] : (T)0;
+            if constexpr (CM == kCoefRecompute) rdt[i] = on ? (T)1 / dt[i] : (T)0;
+        }
+    }
+
     // AU = sum_rays q (D from s00), AV = sum_rays q (D from s20), by point;
     // every ray of the block has the same direction, so the T factors are
     // applied once at the end
@@ -285,63 +371,105 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
     // next batch's loads in flight across the current batch's work.  Batch
     // and lane offsets in a register, the step offset in a scalar register.
     const int bend = bd.wb_first + bd.wb_count;
-    const int bbytes = at.bstride * (int)sizeof(P2);  // one wave-batch of pairs
-    const P2 *tiles =
-        reinterpret_cast<const P2 *>(a.coef) + at.coef_off + (long long)bd.m * at.nwb * at.bstride;
-    const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc((void *)tiles, 0, bend * bbytes, kRawBufferWord3);
-    const double *qdir = a.q + at.q_off + (long long)bd.m * at.nwb * at.G;
+    const int bbytes = at.bstride * (int)sizeof(Ent);  // one wave-batch of tile entries
+    const Ent *tiles = reinterpret_cast<const Ent *>(a.coef) + at.coef_off +
+                       (long long)bd.m * at.nwb * at.bstride;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)tiles, 0, CM == kCoefRecompute ? 0 : bend * bbytes, kRawBufferWord3);
+    const long long rdir = at.q_off + (long long)bd.m * at.nwb * at.G;
     const __amdgpu_buffer_rsrc_t qrsrc =
-        __builtin_amdgcn_make_buffer_rsrc((void *)qdir, 0, bend * at.G * 8, kRawBufferWord3);
-    const int voff = lane * (int)sizeof(P2);
+        __builtin_amdgcn_make_buffer_rsrc((void *)(a.q + rdir), 0, bend * at.G * 8, kRawBufferWord3);
+    // per ray (kappa, 1 / kappa), laid out as the weights; zero for padding rays
+    const double2 *kdir = CM == kCoefPairs ? reinterpret_cast<const double2 *>(a.q) : a.kt + rdir;
+    const __amdgpu_buffer_rsrc_t krsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)kdir, 0, CM == kCoefPairs ? 0 : bend * at.G * 16, kRawBufferWord3);
+    const int voff = lane * (int)sizeof(Ent);
     // the packed last step: short chunks read from past the descriptor's
     // range (zeros, no memory access) and take the identity below
     constexpr int kNoLoad = 1 << 30;
     const int voff_last =
-        longc ? ((LE - 1) * kWave + g * nlong + c) * (int)sizeof(P2) : kNoLoad;
+        longc ? ((LE - 1) * kWave + g * nlong + c) * (int)sizeof(Ent) : kNoLoad;
 
-    auto load_batch = [&](int b, P2 (&cn)[LE], double &qn) {
-        const int vo = voff + b * bbytes;
+    auto load_batch = [&](int b, Ent (&cn)[LE], double &qn, double2 &kn) {
+        if constexpr (CM != kCoefRecompute) {
+            const int vo = voff + b * bbytes;
 #pragma unroll
-        for (int i = 0; i + 1 < LE; ++i) load_pair(rsrc, vo, i * kWave * (int)sizeof(P2), cn[i]);
-        load_pair(rsrc, voff_last + b * bbytes, 0, cn[LE - 1]);
+            for (int i = 0; i + 1 < LE; ++i)
+                load_pair(rsrc, vo, i * kWave * (int)sizeof(Ent), cn[i]);
+            load_pair(rsrc, voff_last + b * bbytes, 0, cn[LE - 1]);
+        }
         qn = load_f64(qrsrc, (b * at.G + g) * 8);
+        if constexpr (CM == kCoefW) kn.x = load_f64(krsrc, (b * at.G + g) * 16);
+        if constexpr (CM == kCoefRecompute) kn = load_f64x2(krsrc, (b * at.G + g) * 16);
     };
 
-    auto process = [&](P2 (&cn)[LE], double qd) {
+    auto process = [&](Ent (&cn)[LE], double qd, double2 kd) {
         const T q = (T)qd;
-        if (!longc) cn[LE - 1].x = cn[LE - 1].y = (T)1;  // zero-length step
+        // the steps' (E, w)
+        T Es[LE], ws[LE];
+        if constexpr (CM == kCoefPairs) {
+#pragma unroll
+            for (int i = 0; i < LE; ++i) {
+                Es[i] = cn[i].x;
+                ws[i] = cn[i].y;
+            }
+            if (!longc) Es[LE - 1] = ws[LE - 1] = (T)1;  // zero-length step
+        } else if constexpr (CM == kCoefW) {
+            const T kap = (T)kd.x;
+#pragma unroll
+            for (int i = 0; i < LE; ++i) ws[i] = cn[i];
+            if (!longc) ws[LE - 1] = (T)1;  // zero-length step (its d is 0)
+#pragma unroll
+            for (int i = 0; i < LE; ++i) Es[i] = fma(-ws[i], kap * dt[i], (T)1);
+        } else {
+            const T kap = (T)kd.x, rkap = (T)kd.y;
+            if (a.fs == RT_FS_DELO_LINEAR) {
+#pragma unroll
+                for (int i = 0; i < LE; ++i) delo_ew(kap * dt[i], rkap * rdt[i], Es[i], ws[i]);
+            } else if (a.fs == RT_FS_TRAPEZOIDAL) {
+#pragma unroll
+                for (int i = 0; i < LE; ++i) {
+                    const T d = kap * dt[i];
+                    ws[i] = recip(fma((T)0.5, d, (T)1));
+                    Es[i] = fma(-ws[i], d, (T)1);
+                }
+            } else {  // implicit Euler
+#pragma unroll
+                for (int i = 0; i < LE; ++i) Es[i] = ws[i] = recip(fma(kap, dt[i], (T)1));
+            }
+        }
         // one pass over the chunk with zero inflow in both directions: the
-        // local deviations go into the quadrature at once, and the running
-        // transmissions Td[i] = E_0..E_i, Tu[i] = E_i..E_{LE-1} are kept for
-        // the inflow term added after the scan (the upward pass forms w dl
-        // anew, as -w dl + E D: keeping the downward products would cost
-        // 2 LE registers)
-        T Td[LE], Tu[LE];
-        T dU = (T)cn[0].y * dl0[0], dV = (T)cn[0].y * dl2[0];
-        Td[0] = (T)cn[0].x;
+        // local deviations go into the quadrature at once.  p = w (S_u - S_k)
+        // is formed once per step and source and serves both directions; the
+        // running transmissions Td[i] = E_0..E_i, Tu[i] = E_i..E_{LE-1} are
+        // kept for the inflow term added after the scan
+        T p0[LE], p2[LE], Td[LE], Tu[LE];
+#pragma unroll
+        for (int i = 0; i < LE; ++i) {
+            p0[i] = ws[i] * dl0[i];
+            p2[i] = ws[i] * dl2[i];
+        }
+        T dU = p0[0], dV = p2[0];
+        Td[0] = Es[0];
         AU[1] = fma(q, dU, AU[1]);
         AV[1] = fma(q, dV, AV[1]);
 #pragma unroll
         for (int i = 1; i < LE; ++i) {
-            const T E = (T)cn[i].x, w = (T)cn[i].y;
-            dU = fma(E, dU, w * dl0[i]);
-            dV = fma(E, dV, w * dl2[i]);
-            Td[i] = Td[i - 1] * E;
+            dU = fma(Es[i], dU, p0[i]);
+            dV = fma(Es[i], dV, p2[i]);
+            Td[i] = Td[i - 1] * Es[i];
             AU[i + 1] = fma(q, dU, AU[i + 1]);
             AV[i + 1] = fma(q, dV, AV[i + 1]);
         }
-        const T wl = (T)cn[LE - 1].y;
-        T uU = -wl * dl0[LE - 1], uV = -wl * dl2[LE - 1];
-        Tu[LE - 1] = (T)cn[LE - 1].x;
+        T uU = -p0[LE - 1], uV = -p2[LE - 1];
+        Tu[LE - 1] = Es[LE - 1];
         AU[LE - 1] = fma(q, uU, AU[LE - 1]);
         AV[LE - 1] = fma(q, uV, AV[LE - 1]);
 #pragma unroll
         for (int i = LE - 2; i >= 0; --i) {
-            const T E = (T)cn[i].x, w = (T)cn[i].y;
-            uU = fma(-w, dl0[i], E * uU);
-            uV = fma(-w, dl2[i], E * uV);
-            Tu[i] = Tu[i + 1] * E;
+            uU = fma(Es[i], uU, -p0[i]);
+            uV = fma(Es[i], uV, -p2[i]);
+            Tu[i] = Tu[i + 1] * Es[i];
             AU[i] = fma(q, uU, AU[i]);
             AV[i] = fma(q, uV, AV[i]);
         }
@@ -376,22 +504,24 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
     const int b0 = bd.wb_first + wave;
     if constexpr (PF == 0) {
         for (int b = b0; b < bend; b += W) {
-            P2 cn[LE];
+            Ent cn[LE];
             double qn;
-            load_batch(b, cn, qn);
-            process(cn, qn);
+            double2 kn = make_double2(0.0, 0.0);
+            load_batch(b, cn, qn, kn);
+            process(cn, qn, kn);
         }
     } else {
         // two register sets, each loaded one batch ahead of its use
-        P2 cA[LE], cB[LE];
+        Ent cA[LE], cB[LE];
         double qA, qB;
-        load_batch(b0, cA, qA);
+        double2 kA = make_double2(0.0, 0.0), kB = kA;
+        load_batch(b0, cA, qA, kA);
         for (int b = b0; b < bend; b += 2 * W) {
-            load_batch(b + W, cB, qB);
-            process(cA, qA);
+            load_batch(b + W, cB, qB, kB);
+            process(cA, qA, kA);
             if (b + W >= bend) break;
-            load_batch(b + 2 * W, cA, qA);
-            process(cB, qB);
+            load_batch(b + 2 * W, cA, qA, kA);
+            process(cB, qB, kB);
         }
     }
 
@@ -469,35 +599,45 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
     }
 }
 
-template <typename T, int L, int W, int PF, int LE, int C>
+template <typename T, int L, int W, int PF, int CM, int LE, int C>
 __device__ __forceinline__ void dispatch_c(const SweepArgs &a, const BlockDesc &bd,
                                            const AtmDesc &at, int wave, int lane, T *sacc,
                                            const T *src) {
     if constexpr (C <= kWave) {
         if (at.C == C) {
-            sweep_rays<T, LE, C, W, PF>(a, bd, at, wave, lane, sacc, src);
+            sweep_rays<T, LE, C, W, PF, CM>(a, bd, at, wave, lane, sacc, src);
             return;
         }
-        dispatch_c<T, L, W, PF, LE, 2 * C>(a, bd, at, wave, lane, sacc, src);
+        dispatch_c<T, L, W, PF, CM, LE, 2 * C>(a, bd, at, wave, lane, sacc, src);
     }
 }
-template <typename T, int L, int W, int PF, int LE>
+template <typename T, int L, int W, int PF, int CM, int LE>
 __device__ __forceinline__ void dispatch_le(const SweepArgs &a, const BlockDesc &bd,
                                             const AtmDesc &at, int wave, int lane, T *sacc,
                                             const T *src) {
     if constexpr (LE <= L) {
         if (at.Leff == LE) {
-            dispatch_c<T, L, W, PF, LE, kMinChunks>(a, bd, at, wave, lane, sacc, src);
+            dispatch_c<T, L, W, PF, CM, LE, kMinChunks>(a, bd, at, wave, lane, sacc, src);
             return;
         }
-        dispatch_le<T, L, W, PF, LE + chunk_len_step(L)>(a, bd, at, wave, lane, sacc, src);
+        dispatch_le<T, L, W, PF, CM, LE + chunk_len_step(L)>(a, bd, at, wave, lane, sacc, src);
     }
 }
 
+// Waves per SIMD the register allocation is held to: 5 for the FP32 body of
+// chunk length 8 that streams w (96 registers without spills, as the
+// pair-streaming body compiles to by itself; the recomputing body would
+// spill).
+template <typename T, int L, int CM>
+struct MinWaves {
+    static constexpr int value = (sizeof(T) == 4 && L == 8 && CM == kCoefW) ? 5 : 1;
+};
+
 // LDS: the quadrature rows (a.rows ? W : 1) x 2 ns_max values of type T, then
 // the slab's sources (2 ns values of type T, scaled) at byte a.src_lds.
-template <typename T, int L, int W, int PF>
-__global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
+template <typename T, int L, int W, int PF, int CM>
+__global__ __launch_bounds__(kWave *W)
+__attribute__((amdgpu_waves_per_eu(MinWaves<T, L, CM>::value, 8))) void sweep_kernel(SweepArgs a) {
     extern __shared__ unsigned char smem_raw[];
     const BlockDesc bd = a.blk[blockIdx.x];
     if (a.mask && a.mask[bd.atm] == 0) return;  // uniform over the block
@@ -523,35 +663,48 @@ __global__ __launch_bounds__(kWave *W) void sweep_kernel(SweepArgs a) {
         }
         __syncthreads();
     }
-    dispatch_le<T, L, W, PF, chunk_len_min(L)>(a, bd, at, wave, lane,
-                                               reinterpret_cast<T *>(smem_raw), src);
+    dispatch_le<T, L, W, PF, CM, chunk_len_min(L)>(a, bd, at, wave, lane,
+                                                   reinterpret_cast<T *>(smem_raw), src);
 }
 
-// Launch for one (T, L): waves per block by register footprint, LDS layout,
-// prefetch choice.
-template <typename T, int L, int W>
+// Launch for one (T, L, CM): waves per block by register footprint, LDS
+// layout, prefetch choice (compiled for the streamed pairs only).
+template <typename T, int L, int W, int CM>
 hipError_t launch_tw(SweepArgs a, bool pf, int nblocks, int ns_max, hipStream_t s) {
     const size_t row = 2 * (size_t)ns_max * sizeof(T);
     a.rows = ((W + 1) * row <= (size_t)kSweepLdsBudget) ? 1 : 0;
     a.src_lds = (int)(a.rows ? W * row : row);
     const size_t lds = a.src_lds + row;
-    if constexpr (L <= 8) {
+    if constexpr (L <= 8 && CM == kCoefPairs) {
         if (pf) {
-            hipLaunchKernelGGL((sweep_kernel<T, L, W, 1>), dim3(nblocks), dim3(kWave * W), lds, s,
-                               a);
+            hipLaunchKernelGGL((sweep_kernel<T, L, W, 1, CM>), dim3(nblocks), dim3(kWave * W), lds,
+                               s, a);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((sweep_kernel<T, L, W, 0>), dim3(nblocks), dim3(kWave * W), lds, s, a);
+    hipLaunchKernelGGL((sweep_kernel<T, L, W, 0, CM>), dim3(nblocks), dim3(kWave * W), lds, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int L>
+template <typename T, int L, int CM>
 hipError_t launch(const SweepArgs &a, int W, bool pf, int nblocks, int ns_max, hipStream_t s) {
     if constexpr (L <= 8) {
-        if (W == 8) return launch_tw<T, L, 8>(a, pf, nblocks, ns_max, s);
+        if (W == 8) return launch_tw<T, L, 8, CM>(a, pf, nblocks, ns_max, s);
     }
-    return launch_tw<T, L, 4>(a, pf, nblocks, ns_max, s);
+    return launch_tw<T, L, 4, CM>(a, pf, nblocks, ns_max, s);
+}
+
+// All chunk lengths of one (T, CM).
+template <typename T, int CM>
+hipError_t launch_any(int L, int W, bool pf, const SweepArgs &a, int nblocks, int ns_max,
+                      hipStream_t s) {
+    switch (L) {
+        case 4: return launch<T, 4, CM>(a, W, pf, nblocks, ns_max, s);
+        case 8: return launch<T, 8, CM>(a, W, pf, nblocks, ns_max, s);
+        case 16: return launch<T, 16, CM>(a, W, pf, nblocks, ns_max, s);
+        case 32: return launch<T, 32, CM>(a, W, pf, nblocks, ns_max, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace sweep
