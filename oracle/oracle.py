@@ -200,7 +200,7 @@ def weights(prob, i=0):
 # ----------------------------------------------------------------------------
 
 def apply(prob, sigma_in):
-    """sigma_out = A sigma_in over all slabs (Algorithm 1 per slab)."""
+    """sigma_out = A sigma_in = sigma_in - J Lambda T sigma_in over all slabs."""
     x = np.ascontiguousarray(sigma_in, dtype=np.float64)
     y = np.empty_like(x)
     for i, s in enumerate(_slices(prob)):

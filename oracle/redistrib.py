@@ -2,8 +2,9 @@
 
 Only the test-suite, the smoke check and the benchmark's CPU leg may import
 this module.  The unknown is sigma^K(k, p) per depth k and frequency p
-(K = 0, 2), laid out per slab as index (k * n_nu + p) * 2 + K.  Following
-the CRD operator of Algorithm 1 step by step, with the quadrature split:
+(K = 0, 2), laid out per slab as index (k * n_nu + p) * 2 + K.  The operator
+is the CRD one (A = Id - J Lambda T) with the frequency quadrature of J
+replaced by the redistribution:
 
   S_I(k, m, p) = s0(k, p) + T1(mu_m) s2(k, p),   S_Q(k, m, p) = T2(mu_m) s2(k, p);
   I, Q = the formal solution along ray (m, p) with zero incoming radiation;

@@ -9,13 +9,19 @@
  * leg of the benchmark use it.  It shares no code, header, table or constant
  * with the GPU library.
  *
- * Every function follows the paper's own order of operations:
- *   Algorithm 1 (Sect. 3.3): S = T sigma for every (k, m); then for every
- *   (m, p) a formal solution along the ray with zero incoming radiation;
- *   then the angle-frequency quadrature of eqs. (J00)/(J02); then
- *   sigma_out = sigma_in - xi * [J00, W2 J20].
- * No fusion, blocking or reordering beyond that.  Built with
- * -ffp-contract=off so every product and sum rounds as written.
+ * The operator is its definition written out: A sigma = sigma - J Lambda T
+ * sigma, three maps applied in turn and each coded on its own --
+ *   T      the source functions of every direction from sigma
+ *          (eqs. sourceI/sourceQ);
+ *   Lambda the formal solution of the transfer equation along every ray
+ *          (mu_m, nu_p) with zero incoming radiation (Sect. 3.1, 4.1),
+ *          giving the whole Stokes field I, Q;
+ *   J      the angle-frequency quadrature of eqs. (J00)/(J02) times the
+ *          scattering factors of eqs. (S00)/(S02): xi [J00, W2 J20].
+ * The right-hand side is b = J t + c with t the transmitted field.  The
+ * field is materialized between the maps (no fusion, blocking or
+ * reordering).  Built with -ffp-contract=off so every product and sum
+ * rounds as written.
  *
  * Readings of the paper taken here (each also recorded in the design notes):
  *  - tau increases downward, tau[0] at the top; mu<0 rays travel downward
@@ -256,69 +262,18 @@ void orc_weights(const orc_slab *s, double *q)
 }
 
 /* ------------------------------------------------------------------------
- * Algorithm 1: sigma_out = A sigma_in, sigma interleaved
- * [s00(z1), s20(z1), s00(z2), ...] (Sect. 3.2).
- * ---------------------------------------------------------------------- */
-int orc_apply(const orc_slab *s, const double *sin, double *sout)
-{
-    int ns = s->ns, nmu = s->nmu, nnu = s->nnu;
-    int k, m, p;
-    double xi = 1.0 - s->eps;
-    double *SI = (double *)malloc(sizeof(double) * ns * nmu);
-    double *SQ = (double *)malloc(sizeof(double) * ns * nmu);
-    double *I = (double *)malloc(sizeof(double) * ns);
-    double *Q = (double *)malloc(sizeof(double) * ns);
-    double *J0 = (double *)calloc(ns, sizeof(double));
-    double *J2 = (double *)calloc(ns, sizeof(double));
-    double *q = (double *)malloc(sizeof(double) * nmu * nnu);
-    if (!SI || !SQ || !I || !Q || !J0 || !J2 || !q) {
-        free(SI); free(SQ); free(I); free(Q); free(J0); free(J2); free(q);
-        return -1;
-    }
-    orc_weights(s, q);
-
-    /* S = T sigma_in (eqs. sourceI/sourceQ) */
-    for (k = 0; k < ns; k++) {
-        for (m = 0; m < nmu; m++) {
-            double t1, t2;
-            orc_t20(s->mu[m], &t1, &t2);
-            SI[m * ns + k] = sin[2 * k] + t1 * sin[2 * k + 1];
-            SQ[m * ns + k] = t2 * sin[2 * k + 1];
-        }
-    }
-
-    /* I = Lambda S with zero incoming radiation; quadrature into J */
-    for (m = 0; m < nmu; m++) {
-        double t1, t2;
-        int upward = s->mu[m] > 0.0;
-        orc_t20(s->mu[m], &t1, &t2);
-        for (p = 0; p < nnu; p++) {
-            double kappa = s->opac[p] / fabs(s->mu[m]);
-            double w = q[m * nnu + p];
-            orc_ray(ns, s->tau, kappa, upward, s->fs, SI + m * ns, 0.0, I);
-            orc_ray(ns, s->tau, kappa, upward, s->fs, SQ + m * ns, 0.0, Q);
-            for (k = 0; k < ns; k++) {
-                J0[k] += w * I[k];
-                J2[k] += w * (t1 * I[k] + t2 * Q[k]);
-            }
-        }
-    }
-
-    for (k = 0; k < ns; k++) {
-        sout[2 * k] = sin[2 * k] - xi * J0[k];
-        sout[2 * k + 1] = sin[2 * k + 1] - xi * s->W2 * J2[k];
-    }
-    free(SI); free(SQ); free(I); free(Q); free(J0); free(J2); free(q);
-    return 0;
-}
-
-/* ------------------------------------------------------------------------
- * The alternative formulation with the Stokes field as unknown (eq.
- * crd_linear_system2): (Id - Lambda T J) I = Lambda T c + t, and sigma =
- * J I + c.  Field index ((st * nmu + m) * nnu + p) * ns + k, st = 0 for I,
- * 1 for Q.  J maps the field to xi [J00, W2 J20] (eqs. J00/J02, S00/S02),
- * T the multipolar components to the source functions, Lambda is the formal
- * solution with zero incoming radiation, t the transmitted field.
+ * The three maps of A = Id - J Lambda T (Sect. 3.2).  A field holds the
+ * Stokes I and Q of every ray at every depth, index
+ * ((st * nmu + m) * nnu + p) * ns + k, st = 0 for I, 1 for Q.
+ *   field_J:          sig = xi [J00, W2 J20] of a field (eqs. J00/J02,
+ *                     S00/S02);
+ *   field_from_sigma: F = Lambda T sig, the formal solution of every ray
+ *                     with the source functions of sig (eqs.
+ *                     sourceI/sourceQ), plus the transmitted field t when
+ *                     with_t is set (I_bot entering at the bottom for
+ *                     mu > 0, nothing at the top, Q = 0).
+ * The same maps give the formulation with the field as unknown (eq.
+ * crd_linear_system2): (Id - Lambda T J) I = Lambda T c + t, sigma = J I + c.
  * ---------------------------------------------------------------------- */
 static void field_J(const orc_slab *s, const double *q, const double *F, double *sig)
 {
@@ -370,6 +325,27 @@ static int field_from_sigma(const orc_slab *s, const double *sig, int with_t, do
     }
     free(SI); free(SQ);
     return 0;
+}
+
+/* A sigma = sigma - J Lambda T sigma, sigma interleaved
+ * [s00(z1), s20(z1), s00(z2), ...] (Sect. 3.2). */
+int orc_apply(const orc_slab *s, const double *sin, double *sout)
+{
+    size_t nf = (size_t)2 * s->ns * s->nmu * s->nnu;
+    int i, rc = -1;
+    double *F = (double *)malloc(sizeof(double) * nf);
+    double *q = (double *)malloc(sizeof(double) * s->nmu * s->nnu);
+    double *em = (double *)malloc(sizeof(double) * 2 * s->ns);
+    if (F && q && em) {
+        orc_weights(s, q);
+        rc = field_from_sigma(s, sin, 0, F);
+        if (rc == 0) {
+            field_J(s, q, F, em);
+            for (i = 0; i < 2 * s->ns; i++) sout[i] = sin[i] - em[i];
+        }
+    }
+    free(F); free(q); free(em);
+    return rc;
 }
 
 /* Iout = Iin - Lambda T J Iin. */
@@ -426,39 +402,21 @@ int orc_sigma_from_I(const orc_slab *s, const double *I, double *sigma)
  * ---------------------------------------------------------------------- */
 int orc_rhs(const orc_slab *s, double *b)
 {
-    int ns = s->ns, nmu = s->nmu, nnu = s->nnu;
-    int k, m, p;
-    double xi = 1.0 - s->eps;
-    double *zero = (double *)calloc(ns, sizeof(double));
-    double *I = (double *)malloc(sizeof(double) * ns);
-    double *J0 = (double *)calloc(ns, sizeof(double));
-    double *J2 = (double *)calloc(ns, sizeof(double));
-    double *q = (double *)malloc(sizeof(double) * nmu * nnu);
-    if (!zero || !I || !J0 || !J2 || !q) {
-        free(zero); free(I); free(J0); free(J2); free(q);
-        return -1;
-    }
-    orc_weights(s, q);
-    for (m = 0; m < nmu; m++) {
-        double t1, t2;
-        int upward = s->mu[m] > 0.0;
-        orc_t20(s->mu[m], &t1, &t2);
-        for (p = 0; p < nnu; p++) {
-            double kappa = s->opac[p] / fabs(s->mu[m]);
-            double w = q[m * nnu + p];
-            orc_ray(ns, s->tau, kappa, upward, s->fs, zero, upward ? s->Ibot : 0.0, I);
-            for (k = 0; k < ns; k++) {
-                J0[k] += w * I[k];
-                J2[k] += w * (t1 * I[k]); /* transmitted Q is zero */
-            }
+    size_t nf = (size_t)2 * s->ns * s->nmu * s->nnu;
+    int k, rc = -1;
+    double *zero = (double *)calloc((size_t)2 * s->ns, sizeof(double));
+    double *F = (double *)malloc(sizeof(double) * nf);
+    double *q = (double *)malloc(sizeof(double) * s->nmu * s->nnu);
+    if (zero && F && q) {
+        orc_weights(s, q);
+        rc = field_from_sigma(s, zero, 1, F);
+        if (rc == 0) {
+            field_J(s, q, F, b);
+            for (k = 0; k < s->ns; k++) b[2 * k] = b[2 * k] + s->eps * s->B[k];
         }
     }
-    for (k = 0; k < ns; k++) {
-        b[2 * k] = xi * J0[k] + s->eps * s->B[k];
-        b[2 * k + 1] = xi * s->W2 * J2[k];
-    }
-    free(zero); free(I); free(J0); free(J2); free(q);
-    return 0;
+    free(zero); free(F); free(q);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------

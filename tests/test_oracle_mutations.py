@@ -26,15 +26,16 @@ BATTERY = os.path.join(ROOT, "tests", "oracle_battery.py")
 MUTATIONS = [
     ("t1_sign", "3.0 * mu * mu - 1.0", "3.0 * mu * mu + 1.0"),
     ("t2_sign", "*t2 = sqrt(2.0) * (3.0 * mu * mu - 3.0)", "*t2 = sqrt(2.0) * (3.0 - 3.0 * mu * mu)"),
-    ("SI_uses_t2", "sin[2 * k] + t1 * sin[2 * k + 1]", "sin[2 * k] + t2 * sin[2 * k + 1]"),
-    ("SQ_uses_t1", "SQ[m * ns + k] = t2 *", "SQ[m * ns + k] = t1 *"),
-    ("J2_drops_Q", "J2[k] += w * (t1 * I[k] + t2 * Q[k]);", "J2[k] += w * (t1 * I[k]);"),
-    ("J2_drops_I", "J2[k] += w * (t1 * I[k] + t2 * Q[k]);", "J2[k] += w * (t2 * Q[k]);"),
+    ("SI_uses_t2", "SI[k] = sig[2 * k] + t1 * sig[2 * k + 1];", "SI[k] = sig[2 * k] + t2 * sig[2 * k + 1];"),
+    ("SQ_uses_t1", "SQ[k] = t2 * sig[2 * k + 1];", "SQ[k] = t1 * sig[2 * k + 1];"),
+    ("J2_drops_Q", "sig[2 * k + 1] += w * (t1 * I[k] + t2 * Q[k]);", "sig[2 * k + 1] += w * (t1 * I[k]);"),
+    ("J2_drops_I", "sig[2 * k + 1] += w * (t1 * I[k] + t2 * Q[k]);", "sig[2 * k + 1] += w * (t2 * Q[k]);"),
     ("weights_no_half", "0.5 * s->wmu[m]", "s->wmu[m]"),
     ("weights_no_phi", "(s->wnu[p] * s->phi[p] / norm)", "(s->wnu[p] / norm)"),
-    ("apply_xi_is_one", "sin[2 * k] - xi * J0[k]", "sin[2 * k] - J0[k]"),
-    ("apply_drops_W2", "sin[2 * k + 1] - xi * s->W2 * J2[k]", "sin[2 * k + 1] - xi * J2[k]"),
-    ("apply_wrong_output_index", "sout[2 * k + 1] = sin[2 * k + 1]", "sout[2 * k + 1] = sin[2 * k]"),
+    ("J20_drops_xi", "sig[2 * k + 1] *= xi * s->W2;", "sig[2 * k + 1] *= s->W2;"),
+    ("J20_drops_W2", "sig[2 * k + 1] *= xi * s->W2;", "sig[2 * k + 1] *= xi;"),
+    ("apply_sign", "sout[i] = sin[i] - em[i];", "sout[i] = sin[i] + em[i];"),
+    ("apply_wrong_output_index", "sout[i] = sin[i] - em[i];", "sout[i] = sin[i ^ 1] - em[i];"),
     ("series_pu_factor", "su += sgn * (double)(n - 1) * term;", "su += sgn * (double)n * term;"),
     ("series_sign", "double sgn = (n % 2 == 0) ? 1.0 : -1.0;", "double sgn = (n % 2 == 0) ? -1.0 : 1.0;"),
     ("closed_w1", "double w1 = w0 - d * e;", "double w1 = w0 - e;"),
@@ -50,9 +51,9 @@ MUTATIONS = [
     ("euler_a", "*a = 1.0 / (1.0 + d);", "*a = 1.0 / (1.0 + 0.5 * d);"),
     ("euler_uses_upwind_source", "I[k] = a * I[u] + b * S[k];", "I[k] = a * I[u] + b * S[u];"),
     ("trap_beta", "*b = h / (1.0 + h);", "*b = h / (1.0 - h);"),
-    ("rhs_drops_thermal", "b[2 * k] = xi * J0[k] + s->eps * s->B[k];", "b[2 * k] = xi * J0[k];"),
-    ("rhs_inflow_wrong_side", "upward ? s->Ibot : 0.0", "upward ? 0.0 : s->Ibot"),
-    ("rhs_drops_W2", "b[2 * k + 1] = xi * s->W2 * J2[k];", "b[2 * k + 1] = xi * J2[k];"),
+    ("rhs_drops_thermal", "b[2 * k] = b[2 * k] + s->eps * s->B[k];", "b[2 * k] = b[2 * k];"),
+    ("rhs_inflow_wrong_side", "(with_t && upward) ? s->Ibot : 0.0", "(with_t && !upward) ? s->Ibot : 0.0"),
+    ("rhs_Q_gets_inflow", "s->fs, SQ, 0.0,", "s->fs, SQ, inflow,"),
     ("diag_wrong_index", "d[j] = col[i];", "d[j] = col[j];"),
     ("gmres_mgs_sign", "for (l = 0; l < n; l++) w[l] -= h * V[(size_t)i * n + l];",
      "for (l = 0; l < n; l++) w[l] += h * V[(size_t)i * n + l];"),

@@ -622,3 +622,97 @@ def test_redistribution_operator_equals_dense_route(gamma):
     for seed in range(2):
         v = np.random.default_rng(seed).uniform(-1, 1, A.shape[0])
         assert np.abs(RDO.apply(p, R, v) - A @ v).max() <= 1e-13 * np.abs(v).max()
+
+
+# Photon conservation of the redistribution.  R's columns are normalized so
+# that sum_p w_p R(p, q) = phi_q (the discrete int R(x, x') dx = phi(x')), so
+# for ANY monochromatic J the contraction Jt(k, p) = sum_q R(p, q) w_q J(k, q)
+# satisfies sum_p w_p Jt(k, p) = sum_q w_q phi_q J(k, q).  A transposed R, or
+# a dropped w_q, breaks it as soon as R is not symmetric (gamma > 0: the
+# Gaussian part phi(x') g(x - x') is not), which the gamma = 0 reduction to
+# complete redistribution cannot see (phi phi' is symmetric).
+
+def _conservation_error(contract, p, R, seed=0):
+    ns, nnu = 6, len(p.w_nu)
+    J = np.random.default_rng(seed).uniform(0.1, 1.0, (ns, nnu))
+    Jt = contract(J)
+    lhs = Jt @ p.w_nu
+    rhs = J @ (p.w_nu * p.phi[0])
+    return np.abs(lhs - rhs).max() / np.abs(rhs).max()
+
+
+@pytest.mark.parametrize("gamma", [0.5, 1.0])
+def test_redistribution_contraction_conserves_photons(gamma):
+    p, R = W.config5(gamma=gamma, ns=8, n_mu=4, n_nu=31)
+    assert np.abs(R - R.T).max() > 1e-3 * np.abs(R).max()  # the pin can see a transpose
+    err = _conservation_error(lambda J: RDO._contract(p, 0, R, J), p, R)
+    assert err <= 1e-13, err
+    # a point mass at frequency q0 comes back as column q0 of R, times w_q0
+    q0 = 7
+    J = np.zeros((1, len(p.w_nu)))
+    J[0, q0] = 1.0
+    assert np.abs(RDO._contract(p, 0, R, J)[0] - R[:, q0] * p.w_nu[q0]).max() <= 1e-15
+
+
+@pytest.mark.parametrize("gamma", [0.5, 1.0])
+def test_redistribution_dense_route_conserves_photons(gamma):
+    """The same law through the explicit A of the dense route: for any sigma,
+    sum_p w_p phi_p ((Id - A) sigma)^K(k, p) = xi W_K sum_q w_q phi_q J^K_q(k),
+    with J^K_q the monochromatic angle quadrature of the formal solution
+    (computed by the redistribution oracle's own ray sweeps)."""
+    p = W.config1_subgrid()
+    R = W.redistribution_matrix(p.x, p.w_nu, p.phi[0], gamma)
+    A = D.redistribution_matrix_A(p, R)
+    ns, nnu = int(p.ns[0]), len(p.w_nu)
+    sig = np.random.default_rng(2).uniform(-1, 1, A.shape[0])
+    lhs = ((sig - A @ sig).reshape(ns, nnu, 2) * (p.w_nu * p.phi[0])[None, :, None]).sum(1)
+    s3 = sig.reshape(ns, nnu, 2)
+    J0, J2 = RDO._mono_J(p, 0, s3[:, :, 0], s3[:, :, 1], False)
+    xi, W2 = 1.0 - float(p.eps[0]), float(p.W2[0])
+    wphi = p.w_nu * p.phi[0]
+    rhs = np.stack([xi * (J0 @ wphi), xi * W2 * (J2 @ wphi)], axis=1)
+    assert np.abs(lhs - rhs).max() <= 1e-13 * np.abs(rhs).max()
+
+
+def _mutated_module(path, name, old, new):
+    import types
+    src = open(path).read()
+    assert old in src, (name, old)
+    mod = types.ModuleType("oracle._mut_" + name)
+    mod.__package__ = "oracle"
+    exec(compile(src.replace(old, new, 1), path + ":" + name, "exec"), mod.__dict__)
+    return mod
+
+
+_RDO_SRC = os.path.join(os.path.dirname(RDO.__file__), "redistrib.py")
+_DENSE_SRC = os.path.join(os.path.dirname(D.__file__), "dense.py")
+_CONTRACT = "return J @ (R * np.asarray(prob.w_nu)[None, :]).T"
+_DENSE_C0 = "Cm[sidx(k, p, 0), sidx(k, q, 0)] = xi * R[p, q] * wnu[q] / phi[p]"
+
+
+@pytest.mark.parametrize("name,old,new", [
+    ("transposed_R", _CONTRACT, "return J @ (R.T * np.asarray(prob.w_nu)[None, :]).T"),
+    ("dropped_w", _CONTRACT, "return J @ R.T"),
+])
+def test_redistribution_pin_rejects_planted_contraction_mistakes(name, old, new):
+    p, R = W.config5(gamma=0.5, ns=8, n_mu=4, n_nu=31)
+    mut = _mutated_module(_RDO_SRC, name, old, new)
+    assert _conservation_error(lambda J: mut._contract(p, 0, R, J), p, R) > 1e-6, name
+
+
+@pytest.mark.parametrize("name,new", [
+    ("dense_transposed_R", "Cm[sidx(k, p, 0), sidx(k, q, 0)] = xi * R[q, p] * wnu[q] / phi[p]"),
+    ("dense_dropped_w", "Cm[sidx(k, p, 0), sidx(k, q, 0)] = xi * R[p, q] / phi[p]"),
+])
+def test_redistribution_dense_pin_rejects_planted_mistakes(name, new):
+    p = W.config1_subgrid()
+    R = W.redistribution_matrix(p.x, p.w_nu, p.phi[0], 0.5)
+    mut = _mutated_module(_DENSE_SRC, name, _DENSE_C0, new)
+    A = mut.redistribution_matrix_A(p, R)
+    ns, nnu = int(p.ns[0]), len(p.w_nu)
+    sig = np.random.default_rng(2).uniform(-1, 1, A.shape[0])
+    lhs = ((sig - A @ sig).reshape(ns, nnu, 2)[:, :, 0] * (p.w_nu * p.phi[0])[None, :]).sum(1)
+    s3 = sig.reshape(ns, nnu, 2)
+    J0, _ = RDO._mono_J(p, 0, s3[:, :, 0], s3[:, :, 1], False)
+    rhs = (1.0 - float(p.eps[0])) * (J0 @ (p.w_nu * p.phi[0]))
+    assert np.abs(lhs - rhs).max() > 1e-6 * np.abs(rhs).max(), name
