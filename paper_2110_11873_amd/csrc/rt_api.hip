@@ -202,6 +202,45 @@ int auto_chunk(const std::vector<int> &ns, int rays) {
     return best;
 }
 
+// The tile geometry of one slab for a plan of longest chunk L: chunks per
+// ray, chunk length, long chunks, rays per wave-batch, wave-batches per
+// direction and tile entries per wave-batch.
+struct SlabTiles {
+    int C, Leff, nlong, G, nwb, bstride;
+};
+SlabTiles slab_tiles(int ns, int L, int n_nu) {
+    SlabTiles t;
+    t.C = chunks_for(ns, L);
+    t.Leff = chunk_len(ns, t.C, L);
+    // chunk lengths Leff and Leff - 1 tile the ns - 1 intervals exactly
+    // when Leff is ceil((ns - 1) / C); otherwise (lengths rounded up to
+    // a compiled one) all chunks are long and the last ones end past the
+    // slab's bottom in identity steps
+    t.nlong = t.C;
+    if (chunk_len_step(L) == 1) {
+        const int r = (ns - 1) - t.C * (t.Leff - 1);
+        if (r >= 1 && r <= t.C) t.nlong = r;
+    }
+    t.G = kWave / t.C;
+    t.nwb = (n_nu + t.G - 1) / t.G;
+    t.bstride = (t.Leff - 1) * kWave + (t.G * t.nlong + 15) / 16 * 16;
+    return t;
+}
+
+// The sweep addresses the tiles of one (slab, direction) through 32-bit
+// buffer offsets, in entries of up to 16 bytes (FP64 pairs): reject plans
+// whose tiles of one direction exceed 2^31 - 1 bytes.
+int check_tile_range(const std::vector<int> &ns, int L, int n_nu) {
+    for (size_t a = 0; a < ns.size(); ++a) {
+        const SlabTiles t = slab_tiles(ns[a], L, n_nu);
+        if ((long long)t.nwb * t.bstride * 16 > 2147483647LL)
+            return fail(RT_EINVAL, idx("ns", (long long)a) +
+                                       ": the coefficient tiles of one direction exceed 2 GiB "
+                                       "(too many frequencies for this depth grid)");
+    }
+    return RT_OK;
+}
+
 template <typename T>
 int dalloc(T **p, size_t count) {
     *p = nullptr;
@@ -424,6 +463,10 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
             delete h;
             return fail(RT_EINVAL, "options.chunk too short for ns (need 64 * chunk >= ns - 1)");
         }
+    if ((rc = check_tile_range(h->ns, h->L, h->n_nu)) != RT_OK) {
+        delete h;
+        return rc;
+    }
     long long coef = 0, part = 0, qt = 0, dense = 0, ew = 0, part_t = 0;
     int blk = 0, blk_t = 0;
     std::vector<AtmDesc> atm_t(h->n_atm);
@@ -439,21 +482,14 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
         AtmDesc d{};
         d.ns = h->ns[a];
         d.doff = h->doff[a];
-        d.C = chunks_for(d.ns, h->L);
-        d.Leff = chunk_len(d.ns, d.C, h->L);
-        // chunk lengths Leff and Leff - 1 tile the ns - 1 intervals exactly
-        // when Leff is ceil((ns - 1) / C); otherwise (lengths rounded up to
-        // a compiled one) all chunks are long and the last ones end past the
-        // slab's bottom in identity steps
-        d.nlong = d.C;
-        if (chunk_len_step(h->L) == 1) {
-            const int r = (d.ns - 1) - d.C * (d.Leff - 1);
-            if (r >= 1 && r <= d.C) d.nlong = r;
-        }
-        d.G = kWave / d.C;
+        const SlabTiles t = slab_tiles(d.ns, h->L, h->n_nu);
+        d.C = t.C;
+        d.Leff = t.Leff;
+        d.nlong = t.nlong;
+        d.G = t.G;
         d.n_nu = h->n_nu;
-        d.nwb = (h->n_nu + d.G - 1) / d.G;
-        d.bstride = (d.Leff - 1) * kWave + (d.G * d.nlong + 15) / 16 * 16;
+        d.nwb = t.nwb;
+        d.bstride = t.bstride;
         d.ray_off = a * rays;
         int nb = (d.nwb + h->W * blocks_per_dir - 1) / (h->W * blocks_per_dir);
         nb = std::min(std::max(nb, 1), 32);
@@ -929,7 +965,15 @@ int rt_validate(const rt_problem *p, const rt_options *o) {
     rt_options opt;
     rt_default_options(&opt);
     if (o) opt = *o;
-    return validate(p, &opt, mp, wp);
+    int rc = validate(p, &opt, mp, wp);
+    if (rc != RT_OK) return rc;
+    // the plan checks rt_setup makes before any device call
+    const std::vector<int> ns(p->ns, p->ns + p->n_atm);
+    const int L = opt.chunk ? opt.chunk : auto_chunk(ns, (p->n_mu / 2) * p->n_nu);
+    for (int n : ns)
+        if ((long long)kWave * L < n - 1)
+            return fail(RT_EINVAL, "options.chunk too short for ns (need 64 * chunk >= ns - 1)");
+    return check_tile_range(ns, L, p->n_nu);
 }
 
 }  // extern "C"

@@ -36,8 +36,9 @@ def test_default_options():
     o = B.default_options()
     assert (o.precision, o.restart, o.maxit, o.rtol, o.inner_rtol, o.inner_maxit, o.max_outer,
             o.chunk, o.wave_batches, o.prefetch, o.check_every, o.sweep_waves, o.graphs,
-            o.precond, o.omega) == (
-                0, 30, 10000, 1e-10, 3e-4, 200, 30, 0, 0, 0, 16, 0, 0, B.RT_PC_JACOBI, 1.0)
+            o.precond, o.omega, o.coef_mode) == (
+                0, 30, 10000, 1e-10, 3e-4, 200, 30, 0, 0, 0, 16, 0, 0, B.RT_PC_JACOBI, 1.0,
+                B.RT_COEF_AUTO)
 
 
 def test_valid_configs_pass_validation():
@@ -76,9 +77,35 @@ def test_invalid_options_rejected():
                      (dict(sweep_waves=8, chunk=16), "sweep_waves"), (dict(graphs=2), "graphs"),
                      (dict(precond=3), "precond"), (dict(precond=-1), "precond"),
                      (dict(omega=0.0), "omega"), (dict(omega=2.0), "omega"),
-                     (dict(precond=B.RT_PC_SSOR, omega=float("nan")), "omega")]:
+                     (dict(precond=B.RT_PC_SSOR, omega=float("nan")), "omega"),
+                     (dict(coef_mode=-1), "coef_mode"), (dict(coef_mode=5), "coef_mode")]:
         assert B.validate(p, B.default_options(**kw)) == B.RT_EINVAL, kw
         assert frag in B.last_error()
+
+
+def _deep_slab(n_nu):
+    """One slab of 2048 depths, 2 directions and n_nu frequencies (host
+    arrays only; validated, never set up on a device)."""
+    ns = 2048
+    x = np.linspace(-10, 10, n_nu)
+    w = np.full(n_nu, x[1] - x[0])
+    phi = np.exp(-x * x)[None, :] + 1e-3
+    return W.Problem(ns=np.array([ns], dtype=np.int32), tau=np.logspace(-4, 8, ns),
+                     mu=np.array([-0.5, 0.5]), w_mu=np.array([1.0, 1.0]), x=x, w_nu=w,
+                     phi=phi, opac=phi / phi.max(), eps=np.array([1e-4]), W2=np.array([0.5]),
+                     I_bot=np.array([1.0]), B=np.ones(ns), formal_solver=W.FS_DELO_LINEAR,
+                     normalize_profile=True, name="deep")
+
+
+def test_tile_range_beyond_32_bit_offsets_rejected():
+    """The sweep addresses one (slab, direction)'s coefficient tiles with
+    32-bit offsets in entries of up to 16 bytes: with 2048 depths (chunks of
+    32, one ray per wave-batch, 2048 entries per batch) 70,000 frequencies
+    need 2.29e9 bytes per direction and are rejected before any device call;
+    65,000 need 2.13e9 and pass."""
+    assert B.validate(_deep_slab(70000)) == B.RT_EINVAL
+    assert "2 GiB" in B.last_error()
+    assert B.validate(_deep_slab(65000)) == 0, B.last_error()
 
 
 def test_setup_without_gpu_fails_cleanly():
