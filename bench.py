@@ -1,7 +1,7 @@
 """Benchmark of the matrix-free (Id - J Lambda T) operator and its Jacobi-Krylov solves.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-    python bench.py --op-only fp32|fp64 [--matvecs N]   # operator leg alone
+    python bench.py --op-only fp32|fp64 [--matvecs N] [--coef-mode M]   # operator leg alone
     python bench.py --copy-calib                        # 512 MiB device copy x3
     python bench.py --summarize-pmc DIR                 # counters -> profiles/
 
@@ -16,14 +16,19 @@ with the inputs resident on the GPU.  `value` counts solved slabs per second.
 
 Also on the same JSON line: the same solve in plain FP64; the operator alone
 (FP64 and FP32 applications per second and their achieved bandwidth against
-the HBM peak, timed with HIP events on the stream the kernels run on); the
-single paper-shaped slab (Ns = 200, 20 mu, 101 nu) solved by Jacobi-GMRES,
-BiCGSTAB and Richardson in FP64; and the FP64 CPU oracle timed on this host.
+the HBM peak, timed with HIP events on the stream the kernels run on), in the
+tuned launch plan and in each coefficient mode of the sweep; the single
+1024-point slab (32 mu, 201 nu) solved in mixed precision to 1e-10; errors
+against the FP64 oracle (the FP32 operator's, the refined solutions' residual
+by the oracle's own operator, and their forward error against LU solutions of
+the oracle's assembled A, with its condition number); the single
+paper-shaped slab (Ns = 200, 20 mu, 101 nu) solved by Jacobi-GMRES, BiCGSTAB
+and Richardson in FP64; and the FP64 CPU oracle timed on this host, on one
+core and on several.
 """
 import argparse
 import csv
 import glob
-import hashlib
 import json
 import os
 import sys
@@ -39,19 +44,14 @@ HBM_PEAK_GBS = 8000.0
 RT_MAX_RESTART_USED = 128  # no restart on the paper's grids (their counts stay below)
 RTOL = 1e-9
 COPY_BYTES = 512 * 1024 * 1024
-# the sources that define the operator's kernels and launch plan: counter
-# readings are only used while these are unchanged
-SWEEP_SOURCES = ["rt_sweep_kernel.h", "rt_sweep.hip", "rt_sweep_f32.hip", "rt_sweep_f64.hip",
-                 "rt_coef.h", "rt_internal.h", "rt_api.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c4.json")
+CPU_SHARE = 16  # host cores of one GPU's share on the benchmark machines
 
 
 def sweep_source_hash():
-    h = hashlib.sha256()
-    for f in SWEEP_SOURCES:
-        with open(os.path.join(ROOT, "paper_2110_11873_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    """Hash of the sweep sources the library was built from (built in)."""
+    from paper_2110_11873_amd import binding as B
+    return B.sweep_source_hash()
 
 
 def measured_traffic(kind):
@@ -67,22 +67,25 @@ def measured_traffic(kind):
     return t[kind]["hbm_bytes_per_launch"]
 
 
-def op_only(kind, n):
-    """The operator leg alone (for counter passes): n applications."""
+def op_only(kind, n, coef_mode=0):
+    """The operator leg alone (for counter passes): n applications, in the
+    tuned launch plan, or with its coefficient mode replaced."""
     import torch
     from paper_2110_11873_amd import binding as B
     from paper_2110_11873_amd import workloads as W
     torch.cuda.set_device(0)
     p = W.config4(512)
     # the handle (and launch plan) the bench times the operator on
-    with B.setup(p, precision=B.RT_PREC_MIXED, autotune=True) as h:
+    kw = dict(coef_mode=coef_mode) if coef_mode else {}
+    with B.setup(p, precision=B.RT_PREC_MIXED, autotune=True, **kw) as h:
         v = torch.from_numpy(W.random_vector(p.n_unknowns, 0)).cuda()
         y = torch.empty_like(v)
         f = h.apply_op_fp32 if kind == "fp32" else h.apply_op
         for _ in range(n):
             f(v, y)
         torch.cuda.synchronize()
-        print(json.dumps(dict(op=kind, applications=n, plan=h.plan_info())), flush=True)
+        print(json.dumps(dict(op=kind, applications=n, plan=h.plan_info(),
+                              kernel=h.sweep_kernel_name(kind == "fp32"))), flush=True)
 
 
 def copy_calib():
@@ -153,10 +156,19 @@ def summarize_pmc(root):
     print(json.dumps(out, indent=1))
 
 
-def op_bytes(plan, n_unknowns, coef_bytes):
-    """Algorithmic bytes of one operator application: one (c_u, c_k) pair per
-    ray-interval, sigma read, sigma_out written (FP64)."""
-    return 2 * coef_bytes * plan["intervals"] + 16.0 * n_unknowns
+def op_bytes(p, plan, coef_mode, s):
+    """Algorithmic bytes of one operator application with the sweep in a
+    coefficient mode (0: (E, w) pairs streamed, 1: w streamed, 2: both
+    computed): the step coefficients the mode streams per ray-interval (2 s,
+    s or 0 bytes, s = 4 or 8), per ray the quadrature weight (8 bytes) and,
+    for the derived modes, kappa (8) or kappa and 1 / kappa (16), per depth
+    point dtau (8, derived modes), and sigma read and sigma_out written
+    (FP64, 16 bytes per unknown)."""
+    n_rays = p.n_atm * (p.n_mu // 2) * p.n_nu
+    coef = {0: 2 * s, 1: s, 2: 0}[coef_mode] * plan["intervals"]
+    ray = {0: 8, 1: 16, 2: 24}[coef_mode] * n_rays
+    dep = 0 if coef_mode == 0 else 8 * int(np.sum(p.ns))
+    return float(coef + ray + dep) + 16.0 * p.n_unknowns
 
 
 def time_ops(torch, fn, v, out, n):
@@ -173,6 +185,7 @@ def time_ops(torch, fn, v, out, n):
 
 
 def time_solves(torch, h, x0, kind, steps, warmup):
+    """Wall time of `steps` solves after `warmup` ones; the last solve's x."""
     x = x0.clone()
     fn = getattr(h, "solve_" + kind)
     info = None
@@ -185,7 +198,7 @@ def time_solves(torch, h, x0, kind, steps, warmup):
         x.copy_(x0)
         _, info = fn(x)
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, info
+    return time.perf_counter() - t0, info, x
 
 
 def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
@@ -204,26 +217,70 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
     return 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
-def cpu_baseline(p, dinv, n_sample=8):
-    """The FP64 oracle's Jacobi-GMRES(30) on a sample of the batch's slabs."""
+def host_cpu():
+    """Model name of this host's CPU (from /proc/cpuinfo) and its core count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def _cpu_prepare(sl):
+    """The oracle's dense A of one slab (column by column from its operator),
+    the LU solution of A x = b, A's 2-norm condition number and the Jacobi
+    diagonal -- untimed preparation."""
     from oracle import oracle as O
-    idx = np.linspace(0, p.n_atm - 1, n_sample).round().astype(int)
-    off = 2 * p.offsets
-    t = 0.0
-    its = []
-    for i in idx:
-        sl = p.slab(int(i))
-        d = dinv[off[i]:off[i + 1]]
-        b = O.rhs(sl)
+    A = O.assemble(sl)
+    b = O.rhs(sl)
+    return dict(b=b, x_lu=np.linalg.solve(A, b), kappa=float(np.linalg.cond(A)),
+                dinv=1.0 / np.diag(A).copy())
+
+
+def _cpu_solve(args):
+    """One timed FP64 Jacobi-GMRES(30) solve of a slab by the oracle."""
+    from oracle import oracle as O
+    sl, b, dinv = args
+    t0 = time.perf_counter()
+    x, info = O.gmres(sl, b=b, dinv=dinv, tol=RTOL, restart=30)
+    return dict(t=time.perf_counter() - t0, x=x, iterations=info[0]["iterations"])
+
+
+def cpu_baseline(p, n_multi=16, n_single=4):
+    """The FP64 oracle's Jacobi-GMRES(30) on a sample of the batch's slabs,
+    timed on one core (n_single slabs in this process) and on several
+    (n_multi slabs, one process per slab, up to one GPU's share of host
+    cores).  Runs before the GPU is touched: the worker processes are forked
+    from a process that has not initialized it."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    idx = [int(i) for i in np.linspace(0, p.n_atm - 1, n_multi).round().astype(int)]
+    slabs = [p.slab(i) for i in idx]
+    workers = max(1, min(n_multi, CPU_SHARE, os.cpu_count() or 1))
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
+        prep = list(ex.map(_cpu_prepare, slabs))
+        jobs = [(sl, pr["b"], pr["dinv"]) for sl, pr in zip(slabs, prep)]
         t0 = time.perf_counter()
-        _, info = O.gmres(sl, b=b, dinv=d, tol=RTOL, restart=30)
-        t += time.perf_counter() - t0
-        its.append(info[0]["iterations"])
-    return dict(value=len(idx) / t, unit="solves/s", cores=1, kind="oracle",
-                sample=f"{len(idx)} of the 512 slabs (indices {idx.tolist()}, Ns "
-                       f"{[int(p.ns[i]) for i in idx]}), each one FP64 Jacobi-GMRES(30) solve "
-                       f"to 1e-9 by the oracle ({sum(its)} iterations, {t:.1f} s single-threaded); "
-                       f"Jacobi diagonal and right-hand side computed before the timed region")
+        sol = list(ex.map(_cpu_solve, jobs))
+        wall = time.perf_counter() - t0
+    single = [_cpu_solve(j) for j in jobs[:n_single]]
+    t1 = sum(r["t"] for r in single)
+    model, ncpu = host_cpu()
+    its = sum(r["iterations"] for r in sol)
+    return dict(idx=idx, prep=prep, sol=sol, line=dict(
+        value=len(idx) / wall, unit="solves/s", cores=workers, kind="oracle",
+        single_core_value=n_single / t1, host=model, host_cores=ncpu,
+        sample=f"{len(idx)} of the 512 slabs (indices {idx}, Ns {[int(p.ns[i]) for i in idx]}), "
+               f"each one FP64 Jacobi-GMRES(30) solve to 1e-9 by the oracle ({its} iterations), "
+               f"one process per slab on {workers} cores: {wall:.1f} s wall; the first "
+               f"{n_single} of them one after another on one core: {t1:.1f} s.  Jacobi "
+               f"diagonal, right-hand side, and the LU solutions and condition numbers "
+               f"of the oracle's assembled A computed before the timed region"))
 
 
 def routes(steps):
@@ -267,7 +324,7 @@ def routes(steps):
         out["c4_lu_solve_ms"] = ev_ms(lambda: h.solve_lu(x), steps)
     for name, pc in (("sor", B.RT_PC_SOR), ("ssor", B.RT_PC_SSOR)):
         with B.setup(p, autotune=True, precond=pc, rtol=1e-10, precision=B.RT_PREC_MIXED) as h:
-            dt, info = time_solves(torch, h, x0, "gmres", max(1, steps // 2), 1)
+            dt, info, _ = time_solves(torch, h, x0, "gmres", max(1, steps // 2), 1)
             out[f"c4_{name}_gmres_mixed_ms"] = 1e3 * dt / max(1, steps // 2)
             out[f"c4_{name}_gmres_iterations_max"] = max(i.iterations for i in info)
             v = torch.from_numpy(W.random_vector(p.n_unknowns, 0)).cuda()
@@ -278,7 +335,7 @@ def routes(steps):
     with B.setup(q, rtol=1e-10) as h:
         vq = torch.from_numpy(W.random_vector(q.n_unknowns, 0)).cuda()
         out["c2_parabolic_matvec_us"] = 1e3 * ev_ms(lambda: h.apply_op(vq), 50)
-        dt, info = time_solves(torch, h, xq, "gmres", steps, 1)
+        dt, info, _ = time_solves(torch, h, xq, "gmres", steps, 1)
         out["c2_parabolic_gmres_ms"] = 1e3 * dt / steps
         out["c2_parabolic_gmres_iterations"] = info[0].iterations
     pp = p.with_(formal_solver=W.FS_DELO_PARABOLIC)
@@ -348,6 +405,23 @@ def routes(steps):
     return 0
 
 
+MODE_NAMES = {0: "pairs", 1: "stream_w", 2: "recompute"}
+MODE_OPTION = {0: 1, 1: 2, 2: 3}  # kernel coefficient mode -> rt_options.coef_mode
+
+
+def normwise(ref, v, y):
+    """||y - ref||_inf / (||v||_inf + ||v - ref||_inf): the operator error
+    relative to its two terms (sigma_in and xi J Lambda T sigma_in)."""
+    return float(np.abs(y - ref).max() / (np.abs(v).max() + np.abs(v - ref).max()))
+
+
+def roofline_hbm(bytes_, us, kname, traffic):
+    a = bytes_ / (us * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": a / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname + " + rt::finalize_kernel",
+            "bytes_per_launch": bytes_, "launch_us": us}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -357,6 +431,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--op-only", choices=["fp32", "fp64"])
+    ap.add_argument("--coef-mode", type=int, default=0,
+                    help="with --op-only: rt_options.coef_mode (0 = the tuned plan's)")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--summarize-pmc", metavar="DIR")
     ap.add_argument("--routes", action="store_true",
@@ -373,27 +449,41 @@ def main():
     if args.copy_calib:
         return copy_calib()
     if args.op_only:
-        return op_only(args.op_only, args.matvecs)
+        return op_only(args.op_only, args.matvecs, args.coef_mode)
     if args.routes:
         return routes(args.steps)
 
+    from oracle import oracle as O
+    from paper_2110_11873_amd import workloads as W
+    p = W.config4(512)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before anything touches the GPU (the worker processes are forked)
+        cpu = cpu_baseline(p)
+        print(json.dumps(dict(stage="cpu baseline done", **{k: cpu["line"][k] for k in (
+            "value", "single_core_value", "cores")})), file=sys.stderr, flush=True)
+
     import torch
     from paper_2110_11873_amd import binding as B
-    from paper_2110_11873_amd import workloads as W
 
     torch.cuda.set_device(0)
     out = {}
-    p = W.config4(512)
     x0 = torch.from_numpy(W.initial_guess(p)).cuda()
-    from paper_2110_11873_amd import autotune as AT
-    tuned = {"mixed": AT.lookup(p, True), "fp64": AT.lookup(p, False)}
-    out["launch_plan"] = {k: (v if v else "defaults (no tuned plan for this shape)")
-                          for k, v in tuned.items()}
+    v = torch.from_numpy(W.random_vector(p.n_unknowns, 0)).cuda()
+    y = torch.empty_like(v)
     with B.setup(p, rtol=RTOL, restart=30, maxit=20000, precision=B.RT_PREC_MIXED,
                  autotune=True) as h:
         plan = h.plan_info()
+        cfg32, cfg64 = h.sweep_config(True), h.sweep_config(False)
+        o = h.effective_options()
+        out["launch_plan"] = {"mixed": dict(chunk=plan["chunk"], sweep_waves=cfg32["waves"],
+                                            prefetch=o.prefetch, wave_batches=o.wave_batches,
+                                            coef_mode=o.coef_mode,
+                                            fp32_sweep=MODE_NAMES[cfg32["coef_mode"]],
+                                            fp64_sweep=MODE_NAMES[cfg64["coef_mode"]],
+                                            status=h.tuned_plan_status())}
         kname32, kname64 = h.sweep_kernel_name(True), h.sweep_kernel_name(False)
-        dt, info = time_solves(torch, h, x0, "gmres", args.steps, args.warmup)
+        dt, info, xg = time_solves(torch, h, x0, "gmres", args.steps, args.warmup)
         value = p.n_atm * args.steps / dt
         ms_step = 1e3 * dt / args.steps
         st = [i.status for i in info]
@@ -401,49 +491,131 @@ def main():
         out["mixed_relres_max"] = max(i.relres for i in info)
         out["mixed_outer_steps_max"] = max(i.outer_steps for i in info)
         out["mixed_iterations_max"] = max(i.iterations for i in info)
-        v = torch.from_numpy(W.random_vector(p.n_unknowns, 0)).cuda()
-        y = torch.empty_like(v)
+        x_mixed = xg.cpu().numpy()
         t32 = time_ops(torch, h.apply_op_fp32, v, y, args.matvecs)
+        y32 = y.cpu().numpy()
         t64 = time_ops(torch, h.apply_op, v, y, args.matvecs)
-        dinv = h.precond_jacobi(torch.ones_like(v)).cpu().numpy()
-    b32, b64 = op_bytes(plan, p.n_unknowns, 4), op_bytes(plan, p.n_unknowns, 8)
-    a32 = b32 / (t32 * 1e-3) / 1e9
-    a64 = b64 / (t64 * 1e-3) / 1e9
+    cm32, cm64 = cfg32["coef_mode"], cfg64["coef_mode"]
+    b32, b64 = op_bytes(p, plan, cm32, 4), op_bytes(p, plan, cm64, 8)
     out["matvecs_per_s_fp32"] = 1e3 / t32
     out["matvecs_per_s_fp64"] = 1e3 / t64
     out["matvec_us_fp32"] = t32 * 1e3
     out["matvec_us_fp64"] = t64 * 1e3
-    out["roofline_fp64"] = {"bound": "hbm", "achieved": a64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": a64 / HBM_PEAK_GBS, "traffic": measured_traffic("fp64"),
-                            "kernel": kname64 + " + rt::finalize_kernel",
-                            "bytes_per_launch": b64, "launch_us": t64 * 1e3}
+    out["roofline_fp64"] = roofline_hbm(b64, t64 * 1e3, kname64, measured_traffic("fp64"))
     out["sweep_plan"] = plan
+
+    # the operator in every coefficient mode, with the tuned plan otherwise
+    modes = {}
+    for cm in (0, 1, 2):
+        with B.setup(p, chunk=plan["chunk"], sweep_waves=cfg32["waves"],
+                     wave_batches=o.wave_batches, coef_mode=MODE_OPTION[cm]) as hm:
+            u32 = time_ops(torch, hm.apply_op_fp32, v, y, max(20, args.matvecs // 3)) * 1e3
+            u64 = time_ops(torch, hm.apply_op, v, y, max(20, args.matvecs // 3)) * 1e3
+        m32, m64 = op_bytes(p, plan, cm, 4), op_bytes(p, plan, cm, 8)
+        modes[MODE_NAMES[cm]] = {"fp32_us": u32, "fp64_us": u64,
+                                 "fp32_bytes": m32, "fp64_bytes": m64,
+                                 "fp32_hbm_frac": m32 / (u32 * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                                 "fp64_hbm_frac": m64 / (u64 * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    out["coef_modes"] = modes
+
     with B.setup(p, rtol=RTOL, restart=30, maxit=20000, autotune=True) as h:
-        dt64, info64 = time_solves(torch, h, x0, "gmres", max(2, args.steps // 2), 1)
-        out["fp64_solves_per_s"] = p.n_atm * max(2, args.steps // 2) / dt64
+        out["launch_plan"]["fp64"] = dict(chunk=h.plan_info()["chunk"],
+                                          sweep_waves=h.sweep_config(False)["waves"],
+                                          coef_mode=h.effective_options().coef_mode,
+                                          fp64_sweep=MODE_NAMES[h.sweep_config(False)["coef_mode"]],
+                                          status=h.tuned_plan_status())
+        n64 = max(2, args.steps // 2)
+        dt64, info64, xg64 = time_solves(torch, h, x0, "gmres", n64, 1)
+        out["fp64_solves_per_s"] = p.n_atm * n64 / dt64
         out["fp64_converged"] = sum(i.status == "converged" for i in info64)
         out["fp64_iterations_max"] = max(i.iterations for i in info64)
+        x_fp64 = xg64.cpu().numpy()
     out["mixed_over_fp64"] = value / out["fp64_solves_per_s"]
     out["hbm_copy_GBs"] = copy_bandwidth(torch)  # measured, beside the 8 TB/s datasheet peak
 
+    # errors against the FP64 oracle on sampled slabs of the batch
+    sl = O._slices(p)
+    vh = v.cpu().numpy()
+    errs = []
+    for i in (0, 123, 300, 511):
+        ref = O.apply_slab(p, i, vh[sl[i]])
+        errs.append(normwise(ref, vh[sl[i]], y32[sl[i]]))
+    out["fp32_op_error_c4"] = max(errs)
+    if cpu is not None:
+        rr, fe_m, fe_64, fe_o, kap = [], [], [], [], []
+        for i, pr, so in zip(cpu["idx"], cpu["prep"], cpu["sol"]):
+            b = pr["b"]
+            rr.append(np.linalg.norm(b - O.apply_slab(p, i, x_mixed[sl[i]])) / np.linalg.norm(b))
+            nl = np.linalg.norm(pr["x_lu"])
+            fe_m.append(np.linalg.norm(x_mixed[sl[i]] - pr["x_lu"]) / nl)
+            fe_64.append(np.linalg.norm(x_fp64[sl[i]] - pr["x_lu"]) / nl)
+            fe_o.append(np.linalg.norm(so["x"] - pr["x_lu"]) / nl)
+            kap.append(pr["kappa"])
+        out["mixed_oracle_relres_max"] = float(max(rr))
+        out["forward_error_c4"] = {
+            "slabs": cpu["idx"], "kappa2_max": float(max(kap)), "kappa2_min": float(min(kap)),
+            "mixed_max": float(max(fe_m)), "fp64_max": float(max(fe_64)),
+            "oracle_gmres_max": float(max(fe_o)),
+            "what": "||x - x_LU|| / ||x_LU||, x_LU the LU solution of the oracle's assembled A "
+                    "(FP64, LAPACK); kappa2 its 2-norm condition number"}
+
     if not args.no_extras:
+        # one 1024-point atmosphere (32 mu, 201 nu), FP32 inner GMRES(30) + FP64
+        # refinement to 1e-10, against the oracle
+        q3 = W.config3()
+        x03 = torch.from_numpy(W.initial_guess(q3)).cuda()
+        with B.setup(q3, rtol=1e-10, restart=30, maxit=20000, precision=B.RT_PREC_MIXED,
+                     autotune=True) as h:
+            d, inf, x3 = time_solves(torch, h, x03, "gmres", 3, 1)
+            out["c3_mixed_solves_per_s"] = 3 / d
+            out["c3_mixed_iterations"] = inf[0].iterations
+            out["c3_mixed_outer_steps"] = inf[0].outer_steps
+            v3 = W.random_vector(q3.n_unknowns, 1)
+            y3 = h.apply_op_fp32(torch.from_numpy(v3).cuda()).cpu().numpy()
+            out["c3_matvec_us_fp32"] = 1e3 * time_ops(
+                torch, h.apply_op_fp32, torch.from_numpy(v3).cuda(),
+                torch.empty(q3.n_unknowns, dtype=torch.float64, device="cuda"), 100)
+        with B.setup(q3, rtol=1e-10, restart=30, maxit=20000, autotune=True) as h:
+            d, inf, _ = time_solves(torch, h, x03, "gmres", 3, 1)
+            out["c3_fp64_solves_per_s"] = 3 / d
+        b3 = O.rhs(q3)
+        x3h = x3.cpu().numpy()
+        out["c3_mixed_oracle_relres"] = float(np.linalg.norm(b3 - O.apply(q3, x3h)) /
+                                              np.linalg.norm(b3))
+        out["fp32_op_error_c3"] = normwise(O.apply(q3, v3), v3, y3)
+
+        # the tiny configuration: forward error against LU with kappa
+        q1 = W.config1()
+        A1 = O.assemble(q1)
+        b1 = O.rhs(q1)
+        xlu = np.linalg.solve(A1, b1)
+        with B.setup(q1, rtol=1e-10, precision=B.RT_PREC_MIXED) as h:
+            x1 = torch.from_numpy(W.initial_guess(q1)).cuda()
+            h.solve_gmres(x1)
+            x1 = x1.cpu().numpy()
+        out["forward_error_c1"] = {"mixed": float(np.linalg.norm(x1 - xlu) / np.linalg.norm(xlu)),
+                                   "kappa2": float(np.linalg.cond(A1)),
+                                   "relres": float(np.linalg.norm(b1 - A1 @ x1) / np.linalg.norm(b1))}
+
         # the single paper-shaped slab (Ns = 200, 20 mu, 101 nu), FP64
         q = W.config2("delo_linear")
         xq = torch.from_numpy(W.initial_guess(q)).cuda()
         with B.setup(q, rtol=1e-10, restart=30) as h:
-            d, inf = time_solves(torch, h, xq, "gmres", 20, 3)
+            d, inf, _ = time_solves(torch, h, xq, "gmres", 20, 3)
             out["c2_gmres_solves_per_s"] = 20 / d
             out["c2_gmres_iterations"] = inf[0].iterations
-            d, inf = time_solves(torch, h, xq, "bicgstab", 10, 2)
+            d, inf, _ = time_solves(torch, h, xq, "bicgstab", 10, 2)
             out["c2_bicgstab_solves_per_s"] = 10 / d
             out["c2_bicgstab_iterations"] = inf[0].iterations
             vq = torch.from_numpy(W.random_vector(q.n_unknowns, 0)).cuda()
             out["c2_matvec_us"] = 1e3 * time_ops(torch, h.apply_op, vq, torch.empty_like(vq), 500)
         with B.setup(q, rtol=1e-10, maxit=200000) as h:
-            d, inf = time_solves(torch, h, xq, "richardson", 3, 1)
+            d, inf, _ = time_solves(torch, h, xq, "richardson", 3, 1)
             out["c2_richardson_solves_per_s"] = 3 / d
             out["c2_richardson_iterations"] = inf[0].iterations
 
+    roof = roofline_hbm(b32, t32 * 1e3, kname32, measured_traffic("fp32"))
+    roof["coef_mode"] = MODE_NAMES[cm32]
     line = {
         "metric": METRIC,
         "value": value,
@@ -462,14 +634,11 @@ def main():
                    "n_slabs": 512, "ns_range": [64, 512], "n_mu": 16, "n_nu": 101,
                    "formal_solver": "DELO-linear", "restart": 30, "rtol": RTOL,
                    "seed": W.SEED_BASE + 4},
-        "roofline": {"bound": "hbm", "achieved": a32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": a32 / HBM_PEAK_GBS, "traffic": measured_traffic("fp32"),
-                     "kernel": kname32 + " + rt::finalize_kernel",
-                     "bytes_per_launch": b32, "launch_us": t32 * 1e3},
+        "roofline": roof,
     }
     line.update(out)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(p, dinv)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu["line"]
     print(json.dumps(line), flush=True)
 
 

@@ -197,6 +197,17 @@ typedef struct rt_problem {
  *              1.5 for Richardson, 1 for the Krylov methods)
  *  coef_mode   where the sweep takes its step coefficients from: one of the
  *              RT_COEF_* values above (RT_COEF_AUTO)
+ *  autotune    1 = apply the launch plan stored for this problem's shape
+ *              (chunk, sweep_waves, prefetch, wave_batches, coef_mode), for
+ *              the fields left automatic (0); 0 = do not look (default).  A
+ *              stored plan that fails validation for these options is not
+ *              applied.  rt_tuned_plan_status reports what was found
+ *  plan_file   the plan file autotune reads: NULL means the file named by the
+ *              environment variable RT_TUNE_PLANS, else tuned_plans.txt in
+ *              the directory of this library.  Text, one plan per line:
+ *                key chunk sweep_waves prefetch wave_batches coef_mode source
+ *              key as rt_plan_key writes it, source the rt_sweep_source_hash
+ *              of the build it was measured with; '#' starts a comment line
  */
 typedef struct rt_options {
     int precision;
@@ -215,6 +226,8 @@ typedef struct rt_options {
     int precond;
     double omega;
     int coef_mode;
+    int autotune;
+    const char *plan_file;
 } rt_options;
 
 /* Per-slab outcome of a solve. */

@@ -62,6 +62,24 @@ int rt_sweep_config(const rt_handle *h, int fp32, int *waves, int *prefetch);
 int rt_sweep_coef_mode(const rt_handle *h, int fp32, int *mode);
 
 /*
+ * Stored launch plans (rt_options.autotune).  rt_tuned_plan_status: 0 = no
+ * plan was stored for the handle's problem (or autotune was off), 1 = a plan
+ * measured with this build's sweep sources was applied, 2 = a plan measured
+ * with other sources was applied (stale: re-tune).  rt_sweep_source_hash: the
+ * hash of the sweep sources this library was built from.  rt_plan_key: the
+ * key of problem p at precision (RT_PREC_*) on architecture arch (NULL: the
+ * current device's, e.g. "gfx950"), written NUL-terminated into buf of
+ * buflen bytes (RT_EINVAL if too short).  Host only.
+ */
+int rt_tuned_plan_status(const rt_handle *h);
+/* The options the handle runs with: the caller's, with the stored plan's
+ * fields filled in where options.autotune applied one (plan_file is returned
+ * as NULL).  Host only. */
+int rt_get_options(const rt_handle *h, rt_options *o);
+const char *rt_sweep_source_hash(void);
+int rt_plan_key(const rt_problem *p, int precision, const char *arch, char *buf, int buflen);
+
+/*
  * Number of doubles of the assembled operator: the sum over slabs of
  * (2 ns)^2.  Host only.
  */

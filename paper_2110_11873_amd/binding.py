@@ -33,7 +33,8 @@ EXPORTS = ["rt_default_options", "rt_setup", "rt_destroy", "rt_num_unknowns", "r
            "rt_precond_jacobi", "rt_get_rhs", "rt_get_jacobi_diag", "rt_solve_gmres",
            "rt_solve_bicgstab", "rt_solve_richardson", "rt_solve_cgs", "rt_last_error",
            "rt_apply_op_fp32",
-           "rt_plan_info", "rt_sweep_config", "rt_sweep_coef_mode", "rt_validate", "rt_assembled_size", "rt_assemble",
+           "rt_plan_info", "rt_sweep_config", "rt_sweep_coef_mode", "rt_validate",
+           "rt_tuned_plan_status", "rt_sweep_source_hash", "rt_plan_key", "rt_get_options", "rt_assembled_size", "rt_assemble",
            "rt_precond_apply", "rt_solve_lu", "rt_field_size", "rt_apply_op_field",
            "rt_get_rhs_field", "rt_sigma_from_field", "rt_solve_field_gmres",
            "rt_set_redistribution", "rt_prd_size", "rt_apply_op_prd", "rt_apply_op_prd_bf16x3", "rt_get_rhs_prd",
@@ -65,6 +66,7 @@ class rt_options(C.Structure):
         ("chunk", C.c_int), ("wave_batches", C.c_int), ("prefetch", C.c_int),
         ("check_every", C.c_int), ("sweep_waves", C.c_int), ("graphs", C.c_int),
         ("precond", C.c_int), ("omega", C.c_double), ("coef_mode", C.c_int),
+        ("autotune", C.c_int), ("plan_file", C.c_char_p),
     ]
 
 
@@ -104,6 +106,11 @@ def lib():
                                    C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         L.rt_sweep_config.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.rt_sweep_coef_mode.argtypes = [vp, C.c_int, C.POINTER(C.c_int)]
+        L.rt_tuned_plan_status.argtypes = [vp]
+        L.rt_get_options.argtypes = [vp, C.POINTER(rt_options)]
+        L.rt_sweep_source_hash.argtypes = []
+        L.rt_sweep_source_hash.restype = C.c_char_p
+        L.rt_plan_key.argtypes = [C.POINTER(rt_problem), C.c_int, C.c_char_p, C.c_char_p, C.c_int]
         L.rt_validate.argtypes = [C.POINTER(rt_problem), C.POINTER(rt_options)]
         L.rt_assembled_size.argtypes = [vp, C.POINTER(C.c_longlong)]
         L.rt_field_size.argtypes = [vp, C.POINTER(C.c_longlong)]
@@ -138,8 +145,24 @@ def default_options(**kw) -> rt_options:
     for k, v in kw.items():
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
+        if k == "plan_file" and isinstance(v, str):
+            v = v.encode()
         setattr(o, k, v)
     return o
+
+
+def sweep_source_hash() -> str:
+    """Hash of the sweep sources the loaded library was built from."""
+    return lib().rt_sweep_source_hash().decode()
+
+
+def plan_key(prob, mixed: bool, arch: Optional[str] = None) -> str:
+    """The key under which the launch plan of `prob` is stored (rt_plan_key)."""
+    pb = _ProblemBuffers(prob)
+    buf = C.create_string_buffer(256)
+    _check(lib().rt_plan_key(C.byref(pb.c), RT_PREC_MIXED if mixed else RT_PREC_FP64,
+                             arch.encode() if arch else None, buf, 256))
+    return buf.value.decode()
 
 
 class _ProblemBuffers:
@@ -273,6 +296,17 @@ class Handle:
         _check(lib().rt_sweep_coef_mode(self._h, 1 if fp32 else 0, C.byref(cm)))
         return dict(waves=w.value, prefetch=pf.value, coef_mode=cm.value)
 
+    def effective_options(self) -> rt_options:
+        """The options the handle runs with (a stored plan applied)."""
+        o = rt_options()
+        _check(lib().rt_get_options(self._h, C.byref(o)))
+        return o
+
+    def tuned_plan_status(self):
+        """'none', 'current' (a stored plan measured with this build's sweep
+        sources was applied) or 'stale' (one measured with other sources)."""
+        return {0: "none", 1: "current", 2: "stale"}[lib().rt_tuned_plan_status(self._h)]
+
     def sweep_kernel_name(self, fp32=False):
         """The sweep kernel rt_apply_op(_fp32) launches, as profilers name it."""
         c = self.sweep_config(fp32)
@@ -404,12 +438,10 @@ class Handle:
 
 
 def setup(prob, options: Optional[rt_options] = None, autotune: bool = False, **kw) -> Handle:
-    """Set up `prob` on the current GPU.  autotune=True applies the launch
-    plan the autotuner stored for this problem shape and precision (see
-    paper_2110_11873_amd.autotune), where the caller did not set it."""
+    """Set up `prob` on the current GPU.  autotune=True sets options.autotune:
+    the library applies the launch plan stored for this problem shape and
+    precision (paper_2110_11873_amd.autotune writes it) where the caller did
+    not set the field."""
     if autotune and options is None:
-        from . import autotune as AT
-        tuned = AT.lookup(prob, kw.get("precision", RT_PREC_FP64) == RT_PREC_MIXED)
-        if tuned:
-            kw = {**tuned, **kw}
+        kw = {"autotune": 1, **kw}
     return Handle(prob, options, **kw)

@@ -8,6 +8,7 @@ into paper_2110_11873_amd/librt.so.  Packed FP32 instructions are disabled for t
 device code (-packed-fp32-ops); hipcc's host pass warns that it does not know
 the feature, which is harmless.
 """
+import hashlib
 import os
 import subprocess
 import sys
@@ -24,6 +25,20 @@ SOURCES = ["rt_api.hip", "rt_sweep.hip", "rt_sweep_f32.hip", "rt_sweep_f64.hip",
            "rt_assemble.hip", "rt_dense.hip", "rt_raysweep.hip", "rt_field.hip",
            "rt_fieldsolve.hip", "rt_prd.hip"]
 OBJDIR = os.path.join(PKG, "_build")
+# the sources of the sweep's kernels and launchers: their hash is built into
+# the library, and stored launch plans and counter readings are trusted only
+# while it is unchanged
+SWEEP_SOURCES = ["rt_sweep_kernel.h", "rt_sweep.hip", "rt_sweep_f32.hip", "rt_sweep_f64.hip",
+                 "rt_sweep_f32_w.hip", "rt_sweep_f64_w.hip", "rt_sweep_f32_rc.hip",
+                 "rt_sweep_f64_rc.hip", "rt_coef.h"]
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -44,8 +59,9 @@ def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     tag = f".{os.getpid()}"
     objs = [os.path.join(OBJDIR, os.path.splitext(src)[0] + tag + ".o") for src in SOURCES]
-    cmds = [[hipcc, *FLAGS, "-I", INCLUDE, "-I", HERE, "-c", os.path.join(HERE, src), "-o", obj]
-            for src, obj in zip(SOURCES, objs)]
+    define = f'-DRT_SWEEP_SOURCE_HASH="{sweep_source_hash()}"'
+    cmds = [[hipcc, *FLAGS, define, "-I", INCLUDE, "-I", HERE, "-c", os.path.join(HERE, src), "-o",
+             obj] for src, obj in zip(SOURCES, objs)]
     jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
     with ThreadPoolExecutor(jobs) as ex:
         results = list(ex.map(lambda c: _run(c, verbose), cmds))

@@ -1,5 +1,6 @@
 // rt_api.hip -- host runtime behind include/rt.h: validation, launch
 // planning, device memory, setup kernels, and the C entry points.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -7,11 +8,17 @@
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <fstream>
 #include <numeric>
+#include <sstream>
 #include <string>
 #include <vector>
 
 #include "rt_internal.h"
+
+#ifndef RT_SWEEP_SOURCE_HASH
+#define RT_SWEEP_SOURCE_HASH "unknown"
+#endif
 
 namespace rt {
 
@@ -155,8 +162,84 @@ int validate(const rt_problem *p, const rt_options *o, std::vector<double> &mu_p
             return fail(RT_EINVAL, "options.omega must lie in (0, 2)");
         if (o->coef_mode < RT_COEF_AUTO || o->coef_mode > RT_COEF_RECOMPUTE_FP32)
             return fail(RT_EINVAL, "options.coef_mode must be one of the RT_COEF_* values");
+        if (o->autotune != 0 && o->autotune != 1)
+            return fail(RT_EINVAL, "options.autotune must be 0 or 1");
     }
     return RT_OK;
+}
+
+// ---- stored launch plans (the autotuner's cache, read by rt_setup) --------
+// Key of a problem shape: architecture, precision, formal solver, directions,
+// frequencies, slabs, deepest slab and a 64-bit FNV-1a hash of the depth
+// counts -- the features the sweep's launch plan depends on.
+std::string plan_key(const rt_problem *p, int precision, const std::string &arch) {
+    unsigned long long f = 0xcbf29ce484222325ULL;
+    int ns_max = 0;
+    for (int a = 0; a < p->n_atm; ++a) {
+        const unsigned int v = (unsigned int)p->ns[a];
+        for (int b = 0; b < 4; ++b) {
+            f ^= (v >> (8 * b)) & 0xffu;
+            f *= 0x100000001b3ULL;
+        }
+        ns_max = std::max(ns_max, p->ns[a]);
+    }
+    char hex[17];
+    std::snprintf(hex, sizeof hex, "%016llx", f);
+    std::ostringstream k;
+    k << arch << '|' << (precision == RT_PREC_MIXED ? "mixed" : "fp64") << '|' << p->formal_solver
+      << '|' << p->n_mu << '|' << p->n_nu << '|' << p->n_atm << '|' << ns_max << '|' << hex;
+    return k.str();
+}
+
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "";
+    }
+    std::string a = prop.gcnArchName;
+    return a.substr(0, a.find(':'));
+}
+
+// The plan file: options.plan_file, else $RT_TUNE_PLANS, else
+// tuned_plans.txt in the directory of this library.
+std::string plan_file_path(const rt_options &o) {
+    if (o.plan_file && o.plan_file[0]) return o.plan_file;
+    const char *env = std::getenv("RT_TUNE_PLANS");
+    if (env && env[0]) return env;
+    Dl_info info;
+    if (dladdr((void *)&plan_key, &info) && info.dli_fname) {
+        std::string lib = info.dli_fname;
+        const size_t slash = lib.rfind('/');
+        return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) +
+               "/tuned_plans.txt";
+    }
+    return "tuned_plans.txt";
+}
+
+// Apply the stored plan for this problem to the options the caller left
+// automatic (0).  Returns 0 when none is stored, 1 when the plan was made
+// with this build's sweep sources, 2 when with other sources.
+int apply_stored_plan(const rt_problem *p, rt_options *o, const std::string &arch) {
+    std::ifstream in(plan_file_path(*o));
+    if (!in) return 0;
+    const std::string key = plan_key(p, o->precision, arch);
+    std::string line;
+    while (std::getline(in, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream ls(line);
+        std::string k, src;
+        int chunk, waves, pf, nb, cm;
+        if (!(ls >> k >> chunk >> waves >> pf >> nb >> cm >> src) || k != key) continue;
+        if (o->chunk == 0) o->chunk = chunk;
+        if (o->sweep_waves == 0) o->sweep_waves = waves;
+        if (o->prefetch == 0) o->prefetch = pf;
+        if (o->wave_batches == 0) o->wave_batches = nb;
+        if (o->coef_mode == RT_COEF_AUTO) o->coef_mode = cm;
+        return src == RT_SWEEP_SOURCE_HASH ? 1 : 2;
+    }
+    return 0;
 }
 
 // Coefficient modes (kCoef*) of the FP64 and FP32 sweeps for options.coef_mode.
@@ -378,6 +461,8 @@ void rt_default_options(rt_options *o) {
     o->omega = 1.0;
     o->check_every = 16;
     o->coef_mode = RT_COEF_AUTO;
+    o->autotune = 0;
+    o->plan_file = nullptr;
 }
 
 const char *rt_last_error(void) { return g_err.c_str(); }
@@ -434,9 +519,26 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
         return fail(RT_EDEVICE, std::string("this library is built for gfx950, device is ") +
                                     prop.gcnArchName);
 
+    int plan_status = 0;
+    if (opt.autotune) {
+        const rt_options asked = opt;
+        plan_status = apply_stored_plan(p, &opt, device_arch());
+        // a stored plan that does not fit these options or slabs is not applied
+        bool fits = true;
+        for (int a = 0; a < p->n_atm && opt.chunk; ++a)
+            fits = fits && (long long)kWave * opt.chunk >= p->ns[a] - 1;
+        if (plan_status && (!fits || validate(p, &opt, mu_pos, w_pos, &mu_index) != RT_OK)) {
+            opt = asked;
+            plan_status = 0;
+            rc = validate(p, &opt, mu_pos, w_pos, &mu_index);
+            if (rc != RT_OK) return rc;
+        }
+    }
+
     rt_handle *h = new rt_handle();
     h->device = dev;
     h->opt = opt;
+    h->plan_status = plan_status;
     resolve_coef_modes(opt.coef_mode, &h->cm64, &h->cm32);
     h->n_atm = p->n_atm;
     h->n_mu = p->n_mu;
@@ -783,6 +885,28 @@ int rt_sweep_config(const rt_handle *h, int fp32, int *waves, int *prefetch) {
     sweep_config(h, fp32 != 0, &W, &pf);
     if (waves) *waves = W;
     if (prefetch) *prefetch = pf ? 1 : 0;
+    return RT_OK;
+}
+
+int rt_tuned_plan_status(const rt_handle *h) { return h ? h->plan_status : 0; }
+
+int rt_get_options(const rt_handle *h, rt_options *o) {
+    if (!h || !o) return fail(RT_EINVAL, "NULL handle or output");
+    *o = h->opt;
+    o->plan_file = nullptr;  // the caller's string is not kept
+    return RT_OK;
+}
+
+const char *rt_sweep_source_hash(void) { return RT_SWEEP_SOURCE_HASH; }
+
+int rt_plan_key(const rt_problem *p, int precision, const char *arch, char *buf, int buflen) {
+    if (!p || !p->ns || p->n_atm < 1 || !buf || buflen < 1)
+        return fail(RT_EINVAL, "NULL problem or buffer");
+    const std::string a = arch ? std::string(arch) : device_arch();
+    if (a.empty()) return fail(RT_EDEVICE, "no device to take the architecture from");
+    const std::string k = plan_key(p, precision, a);
+    if ((int)k.size() + 1 > buflen) return fail(RT_EINVAL, "buffer too short for the plan key");
+    std::memcpy(buf, k.c_str(), k.size() + 1);
     return RT_OK;
 }
 

@@ -259,6 +259,7 @@ struct rt_handle {
     double2 *d_kt = nullptr;      // tile-ordered (kappa, 1 / kappa) per ray
     double *d_dtau = nullptr;     // tau_{k+1} - tau_k per depth point
     int cm64 = 0, cm32 = 0;       // coefficient modes of the FP64 and FP32 sweeps
+    int plan_status = 0;          // stored launch plan: 0 none, 1 current, 2 other sources
     double *d_partial = nullptr;
     double *d_diag = nullptr, *d_dinv = nullptr, *d_b = nullptr;
     double *d_rpart = nullptr;    // ray-per-lane sweep: per-wavefront quadrature slots

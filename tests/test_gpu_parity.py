@@ -516,3 +516,35 @@ def test_invalid_inputs_rejected_before_device_use():
     with pytest.raises(B.RTError) as e:
         B.setup(p.with_(mu=np.abs(p.mu)))
     assert e.value.code == B.RT_EINVAL
+
+
+def test_mixed_solve_config3_against_oracle():
+    """One 1024-point atmosphere (32 mu x 201 nu, Voigt a from a seeded
+    log-uniform draw): FP32 sweeps inside inner GMRES(30), FP64 iterative
+    refinement to ||b - A x|| / ||b|| < 1e-10, checked with the oracle's own
+    FP64 operator and right-hand side."""
+    p = W.config3()
+    with B.setup(p, rtol=1e-10, restart=30, maxit=20000, precision=B.RT_PREC_MIXED) as h:
+        rc, info, x = _solve(h, "gmres", p)
+        v = W.random_vector(p.n_unknowns, 13)
+        y32 = host(h.apply_op_fp32(dev(v)))
+    assert rc == 0 and info[0].status == "converged", info
+    assert info[0].outer_steps >= 2
+    assert oracle_relres(p, x).max() < 1e-10
+    # the inner operator's own error against the oracle (FP32 rounding level)
+    assert 1e-12 < normwise(p, v, y32) < 1e-5
+
+
+def test_full_batch_mixed_solve_sampled_slabs():
+    """The benchmark's own solve (all 512 slabs, mixed precision to 1e-9, the
+    stored launch plan) checked slab by slab by the oracle on a sample."""
+    p = W.config4(n_slabs=512)
+    with B.setup(p, rtol=1e-9, restart=30, maxit=20000, precision=B.RT_PREC_MIXED,
+                 autotune=True) as h:
+        rc, info, x = _solve(h, "gmres", p)
+    assert all(i.status == "converged" for i in info)
+    sl = O._slices(p)
+    for i in (0, 1, 97, 255, 256, 400, 511):
+        b = O.rhs(p.slab(i))
+        r = b - O.apply_slab(p, i, x[sl[i]])
+        assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-9, i
