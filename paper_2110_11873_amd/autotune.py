@@ -136,7 +136,7 @@ def tune(prob, mixed, reps=20, verbose=False, cands=None, solve_top=4, solve_kw=
     x0 = torch.from_numpy(W.initial_guess(prob)).cuda()
     w32 = MIXED_FP32_SHARE if mixed else 0.0
     prec = B.RT_PREC_MIXED if mixed else B.RT_PREC_FP64
-    skw = dict(restart=30, rtol=1e-9, maxit=20000, **(solve_kw or {}))
+    skw = {**dict(restart=30, rtol=1e-9, maxit=20000), **(solve_kw or {})}
     table = []
     for c in (cands or candidates(prob, mixed)):
         with B.setup(prob, **c) as h:
