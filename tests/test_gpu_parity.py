@@ -429,8 +429,12 @@ def test_gmres_tail_plan(mixed):
         assert all(i.status == "converged" for i in info), (fixed, info)
         assert oracle_relres(sub, x).max() < 1e-9, fixed
         out[fixed] = [i.iterations for i in info]
+    # mixed precision: the two plans add the rays' FP32 quadrature sums in a
+    # different block order, which moves where the inner solves (to a relative
+    # 3e-4) stop; 117 against 110 steps has been seen on one slab
+    band = 10 if mixed else 20
     for a, b in zip(out[False], out[True]):
-        assert abs(a - b) <= max(2, b // 20), out
+        assert abs(a - b) <= max(2, b // band), out
 
 
 def test_paper_richardson_counts_on_gpu():
