@@ -69,7 +69,8 @@ def measured_traffic(kind):
 
 def op_only(kind, n, coef_mode=0):
     """The operator leg alone (for counter passes): n applications, in the
-    tuned launch plan, or with its coefficient mode replaced."""
+    tuned launch plan of the mixed solve (FP32) or of the FP64 solve (FP64),
+    or with its coefficient mode replaced."""
     import torch
     from paper_2110_11873_amd import binding as B
     from paper_2110_11873_amd import workloads as W
@@ -77,7 +78,8 @@ def op_only(kind, n, coef_mode=0):
     p = W.config4(512)
     # the handle (and launch plan) the bench times the operator on
     kw = dict(coef_mode=coef_mode) if coef_mode else {}
-    with B.setup(p, precision=B.RT_PREC_MIXED, autotune=True, **kw) as h:
+    prec = B.RT_PREC_MIXED if kind == "fp32" else B.RT_PREC_FP64
+    with B.setup(p, precision=prec, autotune=True, **kw) as h:
         v = torch.from_numpy(W.random_vector(p.n_unknowns, 0)).cuda()
         y = torch.empty_like(v)
         f = h.apply_op_fp32 if kind == "fp32" else h.apply_op
@@ -415,6 +417,24 @@ def normwise(ref, v, y):
     return float(np.abs(y - ref).max() / (np.abs(v).max() + np.abs(v - ref).max()))
 
 
+# FP32 (and FP64) vector peak with packed FP32 instructions off (as this
+# library is built): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+ALU_PEAK_TFLOPS = 78.6
+# algorithmic flops of one ray-interval (both directions, both sources) by
+# coefficient mode: recurrences 4 FMA and quadrature 4 FMA (16), w (S_u - S_k)
+# for the two sources (2); E = 1 - w d with d = kappa dtau (3, w streamed);
+# d, exp(-d), w = (1 - E) / d (5, recomputed)
+FLOPS_PER_INTERVAL = {0: 18, 1: 21, 2: 23}
+
+
+def roofline_alu(flops, us, kname, traffic):
+    a = flops / (us * 1e-6) / 1e12
+    return {"bound": "alu", "achieved": a, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": a / ALU_PEAK_TFLOPS, "traffic": traffic,
+            "kernel": kname + " + rt::finalize_kernel", "flops_per_launch": flops,
+            "launch_us": us}
+
+
 def roofline_hbm(bytes_, us, kname, traffic):
     a = bytes_ / (us * 1e-6) / 1e9
     return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -482,7 +502,7 @@ def main():
                                             fp32_sweep=MODE_NAMES[cfg32["coef_mode"]],
                                             fp64_sweep=MODE_NAMES[cfg64["coef_mode"]],
                                             status=h.tuned_plan_status())}
-        kname32, kname64 = h.sweep_kernel_name(True), h.sweep_kernel_name(False)
+        kname32 = h.sweep_kernel_name(True)
         dt, info, xg = time_solves(torch, h, x0, "gmres", args.steps, args.warmup)
         value = p.n_atm * args.steps / dt
         ms_step = 1e3 * dt / args.steps
@@ -494,14 +514,9 @@ def main():
         x_mixed = xg.cpu().numpy()
         t32 = time_ops(torch, h.apply_op_fp32, v, y, args.matvecs)
         y32 = y.cpu().numpy()
-        t64 = time_ops(torch, h.apply_op, v, y, args.matvecs)
-    cm32, cm64 = cfg32["coef_mode"], cfg64["coef_mode"]
-    b32, b64 = op_bytes(p, plan, cm32, 4), op_bytes(p, plan, cm64, 8)
+    cm32 = cfg32["coef_mode"]
     out["matvecs_per_s_fp32"] = 1e3 / t32
-    out["matvecs_per_s_fp64"] = 1e3 / t64
     out["matvec_us_fp32"] = t32 * 1e3
-    out["matvec_us_fp64"] = t64 * 1e3
-    out["roofline_fp64"] = roofline_hbm(b64, t64 * 1e3, kname64, measured_traffic("fp64"))
     out["sweep_plan"] = plan
 
     # the operator in every coefficient mode, with the tuned plan otherwise
@@ -512,17 +527,23 @@ def main():
             u32 = time_ops(torch, hm.apply_op_fp32, v, y, max(20, args.matvecs // 3)) * 1e3
             u64 = time_ops(torch, hm.apply_op, v, y, max(20, args.matvecs // 3)) * 1e3
         m32, m64 = op_bytes(p, plan, cm, 4), op_bytes(p, plan, cm, 8)
+        fl = FLOPS_PER_INTERVAL[cm] * plan["intervals"]
         modes[MODE_NAMES[cm]] = {"fp32_us": u32, "fp64_us": u64,
                                  "fp32_bytes": m32, "fp64_bytes": m64,
                                  "fp32_hbm_frac": m32 / (u32 * 1e-6) / 1e9 / HBM_PEAK_GBS,
-                                 "fp64_hbm_frac": m64 / (u64 * 1e-6) / 1e9 / HBM_PEAK_GBS}
+                                 "fp64_hbm_frac": m64 / (u64 * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                                 "flops": fl,
+                                 "fp32_alu_frac": fl / (u32 * 1e-6) / 1e12 / ALU_PEAK_TFLOPS,
+                                 "fp64_alu_frac": fl / (u64 * 1e-6) / 1e12 / ALU_PEAK_TFLOPS}
     out["coef_modes"] = modes
 
     with B.setup(p, rtol=RTOL, restart=30, maxit=20000, autotune=True) as h:
+        cm64 = h.sweep_config(False)["coef_mode"]
+        kname64 = h.sweep_kernel_name(False)
         out["launch_plan"]["fp64"] = dict(chunk=h.plan_info()["chunk"],
                                           sweep_waves=h.sweep_config(False)["waves"],
                                           coef_mode=h.effective_options().coef_mode,
-                                          fp64_sweep=MODE_NAMES[h.sweep_config(False)["coef_mode"]],
+                                          fp64_sweep=MODE_NAMES[cm64],
                                           status=h.tuned_plan_status())
         n64 = max(2, args.steps // 2)
         dt64, info64, xg64 = time_solves(torch, h, x0, "gmres", n64, 1)
@@ -530,6 +551,16 @@ def main():
         out["fp64_converged"] = sum(i.status == "converged" for i in info64)
         out["fp64_iterations_max"] = max(i.iterations for i in info64)
         x_fp64 = xg64.cpu().numpy()
+        t64 = time_ops(torch, h.apply_op, v, y, args.matvecs)
+    out["matvecs_per_s_fp64"] = 1e3 / t64
+    out["matvec_us_fp64"] = t64 * 1e3
+    if cm64 == 2:
+        out["roofline_fp64"] = roofline_alu(FLOPS_PER_INTERVAL[2] * plan["intervals"], t64 * 1e3,
+                                            kname64, measured_traffic("fp64"))
+    else:
+        out["roofline_fp64"] = roofline_hbm(op_bytes(p, plan, cm64, 8), t64 * 1e3, kname64,
+                                            measured_traffic("fp64"))
+    out["roofline_fp64"]["coef_mode"] = MODE_NAMES[cm64]
     out["mixed_over_fp64"] = value / out["fp64_solves_per_s"]
     out["hbm_copy_GBs"] = copy_bandwidth(torch)  # measured, beside the 8 TB/s datasheet peak
 
@@ -614,7 +645,12 @@ def main():
             out["c2_richardson_solves_per_s"] = 3 / d
             out["c2_richardson_iterations"] = inf[0].iterations
 
-    roof = roofline_hbm(b32, t32 * 1e3, kname32, measured_traffic("fp32"))
+    if cm32 == 2:
+        roof = roofline_alu(FLOPS_PER_INTERVAL[2] * plan["intervals"], t32 * 1e3, kname32,
+                            measured_traffic("fp32"))
+    else:
+        roof = roofline_hbm(op_bytes(p, plan, cm32, 4), t32 * 1e3, kname32,
+                            measured_traffic("fp32"))
     roof["coef_mode"] = MODE_NAMES[cm32]
     line = {
         "metric": METRIC,

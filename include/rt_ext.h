@@ -22,6 +22,7 @@ extern "C" {
  */
 int rt_apply_op_fp32(rt_handle *h, const double *sigma_in, double *sigma_out, void *stream);
 
+
 /*
  * Solve A x = b with the conjugate gradient squared method (Sect. 2.2;
  * Sonneveld), right-preconditioned by Jacobi: two products by A per step, none

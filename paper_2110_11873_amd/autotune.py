@@ -204,6 +204,7 @@ def main(argv=None):
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--solve-top", type=int, default=4)
+    ap.add_argument("--solve-reps", type=int, default=3)
     ap.add_argument("--cache", default=None)
     args = ap.parse_args(argv)
     modes = {"fp64": [False], "mixed": [True], "both": [False, True]}[args.precision]
@@ -212,7 +213,8 @@ def main(argv=None):
         prob = make()
         for mixed in modes:
             best, table = tune(prob, mixed, reps=args.reps, verbose=True,
-                               solve_top=args.solve_top, solve_kw=skw)
+                               solve_top=args.solve_top, solve_kw=skw,
+                               solve_reps=args.solve_reps)
             store(prob, mixed, best, table, path=args.cache)
             print(json.dumps(dict(config=name, mixed=mixed, best=best)), flush=True)
     return 0
