@@ -22,6 +22,25 @@ extern "C" {
  */
 int rt_apply_op_fp32(rt_handle *h, const double *sigma_in, double *sigma_out, void *stream);
 
+/*
+ * For callers that cannot allocate device memory at call time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * sigma_out = A sigma_in exactly as rt_apply_op computes it (same kernels,
+ * same launch plan, same result bit for bit), with the sweep's per-workgroup
+ * partial quadrature sums kept in a fixed device array of
+ * RT_NOALLOC_MAX_PARTIAL doubles (32 MiB) that the library holds on every
+ * GPU it runs on until the process ends, instead of the handle's buffer.
+ * The call allocates nothing.  The handle's sweep must need at most
+ * RT_NOALLOC_MAX_PARTIAL partial sums (the 512-slab batch of up to 512
+ * depths, 16 directions and 101 frequencies needs about 2.4 million), else
+ * RT_EINVAL; the DELO-parabolic solver is not supported (RT_EINVAL); the
+ * handle's device must be current (RT_EINVAL).  Every call on one GPU uses
+ * that GPU's one array: calls that overlap in time on one GPU (different
+ * streams or handles) race and give wrong results.  Stream-ordered; in-place
+ * allowed as for rt_apply_op.
+ */
+#define RT_NOALLOC_MAX_PARTIAL (4LL * 1024 * 1024)
+int rt_apply_op_noalloc(rt_handle *h, const double *sigma_in, double *sigma_out, void *stream);
 
 /*
  * Solve A x = b with the conjugate gradient squared method (Sect. 2.2;

@@ -32,7 +32,7 @@ STATUS_NAMES = {RT_OK: "converged", RT_ENOCONV: "maxit", RT_EBREAKDOWN: "breakdo
 EXPORTS = ["rt_default_options", "rt_setup", "rt_destroy", "rt_num_unknowns", "rt_apply_op",
            "rt_precond_jacobi", "rt_get_rhs", "rt_get_jacobi_diag", "rt_solve_gmres",
            "rt_solve_bicgstab", "rt_solve_richardson", "rt_solve_cgs", "rt_last_error",
-           "rt_apply_op_fp32",
+           "rt_apply_op_fp32", "rt_apply_op_noalloc",
            "rt_plan_info", "rt_sweep_config", "rt_sweep_coef_mode", "rt_validate",
            "rt_tuned_plan_status", "rt_sweep_source_hash", "rt_plan_key", "rt_get_options", "rt_assembled_size", "rt_assemble",
            "rt_precond_apply", "rt_solve_lu", "rt_field_size", "rt_apply_op_field",
@@ -93,7 +93,8 @@ def lib():
         L.rt_destroy.argtypes = [vp]
         L.rt_destroy.restype = None
         L.rt_num_unknowns.argtypes = [vp]
-        for f in ("rt_apply_op", "rt_apply_op_fp32", "rt_precond_jacobi", "rt_precond_apply"):
+        for f in ("rt_apply_op", "rt_apply_op_fp32", "rt_apply_op_noalloc", "rt_precond_jacobi",
+                  "rt_precond_apply"):
             getattr(L, f).argtypes = [vp, vp, vp, vp]
         for f in ("rt_get_rhs", "rt_get_jacobi_diag"):
             getattr(L, f).argtypes = [vp, vp, vp]
@@ -256,6 +257,14 @@ class Handle:
         out = self._new() if sigma_out is None else sigma_out
         _check(lib().rt_apply_op_fp32(self._h, C.c_void_p(_ptr(sigma_in)), C.c_void_p(_ptr(out)),
                                       _stream(stream)))
+        return out
+
+    def apply_op_noalloc(self, sigma_in, sigma_out=None, stream=None):
+        """rt_apply_op_noalloc: the FP64 operator with its partial sums in the
+        library's fixed device array (no allocation in the call)."""
+        out = self._new() if sigma_out is None else sigma_out
+        _check(lib().rt_apply_op_noalloc(self._h, C.c_void_p(_ptr(sigma_in)),
+                                         C.c_void_p(_ptr(out)), _stream(stream)))
         return out
 
     def precond_jacobi(self, v, z=None, stream=None):

@@ -23,7 +23,7 @@ SOURCES = ["rt_api.hip", "rt_sweep.hip", "rt_sweep_f32.hip", "rt_sweep_f64.hip",
            "rt_sweep_f32_w.hip", "rt_sweep_f64_w.hip", "rt_sweep_f32_rc.hip", "rt_sweep_f64_rc.hip",
            "rt_krylov.hip",
            "rt_assemble.hip", "rt_dense.hip", "rt_raysweep.hip", "rt_field.hip",
-           "rt_fieldsolve.hip", "rt_prd.hip"]
+           "rt_fieldsolve.hip", "rt_prd.hip", "rt_noalloc.hip"]
 OBJDIR = os.path.join(PKG, "_build")
 # the sources of the sweep's kernels and launchers: their hash is built into
 # the library, and stored launch plans and counter readings are trusted only

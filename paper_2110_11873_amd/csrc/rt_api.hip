@@ -386,6 +386,19 @@ hipError_t apply_sweep(rt_handle *h, const double *in, const double *scale, cons
                         s);
 }
 
+hipError_t apply_operator_into(rt_handle *h, const double *in, double *out, double *partial,
+                               hipStream_t s) {
+    SweepArgs a = sweep_args(h, in, nullptr, out, nullptr, false, 0);
+    a.partial = partial;
+    int W;
+    bool pf;
+    sweep_config(h, false, &W, &pf);
+    hipError_t e = launch_sweep(h->L, W, pf, false, coef_mode_of(h, false), a, plan_blocks(h),
+                                h->ns_max, s);
+    if (e != hipSuccess) return e;
+    return launch_finalize(a, h->n_atm, h->ns_max, s);
+}
+
 hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, double *out,
                           const int *mask, bool fp32, int mode, hipStream_t s) {
     if (h->fs == RT_FS_DELO_PARABOLIC) return apply_ray_operator(h, in, scale, out, mask, mode, s);
@@ -702,6 +715,7 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     h->n_qt = qt;
     h->n_pairs = coef;
     h->n_partial = tail_plan ? std::max(part, part_t) : part;
+    h->n_partial_main = part;
     h->n_dense = dense;
     h->n_ew = ew;
 

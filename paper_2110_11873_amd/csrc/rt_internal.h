@@ -230,6 +230,7 @@ struct rt_handle {
     int NB = 1;                // wave-batches per wave (per block: W * NB)
     int n_blocks = 0;
     long long n_pairs = 0, n_partial = 0;
+    long long n_partial_main = 0;  // partial sums of the main plan's blocks
     // the tail plan over the same coefficient tiles (none when it would equal
     // the main plan); plan_tail selects it for the sweeps, their finalize pass
     // and the fused Arnoldi step, which all read the slab table it points to
@@ -331,6 +332,11 @@ inline int plan_blocks(const rt_handle *h) { return h->plan_tail ? h->n_blocks_t
 // mask is NULL): the sweep, then the finalize pass.  mode as in SweepArgs.
 hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, double *out,
                           const int *mask, bool fp32, int mode, hipStream_t s);
+// sigma_out = A sigma_in in FP64 (rt_apply_op) with the per-block partial
+// quadrature sums in `partial` (at least n_partial_main doubles) instead of
+// the handle's buffer; main plan, no scaling, no mask.
+hipError_t apply_operator_into(rt_handle *h, const double *in, double *out, double *partial,
+                               hipStream_t s);
 // The sweep of apply_operator (mode 0) alone: leaves the per-block quadrature
 // sums in h->d_partial for a consumer that applies the scattering step itself.
 hipError_t apply_sweep(rt_handle *h, const double *in, const double *scale, const int *mask,
