@@ -428,22 +428,37 @@ int ensure_workspace(rt_handle *h) {
     int rc;
     if ((rc = dalloc(&h->d_V, (size_t)(m + 1) * N)) != RT_OK) return rc;
     if (!h->d_H) {
-        // restart-independent buffers, sized for the largest restart
+        // restart-independent buffers, sized for the largest restart; all or
+        // none (a failure frees the ones already made, so a later call starts
+        // over rather than finding d_H without the rest)
         const int mm = RT_MAX_RESTART;
-        if ((rc = dalloc(&h->d_H, (size_t)h->n_atm * (mm + 1) * mm)) != RT_OK) return rc;
-        if ((rc = dalloc(&h->d_cs, (size_t)h->n_atm * mm)) != RT_OK) return rc;
-        if ((rc = dalloc(&h->d_sn, (size_t)h->n_atm * mm)) != RT_OK) return rc;
-        if ((rc = dalloc(&h->d_g, (size_t)h->n_atm * (mm + 1))) != RT_OK) return rc;
+        void **group[] = {(void **)&h->d_H,     (void **)&h->d_cs,    (void **)&h->d_sn,
+                          (void **)&h->d_g,     (void **)&h->d_w,     (void **)&h->d_r,
+                          (void **)&h->d_rh,    (void **)&h->d_p,     (void **)&h->d_v,
+                          (void **)&h->d_s,     (void **)&h->d_t,     (void **)&h->d_cq,
+                          (void **)&h->d_state, (void **)&h->d_active, (void **)&h->d_cycle,
+                          (void **)&h->d_count};
+        auto undo = [&](int code) {
+            for (void **q : group) {
+                if (*q) (void)hipFree(*q);
+                *q = nullptr;
+            }
+            return code;
+        };
+        if ((rc = dalloc(&h->d_H, (size_t)h->n_atm * (mm + 1) * mm)) != RT_OK) return undo(rc);
+        if ((rc = dalloc(&h->d_cs, (size_t)h->n_atm * mm)) != RT_OK) return undo(rc);
+        if ((rc = dalloc(&h->d_sn, (size_t)h->n_atm * mm)) != RT_OK) return undo(rc);
+        if ((rc = dalloc(&h->d_g, (size_t)h->n_atm * (mm + 1))) != RT_OK) return undo(rc);
         double **vecs[] = {&h->d_w, &h->d_r, &h->d_rh, &h->d_p, &h->d_v, &h->d_s, &h->d_t, &h->d_cq};
         for (double **v : vecs)
-            if ((rc = dalloc(v, (size_t)N)) != RT_OK) return rc;
-        if ((rc = dalloc(&h->d_state, (size_t)2 * h->n_atm)) != RT_OK) return rc;
-        if ((rc = dalloc(&h->d_active, (size_t)2 * h->n_atm)) != RT_OK) return rc;
-        if ((rc = dalloc(&h->d_cycle, (size_t)h->n_atm)) != RT_OK) return rc;
-        if ((rc = dalloc(&h->d_count, 1)) != RT_OK) return rc;
-        if (hipHostMalloc((void **)&h->h_count, sizeof(int)) != hipSuccess) {
+            if ((rc = dalloc(v, (size_t)N)) != RT_OK) return undo(rc);
+        if ((rc = dalloc(&h->d_state, (size_t)2 * h->n_atm)) != RT_OK) return undo(rc);
+        if ((rc = dalloc(&h->d_active, (size_t)2 * h->n_atm)) != RT_OK) return undo(rc);
+        if ((rc = dalloc(&h->d_cycle, (size_t)h->n_atm)) != RT_OK) return undo(rc);
+        if ((rc = dalloc(&h->d_count, 1)) != RT_OK) return undo(rc);
+        if (!h->h_count && hipHostMalloc((void **)&h->h_count, sizeof(int)) != hipSuccess) {
             h->h_count = nullptr;
-            return fail(RT_ENOMEM, "pinned host allocation failed");
+            return undo(fail(RT_ENOMEM, "pinned host allocation failed"));
         }
     }
     h->ws_restart = m;

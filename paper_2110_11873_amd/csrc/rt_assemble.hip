@@ -356,17 +356,28 @@ int plan_assembly(rt_handle *h, hipStream_t s) {
     });
     h->asm_tasks = (int)tasks.size();
     int rc;
+    // the task list is set on the handle last: it marks the plan as made, so
+    // a failure frees whatever this call allocated and a later call starts over
     AsmTask *dt = nullptr;
-    if ((rc = alloc(&dt, tasks.size())) != RT_OK) return rc;
-    h->d_asm_task = dt;
+    auto undo = [&](int code) {
+        for (void **q : {(void **)&dt, (void **)&h->d_ew, (void **)&h->d_asm_dg,
+                         (void **)&h->d_asm_sc}) {
+            if (*q) (void)hipFree(*q);
+            *q = nullptr;
+        }
+        return code;
+    };
+    if ((rc = alloc(&dt, tasks.size())) != RT_OK) return undo(rc);
     if (hipMemcpy(dt, tasks.data(), tasks.size() * sizeof(AsmTask), hipMemcpyHostToDevice) !=
         hipSuccess)
-        return fail(RT_EDEVICE, "assembly task upload failed");
-    if ((rc = alloc(&h->d_ew, (size_t)h->n_ew)) != RT_OK) return rc;
-    if ((rc = alloc(&h->d_asm_dg, (size_t)best_slices * 2 * h->ns_total * 3)) != RT_OK) return rc;
+        return undo(fail(RT_EDEVICE, "assembly task upload failed"));
+    if ((rc = alloc(&h->d_ew, (size_t)h->n_ew)) != RT_OK) return undo(rc);
+    if ((rc = alloc(&h->d_asm_dg, (size_t)best_slices * 2 * h->ns_total * 3)) != RT_OK)
+        return undo(rc);
     if (best_slices > 1 &&
         (rc = alloc(&h->d_asm_sc, (size_t)(best_slices - 1) * h->n_dense)) != RT_OK)
-        return rc;
+        return undo(rc);
+    h->d_asm_task = dt;
     int ns_max_m1 = 1;
     for (int n : h->ns) ns_max_m1 = std::max(ns_max_m1, n - 1);
     const long long per = (long long)ns_max_m1 * h->M * h->n_nu;

@@ -708,10 +708,16 @@ int lu_factor(rt_handle *h, hipStream_t s) {
         return fail(RT_EINVAL, "the LU route supports the two-point formal solvers only");
     const size_t bytes = sizeof(double) * (size_t)std::max<long long>(h->n_dense, 1);
     if (!h->d_LU) {
+        // all three or none: a failed allocation frees the others, so a later
+        // call starts over instead of finding a partial set
         if (hipMalloc((void **)&h->d_LU, bytes) != hipSuccess ||
             hipMalloc((void **)&h->d_piv, sizeof(int) * h->n_unk) != hipSuccess ||
             hipMalloc((void **)&h->d_sing, sizeof(int) * h->n_atm) != hipSuccess) {
             (void)hipGetLastError();
+            for (void **p : {(void **)&h->d_LU, (void **)&h->d_piv, (void **)&h->d_sing}) {
+                if (*p) (void)hipFree(*p);
+                *p = nullptr;
+            }
             return fail(RT_ENOMEM, "device allocation of the LU factors failed");
         }
     }

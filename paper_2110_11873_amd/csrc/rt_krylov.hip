@@ -1549,9 +1549,14 @@ int run_solver(rt_handle *h, int kind, const double *b, double *x, rt_solve_info
         // the assembled A, P^-1 workspace and unit scaling; then y0 = P x0
         if ((rc = ensure_dense(h, s)) != RT_OK) return rc;
         if (!h->d_pz) {
+            // both or neither (a later call must not find d_pz without d_ones)
             if (hipMalloc((void **)&h->d_pz, sizeof(double) * h->n_unk) != hipSuccess ||
                 hipMalloc((void **)&h->d_ones, sizeof(double) * h->n_unk) != hipSuccess) {
                 (void)hipGetLastError();
+                for (double **p : {&h->d_pz, &h->d_ones}) {
+                    if (*p) (void)hipFree(*p);
+                    *p = nullptr;
+                }
                 return fail(RT_ENOMEM, "preconditioner workspace allocation failed");
             }
             d.ok(fill(h->d_ones, h->n_unk, 1.0, s));
