@@ -70,11 +70,25 @@ def measured_traffic(kind):
 def op_only(kind, n, coef_mode=0):
     """The operator leg alone (for counter passes): n applications, in the
     tuned launch plan of the mixed solve (FP32) or of the FP64 solve (FP64),
-    or with its coefficient mode replaced."""
+    or with its coefficient mode replaced; or the frequency-redistribution
+    operator (256 depths, 32 mu, 256 nu, gamma = 0.5) with its contraction on
+    the FP64 (prd) or the BF16 (prd_bf16) matrix cores."""
     import torch
     from paper_2110_11873_amd import binding as B
     from paper_2110_11873_amd import workloads as W
     torch.cuda.set_device(0)
+    if kind.startswith("prd"):
+        p5, R5 = W.config5()
+        with B.setup(p5) as h:
+            h.set_redistribution(R5)
+            v = torch.from_numpy(np.random.default_rng(0).uniform(-1, 1, h.prd_size())).cuda()
+            y = torch.empty_like(v)
+            f = h.apply_op_prd_bf16x3 if kind == "prd_bf16" else h.apply_op_prd
+            for _ in range(n):
+                f(v, y)
+            torch.cuda.synchronize()
+            print(json.dumps(dict(op=kind, applications=n)), flush=True)
+        return
     p = W.config4(512)
     # the handle (and launch plan) the bench times the operator on
     kw = dict(coef_mode=coef_mode) if coef_mode else {}
@@ -450,7 +464,7 @@ def main():
     ap.add_argument("--matvecs", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--op-only", choices=["fp32", "fp64"])
+    ap.add_argument("--op-only", choices=["fp32", "fp64", "prd", "prd_bf16"])
     ap.add_argument("--coef-mode", type=int, default=0,
                     help="with --op-only: rt_options.coef_mode (0 = the tuned plan's)")
     ap.add_argument("--copy-calib", action="store_true")

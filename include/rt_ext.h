@@ -172,8 +172,9 @@ int rt_sigma_from_field(rt_handle *h, const double *I, double *sigma, void *stre
  * info[i] (host, n_atm entries, or NULL): status (RT_OK or RT_ENOCONV),
  * Arnoldi steps, the batch's operator applications (an upper bound for the
  * slab) and the explicit relative residual.  Workspace of (restart + 2)
- * fields is allocated for the call and released; RT_ENOMEM if it does not
- * fit.  Synchronizes the stream.
+ * fields is allocated on the first call that needs it and kept by the handle
+ * (grown when a later call needs more) until rt_destroy; RT_ENOMEM if it
+ * does not fit.  Synchronizes the stream.
  */
 int rt_solve_field_gmres(rt_handle *h, const double *b_field, double *I, rt_solve_info *info,
                          void *stream);

@@ -83,16 +83,19 @@ def candidates(prob, mixed=True):
     (the FP32-only recompute mode only where FP32 sweeps run), chunk lengths
     that cover the deepest slab, 4 or 8 waves (8 compiled for chunks up to
     8), prefetch where compiled (pairs, chunks up to 8), and 0 (automatic), 8
-    or 16 ray batches per wave."""
+    or 16 ray batches per wave (also 1, 2 and 4 for a handful of slabs)."""
     ns_max = int(max(prob.ns))
     chunks = [L for L in (4, 8, 16, 32) if 64 * L >= ns_max - 1][:3]
     modes = [COEF_PAIRS, COEF_STREAM_W, COEF_RECOMPUTE] + ([COEF_RECOMPUTE_FP32] if mixed else [])
+    # a handful of slabs: also one to four batches per wave (many workgroups
+    # per slab, the chip filled by one slab's rays)
+    nbs = (0, 8, 16) if len(prob.ns) > 8 else (0, 1, 2, 4, 8, 16)
     out = []
     for cm in modes:
         for L in chunks:
             for waves in ((4, 8) if L <= 8 else (4,)):
                 for pf in ((1, 2) if (L <= 8 and cm == COEF_PAIRS) else (1,)):
-                    for nb in (0, 8, 16):
+                    for nb in nbs:
                         out.append(dict(chunk=L, sweep_waves=waves, prefetch=pf,
                                         wave_batches=nb, coef_mode=cm))
     return out

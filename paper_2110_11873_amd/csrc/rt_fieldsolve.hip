@@ -31,6 +31,52 @@ constexpr int kFsChunk = 1024;  // vector entries per workgroup
 constexpr int kFsPerThread = kFsChunk / kFsNT;
 constexpr int kFsPerLane = kFsChunk / kWave;
 
+// Workspace carved from one device allocation that the handle keeps between
+// calls (slot 0: the GMRES, 1: the refinement around it) and grows when a
+// call needs more; every piece starts on a 256-byte boundary.
+class Carve {
+  public:
+    Carve(rt_handle *h, int slot) : h_(h), slot_(slot) {}
+    template <typename T>
+    void want(T **p, size_t count) {
+        *p = nullptr;
+        reqs_.push_back({(void **)p, (count ? count : 1) * sizeof(T)});
+    }
+    bool commit() {
+        size_t total = 0;
+        for (const Req &r : reqs_) total += round(r.bytes);
+        void *&base = h_->seg_ws[slot_];
+        size_t &have = h_->seg_ws_bytes[slot_];
+        if (have < total) {
+            if (base) (void)hipFree(base);
+            base = nullptr;
+            have = 0;
+            if (hipMalloc(&base, total) != hipSuccess) {
+                (void)hipGetLastError();
+                base = nullptr;
+                return false;
+            }
+            have = total;
+        }
+        char *q = static_cast<char *>(base);
+        for (const Req &r : reqs_) {
+            *r.p = q;
+            q += round(r.bytes);
+        }
+        return true;
+    }
+
+  private:
+    struct Req {
+        void **p;
+        size_t bytes;
+    };
+    static size_t round(size_t b) { return (b + 255) / 256 * 256; }
+    rt_handle *h_;
+    int slot_;
+    std::vector<Req> reqs_;
+};
+
 struct FsArgs {
     const long long *off;  // [n_atm + 1] first entry of each slab's segment
     int n_atm, nchunk, m;
@@ -96,14 +142,70 @@ __global__ __launch_bounds__(1024) void fs_reduce_kernel(FsArgs a, int nv, int m
     }
 }
 
-// w -= sum_i h[s][i] V_i over the working slabs' segments; the column of H
-// accumulates h (first pass: set, second: add).
-__global__ __launch_bounds__(kFsNT) void fs_axpy_kernel(FsArgs a, double *w, int nv, int j,
-                                                         int first) {
-    const int s = blockIdx.y;
+// ---------------------------------------------------------------------------
+// The Arnoldi step fused into three launches after the first pass's partial
+// dot products (fs_dots_kernel into part): every workgroup of a slab first
+// adds the partial sums of all chunks itself -- in the order fs_reduce_kernel
+// uses, so every workgroup gets the same coefficients, bit for bit -- and then
+// works on its chunk.
+//   fs_proj_kernel:   h = sum_c part, w -= sum_i h_i V_i on the chunk, H column
+//                     (set or add), then the partial dot products of the new w
+//                     with V_i (nv rows) or with itself (nv = 0) into `out`;
+//   fs_close_kernel:  hn^2 = sum_c part (the norm), Givens (workgroup 0) and
+//                     v_{j+1} = w / hn on the chunk.
+// The dot products are taken from a copy of the chunk in LDS in the layout of
+// fs_dots_kernel, so they add in the same order as that kernel's.
+// ---------------------------------------------------------------------------
+
+// the Givens part of step j for slab s (below)
+__device__ void givens_step(const FsArgs &a, int s, int j);
+
+// sum over the chunks of one slab's partial sums of row i (fs_reduce_kernel's
+// order), by one wavefront
+__device__ inline double chunk_sum(const FsArgs &a, const double *ps, int i, int lane) {
+    double t = 0.0;
+    for (int c = lane; c < a.nchunk; c += kWave) t += ps[(long long)c * (a.m + 1) + i];
+    for (int o = kWave / 2; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    return t;
+}
+
+// the partial dot products of the chunk held in LDS (xs) with rows V_i,
+// i < nv (or of the chunk with itself, nv = 0), as fs_dots_kernel computes them
+__device__ inline void chunk_dots(const FsArgs &a, const double *xs, int nv, long long lo,
+                                  long long hi, double *out) {
+    const int lane = threadIdx.x % kWave;
+    double xv[kFsPerLane];
+#pragma unroll
+    for (int u = 0; u < kFsPerLane; ++u) xv[u] = xs[lane + u * kWave];
+    const int rows = nv > 0 ? nv : 1;
+    for (int i = threadIdx.x / kWave; i < rows; i += kFsNT / kWave) {
+        const double *Vi = a.V + (long long)i * a.N;
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < kFsPerLane; ++u) {
+            const long long e = lo + lane + (long long)u * kWave;
+            acc = fma(xv[u], nv > 0 ? (e < hi ? Vi[e] : 0.0) : xv[u], acc);
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) out[i] = acc;
+    }
+}
+
+__global__ __launch_bounds__(kFsNT) void fs_proj_kernel(FsArgs a, double *w, int nv, int j,
+                                                         int first, const double *in,
+                                                         double *out, int next_nv) {
+    __shared__ double hs[RT_MAX_RESTART + 1];
+    __shared__ double xs[kFsChunk];
+    const int s = blockIdx.y, c = blockIdx.x;
     if (!working(a, s)) return;
-    const double *hs = a.h + (long long)s * (a.m + 1);
-    const long long lo = a.off[s] + (long long)blockIdx.x * kFsChunk;
+    const int lane = threadIdx.x % kWave;
+    const double *ps = in + (long long)s * a.nchunk * (a.m + 1);
+    for (int i = threadIdx.x / kWave; i < nv; i += kFsNT / kWave) {
+        const double t = chunk_sum(a, ps, i, lane);
+        if (lane == 0) hs[i] = t;
+    }
+    __syncthreads();
+    const long long lo = a.off[s] + (long long)c * kFsChunk;
     const long long hi = std::min(a.off[s + 1], lo + kFsChunk);
     double v[kFsPerThread];
 #pragma unroll
@@ -112,31 +214,56 @@ __global__ __launch_bounds__(kFsNT) void fs_axpy_kernel(FsArgs a, double *w, int
         v[u] = e < hi ? w[e] : 0.0;
     }
     for (int i = 0; i < nv; ++i) {
-        const double c = -hs[i];
+        const double cf = -hs[i];
         const double *Vi = a.V + (long long)i * a.N;
 #pragma unroll
         for (int u = 0; u < kFsPerThread; ++u) {
             const long long e = lo + threadIdx.x + (long long)u * kFsNT;
-            if (e < hi) v[u] = fma(c, Vi[e], v[u]);
+            if (e < hi) v[u] = fma(cf, Vi[e], v[u]);
         }
     }
 #pragma unroll
     for (int u = 0; u < kFsPerThread; ++u) {
         const long long e = lo + threadIdx.x + (long long)u * kFsNT;
         if (e < hi) w[e] = v[u];
+        xs[threadIdx.x + u * kFsNT] = v[u];
     }
-    if (blockIdx.x == 0 && threadIdx.x < nv) {
+    if (c == 0 && threadIdx.x < nv) {
         double *Hc = a.H + (long long)s * (a.m + 1) * a.m + (long long)threadIdx.x * a.m + j;
         *Hc = first ? hs[threadIdx.x] : *Hc + hs[threadIdx.x];
     }
+    __syncthreads();
+    chunk_dots(a, xs, next_nv, lo, hi, out + ((long long)s * a.nchunk + c) * (a.m + 1));
 }
 
-// Step j's last part, one thread per slab: h_{j+1,j} = ||w|| (in h[s][0]),
+__global__ __launch_bounds__(kFsNT) void fs_close_kernel(FsArgs a, const double *w, int j,
+                                                          const double *in) {
+    __shared__ double shn;
+    const int s = blockIdx.y, c = blockIdx.x;
+    if (!a.active[s]) return;
+    if (a.done[s] && a.jj[s] != j + 1) return;  // finished before this step
+    if (threadIdx.x < kWave) {
+        const double t = chunk_sum(a, in + (long long)s * a.nchunk * (a.m + 1), 0, threadIdx.x);
+        if (threadIdx.x == 0) shn = t;
+    }
+    __syncthreads();
+    const double hn = sqrt(shn);
+    if (c == 0 && threadIdx.x == 0) {
+        // the rotations of fs_givens_kernel, with h_{j+1,j} = hn
+        a.h[(long long)s * (a.m + 1)] = shn;
+        givens_step(a, s, j);
+    }
+    if (!(hn > 0.0)) return;
+    const long long lo = a.off[s] + (long long)c * kFsChunk;
+    const long long hi = std::min(a.off[s + 1], lo + kFsChunk);
+    for (long long e = lo + threadIdx.x; e < hi; e += kFsNT)
+        a.V[(long long)(j + 1) * a.N + e] = w[e] / hn;
+}
+
+// Step j's last part for slab s: h_{j+1,j} = ||w|| (its square in h[s][0]),
 // previous rotations on column j, the new rotation, g, the residual
-// estimate; v_{j+1} = w / h_{j+1,j} is left to fs_scale_kernel.
-__global__ void fs_givens_kernel(FsArgs a, int j) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= a.n_atm || !working(a, s)) return;
+// estimate; v_{j+1} = w / h_{j+1,j} is left to the caller.
+__device__ void givens_step(const FsArgs &a, int s, int j) {
     const int m = a.m;
     double *H = a.H + (long long)s * (m + 1) * m;
     double *cs = a.cs + (long long)s * m, *sn = a.sn + (long long)s * m;
@@ -315,20 +442,7 @@ int solve_seg_gmres_tol(rt_handle *h, const std::function<hipError_t(const doubl
         off[s + 1] = off[s] + per * h->ns[s];
         nchunk = std::max<int>(nchunk, (int)((per * h->ns[s] + kFsChunk - 1) / kFsChunk));
     }
-    // workspace, released at the end of the call
-    std::vector<void *> bufs;
-    auto get = [&](size_t bytes) -> void * {
-        void *p = nullptr;
-        if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) {
-            (void)hipGetLastError();
-            return nullptr;
-        }
-        bufs.push_back(p);
-        return p;
-    };
-    auto release = [&]() {
-        for (void *p : bufs) (void)hipFree(p);
-    };
+    // workspace, kept by the handle for later calls
     FsArgs a{};
     a.n_atm = n_atm;
     a.nchunk = nchunk;
@@ -336,34 +450,29 @@ int solve_seg_gmres_tol(rt_handle *h, const std::function<hipError_t(const doubl
     a.N = N;
     a.tol = rtol;
     a.maxit = maxit;
-    a.off = (long long *)get(sizeof(long long) * (n_atm + 1));
-    a.V = (double *)get(sizeof(double) * (size_t)(m + 1) * N);
-    double *w = (double *)get(sizeof(double) * N);
-    double *bown = b ? nullptr : (double *)get(sizeof(double) * N);
-    double *tmp = dinv ? (double *)get(sizeof(double) * N) : nullptr;
-    a.part = (double *)get(sizeof(double) * (size_t)n_atm * nchunk * (m + 1));
-    a.h = (double *)get(sizeof(double) * (size_t)n_atm * (m + 1));
-    a.H = (double *)get(sizeof(double) * (size_t)n_atm * (m + 1) * m);
-    a.cs = (double *)get(sizeof(double) * (size_t)n_atm * m);
-    a.sn = (double *)get(sizeof(double) * (size_t)n_atm * m);
-    a.g = (double *)get(sizeof(double) * (size_t)n_atm * (m + 1));
-    a.bnorm = (double *)get(sizeof(double) * n_atm);
-    a.beta = (double *)get(sizeof(double) * n_atm);
-    a.resid = (double *)get(sizeof(double) * n_atm);
-    a.active = (int *)get(sizeof(int) * n_atm);
-    a.done = (int *)get(sizeof(int) * n_atm);
-    a.jj = (int *)get(sizeof(int) * n_atm);
-    a.iters = (int *)get(sizeof(int) * n_atm);
-    for (void *p : bufs)
-        if (!p) {
-            release();
-            return fail(RT_ENOMEM, "GMRES workspace allocation failed");
-        }
-    if (!a.off || !a.V || !w || (!b && !bown) || (dinv && !tmp) || !a.part || !a.h || !a.H || !a.cs || !a.sn ||
-        !a.g || !a.bnorm || !a.beta || !a.resid || !a.active || !a.done || !a.jj || !a.iters) {
-        release();
-        return fail(RT_ENOMEM, "GMRES workspace allocation failed");
-    }
+    double *w, *bown = nullptr, *tmp = nullptr, *part2;
+    Carve cv(h, 0);
+    cv.want((long long **)&a.off, n_atm + 1);
+    cv.want(&a.V, (size_t)(m + 1) * N);
+    cv.want(&w, N);
+    if (!b) cv.want(&bown, N);
+    if (dinv) cv.want(&tmp, N);
+    cv.want(&a.part, (size_t)n_atm * nchunk * (m + 1));
+    cv.want(&part2, (size_t)n_atm * nchunk * (m + 1));
+    cv.want(&a.h, (size_t)n_atm * (m + 1));
+    cv.want(&a.H, (size_t)n_atm * (m + 1) * m);
+    cv.want(&a.cs, (size_t)n_atm * m);
+    cv.want(&a.sn, (size_t)n_atm * m);
+    cv.want(&a.g, (size_t)n_atm * (m + 1));
+    cv.want(&a.bnorm, n_atm);
+    cv.want(&a.beta, n_atm);
+    cv.want(&a.resid, n_atm);
+    cv.want(&a.active, n_atm);
+    cv.want(&a.done, n_atm);
+    cv.want(&a.jj, n_atm);
+    cv.want(&a.iters, n_atm);
+    if (!cv.commit()) return fail(RT_ENOMEM, "GMRES workspace allocation failed");
+    auto release = [] {};
     hipError_t err = hipSuccess;
     auto ok = [&](hipError_t e) {
         if (e != hipSuccess && err == hipSuccess) err = e;
@@ -417,18 +526,17 @@ int solve_seg_gmres_tol(rt_handle *h, const std::function<hipError_t(const doubl
             const double *vj = a.V + (long long)j * N;
             ok(apply(vj, w));
             ++napply;
-            for (int pass = 0; pass < 2; ++pass) {
-                hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)w, j + 1,
-                                   (const double *)a.V, 0);
-                hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, j + 1, 0);
-                hipLaunchKernelGGL(fs_axpy_kernel, seg, blk, 0, st, a, w, j + 1, j,
-                                   pass == 0 ? 1 : 0);
-            }
-            hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)w, 1,
-                               (const double *)nullptr, 0);
-            hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, 1, 0);
-            hipLaunchKernelGGL(fs_givens_kernel, dim3(tg), dim3(tb), 0, st, a, j);
-            hipLaunchKernelGGL(fs_scale_kernel, seg, blk, 0, st, a, (const double *)w, j);
+            // classical Gram-Schmidt twice: first-pass dots; first projection
+            // fused with the second-pass dots; second projection fused with
+            // the norm's partial sums; Givens and the new basis vector
+            hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)w, j + 1,
+                               (const double *)a.V, 0);
+            hipLaunchKernelGGL(fs_proj_kernel, seg, blk, 0, st, a, w, j + 1, j, 1,
+                               (const double *)a.part, part2, j + 1);
+            hipLaunchKernelGGL(fs_proj_kernel, seg, blk, 0, st, a, w, j + 1, j, 0,
+                               (const double *)part2, a.part, 0);
+            hipLaunchKernelGGL(fs_close_kernel, seg, blk, 0, st, a, (const double *)w, j,
+                               (const double *)a.part);
             ok(hipGetLastError());
             if ((j + 1) % 8 == 0 && j + 1 < m) {
                 // stop the cycle early once every slab's cycle has ended
@@ -491,37 +599,25 @@ int solve_seg_refined(rt_handle *h, const std::function<hipError_t(const double 
         off[s + 1] = off[s] + per * h->ns[s];
         nchunk = std::max<int>(nchunk, (int)((per * h->ns[s] + kFsChunk - 1) / kFsChunk));
     }
-    std::vector<void *> bufs;
-    auto get = [&](size_t bytes) -> void * {
-        void *p = nullptr;
-        if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) {
-            (void)hipGetLastError();
-            return nullptr;
-        }
-        bufs.push_back(p);
-        return p;
-    };
-    auto release = [&]() {
-        for (void *p : bufs) (void)hipFree(p);
-    };
-    // per-slab squared norms through the segmented reductions (m = 0: one row)
+    // per-slab squared norms through the segmented reductions (m = 0: one row);
+    // workspace kept by the handle for later calls
     FsArgs a{};
     a.n_atm = n_atm;
     a.nchunk = nchunk;
     a.m = 0;
     a.N = N;
-    a.off = (long long *)get(sizeof(long long) * (n_atm + 1));
-    a.part = (double *)get(sizeof(double) * (size_t)n_atm * nchunk);
-    a.h = (double *)get(sizeof(double) * n_atm);
-    a.active = (int *)get(sizeof(int) * n_atm);
-    double *bown = b_in ? nullptr : (double *)get(sizeof(double) * N);
-    double *r = (double *)get(sizeof(double) * N);
-    double *d = (double *)get(sizeof(double) * N);
-    double *w = (double *)get(sizeof(double) * N);
-    if (!a.off || !a.part || !a.h || !a.active || (!b_in && !bown) || !r || !d || !w) {
-        release();
-        return fail(RT_ENOMEM, "refinement workspace allocation failed");
-    }
+    double *bown = nullptr, *r, *d, *w;
+    Carve cv(h, 1);
+    cv.want((long long **)&a.off, n_atm + 1);
+    cv.want(&a.part, (size_t)n_atm * nchunk);
+    cv.want(&a.h, n_atm);
+    cv.want(&a.active, n_atm);
+    if (!b_in) cv.want(&bown, N);
+    cv.want(&r, N);
+    cv.want(&d, N);
+    cv.want(&w, N);
+    if (!cv.commit()) return fail(RT_ENOMEM, "refinement workspace allocation failed");
+    auto release = [] {};
     hipError_t err = hipSuccess;
     auto ok = [&](hipError_t e) {
         if (e != hipSuccess && err == hipSuccess) err = e;

@@ -306,6 +306,11 @@ struct rt_handle {
     int *d_count = nullptr;     // reduction target for host checks
     int *h_count = nullptr;     // pinned host mirror
 
+    // workspace of the segmented GMRES (slot 0) and of the refinement around
+    // it (slot 1), kept between calls and grown on demand
+    void *seg_ws[2] = {nullptr, nullptr};
+    size_t seg_ws_bytes[2] = {0, 0};
+
     // captured solver segments (one per distinct argument set), the stream
     // they are replayed on and the events that order it after the caller's
     struct Graph {

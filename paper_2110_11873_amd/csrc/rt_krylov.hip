@@ -1524,8 +1524,30 @@ struct Driver {
 // Allocate the Krylov workspace for the handle's restart length.
 int ensure_workspace(rt_handle *h);
 
+// A handful of deep slabs (the single 1024-point atmosphere): the batched
+// solver's Arnoldi step runs one workgroup per slab, which leaves the chip
+// idle and serializes the slab's basis reads on one CU; the segmented GMRES
+// (rt_fieldsolve.hip) spreads every slab's vectors over many workgroups.
+static bool few_deep_slabs(const rt_handle *h) { return h->n_atm <= 4 && 2 * h->ns_max >= 2048; }
+
 int run_solver(rt_handle *h, int kind, const double *b, double *x, rt_solve_info *info,
                hipStream_t s) {
+    if (kind == 0 && h->opt.precond == RT_PC_JACOBI && h->fs != RT_FS_DELO_PARABOLIC &&
+        few_deep_slabs(h)) {
+        const double *bb = b ? b : h->d_b;
+        auto op64 = [&](const double *in, double *out) {
+            return apply_operator(h, in, nullptr, out, nullptr, false, 0, s);
+        };
+        auto op32 = [&](const double *in, double *out) {
+            return apply_operator(h, in, nullptr, out, nullptr, true, 0, s);
+        };
+        auto own = [&](double *bo) {
+            return hipMemcpyAsync(bo, h->d_b, sizeof(double) * h->n_unk, hipMemcpyDeviceToDevice, s);
+        };
+        if (h->opt.precision == RT_PREC_MIXED)
+            return solve_seg_refined(h, op64, op32, 2, bb, own, x, h->d_dinv, info, s);
+        return solve_seg_gmres(h, op64, 2, bb, own, x, h->d_dinv, info, s);
+    }
     int rc = ensure_workspace(h);
     if (rc != RT_OK) return rc;
     if (!b) b = h->d_b;

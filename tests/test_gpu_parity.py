@@ -498,13 +498,16 @@ def test_edge_cases_zero_rhs_maxit_and_exact_start():
 
 
 @pytest.mark.parametrize("mixed", [False, True])
-def test_maximum_depth_and_restart(mixed):
+@pytest.mark.parametrize("extra", [[], [40, 41, 20]])
+def test_maximum_depth_and_restart(mixed, extra):
     """RT_MAX_NS = 2048 depth points with GMRES(RT_MAX_RESTART = 128): the
-    operator, right-hand side and a solve beside a 97-point slab (general
-    Arnoldi path, longest cycle)."""
-    ns = [B.RT_MAX_NS, 97]
-    p = W.make_slabs(ns, [(1e-4, 1e8), (1e-2, 1e4)], 4, 9, 5.0, [1e-3, 1e-2], [1e-4, 1e-2],
-                     [0.5, 0.3])
+    operator, right-hand side and a solve beside a 97-point slab.  Two slabs:
+    the segmented solver (a handful of deep slabs); five: the batched
+    solver's general Arnoldi path with its longest cycle."""
+    ns = [B.RT_MAX_NS, 97] + extra
+    k = len(ns)
+    p = W.make_slabs(ns, [(1e-4, 1e8)] + [(1e-2, 1e4)] * (k - 1), 4, 9, 5.0, [1e-3] * k,
+                     [1e-4] + [1e-2] * (k - 1), [0.5] + [0.3] * (k - 1))
     prec = B.RT_PREC_MIXED if mixed else B.RT_PREC_FP64
     with B.setup(p, rtol=1e-10, restart=B.RT_MAX_RESTART, maxit=20000, precision=prec) as h:
         if not mixed:
