@@ -26,7 +26,7 @@ namespace rt {
 
 namespace {
 
-constexpr int kFsNT = 256;
+constexpr int kFsNT = 1024;  // 16 wavefronts per chunk: its basis rows spread over them
 constexpr int kFsChunk = 1024;  // vector entries per workgroup
 constexpr int kFsPerThread = kFsChunk / kFsNT;
 constexpr int kFsPerLane = kFsChunk / kWave;
@@ -213,6 +213,7 @@ __global__ __launch_bounds__(kFsNT) void fs_proj_kernel(FsArgs a, double *w, int
         const long long e = lo + threadIdx.x + (long long)u * kFsNT;
         v[u] = e < hi ? w[e] : 0.0;
     }
+#pragma unroll 4
     for (int i = 0; i < nv; ++i) {
         const double cf = -hs[i];
         const double *Vi = a.V + (long long)i * a.N;
@@ -303,8 +304,30 @@ __global__ __launch_bounds__(kFsNT) void fs_scale_kernel(FsArgs a, const double 
         a.V[(long long)(j + 1) * a.N + e] = w[e] / hn;
 }
 
-// End of a cycle, one thread per active slab: y = H^-1 g (back substitution
-// over the cycle's steps), into h.
+// End of a cycle, one wavefront per active slab (restart below 64): y = H^-1 g
+// over the cycle's n steps, into h.  The n x n triangle goes to LDS first;
+// lane r holds row r's right-hand side, and for i = n-1 down to 0 the solved
+// y_i (from lane i) is removed from every row above it at once.
+constexpr int kBacksolveMaxM = kWave - 1;  // lanes 0..m write y_0..y_m
+__global__ __launch_bounds__(kWave) void fs_backsolve_wave_kernel(FsArgs a) {
+    extern __shared__ double Hs[];  // [n][n]
+    const int s = blockIdx.x;
+    if (!a.active[s]) return;
+    const int m = a.m, n = a.jj[s], r = threadIdx.x;
+    const double *H = a.H + (long long)s * (m + 1) * m;
+    for (int e = r; e < n * n; e += kWave) Hs[e] = H[(long long)(e / n) * m + e % n];
+    double t = r < n ? a.g[(long long)s * (m + 1) + r] : 0.0;
+    __syncthreads();
+    double yr = 0.0;
+    for (int i = n - 1; i >= 0; --i) {
+        const double yi = __shfl(t / Hs[i * n + i], i);
+        if (r == i) yr = yi;
+        if (r < i) t = fma(-Hs[r * n + i], yi, t);
+    }
+    if (r <= m) a.h[(long long)s * (m + 1) + r] = r < n ? yr : 0.0;
+}
+
+// The same for any restart, one thread per active slab, from global memory.
 __global__ void fs_backsolve_kernel(FsArgs a) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= a.n_atm || !a.active[s]) return;
@@ -334,6 +357,7 @@ __global__ __launch_bounds__(kFsNT) void fs_update_kernel(FsArgs a, double *x) {
         const long long e = lo + threadIdx.x + (long long)u * kFsNT;
         v[u] = e < hi ? x[e] : 0.0;
     }
+#pragma unroll 4
     for (int i = 0; i < n; ++i) {
         const double *Vi = a.V + (long long)i * a.N;
 #pragma unroll
@@ -420,7 +444,7 @@ __global__ void fs_axpby_kernel(const double *b, const double *w, double *r, lon
 // entries per depth point; dinv (optional) preconditions from the right by
 // diag(dinv): the solve runs on y with x = dinv .* y, starting from y0 =
 // x0 ./ dinv, so that the residual tested is still b - A x.
-int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *, double *)> &op,
+int solve_seg_gmres(rt_handle *h, const SegOp &op,
                     long long per, const double *b_in,
                     const std::function<hipError_t(double *)> &own_rhs, double *x,
                     const double *dinv, rt_solve_info *info, hipStream_t st) {
@@ -428,7 +452,7 @@ int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *,
                                st);
 }
 
-int solve_seg_gmres_tol(rt_handle *h, const std::function<hipError_t(const double *, double *)> &op,
+int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
                         long long per, const double *b_in,
                         const std::function<hipError_t(double *)> &own_rhs, double *x,
                         const double *dinv, double rtol, int maxit, rt_solve_info *info,
@@ -450,13 +474,12 @@ int solve_seg_gmres_tol(rt_handle *h, const std::function<hipError_t(const doubl
     a.N = N;
     a.tol = rtol;
     a.maxit = maxit;
-    double *w, *bown = nullptr, *tmp = nullptr, *part2;
+    double *w, *bown = nullptr, *part2;
     Carve cv(h, 0);
     cv.want((long long **)&a.off, n_atm + 1);
     cv.want(&a.V, (size_t)(m + 1) * N);
     cv.want(&w, N);
     if (!b) cv.want(&bown, N);
-    if (dinv) cv.want(&tmp, N);
     cv.want(&a.part, (size_t)n_atm * nchunk * (m + 1));
     cv.want(&part2, (size_t)n_atm * nchunk * (m + 1));
     cv.want(&a.h, (size_t)n_atm * (m + 1));
@@ -485,13 +508,9 @@ int solve_seg_gmres_tol(rt_handle *h, const std::function<hipError_t(const doubl
         b = bown;
     }
     const int mgrid = (int)std::min<long long>((N + 255) / 256, 4096);
-    // the preconditioned operator A diag(dinv), on y = x ./ dinv
-    auto apply = [&](const double *v, double *out) {
-        if (!dinv) return op(v, out);
-        hipLaunchKernelGGL(fs_mul_kernel, dim3(mgrid), dim3(256), 0, st, dinv, v, tmp, N, 0);
-        hipError_t e = hipGetLastError();
-        return e != hipSuccess ? e : op(tmp, out);
-    };
+    // the preconditioned operator A diag(dinv), on y = x ./ dinv (the scaling
+    // is done by the operator's kernels as they read v)
+    auto apply = [&](const double *v, double *out) { return op(v, dinv, out); };
     if (dinv) hipLaunchKernelGGL(fs_mul_kernel, dim3(mgrid), dim3(256), 0, st, dinv, (const double *)x, x, N, 1);
     const dim3 seg(nchunk, n_atm), blk(kFsNT);
     const int tb = 64, tg = (n_atm + tb - 1) / tb;
@@ -550,12 +569,16 @@ int solve_seg_gmres_tol(rt_handle *h, const std::function<hipError_t(const doubl
                 if (all) break;
             }
         }
-        hipLaunchKernelGGL(fs_backsolve_kernel, dim3(tg), dim3(tb), 0, st, a);
+        if (m <= kBacksolveMaxM)
+            hipLaunchKernelGGL(fs_backsolve_wave_kernel, dim3(n_atm), dim3(kWave),
+                               sizeof(double) * m * m, st, a);
+        else
+            hipLaunchKernelGGL(fs_backsolve_kernel, dim3(tg), dim3(tb), 0, st, a);
         hipLaunchKernelGGL(fs_update_kernel, seg, blk, 0, st, a, x);
     }
     // back to x = dinv .* y, then the final explicit residuals b - A x
     if (dinv) hipLaunchKernelGGL(fs_mul_kernel, dim3(mgrid), dim3(256), 0, st, dinv, (const double *)x, x, N, 0);
-    ok(op(x, w));
+    ok(op(x, nullptr, w));
     hipLaunchKernelGGL(fs_init_kernel, dim3(tg), dim3(tb), 0, st, a);
     hipLaunchKernelGGL(fs_residual_kernel, seg, blk, 0, st, a, b, (const double *)w);
     hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)a.V, 1,
@@ -586,8 +609,7 @@ int solve_seg_gmres_tol(rt_handle *h, const std::function<hipError_t(const doubl
     return worst;
 }
 
-int solve_seg_refined(rt_handle *h, const std::function<hipError_t(const double *, double *)> &op,
-                      const std::function<hipError_t(const double *, double *)> &op_lo,
+int solve_seg_refined(rt_handle *h, const SegOp &op, const SegOp &op_lo,
                       long long per, const double *b_in,
                       const std::function<hipError_t(double *)> &own_rhs, double *x,
                       const double *dinv, rt_solve_info *info, hipStream_t st) {
@@ -651,7 +673,7 @@ int solve_seg_refined(rt_handle *h, const std::function<hipError_t(const double 
     bool done = false;
     while (err == hipSuccess) {
         // r = b - A x (FP64)
-        ok(op(x, w));
+        ok(op(x, nullptr, w));
         ++napply;
         hipLaunchKernelGGL(fs_axpby_kernel, dim3(mgrid), dim3(256), 0, st, b, (const double *)w, r,
                            N);
@@ -704,7 +726,10 @@ int solve_seg_refined(rt_handle *h, const std::function<hipError_t(const double 
 int solve_field_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *info,
                       hipStream_t st) {
     return solve_seg_gmres(
-        h, [&](const double *in, double *out) { return apply_field_operator(h, in, out, st); },
+        h,
+        [&](const double *in, const double *, double *out) {
+            return apply_field_operator(h, in, out, st);  // unpreconditioned: no scaling
+        },
         2LL * h->n_mu * h->n_nu, b, [&](double *bo) { return field_rhs(h, bo, st); }, x, nullptr,
         info, st);
 }

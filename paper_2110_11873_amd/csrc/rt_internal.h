@@ -273,6 +273,8 @@ struct rt_handle {
     double *d_prd_J = nullptr;    // monochromatic J, frequency-major [p][k][K]
     double *d_prd_diag = nullptr, *d_prd_dinv = nullptr;
     bool prd_ready = false;
+    int prd_cached_nt = 0;        // threads of the cached-coefficient sweep, 0: the general sweep
+    int prd_cached_nch = 0;       // its chunks per ray
     long long n_dense = 0;        // entries of the assembled A: sum over slabs of (2 ns)^2
     long long n_ew = 0;           // entries of the assembly coefficient table
 
@@ -360,15 +362,18 @@ hipError_t field_sigma(rt_handle *h, const double *I, double *sigma, int with_c,
 // (rt_fieldsolve.hip); b NULL: the handle's own Lambda T c + t.
 int solve_field_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *info,
                       hipStream_t s);
+// The operator of a segmented solve: out = A (scale .* in), scale NULL for
+// none (the right Jacobi scaling is applied by the operator's own kernels).
+using SegOp = std::function<hipError_t(const double *in, const double *scale, double *out)>;
 // The generic form: any block-diagonal operator with `per` entries per depth
 // point, own_rhs filling b when b is NULL, optional right Jacobi scaling.
-int solve_seg_gmres(rt_handle *h, const std::function<hipError_t(const double *, double *)> &op,
+int solve_seg_gmres(rt_handle *h, const SegOp &op,
                     long long per, const double *b,
                     const std::function<hipError_t(double *)> &own_rhs, double *x,
                     const double *dinv, rt_solve_info *info, hipStream_t st);
 // The same with an explicit tolerance and iteration limit (the inner solves
 // of the refinement below).
-int solve_seg_gmres_tol(rt_handle *h, const std::function<hipError_t(const double *, double *)> &op,
+int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
                         long long per, const double *b,
                         const std::function<hipError_t(double *)> &own_rhs, double *x,
                         const double *dinv, double rtol, int maxit, rt_solve_info *info,
@@ -376,16 +381,16 @@ int solve_seg_gmres_tol(rt_handle *h, const std::function<hipError_t(const doubl
 // FP64 iterative refinement: r = b - A x with op, d from GMRES(m) on op_lo to
 // inner_rtol, x += d, until every slab's ||r|| < rtol ||b|| (or maxit inner
 // steps in total).
-int solve_seg_refined(rt_handle *h, const std::function<hipError_t(const double *, double *)> &op,
-                      const std::function<hipError_t(const double *, double *)> &op_lo,
+int solve_seg_refined(rt_handle *h, const SegOp &op, const SegOp &op_lo,
                       long long per, const double *b,
                       const std::function<hipError_t(double *)> &own_rhs, double *x,
                       const double *dinv, rt_solve_info *info, hipStream_t st);
 
-// The frequency-redistribution variant (rt_prd.hip): out = A in, or the
-// right-hand side when in is NULL; its Jacobi diagonal; workspace set-up.
+// The frequency-redistribution variant (rt_prd.hip): out = A (scale .* in)
+// (scale NULL: none), or the right-hand side when in is NULL; its Jacobi
+// diagonal; workspace set-up.
 hipError_t apply_prd_operator(const rt_handle *h, const double *in, double *out, hipStream_t s,
-                              bool bf16x3 = false);
+                              bool bf16x3 = false, const double *scale = nullptr);
 hipError_t prd_diag(const rt_handle *h, double *diag, double *dinv, hipStream_t s);
 int ensure_prd(rt_handle *h, hipStream_t s);
 int solve_prd_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *info,

@@ -1535,11 +1535,11 @@ int run_solver(rt_handle *h, int kind, const double *b, double *x, rt_solve_info
     if (kind == 0 && h->opt.precond == RT_PC_JACOBI && h->fs != RT_FS_DELO_PARABOLIC &&
         few_deep_slabs(h)) {
         const double *bb = b ? b : h->d_b;
-        auto op64 = [&](const double *in, double *out) {
-            return apply_operator(h, in, nullptr, out, nullptr, false, 0, s);
+        auto op64 = [&](const double *in, const double *scale, double *out) {
+            return apply_operator(h, in, scale, out, nullptr, false, 0, s);
         };
-        auto op32 = [&](const double *in, double *out) {
-            return apply_operator(h, in, nullptr, out, nullptr, true, 0, s);
+        auto op32 = [&](const double *in, const double *scale, double *out) {
+            return apply_operator(h, in, scale, out, nullptr, true, 0, s);
         };
         auto own = [&](double *bo) {
             return hipMemcpyAsync(bo, h->d_b, sizeof(double) * h->n_unk, hipMemcpyDeviceToDevice, s);

@@ -15,7 +15,11 @@
 //    (eqs. J00/J02 before the frequency integral) per |mu| to a stage; the
 //    stage is then summed over |mu| in order into J, frequency-major
 //    (J[p][k][K]).  The stage lives in LDS when it fits, else in a global
-//    buffer private to the workgroup;
+//    buffer private to the workgroup.  When a lane's chunk has at most 8
+//    points, prd_sweep_cached_kernel does the same with the sources staged
+//    in LDS and each step's coefficients computed once: the second pass only
+//    adds the entering intensity's share through the attenuation products
+//    kept from the first;
 //  * prd_contract_kernel: the redistribution Jt(p, c) = sum_q R(p, q) w_q
 //    J(q, c) over the columns c = (k, K) of a slab -- a dense product, on
 //    the FP64 matrix cores (v_mfma_f64_16x16x4: one workgroup per 16 x 16
@@ -58,10 +62,11 @@ struct PrdArgs {
     long long nbf;        // entries per half of Rbf
     int nqp;
     const double *sig_in; // NULL: right-hand side (zero source, bottom inflow)
+    const double *scale;  // optional: the operator acts on scale .* sig_in
     double *sig_out;
     double *stage;        // global stage (when the LDS one does not fit)
     double *J;            // [n_nu][ns_total][2]
-    int fs, M, n_nu, ns_total, nch;
+    int fs, M, n_nu, ns_total, ns_max, nch;
 };
 
 // Lanes per (|mu|, chunk): M |mu| values times nch chunks <= kPrdSweepNT.
@@ -99,10 +104,15 @@ __global__ __launch_bounds__(kPrdSweepNT) void prd_sweep_kernel(PrdArgs a) {
     const double *tau = a.tau + at.doff;
     auto src = [&](int j, double &s0, double &s2) {
         if (a.sig_in) {
-            const double2 v = *reinterpret_cast<const double2 *>(
-                a.sig_in + 2 * ((long long)(at.doff + j) * a.n_nu + p));
+            const long long e = 2 * ((long long)(at.doff + j) * a.n_nu + p);
+            const double2 v = *reinterpret_cast<const double2 *>(a.sig_in + e);
             s0 = v.x;
             s2 = v.y;
+            if (a.scale) {
+                const double2 sc = *reinterpret_cast<const double2 *>(a.scale + e);
+                s0 *= sc.x;
+                s2 *= sc.y;
+            }
         } else {
             s0 = s2 = 0.0;
         }
@@ -228,6 +238,171 @@ __global__ __launch_bounds__(kPrdSweepNT) void prd_sweep_kernel(PrdArgs a) {
     }
 }
 
+// The same sweep for one formal solver FS, with the step coefficients of a
+// chunk computed once.  The frequency's sources and the slab's depths are
+// staged in LDS first.  Pass 1 runs each chunk from zero entering intensity,
+// writes that part of the lane's quadrature share to the stage (the downward
+// direction sets a slot, the upward one adds to it), keeps the running
+// attenuation products alpha_i = E_first .. E_i of its points in registers,
+// and leaves the chunk's map in LDS.  After the fold over the preceding
+// chunks, pass 2 only adds alpha_i times the share of the entering intensity
+// (the response is linear in it): no coefficient is computed twice.  A lane
+// holds at most LMAX points per direction; the host launches this kernel only
+// when every chunk fits.  LDS (doubles): stage [ns_max][M][2], maps
+// [2][nch][M][3], sources [ns_max][2], depths [ns_max].
+template <int FS, int NT, int LMAX>
+__global__ __launch_bounds__(NT) void prd_sweep_cached_kernel(PrdArgs a) {
+    extern __shared__ double lds[];
+    const int p = blockIdx.x, slab = blockIdx.y;
+    const AtmDesc at = a.atm[slab];
+    const int M = a.M, nch = a.nch, ns = at.ns, t = threadIdx.x;
+    double *stage = lds;
+    double *carry = stage + 2LL * M * a.ns_max;
+    double *ssrc = carry + 6LL * nch * M;
+    double *stau = ssrc + 2LL * a.ns_max;
+    for (int j = t; j < ns; j += NT) {
+        double2 v = make_double2(0.0, 0.0);
+        if (a.sig_in) {
+            const long long e = 2 * ((long long)(at.doff + j) * a.n_nu + p);
+            v = *reinterpret_cast<const double2 *>(a.sig_in + e);
+            if (a.scale) {
+                const double2 sc = *reinterpret_cast<const double2 *>(a.scale + e);
+                v.x *= sc.x;
+                v.y *= sc.y;
+            }
+        }
+        ssrc[2 * j] = v.x;
+        ssrc[2 * j + 1] = v.y;
+        stau[j] = a.tau[at.doff + j];
+    }
+    __syncthreads();
+
+    const bool active = t < M * nch;
+    const int mp = active ? t % M : 0, c = active ? t / M : 0;
+    const int L = (ns + nch - 1) / nch;
+    const int j0 = min(c * L, ns), j1 = min(j0 + L, ns);
+    const double kap = a.opac[(long long)slab * a.n_nu + p] / a.mu_pos[mp];
+    const double wq = 0.5 * a.w_pos[mp];
+    const double t1 = a.dirc[mp].x, t12 = a.dirc[mp].y;
+    auto slot = [&](int j) {
+        return reinterpret_cast<double2 *>(stage + 2 * stage_slot(j, mp, M));
+    };
+    // the lane's share of the quadrature at depth j: set (downward) or add
+    auto emit = [&](int dir, int j, double X, double Y) {
+        double2 v = make_double2(wq * fma(t1, Y, X), wq * fma(t12, Y, t1 * X));
+        double2 *d = slot(j);
+        if (dir == 1) {
+            const double2 o = *d;
+            v.x += o.x;
+            v.y += o.y;
+        }
+        *d = v;
+    };
+
+    double alpha[2][LMAX];
+    int r0s[2], r1s[2];
+    if (active) {
+#pragma unroll
+        for (int dir = 0; dir < 2; ++dir) {
+            // ray points [r0, r1): point k is depth k going down, ns - 1 - k going up
+            const int r0 = dir == 0 ? j0 : ns - j1, r1 = dir == 0 ? j1 : ns - j0;
+            r0s[dir] = r0;
+            r1s[dir] = r1;
+            auto pt = [&](int k) { return dir == 0 ? k : ns - 1 - k; };
+            double X = 0.0, Y = 0.0, al = 1.0;
+            if (r0 < r1 && r0 == 0) {
+                X = (!a.sig_in && dir == 1) ? at.Ibot : 0.0;  // inflow at the entry point
+                emit(dir, pt(0), X, 0.0);
+            }
+            const int kb = max(r0, 1);
+            // upwind and current point of the first step (registers carry them on)
+            int ju = pt(kb - 1);
+            double su0 = 0.0, su2 = 0.0, tu = 0.0;
+            if (kb - 1 < ns) {
+                su0 = ssrc[2 * ju];
+                su2 = ssrc[2 * ju + 1];
+                tu = stau[ju];
+            }
+#pragma unroll
+            for (int i = 0; i < LMAX; ++i) {
+                const int k = kb + i;
+                alpha[dir][i] = 0.0;
+                if (k < r1) {
+                    const int jk = pt(k);
+                    const double sk0 = ssrc[2 * jk], sk2 = ssrc[2 * jk + 1], tk = stau[jk];
+                    const double d = kap * fabs(tk - tu);
+                    double E, cu, ck, cd = 0.0;
+                    if constexpr (FS == RT_FS_DELO_PARABOLIC) {
+                        const bool has_dn = k + 1 < ns;
+                        const int jd = pt(min(k + 1, ns - 1));
+                        const double dd = has_dn ? kap * fabs(stau[jd] - tk) : 1.0;
+                        ray_step(FS, d, dd, has_dn, E, cu, ck, cd);
+                        const double sd0 = has_dn ? ssrc[2 * jd] : 0.0;
+                        const double sd2 = has_dn ? ssrc[2 * jd + 1] : 0.0;
+                        X = E * X + cu * su0 + ck * sk0 + cd * sd0;
+                        Y = E * Y + cu * su2 + ck * sk2 + cd * sd2;
+                    } else {
+                        ray_step(FS, d, 1.0, false, E, cu, ck, cd);
+                        X = E * X + cu * su0 + ck * sk0;
+                        Y = E * Y + cu * su2 + ck * sk2;
+                    }
+                    al *= E;
+                    alpha[dir][i] = al;
+                    emit(dir, jk, X, Y);
+                    su0 = sk0;
+                    su2 = sk2;
+                    tu = tk;
+                }
+            }
+            if (r0 < r1 && r0 == 0) al = 0.0;  // the boundary fixes this chunk's exit
+            double *m = carry + ((dir * nch + c) * M + mp) * 3;
+            m[0] = r0 < r1 ? al : 1.0;
+            m[1] = X;
+            m[2] = Y;
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int dir = 0; dir < 2; ++dir) {
+            const int r0 = r0s[dir], r1 = r1s[dir];
+            // a chunk that starts at the ray's entry is fixed by the boundary
+            if (r0 >= r1 || r0 == 0) continue;
+            // fold the preceding chunks (in ray order) into the entering intensity
+            double Xin = 0.0, Yin = 0.0;
+            const int n = dir == 0 ? c : nch - 1 - c;
+#pragma unroll 4
+            for (int i = 0; i < n; ++i) {
+                const int cc = dir == 0 ? i : nch - 1 - i;
+                const double *m = carry + ((dir * nch + cc) * M + mp) * 3;
+                Xin = m[0] * Xin + m[1];
+                Yin = m[0] * Yin + m[2];
+            }
+            const double u = wq * fma(t1, Yin, Xin), v = wq * fma(t12, Yin, t1 * Xin);
+#pragma unroll
+            for (int i = 0; i < LMAX; ++i) {
+                const int k = r0 + i;
+                if (k < r1) {
+                    double2 *d = slot(dir == 0 ? k : ns - 1 - k);
+                    double2 o = *d;
+                    o.x = fma(alpha[dir][i], u, o.x);
+                    o.y = fma(alpha[dir][i], v, o.y);
+                    *d = o;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // J[p][k][K] = sum over |mu| in order
+    double *Jo = a.J + 2 * ((long long)p * a.ns_total + at.doff);
+    for (int e = t; e < 2 * ns; e += NT) {
+        const int j = e >> 1, K = e & 1;
+        double s = 0.0;
+        for (int m = 0; m < M; ++m) s += stage[2 * stage_slot(j, m, M) + K];
+        Jo[e] = s;
+    }
+}
+
 // One workgroup per 16 x 16 tile of Jt (rows p, columns c = 2k + K) of one
 // slab; its four wavefronts take the q-steps q0 = 4 (w + 4 t), and their
 // accumulators are added in wavefront order through LDS.  Lane l feeds
@@ -279,7 +454,7 @@ __global__ __launch_bounds__(kPrdNT) void prd_contract_kernel(PrdArgs a) {
         const long long e = 2 * ((long long)(at.doff + k) * nnu + p) + K;
         const double t = wk * acc[rr] / a.phi[(long long)slab * nnu + p];
         if (a.sig_in)
-            a.sig_out[e] = a.sig_in[e] - t;
+            a.sig_out[e] = (a.scale ? a.scale[e] * a.sig_in[e] : a.sig_in[e]) - t;
         else
             a.sig_out[e] = t + (K == 0 ? at.eps * a.B[at.doff + k] : 0.0);
     }
@@ -361,7 +536,7 @@ __global__ __launch_bounds__(kPrdNT) void prd_contract_bf16x3_kernel(PrdArgs a) 
         const long long e = 2 * ((long long)(at.doff + k) * nnu + p) + K;
         const double t = wk * acc[r] / a.phi[(long long)slab * nnu + p];
         if (a.sig_in)
-            a.sig_out[e] = a.sig_in[e] - t;
+            a.sig_out[e] = (a.scale ? a.scale[e] * a.sig_in[e] : a.sig_in[e]) - t;
         else
             a.sig_out[e] = t + (K == 0 ? at.eps * a.B[at.doff + k] : 0.0);
     }
@@ -429,17 +604,71 @@ PrdArgs prd_args(const rt_handle *h, const double *in, double *out) {
     a.M = h->M;
     a.n_nu = h->n_nu;
     a.ns_total = h->ns_total;
-    a.nch = prd_chunks(h);
+    a.ns_max = h->ns_max;
+    a.nch = h->prd_cached_nt ? h->prd_cached_nch : prd_chunks(h);
     return a;
+}
+
+// The cached-coefficient sweep (kPrdSweepNT threads, as the general one):
+// its LDS bytes, and its kernel for the handle's formal solver.  A
+// 1024-thread variant (chunks half as long, twice as many) measured slower
+// on the 256-depth, 32 x 256 grid: 27.3 against 25.3 us per application.
+constexpr int kPrdCachedLen = 8;  // most points per chunk and direction
+size_t prd_cached_lds(const rt_handle *h, int nch) {
+    return ((size_t)2 * h->M * h->ns_max + (size_t)6 * nch * h->M + (size_t)3 * h->ns_max) *
+           sizeof(double);
+}
+const void *prd_cached_kernel(int fs) {
+    constexpr int NT = kPrdSweepNT, LM = kPrdCachedLen;
+    switch (fs) {
+        case RT_FS_TRAPEZOIDAL: return (const void *)prd_sweep_cached_kernel<RT_FS_TRAPEZOIDAL, NT, LM>;
+        case RT_FS_IMPLICIT_EULER:
+            return (const void *)prd_sweep_cached_kernel<RT_FS_IMPLICIT_EULER, NT, LM>;
+        case RT_FS_DELO_PARABOLIC:
+            return (const void *)prd_sweep_cached_kernel<RT_FS_DELO_PARABOLIC, NT, LM>;
+        default: return (const void *)prd_sweep_cached_kernel<RT_FS_DELO_LINEAR, NT, LM>;
+    }
+}
+
+// Take the cached sweep when every chunk fits its registers and its LDS fits
+// the device (raising the kernel's LDS limit where needed); else the general
+// sweep.
+void choose_prd_sweep(rt_handle *h) {
+    h->prd_cached_nt = h->prd_cached_nch = 0;
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    const int nch = prd_chunks(h);
+    const size_t lds = prd_cached_lds(h, nch);
+    if ((h->ns_max + nch - 1) / nch > kPrdCachedLen || lds > (size_t)lds_max) return;
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute(prd_cached_kernel(h->fs), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    h->prd_cached_nt = kPrdSweepNT;
+    h->prd_cached_nch = nch;
 }
 
 }  // namespace
 
 hipError_t apply_prd_operator(const rt_handle *h, const double *in, double *out, hipStream_t s,
-                              bool bf16x3) {
-    const PrdArgs a = prd_args(h, in, out);
+                              bool bf16x3, const double *scale) {
+    PrdArgs a = prd_args(h, in, out);
+    a.scale = in ? scale : nullptr;
     const dim3 grid(h->n_nu, h->n_atm);
-    if (prd_global_stage(h))
+    if (h->prd_cached_nt) {
+        PrdArgs arg = a;
+        void *args[] = {&arg};
+        const hipError_t e = hipLaunchKernel(prd_cached_kernel(h->fs), grid,
+                                             dim3(h->prd_cached_nt), args,
+                                             prd_cached_lds(h, h->prd_cached_nch), s);
+        if (e != hipSuccess) return e;
+    } else if (prd_global_stage(h))
         hipLaunchKernelGGL(prd_sweep_kernel<true>, grid, dim3(kPrdSweepNT), prd_carry_bytes(h), s,
                            a);
     else
@@ -480,6 +709,7 @@ int ensure_prd(rt_handle *h, hipStream_t s) {
     if ((prd_global_stage(h) && !get(&h->d_prd_Jm, 2LL * h->M * npts)) || !get(&h->d_prd_J, 2 * npts) ||
         !get(&h->d_prd_diag, 2 * npts) || !get(&h->d_prd_dinv, 2 * npts))
         return fail(RT_ENOMEM, "redistribution workspace allocation failed");
+    choose_prd_sweep(h);
     if (prd_diag(h, h->d_prd_diag, h->d_prd_dinv, s) != hipSuccess)
         return fail(RT_EDEVICE, "redistribution diagonal launch failed");
     h->prd_ready = true;
@@ -490,12 +720,16 @@ int solve_prd_gmres(rt_handle *h, const double *b, double *x, rt_solve_info *inf
                     hipStream_t st) {
     const int rc = ensure_prd(h, st);
     if (rc != RT_OK) return rc;
-    auto op = [&](const double *in, double *out) { return apply_prd_operator(h, in, out, st); };
+    auto op = [&](const double *in, const double *scale, double *out) {
+        return apply_prd_operator(h, in, out, st, false, scale);
+    };
     auto rhs = [&](double *bo) { return apply_prd_operator(h, nullptr, bo, st); };
     if (h->opt.precision == RT_PREC_MIXED)
         return solve_seg_refined(
             h, op,
-            [&](const double *in, double *out) { return apply_prd_operator(h, in, out, st, true); },
+            [&](const double *in, const double *scale, double *out) {
+                return apply_prd_operator(h, in, out, st, true, scale);
+            },
             2LL * h->n_nu, b, rhs, x, h->d_prd_dinv, info, st);
     return solve_seg_gmres(h, op, 2LL * h->n_nu, b, rhs, x, h->d_prd_dinv, info, st);
 }

@@ -31,7 +31,7 @@ def normwise(ref, y, v):
 
 
 @pytest.mark.parametrize("gamma", [0.0, 0.5])
-@pytest.mark.parametrize("fs", ["delo_linear", "delo_parabolic"])
+@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal", "implicit_euler", "delo_parabolic"])
 def test_prd_subgrid_against_oracle_and_dense(gamma, fs):
     p = W.config1_subgrid(fs)
     R = W.redistribution_matrix(p.x, p.w_nu, p.phi[0], gamma)
@@ -130,6 +130,14 @@ def test_prd_uneven_batch(fs):
     """Three slabs of 7, 23 and 40 depths with their own R, profiles and
     parameters: per-slab depth chunks (some empty) and slab offsets."""
     _check_batch(*_batch_case([7, 23, 40], 8, 12, fs, 0.5, 5))
+
+
+@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal", "implicit_euler", "delo_parabolic"])
+def test_prd_ragged_depth_chunks(fs):
+    """16 |mu| and slabs of 250, 77 and 130 depths: 32 depth chunks per ray of
+    8, 3 and 5 points, ragged last chunks and empty ones, for every formal
+    solver."""
+    _check_batch(*_batch_case([250, 77, 130], 32, 10, fs, 0.5, 9))
 
 
 def test_prd_long_rays_global_stage():
