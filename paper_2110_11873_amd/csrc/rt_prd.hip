@@ -16,10 +16,10 @@
 //    stage is then summed over |mu| in order into J, frequency-major
 //    (J[p][k][K]).  The stage lives in LDS when it fits, else in a global
 //    buffer private to the workgroup.  When a lane's chunk has at most 8
-//    points, prd_sweep_cached_kernel does the same with the sources staged
-//    in LDS and each step's coefficients computed once: the second pass only
-//    adds the entering intensity's share through the attenuation products
-//    kept from the first;
+//    points, prd_sweep_cached_kernel does the same with the chunk in
+//    registers, each interval's coefficients computed once for both
+//    directions, and the entering intensity's share added through the
+//    attenuation products kept from the one pass;
 //  * prd_contract_kernel: the redistribution Jt(p, c) = sum_q R(p, q) w_q
 //    J(q, c) over the columns c = (k, K) of a slab -- a dense product, on
 //    the FP64 matrix cores (v_mfma_f64_16x16x4: one workgroup per 16 x 16
@@ -238,17 +238,19 @@ __global__ __launch_bounds__(kPrdSweepNT) void prd_sweep_kernel(PrdArgs a) {
     }
 }
 
-// The same sweep for one formal solver FS, with the step coefficients of a
-// chunk computed once.  The frequency's sources and the slab's depths are
-// staged in LDS first.  Pass 1 runs each chunk from zero entering intensity,
-// writes that part of the lane's quadrature share to the stage (the downward
-// direction sets a slot, the upward one adds to it), keeps the running
-// attenuation products alpha_i = E_first .. E_i of its points in registers,
-// and leaves the chunk's map in LDS.  After the fold over the preceding
-// chunks, pass 2 only adds alpha_i times the share of the entering intensity
-// (the response is linear in it): no coefficient is computed twice.  A lane
-// holds at most LMAX points per direction; the host launches this kernel only
-// when every chunk fits.  LDS (doubles): stage [ns_max][M][2], maps
+// The same sweep for one formal solver FS, each chunk held in registers.  The
+// frequency's sources and the slab's depths are staged in LDS; a lane loads
+// its chunk's points (and the one before and after it) into registers, and
+// for the two-point formal solvers computes each interval's coefficients once
+// for both directions (they depend on the interval's optical step only).
+// Both directions then run from zero entering intensity (or from the
+// boundary, for the chunk that holds the ray's entry point), keeping per
+// point the sum of the two local intensities and each direction's running
+// attenuation product alpha; the chunk maps go to LDS and are folded as in
+// the general sweep, and each point's share, local part plus alpha times the
+// entering intensity of either direction, is written to the stage once.  A
+// lane holds at most LMAX points; the host launches this kernel only when
+// every chunk fits.  LDS (doubles): stage [ns_max][M][2], maps
 // [2][nch][M][3], sources [ns_max][2], depths [ns_max].
 template <int FS, int NT, int LMAX>
 __global__ __launch_bounds__(NT) void prd_sweep_cached_kernel(PrdArgs a) {
@@ -280,116 +282,149 @@ __global__ __launch_bounds__(NT) void prd_sweep_cached_kernel(PrdArgs a) {
     const bool active = t < M * nch;
     const int mp = active ? t % M : 0, c = active ? t / M : 0;
     const int L = (ns + nch - 1) / nch;
-    const int j0 = min(c * L, ns), j1 = min(j0 + L, ns);
+    const int j0 = min(c * L, ns), j1 = min(j0 + L, ns), len = j1 - j0;
     const double kap = a.opac[(long long)slab * a.n_nu + p] / a.mu_pos[mp];
     const double wq = 0.5 * a.w_pos[mp];
     const double t1 = a.dirc[mp].x, t12 = a.dirc[mp].y;
-    auto slot = [&](int j) {
-        return reinterpret_cast<double2 *>(stage + 2 * stage_slot(j, mp, M));
-    };
-    // the lane's share of the quadrature at depth j: set (downward) or add
-    auto emit = [&](int dir, int j, double X, double Y) {
-        double2 v = make_double2(wq * fma(t1, Y, X), wq * fma(t12, Y, t1 * X));
-        double2 *d = slot(j);
-        if (dir == 1) {
-            const double2 o = *d;
-            v.x += o.x;
-            v.y += o.y;
-        }
-        *d = v;
-    };
 
-    double alpha[2][LMAX];
-    int r0s[2], r1s[2];
-    if (active) {
+    // point index i <-> depth j0 - 1 + i, i = 0 .. LMAX + 1; the chunk's own
+    // points are i = 1 .. len; zero source and depth off the slab
+    double s0[LMAX + 2], s2[LMAX + 2], dq[LMAX + 1];
+    {
+        double tt[LMAX + 2];
 #pragma unroll
-        for (int dir = 0; dir < 2; ++dir) {
-            // ray points [r0, r1): point k is depth k going down, ns - 1 - k going up
-            const int r0 = dir == 0 ? j0 : ns - j1, r1 = dir == 0 ? j1 : ns - j0;
-            r0s[dir] = r0;
-            r1s[dir] = r1;
-            auto pt = [&](int k) { return dir == 0 ? k : ns - 1 - k; };
+        for (int i = 0; i < LMAX + 2; ++i) {
+            const int j = j0 - 1 + i;
+            const bool on = j >= 0 && j < ns && i <= len + 1;
+            const int jc = min(max(j, 0), ns - 1);
+            s0[i] = on ? ssrc[2 * jc] : 0.0;
+            s2[i] = on ? ssrc[2 * jc + 1] : 0.0;
+            tt[i] = stau[jc];
+        }
+        // optical step of interval q, between points q and q + 1 (0 off the slab)
+#pragma unroll
+        for (int q = 0; q < LMAX + 1; ++q) {
+            const int j = j0 - 1 + q;
+            dq[q] = (j >= 0 && j + 1 < ns) ? kap * fabs(tt[q + 1] - tt[q]) : 0.0;
+        }
+    }
+    // XL, YL: sum of the two directions' local intensities at point i;
+    // ad, au: attenuation from the chunk's entry to point i, downward and upward
+    double XL[LMAX + 1], YL[LMAX + 1], ad[LMAX + 1], au[LMAX + 1];
+#pragma unroll
+    for (int i = 0; i <= LMAX; ++i) XL[i] = YL[i] = ad[i] = au[i] = 0.0;
+    const bool top_entry = j0 == 0, bot_entry = j1 == ns;
+    double mapd[3] = {1.0, 0.0, 0.0}, mapu[3] = {1.0, 0.0, 0.0};
+    if (active && len > 0) {
+        // step coefficients of every interval (two-point solvers: shared by
+        // both directions)
+        double Eq[LMAX + 1], uq[LMAX + 1], kq[LMAX + 1];
+        if constexpr (FS != RT_FS_DELO_PARABOLIC) {
+#pragma unroll
+            for (int q = 0; q < LMAX + 1; ++q) {
+                double cd;
+                ray_step(FS, dq[q], 1.0, false, Eq[q], uq[q], kq[q], cd);
+            }
+        }
+        // downward: point i from i - 1 through interval i - 1
+        {
             double X = 0.0, Y = 0.0, al = 1.0;
-            if (r0 < r1 && r0 == 0) {
-                X = (!a.sig_in && dir == 1) ? at.Ibot : 0.0;  // inflow at the entry point
-                emit(dir, pt(0), X, 0.0);
-            }
-            const int kb = max(r0, 1);
-            // upwind and current point of the first step (registers carry them on)
-            int ju = pt(kb - 1);
-            double su0 = 0.0, su2 = 0.0, tu = 0.0;
-            if (kb - 1 < ns) {
-                su0 = ssrc[2 * ju];
-                su2 = ssrc[2 * ju + 1];
-                tu = stau[ju];
-            }
 #pragma unroll
-            for (int i = 0; i < LMAX; ++i) {
-                const int k = kb + i;
-                alpha[dir][i] = 0.0;
-                if (k < r1) {
-                    const int jk = pt(k);
-                    const double sk0 = ssrc[2 * jk], sk2 = ssrc[2 * jk + 1], tk = stau[jk];
-                    const double d = kap * fabs(tk - tu);
-                    double E, cu, ck, cd = 0.0;
-                    if constexpr (FS == RT_FS_DELO_PARABOLIC) {
-                        const bool has_dn = k + 1 < ns;
-                        const int jd = pt(min(k + 1, ns - 1));
-                        const double dd = has_dn ? kap * fabs(stau[jd] - tk) : 1.0;
-                        ray_step(FS, d, dd, has_dn, E, cu, ck, cd);
-                        const double sd0 = has_dn ? ssrc[2 * jd] : 0.0;
-                        const double sd2 = has_dn ? ssrc[2 * jd + 1] : 0.0;
-                        X = E * X + cu * su0 + ck * sk0 + cd * sd0;
-                        Y = E * Y + cu * su2 + ck * sk2 + cd * sd2;
-                    } else {
-                        ray_step(FS, d, 1.0, false, E, cu, ck, cd);
-                        X = E * X + cu * su0 + ck * sk0;
-                        Y = E * Y + cu * su2 + ck * sk2;
-                    }
-                    al *= E;
-                    alpha[dir][i] = al;
-                    emit(dir, jk, X, Y);
-                    su0 = sk0;
-                    su2 = sk2;
-                    tu = tk;
+            for (int i = 1; i <= LMAX; ++i) {
+                if (i > len) break;
+                const int j = j0 - 1 + i;
+                if (j == 0) {  // the ray's entry point: no incoming radiation at the top
+                    X = Y = 0.0;
+                    ad[i] = 0.0;
+                    continue;
                 }
+                double E, cu, ck, cd = 0.0;
+                if constexpr (FS == RT_FS_DELO_PARABOLIC) {
+                    const bool has_dn = j + 1 < ns;
+                    ray_step(FS, dq[i - 1], has_dn ? dq[i] : 1.0, has_dn, E, cu, ck, cd);
+                } else {
+                    E = Eq[i - 1];
+                    cu = uq[i - 1];
+                    ck = kq[i - 1];
+                }
+                X = E * X + cu * s0[i - 1] + ck * s0[i] + cd * s0[i + 1];
+                Y = E * Y + cu * s2[i - 1] + ck * s2[i] + cd * s2[i + 1];
+                al *= E;
+                XL[i] = X;
+                YL[i] = Y;
+                ad[i] = al;
             }
-            if (r0 < r1 && r0 == 0) al = 0.0;  // the boundary fixes this chunk's exit
-            double *m = carry + ((dir * nch + c) * M + mp) * 3;
-            m[0] = r0 < r1 ? al : 1.0;
-            m[1] = X;
-            m[2] = Y;
+            mapd[0] = top_entry ? 0.0 : al;  // the boundary fixes this chunk's exit
+            mapd[1] = X;
+            mapd[2] = Y;
+        }
+        // upward: point i from i + 1 through interval i
+        {
+            double X = 0.0, Y = 0.0, al = 1.0;
+#pragma unroll
+            for (int i = LMAX; i >= 1; --i) {
+                if (i > len) continue;
+                const int j = j0 - 1 + i;
+                if (j == ns - 1) {  // the ray's entry point: the bottom inflow
+                    X = (!a.sig_in) ? at.Ibot : 0.0;
+                    Y = 0.0;
+                    XL[i] += X;
+                    au[i] = 0.0;
+                    continue;
+                }
+                double E, cu, ck, cd = 0.0;
+                if constexpr (FS == RT_FS_DELO_PARABOLIC) {
+                    const bool has_dn = j >= 1;
+                    ray_step(FS, dq[i], has_dn ? dq[i - 1] : 1.0, has_dn, E, cu, ck, cd);
+                } else {
+                    E = Eq[i];
+                    cu = uq[i];
+                    ck = kq[i];
+                }
+                X = E * X + cu * s0[i + 1] + ck * s0[i] + cd * s0[i - 1];
+                Y = E * Y + cu * s2[i + 1] + ck * s2[i] + cd * s2[i - 1];
+                al *= E;
+                XL[i] += X;
+                YL[i] += Y;
+                au[i] = al;
+            }
+            mapu[0] = bot_entry ? 0.0 : al;
+            mapu[1] = X;
+            mapu[2] = Y;
+        }
+    }
+    if (active) {
+        double *md = carry + ((0 * nch + c) * M + mp) * 3;
+        double *mu = carry + ((1 * nch + c) * M + mp) * 3;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            md[e] = mapd[e];
+            mu[e] = mapu[e];
         }
     }
     __syncthreads();
-    if (active) {
-#pragma unroll
-        for (int dir = 0; dir < 2; ++dir) {
-            const int r0 = r0s[dir], r1 = r1s[dir];
-            // a chunk that starts at the ray's entry is fixed by the boundary
-            if (r0 >= r1 || r0 == 0) continue;
-            // fold the preceding chunks (in ray order) into the entering intensity
-            double Xin = 0.0, Yin = 0.0;
-            const int n = dir == 0 ? c : nch - 1 - c;
+    if (active && len > 0) {
+        // entering intensities: the preceding chunks (in ray order) folded
+        double Xd = 0.0, Yd = 0.0, Xu = 0.0, Yu = 0.0;
 #pragma unroll 4
-            for (int i = 0; i < n; ++i) {
-                const int cc = dir == 0 ? i : nch - 1 - i;
-                const double *m = carry + ((dir * nch + cc) * M + mp) * 3;
-                Xin = m[0] * Xin + m[1];
-                Yin = m[0] * Yin + m[2];
-            }
-            const double u = wq * fma(t1, Yin, Xin), v = wq * fma(t12, Yin, t1 * Xin);
+        for (int i = 0; i < c; ++i) {
+            const double *m = carry + ((0 * nch + i) * M + mp) * 3;
+            Xd = m[0] * Xd + m[1];
+            Yd = m[0] * Yd + m[2];
+        }
+#pragma unroll 4
+        for (int i = nch - 1; i > c; --i) {
+            const double *m = carry + ((1 * nch + i) * M + mp) * 3;
+            Xu = m[0] * Xu + m[1];
+            Yu = m[0] * Yu + m[2];
+        }
 #pragma unroll
-            for (int i = 0; i < LMAX; ++i) {
-                const int k = r0 + i;
-                if (k < r1) {
-                    double2 *d = slot(dir == 0 ? k : ns - 1 - k);
-                    double2 o = *d;
-                    o.x = fma(alpha[dir][i], u, o.x);
-                    o.y = fma(alpha[dir][i], v, o.y);
-                    *d = o;
-                }
-            }
+        for (int i = 1; i <= LMAX; ++i) {
+            if (i > len) break;
+            const double X = XL[i] + ad[i] * Xd + au[i] * Xu;
+            const double Y = YL[i] + ad[i] * Yd + au[i] * Yu;
+            *reinterpret_cast<double2 *>(stage + 2 * stage_slot(j0 - 1 + i, mp, M)) =
+                make_double2(wq * fma(t1, Y, X), wq * fma(t12, Y, t1 * X));
         }
     }
     __syncthreads();
