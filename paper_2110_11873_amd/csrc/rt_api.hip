@@ -511,7 +511,7 @@ void rt_destroy(rt_handle *h) {
                     h->d_pz,    h->d_ones,  h->d_LU,      h->d_piv,     h->d_sing,
                     h->d_rpart, h->d_mu_idx, h->d_fsig, h->d_Rw,   h->d_Rw_bf, h->d_prd_Jm,
                     h->d_prd_J, h->d_prd_diag, h->d_prd_dinv, h->d_w64, h->d_w32, h->d_kt,
-                    h->d_dtau, h->seg_ws[0], h->seg_ws[1]};
+                    h->d_dtau, h->seg_ws[0], h->seg_ws[1], h->d_lu_order};
     clear_graphs(h);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
     for (hipEvent_t e : h->gev)

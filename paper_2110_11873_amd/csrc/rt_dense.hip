@@ -273,6 +273,7 @@ struct LuArgs {
     double *LU;    // in: A; out: L (unit, strictly below the diagonal) and U
     int *piv;      // at 2 doff + k
     int *sing;     // per slab: 1 if a pivot was zero
+    const int *order;  // workgroup -> slab (largest first), or NULL: workgroup = slab
 };
 
 template <int R, int NB, bool SPLIT = false>
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g, int K0s = 0)
     __shared__ double Lb21[kLuRows][kLuBB];   // its L21, staged rows
     __shared__ double Ub[NB][kLuBB];          // a panel's U12 on the rest of its block
     static_assert(kLuBB % NB == 0, "the outer block is whole panels");
-    const int slab = blockIdx.x;
+    const int slab = g.order ? g.order[blockIdx.x] : blockIdx.x;
     const AtmDesc at = g.atm[slab];
     const int N = 2 * at.ns;
     double *A = g.LU + at.a_off;
@@ -708,17 +709,31 @@ int lu_factor(rt_handle *h, hipStream_t s) {
         return fail(RT_EINVAL, "the LU route supports the two-point formal solvers only");
     const size_t bytes = sizeof(double) * (size_t)std::max<long long>(h->n_dense, 1);
     if (!h->d_LU) {
-        // all three or none: a failed allocation frees the others, so a later
+        // all four or none: a failed allocation frees the others, so a later
         // call starts over instead of finding a partial set
         if (hipMalloc((void **)&h->d_LU, bytes) != hipSuccess ||
             hipMalloc((void **)&h->d_piv, sizeof(int) * h->n_unk) != hipSuccess ||
-            hipMalloc((void **)&h->d_sing, sizeof(int) * h->n_atm) != hipSuccess) {
+            hipMalloc((void **)&h->d_sing, sizeof(int) * h->n_atm) != hipSuccess ||
+            hipMalloc((void **)&h->d_lu_order, sizeof(int) * h->n_atm) != hipSuccess) {
             (void)hipGetLastError();
-            for (void **p : {(void **)&h->d_LU, (void **)&h->d_piv, (void **)&h->d_sing}) {
+            for (void **p : {(void **)&h->d_LU, (void **)&h->d_piv, (void **)&h->d_sing,
+                             (void **)&h->d_lu_order}) {
                 if (*p) (void)hipFree(*p);
                 *p = nullptr;
             }
             return fail(RT_ENOMEM, "device allocation of the LU factors failed");
+        }
+        // one workgroup per slab, dispatched in order: the largest slabs first,
+        // so that the small ones fill in behind them (a factorization costs
+        // about N^3)
+        std::vector<int> order(h->n_atm);
+        for (int i = 0; i < h->n_atm; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return h->ns[x] > h->ns[y]; });
+        if (hipMemcpy(h->d_lu_order, order.data(), sizeof(int) * h->n_atm,
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(RT_EDEVICE, "copy of the factorization order failed");
         }
     }
     int rc = h->dense_ready ? RT_OK : assemble(h, h->d_LU, s);
@@ -726,7 +741,7 @@ int lu_factor(rt_handle *h, hipStream_t s) {
     if (h->dense_ready &&
         hipMemcpyAsync(h->d_LU, h->d_A, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return fail(RT_EDEVICE, "copy of the assembled operator failed");
-    LuArgs g{h->d_atm, h->d_LU, h->d_piv, h->d_sing};
+    LuArgs g{h->d_atm, h->d_LU, h->d_piv, h->d_sing, nullptr};
     const int N = 2 * h->ns_max;
     if (h->n_atm <= kLuSplitSlabs && N > kLuBB) {
         // few slabs: each 32-column block factored by one workgroup per slab,
@@ -752,6 +767,7 @@ int lu_factor(rt_handle *h, hipStream_t s) {
         h->lu_ready = true;
         return RT_OK;
     }
+    g.order = h->d_lu_order;
     if (N <= kLuNT)
         hipLaunchKernelGGL((lu_factor_kernel<1, kLuNB>), dim3(h->n_atm), dim3(kLuNT), 0, s, g);
     else if (N <= 2 * kLuNT)

@@ -291,6 +291,7 @@ struct rt_handle {
     double *d_LU = nullptr;       // LU factors of the assembled A
     int *d_piv = nullptr;         // their row exchanges
     int *d_sing = nullptr;        // per slab: a zero pivot was met
+    int *d_lu_order = nullptr;    // slabs by decreasing size: the factorization's workgroup order
     bool lu_ready = false;
 
     // solver workspace (allocated on first use)
