@@ -4,6 +4,7 @@
     python bench.py --op-only fp32|fp64 [--matvecs N] [--coef-mode M]   # operator leg alone
     python bench.py --copy-calib                        # 512 MiB device copy x3
     python bench.py --summarize-pmc DIR                 # counters -> profiles/
+    python bench.py --summarize-valu DIR                # VALU counters -> profiles/
 
 Workload: a batch of 512 independent isothermal slabs of uneven depth
 (Ns ~ U{64..512}, tau in [1e-4, tau_max], tau_max ~ logU[1e4, 1e8], 16
@@ -45,6 +46,8 @@ RT_MAX_RESTART_USED = 128  # no restart on the paper's grids (their counts stay 
 RTOL = 1e-9
 COPY_BYTES = 512 * 1024 * 1024
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c4.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "sweep_valu_c4.json")
+SIMDS, CLOCK_HZ, VALU_CYCLES = 1024, 2.4e9, 4  # 256 CUs x 4 SIMDs; a wave64 VALU op: 4 cycles
 CPU_SHARE = 16  # host cores of one GPU's share on the benchmark machines
 
 
@@ -65,6 +68,27 @@ def measured_traffic(kind):
     if t.get("source_hash") != sweep_source_hash() or kind not in t:
         return None
     return t[kind]["hbm_bytes_per_launch"]
+
+
+def measured_valu(kind):
+    """VALU instructions (per wavefront, summed over the dispatch) of one
+    sweep launch from the committed counter summary, or None if there is none
+    or the kernels changed since."""
+    try:
+        with open(VALU_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != sweep_source_hash() or kind not in t:
+        return None
+    return t[kind]["valu_insts_per_launch"]
+
+
+def valu_issue_frac(kind, us):
+    """Share of the operator's time that its sweep's VALU instructions keep
+    the 1024 SIMDs issuing (4 cycles per wave64 instruction at 2.4 GHz)."""
+    n = measured_valu(kind)
+    return None if n is None else n * VALU_CYCLES / (SIMDS * CLOCK_HZ * us * 1e-6)
 
 
 def op_only(kind, n, coef_mode=0):
@@ -168,6 +192,29 @@ def summarize_pmc(root):
         rec["hbm_bytes_per_launch"] = total
         out[kind] = rec
     with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def summarize_valu(root):
+    """Turn the SQ counter passes fp32_sq and fp64_sq under `root` (each a
+    rocprofv3 --pmc run of --op-only fp32 / fp64 with SQ_INSTS_VALU, its log
+    beside it as fp32_sq.log / fp64_sq.log) into profiles/sweep_valu_c4.json."""
+    out = {"source_hash": sweep_source_hash(), "simds": SIMDS, "clock_hz": CLOCK_HZ,
+           "cycles_per_valu": VALU_CYCLES}
+    for kind, tname in (("fp32", "sweep_kernel<float"), ("fp64", "sweep_kernel<double")):
+        fs = glob.glob(os.path.join(root, kind + "_sq", "**", "*counter_collection.csv"),
+                       recursive=True)
+        if len(fs) != 1:
+            raise SystemExit(f"{kind}_sq: expected one counter CSV, found {fs}")
+        with open(os.path.join(root, kind + "_sq.log")) as fh:
+            n = [json.loads(ln) for ln in fh if ln.startswith('{"op"')][0]["applications"]
+        c = _find(_counters(fs[0]), tname)
+        v = c["SQ_INSTS_VALU"][-n:]
+        w = c["SQ_WAVES"][-n:] if "SQ_WAVES" in c else [0.0]
+        out[kind] = {"applications": n, "valu_insts_per_launch": sum(v) / len(v),
+                     "waves_per_launch": sum(w) / len(w)}
+    with open(VALU_FILE, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
 
@@ -469,11 +516,14 @@ def main():
                     help="with --op-only: rt_options.coef_mode (0 = the tuned plan's)")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--summarize-pmc", metavar="DIR")
+    ap.add_argument("--summarize-valu", metavar="DIR")
     ap.add_argument("--routes", action="store_true",
                     help="time the dense, DELO-parabolic and field-unknown routes instead")
     args = ap.parse_args()
     if args.summarize_pmc:
         return summarize_pmc(args.summarize_pmc)
+    if args.summarize_valu:
+        return summarize_valu(args.summarize_valu)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the slabs of the batch are independent (a multi-GPU "
@@ -551,6 +601,16 @@ def main():
                                  "fp64_alu_frac": fl / (u64 * 1e-6) / 1e12 / ALU_PEAK_TFLOPS}
     out["coef_modes"] = modes
 
+    # the same mixed solve with every GMRES cycle replayed from a HIP graph
+    # (options.graphs), beside the eager launches `value` is measured with
+    if not args.no_extras:
+        with B.setup(p, rtol=RTOL, restart=30, maxit=20000, precision=B.RT_PREC_MIXED,
+                     autotune=True, graphs=1) as hg:
+            ng = max(2, args.steps // 2)
+            dtg, infog, _ = time_solves(torch, hg, x0, "gmres", ng, 1)
+            out["mixed_graph_replay_solves_per_s"] = p.n_atm * ng / dtg
+            out["mixed_graph_replay_relres_max"] = max(i.relres for i in infog)
+
     with B.setup(p, rtol=RTOL, restart=30, maxit=20000, autotune=True) as h:
         cm64 = h.sweep_config(False)["coef_mode"]
         kname64 = h.sweep_kernel_name(False)
@@ -575,6 +635,7 @@ def main():
         out["roofline_fp64"] = roofline_hbm(op_bytes(p, plan, cm64, 8), t64 * 1e3, kname64,
                                             measured_traffic("fp64"))
     out["roofline_fp64"]["coef_mode"] = MODE_NAMES[cm64]
+    out["roofline_fp64"]["valu_issue_frac"] = valu_issue_frac("fp64", t64 * 1e3)
     out["mixed_over_fp64"] = value / out["fp64_solves_per_s"]
     out["hbm_copy_GBs"] = copy_bandwidth(torch)  # measured, beside the 8 TB/s datasheet peak
 
@@ -666,6 +727,9 @@ def main():
         roof = roofline_hbm(op_bytes(p, plan, cm32, 4), t32 * 1e3, kname32,
                             measured_traffic("fp32"))
     roof["coef_mode"] = MODE_NAMES[cm32]
+    # the sweep's VALU issue time (counters of the same sources) over the
+    # operator's measured time: what holds the kernel when the bytes do not
+    roof["valu_issue_frac"] = valu_issue_frac("fp32", t32 * 1e3)
     line = {
         "metric": METRIC,
         "value": value,

@@ -30,6 +30,7 @@ constexpr int kFsNT = 1024;  // 16 wavefronts per chunk: its basis rows spread o
 constexpr int kFsChunk = 1024;  // vector entries per workgroup
 constexpr int kFsPerThread = kFsChunk / kFsNT;
 constexpr int kFsPerLane = kFsChunk / kWave;
+constexpr int kFsFuseMaxChunks = 256;  // more chunks: the partial sums are added once, apart
 
 // Workspace carved from one device allocation that the handle keeps between
 // calls (slot 0: the GMRES, 1: the refinement around it) and grows when a
@@ -148,6 +149,9 @@ __global__ __launch_bounds__(1024) void fs_reduce_kernel(FsArgs a, int nv, int m
 // adds the partial sums of all chunks itself -- in the order fs_reduce_kernel
 // uses, so every workgroup gets the same coefficients, bit for bit -- and then
 // works on its chunk.
+// (With many chunks that redundant sum costs more than a launch: from
+// kFsFuseMaxChunks chunks on, fs_reduce_kernel adds them once into h first
+// and fs_proj_kernel reads h; the sums are the same, bit for bit.)
 //   fs_proj_kernel:   h = sum_c part, w -= sum_i h_i V_i on the chunk, H column
 //                     (set or add), then the partial dot products of the new w
 //                     with V_i (nv rows) or with itself (nv = 0) into `out`;
@@ -199,10 +203,14 @@ __global__ __launch_bounds__(kFsNT) void fs_proj_kernel(FsArgs a, double *w, int
     const int s = blockIdx.y, c = blockIdx.x;
     if (!working(a, s)) return;
     const int lane = threadIdx.x % kWave;
-    const double *ps = in + (long long)s * a.nchunk * (a.m + 1);
-    for (int i = threadIdx.x / kWave; i < nv; i += kFsNT / kWave) {
-        const double t = chunk_sum(a, ps, i, lane);
-        if (lane == 0) hs[i] = t;
+    if (in) {
+        const double *ps = in + (long long)s * a.nchunk * (a.m + 1);
+        for (int i = threadIdx.x / kWave; i < nv; i += kFsNT / kWave) {
+            const double t = chunk_sum(a, ps, i, lane);
+            if (lane == 0) hs[i] = t;
+        }
+    } else {  // already added by fs_reduce_kernel (the same order)
+        for (int i = threadIdx.x; i < nv; i += kFsNT) hs[i] = a.h[(long long)s * (a.m + 1) + i];
     }
     __syncthreads();
     const long long lo = a.off[s] + (long long)c * kFsChunk;
@@ -550,10 +558,21 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
             // the norm's partial sums; Givens and the new basis vector
             hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)w, j + 1,
                                (const double *)a.V, 0);
-            hipLaunchKernelGGL(fs_proj_kernel, seg, blk, 0, st, a, w, j + 1, j, 1,
-                               (const double *)a.part, part2, j + 1);
-            hipLaunchKernelGGL(fs_proj_kernel, seg, blk, 0, st, a, w, j + 1, j, 0,
-                               (const double *)part2, a.part, 0);
+            if (nchunk <= kFsFuseMaxChunks) {
+                hipLaunchKernelGGL(fs_proj_kernel, seg, blk, 0, st, a, w, j + 1, j, 1,
+                                   (const double *)a.part, part2, j + 1);
+                hipLaunchKernelGGL(fs_proj_kernel, seg, blk, 0, st, a, w, j + 1, j, 0,
+                                   (const double *)part2, a.part, 0);
+            } else {
+                FsArgs a2 = a;
+                a2.part = part2;
+                hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, j + 1, 0);
+                hipLaunchKernelGGL(fs_proj_kernel, seg, blk, 0, st, a, w, j + 1, j, 1,
+                                   (const double *)nullptr, part2, j + 1);
+                hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a2, j + 1, 0);
+                hipLaunchKernelGGL(fs_proj_kernel, seg, blk, 0, st, a, w, j + 1, j, 0,
+                                   (const double *)nullptr, a.part, 0);
+            }
             hipLaunchKernelGGL(fs_close_kernel, seg, blk, 0, st, a, (const double *)w, j,
                                (const double *)a.part);
             ok(hipGetLastError());

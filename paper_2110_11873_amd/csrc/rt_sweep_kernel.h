@@ -624,13 +624,14 @@ __device__ __forceinline__ void dispatch_le(const SweepArgs &a, const BlockDesc 
     }
 }
 
-// Waves per SIMD the register allocation is held to: 5 for the FP32 body of
-// chunk length 8 that streams w (96 registers without spills, as the
-// pair-streaming body compiles to by itself; the recomputing body would
-// spill).
+// Waves per SIMD the register allocation is held to, for the bodies of chunk
+// length 8 that stream w: 5 in FP32 (96 registers, a handful spilled) and 3
+// in FP64 (168 registers, about 20 spilled; left alone it takes 244 and runs
+// two waves per SIMD, 3-6% slower).  The recomputing bodies would spill more.
 template <typename T, int L, int CM>
 struct MinWaves {
-    static constexpr int value = (sizeof(T) == 4 && L == 8 && CM == kCoefW) ? 5 : 1;
+    static constexpr int value =
+        (L == 8 && CM == kCoefW) ? (sizeof(T) == 4 ? 5 : 3) : 1;
 };
 
 // LDS: the quadrature rows (a.rows ? W : 1) x 2 ns_max values of type T, then
