@@ -131,6 +131,10 @@ typedef struct rt_handle rt_handle;
  *  normalize_profile  nonzero: divide the spectral weights w_p phi_p by their
  *                   sum so scattering conserves photons on the truncated grid;
  *                   zero: use w_p phi_p as given (the paper's setting)
+ *  R                NULL (complete redistribution), or the frequency
+ *                   redistribution matrices [n_atm][n_nu][n_nu], R[s][p][q],
+ *                   which rt_setup hands to rt_set_redistribution (rt_ext.h):
+ *                   the same as calling it after setup
  */
 typedef struct rt_problem {
     int n_atm;
@@ -149,6 +153,7 @@ typedef struct rt_problem {
     const double *I_bot;
     int formal_solver;
     int normalize_profile;
+    const double *R;
 } rt_problem;
 
 /*

@@ -192,8 +192,9 @@ int rt_solve_field_gmres(rt_handle *h, const double *b_field, double *I, rt_solv
  * [eps B, 0].  R proportional to phi(p) phi(q) gives back CRD at every p.
  * rt_set_redistribution: R (host, n_atm x n_nu x n_nu, R[s][p][q] row-major;
  *   copied, finite) for the handle's slabs; enables the calls below (RT_EINVAL
- *   before).  The contraction runs on the FP64 matrix cores (and on the BF16
- *   ones in the calls so named).
+ *   before).  rt_setup calls it itself when rt_problem.R is set.  The
+ *   contraction runs on the FP64 matrix cores (and on the BF16 ones in the
+ *   calls so named).
  * rt_prd_size: 2 n_nu sum ns doubles.
  * rt_apply_op_prd / rt_get_rhs_prd / rt_get_jacobi_diag_prd: A sigma, b,
  *   diag(A) (device arrays, stream-ordered).

@@ -55,7 +55,7 @@ class rt_problem(C.Structure):
         ("opac", C.POINTER(C.c_double)), ("eps", C.POINTER(C.c_double)),
         ("W2", C.POINTER(C.c_double)), ("B", C.POINTER(C.c_double)),
         ("I_bot", C.POINTER(C.c_double)), ("formal_solver", C.c_int),
-        ("normalize_profile", C.c_int),
+        ("normalize_profile", C.c_int), ("R", C.POINTER(C.c_double)),
     ]
 
 
@@ -169,7 +169,7 @@ def plan_key(prob, mixed: bool, arch: Optional[str] = None) -> str:
 class _ProblemBuffers:
     """Holds contiguous host copies while rt_setup reads them."""
 
-    def __init__(self, prob):
+    def __init__(self, prob, R=None):
         f = lambda a: np.ascontiguousarray(a, dtype=np.float64)  # noqa: E731
         self.ns = np.ascontiguousarray(prob.ns, dtype=np.int32)
         self.tau, self.mu, self.w_mu = f(prob.tau), f(prob.mu), f(prob.w_mu)
@@ -181,6 +181,11 @@ class _ProblemBuffers:
             int(self.mu.shape[0]), d(self.mu), d(self.w_mu), int(self.w_nu.shape[0]), d(self.w_nu),
             d(self.phi), d(self.opac), d(self.eps), d(self.W2), d(self.B), d(self.I_bot),
             int(prob.formal_solver), int(bool(prob.normalize_profile)))
+        # optional redistribution matrices, R[s][p][q] (one (n_nu, n_nu) matrix
+        # serves a single slab)
+        self.R = None if R is None else f(R)
+        if self.R is not None:
+            self.c.R = d(self.R)
 
 
 def validate(prob, options: Optional[rt_options] = None) -> int:
@@ -215,9 +220,9 @@ def _stream(stream):
 class Handle:
     """An rt_handle: a problem set up on the current GPU."""
 
-    def __init__(self, prob, options: Optional[rt_options] = None, **kw):
+    def __init__(self, prob, options: Optional[rt_options] = None, R=None, **kw):
         self.options = options if options is not None else default_options(**kw)
-        pb = _ProblemBuffers(prob)
+        pb = _ProblemBuffers(prob, R)
         h = C.c_void_p()
         _check(lib().rt_setup(C.byref(h), C.byref(pb.c), C.byref(self.options)))
         self._h = h

@@ -822,6 +822,8 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     RT_TRY(hip_check(apply_operator(h, nullptr, nullptr, h->d_b, nullptr, false, 1, s),
                      "right-hand side launch"));
     RT_TRY(hip_check(hipDeviceSynchronize(), "setup"));
+    // the frequency-redistribution variant, when the problem carries R
+    if (p->R) RT_TRY(rt_set_redistribution(h, p->R));
 #undef RT_TRY
     *out = h;
     return RT_OK;

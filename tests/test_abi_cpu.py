@@ -127,3 +127,34 @@ def test_null_handle_calls_fail_with_einval():
     L.rt_destroy(None)
     h = C.c_void_p()
     assert L.rt_setup(C.byref(h), None, None) == B.RT_EINVAL
+
+
+def test_binding_structs_match_the_c_header(tmp_path):
+    """Every field of rt_problem, rt_options and rt_solve_info sits at the
+    offset the C compiler gives it from include/rt.h (the binding's ctypes
+    layouts are written by hand)."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"rt_problem": B.rt_problem, "rt_options": B.rt_options,
+               "rt_solve_info": B.rt_solve_info}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rt.h"', '#include "rt_ext.h"',
+             "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'    printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'    printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln.strip()}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)

@@ -140,6 +140,20 @@ def test_prd_ragged_depth_chunks(fs):
     _check_batch(*_batch_case([250, 77, 130], 32, 10, fs, 0.5, 9))
 
 
+def test_prd_R_given_at_setup_equals_set_redistribution():
+    """rt_problem.R hands the matrices to rt_setup: the operator, right-hand
+    side and solve are those of a handle given R afterwards, bit for bit."""
+    p, R, v = _batch_case([23, 40], 8, 12, "delo_linear", 0.5, 10)
+    with B.setup(p) as h:
+        h.set_redistribution(R)
+        y0 = host(h.apply_op_prd(dev(v)))
+        b0 = host(h.get_rhs_prd())
+    with B.setup(p, R=R) as h:
+        y1 = host(h.apply_op_prd(dev(v)))
+        b1 = host(h.get_rhs_prd())
+    assert np.array_equal(y0, y1) and np.array_equal(b0, b1)
+
+
 def test_prd_long_rays_global_stage():
     """700 depths x 16 |mu|: the per-frequency quadrature stage exceeds the
     LDS budget and lives in global memory; a 300-depth slab beside it."""
