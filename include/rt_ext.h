@@ -84,8 +84,8 @@ int rt_sweep_coef_mode(const rt_handle *h, int fp32, int *mode);
 /*
  * Stored launch plans (rt_options.autotune).  rt_tuned_plan_status: 0 = no
  * plan was stored for the handle's problem (or autotune was off), 1 = a plan
- * measured with this build's sweep sources was applied, 2 = a plan measured
- * with other sources was applied (stale: re-tune).  rt_sweep_source_hash: the
+ * measured with the sweep sources this library was built from was applied,
+ * 2 = a plan measured with other sources was applied (stale: re-tune).  rt_sweep_source_hash: the
  * hash of the sweep sources this library was built from.  rt_plan_key: the
  * key of problem p at precision (RT_PREC_*) on architecture arch (NULL: the
  * current device's, e.g. "gfx950"), written NUL-terminated into buf of

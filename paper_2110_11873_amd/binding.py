@@ -317,8 +317,9 @@ class Handle:
         return o
 
     def tuned_plan_status(self):
-        """'none', 'current' (a stored plan measured with this build's sweep
-        sources was applied) or 'stale' (one measured with other sources)."""
+        """'none', 'current' (a stored plan measured with the sweep sources
+        this library was built from was applied) or 'stale' (one measured with other
+        sources)."""
         return {0: "none", 1: "current", 2: "stale"}[lib().rt_tuned_plan_status(self._h)]
 
     def sweep_kernel_name(self, fp32=False):

@@ -220,7 +220,7 @@ std::string plan_file_path(const rt_options &o) {
 
 // Apply the stored plan for this problem to the options the caller left
 // automatic (0).  Returns 0 when none is stored, 1 when the plan was made
-// with this build's sweep sources, 2 when with other sources.
+// with the sweep sources this library was built from, 2 when with other sources.
 int apply_stored_plan(const rt_problem *p, rt_options *o, const std::string &arch) {
     std::ifstream in(plan_file_path(*o));
     if (!in) return 0;

@@ -77,7 +77,7 @@ def test_stale_missing_and_unusable_plans(tmp_path):
 
 def test_shipped_plans_are_current_for_the_benchmark_batch():
     """The plan index next to the library holds plans for the 512-slab batch
-    measured with this build's sweep sources."""
+    measured with the sweep sources the library was built from."""
     p = W.config4(512)
     for prec in (B.RT_PREC_MIXED, B.RT_PREC_FP64):
         with B.setup(p, precision=prec, autotune=True) as h:
