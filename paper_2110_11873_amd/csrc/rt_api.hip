@@ -373,6 +373,7 @@ static SweepArgs sweep_args(rt_handle *h, const double *in, const double *scale,
     a.mask = mask;
     a.B = h->d_B;
     a.mode = mode;
+    a.part_f32 = fp32 ? 1 : 0;
     return a;
 }
 

@@ -90,7 +90,7 @@ struct SweepArgs {
     const double *sig_in;    // FP64 input, NULL = zero source
     const double *scale;     // optional elementwise scaling of sig_in
     double *sig_out;         // FP64 output
-    double *partial;         // per-block partial quadrature sums
+    double *partial;         // per-block partial quadrature sums (float values when part_f32)
     const int *mask;         // optional per-slab activity mask
     const double *B;         // Planck function (right-hand-side mode)
     int mode;                // 0: sigma_out = z - xi [J00, W2 J20]
@@ -100,6 +100,7 @@ struct SweepArgs {
                              // 0: one shared row filled wave after wave
     int src_lds;             // byte offset of the sources in the sweep's LDS (set at launch)
     int fs;                  // formal solver (coefficients computed in the sweep)
+    int part_f32;            // 1: the partial sums are FP32 (written by an FP32 sweep)
 };
 
 // --------------------------------------------------------------------------

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "rt_internal.h"
@@ -182,7 +183,8 @@ struct VecArgs {
     double tol;
     int maxit;
     int max_outer;
-    const double *partial;  // the sweep's per-block quadrature sums
+    const double *partial;  // the sweep's per-block quadrature sums (float values when part_f32)
+    int part_f32;           // 1: written by an FP32 sweep
     const double4 *Qs;      // per slab: sums over all rays of q, q T1, q (T1^2 + T2^2)
     const double *zin;      // fused Arnoldi step: the sweep's input P^-1 v_j when the
                             // preconditioner is not diagonal (NULL: v_j .* dinv)
@@ -526,21 +528,27 @@ __global__ __launch_bounds__(NTF) void gm_arnoldi_fused_kernel(VecArgs a, int j)
     double w0 = 0.0, w2 = 0.0;
     if (on) {
         double J0 = 0.0, J2 = 0.0;
-        const double *pJ = a.partial + at.part_off + 2 * k;
         const long long stride = 2LL * at.ns;
-        for (int b0 = 0; b0 < at.nblk; b0 += 8) {
-            double2 p[8];
+        auto add_slots = [&](const auto *pJ) {
+            using V2 = typename std::conditional<sizeof(*pJ) == 4, float2, double2>::type;
+            for (int b0 = 0; b0 < at.nblk; b0 += 8) {
+                V2 p[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                p[u] = *reinterpret_cast<const double2 *>(pJ + min(b0 + u, at.nblk - 1) * stride);
+                for (int u = 0; u < 8; ++u)
+                    p[u] = *reinterpret_cast<const V2 *>(pJ + min(b0 + u, at.nblk - 1) * stride);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (b0 + u < at.nblk) {
-                    J0 += p[u].x;
-                    J2 += p[u].y;
+                for (int u = 0; u < 8; ++u) {
+                    if (b0 + u < at.nblk) {
+                        J0 += (double)p[u].x;
+                        J2 += (double)p[u].y;
+                    }
                 }
             }
-        }
+        };
+        if (a.part_f32)
+            add_slots(reinterpret_cast<const float *>(a.partial) + at.part_off + 2 * k);
+        else
+            add_slots(a.partial + at.part_off + 2 * k);
         double vj0 = 0.0, vj2 = 0.0;
 #pragma unroll
         for (int t = 0; t < MR_; ++t)
@@ -1270,10 +1278,12 @@ struct Driver {
             } else {
                 ok(apply_sweep(h, vj, h->d_dinv, h->d_cycle, fp32, s));
             }
+            VecArgs af = a;
+            af.part_f32 = fp32 ? 1 : 0;  // the sweep's partial sums are in its precision
             if (j < 16)
-                hipLaunchKernelGGL(gm_arnoldi_fused_kernel<16>, dim3(h->n_atm), dim3(NTF), 0, s, a, j);
+                hipLaunchKernelGGL(gm_arnoldi_fused_kernel<16>, dim3(h->n_atm), dim3(NTF), 0, s, af, j);
             else
-                hipLaunchKernelGGL(gm_arnoldi_fused_kernel<MR>, dim3(h->n_atm), dim3(NTF), 0, s, a, j);
+                hipLaunchKernelGGL(gm_arnoldi_fused_kernel<MR>, dim3(h->n_atm), dim3(NTF), 0, s, af, j);
             ok(hipGetLastError());
         } else {
             prec_sweep(vj, h->d_w, h->d_cycle, fp32);

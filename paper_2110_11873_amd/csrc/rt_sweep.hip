@@ -32,6 +32,8 @@
 //    invalidate a whole L2): results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "rt_coef.h"
 #include "rt_internal.h"
 
@@ -238,23 +240,29 @@ __global__ void finalize_kernel(SweepArgs a) {
     if (k >= at.ns) return;
     const int kk = at.doff + k;
     const long long stride = 2LL * at.ns;
-    const double *pJ = a.partial + at.part_off + 2 * k;
     double J0 = 0.0, J2 = 0.0;
-    for (int j0 = 0; j0 < at.nblk; j0 += 8) {
-        double2 v[8];
+    auto add_slots = [&](const auto *pJ) {
+        using V2 = typename std::conditional<sizeof(*pJ) == 4, float2, double2>::type;
+        for (int j0 = 0; j0 < at.nblk; j0 += 8) {
+            V2 v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int j = min(j0 + u, at.nblk - 1);
-            v[u] = *reinterpret_cast<const double2 *>(pJ + j * stride);
-        }
+            for (int u = 0; u < 8; ++u) {
+                const int j = min(j0 + u, at.nblk - 1);
+                v[u] = *reinterpret_cast<const V2 *>(pJ + j * stride);
+            }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (j0 + u < at.nblk) {
-                J0 += v[u].x;
-                J2 += v[u].y;
+            for (int u = 0; u < 8; ++u) {
+                if (j0 + u < at.nblk) {
+                    J0 += (double)v[u].x;
+                    J2 += (double)v[u].y;
+                }
             }
         }
-    }
+    };
+    if (a.part_f32)
+        add_slots(reinterpret_cast<const float *>(a.partial) + at.part_off + 2 * k);
+    else
+        add_slots(a.partial + at.part_off + 2 * k);
     const long long e = 2LL * kk;
     double o0, o2;
     if (a.mode == 0) {

@@ -548,9 +548,10 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
     const double2 tf = a.dirc[bd.m];
     const T t1 = (T)tf.x, t12 = (T)tf.y;
 
-    // block totals of the 2 ns quadrature sums
+    // block totals of the 2 ns quadrature sums, stored in the sweep's type
+    // (an FP32 sweep's sums are FP32 values: half the bytes, the same numbers)
     const int nthr = kWave * W;
-    double *mine = a.partial + at.part_off + (long long)bd.slot * 2 * ns;
+    T *mine = reinterpret_cast<T *>(a.partial) + at.part_off + (long long)bd.slot * 2 * ns;
     if (a.rows) {
         // one LDS row per wave, then a fixed-order sum over the rows
         T *row = sacc + (long long)wave * 2 * ns;
@@ -572,7 +573,7 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
         for (int e = threadIdx.x; e < 2 * ns; e += nthr) {
             T s = sacc[e];
             for (int w = 1; w < W; ++w) s += sacc[(long long)w * 2 * ns + e];
-            mine[e] = (double)s;
+            mine[e] = s;
         }
     } else {
         // one shared row, filled wave after wave (fixed order)
@@ -595,7 +596,7 @@ __device__ __forceinline__ void sweep_rays(const SweepArgs &a, const BlockDesc &
             }
             __syncthreads();
         }
-        for (int e = threadIdx.x; e < 2 * ns; e += nthr) mine[e] = (double)sacc[e];
+        for (int e = threadIdx.x; e < 2 * ns; e += nthr) mine[e] = sacc[e];
     }
 }
 
