@@ -558,3 +558,37 @@ def test_full_batch_mixed_solve_sampled_slabs():
         b = O.rhs(p.slab(i))
         r = b - O.apply_slab(p, i, x[sl[i]])
         assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-9, i
+
+
+# ------------------------------------------------------- degenerate grids
+def _one_frequency(p):
+    """The same slabs with only the line-centre frequency of a 3-point grid."""
+    import dataclasses
+    return dataclasses.replace(p, x=p.x[1:2], w_nu=p.w_nu[1:2], phi=p.phi[:, 1:2],
+                               opac=p.opac[:, 1:2], name=p.name + "_1nu")
+
+
+@pytest.mark.parametrize("fs", ["delo_linear", "trapezoidal", "implicit_euler", "delo_parabolic"])
+@pytest.mark.parametrize("n_mu,n_nu", [(2, 1), (2, 3), (4, 1)])
+def test_degenerate_angle_and_frequency_grids(fs, n_mu, n_nu):
+    """One pair of directions and/or a single frequency (wave-batches mostly
+    padding rays), with slabs of 2, 3, 40 and 130 depths: operator, right-hand
+    side and diagonal against the oracle, and a GMRES solve checked by the
+    oracle's own residual."""
+    ns = [2, 3, 40, 130]
+    p = W.make_slabs(ns, [(1e-3, 1e5)] * len(ns), n_mu, 3, 6.0, [1e-3] * len(ns),
+                     [1e-2] * len(ns), [0.5] * len(ns), formal_solver=fs)
+    if n_nu == 1:
+        p = _one_frequency(p)
+    with B.setup(p, rtol=1e-10, restart=30, maxit=4000) as h:
+        check_apply(p, h, seeds=(21,))
+        b = host(h.get_rhs())
+        d = host(h.get_jacobi_diag())
+        x = dev(W.initial_guess(p))
+        rc, info = h.solve_gmres(x)
+        xs = host(x)
+    rb = O.rhs(p)
+    assert np.abs(b - rb).max() <= 1e-12 * np.abs(rb).max()
+    assert np.abs(d - O.diag(p)).max() <= 1e-12
+    assert rc == 0 and all(i.status == "converged" for i in info)
+    assert oracle_relres(p, xs).max() < 1e-10
