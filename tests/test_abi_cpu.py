@@ -67,6 +67,21 @@ def test_invalid_problems_rejected(mutate, fragment):
     assert fragment in B.last_error()
 
 
+def test_empty_problems_rejected():
+    """No slabs, no frequencies or no directions: RT_EINVAL naming the count."""
+    p = W.config1()
+    cases = [
+        (p.with_(ns=np.array([], dtype=np.int32), tau=np.array([]), B=np.array([]),
+                 phi=p.phi[:0], opac=p.opac[:0], eps=p.eps[:0], W2=p.W2[:0],
+                 I_bot=p.I_bot[:0]), "n_atm"),
+        (p.with_(w_nu=p.w_nu[:0], phi=p.phi[:, :0], opac=p.opac[:, :0], x=p.x[:0]), "n_nu"),
+        (p.with_(mu=p.mu[:0], w_mu=p.w_mu[:0]), "n_mu"),
+    ]
+    for q, frag in cases:
+        assert B.validate(q) == B.RT_EINVAL, frag
+        assert frag in B.last_error()
+
+
 def test_invalid_options_rejected():
     p = W.config1()
     for kw, frag in [(dict(restart=0), "restart"), (dict(restart=500), "restart"),
