@@ -154,6 +154,13 @@ def test_prd_R_given_at_setup_equals_set_redistribution():
     assert np.array_equal(y0, y1) and np.array_equal(b0, b1)
 
 
+@pytest.mark.parametrize("fs", ["delo_linear", "delo_parabolic"])
+def test_prd_one_direction_pair_two_frequencies(fs):
+    """One pair of directions (one lane per depth chunk, up to 300 chunks of
+    one point) and two frequencies, slabs of 2, 3, 40 and 300 depths."""
+    _check_batch(*_batch_case([2, 3, 40, 300], 2, 2, fs, 0.5, 11))
+
+
 def test_prd_long_rays_global_stage():
     """700 depths x 16 |mu|: the per-frequency quadrature stage exceeds the
     LDS budget and lives in global memory; a 300-depth slab beside it."""
