@@ -167,7 +167,9 @@ typedef struct rt_problem {
  *              relative residual of Sect. 4.2, computed in FP64 (1e-10)
  *  inner_rtol  MIXED: each inner FP32 GMRES solve stops once its Arnoldi
  *              residual estimate falls below inner_rtol times its right-hand
- *              side (3e-4) ...
+ *              side r (3e-4), or below 0.5 rtol ||b|| where that is looser
+ *              (the last refinement step: enough to bring the slab under
+ *              rtol, with a factor 2 to spare) ...
  *  inner_maxit MIXED: ... or after this many Arnoldi steps (200)
  *  max_outer   MIXED: refinement steps limit (30)
  *  chunk       formal-solver sweep chunk length: 0 = choose automatically,

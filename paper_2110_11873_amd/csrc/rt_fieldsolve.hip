@@ -702,10 +702,16 @@ int solve_seg_refined(rt_handle *h, const SegOp &op, const SegOp &op_lo,
             if (!(bn[s] == 0.0 || rn[s] < rtol * bn[s])) done = false;
         if (done || err != hipSuccess || total >= h->opt.maxit) break;
         // d from the cheaper operator, from zero; slabs already converged
-        // carry a tiny r and change x by a tiny d
+        // carry a tiny r and change x by a tiny d.  One tolerance for all
+        // slabs: the tightest that the slabs still refining need
+        double tol_in = 1.0;
+        for (int s = 0; s < n_atm; ++s)
+            if (bn[s] > 0.0 && !(rn[s] < rtol * bn[s]))
+                tol_in = std::min(tol_in, kIrMargin * rtol * bn[s] / rn[s]);
+        tol_in = std::max(tol_in, h->opt.inner_rtol);
         ok(fill(d, N, 0.0, st));
         std::vector<rt_solve_info> in(n_atm);
-        const int rc = solve_seg_gmres_tol(h, op_lo, per, r, own_rhs, d, dinv, h->opt.inner_rtol,
+        const int rc = solve_seg_gmres_tol(h, op_lo, per, r, own_rhs, d, dinv, tol_in,
                                            h->opt.inner_maxit, in.data(), st);
         if (rc != RT_OK && rc != RT_ENOCONV) {
             release();

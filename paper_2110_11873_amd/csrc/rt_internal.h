@@ -199,6 +199,13 @@ int ensure_dense(rt_handle *h, hipStream_t s);
 int lu_factor(rt_handle *h, hipStream_t s);
 hipError_t lu_solve(const rt_handle *h, const double *b, double *x, hipStream_t s);
 
+// Mixed-precision refinement: the inner solve of A d = r only has to bring
+// ||r - A d|| below rtol ||b||.  Asking for kIrMargin rtol ||b|| is a
+// relative tolerance of kIrMargin rtol ||b|| / ||r|| on the inner solve; where
+// that is looser than inner_rtol (the last refinement step) the inner solve
+// stops there instead of reducing the residual by the full inner_rtol.
+constexpr double kIrMargin = 0.5;
+
 // Krylov state kept on the device, one entry per slab.
 struct KState {
     double bnorm;     // ||b||
@@ -213,6 +220,7 @@ struct KState {
     int outer;        // mixed precision: refinement steps
     int half_done;    // BiCGSTAB: converged at the half step
     int pad0, pad1;
+    double tol_next;  // mixed precision: relative tolerance the next inner solve needs
 };
 
 }  // namespace rt
@@ -381,8 +389,8 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
                         const double *dinv, double rtol, int maxit, rt_solve_info *info,
                         hipStream_t st);
 // FP64 iterative refinement: r = b - A x with op, d from GMRES(m) on op_lo to
-// inner_rtol, x += d, until every slab's ||r|| < rtol ||b|| (or maxit inner
-// steps in total).
+// inner_rtol (or the looser tolerance kIrMargin allows), x += d, until every
+// slab's ||r|| < rtol ||b|| (or maxit inner steps in total).
 int solve_seg_refined(rt_handle *h, const SegOp &op, const SegOp &op_lo,
                       long long per, const double *b,
                       const std::function<hipError_t(double *)> &own_rhs, double *x,

@@ -188,7 +188,14 @@ struct VecArgs {
     const double4 *Qs;      // per slab: sums over all rays of q, q T1, q (T1^2 + T2^2)
     const double *zin;      // fused Arnoldi step: the sweep's input P^-1 v_j when the
                             // preconditioner is not diagonal (NULL: v_j .* dinv)
+    const KState *outer;    // inner solve of the mixed refinement: the outer states, whose
+                            // tol_next may loosen tol per slab (NULL: tol for every slab)
 };
+
+// The relative tolerance slab atm iterates to.
+__device__ inline double slab_tol(const VecArgs &a, int atm) {
+    return a.outer ? fmax(a.tol, a.outer[atm].tol_next) : a.tol;
+}
 
 // ---------------------------------------------------------------- counting
 __global__ void count_kernel(const int *flags, int n, int *out) {
@@ -255,8 +262,8 @@ __global__ void gm_restart_kernel(VecArgs a, int first, int x_zero, int accept_e
         } else if (!(beta == beta) || isinf(beta)) {
             S.status = RT_EBREAKDOWN;
             S.relres = beta / S.bnorm;
-        } else if (beta / S.bnorm < a.tol ||
-                   (accept_est && !first && S.resid / S.bnorm < a.tol)) {
+        } else if (beta / S.bnorm < slab_tol(a, atm) ||
+                   (accept_est && !first && S.resid / S.bnorm < slab_tol(a, atm))) {
             S.status = RT_OK;
             S.relres = beta / S.bnorm;
         } else if (S.iters >= a.maxit) {
@@ -310,8 +317,8 @@ __device__ inline void hessenberg_finish(const VecArgs &a, int atm, int j, doubl
     S.iters += 1;
     S.matvecs += 1;
     S.inner = j + 1;
-    const bool done = (S.resid / S.bnorm < a.tol) || !(hn > 0.0) || (S.iters >= a.maxit) ||
-                      (j + 1 == m) || !(S.resid == S.resid);
+    const bool done = (S.resid / S.bnorm < slab_tol(a, atm)) || !(hn > 0.0) ||
+                      (S.iters >= a.maxit) || (j + 1 == m) || !(S.resid == S.resid);
     if (done) a.cycle[atm] = 0;
 }
 
@@ -1088,7 +1095,8 @@ __global__ void direct_status_kernel(KState *st, const int *sing, int n_atm) {
 }
 
 // Outer step of the mixed-precision refinement: r = b - A x in FP64 (A x in
-// a.w), test it; if the slab goes on, clear the correction d (a.s).
+// a.w), test it; if the slab goes on, clear the correction d (a.s), and
+// record the relative tolerance that brings it below rtol (kIrMargin).
 __global__ void ir_residual_kernel(VecArgs a, int first) {
     __shared__ double red[2 * NW];
     __shared__ int s_go;
@@ -1125,6 +1133,7 @@ __global__ void ir_residual_kernel(VecArgs a, int first) {
         } else {
             go = 1;
             S.outer += 1;
+            S.tol_next = kIrMargin * a.tol / rel;
         }
         if (go != 1) a.active[atm] = 0;
         s_go = go;
@@ -1177,6 +1186,9 @@ struct Driver {
     // unit scaling in their updates (right preconditioning, the same iterates),
     // and x = P^-1 y at the end.  Jacobi folds D^-1 into the sweep instead.
     bool tri = false;
+    // mixed refinement: the outer states while an inner solve runs (per-slab
+    // tolerances, VecArgs::outer)
+    const KState *outer = nullptr;
 
     bool ok(hipError_t e) {
         if (e != hipSuccess && err == hipSuccess) err = e;
@@ -1358,6 +1370,7 @@ struct Driver {
         a.max_outer = h->opt.max_outer;
         a.partial = h->d_partial;
         a.Qs = h->d_Qs;
+        a.outer = outer;
         return a;
     }
 
@@ -1385,7 +1398,7 @@ struct Driver {
         // the last entry is the block plan the cycle was captured with
         std::vector<unsigned long long> key = {
             0, bits(b), bits(x), bits(st), bits(tol), (unsigned long long)maxit, fp32 ? 1ull : 0ull,
-            accept_est ? 1ull : 0ull, 0};
+            accept_est ? 1ull : 0ull, bits(outer), 0};
         while (err == hipSuccess) {
             const int act = count(h->d_active);
             if (act == 0) break;
@@ -1522,7 +1535,9 @@ struct Driver {
             if (count(outer_active) == 0) break;
             // inner: A32 d = r, d = 0 initially, on the slabs still refining
             init_state(st_in, outer_active);
+            outer = st;
             gmres(h->d_r, h->d_s, st_in, h->opt.inner_rtol, h->opt.inner_maxit, true, true, true);
+            outer = nullptr;
             hipLaunchKernelGGL(ir_update_kernel, dim3(nb), dim3(NT), 0, s, a, (const KState *)st_in);
             ok(hipGetLastError());
         }
