@@ -397,7 +397,7 @@ hipError_t apply_operator_into(rt_handle *h, const double *in, double *out, doub
     hipError_t e = launch_sweep(h->L, W, pf, false, coef_mode_of(h, false), a, plan_blocks(h),
                                 h->ns_max, s);
     if (e != hipSuccess) return e;
-    return launch_finalize(a, h->n_atm, h->ns_max, s);
+    return launch_finalize(a, h->n_atm, h->ns_max, plan_nblk_max(h), s);
 }
 
 hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, double *out,
@@ -410,7 +410,7 @@ hipError_t apply_operator(rt_handle *h, const double *in, const double *scale, d
     hipError_t e = launch_sweep(h->L, W, pf, fp32, coef_mode_of(h, fp32), a, plan_blocks(h),
                                 h->ns_max, s);
     if (e != hipSuccess) return e;
-    return launch_finalize(a, h->n_atm, h->ns_max, s);
+    return launch_finalize(a, h->n_atm, h->ns_max, plan_nblk_max(h), s);
 }
 
 void clear_graphs(rt_handle *h) {
@@ -600,6 +600,7 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
     }
     long long coef = 0, part = 0, qt = 0, dense = 0, ew = 0, part_t = 0;
     int blk = 0, blk_t = 0;
+    h->nblk_max = h->nblk_max_tail = 0;
     std::vector<AtmDesc> atm_t(h->n_atm);
     std::vector<BlockDesc> blk_t_h;
     // Waves per block and wave-batches per wave.  A block never mixes
@@ -678,6 +679,8 @@ int rt_setup(rt_handle **out, const rt_problem *p, const rt_options *o) {
             atm_t[a] = dt;
         }
         blk += d.nblk;
+        h->nblk_max = std::max(h->nblk_max, d.nblk);
+        h->nblk_max_tail = std::max(h->nblk_max_tail, atm_t[a].nblk);
         coef += (long long)h->M * d.nwb * d.bstride;
         qt += (long long)h->M * d.nwb * d.G;
         part += (long long)d.nblk * 2 * d.ns;

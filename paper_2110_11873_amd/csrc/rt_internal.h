@@ -162,7 +162,10 @@ int coef_mode_of(const rt_handle *h, bool fp32);
 // Launch configuration of the sweep for a handle: waves per block and whether
 // the next ray batch is loaded during the current one.
 void sweep_config(const rt_handle *h, bool fp32, int *W, bool *pf);
-hipError_t launch_finalize(const SweepArgs &a, int n_atm, int ns_max, hipStream_t s);
+// nblk_max: the most blocks of one slab in the plan a.atm describes (it sets
+// how many lanes share a point).
+hipError_t launch_finalize(const SweepArgs &a, int n_atm, int ns_max, int nblk_max,
+                           hipStream_t s);
 // Tile-ordered step coefficients of the modes that stream them (any output
 // may be NULL: not built), the tile-ordered weights and (kappa, 1 / kappa).
 hipError_t launch_coef_build(int nblocks, int W, const AtmDesc *atm, const BlockDesc *blk,
@@ -238,6 +241,7 @@ struct rt_handle {
     int W = 4;                 // waves per sweep block the plan was made for
     int NB = 1;                // wave-batches per wave (per block: W * NB)
     int n_blocks = 0;
+    int nblk_max = 0, nblk_max_tail = 0;  // most blocks of one slab, per plan
     long long n_pairs = 0, n_partial = 0;
     long long n_partial_main = 0;  // partial sums of the main plan's blocks
     // the tail plan over the same coefficient tiles (none when it would equal
@@ -344,6 +348,9 @@ inline const BlockDesc *plan_blk(const rt_handle *h) {
     return h->plan_tail ? h->d_blk_tail : h->d_blk;
 }
 inline int plan_blocks(const rt_handle *h) { return h->plan_tail ? h->n_blocks_tail : h->n_blocks; }
+inline int plan_nblk_max(const rt_handle *h) {
+    return h->plan_tail ? h->nblk_max_tail : h->nblk_max;
+}
 
 // sigma_out = A (scale .* sigma_in) for the slabs whose mask is set (all if
 // mask is NULL): the sweep, then the finalize pass.  mode as in SweepArgs.

@@ -232,37 +232,12 @@ int chunk_len(int ns, int C, int L) {
 // --------------------------------------------------------------------------
 // One workgroup per (256 depth points, slab): the slab's descriptor is a
 // uniform load, so the partial sums are one memory round trip from the start.
-__global__ void finalize_kernel(SweepArgs a) {
-    const int atm = blockIdx.y;
-    if (a.mask && a.mask[atm] == 0) return;
-    const AtmDesc at = a.atm[atm];
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= at.ns) return;
+// sigma_out at point k of slab atm from its quadrature sums over the
+// sweep's blocks (J0, J2): the source part of the quadrature and the
+// scattering step (operator), or the right-hand side.
+__device__ inline void finalize_point(const SweepArgs &a, int atm, const AtmDesc &at, int k,
+                                      double J0, double J2) {
     const int kk = at.doff + k;
-    const long long stride = 2LL * at.ns;
-    double J0 = 0.0, J2 = 0.0;
-    auto add_slots = [&](const auto *pJ) {
-        using V2 = typename std::conditional<sizeof(*pJ) == 4, float2, double2>::type;
-        for (int j0 = 0; j0 < at.nblk; j0 += 8) {
-            V2 v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int j = min(j0 + u, at.nblk - 1);
-                v[u] = *reinterpret_cast<const V2 *>(pJ + j * stride);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (j0 + u < at.nblk) {
-                    J0 += (double)v[u].x;
-                    J2 += (double)v[u].y;
-                }
-            }
-        }
-    };
-    if (a.part_f32)
-        add_slots(reinterpret_cast<const float *>(a.partial) + at.part_off + 2 * k);
-    else
-        add_slots(a.partial + at.part_off + 2 * k);
     const long long e = 2LL * kk;
     double o0, o2;
     if (a.mode == 0) {
@@ -285,6 +260,82 @@ __global__ void finalize_kernel(SweepArgs a) {
     a.sig_out[e + 1] = o2;
 }
 
+// Adds the sums of blocks j0, j0 + step, ... (< nblk) at one point, eight
+// loads in flight; pJ points at the point's (J0, J2) in block 0's row.
+template <typename P>
+__device__ inline void add_block_sums(const P *pJ, long long stride, int j0, int step, int nblk,
+                                      double &J0, double &J2) {
+    using V2 = typename std::conditional<sizeof(P) == 4, float2, double2>::type;
+    for (int j = j0; j < nblk; j += 8 * step) {
+        V2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int ju = min(j + u * step, nblk - 1);
+            v[u] = *reinterpret_cast<const V2 *>(pJ + ju * stride);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (j + u * step < nblk) {
+                J0 += (double)v[u].x;
+                J2 += (double)v[u].y;
+            }
+        }
+    }
+}
+
+__global__ void finalize_kernel(SweepArgs a) {
+    const int atm = blockIdx.y;
+    if (a.mask && a.mask[atm] == 0) return;
+    const AtmDesc at = a.atm[atm];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= at.ns) return;
+    const long long stride = 2LL * at.ns;
+    double J0 = 0.0, J2 = 0.0;
+    if (a.part_f32)
+        add_block_sums(reinterpret_cast<const float *>(a.partial) + at.part_off + 2 * k, stride, 0,
+                       1, at.nblk, J0, J2);
+    else
+        add_block_sums(a.partial + at.part_off + 2 * k, stride, 0, 1, at.nblk, J0, J2);
+    finalize_point(a, atm, at, k, J0, J2);
+}
+
+// The same pass for slabs of many blocks (a single deep slab's plan has
+// hundreds): G lanes share a point, lane r adds blocks r, r + G, ..., and a
+// fixed tree in LDS combines the G partial sums, so every call adds in the
+// same order.  kFinNT / G consecutive points per workgroup.
+constexpr int kFinNT = 1024;
+
+__global__ __launch_bounds__(kFinNT) void finalize_split_kernel(SweepArgs a, int G) {
+    __shared__ double2 red[kFinNT];
+    const int atm = blockIdx.y;
+    if (a.mask && a.mask[atm] == 0) return;
+    const AtmDesc at = a.atm[atm];
+    const int P = kFinNT / G;
+    if (blockIdx.x * P >= at.ns) return;  // the whole workgroup
+    const int sub = threadIdx.x / P, kl = threadIdx.x % P;
+    const int k = blockIdx.x * P + kl;
+    const long long stride = 2LL * at.ns;
+    double J0 = 0.0, J2 = 0.0;
+    if (k < at.ns) {
+        if (a.part_f32)
+            add_block_sums(reinterpret_cast<const float *>(a.partial) + at.part_off + 2 * k, stride,
+                           sub, G, at.nblk, J0, J2);
+        else
+            add_block_sums(a.partial + at.part_off + 2 * k, stride, sub, G, at.nblk, J0, J2);
+    }
+    red[threadIdx.x] = make_double2(J0, J2);
+    __syncthreads();
+    for (int h = G / 2; h >= 1; h >>= 1) {
+        if (sub < h) {
+            const double2 o = red[threadIdx.x + h * P];
+            red[threadIdx.x].x += o.x;
+            red[threadIdx.x].y += o.y;
+        }
+        __syncthreads();
+    }
+    if (sub == 0 && k < at.ns) finalize_point(a, atm, at, k, red[kl].x, red[kl].y);
+}
+
 // --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
@@ -304,9 +355,24 @@ void sweep_config(const rt_handle *h, bool fp32, int *W, bool *pf) {
     *pf = (h->opt.prefetch >= 2) && h->L <= 8;
 }
 
-hipError_t launch_finalize(const SweepArgs &a, int n_atm, int ns_max, hipStream_t s) {
+int finalize_lanes(int nblk_max) {
+    if (nblk_max <= 32) return 1;  // at most four rounds of loads per point
+    int g = 2;
+    while (g < 64 && 8 * g < nblk_max) g *= 2;
+    return g;
+}
+
+hipError_t launch_finalize(const SweepArgs &a, int n_atm, int ns_max, int nblk_max,
+                           hipStream_t s) {
     if (n_atm <= 0 || ns_max <= 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_kernel, dim3((ns_max + 255) / 256, n_atm), dim3(256), 0, s, a);
+    const int G = finalize_lanes(nblk_max);
+    if (G == 1) {
+        hipLaunchKernelGGL(finalize_kernel, dim3((ns_max + 255) / 256, n_atm), dim3(256), 0, s, a);
+    } else {
+        const int P = kFinNT / G;
+        hipLaunchKernelGGL(finalize_split_kernel, dim3((ns_max + P - 1) / P, n_atm), dim3(kFinNT), 0,
+                           s, a, G);
+    }
     return hipGetLastError();
 }
 

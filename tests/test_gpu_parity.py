@@ -143,6 +143,35 @@ def test_apply_full_batch_sampled_slabs():
         assert np.abs(y[sl[i]] - ref).max() / scale <= MATVEC_TOL, i
 
 
+@pytest.mark.parametrize("chunk", [8, 16])
+def test_finalize_many_blocks_per_slab(chunk):
+    """A plan of one wave-batch per wave gives each slab of an 8-slab batch
+    (73 to 387 points) tens to hundreds of sweep blocks, whose sums the
+    finalize pass adds with several lanes per point; the plan of 32
+    wave-batches per wave gives 8 blocks per slab, one lane per point.  Both
+    against the oracle (operator, FP32 operator, right-hand side), and the
+    two FP64 results against each other."""
+    p = W.config4(8)
+    v = W.random_vector(p.n_unknowns, 5)
+    out = {}
+    for wb in (1, 32):
+        with B.setup(p, chunk=chunk, wave_batches=wb, precision=B.RT_PREC_MIXED) as h:
+            blocks = h.plan_info()["blocks"]
+            if wb == 1:
+                # more than 32 blocks per slab on average: some slab has more
+                assert blocks > 32 * p.n_atm, blocks
+            else:
+                assert blocks == p.n_atm * (p.n_mu // 2), blocks  # one per direction
+            y = host(h.apply_op(dev(v)))
+            assert normwise(p, v, y) <= MATVEC_TOL
+            assert normwise(p, v, host(h.apply_op_fp32(dev(v)))) < 1e-5
+            b = host(h.get_rhs())
+            ref = O.rhs(p)
+            assert np.abs(b - ref).max() / np.abs(ref).max() <= MATVEC_TOL
+            out[wb] = y
+    assert np.abs(out[1] - out[32]).max() / np.abs(v).max() <= 1e-13
+
+
 def test_apply_config3_full():
     p = W.config3()
     with B.setup(p) as h:
