@@ -6,9 +6,12 @@
 // its own system with its own basis rows, Hessenberg matrix, Givens
 // rotations and test ||b - K I|| / ||b|| < rtol, all kept on the device; the
 // slabs advance in lock step and a converged slab stops updating.  Classical
-// Gram-Schmidt applied twice, with segmented reductions: each workgroup sums
-// a chunk of one slab's segment for all basis rows at once, and a second
-// pass adds the chunks in a fixed order (deterministic).  No preconditioner:
+// Gram-Schmidt applied twice with the second pass delayed by one step, so
+// that one reduction per step serves both passes (DCGS2: Swirydowicz,
+// Langou, Ananthan, Yang and Thomas, 2020), with segmented reductions: each
+// workgroup sums a chunk of one slab's segment for all basis rows at once,
+// and a second pass adds the chunks in a fixed order (deterministic).  No
+// preconditioner:
 // the field system is the one Sect. 3.2 calls more favourable to Krylov
 // methods.  The redistribution variant uses the same solver with its own
 // operator and a Jacobi scaling.
@@ -82,10 +85,13 @@ struct FsArgs {
     const long long *off;  // [n_atm + 1] first entry of each slab's segment
     int n_atm, nchunk, m;
     long long N;           // field length (row stride of V)
+    int hs;                // entries per (slab, chunk) of part and per slab of h
     double *V;             // (m + 1) x N basis
-    double *part;          // [n_atm][nchunk][m + 1] partial sums
-    double *h;             // [n_atm][m + 1] current column / coefficients
-    double *H;             // [n_atm][m + 1][m]
+    double *part;          // [n_atm][nchunk][hs] partial sums
+    double *h;             // [n_atm][hs] sums / coefficients
+    double *H;             // [n_atm][m + 1][m] Hessenberg columns, rotated (the triangle)
+    double *Hu;            // [n_atm][m + 1][m] the same columns before the rotations
+    double *hc;            // [2][n_atm][m + 1] a step's column before its second pass
     double *cs, *sn, *g;   // [n_atm][m], [n_atm][m], [n_atm][m + 1]
     double *bnorm, *beta, *resid;  // [n_atm]
     int *active, *done;    // [n_atm]: still iterating; current cycle finished
@@ -123,7 +129,7 @@ __global__ __launch_bounds__(kFsNT) void fs_dots_kernel(FsArgs a, const double *
             acc = fma(xv[u], V ? (e < hi ? Vi[e] : 0.0) : xv[u], acc);
         }
         for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) a.part[((long long)s * a.nchunk + c) * (a.m + 1) + i] = acc;
+        if (lane == 0) a.part[((long long)s * a.nchunk + c) * a.hs + i] = acc;
     }
 }
 
@@ -134,182 +140,234 @@ __global__ __launch_bounds__(1024) void fs_reduce_kernel(FsArgs a, int nv, int m
     const int s = blockIdx.x;
     if (!(mode ? a.active[s] : working(a, s))) return;
     const int lane = threadIdx.x % kWave;
-    const double *ps = a.part + (long long)s * a.nchunk * (a.m + 1);
+    const double *ps = a.part + (long long)s * a.nchunk * a.hs;
     for (int i = threadIdx.x / kWave; i < nv; i += blockDim.x / kWave) {
         double t = 0.0;
-        for (int c = lane; c < a.nchunk; c += kWave) t += ps[(long long)c * (a.m + 1) + i];
+        for (int c = lane; c < a.nchunk; c += kWave) t += ps[(long long)c * a.hs + i];
         for (int o = kWave / 2; o > 0; o >>= 1) t += __shfl_xor(t, o);
-        if (lane == 0) a.h[(long long)s * (a.m + 1) + i] = t;
+        if (lane == 0) a.h[(long long)s * a.hs + i] = t;
     }
 }
 
 // ---------------------------------------------------------------------------
-// The Arnoldi step fused into three launches after the first pass's partial
-// dot products (fs_dots_kernel into part): every workgroup of a slab first
-// adds the partial sums of all chunks itself -- in the order fs_reduce_kernel
-// uses, so every workgroup gets the same coefficients, bit for bit -- and then
-// works on its chunk.
-// (With many chunks that redundant sum costs more than a launch: from
-// kFsFuseMaxChunks chunks on, fs_reduce_kernel adds them once into h first
-// and fs_proj_kernel reads h; the sums are the same, bit for bit.)
-//   fs_proj_kernel:   h = sum_c part, w -= sum_i h_i V_i on the chunk, H column
-//                     (set or add), then the partial dot products of the new w
-//                     with V_i (nv rows) or with itself (nv = 0) into `out`;
-//   fs_close_kernel:  hn^2 = sum_c part (the norm), Givens (workgroup 0) and
-//                     v_{j+1} = w / hn on the chunk.
-// The dot products are taken from a copy of the chunk in LDS in the layout of
-// fs_dots_kernel, so they add in the same order as that kernel's.
+// One Arnoldi step in two launches after the operator.  Step j holds the
+// finished rows q_0..q_{j-1} and u = V_j, the candidate projected once
+// against them (q_0 = r / beta is finished at the start of a cycle), and w =
+// A u.  One reduction gives, for i < j, s_i = q_i.u (the candidate's second
+// pass, delayed) and z_i = q_i.w, and nu = u.u, zeta = u.w; then
+//   rho = sqrt(nu - |s|^2),  q_j = (u - sum s_i q_i) / rho,
+//   c_i = z_i / rho (i < j),  c_j = (zeta - s.z) / rho^2,
+//   u_{j+1} = w / rho - sum_{i <= j} c_i q_i     (the first pass of A q_j),
+// column j-1 of the Hessenberg matrix is finished (its first-pass
+// coefficients plus s, subdiagonal rho) and rotated, and column j's first
+// pass is c - (H s) / rho, H with the finished column j-1 (A q_j = (w -
+// A Q s) / rho and A Q = Q H).  The convergence test of column j-1 thus comes
+// one step late; the last column of a cycle is finished by a reduction
+// without an operator application.
+//   fs_dd_dots_kernel:   the partial dot products on each chunk;
+//   fs_dd_update_kernel: every workgroup of a slab adds all chunks' partial
+//                        sums itself (the order fs_reduce_kernel uses: the
+//                        same coefficients, bit for bit, in every workgroup),
+//                        then updates q_j and u_{j+1} on its chunk; the first
+//                        workgroup finishes column j-1 and runs the Givens
+//                        step.  (From kFsFuseMaxChunks chunks on,
+//                        fs_reduce_kernel adds them once into h first.)
 // ---------------------------------------------------------------------------
 
 // the Givens part of step j for slab s (below)
-__device__ void givens_step(const FsArgs &a, int s, int j);
+__device__ void givens_step(const FsArgs &a, int s, int j, const double *col,
+                            const double *rcs, const double *rsn);
 
-// sum over the chunks of one slab's partial sums of row i (fs_reduce_kernel's
+// sum over the chunks of one slab's partial sums of entry i (fs_reduce_kernel's
 // order), by one wavefront
 __device__ inline double chunk_sum(const FsArgs &a, const double *ps, int i, int lane) {
     double t = 0.0;
-    for (int c = lane; c < a.nchunk; c += kWave) t += ps[(long long)c * (a.m + 1) + i];
+    for (int c = lane; c < a.nchunk; c += kWave) t += ps[(long long)c * a.hs + i];
     for (int o = kWave / 2; o > 0; o >>= 1) t += __shfl_xor(t, o);
     return t;
 }
 
-// the partial dot products of the chunk held in LDS (xs) with rows V_i,
-// i < nv (or of the chunk with itself, nv = 0), as fs_dots_kernel computes them
-__device__ inline void chunk_dots(const FsArgs &a, const double *xs, int nv, long long lo,
-                                  long long hi, double *out) {
-    const int lane = threadIdx.x % kWave;
-    double xv[kFsPerLane];
-#pragma unroll
-    for (int u = 0; u < kFsPerLane; ++u) xv[u] = xs[lane + u * kWave];
-    const int rows = nv > 0 ? nv : 1;
-    for (int i = threadIdx.x / kWave; i < rows; i += kFsNT / kWave) {
-        const double *Vi = a.V + (long long)i * a.N;
-        double acc = 0.0;
-#pragma unroll
-        for (int u = 0; u < kFsPerLane; ++u) {
-            const long long e = lo + lane + (long long)u * kWave;
-            acc = fma(xv[u], nv > 0 ? (e < hi ? Vi[e] : 0.0) : xv[u], acc);
-        }
-        for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) out[i] = acc;
-    }
-}
-
-__global__ __launch_bounds__(kFsNT) void fs_proj_kernel(FsArgs a, double *w, int nv, int j,
-                                                         int first, const double *in,
-                                                         double *out, int next_nv) {
-    __shared__ double hs[RT_MAX_RESTART + 1];
-    __shared__ double xs[kFsChunk];
+// part[2i] = V_i.u, part[2i+1] = V_i.w (i < j); part[2j] = u.u, part[2j+1] =
+// u.w, with u = V_j; w = NULL (the end of a cycle): the u products only.
+__global__ __launch_bounds__(kFsNT) void fs_dd_dots_kernel(FsArgs a, const double *w, int j) {
     const int s = blockIdx.y, c = blockIdx.x;
     if (!working(a, s)) return;
+    const long long lo = a.off[s] + (long long)c * kFsChunk;
+    const long long hi = std::min(a.off[s + 1], lo + kFsChunk);
     const int lane = threadIdx.x % kWave;
-    if (in) {
-        const double *ps = in + (long long)s * a.nchunk * (a.m + 1);
-        for (int i = threadIdx.x / kWave; i < nv; i += kFsNT / kWave) {
-            const double t = chunk_sum(a, ps, i, lane);
-            if (lane == 0) hs[i] = t;
+    const double *u = a.V + (long long)j * a.N;
+    double uv[kFsPerLane], wv[kFsPerLane];
+#pragma unroll
+    for (int k = 0; k < kFsPerLane; ++k) {
+        const long long e = lo + lane + (long long)k * kWave;
+        uv[k] = e < hi ? u[e] : 0.0;
+        wv[k] = (w && e < hi) ? w[e] : 0.0;
+    }
+    double *out = a.part + ((long long)s * a.nchunk + c) * a.hs;
+    for (int i = threadIdx.x / kWave; i <= j; i += kFsNT / kWave) {
+        const double *Vi = a.V + (long long)i * a.N;  // i == j: u itself
+        double as = 0.0, az = 0.0;
+#pragma unroll
+        for (int k = 0; k < kFsPerLane; ++k) {
+            const long long e = lo + lane + (long long)k * kWave;
+            const double vi = e < hi ? Vi[e] : 0.0;
+            as = fma(vi, uv[k], as);
+            az = fma(vi, wv[k], az);
         }
-    } else {  // already added by fs_reduce_kernel (the same order)
-        for (int i = threadIdx.x; i < nv; i += kFsNT) hs[i] = a.h[(long long)s * (a.m + 1) + i];
-    }
-    __syncthreads();
-    const long long lo = a.off[s] + (long long)c * kFsChunk;
-    const long long hi = std::min(a.off[s + 1], lo + kFsChunk);
-    double v[kFsPerThread];
-#pragma unroll
-    for (int u = 0; u < kFsPerThread; ++u) {
-        const long long e = lo + threadIdx.x + (long long)u * kFsNT;
-        v[u] = e < hi ? w[e] : 0.0;
-    }
-#pragma unroll 4
-    for (int i = 0; i < nv; ++i) {
-        const double cf = -hs[i];
-        const double *Vi = a.V + (long long)i * a.N;
-#pragma unroll
-        for (int u = 0; u < kFsPerThread; ++u) {
-            const long long e = lo + threadIdx.x + (long long)u * kFsNT;
-            if (e < hi) v[u] = fma(cf, Vi[e], v[u]);
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            as += __shfl_xor(as, o);
+            az += __shfl_xor(az, o);
+        }
+        if (lane == 0) {
+            out[2 * i] = as;
+            out[2 * i + 1] = az;
         }
     }
-#pragma unroll
-    for (int u = 0; u < kFsPerThread; ++u) {
-        const long long e = lo + threadIdx.x + (long long)u * kFsNT;
-        if (e < hi) w[e] = v[u];
-        xs[threadIdx.x + u * kFsNT] = v[u];
-    }
-    if (c == 0 && threadIdx.x < nv) {
-        double *Hc = a.H + (long long)s * (a.m + 1) * a.m + (long long)threadIdx.x * a.m + j;
-        *Hc = first ? hs[threadIdx.x] : *Hc + hs[threadIdx.x];
-    }
-    __syncthreads();
-    chunk_dots(a, xs, next_nv, lo, hi, out + ((long long)s * a.nchunk + c) * (a.m + 1));
 }
 
-__global__ __launch_bounds__(kFsNT) void fs_close_kernel(FsArgs a, const double *w, int j,
-                                                          const double *in) {
-    __shared__ double shn;
+// summed: the sums are in h (fs_reduce_kernel); flush: the end of a cycle
+// (j = m): finish column m-1 only.
+__global__ __launch_bounds__(kFsNT) void fs_dd_update_kernel(FsArgs a, const double *w, int j,
+                                                              int flush, int summed) {
+    __shared__ double sv[2 * (RT_MAX_RESTART + 1)];  // s_i, z_i interleaved; nu, zeta
+    __shared__ double cf[RT_MAX_RESTART + 1];        // c
+    __shared__ double col[RT_MAX_RESTART + 1];       // the finished column j-1
+    __shared__ double rcs[RT_MAX_RESTART], rsn[RT_MAX_RESTART];  // earlier rotations
+    __shared__ double srho, ssz;
     const int s = blockIdx.y, c = blockIdx.x;
-    if (!a.active[s]) return;
-    if (a.done[s] && a.jj[s] != j + 1) return;  // finished before this step
-    if (threadIdx.x < kWave) {
-        const double t = chunk_sum(a, in + (long long)s * a.nchunk * (a.m + 1), 0, threadIdx.x);
-        if (threadIdx.x == 0) shn = t;
+    if (!working(a, s)) return;
+    const int m = a.m, lane = threadIdx.x % kWave, nval = 2 * j + 2;
+    if (summed) {
+        for (int i = threadIdx.x; i < nval; i += kFsNT) sv[i] = a.h[(long long)s * a.hs + i];
+    } else {
+        const double *ps = a.part + (long long)s * a.nchunk * a.hs;
+        for (int i = threadIdx.x / kWave; i < nval; i += kFsNT / kWave) {
+            const double t = chunk_sum(a, ps, i, lane);
+            if (lane == 0) sv[i] = t;
+        }
     }
     __syncthreads();
-    const double hn = sqrt(shn);
-    if (c == 0 && threadIdx.x == 0) {
-        // the rotations of fs_givens_kernel, with h_{j+1,j} = hn
-        a.h[(long long)s * (a.m + 1)] = shn;
-        givens_step(a, s, j);
+    if (threadIdx.x < kWave) {  // |s|^2 and s.z by the first wavefront
+        double ss = 0.0, sz = 0.0;
+        for (int i = lane; i < j; i += kWave) {
+            ss = fma(sv[2 * i], sv[2 * i], ss);
+            sz = fma(sv[2 * i], sv[2 * i + 1], sz);
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            ss += __shfl_xor(ss, o);
+            sz += __shfl_xor(sz, o);
+        }
+        if (lane == 0) {
+            srho = j > 0 ? sqrt(fmax(sv[2 * j] - ss, 0.0)) : 1.0;  // q_0 is finished
+            ssz = sz;
+        }
     }
-    if (!(hn > 0.0)) return;
+    __syncthreads();
+    const double rho = srho;
+    if (!flush && rho > 0.0) {
+        for (int i = threadIdx.x; i < j; i += kFsNT) cf[i] = sv[2 * i + 1] / rho;
+        if (threadIdx.x == 0) cf[j] = (sv[2 * j + 1] - ssz) / (rho * rho);
+    }
+    if (j > 0 && threadIdx.x <= j) {
+        const double *hp = a.hc + ((long long)((j - 1) & 1) * a.n_atm + s) * (m + 1);
+        col[threadIdx.x] = threadIdx.x < j ? hp[threadIdx.x] + sv[2 * threadIdx.x] : rho;
+    }
+    __syncthreads();
+    if (c == 0) {
+        // the first workgroup: column j-1 kept as it is and rotated (the
+        // earlier rotations read into LDS, applied by one thread in
+        // registers), and column j before its second pass
+        const int jc = j - 1;
+        if (j > 0) {
+            for (int i = threadIdx.x; i < jc; i += kFsNT) {
+                rcs[i] = a.cs[(long long)s * m + i];
+                rsn[i] = a.sn[(long long)s * m + i];
+            }
+            if (threadIdx.x <= j)
+                a.Hu[((long long)s * (m + 1) + threadIdx.x) * m + jc] = col[threadIdx.x];
+        }
+        __syncthreads();
+        if (j > 0 && threadIdx.x == 0) givens_step(a, s, jc, col, rcs, rsn);
+        if (!flush && rho > 0.0) {
+            // row i: c_i - (H s)_i / rho, one wavefront per row
+            const double *Hs = a.Hu + (long long)s * (m + 1) * m;
+            for (int i = threadIdx.x / kWave; i <= j; i += kFsNT / kWave) {
+                double t = 0.0;
+                if (j > 0) {
+                    for (int l = (i > 0 ? i - 1 : 0) + lane; l < j - 1; l += kWave)
+                        t = fma(Hs[(long long)i * m + l], sv[2 * l], t);
+                    for (int o = kWave / 2; o > 0; o >>= 1) t += __shfl_xor(t, o);
+                    t = fma(col[i], sv[2 * (j - 1)], t);
+                }
+                if (lane == 0)
+                    a.hc[((long long)(j & 1) * a.n_atm + s) * (m + 1) + i] = cf[i] - t / rho;
+            }
+        }
+    }
+    if (flush || !(rho > 0.0)) return;
     const long long lo = a.off[s] + (long long)c * kFsChunk;
     const long long hi = std::min(a.off[s + 1], lo + kFsChunk);
-    for (long long e = lo + threadIdx.x; e < hi; e += kFsNT)
-        a.V[(long long)(j + 1) * a.N + e] = w[e] / hn;
+    double *Vj = a.V + (long long)j * a.N, *Vn = a.V + (long long)(j + 1) * a.N;
+#pragma unroll
+    for (int k = 0; k < kFsPerThread; ++k) {
+        const long long e = lo + threadIdx.x + (long long)k * kFsNT;
+        if (e >= hi) continue;
+        double q = Vj[e], nw = w[e] / rho;
+#pragma unroll 4
+        for (int i = 0; i < j; ++i) {
+            const double vi = a.V[(long long)i * a.N + e];
+            q = fma(-sv[2 * i], vi, q);
+            nw = fma(-cf[i], vi, nw);
+        }
+        if (j > 0) {
+            q /= rho;
+            Vj[e] = q;
+        }
+        Vn[e] = fma(-cf[j], q, nw);
+    }
 }
 
-// Step j's last part for slab s: h_{j+1,j} = ||w|| (its square in h[s][0]),
-// previous rotations on column j, the new rotation, g, the residual
-// estimate; v_{j+1} = w / h_{j+1,j} is left to the caller.
-__device__ void givens_step(const FsArgs &a, int s, int j) {
+// Column j's last part for slab s (one thread): col[0..j+1] is the column as
+// computed, (rcs, rsn)[0..j-1] the earlier rotations.  They are applied, the
+// new rotation is formed, the rotated column goes to H and g, the residual
+// estimate and the convergence test are updated.
+__device__ void givens_step(const FsArgs &a, int s, int j, const double *col, const double *rcs,
+                            const double *rsn) {
     const int m = a.m;
     double *H = a.H + (long long)s * (m + 1) * m;
-    double *cs = a.cs + (long long)s * m, *sn = a.sn + (long long)s * m;
     double *g = a.g + (long long)s * (m + 1);
-    const double hn = sqrt(a.h[(long long)s * (m + 1)]);
-    H[(long long)(j + 1) * m + j] = hn;
+    double x = col[0];
     for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * H[(long long)i * m + j] + sn[i] * H[(long long)(i + 1) * m + j];
-        H[(long long)(i + 1) * m + j] = -sn[i] * H[(long long)i * m + j] + cs[i] * H[(long long)(i + 1) * m + j];
-        H[(long long)i * m + j] = t;
+        const double y = col[i + 1];
+        H[(long long)i * m + j] = rcs[i] * x + rsn[i] * y;
+        x = -rsn[i] * x + rcs[i] * y;
     }
-    const double hjj = H[(long long)j * m + j];
-    const double den = sqrt(hjj * hjj + hn * hn);
-    cs[j] = den > 0.0 ? hjj / den : 1.0;
-    sn[j] = den > 0.0 ? hn / den : 0.0;
+    const double hn = col[j + 1];
+    const double den = sqrt(x * x + hn * hn);
+    const double cj = den > 0.0 ? x / den : 1.0, sj = den > 0.0 ? hn / den : 0.0;
+    a.cs[(long long)s * m + j] = cj;
+    a.sn[(long long)s * m + j] = sj;
     H[(long long)j * m + j] = den;
     H[(long long)(j + 1) * m + j] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
+    const double gj = g[j];
+    g[j + 1] = -sj * gj;
+    g[j] = cj * gj;
     a.resid[s] = fabs(g[j + 1]);
     a.jj[s] = j + 1;
     a.iters[s] += 1;
-    a.h[(long long)s * (m + 1) + 1] = hn;  // for the normalization
     if (a.resid[s] < a.tol * a.bnorm[s] || hn == 0.0 || j + 1 == m || a.iters[s] >= a.maxit)
         a.done[s] = 1;
 }
 
-__global__ __launch_bounds__(kFsNT) void fs_scale_kernel(FsArgs a, const double *w, int j) {
+// v_0 = r / beta (beta in h[s][1]) at the start of a cycle.
+__global__ __launch_bounds__(kFsNT) void fs_scale_kernel(FsArgs a) {
     const int s = blockIdx.y;
     if (!a.active[s]) return;
-    if (a.done[s] && a.jj[s] != j + 1) return;  // finished before this step
-    const double hn = a.h[(long long)s * (a.m + 1) + 1];
-    if (!(hn > 0.0)) return;
+    const double beta = a.h[(long long)s * a.hs + 1];
+    if (!(beta > 0.0)) return;
     const long long lo = a.off[s] + (long long)blockIdx.x * kFsChunk;
     const long long hi = std::min(a.off[s + 1], lo + kFsChunk);
-    for (long long e = lo + threadIdx.x; e < hi; e += kFsNT)
-        a.V[(long long)(j + 1) * a.N + e] = w[e] / hn;
+    for (long long e = lo + threadIdx.x; e < hi; e += kFsNT) a.V[e] = a.V[e] / beta;
 }
 
 // End of a cycle, one wavefront per active slab (restart below 64): y = H^-1 g
@@ -332,7 +390,7 @@ __global__ __launch_bounds__(kWave) void fs_backsolve_wave_kernel(FsArgs a) {
         if (r == i) yr = yi;
         if (r < i) t = fma(-Hs[r * n + i], yi, t);
     }
-    if (r <= m) a.h[(long long)s * (m + 1) + r] = r < n ? yr : 0.0;
+    if (r <= m) a.h[(long long)s * a.hs + r] = r < n ? yr : 0.0;
 }
 
 // The same for any restart, one thread per active slab, from global memory.
@@ -342,7 +400,7 @@ __global__ void fs_backsolve_kernel(FsArgs a) {
     const int m = a.m, n = a.jj[s];
     const double *H = a.H + (long long)s * (m + 1) * m;
     const double *g = a.g + (long long)s * (m + 1);
-    double *y = a.h + (long long)s * (m + 1);
+    double *y = a.h + (long long)s * a.hs;
     for (int i = n - 1; i >= 0; --i) {
         double t = g[i];
         for (int l = i + 1; l < n; ++l) t -= H[(long long)i * m + l] * y[l];
@@ -355,7 +413,7 @@ __global__ void fs_backsolve_kernel(FsArgs a) {
 __global__ __launch_bounds__(kFsNT) void fs_update_kernel(FsArgs a, double *x) {
     const int s = blockIdx.y;
     if (!a.active[s]) return;
-    const double *y = a.h + (long long)s * (a.m + 1);
+    const double *y = a.h + (long long)s * a.hs;
     const int n = a.jj[s];
     const long long lo = a.off[s] + (long long)blockIdx.x * kFsChunk;
     const long long hi = std::min(a.off[s + 1], lo + kFsChunk);
@@ -397,7 +455,7 @@ __global__ __launch_bounds__(kFsNT) void fs_residual_kernel(FsArgs a, const doub
 __global__ void fs_restart_kernel(FsArgs a, int first, int maxit) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= a.n_atm || !a.active[s]) return;
-    const double beta = sqrt(a.h[(long long)s * (a.m + 1)]);
+    const double beta = sqrt(a.h[(long long)s * a.hs]);
     if (first) {
         a.bnorm[s] = sqrt(a.resid[s]);
         a.iters[s] = 0;
@@ -412,7 +470,7 @@ __global__ void fs_restart_kernel(FsArgs a, int first, int maxit) {
     double *g = a.g + (long long)s * (a.m + 1);
     g[0] = beta;
     for (int i = 1; i <= a.m; ++i) g[i] = 0.0;
-    a.h[(long long)s * (a.m + 1) + 1] = beta;  // v_0 = r / beta
+    a.h[(long long)s * a.hs + 1] = beta;  // v_0 = r / beta
 }
 
 __global__ void fs_init_kernel(FsArgs a) {
@@ -427,7 +485,7 @@ __global__ void fs_init_kernel(FsArgs a) {
 __global__ void fs_keep_bnorm_kernel(FsArgs a) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= a.n_atm) return;
-    a.resid[s] = a.h[(long long)s * (a.m + 1)];
+    a.resid[s] = a.h[(long long)s * a.hs];
 }
 
 // out = d .* in (mode 0), in ./ d (1) or out + in (2) over the whole vector
@@ -482,16 +540,18 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
     a.N = N;
     a.tol = rtol;
     a.maxit = maxit;
-    double *w, *bown = nullptr, *part2;
+    a.hs = 2 * (m + 1);
+    double *w, *bown = nullptr;
     Carve cv(h, 0);
     cv.want((long long **)&a.off, n_atm + 1);
     cv.want(&a.V, (size_t)(m + 1) * N);
     cv.want(&w, N);
     if (!b) cv.want(&bown, N);
-    cv.want(&a.part, (size_t)n_atm * nchunk * (m + 1));
-    cv.want(&part2, (size_t)n_atm * nchunk * (m + 1));
-    cv.want(&a.h, (size_t)n_atm * (m + 1));
+    cv.want(&a.part, (size_t)n_atm * nchunk * a.hs);
+    cv.want(&a.h, (size_t)n_atm * a.hs);
     cv.want(&a.H, (size_t)n_atm * (m + 1) * m);
+    cv.want(&a.Hu, (size_t)n_atm * (m + 1) * m);
+    cv.want(&a.hc, (size_t)2 * n_atm * (m + 1));
     cv.want(&a.cs, (size_t)n_atm * m);
     cv.want(&a.sn, (size_t)n_atm * m);
     cv.want(&a.g, (size_t)n_atm * (m + 1));
@@ -548,34 +608,24 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
         first = false;
         if (!any_active(a.active)) break;
         // v_0 = r / beta (h[s][1] holds beta)
-        hipLaunchKernelGGL(fs_scale_kernel, seg, blk, 0, st, a, (const double *)a.V, -1);
-        for (int j = 0; j < m && err == hipSuccess; ++j) {
-            const double *vj = a.V + (long long)j * N;
-            ok(apply(vj, w));
-            ++napply;
-            // classical Gram-Schmidt twice: first-pass dots; first projection
-            // fused with the second-pass dots; second projection fused with
-            // the norm's partial sums; Givens and the new basis vector
-            hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)w, j + 1,
-                               (const double *)a.V, 0);
-            if (nchunk <= kFsFuseMaxChunks) {
-                hipLaunchKernelGGL(fs_proj_kernel, seg, blk, 0, st, a, w, j + 1, j, 1,
-                                   (const double *)a.part, part2, j + 1);
-                hipLaunchKernelGGL(fs_proj_kernel, seg, blk, 0, st, a, w, j + 1, j, 0,
-                                   (const double *)part2, a.part, 0);
-            } else {
-                FsArgs a2 = a;
-                a2.part = part2;
-                hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, j + 1, 0);
-                hipLaunchKernelGGL(fs_proj_kernel, seg, blk, 0, st, a, w, j + 1, j, 1,
-                                   (const double *)nullptr, part2, j + 1);
-                hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a2, j + 1, 0);
-                hipLaunchKernelGGL(fs_proj_kernel, seg, blk, 0, st, a, w, j + 1, j, 0,
-                                   (const double *)nullptr, a.part, 0);
-            }
-            hipLaunchKernelGGL(fs_close_kernel, seg, blk, 0, st, a, (const double *)w, j,
-                               (const double *)a.part);
+        hipLaunchKernelGGL(fs_scale_kernel, seg, blk, 0, st, a);
+        // one reduction and one update per step (fs_dd_*), with the sums
+        // added once apart from many chunks on
+        const bool apart = nchunk > kFsFuseMaxChunks;
+        auto reduce_update = [&](const double *wv, int j, int flush) {
+            hipLaunchKernelGGL(fs_dd_dots_kernel, seg, blk, 0, st, a, wv, j);
+            if (apart)
+                hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, 2 * j + 2,
+                                   0);
+            hipLaunchKernelGGL(fs_dd_update_kernel, seg, blk, 0, st, a, wv, j, flush,
+                               apart ? 1 : 0);
             ok(hipGetLastError());
+        };
+        bool ended = false;  // every slab's cycle ended before step m
+        for (int j = 0; j < m && err == hipSuccess; ++j) {
+            ok(apply(a.V + (long long)j * N, w));
+            ++napply;
+            reduce_update(w, j, 0);
             if ((j + 1) % 8 == 0 && j + 1 < m) {
                 // stop the cycle early once every slab's cycle has ended
                 std::vector<int> d(n_atm), ac(n_atm);
@@ -585,9 +635,14 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
                 bool all = true;
                 for (int s = 0; s < n_atm; ++s)
                     if (ac[s] && !d[s]) all = false;
-                if (all) break;
+                if (all) {
+                    ended = true;
+                    break;
+                }
             }
         }
+        // the last column of the cycle, for the slabs still in it
+        if (!ended) reduce_update(nullptr, m, 1);
         if (m <= kBacksolveMaxM)
             hipLaunchKernelGGL(fs_backsolve_wave_kernel, dim3(n_atm), dim3(kWave),
                                sizeof(double) * m * m, st, a);
@@ -603,7 +658,7 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
     hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)a.V, 1,
                        (const double *)nullptr, 1);
     hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, 1, 1);
-    std::vector<double> hh((size_t)n_atm * (m + 1)), bn(n_atm);
+    std::vector<double> hh((size_t)n_atm * a.hs), bn(n_atm);
     std::vector<int> its(n_atm);
     ok(hipMemcpyAsync(hh.data(), a.h, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, st));
     ok(hipMemcpyAsync(bn.data(), a.bnorm, sizeof(double) * n_atm, hipMemcpyDeviceToHost, st));
@@ -613,7 +668,7 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
     if (err != hipSuccess) return fail(RT_EDEVICE, std::string("GMRES: ") + hipGetErrorString(err));
     int worst = RT_OK;
     for (int s = 0; s < n_atm; ++s) {
-        const double rel = bn[s] > 0.0 ? std::sqrt(hh[(size_t)s * (m + 1)]) / bn[s] : 0.0;
+        const double rel = bn[s] > 0.0 ? std::sqrt(hh[(size_t)s * a.hs]) / bn[s] : 0.0;
         const int status = rel < rtol ? RT_OK : RT_ENOCONV;
         worst = std::max(worst, status);
         if (info) {
@@ -646,6 +701,7 @@ int solve_seg_refined(rt_handle *h, const SegOp &op, const SegOp &op_lo,
     a.n_atm = n_atm;
     a.nchunk = nchunk;
     a.m = 0;
+    a.hs = 1;
     a.N = N;
     double *bown = nullptr, *r, *d, *w;
     Carve cv(h, 1);
