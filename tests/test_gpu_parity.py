@@ -550,6 +550,29 @@ def test_maximum_depth_and_restart(mixed, extra):
     assert rr.max() < 1e-10, rr
 
 
+@pytest.mark.parametrize("restart", [1, 2, 5, 64])
+def test_segmented_gmres_restarts(restart):
+    """Two deep slabs (1024 and 1100 points) take the solver for a few long
+    vectors, whose Arnoldi step delays the second Gram-Schmidt pass by one
+    step and finishes each Hessenberg column one step late: every restart
+    length (down to GMRES(1), where each cycle is only the closing reduction
+    after one step) reaches the oracle's residual, with iteration counts
+    close to the oracle's own GMRES(restart), which orthogonalizes by
+    modified Gram-Schmidt (the same Krylov iterates in exact arithmetic)."""
+    ns = [1024, 1100]
+    p = W.make_slabs(ns, [(1e-2, 1e4)] * 2, 2, 3, 5.0, [1e-3] * 2, [1e-2, 3e-2], [0.5, 0.3])
+    with B.setup(p, rtol=1e-10, restart=restart, maxit=20000) as h:
+        rc, info, x = _solve(h, "gmres", p)
+    assert rc == 0 and all(i.status == "converged" for i in info), info
+    rr = oracle_relres(p, x)
+    assert rr.max() < 1e-10, rr
+    for i in range(len(ns)):
+        _, oi = O.gmres(p.slab(i), tol=1e-10, restart=restart, maxit=20000)
+        it = oi[0]["iterations"]
+        band = max(2, it // 20) if restart >= 30 else max(2, it * 3 // 10)
+        assert abs(info[i].iterations - it) <= band, (i, info[i].iterations, it)
+
+
 def test_invalid_inputs_rejected_before_device_use():
     p = W.config1()
     with pytest.raises(B.RTError) as e:
