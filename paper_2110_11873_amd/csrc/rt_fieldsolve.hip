@@ -103,33 +103,24 @@ struct FsArgs {
 
 __device__ inline bool working(const FsArgs &a, int s) { return a.active[s] && !a.done[s]; }
 
-// part[s][c][i] = sum over chunk c of slab s of x[e] * V_i[e] (i < nv), or of
-// x[e]^2 when V is NULL.  mode 1: all active slabs (restart); 0: working ones.
-// Each lane keeps its entries of x in registers and every wavefront reduces
-// whole rows (rows w, w + 4, ...) with a butterfly: no LDS, no barrier.
-__global__ __launch_bounds__(kFsNT) void fs_dots_kernel(FsArgs a, const double *x, int nv,
-                                                         const double *V, int mode) {
+// part[s][c][0] = sum over chunk c of slab s of x[e]^2, for the active slabs:
+// each wavefront adds its lanes' strided entries, then a butterfly and one
+// pass over the 16 wavefronts in LDS (a fixed order).
+__global__ __launch_bounds__(kFsNT) void fs_norm2_kernel(FsArgs a, const double *x) {
+    __shared__ double red[kFsNT / kWave];
     const int s = blockIdx.y, c = blockIdx.x;
-    if (!(mode ? a.active[s] : working(a, s))) return;
+    if (!a.active[s]) return;
     const long long lo = a.off[s] + (long long)c * kFsChunk;
     const long long hi = std::min(a.off[s + 1], lo + kFsChunk);
-    const int lane = threadIdx.x % kWave;
-    double xv[kFsPerLane];
-#pragma unroll
-    for (int u = 0; u < kFsPerLane; ++u) {
-        const long long e = lo + lane + (long long)u * kWave;
-        xv[u] = e < hi ? x[e] : 0.0;
-    }
-    for (int i = threadIdx.x / kWave; i < nv; i += kFsNT / kWave) {
-        const double *Vi = V ? V + (long long)i * a.N : x;
-        double acc = 0.0;
-#pragma unroll
-        for (int u = 0; u < kFsPerLane; ++u) {
-            const long long e = lo + lane + (long long)u * kWave;
-            acc = fma(xv[u], V ? (e < hi ? Vi[e] : 0.0) : xv[u], acc);
-        }
-        for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) a.part[((long long)s * a.nchunk + c) * a.hs + i] = acc;
+    double acc = 0.0;
+    for (long long e = lo + threadIdx.x; e < hi; e += kFsNT) acc = fma(x[e], x[e], acc);
+    for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kFsNT / kWave; ++w) t += red[w];
+        a.part[((long long)s * a.nchunk + c) * a.hs] = t;
     }
 }
 
@@ -592,7 +583,7 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
     };
     hipLaunchKernelGGL(fs_init_kernel, dim3(tg), dim3(tb), 0, st, a);
     // ||b||, then r = b - K x
-    hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, b, 1, (const double *)nullptr, 1);
+    hipLaunchKernelGGL(fs_norm2_kernel, seg, blk, 0, st, a, b);
     hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, 1, 1);
     hipLaunchKernelGGL(fs_keep_bnorm_kernel, dim3(tg), dim3(tb), 0, st, a);
     bool first = true;
@@ -601,8 +592,7 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
         ok(apply(x, w));
         ++napply;
         hipLaunchKernelGGL(fs_residual_kernel, seg, blk, 0, st, a, b, (const double *)w);
-        hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)a.V, 1,
-                           (const double *)nullptr, 1);
+        hipLaunchKernelGGL(fs_norm2_kernel, seg, blk, 0, st, a, (const double *)a.V);
         hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, 1, 1);
         hipLaunchKernelGGL(fs_restart_kernel, dim3(tg), dim3(tb), 0, st, a, first ? 1 : 0, maxit);
         first = false;
@@ -655,8 +645,7 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
     ok(op(x, nullptr, w));
     hipLaunchKernelGGL(fs_init_kernel, dim3(tg), dim3(tb), 0, st, a);
     hipLaunchKernelGGL(fs_residual_kernel, seg, blk, 0, st, a, b, (const double *)w);
-    hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, (const double *)a.V, 1,
-                       (const double *)nullptr, 1);
+    hipLaunchKernelGGL(fs_norm2_kernel, seg, blk, 0, st, a, (const double *)a.V);
     hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, 1, 1);
     std::vector<double> hh((size_t)n_atm * a.hs), bn(n_atm);
     std::vector<int> its(n_atm);
@@ -732,7 +721,7 @@ int solve_seg_refined(rt_handle *h, const SegOp &op, const SegOp &op_lo,
     const dim3 seg(nchunk, n_atm), blk(kFsNT);
     const int mgrid = (int)std::min<long long>((N + 255) / 256, 4096);
     auto norms = [&](const double *v, std::vector<double> &out) {
-        hipLaunchKernelGGL(fs_dots_kernel, seg, blk, 0, st, a, v, 1, (const double *)nullptr, 1);
+        hipLaunchKernelGGL(fs_norm2_kernel, seg, blk, 0, st, a, v);
         hipLaunchKernelGGL(fs_reduce_kernel, dim3(n_atm), dim3(1024), 0, st, a, 1, 1);
         ok(hipGetLastError());
         out.resize(n_atm);
