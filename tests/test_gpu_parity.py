@@ -408,6 +408,33 @@ def test_mixed_precision_config2():
     assert oracle_relres(p, x).max() < 1e-10
 
 
+@pytest.mark.parametrize("few_deep", [False, True])
+def test_mixed_last_inner_solve_stops_near_rtol(few_deep):
+    """With an inner tolerance far below the outer one (1e-8 against 1e-9)
+    the first inner solve brings a slab close to rtol, and the next one only
+    needs to finish the job: it stops once ||r - A d|| < 0.5 rtol ||b||
+    instead of cutting its right-hand side by another 1e-8.  Every slab then
+    ends between 1e-3 rtol and rtol (without the per-slab tolerance the last
+    step would leave the residual near 1e-8 of its start, far below 1e-3
+    rtol), checked by the oracle's own residual.  few_deep: two 1024-point
+    slabs (the segmented solver, one tolerance for all slabs); otherwise a
+    batch of 8 uneven slabs."""
+    if few_deep:
+        p = W.make_slabs([1024, 1100], [(1e-2, 1e4)] * 2, 2, 3, 5.0, [1e-3] * 2, [1e-2, 3e-2],
+                         [0.5, 0.3])
+    else:
+        p = W.config4(8)
+    rtol = 1e-9
+    with B.setup(p, rtol=rtol, precision=B.RT_PREC_MIXED, inner_rtol=1e-8, inner_maxit=2000,
+                 maxit=20000) as h:
+        rc, info, x = _solve(h, "gmres", p)
+    assert rc == 0 and all(i.status == "converged" for i in info), info
+    rr = oracle_relres(p, x)
+    assert rr.max() < rtol, rr
+    assert rr.min() > 1e-3 * rtol, rr
+    assert all(i.outer_steps >= 2 for i in info), info
+
+
 def test_fp32_operator_error_is_bounded():
     p = W.config2()
     v = W.random_vector(p.n_unknowns, 10)
