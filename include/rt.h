@@ -297,9 +297,12 @@ int rt_get_jacobi_diag(rt_handle *h, double *d, void *stream);
  * Solve A x = b with restarted GMRES (Sect. 2.1; Saad & Schultz), right-
  * preconditioned by Jacobi so the residual it minimizes and stops on is the
  * unpreconditioned one of Sect. 4.2.  Arnoldi runs on the device with
- * classical Gram-Schmidt applied twice; the Hessenberg least-squares problem
- * is solved with Givens rotations in FP64.  In MIXED precision the solve is an
- * FP64 iterative refinement around inner FP32-sweep GMRES solves.
+ * classical Gram-Schmidt applied twice (for at most 4 slabs of 1024 points or
+ * more, with the second pass delayed by one step, so that the convergence
+ * test of a step comes one operator application later); the Hessenberg
+ * least-squares problem is solved with Givens rotations in FP64.  In MIXED
+ * precision the solve is an FP64 iterative refinement around inner
+ * FP32-sweep GMRES solves.
  *  b     right-hand side (device, N); NULL means the handle's own J t + c
  *  x     in: initial guess (the paper uses [1, 0, 1, 0, ...]); out: solution
  *  info  host array of n_atm entries, or NULL

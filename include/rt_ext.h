@@ -208,7 +208,8 @@ int rt_solve_field_gmres(rt_handle *h, const double *b_field, double *I, rt_solv
  *   guess and receives the solution; info as for rt_solve_gmres.  FP64:
  *   FP64 operator throughout.  MIXED: FP64 iterative refinement, r = b - A x
  *   with the FP64 operator, an inner GMRES on the BF16x3 operator to
- *   options.inner_rtol (inner_maxit steps at most), x += d, until
+ *   options.inner_rtol or the looser 0.5 rtol ||b|| (inner_maxit steps at
+ *   most), x += d, until
  *   ||r|| < rtol ||b|| per slab; iterations counts the inner steps,
  *   outer_steps the refinement steps.  Synchronizes the stream.
  */
