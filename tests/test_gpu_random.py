@@ -1,0 +1,93 @@
+"""GPU parity on seeded random shapes: batches of 1 to 6 slabs of 2 to 1030
+depth points, 2 to 12 angles and 2 to 13 frequencies, each formal solver,
+each chunk length that fits the deepest slab, each coefficient mode, random
+optical-depth ranges, thermalization, polarizability and damping.  Each case
+checks the operator (FP64 and FP32), the right-hand side and sampled
+diagonal entries against the oracle, and FP64 and mixed-precision GMRES by
+the oracle's own residual.  The shapes come from the seeded input module
+only; nothing here computes the method.
+
+Tolerances as in test_gpu_parity: the FP64 operator, right-hand side and
+diagonal to 1e-12 (normwise on the terms), the FP32 operator below 1e-5,
+and the solves below their rtol by the oracle's residual."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_2110_11873_amd import binding as B  # noqa: E402
+from paper_2110_11873_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+N_CASES = 64
+FS = ["delo_linear", "trapezoidal", "implicit_euler", "delo_parabolic"]
+COEF = [B.RT_COEF_AUTO, B.RT_COEF_PAIRS, B.RT_COEF_STREAM_W, B.RT_COEF_RECOMPUTE,
+        B.RT_COEF_RECOMPUTE_FP32]
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _case(seed):
+    """A random problem and launch options (inputs only)."""
+    rng = np.random.default_rng(20211011 + seed)
+    n_atm = int(rng.integers(1, 7))
+    ns = [int(v) for v in rng.choice([2, 3, 5, 17, 64, 65, 127, 200, 257, 511, 600, 1030], n_atm)]
+    n_mu = int(rng.choice([2, 4, 6, 8, 12]))
+    n_nu = int(rng.choice([2, 3, 7, 13]))
+    fs = FS[seed % len(FS)]
+    ranges = [(10.0 ** rng.uniform(-5, -2), 10.0 ** rng.uniform(2, 7)) for _ in ns]
+    p = W.make_slabs(ns, ranges, n_mu, n_nu, float(rng.uniform(3.0, 8.0)),
+                     list(10.0 ** rng.uniform(-4, -2, n_atm)), list(10.0 ** rng.uniform(-3, -1, n_atm)),
+                     list(rng.uniform(0.0, 1.0, n_atm)), formal_solver=fs,
+                     name=f"random{seed}")
+    chunks = [0] + [c for c in (4, 8, 16, 32) if 64 * c >= max(ns) - 1]
+    opts = dict(chunk=int(rng.choice(chunks)), coef_mode=int(rng.choice(COEF)))
+    return p, opts
+
+
+def normwise(p, v, y):
+    ref = O.apply(p, v)
+    return np.abs(y - ref).max() / (np.abs(v).max() + np.abs(v - ref).max())
+
+
+def oracle_relres(p, x):
+    b = O.rhs(p)
+    out = []
+    for i, s in enumerate(O._slices(p)):
+        out.append(np.linalg.norm(b[s] - O.apply_slab(p, i, x[s])) / np.linalg.norm(b[s]))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("seed", range(N_CASES))
+def test_random_shapes_against_the_oracle(seed):
+    p, opts = _case(seed)
+    print(f"case {seed}: ns={list(p.ns)} n_mu={p.n_mu} n_nu={p.n_nu} fs={p.formal_solver} {opts}",
+          flush=True)
+    v = W.random_vector(p.n_unknowns, seed)
+    idx = sorted({0, 1, p.n_unknowns // 3, p.n_unknowns - 2, p.n_unknowns - 1})
+    with B.setup(p, precision=B.RT_PREC_MIXED, rtol=1e-9, maxit=50000, **opts) as h:
+        assert normwise(p, v, host(h.apply_op(dev(v)))) <= 1e-12
+        assert normwise(p, v, host(h.apply_op_fp32(dev(v)))) < 1e-5
+        b = host(h.get_rhs())
+        ref = O.rhs(p)
+        assert np.abs(b - ref).max() <= 1e-12 * np.abs(ref).max()
+        d = host(h.get_jacobi_diag())
+        assert np.abs(d[idx] - O.diag(p, idx)).max() <= 1e-12
+        x = dev(W.initial_guess(p))
+        rc, info = h.solve_gmres(x)
+        assert rc == 0 and all(i.status == "converged" for i in info), info
+        assert oracle_relres(p, host(x)).max() < 1e-9
+    with B.setup(p, rtol=1e-10, maxit=50000, **opts) as h:
+        x = dev(W.initial_guess(p))
+        rc, info = h.solve_gmres(x)
+        assert rc == 0 and all(i.status == "converged" for i in info), info
+        assert oracle_relres(p, host(x)).max() < 1e-10
