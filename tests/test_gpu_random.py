@@ -3,8 +3,8 @@ depth points, 2 to 12 angles and 2 to 13 frequencies, each formal solver,
 each chunk length that fits the deepest slab, each coefficient mode, random
 optical-depth ranges, thermalization, polarizability and damping.  Each case
 checks the operator (FP64 and FP32), the right-hand side and sampled
-diagonal entries against the oracle, and FP64 and mixed-precision GMRES by
-the oracle's own residual.  The shapes come from the seeded input module
+diagonal entries against the oracle, and FP64 and mixed-precision GMRES and
+FP64 BiCGSTAB by the oracle's own residual.  The shapes come from the seeded input module
 only; nothing here computes the method.
 
 Tolerances as in test_gpu_parity: the FP64 operator, right-hand side and
@@ -91,3 +91,9 @@ def test_random_shapes_against_the_oracle(seed):
         rc, info = h.solve_gmres(x)
         assert rc == 0 and all(i.status == "converged" for i in info), info
         assert oracle_relres(p, host(x)).max() < 1e-10
+        # BiCGSTAB stops on its recursively updated residual: the true one
+        # may sit slightly above rtol (measured at most 9.95e-11 here)
+        x = dev(W.initial_guess(p))
+        rc, info = h.solve_bicgstab(x)
+        assert rc == 0 and all(i.status == "converged" for i in info), info
+        assert oracle_relres(p, host(x)).max() < 2e-10
