@@ -97,3 +97,23 @@ def test_random_shapes_against_the_oracle(seed):
         rc, info = h.solve_bicgstab(x)
         assert rc == 0 and all(i.status == "converged" for i in info), info
         assert oracle_relres(p, host(x)).max() < 2e-10
+
+
+def test_richardson_divergence_matches_oracle():
+    """Jacobi-Richardson converges only where the Jacobi iteration matrix
+    contracts.  On random case 1 (trapezoidal solver; slabs of 64, 511 and 2
+    points) it diverges on the two deep slabs and converges on the 2-point
+    one; the oracle's own Richardson does the same, so the library must
+    report a breakdown (non-finite residual) for the first two slabs and the
+    oracle's step count for the third."""
+    p, opts = _case(1)
+    with B.setup(p, rtol=1e-10, maxit=3000, **opts) as h:
+        x = dev(W.initial_guess(p))
+        rc, info = h.solve_richardson(x)
+    statuses = [i.status for i in info]
+    ref = [O.richardson(p.slab(i), tol=1e-10, maxit=3000)[1][0] for i in range(p.n_atm)]
+    assert [r["status"] for r in ref] == ["breakdown", "breakdown", "converged"], ref
+    assert statuses == ["breakdown", "breakdown", "converged"], info
+    assert rc == B.RT_EBREAKDOWN
+    assert abs(info[2].iterations - ref[2]["iterations"]) <= 2, (info[2], ref[2])
+    assert oracle_relres(p.slab(2), host(x)[O._slices(p)[2]]).max() < 1e-10
