@@ -256,3 +256,56 @@ def test_prd_requires_R():
             h.get_rhs_prd()
         with pytest.raises(B.RTError):
             h.set_redistribution(np.full((5, 5), np.nan))
+
+
+def _random_case(seed):
+    """A random redistribution problem (inputs only): 1 to 3 slabs of 2 to
+    700 points, 2 to 16 angles, 2 to 33 frequencies, any formal solver, a
+    redistribution parameter per slab."""
+    rng = np.random.default_rng(110873 + seed)
+    n = int(rng.integers(1, 4))
+    ns = [int(v) for v in rng.choice([2, 3, 9, 40, 77, 130, 256, 700], n)]
+    n_mu = int(rng.choice([2, 4, 8, 16]))
+    n_nu = int(rng.choice([2, 3, 9, 17, 33]))
+    fs = ["delo_linear", "trapezoidal", "implicit_euler", "delo_parabolic"][seed % 4]
+    ranges = [(10.0 ** rng.uniform(-4, -2), 10.0 ** rng.uniform(2, 6)) for _ in ns]
+    p = W.make_slabs(ns, ranges, n_mu, n_nu, float(rng.uniform(3.0, 7.0)),
+                     list(10.0 ** rng.uniform(-4, -2, n)), list(10.0 ** rng.uniform(-3, -1, n)),
+                     list(rng.uniform(0.0, 1.0, n)), formal_solver=fs)
+    R = np.stack([W.redistribution_matrix(p.x, p.w_nu, p.phi[i], float(rng.uniform(0.0, 1.0)))
+                  for i in range(n)])
+    v = rng.uniform(-1, 1, 2 * n_nu * int(np.sum(ns)))
+    return p, R, v
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_prd_random_shapes(seed):
+    """Seeded random shapes (all within the cached sweep's chunk length;
+    longer chunks: test_prd_long_rays_global_stage): FP64 operator and
+    right-hand side per slab
+    against the redistribution oracle, the BF16x3 operator within its 2e-5
+    bound, and Jacobi-GMRES by the oracle's residual."""
+    p, R, v = _random_case(seed)
+    print(f"case {seed}: ns={list(p.ns)} n_mu={p.n_mu} n_nu={p.n_nu} fs={p.formal_solver}",
+          flush=True)
+    nnu = len(p.w_nu)
+    with B.setup(p, rtol=1e-9, restart=30, maxit=20000) as h:
+        h.set_redistribution(R)
+        y = host(h.apply_op_prd(dev(v)))
+        y3 = host(h.apply_op_prd_bf16x3(dev(v)))
+        b = host(h.get_rhs_prd())
+        x = torch.zeros(h.prd_size(), dtype=torch.float64, device="cuda")
+        rc, info = h.solve_prd_gmres(x)
+        xs = host(x)
+    assert rc == 0 and all(i.status == "converged" for i in info), info
+    off = 0
+    for i, ns in enumerate(int(n) for n in p.ns):
+        seg = slice(2 * nnu * off, 2 * nnu * (off + ns))
+        ref = RDO.apply(p, R[i], v[seg], i=i)
+        assert normwise(ref, y[seg], v[seg]) <= 1e-12, i
+        assert normwise(ref, y3[seg], v[seg]) <= 2e-5, i
+        rb = RDO.rhs(p, R[i], i=i)
+        assert np.abs(b[seg] - rb).max() <= 1e-12 * np.abs(rb).max(), i
+        rel = np.linalg.norm(rb - RDO.apply(p, R[i], xs[seg], i=i)) / np.linalg.norm(rb)
+        assert rel < 1e-9, (i, rel)
+        off += ns
