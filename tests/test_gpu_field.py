@@ -144,3 +144,51 @@ def test_field_gmres_batch_per_slab():
         r = O.rhs_I(ps) - O.apply_I(ps, fo)
         assert np.linalg.norm(r) / np.linalg.norm(O.rhs_I(ps)) < 1e-10, i
     assert rc2 == B.RT_ENOCONV and all(i.iterations == 7 for i in info2)
+
+
+def _random_case(seed):
+    """A random field-unknown problem (inputs only): 1 to 3 slabs of 2 to 130
+    points, 2 to 8 angles, 2 to 13 frequencies, any formal solver."""
+    rng = np.random.default_rng(3211 + seed)
+    n = int(rng.integers(1, 4))
+    ns = [int(v) for v in rng.choice([2, 3, 9, 40, 77, 130], n)]
+    fs = ["delo_linear", "trapezoidal", "implicit_euler", "delo_parabolic"][seed % 4]
+    ranges = [(10.0 ** rng.uniform(-3, -1), 10.0 ** rng.uniform(1, 4)) for _ in ns]
+    return W.make_slabs(ns, ranges, int(rng.choice([2, 4, 8])), int(rng.choice([2, 3, 9, 13])),
+                        float(rng.uniform(3.0, 7.0)), list(10.0 ** rng.uniform(-4, -2, n)),
+                        list(10.0 ** rng.uniform(-2, -1, n)), list(rng.uniform(0.0, 1.0, n)),
+                        formal_solver=fs)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_field_random_shapes(seed):
+    """Seeded random shapes: per slab the field operator, its right-hand
+    side and sigma = J I + c against the oracle, and field GMRES by the
+    oracle's own residual."""
+    p = _random_case(seed)
+    print(f"case {seed}: ns={list(p.ns)} n_mu={p.n_mu} n_nu={p.n_nu} fs={p.formal_solver}",
+          flush=True)
+    rng = np.random.default_rng(seed)
+    with B.setup(p, rtol=1e-10, restart=30, maxit=20000) as h:
+        f = rng.uniform(-1, 1, h.field_size())
+        y = host(h.apply_op_field(dev(f)))
+        bI = host(h.get_rhs_field())
+        sg = host(h.sigma_from_field(dev(f)))
+        I = dev(np.zeros(h.field_size()))
+        rc, info = h.solve_field_gmres(I)
+        If = host(I)
+    assert rc == 0 and all(i.status == "converged" for i in info), info
+    sl = O._slices(p)
+    for i, (fi, yi, bi, xi) in enumerate(zip(slab_fields(p, f), slab_fields(p, y),
+                                             slab_fields(p, bI), slab_fields(p, If))):
+        ps = p.slab(i)
+        fo = to_oracle_order(p, fi, i)
+        ref = O.apply_I(ps, fo)
+        scale = np.abs(fi).max() + np.abs(fo - ref).max()
+        assert np.abs(to_oracle_order(p, yi, i) - ref).max() / scale <= 1e-12, i
+        rb = O.rhs_I(ps)
+        assert np.abs(to_oracle_order(p, bi, i) - rb).max() <= 1e-12 * np.abs(rb).max(), i
+        rs = O.sigma_from_I(ps, fo)
+        assert np.abs(sg[sl[i]] - rs).max() <= 1e-12 * np.abs(rs).max(), i
+        r = rb - O.apply_I(ps, to_oracle_order(p, xi, i))
+        assert np.linalg.norm(r) / np.linalg.norm(rb) < 1e-10, i
