@@ -1,7 +1,7 @@
 """Benchmark of the matrix-free (Id - J Lambda T) operator and its Jacobi-Krylov solves.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-    python bench.py --op-only fp32|fp64 [--matvecs N] [--coef-mode M]   # operator leg alone
+    python bench.py --op-only fp32|fp64|prd|prd_bf16|lu [--matvecs N] [--coef-mode M]  # one leg alone
     python bench.py --copy-calib                        # 512 MiB device copy x3
     python bench.py --summarize-pmc DIR                 # counters -> profiles/
     python bench.py --summarize-valu DIR                # VALU counters -> profiles/
@@ -96,11 +96,23 @@ def op_only(kind, n, coef_mode=0):
     tuned launch plan of the mixed solve (FP32) or of the FP64 solve (FP64),
     or with its coefficient mode replaced; or the frequency-redistribution
     operator (256 depths, 32 mu, 256 nu, gamma = 0.5) with its contraction on
-    the FP64 (prd) or the BF16 (prd_bf16) matrix cores."""
+    the FP64 (prd) or the BF16 (prd_bf16) matrix cores; or (lu) n direct
+    solves of the 512-slab batch, each on a fresh handle, so that each
+    assembles and factors the batch once."""
     import torch
     from paper_2110_11873_amd import binding as B
     from paper_2110_11873_amd import workloads as W
     torch.cuda.set_device(0)
+    if kind == "lu":
+        p = W.config4(512)
+        for _ in range(n):
+            with B.setup(p, precision=B.RT_PREC_MIXED) as h:
+                x = torch.zeros(p.n_unknowns, dtype=torch.float64, device="cuda")
+                rc, info = h.solve_lu(x)
+                torch.cuda.synchronize()
+        print(json.dumps(dict(op=kind, factorizations=n, relres_max=max(i.relres for i in info))),
+              flush=True)
+        return
     if kind.startswith("prd"):
         p5, R5 = W.config5()
         with B.setup(p5) as h:
@@ -511,7 +523,7 @@ def main():
     ap.add_argument("--matvecs", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--op-only", choices=["fp32", "fp64", "prd", "prd_bf16"])
+    ap.add_argument("--op-only", choices=["fp32", "fp64", "prd", "prd_bf16", "lu"])
     ap.add_argument("--coef-mode", type=int, default=0,
                     help="with --op-only: rt_options.coef_mode (0 = the tuned plan's)")
     ap.add_argument("--copy-calib", action="store_true")

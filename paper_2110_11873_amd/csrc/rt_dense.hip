@@ -276,6 +276,69 @@ struct LuArgs {
     const int *order;  // workgroup -> slab (largest first), or NULL: workgroup = slab
 };
 
+constexpr int kLuUsCols = 128;  // U12 columns staged in LDS per pass of the update
+typedef double lu_v4d __attribute__((ext_vector_type(4)));
+
+// A22 -= L21 U12 after outer block K0 (columns K0..K0+31, rows and columns
+// from cend on), by the workgroup: U12 is staged in LDS 128 columns at a
+// time; each wavefront takes 16-row tiles of the trailing rows, keeps the
+// tile's -L21 (16 x 32) as eight v_mfma_f64_16x16x4 A operands in registers,
+// and adds the eight products to each of the pass's 16 x 16 tiles of A22 it
+// loads and stores back.  Each trailing element is read and written once per
+// outer block, as in the vector version this replaces; the batch's
+// factorization is bound by that traffic.  Operand layout of the instruction: lane l feeds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; result register r of lane l is
+// D[4 r + l / 16][l % 16].
+__device__ inline void lu_trailing_mfma(double *A, int N, int K0, int cend,
+                                        double (*Us)[kLuUsCols]) {
+    constexpr int NW = kLuNT / kWave;
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const int li = lane % 16, lk = lane / 16;
+    for (int cc0 = cend; cc0 < N; cc0 += kLuUsCols) {
+        __syncthreads();
+        for (int e = tid; e < kLuBB * kLuUsCols; e += kLuNT) {
+            const int i = e / kLuUsCols, cc = e % kLuUsCols, c = cc0 + cc;
+            Us[i][cc] = c < N ? A[(long long)(K0 + i) * N + c] : 0.0;
+        }
+        __syncthreads();
+        for (int r0 = cend + 16 * wave; r0 < N; r0 += 16 * NW) {
+            const int ra = r0 + li;
+            double av[kLuBB / 4];
+#pragma unroll
+            for (int kk = 0; kk < kLuBB / 4; ++kk)
+                av[kk] = ra < N ? -A[(long long)ra * N + K0 + 4 * kk + lk] : 0.0;
+            // the pass's eight 16-column tiles together: their loads in flight
+            // at once and eight independent chains of products
+            constexpr int CT = kLuUsCols / 16;
+            lu_v4d acc[CT];
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+                const int col = cc0 + 16 * t + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = r0 + 4 * r + lk;
+                    acc[t][r] = (row < N && col < N) ? A[(long long)row * N + col] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int kk = 0; kk < kLuBB / 4; ++kk)
+#pragma unroll
+                for (int t = 0; t < CT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], Us[4 * kk + lk][16 * t + li],
+                                                                  acc[t], 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+                const int col = cc0 + 16 * t + li;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = r0 + 4 * r + lk;
+                    if (row < N && col < N) A[(long long)row * N + col] = acc[t][r];
+                }
+            }
+        }
+    }
+}
+
 template <int R, int NB, bool SPLIT = false>
 __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g, int K0s = 0) {
     constexpr int NW = kLuNT / kWave;
@@ -286,7 +349,7 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g, int K0s = 0)
     __shared__ double L11[NB][NB + 1];
     __shared__ double L21[kLuRows][NB];
     __shared__ double Lb[kLuBB][kLuBB + 1];   // the outer block's unit lower L11
-    __shared__ double Lb21[kLuRows][kLuBB];   // its L21, staged rows
+    __shared__ double Us[kLuBB][kLuUsCols];   // U12 columns staged for the update
     __shared__ double Ub[NB][kLuBB];          // a panel's U12 on the rest of its block
     static_assert(kLuBB % NB == 0, "the outer block is whole panels");
     const int slab = g.order ? g.order[blockIdx.x] : blockIdx.x;
@@ -351,7 +414,10 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g, int K0s = 0)
                         bi = oi;
                     }
                 }
-                const int p = bi;
+                // no candidate compared (a column of NaNs): keep row j, and
+                // the zero test below does not pass a NaN pivot, so mark it
+                const int p = bi < N ? bi : j;
+                if (bi >= N) singular = 1;
                 // exchange rows j and p of the panel through LDS
                 const int oj = j - k0, op = p - k0;
 #pragma unroll
@@ -464,52 +530,29 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g, int K0s = 0)
         }
         __syncthreads();
         if (SPLIT || c0 < cend || cend >= N) continue;
-        // the outer block is factored: U12 = Lb^-1 A12 and A22 -= Lb21 U12 on
-        // the columns beyond it, one rank-32 pass (each trailing element read
-        // and written once per 32 columns)
+        // the outer block is factored: U12 = Lb^-1 A12 on the columns beyond
+        // it (one thread per column, written back), then A22 -= L21 U12 for
+        // the trailing rows and columns on the FP64 matrix cores
         for (int e = tid; e < kLuBB * kLuBB; e += kLuNT) {
             const int r = e / kLuBB, c = e % kLuBB;
             Lb[r][c] = A[(long long)(K0 + r) * N + K0 + c];
         }
         __syncthreads();
-        for (int cb = cend; cb < N; cb += kLuNT) {
-            const int c = cb + tid;
+        for (int c = cend + tid; c < N; c += kLuNT) {
+            // a compiler-only barrier: Lb is read from LDS per column rather
+            // than hoisted into registers (496 of them) across the loop
+            asm volatile("" ::: "memory");
             double u[kLuBB];
 #pragma unroll
-            for (int i = 0; i < kLuBB; ++i) u[i] = c < N ? A[(long long)(K0 + i) * N + c] : 0.0;
+            for (int i = 0; i < kLuBB; ++i) u[i] = A[(long long)(K0 + i) * N + c];
 #pragma unroll
             for (int i = 1; i < kLuBB; ++i)
 #pragma unroll
                 for (int l = 0; l < i; ++l) u[i] = fma(-Lb[i][l], u[l], u[i]);
-            if (c < N)
 #pragma unroll
-                for (int i = 0; i < kLuBB; ++i) A[(long long)(K0 + i) * N + c] = u[i];
-            for (int r0 = cend; r0 < N; r0 += kLuRows) {
-                const int nr = min(kLuRows, N - r0);
-                __syncthreads();
-                for (int e = tid; e < kLuRows * kLuBB; e += kLuNT) {
-                    const int rr = e / kLuBB, i = e % kLuBB;
-                    Lb21[rr][i] = rr < nr ? A[(long long)(r0 + rr) * N + K0 + i] : 0.0;
-                }
-                __syncthreads();
-                if (c < N) {
-                    // 32 rows' loads in flight together (the stores of a
-                    // batch come before the next batch's loads)
-                    for (int rr0 = 0; rr0 < nr; rr0 += 32) {
-                        double a[32];
-#pragma unroll
-                        for (int t = 0; t < 32; ++t)
-                            a[t] = rr0 + t < nr ? A[(long long)(r0 + rr0 + t) * N + c] : 0.0;
-#pragma unroll
-                        for (int t = 0; t < 32; ++t) {
-#pragma unroll
-                            for (int i = 0; i < kLuBB; ++i) a[t] = fma(-Lb21[rr0 + t][i], u[i], a[t]);
-                            if (rr0 + t < nr) A[(long long)(r0 + rr0 + t) * N + c] = a[t];
-                        }
-                    }
-                }
-            }
+            for (int i = 0; i < kLuBB; ++i) A[(long long)(K0 + i) * N + c] = u[i];
         }
+        lu_trailing_mfma(A, N, K0, cend, Us);
         __syncthreads();
     }
     if (tid == 0) {
