@@ -254,18 +254,18 @@ __global__ void fill_kernel(double *v, long long n, double c) {
 //    the column below it -- two barriers per column;
 //  * the panel's row exchanges are then applied to the other columns (one
 //    thread per column, in order), U12 = L11^-1 A12 is solved one thread per
-//    column, and A22 -= L21 U12 streams the trailing rows with the column's
-//    U12 in registers and L21 staged in LDS 64 rows at a time -- within the
-//    panel's outer block of 32 columns; once the block is factored, the
-//    columns beyond it get U12 from the block's 32 x 32 unit lower triangle
-//    and one rank-32 update (a quarter of the rank-8 passes' traffic).
+//    column, and A22 -= L21 U12 streams the trailing rows with the row's
+//    L21 in registers and U12 staged in LDS -- within the panel's outer
+//    block of BB columns; once the block is factored, the columns beyond it
+//    get U12 from the block's BB x BB unit lower triangle and one rank-BB
+//    update on the FP64 matrix cores (lu_trailing_mfma).
 // piv[k] (slab-local) is the row exchanged with row k at step k, as LAPACK's
 // getrf returns it.  A zero pivot marks the slab singular.
 // --------------------------------------------------------------------------
-constexpr int kLuNT = 512;   // 256 VGPRs per lane for the rank-32 pass
-constexpr int kLuRows = 64;  // L21 rows staged per pass of the trailing update
+constexpr int kLuNT = 512;   // 8 wavefronts; the block's U12 column solve holds BB values
 constexpr int kLuNB = 8;     // panel width (16 spills the panel's registers)
-constexpr int kLuBB = 32;    // outer block: its trailing update is one rank-32 pass
+constexpr int kLuBB = 32;    // outer block of the few-slab path (multi-workgroup updates)
+constexpr int kLuBBBatch = 64;  // the batch kernel's outer block (half the trailing traffic)
 constexpr int kLuSplitSlabs = 32;  // batches up to this many slabs: multi-workgroup updates
 
 struct LuArgs {
@@ -279,16 +279,17 @@ struct LuArgs {
 constexpr int kLuUsCols = 128;  // U12 columns staged in LDS per pass of the update
 typedef double lu_v4d __attribute__((ext_vector_type(4)));
 
-// A22 -= L21 U12 after outer block K0 (columns K0..K0+31, rows and columns
+// A22 -= L21 U12 after outer block K0 (columns K0..K0+BB-1, rows and columns
 // from cend on), by the workgroup: U12 is staged in LDS 128 columns at a
 // time; each wavefront takes 16-row tiles of the trailing rows, keeps the
-// tile's -L21 (16 x 32) as eight v_mfma_f64_16x16x4 A operands in registers,
-// and adds the eight products to each of the pass's 16 x 16 tiles of A22 it
-// loads and stores back.  Each trailing element is read and written once per
-// outer block, as in the vector version this replaces; the batch's
-// factorization is bound by that traffic.  Operand layout of the instruction: lane l feeds
+// tile's -L21 (16 x BB) as BB / 4 v_mfma_f64_16x16x4 A operands in
+// registers, and adds the products to each of the pass's 16 x 16 tiles of
+// A22 it loads and stores back.  Each trailing element is read and written
+// once per outer block: the batch's factorization is bound by that traffic,
+// hence 64-column blocks there.  Operand layout of the instruction: lane l feeds
 // A[l % 16][l / 16] and B[l / 16][l % 16]; result register r of lane l is
 // D[4 r + l / 16][l % 16].
+template <int BB>
 __device__ inline void lu_trailing_mfma(double *A, int N, int K0, int cend,
                                         double (*Us)[kLuUsCols]) {
     constexpr int NW = kLuNT / kWave;
@@ -296,16 +297,16 @@ __device__ inline void lu_trailing_mfma(double *A, int N, int K0, int cend,
     const int li = lane % 16, lk = lane / 16;
     for (int cc0 = cend; cc0 < N; cc0 += kLuUsCols) {
         __syncthreads();
-        for (int e = tid; e < kLuBB * kLuUsCols; e += kLuNT) {
+        for (int e = tid; e < BB * kLuUsCols; e += kLuNT) {
             const int i = e / kLuUsCols, cc = e % kLuUsCols, c = cc0 + cc;
             Us[i][cc] = c < N ? A[(long long)(K0 + i) * N + c] : 0.0;
         }
         __syncthreads();
         for (int r0 = cend + 16 * wave; r0 < N; r0 += 16 * NW) {
             const int ra = r0 + li;
-            double av[kLuBB / 4];
+            double av[BB / 4];
 #pragma unroll
-            for (int kk = 0; kk < kLuBB / 4; ++kk)
+            for (int kk = 0; kk < BB / 4; ++kk)
                 av[kk] = ra < N ? -A[(long long)ra * N + K0 + 4 * kk + lk] : 0.0;
             // the pass's eight 16-column tiles together: their loads in flight
             // at once and eight independent chains of products
@@ -321,7 +322,7 @@ __device__ inline void lu_trailing_mfma(double *A, int N, int K0, int cend,
                 }
             }
 #pragma unroll
-            for (int kk = 0; kk < kLuBB / 4; ++kk)
+            for (int kk = 0; kk < BB / 4; ++kk)
 #pragma unroll
                 for (int t = 0; t < CT; ++t)
                     acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], Us[4 * kk + lk][16 * t + li],
@@ -339,7 +340,7 @@ __device__ inline void lu_trailing_mfma(double *A, int N, int K0, int cend,
     }
 }
 
-template <int R, int NB, bool SPLIT = false>
+template <int R, int NB, bool SPLIT = false, int BB = kLuBB>
 __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g, int K0s = 0) {
     constexpr int NW = kLuNT / kWave;
     __shared__ double swp[2][2][NB];       // [buffer][row j, row p][column]
@@ -347,11 +348,11 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g, int K0s = 0)
     __shared__ int redi[2][NW];
     __shared__ int s_piv[NB];
     __shared__ double L11[NB][NB + 1];
-    __shared__ double L21[kLuRows][NB];
-    __shared__ double Lb[kLuBB][kLuBB + 1];   // the outer block's unit lower L11
-    __shared__ double Us[kLuBB][kLuUsCols];   // U12 columns staged for the update
-    __shared__ double Ub[NB][kLuBB];          // a panel's U12 on the rest of its block
-    static_assert(kLuBB % NB == 0, "the outer block is whole panels");
+    __shared__ double Lb[BB][BB + 1];   // the outer block's unit lower L11
+    extern __shared__ double lu_dyn[];        // U12 columns staged for the update
+    double(*Us)[kLuUsCols] = reinterpret_cast<double(*)[kLuUsCols]>(lu_dyn);
+    __shared__ double Ub[NB][BB];          // a panel's U12 on the rest of its block
+    static_assert(BB % NB == 0, "the outer block is whole panels");
     const int slab = g.order ? g.order[blockIdx.x] : blockIdx.x;
     const AtmDesc at = g.atm[slab];
     const int N = 2 * at.ns;
@@ -364,9 +365,9 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g, int K0s = 0)
     // multi-workgroup kernels below
     if (SPLIT && K0s >= N) return;
     if (SPLIT && K0s == 0 && tid == 0) g.sing[slab] = 0;
-    for (int k0 = SPLIT ? K0s : 0; k0 < (SPLIT ? min(K0s + kLuBB, N) : N); k0 += NB) {
+    for (int k0 = SPLIT ? K0s : 0; k0 < (SPLIT ? min(K0s + BB, N) : N); k0 += NB) {
         const int nb = min(NB, N - k0);
-        const int K0 = k0 / kLuBB * kLuBB, cend = min(K0 + kLuBB, N);  // this panel's outer block
+        const int K0 = k0 / BB * BB, cend = min(K0 + BB, N);  // this panel's outer block
         double P[R][NB];
 #pragma unroll
         for (int u = 0; u < R; ++u) {
@@ -502,12 +503,12 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g, int K0s = 0)
                 if (i < nb) A[(long long)(k0 + i) * N + c] = u[i];
         }
         __syncthreads();
-        // A22 -= L21 U12 on the rest of the outer block (at most kLuBB - NB
+        // A22 -= L21 U12 on the rest of the outer block (at most BB - NB
         // columns): U12 staged in LDS, one thread per trailing row, the row's
         // L21 and block entries loaded together
         __syncthreads();
-        for (int e = tid; e < NB * kLuBB; e += kLuNT) {
-            const int i = e / kLuBB, cc = e % kLuBB, c = c0 + cc;
+        for (int e = tid; e < NB * BB; e += kLuNT) {
+            const int i = e / BB, cc = e % BB, c = c0 + cc;
             Ub[i][cc] = (i < nb && c < cend) ? A[(long long)(k0 + i) * N + c] : 0.0;
         }
         __syncthreads();
@@ -515,14 +516,14 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g, int K0s = 0)
             // a compiler-only barrier: Ub is read from LDS per row rather than
             // kept in registers across the loop
             asm volatile("" ::: "memory");
-            double l[NB], v[kLuBB - NB];
+            double l[NB], v[BB - NB];
             const double *row = A + (long long)r * N;
 #pragma unroll
             for (int i = 0; i < NB; ++i) l[i] = i < nb ? row[k0 + i] : 0.0;
 #pragma unroll
-            for (int cc = 0; cc < kLuBB - NB; ++cc) v[cc] = c0 + cc < cend ? row[c0 + cc] : 0.0;
+            for (int cc = 0; cc < BB - NB; ++cc) v[cc] = c0 + cc < cend ? row[c0 + cc] : 0.0;
 #pragma unroll
-            for (int cc = 0; cc < kLuBB - NB; ++cc) {
+            for (int cc = 0; cc < BB - NB; ++cc) {
 #pragma unroll
                 for (int i = 0; i < NB; ++i) v[cc] = fma(-l[i], Ub[i][cc], v[cc]);
                 if (c0 + cc < cend) A[(long long)r * N + c0 + cc] = v[cc];
@@ -533,8 +534,8 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g, int K0s = 0)
         // the outer block is factored: U12 = Lb^-1 A12 on the columns beyond
         // it (one thread per column, written back), then A22 -= L21 U12 for
         // the trailing rows and columns on the FP64 matrix cores
-        for (int e = tid; e < kLuBB * kLuBB; e += kLuNT) {
-            const int r = e / kLuBB, c = e % kLuBB;
+        for (int e = tid; e < BB * BB; e += kLuNT) {
+            const int r = e / BB, c = e % BB;
             Lb[r][c] = A[(long long)(K0 + r) * N + K0 + c];
         }
         __syncthreads();
@@ -542,17 +543,17 @@ __global__ __launch_bounds__(kLuNT) void lu_factor_kernel(LuArgs g, int K0s = 0)
             // a compiler-only barrier: Lb is read from LDS per column rather
             // than hoisted into registers (496 of them) across the loop
             asm volatile("" ::: "memory");
-            double u[kLuBB];
+            double u[BB];
 #pragma unroll
-            for (int i = 0; i < kLuBB; ++i) u[i] = A[(long long)(K0 + i) * N + c];
+            for (int i = 0; i < BB; ++i) u[i] = A[(long long)(K0 + i) * N + c];
 #pragma unroll
-            for (int i = 1; i < kLuBB; ++i)
+            for (int i = 1; i < BB; ++i)
 #pragma unroll
                 for (int l = 0; l < i; ++l) u[i] = fma(-Lb[i][l], u[l], u[i]);
 #pragma unroll
-            for (int i = 0; i < kLuBB; ++i) A[(long long)(K0 + i) * N + c] = u[i];
+            for (int i = 0; i < BB; ++i) A[(long long)(K0 + i) * N + c] = u[i];
         }
-        lu_trailing_mfma(A, N, K0, cend, Us);
+        lu_trailing_mfma<BB>(A, N, K0, cend, Us);
         __syncthreads();
     }
     if (tid == 0) {
@@ -811,14 +812,23 @@ int lu_factor(rt_handle *h, hipStream_t s) {
         return RT_OK;
     }
     g.order = h->d_lu_order;
+    // one workgroup per slab with 64-column outer blocks; their U12 stage
+    // (64 x kLuUsCols doubles) in dynamic LDS
+    const size_t lds = (size_t)kLuBBBatch * kLuUsCols * sizeof(double);
+    auto launch = [&](auto kernel) {
+        if (hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds) != hipSuccess)
+            return;  // the launch below reports the error
+        hipLaunchKernelGGL(kernel, dim3(h->n_atm), dim3(kLuNT), lds, s, g, 0);
+    };
     if (N <= kLuNT)
-        hipLaunchKernelGGL((lu_factor_kernel<1, kLuNB>), dim3(h->n_atm), dim3(kLuNT), 0, s, g);
+        launch(lu_factor_kernel<1, kLuNB, false, kLuBBBatch>);
     else if (N <= 2 * kLuNT)
-        hipLaunchKernelGGL((lu_factor_kernel<2, kLuNB>), dim3(h->n_atm), dim3(kLuNT), 0, s, g);
+        launch(lu_factor_kernel<2, kLuNB, false, kLuBBBatch>);
     else if (N <= 4 * kLuNT)
-        hipLaunchKernelGGL((lu_factor_kernel<4, kLuNB>), dim3(h->n_atm), dim3(kLuNT), 0, s, g);
+        launch(lu_factor_kernel<4, kLuNB, false, kLuBBBatch>);
     else
-        hipLaunchKernelGGL((lu_factor_kernel<8, kLuNB>), dim3(h->n_atm), dim3(kLuNT), 0, s, g);
+        launch(lu_factor_kernel<8, kLuNB, false, kLuBBBatch>);
     if (hipGetLastError() != hipSuccess) return fail(RT_EDEVICE, "LU factorization launch failed");
     h->lu_ready = true;
     return RT_OK;
