@@ -530,32 +530,55 @@ __global__ __launch_bounds__(NTF) void gm_arnoldi_fused_kernel(VecArgs a, int j)
     }
     if (tid < MR_) hsum[tid] = 0.0;
 
-    // w = A P^-1 v_j; the block slots are read 8 at a time, all loads of a
-    // group in flight together (addresses clamped, extra values unused)
-    double w0 = 0.0, w2 = 0.0;
-    if (on) {
-        double J0 = 0.0, J2 = 0.0;
+    // w = A P^-1 v_j from the sweep's block slots, read 8 at a time with all
+    // loads of a group in flight (addresses clamped, extra values unused).
+    // A slab of many blocks and few points (a single small slab's plan) lets
+    // the idle threads share them: G lanes per point, lane s adding slots s,
+    // s + G, ..., and the point's thread adding the G sums in order.
+    double J0 = 0.0, J2 = 0.0;
+    {
         const long long stride = 2LL * at.ns;
-        auto add_slots = [&](const auto *pJ) {
+        auto add_slots = [&](const auto *pJ, int s0, int step, double &X0, double &X2) {
             using V2 = typename std::conditional<sizeof(*pJ) == 4, float2, double2>::type;
-            for (int b0 = 0; b0 < at.nblk; b0 += 8) {
+            for (int b0 = s0; b0 < at.nblk; b0 += 8 * step) {
                 V2 p[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
-                    p[u] = *reinterpret_cast<const V2 *>(pJ + min(b0 + u, at.nblk - 1) * stride);
+                    p[u] = *reinterpret_cast<const V2 *>(pJ + min(b0 + u * step, at.nblk - 1) * stride);
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    if (b0 + u < at.nblk) {
-                        J0 += (double)p[u].x;
-                        J2 += (double)p[u].y;
+                    if (b0 + u * step < at.nblk) {
+                        X0 += (double)p[u].x;
+                        X2 += (double)p[u].y;
                     }
                 }
             }
         };
-        if (a.part_f32)
-            add_slots(reinterpret_cast<const float *>(a.partial) + at.part_off + 2 * k);
-        else
-            add_slots(a.partial + at.part_off + 2 * k);
+        auto add_point = [&](int kp, int s0, int step, double &X0, double &X2) {
+            if (a.part_f32)
+                add_slots(reinterpret_cast<const float *>(a.partial) + at.part_off + 2 * kp, s0, step,
+                          X0, X2);
+            else
+                add_slots(a.partial + at.part_off + 2 * kp, s0, step, X0, X2);
+        };
+        const int G = at.nblk > 16 ? max(1, min(16, NTF / at.ns)) : 1;
+        if (G == 1) {
+            if (on) add_point(k, 0, 1, J0, J2);
+        } else {
+            __shared__ double2 sred[NTF];
+            double X0 = 0.0, X2 = 0.0;
+            if (tid < G * at.ns) add_point(tid % at.ns, tid / at.ns, G, X0, X2);
+            sred[tid] = make_double2(X0, X2);
+            __syncthreads();
+            if (on)
+                for (int g = 0; g < G; ++g) {
+                    J0 += sred[k + g * at.ns].x;
+                    J2 += sred[k + g * at.ns].y;
+                }
+        }
+    }
+    double w0 = 0.0, w2 = 0.0;
+    if (on) {
         double vj0 = 0.0, vj2 = 0.0;
 #pragma unroll
         for (int t = 0; t < MR_; ++t)
