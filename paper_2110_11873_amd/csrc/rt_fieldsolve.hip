@@ -128,16 +128,28 @@ __global__ __launch_bounds__(kFsNT) void fs_norm2_kernel(FsArgs a, const double 
 // lane l adding chunks l, l + 64, ... in order, then a butterfly (a fixed
 // order for a given chunk count: deterministic).
 __global__ __launch_bounds__(1024) void fs_reduce_kernel(FsArgs a, int nv, int mode) {
+    __shared__ double red[1024];
     const int s = blockIdx.x;
     if (!(mode ? a.active[s] : working(a, s))) return;
-    const int lane = threadIdx.x % kWave;
+    // G groups of nv threads (G a power of two): group g adds chunks g, g + G,
+    // ... of entry i, so neighbouring threads read neighbouring entries of a
+    // chunk's row; the groups' sums are then added pairwise in a fixed tree
+    int G = 1;
+    while (2 * G * nv <= (int)blockDim.x) G *= 2;
+    const int t = threadIdx.x, i = t % nv, g = t / nv;
     const double *ps = a.part + (long long)s * a.nchunk * a.hs;
-    for (int i = threadIdx.x / kWave; i < nv; i += blockDim.x / kWave) {
-        double t = 0.0;
-        for (int c = lane; c < a.nchunk; c += kWave) t += ps[(long long)c * a.hs + i];
-        for (int o = kWave / 2; o > 0; o >>= 1) t += __shfl_xor(t, o);
-        if (lane == 0) a.h[(long long)s * a.hs + i] = t;
+    if (g < G) {
+        double acc = 0.0;
+#pragma unroll 8
+        for (int c = g; c < a.nchunk; c += G) acc += ps[(long long)c * a.hs + i];
+        red[t] = acc;
     }
+    __syncthreads();
+    for (int half = G / 2; half > 0; half /= 2) {
+        if (g < half) red[t] += red[t + half * nv];
+        __syncthreads();
+    }
+    if (t < nv) a.h[(long long)s * a.hs + t] = red[t];
 }
 
 // ---------------------------------------------------------------------------
@@ -157,8 +169,8 @@ __global__ __launch_bounds__(1024) void fs_reduce_kernel(FsArgs a, int nv, int m
 // without an operator application.
 //   fs_dd_dots_kernel:   the partial dot products on each chunk;
 //   fs_dd_update_kernel: every workgroup of a slab adds all chunks' partial
-//                        sums itself (the order fs_reduce_kernel uses: the
-//                        same coefficients, bit for bit, in every workgroup),
+//                        sums itself (in one order: the same coefficients,
+//                        bit for bit, in every workgroup),
 //                        then updates q_j and u_{j+1} on its chunk; the first
 //                        workgroup finishes column j-1 and runs the Givens
 //                        step.  (From kFsFuseMaxChunks chunks on,
@@ -169,8 +181,8 @@ __global__ __launch_bounds__(1024) void fs_reduce_kernel(FsArgs a, int nv, int m
 __device__ void givens_step(const FsArgs &a, int s, int j, const double *col,
                             const double *rcs, const double *rsn);
 
-// sum over the chunks of one slab's partial sums of entry i (fs_reduce_kernel's
-// order), by one wavefront
+// sum over the chunks of one slab's partial sums of entry i, by one wavefront
+// (the same order in every workgroup)
 __device__ inline double chunk_sum(const FsArgs &a, const double *ps, int i, int lane) {
     double t = 0.0;
     for (int c = lane; c < a.nchunk; c += kWave) t += ps[(long long)c * a.hs + i];
