@@ -199,23 +199,26 @@ __global__ __launch_bounds__(kFsNT) void fs_dd_dots_kernel(FsArgs a, const doubl
     const long long hi = std::min(a.off[s + 1], lo + kFsChunk);
     const int lane = threadIdx.x % kWave;
     const double *u = a.V + (long long)j * a.N;
-    double uv[kFsPerLane], wv[kFsPerLane];
-#pragma unroll
-    for (int k = 0; k < kFsPerLane; ++k) {
-        const long long e = lo + lane + (long long)k * kWave;
-        uv[k] = e < hi ? u[e] : 0.0;
-        wv[k] = (w && e < hi) ? w[e] : 0.0;
+    // the chunk of u and w, read once for all wavefronts (each wavefront
+    // reading it into registers made every workgroup fetch it 16 times)
+    __shared__ double su[kFsChunk], sw[kFsChunk];
+    for (int t = threadIdx.x; t < kFsChunk; t += kFsNT) {
+        const long long e = lo + t;
+        su[t] = e < hi ? u[e] : 0.0;
+        sw[t] = (w && e < hi) ? w[e] : 0.0;
     }
+    __syncthreads();
     double *out = a.part + ((long long)s * a.nchunk + c) * a.hs;
     for (int i = threadIdx.x / kWave; i <= j; i += kFsNT / kWave) {
         const double *Vi = a.V + (long long)i * a.N;  // i == j: u itself
         double as = 0.0, az = 0.0;
 #pragma unroll
         for (int k = 0; k < kFsPerLane; ++k) {
-            const long long e = lo + lane + (long long)k * kWave;
+            const int t = lane + k * kWave;
+            const long long e = lo + t;
             const double vi = e < hi ? Vi[e] : 0.0;
-            as = fma(vi, uv[k], as);
-            az = fma(vi, wv[k], az);
+            as = fma(vi, su[t], as);
+            az = fma(vi, sw[t], az);
         }
         for (int o = kWave / 2; o > 0; o >>= 1) {
             as += __shfl_xor(as, o);
