@@ -28,6 +28,7 @@ namespace rt {
 namespace {
 
 constexpr int kFieldNT = 256;
+constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 
 struct FieldArgs {
     const AtmDesc *atm;
@@ -94,11 +95,17 @@ __global__ __launch_bounds__(kFieldNT) void field_quad_kernel(FieldArgs a) {
 // c = t / G, with G * nch = kFieldNT.
 __global__ __launch_bounds__(kFieldNT) void field_sweep_kernel(FieldArgs a) {
     __shared__ double carry[2 * kFieldNT * 3];  // [dir][chunk][ray][alpha, bx, by]
-    const int slab = blockIdx.y;
+    // Workgroups are dealt to the eight XCDs in turn; give each XCD a run of
+    // consecutive ray groups, so the groups that share the field's cache
+    // lines (G rays of one depth row each) meet in one L2
+    const int nwg = gridDim.x * gridDim.y, lin = blockIdx.y * gridDim.x + blockIdx.x;
+    const int xcd = lin % kXcds, q = nwg / kXcds, rem = nwg % kXcds;
+    const int wg = xcd * q + std::min(xcd, rem) + lin / kXcds;
+    const int slab = wg / gridDim.x, rg = wg % gridDim.x;
     const AtmDesc at = a.atm[slab];
     const int nch = a.nch, G = kFieldNT / nch, t = threadIdx.x;
     const int g = t % G, c = t / G;
-    const int r = blockIdx.x * G + g;
+    const int r = rg * G + g;
     const bool active = r < a.M * a.n_nu;
     const int mp = active ? r / a.n_nu : 0, p = active ? r % a.n_nu : 0;
     const int ns = at.ns;
