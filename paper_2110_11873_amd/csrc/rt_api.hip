@@ -520,6 +520,7 @@ void rt_destroy(rt_handle *h) {
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (h->h_count) (void)hipHostFree(h->h_count);
+    if (h->h_seg_flag) (void)hipHostFree(h->h_seg_flag);
     delete h;
 }
 

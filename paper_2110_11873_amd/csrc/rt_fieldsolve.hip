@@ -103,6 +103,14 @@ struct FsArgs {
 
 __device__ inline bool working(const FsArgs &a, int s) { return a.active[s] && !a.done[s]; }
 
+// out = 1 when no slab is still in its cycle (every slab done or inactive)
+__global__ __launch_bounds__(256) void fs_ended_kernel(FsArgs a, int *out) {
+    int in_cycle = 0;
+    for (int s = threadIdx.x; s < a.n_atm; s += blockDim.x) in_cycle |= working(a, s) ? 1 : 0;
+    in_cycle = __syncthreads_or(in_cycle);
+    if (threadIdx.x == 0) *out = in_cycle ? 0 : 1;
+}
+
 // part[s][c][0] = sum over chunk c of slab s of x[e]^2, for the active slabs:
 // each wavefront adds its lanes' strided entries, then a butterfly and one
 // pass over the 16 wavefronts in LDS (a fixed order).
@@ -568,8 +576,18 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
     cv.want(&a.done, n_atm);
     cv.want(&a.jj, n_atm);
     cv.want(&a.iters, n_atm);
+    int *dflag;
+    cv.want(&dflag, 1);
     if (!cv.commit()) return fail(RT_ENOMEM, "GMRES workspace allocation failed");
-    auto release = [] {};
+    if (!h->h_seg_flag && hipHostMalloc((void **)&h->h_seg_flag, sizeof(int)) != hipSuccess) {
+        h->h_seg_flag = nullptr;
+        return fail(RT_ENOMEM, "pinned host allocation failed");
+    }
+    volatile int *hflag = h->h_seg_flag;
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+        return fail(RT_EDEVICE, "GMRES: event creation failed");
+    auto release = [&] { (void)hipEventDestroy(ev); };
     hipError_t err = hipSuccess;
     auto ok = [&](hipError_t e) {
         if (e != hipSuccess && err == hipSuccess) err = e;
@@ -626,24 +644,36 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
                                apart ? 1 : 0);
             ok(hipGetLastError());
         };
+        // Stop the cycle early once every slab's cycle has ended.  Every 8
+        // steps the end flag is copied to pinned memory behind an event that
+        // the following steps poll, so the host never waits for the stream;
+        // steps run after the cycle ended and before the copy lands change
+        // nothing (their kernels skip slabs out of their cycle).
         bool ended = false;  // every slab's cycle ended before step m
+        bool pending = false;
         for (int j = 0; j < m && err == hipSuccess; ++j) {
             ok(apply(a.V + (long long)j * N, w));
             ++napply;
             reduce_update(w, j, 0);
-            if ((j + 1) % 8 == 0 && j + 1 < m) {
-                // stop the cycle early once every slab's cycle has ended
-                std::vector<int> d(n_atm), ac(n_atm);
-                ok(hipMemcpyAsync(d.data(), a.done, sizeof(int) * n_atm, hipMemcpyDeviceToHost, st));
-                ok(hipMemcpyAsync(ac.data(), a.active, sizeof(int) * n_atm, hipMemcpyDeviceToHost, st));
-                ok(hipStreamSynchronize(st));
-                bool all = true;
-                for (int s = 0; s < n_atm; ++s)
-                    if (ac[s] && !d[s]) all = false;
-                if (all) {
-                    ended = true;
-                    break;
+            if (pending) {
+                const hipError_t q = hipEventQuery(ev);
+                if (q == hipSuccess) {
+                    pending = false;
+                    if (*hflag) {
+                        ended = true;
+                        break;
+                    }
+                } else if (q == hipErrorNotReady) {
+                    (void)hipGetLastError();  // the copy is still running: no error
+                } else {
+                    ok(q);
                 }
+            }
+            if (!pending && (j + 1) % 8 == 0 && j + 1 < m) {
+                hipLaunchKernelGGL(fs_ended_kernel, dim3(1), dim3(256), 0, st, a, dflag);
+                ok(hipMemcpyAsync((void *)hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+                ok(hipEventRecord(ev, st));
+                pending = true;
             }
         }
         // the last column of the cycle, for the slabs still in it

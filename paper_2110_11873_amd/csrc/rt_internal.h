@@ -321,6 +321,7 @@ struct rt_handle {
     int *d_cycle = nullptr;     // per slab: GMRES cycle still running
     int *d_count = nullptr;     // reduction target for host checks
     int *h_count = nullptr;     // pinned host mirror
+    int *h_seg_flag = nullptr;  // pinned: the segmented GMRES's end-of-cycle flag
 
     // workspace of the segmented GMRES (slot 0) and of the refinement around
     // it (slot 1), kept between calls and grown on demand
