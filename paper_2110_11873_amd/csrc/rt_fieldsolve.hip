@@ -103,6 +103,14 @@ struct FsArgs {
 
 __device__ inline bool working(const FsArgs &a, int s) { return a.active[s] && !a.done[s]; }
 
+// out = 1 when some slab's flag is set
+__global__ __launch_bounds__(256) void fs_any_kernel(const int *flags, int n, int *out) {
+    int any = 0;
+    for (int s = threadIdx.x; s < n; s += blockDim.x) any |= flags[s] ? 1 : 0;
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) *out = any;
+}
+
 // out = 1 when no slab is still in its cycle (every slab done or inactive)
 __global__ __launch_bounds__(256) void fs_ended_kernel(FsArgs a, int *out) {
     int in_cycle = 0;
@@ -606,13 +614,12 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
     if (dinv) hipLaunchKernelGGL(fs_mul_kernel, dim3(mgrid), dim3(256), 0, st, dinv, (const double *)x, x, N, 1);
     const dim3 seg(nchunk, n_atm), blk(kFsNT);
     const int tb = 64, tg = (n_atm + tb - 1) / tb;
-    std::vector<int> act(n_atm);
+    // whether any slab's flag is set: one int through pinned memory
     auto any_active = [&](const int *flags) {
-        ok(hipMemcpyAsync(act.data(), flags, sizeof(int) * n_atm, hipMemcpyDeviceToHost, st));
+        hipLaunchKernelGGL(fs_any_kernel, dim3(1), dim3(256), 0, st, flags, n_atm, dflag);
+        ok(hipMemcpyAsync((void *)hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
         ok(hipStreamSynchronize(st));
-        for (int v : act)
-            if (v) return true;
-        return false;
+        return err == hipSuccess && *hflag != 0;
     };
     hipLaunchKernelGGL(fs_init_kernel, dim3(tg), dim3(tb), 0, st, a);
     // ||b||, then r = b - K x
