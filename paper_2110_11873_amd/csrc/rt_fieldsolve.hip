@@ -653,9 +653,11 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
         };
         // Stop the cycle early once every slab's cycle has ended.  Every 8
         // steps the end flag is copied to pinned memory behind an event that
-        // the following steps poll, so the host never waits for the stream;
-        // steps run after the cycle ended and before the copy lands change
-        // nothing (their kernels skip slabs out of their cycle).
+        // the following steps poll, so the host never drains the stream; a
+        // host that reaches the next check first waits for that event, which
+        // keeps it at most two checks ahead.  Steps run after the cycle ended
+        // and before the flag is seen change nothing (their kernels skip
+        // slabs out of their cycle).
         bool ended = false;  // every slab's cycle ended before step m
         bool pending = false;
         for (int j = 0; j < m && err == hipSuccess; ++j) {
@@ -676,7 +678,17 @@ int solve_seg_gmres_tol(rt_handle *h, const SegOp &op,
                     ok(q);
                 }
             }
-            if (!pending && (j + 1) % 8 == 0 && j + 1 < m) {
+            if ((j + 1) % 8 == 0 && j + 1 < m) {
+                if (pending) {
+                    // the host is a full check ahead: wait for the last one
+                    // (the GPU still has the 8 steps since it queued)
+                    ok(hipEventSynchronize(ev));
+                    pending = false;
+                    if (err == hipSuccess && *hflag) {
+                        ended = true;
+                        break;
+                    }
+                }
                 hipLaunchKernelGGL(fs_ended_kernel, dim3(1), dim3(256), 0, st, a, dflag);
                 ok(hipMemcpyAsync((void *)hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
                 ok(hipEventRecord(ev, st));
